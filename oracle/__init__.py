@@ -1,0 +1,329 @@
+"""Plain FP64 CPU oracle (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
+``cpu_baseline`` leg may import this package.  The product path (the HIP
+library and its Python binding) never imports, links or calls it, and the two
+share no code: this package wraps ``poly_oracle.c`` (the plain definitions of
+simplify, times, eval, diff and the reverse mode of eval) through ctypes, and
+adds a brute-force simplify built on a Python dict as a second, independent
+data structure for self-checks.
+
+Each function states the passage of the paper it follows; conventions where
+the paper is silent are documented in ``poly_oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "poly_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liborc.so")
+_lib = None
+
+
+def build_library() -> str:
+    """Compile the C oracle with gcc (plain -O2, no FMA contraction)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+           "-shared", "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        build_library()
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    i32 = ctypes.c_int
+    d = ctypes.c_double
+    lib.orc_simplify.argtypes = [i32, i64, P, P, d, P, P]
+    lib.orc_simplify.restype = i64
+    lib.orc_expand.argtypes = [i32, i64, P, P, i64, P, P, P, P]
+    lib.orc_expand.restype = i64
+    lib.orc_mul.argtypes = [i32, i64, P, P, i64, P, P, d, P, P]
+    lib.orc_mul.restype = i64
+    lib.orc_eval_point.argtypes = [i32, i64, P, P, P]
+    lib.orc_eval_point.restype = d
+    lib.orc_eval_batch.argtypes = [i32, i64, P, P, P, i64, P, P]
+    lib.orc_eval_batch.restype = None
+    lib.orc_eval_dense.argtypes = [i32, i64, P, i64, P, i64, P, P]
+    lib.orc_eval_dense.restype = None
+    lib.orc_eval_dense_ld.argtypes = [i32, i64, P, i64, P, i64, P, P, P]
+    lib.orc_eval_dense_ld.restype = None
+    lib.orc_eval_batch_ld.argtypes = [i32, i64, P, P, P, i64, P, P, P]
+    lib.orc_eval_batch_ld.restype = None
+    lib.orc_diff.argtypes = [i32, i64, P, P, i32, P, P]
+    lib.orc_diff.restype = i64
+    lib.orc_diff2.argtypes = [i32, i64, P, P, i32, i32, P, P]
+    lib.orc_diff2.restype = i64
+    lib.orc_grad_batch.argtypes = [i32, i64, P, P, P, i64, P, P]
+    lib.orc_grad_batch.restype = i32
+    lib.orc_hess_batch.argtypes = [i32, i64, P, P, P, i64, P, P]
+    lib.orc_hess_batch.restype = i32
+    lib.orc_eval_backward.argtypes = [i32, i64, P, P, P, i64, P, P, P, P]
+    lib.orc_eval_backward.restype = i32
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _u8(e, n):
+    return np.ascontiguousarray(np.asarray(e, dtype=np.uint8).reshape(-1, n))
+
+
+def _f64(c):
+    return np.ascontiguousarray(np.asarray(c, dtype=np.float64).ravel())
+
+
+def _check(rc: int):
+    if rc == -1:
+        raise MemoryError("oracle allocation failed")
+    if rc == -2:
+        raise OverflowError("exponent sum exceeds 255")
+    if rc < 0:
+        raise RuntimeError(f"oracle error {rc}")
+
+
+# --------------------------------------------------------------------- simplify
+
+def simplify(exps, coefs, tol: float = 0.0, n: int | None = None):
+    """``simplify(p, zeroprec)`` (Table "coresemantics"; Table "apisignature"):
+    merge repeated monomials and drop coefficients with |s| <= tol.  Output in
+    canonical order (lex, x1 most significant, ascending)."""
+    n = n if n is not None else np.asarray(exps).shape[1]
+    e = _u8(exps, n)
+    c = _f64(coefs)
+    t = e.shape[0]
+    oe = np.empty((max(t, 1), n), dtype=np.uint8)
+    oc = np.empty(max(t, 1), dtype=np.float64)
+    r = _load().orc_simplify(n, t, _p(e), _p(c), float(tol), _p(oe), _p(oc))
+    _check(r)
+    return oe[:r].copy(), oc[:r].copy()
+
+
+def simplify_batch(row_ptr, exps, coefs, tol: float = 0.0, n: int | None = None):
+    """simplify applied entrywise to a CSR batch (a polynomial matrix is an
+    array of scalar objects, Section 2.1 / 3.1)."""
+    n = n if n is not None else np.asarray(exps).shape[1]
+    rp = np.asarray(row_ptr, dtype=np.int64)
+    e = _u8(exps, n)
+    c = _f64(coefs)
+    outs = []
+    for p in range(rp.shape[0] - 1):
+        outs.append(simplify(e[rp[p]:rp[p + 1]], c[rp[p]:rp[p + 1]], tol, n))
+    return _csr(outs, n)
+
+
+def brute_simplify(exps, coefs, tol: float = 0.0):
+    """Second, independent simplify: a dict keyed by the exponent tuple,
+    accumulated in storage order, emitted in tuple order (Python's tuple
+    comparison is lexicographic with the first variable most significant)."""
+    acc: dict[tuple, float] = {}
+    for row, c in zip(np.asarray(exps).tolist(), np.asarray(coefs, dtype=np.float64).tolist()):
+        k = tuple(row)
+        if k in acc:
+            acc[k] = acc[k] + c
+        else:
+            acc[k] = c
+    keys = sorted(k for k, s in acc.items() if not (abs(s) <= tol))
+    n = np.asarray(exps).shape[1]
+    e = np.array(keys, dtype=np.uint8).reshape(-1, n)
+    c = np.array([acc[k] for k in keys], dtype=np.float64)
+    return e, c
+
+
+# ------------------------------------------------------------------------ times
+
+def expand(ae, ac, be, bc, n: int | None = None):
+    """Raw product terms, i-major (entrywise ``times``, Section 3.3)."""
+    n = n if n is not None else np.asarray(ae).shape[1]
+    ae, be = _u8(ae, n), _u8(be, n)
+    ac, bc = _f64(ac), _f64(bc)
+    raw = ae.shape[0] * be.shape[0]
+    re = np.empty((max(raw, 1), n), dtype=np.uint8)
+    rc = np.empty(max(raw, 1), dtype=np.float64)
+    r = _load().orc_expand(n, ae.shape[0], _p(ae), _p(ac), be.shape[0], _p(be), _p(bc), _p(re), _p(rc))
+    _check(r)
+    return re[:raw].copy(), rc[:raw].copy()
+
+
+def mul(ae, ac, be, bc, tol: float = 0.0, n: int | None = None):
+    """``simplify(a .* b)``: expand every pair of terms, then simplify."""
+    n = n if n is not None else np.asarray(ae).shape[1]
+    ae, be = _u8(ae, n), _u8(be, n)
+    ac, bc = _f64(ac), _f64(bc)
+    raw = ae.shape[0] * be.shape[0]
+    oe = np.empty((max(raw, 1), n), dtype=np.uint8)
+    oc = np.empty(max(raw, 1), dtype=np.float64)
+    r = _load().orc_mul(n, ae.shape[0], _p(ae), _p(ac), be.shape[0], _p(be), _p(bc), float(tol), _p(oe), _p(oc))
+    _check(r)
+    return oe[:r].copy(), oc[:r].copy()
+
+
+def mul_batch(a_rp, a_e, a_c, b_rp, b_e, b_c, tol: float = 0.0, n: int | None = None):
+    """Entrywise ``times`` over two CSR batches of equal length."""
+    n = n if n is not None else np.asarray(a_e).shape[1]
+    a_e, b_e = _u8(a_e, n), _u8(b_e, n)
+    a_c, b_c = _f64(a_c), _f64(b_c)
+    outs = []
+    for p in range(len(a_rp) - 1):
+        outs.append(mul(a_e[a_rp[p]:a_rp[p + 1]], a_c[a_rp[p]:a_rp[p + 1]],
+                        b_e[b_rp[p]:b_rp[p + 1]], b_c[b_rp[p]:b_rp[p + 1]], tol, n))
+    return _csr(outs, n)
+
+
+def _csr(polys, n):
+    rp = np.zeros(len(polys) + 1, dtype=np.int64)
+    for i, (e, _c) in enumerate(polys):
+        rp[i + 1] = rp[i] + e.shape[0]
+    E = np.vstack([e for e, _ in polys]).astype(np.uint8) if polys else np.zeros((0, n), np.uint8)
+    C = np.concatenate([c for _, c in polys]) if polys else np.zeros(0)
+    return rp, E.reshape(-1, n), C
+
+
+# ------------------------------------------------------------------------- eval
+
+def eval_points(exps, coefs, X, n: int | None = None) -> np.ndarray:
+    """``p.eval(x0)`` at each row of X (Section 3.3)."""
+    X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+    n = n if n is not None else X.shape[1]
+    e, c = _u8(exps, n), _f64(coefs)
+    rp = np.array([0, e.shape[0]], dtype=np.int64)
+    return eval_batch(rp, e, c, X)[0]
+
+
+def eval_batch(row_ptr, exps, coefs, X) -> np.ndarray:
+    """Y[p, pt] for every polynomial of a CSR batch at every point."""
+    X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+    n = X.shape[1]
+    rp = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int64))
+    e, c = _u8(exps, n), _f64(coefs)
+    P = rp.shape[0] - 1
+    Y = np.empty((P, X.shape[0]), dtype=np.float64)
+    _load().orc_eval_batch(n, P, _p(rp), _p(e), _p(c), X.shape[0], _p(X), _p(Y))
+    return Y
+
+
+def eval_batch_ld(row_ptr, exps, coefs, X):
+    """Extended-precision (80-bit) evaluation; returns (Y, sum_t |c_t v_t|)."""
+    X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+    n = X.shape[1]
+    rp = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int64))
+    e, c = _u8(exps, n), _f64(coefs)
+    P = rp.shape[0] - 1
+    Y = np.empty((P, X.shape[0]))
+    A = np.empty((P, X.shape[0]))
+    _load().orc_eval_batch_ld(n, P, _p(rp), _p(e), _p(c), X.shape[0], _p(X), _p(Y), _p(A))
+    return Y, A
+
+
+def eval_dense(basis, C, X) -> np.ndarray:
+    """Y = C V for a shared monomial set: Y[p, pt] = sum_k C[p,k] x_pt^basis_k."""
+    X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+    n = X.shape[1]
+    b = _u8(basis, n)
+    C = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
+    P, K = C.shape
+    assert K == b.shape[0]
+    Y = np.empty((P, X.shape[0]))
+    _load().orc_eval_dense(n, K, _p(b), P, _p(C), X.shape[0], _p(X), _p(Y))
+    return Y
+
+
+def eval_dense_ld(basis, C, X):
+    """Extended-precision twin of eval_dense; returns (Y, sum_k |C v|)."""
+    X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+    n = X.shape[1]
+    b = _u8(basis, n)
+    C = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
+    P, K = C.shape
+    Y = np.empty((P, X.shape[0]))
+    A = np.empty((P, X.shape[0]))
+    _load().orc_eval_dense_ld(n, K, _p(b), P, _p(C), X.shape[0], _p(X), _p(Y), _p(A))
+    return Y, A
+
+
+# ------------------------------------------------------------------ derivatives
+
+def diff(exps, coefs, j: int, n: int | None = None):
+    """``diff(p, j)`` with 0-based j (Section 3.3)."""
+    n = n if n is not None else np.asarray(exps).shape[1]
+    e, c = _u8(exps, n), _f64(coefs)
+    oe = np.empty((max(e.shape[0], 1), n), dtype=np.uint8)
+    oc = np.empty(max(e.shape[0], 1))
+    r = _load().orc_diff(n, e.shape[0], _p(e), _p(c), j, _p(oe), _p(oc))
+    return oe[:r].copy(), oc[:r].copy()
+
+
+def diff2(exps, coefs, j: int, k: int, n: int | None = None):
+    """Hessian entry (j,k) as a polynomial, integer multiplier formed first."""
+    n = n if n is not None else np.asarray(exps).shape[1]
+    e, c = _u8(exps, n), _f64(coefs)
+    oe = np.empty((max(e.shape[0], 1), n), dtype=np.uint8)
+    oc = np.empty(max(e.shape[0], 1))
+    r = _load().orc_diff2(n, e.shape[0], _p(e), _p(c), j, k, _p(oe), _p(oc))
+    return oe[:r].copy(), oc[:r].copy()
+
+
+def jacobian_batch(row_ptr, exps, coefs, n: int | None = None):
+    """``jacobian`` of a polynomial vector/matrix flattened to a CSR batch:
+    output entry (p, j) = diff(f_p, j), laid out p-major then j."""
+    n = n if n is not None else np.asarray(exps).shape[1]
+    rp = np.asarray(row_ptr, dtype=np.int64)
+    e, c = _u8(exps, n), _f64(coefs)
+    outs = []
+    for p in range(rp.shape[0] - 1):
+        for j in range(n):
+            outs.append(diff(e[rp[p]:rp[p + 1]], c[rp[p]:rp[p + 1]], j, n))
+    return _csr(outs, n)
+
+
+def grad_batch(row_ptr, exps, coefs, X) -> np.ndarray:
+    """G[p, pt, j] = d f_p / d x_j at x_pt (jacobian then eval)."""
+    X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+    n = X.shape[1]
+    rp = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int64))
+    e, c = _u8(exps, n), _f64(coefs)
+    P = rp.shape[0] - 1
+    G = np.empty((P, X.shape[0], n))
+    _check(_load().orc_grad_batch(n, P, _p(rp), _p(e), _p(c), X.shape[0], _p(X), _p(G)))
+    return G
+
+
+def hess_batch(row_ptr, exps, coefs, X) -> np.ndarray:
+    """H[p, pt, j, k] = d^2 f_p / dx_j dx_k at x_pt, both triangles."""
+    X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+    n = X.shape[1]
+    rp = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int64))
+    e, c = _u8(exps, n), _f64(coefs)
+    P = rp.shape[0] - 1
+    H = np.empty((P, X.shape[0], n, n))
+    _check(_load().orc_hess_batch(n, P, _p(rp), _p(e), _p(c), X.shape[0], _p(X), _p(H)))
+    return H
+
+
+def eval_backward(row_ptr, exps, coefs, X, gY, want_dX: bool = True, want_dC: bool = True):
+    """Reverse mode of Y = eval(f, X) for the cotangent gY[p, pt]:
+    dC[t] = sum_pt gY[p(t), pt] v_t(x_pt); dX[pt, j] = sum_p gY[p, pt] df_p/dx_j."""
+    X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+    n = X.shape[1]
+    rp = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int64))
+    e, c = _u8(exps, n), _f64(coefs)
+    gY = np.ascontiguousarray(np.asarray(gY, dtype=np.float64))
+    P = rp.shape[0] - 1
+    dX = np.empty((X.shape[0], n)) if want_dX else None
+    dC = np.empty(e.shape[0]) if want_dC else None
+    _check(_load().orc_eval_backward(n, P, _p(rp), _p(e), _p(c), X.shape[0], _p(X), _p(gY), _p(dX), _p(dC)))
+    return dX, dC

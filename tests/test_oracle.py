@@ -1,0 +1,411 @@
+"""Pins for the CPU oracle: worked examples the paper prints, closed forms,
+exact identities, brute force on tiny inputs.  No GPU involved.
+
+Each pin is chosen so that a plausible slip in the oracle (a dropped term, a
+wrong sign, a transposed index, a wrong order, an unstable merge) fails at
+least one test here.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import signal
+
+import oracle
+import workloads as W
+from conftest import as_termset, poly_from_json
+
+
+def _poly(g, key):
+    return poly_from_json(g[key], g["n"])
+
+
+# --------------------------------------------------------------- worked examples
+
+def test_w1_canonical_order(golden):
+    g = golden["W1_scalar_workflow"]
+    e, c = _poly(g, "input")
+    oe, oc = oracle.simplify(e, c)
+    xe, xc = _poly(g, "simplified")
+    assert np.array_equal(oe, xe) and np.array_equal(oc, xc)
+    assert int(oe.astype(int).sum(axis=1).max()) == g["degree"]
+
+
+def test_w2_diff_grad_eval(golden):
+    g = golden["W2_differentiation"]
+    n = g["n"]
+    e, c = _poly(g, "input")
+    de, dc = oracle.diff(e, c, 0)
+    # diff keeps storage order; simplify gives the printed (canonical) order
+    se, sc = oracle.simplify(de, dc)
+    xe, xc = poly_from_json(g["diff_x1"], n)
+    assert np.array_equal(se, xe) and np.array_equal(sc, xc)
+    for j, expect in enumerate(g["jacobian"]):
+        je, jc = oracle.diff(e, c, j)
+        ee, ec = poly_from_json(expect, n)
+        assert as_termset(*oracle.simplify(je, jc)) == as_termset(ee, ec)
+    x = np.array([g["point"]], dtype=np.float64)
+    assert oracle.eval_points(e, c, x)[0] == g["value"]
+    G = oracle.grad_batch([0, len(c)], e, c, x)[0, 0]
+    assert G.tolist() == [7.0, 2.0, -1.0]          # [3x1^2 + 2x2, 2x1, -1] at (1,2,3)
+    H = oracle.hess_batch([0, len(c)], e, c, x)[0, 0]
+    assert H.tolist() == [[6.0, 2.0, 0.0], [2.0, 0.0, 0.0], [0.0, 0.0, 0.0]]
+
+
+def test_w3_trace_merge(golden):
+    g = golden["W3_trace"]
+    n = g["n"]
+    parts = [poly_from_json(t, n) for t in g["diagonal"]]
+    e = np.vstack([p[0] for p in parts])
+    c = np.concatenate([p[1] for p in parts])
+    oe, oc = oracle.simplify(e, c)
+    assert as_termset(oe, oc) == as_termset(*_poly(g, "trace"))
+
+
+def test_w4_monolist_count(golden):
+    g = golden["W4_monolist"]
+    assert W.basis(g["n"], g["d"]).shape[0] == g["count"] == math.comb(g["n"] + g["d"], g["d"])
+
+
+def test_w5_simplify_order(golden):
+    g = golden["W5_mixed_simplify"]
+    pe, pc = _poly(g, "p")
+    qe, qc = _poly(g, "q")
+    oe, oc = oracle.simplify(np.vstack([pe, qe]), np.concatenate([pc, qc]))
+    xe, xc = _poly(g, "simplified")
+    assert np.array_equal(oe, xe) and np.array_equal(oc, xc)
+
+
+def test_w6_matrix_ops(golden):
+    g = golden["W6_matrix_ops"]
+    n = g["n"]
+    A = [poly_from_json(t, n) for t in g["A"]]
+    sq = [oracle.mul(a[0], a[1], a[0], a[1]) for a in A]
+    for got, exp in zip(sq, g["elem_square"]):
+        assert as_termset(*got) == as_termset(*poly_from_json(exp, n))
+    assert sq[2][0].shape[0] == 0                    # 0 .* 0 is the structural zero
+    # matrix square: C_ij = simplify(sum_k A_ik A_kj), 2x2 row-major
+    for i in range(2):
+        for j in range(2):
+            prods = [oracle.mul(*A[i * 2 + k], *A[k * 2 + j]) for k in range(2)]
+            e = np.vstack([p[0] for p in prods])
+            c = np.concatenate([p[1] for p in prods])
+            got = oracle.simplify(e, c, n=n)
+            assert as_termset(*got) == as_termset(*poly_from_json(g["matrix_square"][i * 2 + j], n))
+    # sum(A,1): column sums
+    for j in range(2):
+        e = np.vstack([A[j][0], A[2 + j][0]])
+        c = np.concatenate([A[j][1], A[2 + j][1]])
+        assert as_termset(*oracle.simplify(e, c, n=n)) == as_termset(*poly_from_json(g["sum_dim1"][j], n))
+    # prod(A,2): row products
+    for i in range(2):
+        got = oracle.mul(*A[i * 2], *A[i * 2 + 1])
+        assert as_termset(*got) == as_termset(*poly_from_json(g["prod_dim2"][i], n))
+
+
+def test_w8_substitution_expansion(golden):
+    g = golden["W8_substitution"]
+    n = g["n"]
+    ue, uc = _poly(g, "u")
+    assert uc.tolist() == [3.0, 5.0]                 # constructor keeps the caller's order
+    s = _poly(g, "z1_plus_1")
+    sq = oracle.mul(*s, *s)                          # (z1+1)^2
+    three = (np.zeros((1, n), np.uint8), np.array([3.0]))
+    t1 = oracle.mul(*three, *sq)
+    e = np.vstack([t1[0], np.array([[0, 1]], np.uint8)])
+    c = np.concatenate([t1[1], [5.0]])
+    assert as_termset(*oracle.simplify(e, c)) == as_termset(*_poly(g, "result"))
+
+
+def test_w9_quadratic_form(golden):
+    g = golden["W9_quadratic_form"]
+    n = g["n"]
+    Q = g["Q"]
+    b = [poly_from_json(t, n) for t in g["b"]]
+    es, cs = [], []
+    for i in range(2):
+        for j in range(2):
+            qe, qc = oracle.mul(*b[i], *b[j])
+            es.append(qe)
+            cs.append(qc * Q[i][j])
+    got = oracle.simplify(np.vstack(es), np.concatenate(cs))
+    assert as_termset(*got) == as_termset(*_poly(g, "qf"))
+
+
+def test_w11_gradient_norm(golden):
+    g = golden["W11_affine_example_gradient"]
+    e, c = _poly(g, "f")
+    G = oracle.grad_batch([0, len(c)], e, c, np.array([g["x0"]]))[0, 0]
+    assert round(float(np.linalg.norm(G)), 6) == g["grad_norm"]
+
+
+def test_xy_square(golden):
+    g = golden["XY_square"]
+    p = _poly(g, "p")
+    oe, oc = oracle.mul(*p, *p)
+    xe, xc = _poly(g, "square")
+    assert np.array_equal(oe, xe) and np.array_equal(oc, xc)
+
+
+# ------------------------------------------------------------------ closed forms
+
+@pytest.mark.parametrize("n,d", [(2, 2), (3, 4), (4, 5), (5, 3), (6, 4)])
+def test_multinomial_closed_form(n, d):
+    """(x1+...+xn)^d has C(n+d-1, d) terms with coefficients d!/prod(a_i!)."""
+    lin = (np.eye(n, dtype=np.uint8), np.ones(n))
+    acc = (np.zeros((1, n), np.uint8), np.ones(1))
+    for _ in range(d):
+        acc = oracle.mul(*acc, *lin)
+    e, c = acc
+    assert e.shape[0] == math.comb(n + d - 1, d)
+    for row, coef in zip(e.astype(int).tolist(), c.tolist()):
+        assert sum(row) == d
+        expect = math.factorial(d)
+        for a in row:
+            expect //= math.factorial(a)
+        assert coef == expect
+    # ascending canonical order
+    assert all(tuple(e[i]) < tuple(e[i + 1]) for i in range(e.shape[0] - 1))
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_pd_cubed_closed_form(golden, d):
+    """simplify(p_d^3) in five variables (Section 6.3): C(3d+5, 5) terms; the
+    coefficient of x^g counts triples (a, b, c), |a|,|b|,|c| <= d, a+b+c = g.
+    The counts come from a dense 5-D convolution (no sorting, no merging)."""
+    n = 5
+    e, c = W.all_ones_family(n, d)
+    assert e.shape[0] == golden["PD_family"]["base_counts"][str(d)]
+    sq = oracle.mul(e, c, e, c)
+    cube = oracle.mul(*sq, e, c)
+    assert cube[0].shape[0] == math.comb(3 * d + 5, 5)
+    ind = np.zeros((d + 1,) * n)
+    for row in e.astype(int):
+        ind[tuple(row)] = 1.0
+    dense = signal.convolve(signal.convolve(ind, ind, method="direct"), ind, method="direct")
+    dense = np.rint(dense).astype(np.int64)
+    nz = np.argwhere(dense > 0)
+    assert nz.shape[0] == cube[0].shape[0]
+    for row, coef in zip(cube[0].astype(int), cube[1]):
+        assert dense[tuple(row)] == coef
+
+
+# ------------------------------------------------------------------- brute force
+
+@pytest.mark.parametrize("seed", range(12))
+def test_simplify_matches_brute_force(seed):
+    rng = W.rng_for(1000 + seed)
+    n = int(rng.integers(1, 6))
+    d = int(rng.integers(0, 5))
+    t = int(rng.integers(0, 60))
+    e, c = W.random_poly(rng, n, d, t, integer=bool(seed % 2))
+    if seed % 3 == 0 and t:
+        c[rng.integers(0, t, size=max(1, t // 5))] = 0.0
+    for tol in (0.0, 0.5):
+        oe, oc = oracle.simplify(e, c, tol, n=n)
+        be, bc = oracle.brute_simplify(e.reshape(-1, n), c, tol)
+        assert np.array_equal(oe, be)
+        assert oc.view(np.uint64).tolist() == bc.view(np.uint64).tolist()
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_mul_matches_brute_force(seed):
+    rng = W.rng_for(2000 + seed)
+    n = int(rng.integers(1, 5))
+    a = W.random_poly(rng, n, 3, int(rng.integers(0, 12)), integer=bool(seed % 2))
+    b = W.random_poly(rng, n, 3, int(rng.integers(0, 12)), integer=bool(seed % 2))
+    # brute force: nested loops over a Python dict
+    raw_e, raw_c = [], []
+    for i in range(a[0].shape[0]):
+        for j in range(b[0].shape[0]):
+            raw_e.append([int(x) + int(y) for x, y in zip(a[0][i], b[0][j])])
+            raw_c.append(float(a[1][i]) * float(b[1][j]))
+    be, bc = oracle.brute_simplify(np.array(raw_e, dtype=np.uint8).reshape(-1, n), np.array(raw_c))
+    oe, oc = oracle.mul(*a, *b, n=n)
+    assert np.array_equal(oe, be)
+    assert oc.view(np.uint64).tolist() == bc.view(np.uint64).tolist()
+
+
+def test_zero_rule_and_nan():
+    e = np.array([[1], [1], [2], [3], [3], [4]], dtype=np.uint8)
+    c = np.array([1.0, -1.0, 1e-3, np.nan, 1.0, -0.0])
+    oe, oc = oracle.simplify(e, c, 0.0)
+    assert oe.ravel().tolist() == [2, 3]             # 1-1 = 0 and -0.0 dropped; NaN kept
+    assert oc[0] == 1e-3 and np.isnan(oc[1])
+    oe, oc = oracle.simplify(e, c, 1e-3)
+    assert oe.ravel().tolist() == [3]                # |1e-3| <= tol is dropped
+
+
+# ------------------------------------------------------------------- identities
+
+def test_mul_coefficient_sum_invariant():
+    wl = W.plain_small()
+    oe, oc = oracle.mul(wl.a_exps, wl.a_coefs, wl.b_exps, wl.b_coefs)
+    assert oc.sum() == wl.a_coefs.sum() * wl.b_coefs.sum()
+    assert oe.shape[0] <= 1820 and (oc != 0).all()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_eval_product_identity_bitwise(seed):
+    """eval(p*q) == eval(p)*eval(q) exactly at small integer points with
+    integer coefficients (every intermediate stays below 2^53)."""
+    rng = W.rng_for(3000 + seed)
+    n = 3
+    p = W.random_poly(rng, n, 4, 15)
+    q = W.random_poly(rng, n, 4, 15)
+    pq = oracle.mul(*p, *q)
+    X = W.integer_points(3100 + seed, 32, n)
+    yp = oracle.eval_points(*p, X)
+    yq = oracle.eval_points(*q, X)
+    ypq = oracle.eval_points(*pq, X)
+    assert np.array_equal(ypq, yp * yq)
+
+
+def test_eval_constants_and_empty():
+    X = np.array([[0.0, 0.0], [2.0, -1.0]])
+    empty = (np.zeros((0, 2), np.uint8), np.zeros(0))
+    assert oracle.eval_points(*empty, X).tolist() == [0.0, 0.0]
+    const = (np.zeros((1, 2), np.uint8), np.array([-4.5]))
+    assert oracle.eval_points(*const, X).tolist() == [-4.5, -4.5]
+    zero_pow = (np.array([[0, 3]], np.uint8), np.array([2.0]))   # 0^0 = 1 at x1 = 0
+    assert oracle.eval_points(*zero_pow, X).tolist() == [0.0, -2.0]
+
+
+def test_eval_dense_against_numpy_power():
+    b = W.basis(3, 4)
+    rng = W.rng_for(77)
+    C = rng.integers(-5, 6, size=(4, b.shape[0])).astype(np.float64)
+    X = W.integer_points(78, 10, 3, -2, 2)
+    V = np.prod(X[None, :, :] ** b.astype(np.float64)[:, None, :], axis=2)   # [K, N]
+    assert np.array_equal(oracle.eval_dense(b, C, X), C @ V)
+    Yld, A = oracle.eval_dense_ld(b, C, X)
+    assert np.array_equal(Yld, C @ V)
+
+
+@pytest.mark.parametrize("d", [2, 3, 4])
+def test_euler_identities_bitwise(d):
+    n = 4
+    e, c = W.homogeneous(40 + d, n, d, 25)
+    X = W.integer_points(50 + d, 16, n, -3, 3)
+    rp = [0, e.shape[0]]
+    f = oracle.eval_batch(rp, e, c, X)[0]
+    G = oracle.grad_batch(rp, e, c, X)[0]
+    H = oracle.hess_batch(rp, e, c, X)[0]
+    assert np.array_equal((G * X).sum(axis=1), d * f)
+    assert np.array_equal(np.einsum("pjk,pk->pj", H, X), (d - 1) * G)
+
+
+def test_hessian_symmetry_and_second_jacobian():
+    rng = W.rng_for(91)
+    n = 5
+    e, c = W.random_poly(rng, n, 5, 40, integer=False)
+    X = W.points(92, 8, n)
+    H = oracle.hess_batch([0, e.shape[0]], e, c, X)[0]
+    assert np.array_equal(H, np.swapaxes(H, 1, 2))
+    # with integer coefficients the Hessian equals jacobian(jacobian(p)) exactly
+    ei, ci = W.random_poly(rng, n, 5, 40, integer=True)
+    Hi = oracle.hess_batch([0, ei.shape[0]], ei, ci, X)[0]
+    for j in range(n):
+        dj = oracle.diff(ei, ci, j)
+        for k in range(n):
+            djk = oracle.diff(*dj, k)
+            assert np.array_equal(oracle.eval_points(*djk, X), Hi[:, j, k])
+
+
+def test_gradient_and_hessian_vs_finite_differences():
+    rng = W.rng_for(93)
+    n = 4
+    e, c = W.random_poly(rng, n, 4, 30, integer=False)
+    X = W.points(94, 6, n, -0.9, 0.9)
+    rp = [0, e.shape[0]]
+    G = oracle.grad_batch(rp, e, c, X)[0]
+    H = oracle.hess_batch(rp, e, c, X)[0]
+    h = 1e-5
+    for j in range(n):
+        Xp, Xm = X.copy(), X.copy()
+        Xp[:, j] += h
+        Xm[:, j] -= h
+        fd = (oracle.eval_batch(rp, e, c, Xp)[0] - oracle.eval_batch(rp, e, c, Xm)[0]) / (2 * h)
+        assert np.allclose(fd, G[:, j], rtol=1e-7, atol=1e-7)
+        fdg = (oracle.grad_batch(rp, e, c, Xp)[0] - oracle.grad_batch(rp, e, c, Xm)[0]) / (2 * h)
+        assert np.allclose(fdg, H[:, :, j], rtol=1e-6, atol=1e-6)
+
+
+def test_diff_product_rule_bitwise():
+    rng = W.rng_for(95)
+    n = 3
+    p = W.random_poly(rng, n, 3, 10)
+    q = W.random_poly(rng, n, 3, 10)
+    X = W.integer_points(96, 12, n)
+    pq = oracle.mul(*p, *q)
+    for j in range(n):
+        lhs = oracle.eval_points(*oracle.diff(*pq, j), X)
+        rhs = oracle.eval_points(*oracle.diff(*p, j), X) * oracle.eval_points(*q, X) \
+            + oracle.eval_points(*p, X) * oracle.eval_points(*oracle.diff(*q, j), X)
+        assert np.array_equal(lhs, rhs)
+
+
+def test_eval_backward_pins():
+    rng = W.rng_for(97)
+    n = 3
+    polys = [W.random_poly(rng, n, 3, k) for k in (7, 0, 12)]
+    rp, E, C = W.csr_from_list(polys, n)
+    X = W.integer_points(98, 9, n, -2, 2)
+    P = len(polys)
+    # gY = 1: dX is the sum of gradients; dC_t is the sum over points of v_t
+    dX, dC = oracle.eval_backward(rp, E, C, X, np.ones((P, X.shape[0])))
+    G = oracle.grad_batch(rp, E, C, X)
+    assert np.array_equal(dX, G.sum(axis=0))
+    V = np.prod(X[None, :, :] ** E.astype(np.float64)[:, None, :], axis=2)
+    assert np.array_equal(dC, V.sum(axis=1))
+    # linearity in C: <gY, Y(C + dC') - Y(C)> = <dC, dC'>  (integers: exact)
+    gY = rng.integers(-3, 4, size=(P, X.shape[0])).astype(np.float64)
+    _, dC = oracle.eval_backward(rp, E, C, X, gY, want_dX=False)
+    delta = rng.integers(-3, 4, size=C.shape[0]).astype(np.float64)
+    Y0 = oracle.eval_batch(rp, E, C, X)
+    Y1 = oracle.eval_batch(rp, E, C + delta, X)
+    assert (gY * (Y1 - Y0)).sum() == (dC * delta).sum()
+
+
+def test_eval_backward_dx_vs_finite_differences():
+    rng = W.rng_for(99)
+    n = 3
+    polys = [W.random_poly(rng, n, 4, 9, integer=False) for _ in range(3)]
+    rp, E, C = W.csr_from_list(polys, n)
+    X = W.points(100, 5, n)
+    gY = rng.standard_normal((3, 5))
+    dX, _ = oracle.eval_backward(rp, E, C, X, gY, want_dC=False)
+    h = 1e-6
+    for pt in range(5):
+        for j in range(n):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[pt, j] += h
+            Xm[pt, j] -= h
+            fd = ((oracle.eval_batch(rp, E, C, Xp) - oracle.eval_batch(rp, E, C, Xm)) * gY).sum() / (2 * h)
+            assert abs(fd - dX[pt, j]) <= 1e-7 * (1 + abs(fd))
+
+
+def test_fp64_eval_within_error_bound_of_long_double():
+    wl = W.quartic(seed=5, n=12, terms=1500, npts=64)
+    rp = [0, wl.exps.shape[0]]
+    y = oracle.eval_batch(rp, wl.exps, wl.coefs, wl.X)[0]
+    yl, A = oracle.eval_batch_ld(rp, wl.exps, wl.coefs, wl.X)
+    # a-priori bound for a T-term recursive sum of products of <= 5 factors
+    T = wl.exps.shape[0]
+    bound = (T + 6) * 2.0 ** -53 * A[0]
+    assert (np.abs(y - yl[0]) <= bound).all()
+
+
+def test_jacobian_batch_layout():
+    rng = W.rng_for(101)
+    n = 3
+    polys = [W.random_poly(rng, n, 3, k) for k in (5, 0, 8)]
+    rp, E, C = W.csr_from_list(polys, n)
+    jrp, jE, jC = oracle.jacobian_batch(rp, E, C)
+    assert jrp.shape[0] == 3 * n + 1
+    for p in range(3):
+        for j in range(n):
+            k = p * n + j
+            de, dc = oracle.diff(*polys[p], j)
+            assert np.array_equal(jE[jrp[k]:jrp[k + 1]], de)
+            assert np.array_equal(jC[jrp[k]:jrp[k + 1]], dc)
