@@ -1,0 +1,192 @@
+/*
+ * polyhip -- C ABI of the MI355X (gfx950) sparse monomial-table algebra core.
+ *
+ * Operations follow "Polylab: A MATLAB Toolbox for Multivariate Polynomial
+ * Modeling" (Niu & Yau):
+ *   poly_mul       entrywise times followed by simplify   (Table "coresemantics"; Section 3.3)
+ *   poly_simplify  merge repeated monomials, drop |s| <= tol (Table "apisignature", simplify(p,zeroprec))
+ *   poly_jacobian  symbolic diff / jacobian                 (Section 3.3, diff(p,i), jacobian(p))
+ *   poly_eval      value at numeric points                  (Section 3.3, p.eval(x0))
+ *   poly_grad      gradient row evaluated at points         (Table "apisignature", g = jacobian(p))
+ *   poly_hess      Hessian array evaluated at points        (Table "apisignature", H = jacobian(g))
+ *   poly_eval_backward  reverse mode of poly_eval w.r.t. points and coefficients
+ *   poly_eval_dense     P polynomials over one shared monomial set (coefficient
+ *                       matrix times monomial-value matrix), in FP64 or in
+ *                       split BF16 products with FP32 accumulation and FP64
+ *                       recombination.
+ *
+ * Data model.  A polynomial in n variables is T terms; term t has a row of n
+ * unsigned 8-bit exponents and an FP64 coefficient (the coefficient/exponent
+ * constructor MPOLY(n,coef,pow), Table "apisignature").  A batch of P
+ * polynomials (a polynomial matrix flattened row-major, or any list) is CSR:
+ * polynomial p owns terms [row_ptr[p], row_ptr[p+1]).  Zero terms is the
+ * structural zero polynomial.
+ *
+ * Canonical order.  Outputs of poly_mul and poly_simplify list each
+ * polynomial's terms with exponent rows in ascending lexicographic order,
+ * x1 most significant (the order of the paper's simplify(p+q) transcript,
+ * Section 3.2).  Equal rows are merged by summing their coefficients in the
+ * order the raw terms appear (for poly_mul: term i of a, then term j of b,
+ * i-major) and the merged term is kept iff !(|s| <= zero_tol).
+ *
+ * Memory.  Every pointer is a DEVICE pointer unless its comment says [host].
+ * The caller owns all memory (inputs, outputs, workspace).  The library keeps
+ * no per-call state and allocates nothing on the device; every entry point
+ * enqueues its kernels on `stream` (a hipStream_t passed as void*, NULL = the
+ * default stream) and returns without synchronising.
+ *
+ * Errors.  Every entry point returns a poly_status.  Argument, shape and
+ * size errors are detected on the host before any launch.  Data-dependent
+ * problems found on the device (an exponent above the declared max_exp, an
+ * output capacity that is too small) are recorded in the first 256 bytes of
+ * the workspace; poly_read_status() synchronises the stream and returns them.
+ * A launch failure returns POLY_ERR_HIP.
+ */
+#ifndef POLYHIP_H
+#define POLYHIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum poly_status {
+    POLY_OK = 0,
+    POLY_ERR_ARG = 1,          /* bad pointer, size or shape (host-detected)          */
+    POLY_ERR_KEY_OVERFLOW = 2, /* n * field width exceeds the 64-bit key              */
+    POLY_ERR_WORKSPACE = 3,    /* workspace smaller than the query returned           */
+    POLY_ERR_CAPACITY = 4,     /* output capacity too small (device-detected)         */
+    POLY_ERR_EXPONENT = 5,     /* an exponent exceeds the declared max_exp (device)   */
+    POLY_ERR_UNSUPPORTED = 6,  /* shape beyond this library's limits                  */
+    POLY_ERR_HIP = 7           /* a HIP runtime call or kernel launch failed          */
+} poly_status;
+
+typedef enum poly_prec {
+    POLY_FP64 = 0,             /* FP64 arithmetic throughout                           */
+    POLY_SPLIT_BF16 = 1        /* split BF16 slices, FP32 MFMA accumulation, FP64 sum  */
+} poly_prec;
+
+/* A CSR batch of npolys polynomials, all in nvars variables.
+ *   nvars        n, 1 <= n <= 255.
+ *   max_exp      [host] caller's bound on every exponent stored in exps
+ *                (0..255).  Packed-key widths are derived from it; a stored
+ *                exponent above it is reported as POLY_ERR_EXPONENT.
+ *   npolys       P >= 0.
+ *   capacity     number of term slots allocated in exps / coefs.
+ *   row_ptr_host [host] copy of row_ptr (P+1 entries) for inputs; the
+ *                library plans launches from it and never reads row_ptr on
+ *                the host.  Ignored (may be NULL) for outputs.
+ *   row_ptr      [P+1] int64, row_ptr[0] = 0, nondecreasing.  Written by the
+ *                library for outputs.
+ *   exps         [capacity * n] uint8, row-major (term-major).
+ *   coefs        [capacity] double. */
+typedef struct poly_csr {
+    int32_t nvars;
+    int32_t max_exp;
+    int64_t npolys;
+    int64_t capacity;
+    const int64_t *row_ptr_host;
+    int64_t *row_ptr;
+    uint8_t *exps;
+    double *coefs;
+} poly_csr;
+
+/* Human-readable text for a status code. Never NULL. */
+const char *poly_strerror(int32_t status);
+
+/* Synchronises `stream`, then returns the device-detected status recorded in
+ * the workspace `ws` by the last call that used it (POLY_OK if none). */
+poly_status poly_read_status(const void *ws, void *stream);
+
+/* ---------------------------------------------------------------- simplify
+ * out_p = simplify(in_p, zero_tol) for every p (Table "coresemantics").
+ * Inputs may hold repeated monomials in any order.  All P entries are
+ * processed by one persistent launch that takes entries largest first.
+ * out->npolys must equal in->npolys, out->nvars in->nvars; out->capacity >=
+ * total input terms always suffices.  zero_tol >= 0 (NaN sums are kept).
+ * Exponent rows are packed into 64-bit keys with b = bit width of max_exp
+ * bits per variable, x1 in the top field; n*b > 64 -> POLY_ERR_KEY_OVERFLOW. */
+poly_status poly_simplify_workspace(const poly_csr *in, size_t *ws_bytes);
+poly_status poly_simplify(const poly_csr *in, poly_csr *out, double zero_tol,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/* --------------------------------------------------------------------- mul
+ * out_p = simplify(a_p .* b_p, zero_tol): every term of a_p times every term
+ * of b_p (exponent rows added, coefficients multiplied once, no fused
+ * multiply-add), then merged as in poly_simplify (Section 3.3, entrywise
+ * times; Section 6.3, expansion followed by simplify).  a and b must have
+ * equal nvars and npolys.  Field width b = bit width of
+ * (a->max_exp + b->max_exp); n*b > 64 -> POLY_ERR_KEY_OVERFLOW.  Per pair,
+ * |a_p| * |b_p| must be below 2^32.  *raw_terms (host) receives
+ * sum_p |a_p| * |b_p|; out->capacity >= that always suffices (the exact need
+ * is the final row_ptr[P]).  The raw product terms are never written to
+ * memory: they are generated per key range inside the merge kernel. */
+poly_status poly_mul_workspace(const poly_csr *a, const poly_csr *b,
+                               size_t *ws_bytes, int64_t *raw_terms);
+poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out,
+                     double zero_tol, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------- jacobian
+ * Symbolic Jacobian (Section 3.3): out entry p*n + j = diff(in_p, x_{j+1}).
+ * A term with e_j > 0 becomes (e - u_j, c * e_j); other terms vanish; term
+ * order is preserved.  out->npolys = P * n; out->capacity >= n * total input
+ * terms always suffices. */
+poly_status poly_jacobian_workspace(const poly_csr *in, size_t *ws_bytes);
+poly_status poly_jacobian(const poly_csr *in, poly_csr *out,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------- evaluation
+ * X is [N * n] row-major FP64 points.  x^0 = 1 (also 0^0); an empty
+ * polynomial evaluates to 0.
+ *   poly_eval: Y[p*N + pt]                = f_p(x_pt)
+ *   poly_grad: G[(p*N + pt)*n + j]        = d f_p / d x_{j+1} (x_pt)
+ *   poly_hess: H[((p*N + pt)*n + j)*n + k] = d^2 f_p / dx_{j+1} dx_{k+1} (x_pt),
+ *              both triangles, bitwise symmetric (each Hessian entry is the
+ *              polynomial with coefficient c * e_j * (e_k - [j==k]), the
+ *              integer multiplier formed first).
+ * Summation order inside the library is not the oracle's storage order, so
+ * results agree with a sequential FP64 sum to rounding, not bitwise. */
+poly_status poly_eval_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes);
+poly_status poly_eval(const poly_csr *f, const double *X, int64_t N, double *Y,
+                      void *ws, size_t ws_bytes, void *stream);
+poly_status poly_grad_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes);
+poly_status poly_grad(const poly_csr *f, const double *X, int64_t N, double *G,
+                      void *ws, size_t ws_bytes, void *stream);
+poly_status poly_hess_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes);
+poly_status poly_hess(const poly_csr *f, const double *X, int64_t N, double *H,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/* Reverse mode of Y = poly_eval(f, X) for a cotangent gY[P*N]:
+ *   dC[t]        = sum_pt gY[p(t)*N + pt] * x_pt^{e_t}          (may be NULL)
+ *   dX[pt*n + j] = sum_p  gY[p*N + pt] * d f_p / d x_{j+1}(x_pt) (may be NULL) */
+poly_status poly_eval_backward_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes);
+poly_status poly_eval_backward(const poly_csr *f, const double *X, int64_t N,
+                               const double *gY, double *dX, double *dC,
+                               void *ws, size_t ws_bytes, void *stream);
+
+/* ----------------------------------------------------- shared monomial set
+ * Y[p*N + pt] = sum_k C[p*K + k] * prod_i X[pt*n + i]^basis[k*n + i]:
+ * P polynomials over one set of K monomials (basis, [K * n] uint8), i.e. the
+ * coefficient matrix C [P x K] times the monomial-value matrix V [K x N]
+ * built on the fly from per-point power tables.
+ *   prec = POLY_FP64:       V and the products in FP64 (FP64 MFMA).
+ *   prec = POLY_SPLIT_BF16: C and V are split into `nslices` BF16 slices
+ *       with a power-of-two scale per (row, K-block) and (point, K-block);
+ *       slice products are accumulated exactly in FP32 by BF16 MFMA within
+ *       each K-block and recombined in FP64.  nslices in [2, 8]; pairs with
+ *       s + t > nslices + 1 are skipped.
+ * Error of the split result relative to sum_k |C v| is about 2^-(8*nslices - 10). */
+poly_status poly_eval_dense_workspace(int32_t n, int64_t K, int64_t P, int64_t N,
+                                      poly_prec prec, int32_t nslices, size_t *ws_bytes);
+poly_status poly_eval_dense(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp,
+                            int64_t P, const double *C, int64_t N, const double *X,
+                            double *Y, poly_prec prec, int32_t nslices,
+                            void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLYHIP_H */

@@ -1,0 +1,368 @@
+"""Python binding of the polyhip C ABI (``include/polyhip.h``).
+
+Argument marshalling only: torch supplies device memory and the current HIP
+stream; every step of every operation runs in the library's HIP kernels.
+There is no CPU fallback: if ``libpolyhip.so`` is missing or no GPU is
+present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+__all__ = [
+    "Batch", "PolyError", "PolyEval", "batch_from_numpy", "batch_to_numpy", "mul", "simplify", "jacobian",
+    "eval", "grad", "hess", "eval_backward", "eval_dense", "library_path", "lib",
+    "POLY_FP64", "POLY_SPLIT_BF16",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libpolyhip.so")
+_lib = None
+
+POLY_FP64 = 0
+POLY_SPLIT_BF16 = 1
+
+EXPORTS = [
+    "poly_strerror", "poly_read_status",
+    "poly_simplify_workspace", "poly_simplify",
+    "poly_mul_workspace", "poly_mul",
+    "poly_jacobian_workspace", "poly_jacobian",
+    "poly_eval_workspace", "poly_eval",
+    "poly_grad_workspace", "poly_grad",
+    "poly_hess_workspace", "poly_hess",
+    "poly_eval_backward_workspace", "poly_eval_backward",
+    "poly_eval_dense_workspace", "poly_eval_dense",
+]
+
+
+class PolyError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = lib().poly_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{where}: status {code} ({msg})")
+
+
+class PolyCSR(ctypes.Structure):
+    _fields_ = [
+        ("nvars", ctypes.c_int32),
+        ("max_exp", ctypes.c_int32),
+        ("npolys", ctypes.c_int64),
+        ("capacity", ctypes.c_int64),
+        ("row_ptr_host", ctypes.c_void_p),
+        ("row_ptr", ctypes.c_void_p),
+        ("exps", ctypes.c_void_p),
+        ("coefs", ctypes.c_void_p),
+    ]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libpolyhip.so (built in-tree by ``paper_2604_06575_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {_LIB_PATH} is missing "
+                           "(run `python -m paper_2604_06575_amd.build`)")
+    L = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    i32 = ctypes.c_int32
+    d = ctypes.c_double
+    pcsr = ctypes.POINTER(PolyCSR)
+    psz = ctypes.POINTER(ctypes.c_size_t)
+    sig = {
+        "poly_strerror": ([i32], ctypes.c_char_p),
+        "poly_read_status": ([P, P], i32),
+        "poly_simplify_workspace": ([pcsr, psz], i32),
+        "poly_simplify": ([pcsr, pcsr, d, P, ctypes.c_size_t, P], i32),
+        "poly_mul_workspace": ([pcsr, pcsr, psz, ctypes.POINTER(i64)], i32),
+        "poly_mul": ([pcsr, pcsr, pcsr, d, P, ctypes.c_size_t, P], i32),
+        "poly_jacobian_workspace": ([pcsr, psz], i32),
+        "poly_jacobian": ([pcsr, pcsr, P, ctypes.c_size_t, P], i32),
+        "poly_eval_workspace": ([pcsr, i64, psz], i32),
+        "poly_eval": ([pcsr, P, i64, P, P, ctypes.c_size_t, P], i32),
+        "poly_grad_workspace": ([pcsr, i64, psz], i32),
+        "poly_grad": ([pcsr, P, i64, P, P, ctypes.c_size_t, P], i32),
+        "poly_hess_workspace": ([pcsr, i64, psz], i32),
+        "poly_hess": ([pcsr, P, i64, P, P, ctypes.c_size_t, P], i32),
+        "poly_eval_backward_workspace": ([pcsr, i64, psz], i32),
+        "poly_eval_backward": ([pcsr, P, i64, P, P, P, P, ctypes.c_size_t, P], i32),
+        "poly_eval_dense_workspace": ([i32, i64, i64, i64, i32, i32, psz], i32),
+        "poly_eval_dense": ([i32, i64, P, i32, i64, P, i64, P, P, i32, i32, P, ctypes.c_size_t, P], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise PolyError(code, where)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None or t.numel() == 0 else ctypes.c_void_p(t.data_ptr())
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+# --------------------------------------------------------------------- batches
+
+@dataclass
+class Batch:
+    """A CSR batch of polynomials on the GPU.
+
+    ``row_ptr`` (int64 [P+1]) lives on the device and ``row_ptr_host``
+    (numpy int64 [P+1]) is its host copy; ``exps`` is uint8 [T, n] and
+    ``coefs`` float64 [T], both on the device.  ``max_exp`` bounds every
+    stored exponent."""
+    n: int
+    max_exp: int
+    row_ptr: torch.Tensor
+    row_ptr_host: np.ndarray
+    exps: torch.Tensor
+    coefs: torch.Tensor
+
+    @property
+    def npolys(self) -> int:
+        return int(self.row_ptr_host.shape[0] - 1)
+
+    @property
+    def nterms(self) -> int:
+        return int(self.row_ptr_host[-1])
+
+    def csr(self) -> PolyCSR:
+        c = PolyCSR()
+        c.nvars = self.n
+        c.max_exp = self.max_exp
+        c.npolys = self.npolys
+        c.capacity = int(self.coefs.shape[0])
+        self._rph = np.ascontiguousarray(self.row_ptr_host, dtype=np.int64)
+        c.row_ptr_host = self._rph.ctypes.data_as(ctypes.c_void_p)
+        c.row_ptr = ctypes.c_void_p(self.row_ptr.data_ptr())
+        c.exps = _ptr(self.exps)
+        c.coefs = _ptr(self.coefs)
+        return c
+
+    def with_coefs(self, coefs: torch.Tensor) -> "Batch":
+        return Batch(self.n, self.max_exp, self.row_ptr, self.row_ptr_host, self.exps, coefs)
+
+
+def batch_from_numpy(row_ptr, exps, coefs, n: int | None = None, max_exp: int | None = None,
+                     device="cuda") -> Batch:
+    exps = np.ascontiguousarray(np.asarray(exps, dtype=np.uint8))
+    n = n if n is not None else exps.shape[1]
+    exps = exps.reshape(-1, n)
+    rp = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int64))
+    me = int(exps.max()) if (max_exp is None and exps.size) else (max_exp or 0)
+    return Batch(n, me, torch.from_numpy(rp).to(device), rp,
+                 torch.from_numpy(exps).to(device),
+                 torch.from_numpy(np.ascontiguousarray(np.asarray(coefs, dtype=np.float64))).to(device))
+
+
+def batch_to_numpy(b: Batch):
+    T = b.nterms
+    return (b.row_ptr_host.copy(), b.exps[:T].cpu().numpy().reshape(-1, b.n), b.coefs[:T].cpu().numpy())
+
+
+def _empty_out(n: int, P: int, cap: int, max_exp: int, device) -> Batch:
+    return Batch(n, max_exp, torch.zeros(P + 1, dtype=torch.int64, device=device), np.zeros(P + 1, np.int64),
+                 torch.empty((max(cap, 1), n), dtype=torch.uint8, device=device),
+                 torch.empty(max(cap, 1), dtype=torch.float64, device=device))
+
+
+def _finish(out: Batch, ws: torch.Tensor, where: str, trim: bool) -> Batch:
+    """Read back the device row pointer (one sync) and the device status."""
+    st = lib().poly_read_status(ctypes.c_void_p(ws.data_ptr()), _stream())
+    _check(st, where)
+    out.row_ptr_host = out.row_ptr.cpu().numpy()
+    if trim:
+        T = out.nterms
+        out.exps = out.exps[:T]
+        out.coefs = out.coefs[:T]
+    return out
+
+
+# ------------------------------------------------------------------ operations
+
+def simplify(b: Batch, tol: float = 0.0, trim: bool = True) -> Batch:
+    """simplify(p, zeroprec) for every entry of the batch."""
+    L = lib()
+    cin = b.csr()
+    ws_bytes = ctypes.c_size_t()
+    _check(L.poly_simplify_workspace(ctypes.byref(cin), ctypes.byref(ws_bytes)), "poly_simplify_workspace")
+    ws = _workspace(ws_bytes.value, b.coefs.device)
+    out = _empty_out(b.n, b.npolys, b.nterms, b.max_exp, b.coefs.device)
+    cout = out.csr()
+    _check(L.poly_simplify(ctypes.byref(cin), ctypes.byref(cout), float(tol), ctypes.c_void_p(ws.data_ptr()),
+                           ws.numel(), _stream()), "poly_simplify")
+    return _finish(out, ws, "poly_simplify", trim)
+
+
+def mul_workspace(a: Batch, b: Batch) -> tuple[int, int]:
+    L = lib()
+    ca, cb = a.csr(), b.csr()
+    ws_bytes = ctypes.c_size_t()
+    raw = ctypes.c_int64()
+    _check(L.poly_mul_workspace(ctypes.byref(ca), ctypes.byref(cb), ctypes.byref(ws_bytes), ctypes.byref(raw)),
+           "poly_mul_workspace")
+    return int(ws_bytes.value), int(raw.value)
+
+
+def mul(a: Batch, b: Batch, tol: float = 0.0, trim: bool = True, ws: torch.Tensor | None = None,
+        out: Batch | None = None, finish: bool = True) -> Batch:
+    """Entrywise simplify(a_p .* b_p)."""
+    L = lib()
+    ca, cb = a.csr(), b.csr()
+    ws_bytes, raw = mul_workspace(a, b)
+    if ws is None or ws.numel() < ws_bytes:
+        ws = _workspace(ws_bytes, a.coefs.device)
+    if out is None:
+        out = _empty_out(a.n, a.npolys, raw, a.max_exp + b.max_exp, a.coefs.device)
+    cout = out.csr()
+    _check(L.poly_mul(ctypes.byref(ca), ctypes.byref(cb), ctypes.byref(cout), float(tol),
+                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "poly_mul")
+    if not finish:
+        return out
+    return _finish(out, ws, "poly_mul", trim)
+
+
+def jacobian(b: Batch, trim: bool = True) -> Batch:
+    """Symbolic Jacobian: entry p*n + j = diff(b_p, x_{j+1})."""
+    L = lib()
+    cin = b.csr()
+    ws_bytes = ctypes.c_size_t()
+    _check(L.poly_jacobian_workspace(ctypes.byref(cin), ctypes.byref(ws_bytes)), "poly_jacobian_workspace")
+    ws = _workspace(ws_bytes.value, b.coefs.device)
+    cap = b.nterms * b.n
+    out = _empty_out(b.n, b.npolys * b.n, cap, b.max_exp, b.coefs.device)
+    cout = out.csr()
+    _check(L.poly_jacobian(ctypes.byref(cin), ctypes.byref(cout), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                           _stream()), "poly_jacobian")
+    return _finish(out, ws, "poly_jacobian", trim)
+
+
+def _eval_like(fname: str, b: Batch, X: torch.Tensor, shape, check: bool):
+    L = lib()
+    X = X.contiguous()
+    assert X.dtype == torch.float64 and X.dim() == 2 and X.shape[1] == b.n
+    N = X.shape[0]
+    cin = b.csr()
+    ws_bytes = ctypes.c_size_t()
+    _check(getattr(L, fname + "_workspace")(ctypes.byref(cin), N, ctypes.byref(ws_bytes)), fname + "_workspace")
+    ws = _workspace(ws_bytes.value, b.coefs.device)
+    Y = torch.empty(shape, dtype=torch.float64, device=b.coefs.device)
+    _check(getattr(L, fname)(ctypes.byref(cin), _ptr(X), N, _ptr(Y), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                             _stream()), fname)
+    if check:
+        _check(L.poly_read_status(ctypes.c_void_p(ws.data_ptr()), _stream()), fname)
+    return Y
+
+
+def eval(b: Batch, X: torch.Tensor, check: bool = False) -> torch.Tensor:
+    """Y[p, pt] = f_p(x_pt)."""
+    return _eval_like("poly_eval", b, X, (b.npolys, X.shape[0]), check)
+
+
+def grad(b: Batch, X: torch.Tensor, check: bool = False) -> torch.Tensor:
+    """G[p, pt, j] = d f_p / d x_j at x_pt."""
+    return _eval_like("poly_grad", b, X, (b.npolys, X.shape[0], b.n), check)
+
+
+def hess(b: Batch, X: torch.Tensor, check: bool = False) -> torch.Tensor:
+    """H[p, pt, j, k] = d^2 f_p / dx_j dx_k at x_pt."""
+    return _eval_like("poly_hess", b, X, (b.npolys, X.shape[0], b.n, b.n), check)
+
+
+def eval_backward(b: Batch, X: torch.Tensor, gY: torch.Tensor, want_dX: bool = True, want_dC: bool = True,
+                  check: bool = False):
+    """Reverse mode of eval: (dX [N, n], dC [T])."""
+    L = lib()
+    X = X.contiguous()
+    gY = gY.contiguous()
+    N = X.shape[0]
+    cin = b.csr()
+    ws_bytes = ctypes.c_size_t()
+    _check(L.poly_eval_backward_workspace(ctypes.byref(cin), N, ctypes.byref(ws_bytes)),
+           "poly_eval_backward_workspace")
+    ws = _workspace(ws_bytes.value, b.coefs.device)
+    dX = torch.empty((N, b.n), dtype=torch.float64, device=b.coefs.device) if want_dX else None
+    dC = torch.empty(b.nterms, dtype=torch.float64, device=b.coefs.device) if want_dC else None
+    _check(L.poly_eval_backward(ctypes.byref(cin), _ptr(X), N, _ptr(gY), _ptr(dX), _ptr(dC),
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "poly_eval_backward")
+    if check:
+        _check(L.poly_read_status(ctypes.c_void_p(ws.data_ptr()), _stream()), "poly_eval_backward")
+    return dX, dC
+
+
+def eval_dense_workspace(n: int, K: int, P: int, N: int, prec: int = POLY_FP64, nslices: int = 5) -> int:
+    ws_bytes = ctypes.c_size_t()
+    _check(lib().poly_eval_dense_workspace(n, K, P, N, prec, nslices, ctypes.byref(ws_bytes)),
+           "poly_eval_dense_workspace")
+    return int(ws_bytes.value)
+
+
+def eval_dense(basis: torch.Tensor, C: torch.Tensor, X: torch.Tensor, prec: int = POLY_FP64, nslices: int = 5,
+               max_exp: int | None = None, ws: torch.Tensor | None = None, Y: torch.Tensor | None = None):
+    """Y = C V for P polynomials over one shared monomial set."""
+    L = lib()
+    basis = basis.contiguous()
+    C = C.contiguous()
+    X = X.contiguous()
+    K, n = basis.shape
+    P = C.shape[0]
+    N = X.shape[0]
+    assert C.shape[1] == K and X.shape[1] == n
+    need = eval_dense_workspace(n, K, P, N, prec, nslices)
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, C.device)
+    if Y is None:
+        Y = torch.empty((P, N), dtype=torch.float64, device=C.device)
+    me = int(max_exp) if max_exp is not None else 255
+    _check(L.poly_eval_dense(n, K, _ptr(basis), me, P, _ptr(C), N, _ptr(X), _ptr(Y), prec, nslices,
+                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "poly_eval_dense")
+    return Y
+
+
+# -------------------------------------------------------------------- autograd
+
+class PolyEval(torch.autograd.Function):
+    """Y = eval(f, X) as a differentiable function of (coefs, X).
+
+    The backward pass is the library's reverse-mode kernel
+    (``poly_eval_backward``): dC from the monomial values, dX from the
+    symbolic first derivatives."""
+
+    @staticmethod
+    def forward(ctx, coefs, X, structure: Batch):
+        b = structure.with_coefs(coefs.detach().contiguous())
+        ctx.structure = structure
+        ctx.save_for_backward(coefs, X)
+        return eval(b, X.detach())
+
+    @staticmethod
+    def backward(ctx, gY):
+        coefs, X = ctx.saved_tensors
+        b = ctx.structure.with_coefs(coefs.detach().contiguous())
+        dX, dC = eval_backward(b, X.detach(), gY.detach().contiguous(), want_dX=ctx.needs_input_grad[1],
+                               want_dC=ctx.needs_input_grad[0])
+        return dC, dX, None

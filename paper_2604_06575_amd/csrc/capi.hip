@@ -1,0 +1,762 @@
+// C ABI entry points: argument checks, workspace layout, launch sequences.
+// Declarations and their contracts are in include/polyhip.h.
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace polyhip;
+
+namespace polyhip {
+poly_status dense_workspace(int32_t n, int64_t K, int64_t P, int64_t N, poly_prec prec, int32_t nslices,
+                            size_t *ws_bytes);
+poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp, int64_t P, const double *C,
+                      int64_t N, const double *X, double *Y, poly_prec prec, int32_t nslices, void *ws,
+                      size_t ws_bytes, hipStream_t stream);
+}  // namespace polyhip
+
+namespace {
+
+// Sequential workspace layout: the same walk sizes the query and places the
+// buffers for the call, so the two can never disagree.
+struct Layout {
+    size_t off = kWsHeadBytes;
+    size_t take(size_t bytes)
+    {
+        const size_t o = align_up(off, 256);
+        off = o + (bytes ? bytes : 0);
+        return o;
+    }
+    size_t total() const { return align_up(off, 256); }
+};
+
+template <class T>
+T *at(void *ws, size_t off)
+{
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+int device_cus()
+{
+    static std::mutex mu;
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    std::lock_guard<std::mutex> g(mu);
+    if (cache[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cache[dev] = cus;
+    }
+    return cache[dev];
+}
+
+#define LAUNCH_CHECK()                                     \
+    do {                                                   \
+        if (hipGetLastError() != hipSuccess) return POLY_ERR_HIP; \
+    } while (0)
+
+poly_status check_csr(const poly_csr *c, bool input)
+{
+    if (!c) return POLY_ERR_ARG;
+    if (c->nvars < 1 || c->nvars > 255) return POLY_ERR_ARG;
+    if (c->npolys < 0 || c->capacity < 0) return POLY_ERR_ARG;
+    if (c->max_exp < 0 || c->max_exp > 255) return POLY_ERR_ARG;
+    if (!c->row_ptr) return POLY_ERR_ARG;
+    if (input) {
+        if (!c->row_ptr_host) return POLY_ERR_ARG;
+        if (c->row_ptr_host[0] != 0) return POLY_ERR_ARG;
+        for (int64_t p = 0; p < c->npolys; ++p)
+            if (c->row_ptr_host[p + 1] < c->row_ptr_host[p]) return POLY_ERR_ARG;
+        const int64_t T = c->row_ptr_host[c->npolys];
+        if (T > c->capacity) return POLY_ERR_ARG;
+        if (T > 0 && (!c->exps || !c->coefs)) return POLY_ERR_ARG;
+        if (T >= (int64_t(1) << 32)) return POLY_ERR_UNSUPPORTED;
+    } else {
+        if (c->capacity > 0 && (!c->exps || !c->coefs)) return POLY_ERR_ARG;
+    }
+    return POLY_OK;
+}
+
+inline int64_t total_terms(const poly_csr *c) { return c->row_ptr_host[c->npolys]; }
+
+inline unsigned grid1(int64_t n, int threads) { return (unsigned)std::max<int64_t>(1, ceil_div(n, threads)); }
+
+// Clear the status word and small counters (a kernel, never a memset, so the
+// sequence can be captured in a graph).
+inline void clear_u64(unsigned long long *p, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid1(count, 256)), dim3(256), 0, s, p, 0ull, count);
+}
+
+inline void set_u64(unsigned long long *p, unsigned long long v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, p, v, (int64_t)1);
+}
+
+// ------------------------------------------------------------ simplify plan
+
+struct SimplifyPlan {
+    size_t keys, st_key, st_coef, seg_count, order, queue;
+    size_t total;
+};
+
+SimplifyPlan plan_simplify(int64_t P, int64_t T)
+{
+    Layout L;
+    SimplifyPlan s;
+    s.keys = L.take(8 * T);
+    s.st_key = L.take(8 * T);
+    s.st_coef = L.take(8 * T);
+    s.seg_count = L.take(8 * P);
+    s.order = L.take(8 * P);
+    s.queue = L.take(8);
+    s.total = L.total();
+    return s;
+}
+
+// ---------------------------------------------------------------- mul plan
+
+struct MulPlan {
+    size_t ka, kb, ka_s, kb_s, perm_a, perm_b, cnt_tmp, order_a, order_b, queues, pb_count, pb_start;
+    size_t bk_pair, bk_lo, bk_hi, bk_stage_off, bk_count, out_off, cursor, st_key, st_coef;
+    int64_t raw, nbuckets;
+    size_t total;
+};
+
+poly_status plan_mul(const poly_csr *a, const poly_csr *b, MulPlan &m)
+{
+    const int64_t P = a->npolys;
+    const int64_t Ta = total_terms(a), Tb = total_terms(b);
+    int64_t raw = 0, nb = 0;
+    for (int64_t p = 0; p < P; ++p) {
+        const int64_t ta = a->row_ptr_host[p + 1] - a->row_ptr_host[p];
+        const int64_t tb = b->row_ptr_host[p + 1] - b->row_ptr_host[p];
+        const int64_t r = ta * tb;
+        if (r >= (int64_t(1) << 32)) return POLY_ERR_UNSUPPORTED;
+        raw += r;
+        nb += mul_buckets_for(r);
+    }
+    if (nb >= (int64_t(1) << 31)) return POLY_ERR_UNSUPPORTED;
+    Layout L;
+    m.ka = L.take(8 * Ta);
+    m.kb = L.take(8 * Tb);
+    m.ka_s = L.take(8 * Ta);
+    m.kb_s = L.take(8 * Tb);
+    m.perm_a = L.take(4 * Ta);
+    m.perm_b = L.take(4 * Tb);
+    m.cnt_tmp = L.take(8 * P);
+    m.order_a = L.take(8 * P);
+    m.order_b = L.take(8 * P);
+    m.queues = L.take(8 * 4);
+    m.pb_count = L.take(8 * P);
+    m.pb_start = L.take(8 * (P + 1));
+    m.bk_pair = L.take(4 * nb);
+    m.bk_lo = L.take(8 * nb);
+    m.bk_hi = L.take(8 * nb);
+    m.bk_stage_off = L.take(8 * nb);
+    m.bk_count = L.take(8 * nb);
+    m.out_off = L.take(8 * (nb + 1));
+    m.cursor = L.take(8);
+    m.st_key = L.take(8 * raw);
+    m.st_coef = L.take(8 * raw);
+    m.raw = raw;
+    m.nbuckets = nb;
+    m.total = L.total();
+    return POLY_OK;
+}
+
+void launch_presort(const poly_csr *c, uint64_t *keys, uint64_t *sorted, uint32_t *perm, int64_t *cnt_tmp,
+                    int64_t *order, unsigned long long *queue, hipStream_t s)
+{
+    const int64_t P = c->npolys;
+    hipLaunchKernelGGL(k_order_by_size, dim3(1), dim3(1024), 0, s, c->row_ptr, P, order);
+    SegArgs A;
+    A.rp = c->row_ptr;
+    A.keys = keys;
+    A.coefs = c->coefs;
+    A.order = order;
+    A.P = P;
+    A.queue = queue;
+    A.st_key = sorted;
+    A.st_coef = nullptr;
+    A.st_idx = perm;
+    A.seg_count = cnt_tmp;
+    A.tol = 0.0;
+    const int64_t grid = std::min<int64_t>(P, (int64_t)device_cus() * 3);
+    hipLaunchKernelGGL(k_seg_sort, dim3((unsigned)grid), dim3(SEG_THREADS), 0, s, A);
+}
+
+// ----------------------------------------------------------- eval helpers
+
+struct EvalPlan {
+    size_t enc;
+    size_t total;
+};
+
+void launch_eval_blocks(const EvalArgs &A, const uint64_t *enc, hipStream_t s)
+{
+    if (A.Q <= 0 || A.N <= 0) return;
+    const unsigned gx = (unsigned)ceil_div(A.N, kWave);
+    // enough blocks to fill the machine several times over, each looping
+    // over polynomials so that its point tile is loaded once.
+    int64_t want = std::max<int64_t>(1, ((int64_t)device_cus() * 8 + gx - 1) / gx);
+    const unsigned gy = (unsigned)std::min<int64_t>(std::min<int64_t>(A.Q, want * 4), 65535);
+    const size_t lds = (size_t)A.n * kWave * sizeof(double);
+    hipLaunchKernelGGL(k_eval_blocks, dim3(gx, gy), dim3(EV_THREADS), lds, s, A, enc);
+}
+
+bool lds_attr_done = false;
+std::mutex lds_mu;
+void ensure_lds_attrs()
+{
+    std::lock_guard<std::mutex> g(lds_mu);
+    if (lds_attr_done) return;
+    (void)hipFuncSetAttribute((const void *)k_eval_blocks, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
+    (void)hipFuncSetAttribute((const void *)k_backward_dc, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
+    lds_attr_done = true;
+}
+
+// Bound used to size formed derivative polynomials: a term with at most
+// eight nonzero exponents has at most 8 first derivatives and 36 Hessian
+// entries (j <= k).  Terms beyond that are still handled; if the formed
+// polynomials outgrow the workspace the device reports POLY_ERR_WORKSPACE.
+inline int64_t grad_terms_bound(int64_t T, int n) { return T * std::min<int64_t>(n, 8); }
+constexpr int64_t HESS_BATCH = 256;   // pairs formed and evaluated per pass
+inline int64_t hess_terms_bound(int64_t T, int64_t nb) { return T * std::min<int64_t>(nb, 36); }
+
+struct GradPlan {
+    size_t counts, jrp, jexps, jcoefs, jenc;
+    int64_t cap;
+    size_t total;
+};
+
+GradPlan plan_grad(int64_t P, int64_t T, int n, Layout &L)
+{
+    GradPlan g;
+    g.cap = grad_terms_bound(T, n);
+    g.counts = L.take(8 * P * n);
+    g.jrp = L.take(8 * (P * n + 1));
+    g.jexps = L.take((size_t)g.cap * n);
+    g.jcoefs = L.take(8 * g.cap);
+    g.jenc = L.take(16 * g.cap);
+    return g;
+}
+
+poly_status run_grad(const poly_csr *f, const double *X, int64_t N, double *G, void *ws, const GradPlan &g,
+                     hipStream_t s)
+{
+    const int64_t P = f->npolys;
+    const int n = f->nvars;
+    int32_t *status = at<int32_t>(ws, 0);
+    int64_t *counts = at<int64_t>(ws, g.counts);
+    int64_t *jrp = at<int64_t>(ws, g.jrp);
+    uint8_t *jexps = at<uint8_t>(ws, g.jexps);
+    double *jcoefs = at<double>(ws, g.jcoefs);
+    uint64_t *jenc = at<uint64_t>(ws, g.jenc);
+    hipLaunchKernelGGL(k_jac_count, dim3((unsigned)P), dim3(JAC_THREADS), 0, s, f->row_ptr, f->exps, n, counts);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, counts, P * n, jrp);
+    hipLaunchKernelGGL(k_jac_write, dim3((unsigned)P), dim3(JAC_THREADS), 0, s, f->row_ptr, f->exps, f->coefs, n,
+                       jrp, jexps, jcoefs, g.cap, status, (int32_t)POLY_ERR_WORKSPACE);
+    hipLaunchKernelGGL(k_encode_support, dim3(grid1(g.cap, 256)), dim3(256), 0, s, jexps, g.cap, n, jenc);
+    LAUNCH_CHECK();
+    EvalArgs A;
+    memset(&A, 0, sizeof(A));
+    A.rp = jrp;
+    A.exps = jexps;
+    A.coefs = jcoefs;
+    A.n = n;
+    A.X = X;
+    A.N = N;
+    A.Q = P * n;
+    A.mode = OUT_GRAD;
+    A.Y = G;
+    A.term_limit = g.cap;
+    launch_eval_blocks(A, jenc, s);
+    LAUNCH_CHECK();
+    return POLY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *poly_strerror(int32_t status)
+{
+    switch (status) {
+    case POLY_OK: return "ok";
+    case POLY_ERR_ARG: return "invalid argument, size or shape";
+    case POLY_ERR_KEY_OVERFLOW: return "packed exponent key would exceed 64 bits (n * field width > 64)";
+    case POLY_ERR_WORKSPACE: return "workspace too small";
+    case POLY_ERR_CAPACITY: return "output capacity too small";
+    case POLY_ERR_EXPONENT: return "an exponent exceeds the declared max_exp";
+    case POLY_ERR_UNSUPPORTED: return "shape beyond the library's limits";
+    case POLY_ERR_HIP: return "HIP runtime or launch failure";
+    default: return "unknown status";
+    }
+}
+
+poly_status poly_read_status(const void *ws, void *stream)
+{
+    if (!ws) return POLY_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t st = 0;
+    if (hipMemcpyAsync(&st, ws, sizeof(st), hipMemcpyDeviceToHost, s) != hipSuccess) return POLY_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return POLY_ERR_HIP;
+    return (poly_status)st;
+}
+
+// ------------------------------------------------------------------ simplify
+
+poly_status poly_simplify_workspace(const poly_csr *in, size_t *ws_bytes)
+{
+    poly_status st = check_csr(in, true);
+    if (st != POLY_OK) return st;
+    if (!ws_bytes) return POLY_ERR_ARG;
+    *ws_bytes = plan_simplify(in->npolys, total_terms(in)).total;
+    return POLY_OK;
+}
+
+poly_status poly_simplify(const poly_csr *in, poly_csr *out, double zero_tol, void *ws, size_t ws_bytes,
+                          void *stream)
+{
+    poly_status st = check_csr(in, true);
+    if (st != POLY_OK) return st;
+    if ((st = check_csr(out, false)) != POLY_OK) return st;
+    if (out->nvars != in->nvars || out->npolys != in->npolys) return POLY_ERR_ARG;
+    if (!(zero_tol >= 0.0)) return POLY_ERR_ARG;
+    const int n = in->nvars;
+    const int bits = bit_width_u32((uint32_t)in->max_exp);
+    if ((int64_t)n * bits > 64) return POLY_ERR_KEY_OVERFLOW;
+    const int64_t P = in->npolys, T = total_terms(in);
+    const SimplifyPlan pl = plan_simplify(P, T);
+    if (!ws || ws_bytes < pl.total) return POLY_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t *status = at<int32_t>(ws, 0);
+    clear_u64(at<unsigned long long>(ws, 0), 1, s);
+    if (P == 0) {
+        clear_u64((unsigned long long *)out->row_ptr, 1, s);
+        LAUNCH_CHECK();
+        return POLY_OK;
+    }
+    uint64_t *keys = at<uint64_t>(ws, pl.keys);
+    unsigned long long *queue = at<unsigned long long>(ws, pl.queue);
+    clear_u64(queue, 1, s);
+    if (T > 0)
+        hipLaunchKernelGGL(k_pack, dim3(grid1(T, 256)), dim3(256), 0, s, in->exps, T, n, bits, in->max_exp, keys,
+                           status);
+    int64_t *order = at<int64_t>(ws, pl.order);
+    hipLaunchKernelGGL(k_order_by_size, dim3(1), dim3(1024), 0, s, in->row_ptr, P, order);
+    SegArgs A;
+    A.rp = in->row_ptr;
+    A.keys = keys;
+    A.coefs = in->coefs;
+    A.order = order;
+    A.P = P;
+    A.queue = queue;
+    A.st_key = at<uint64_t>(ws, pl.st_key);
+    A.st_coef = at<double>(ws, pl.st_coef);
+    A.st_idx = nullptr;
+    A.seg_count = at<int64_t>(ws, pl.seg_count);
+    A.tol = zero_tol;
+    const int64_t grid = std::min<int64_t>(P, (int64_t)device_cus() * 3);
+    hipLaunchKernelGGL(k_seg_merge, dim3((unsigned)grid), dim3(SEG_THREADS), 0, s, A);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, A.seg_count, P, out->row_ptr);
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)P), dim3(256), 0, s, in->row_ptr, A.seg_count, out->row_ptr,
+                       A.st_key, A.st_coef, n, bits, out->exps, out->coefs, out->capacity, status);
+    LAUNCH_CHECK();
+    return POLY_OK;
+}
+
+// ----------------------------------------------------------------------- mul
+
+poly_status poly_mul_workspace(const poly_csr *a, const poly_csr *b, size_t *ws_bytes, int64_t *raw_terms)
+{
+    poly_status st = check_csr(a, true);
+    if (st != POLY_OK) return st;
+    if ((st = check_csr(b, true)) != POLY_OK) return st;
+    if (a->nvars != b->nvars || a->npolys != b->npolys) return POLY_ERR_ARG;
+    MulPlan m;
+    if ((st = plan_mul(a, b, m)) != POLY_OK) return st;
+    if (ws_bytes) *ws_bytes = m.total;
+    if (raw_terms) *raw_terms = m.raw;
+    return POLY_OK;
+}
+
+poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double zero_tol, void *ws,
+                     size_t ws_bytes, void *stream)
+{
+    poly_status st = check_csr(a, true);
+    if (st != POLY_OK) return st;
+    if ((st = check_csr(b, true)) != POLY_OK) return st;
+    if ((st = check_csr(out, false)) != POLY_OK) return st;
+    if (a->nvars != b->nvars || a->npolys != b->npolys) return POLY_ERR_ARG;
+    if (out->nvars != a->nvars || out->npolys != a->npolys) return POLY_ERR_ARG;
+    if (!(zero_tol >= 0.0)) return POLY_ERR_ARG;
+    if (a->max_exp + b->max_exp > 255) return POLY_ERR_UNSUPPORTED;
+    const int n = a->nvars;
+    const int bits = bit_width_u32((uint32_t)(a->max_exp + b->max_exp));
+    if ((int64_t)n * bits > 64) return POLY_ERR_KEY_OVERFLOW;
+    MulPlan m;
+    if ((st = plan_mul(a, b, m)) != POLY_OK) return st;
+    if (!ws || ws_bytes < m.total) return POLY_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t P = a->npolys;
+    const int64_t Ta = total_terms(a), Tb = total_terms(b);
+    int32_t *status = at<int32_t>(ws, 0);
+    clear_u64(at<unsigned long long>(ws, 0), 1, s);
+    if (P == 0) {
+        clear_u64((unsigned long long *)out->row_ptr, 1, s);
+        LAUNCH_CHECK();
+        return POLY_OK;
+    }
+    unsigned long long *queues = at<unsigned long long>(ws, m.queues);
+    clear_u64(queues, 4, s);
+    clear_u64(at<unsigned long long>(ws, m.cursor), 1, s);
+    MulArgs A;
+    A.P = P;
+    A.a_rp = a->row_ptr;
+    A.b_rp = b->row_ptr;
+    A.a_c = a->coefs;
+    A.b_c = b->coefs;
+    A.ka = at<uint64_t>(ws, m.ka);
+    A.kb = at<uint64_t>(ws, m.kb);
+    A.ka_s = at<uint64_t>(ws, m.ka_s);
+    A.kb_s = at<uint64_t>(ws, m.kb_s);
+    A.perm_a = at<uint32_t>(ws, m.perm_a);
+    A.perm_b = at<uint32_t>(ws, m.perm_b);
+    A.pb_start = at<int64_t>(ws, m.pb_start);
+    A.bk_pair = at<int32_t>(ws, m.bk_pair);
+    A.bk_lo = at<uint64_t>(ws, m.bk_lo);
+    A.bk_hi = at<uint64_t>(ws, m.bk_hi);
+    A.bk_stage_off = at<int64_t>(ws, m.bk_stage_off);
+    A.bk_count = at<int64_t>(ws, m.bk_count);
+    A.stage_cursor = at<unsigned long long>(ws, m.cursor);
+    A.st_key = at<uint64_t>(ws, m.st_key);
+    A.st_coef = at<double>(ws, m.st_coef);
+    A.tol = zero_tol;
+    A.nbuckets = m.nbuckets;
+    A.st_capacity = m.raw;
+    A.status = status;
+    hipLaunchKernelGGL(k_mul_init_buckets, dim3(grid1(m.nbuckets, 256)), dim3(256), 0, s, A);
+    if (Ta > 0)
+        hipLaunchKernelGGL(k_pack, dim3(grid1(Ta, 256)), dim3(256), 0, s, a->exps, Ta, n, bits, a->max_exp,
+                           (uint64_t *)A.ka, status);
+    if (Tb > 0)
+        hipLaunchKernelGGL(k_pack, dim3(grid1(Tb, 256)), dim3(256), 0, s, b->exps, Tb, n, bits, b->max_exp,
+                           (uint64_t *)A.kb, status);
+    int64_t *cnt_tmp = at<int64_t>(ws, m.cnt_tmp);
+    launch_presort(a, (uint64_t *)A.ka, (uint64_t *)A.ka_s, (uint32_t *)A.perm_a, cnt_tmp,
+                   at<int64_t>(ws, m.order_a), queues + 0, s);
+    launch_presort(b, (uint64_t *)A.kb, (uint64_t *)A.kb_s, (uint32_t *)A.perm_b, cnt_tmp,
+                   at<int64_t>(ws, m.order_b), queues + 1, s);
+    int64_t *pb_count = at<int64_t>(ws, m.pb_count);
+    hipLaunchKernelGGL(k_mul_plan, dim3(grid1(P, 256)), dim3(256), 0, s, a->row_ptr, b->row_ptr, P, pb_count);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, pb_count, P, (int64_t *)A.pb_start);
+    hipLaunchKernelGGL(k_mul_splitters, dim3((unsigned)P), dim3(1024), 0, s, A);
+    hipLaunchKernelGGL(k_mul_buckets, dim3((unsigned)m.nbuckets), dim3(MUL_THREADS), 0, s, A);
+    int64_t *out_off = at<int64_t>(ws, m.out_off);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, A.bk_count, m.nbuckets, out_off);
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)m.nbuckets), dim3(256), 0, s, A.bk_stage_off, A.bk_count,
+                       out_off, A.st_key, A.st_coef, n, bits, out->exps, out->coefs, out->capacity, status);
+    hipLaunchKernelGGL(k_mul_rowptr, dim3(grid1(P + 1, 256)), dim3(256), 0, s, out_off, A.pb_start, P,
+                       out->row_ptr, m.nbuckets);
+    LAUNCH_CHECK();
+    return POLY_OK;
+}
+
+// ------------------------------------------------------------------ jacobian
+
+poly_status poly_jacobian_workspace(const poly_csr *in, size_t *ws_bytes)
+{
+    poly_status st = check_csr(in, true);
+    if (st != POLY_OK) return st;
+    if (!ws_bytes) return POLY_ERR_ARG;
+    Layout L;
+    L.take(8 * in->npolys * in->nvars);
+    *ws_bytes = L.total();
+    return POLY_OK;
+}
+
+poly_status poly_jacobian(const poly_csr *in, poly_csr *out, void *ws, size_t ws_bytes, void *stream)
+{
+    poly_status st = check_csr(in, true);
+    if (st != POLY_OK) return st;
+    if ((st = check_csr(out, false)) != POLY_OK) return st;
+    const int n = in->nvars;
+    const int64_t P = in->npolys;
+    if (out->nvars != n || out->npolys != P * n) return POLY_ERR_ARG;
+    Layout L;
+    const size_t o_counts = L.take(8 * P * n);
+    if (!ws || ws_bytes < L.total()) return POLY_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t *status = at<int32_t>(ws, 0);
+    clear_u64(at<unsigned long long>(ws, 0), 1, s);
+    if (P == 0) {
+        clear_u64((unsigned long long *)out->row_ptr, 1, s);
+        LAUNCH_CHECK();
+        return POLY_OK;
+    }
+    int64_t *counts = at<int64_t>(ws, o_counts);
+    hipLaunchKernelGGL(k_jac_count, dim3((unsigned)P), dim3(JAC_THREADS), 0, s, in->row_ptr, in->exps, n, counts);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, counts, P * n, out->row_ptr);
+    hipLaunchKernelGGL(k_jac_write, dim3((unsigned)P), dim3(JAC_THREADS), 0, s, in->row_ptr, in->exps, in->coefs, n,
+                       out->row_ptr, out->exps, out->coefs, out->capacity, status, (int32_t)POLY_ERR_CAPACITY);
+    LAUNCH_CHECK();
+    return POLY_OK;
+}
+
+// ---------------------------------------------------------------------- eval
+
+static poly_status check_eval(const poly_csr *f, const double *X, int64_t N, const void *out)
+{
+    poly_status st = check_csr(f, true);
+    if (st != POLY_OK) return st;
+    if (N < 0) return POLY_ERR_ARG;
+    if (N > 0 && f->npolys > 0 && (!X || !out)) return POLY_ERR_ARG;
+    return POLY_OK;
+}
+
+poly_status poly_eval_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)
+{
+    poly_status st = check_eval(f, nullptr, 0, nullptr);
+    if (st != POLY_OK) return st;
+    if (!ws_bytes || N < 0) return POLY_ERR_ARG;
+    Layout L;
+    L.take(16 * total_terms(f));
+    *ws_bytes = L.total();
+    return POLY_OK;
+}
+
+poly_status poly_eval(const poly_csr *f, const double *X, int64_t N, double *Y, void *ws, size_t ws_bytes,
+                      void *stream)
+{
+    poly_status st = check_eval(f, X, N, Y);
+    if (st != POLY_OK) return st;
+    const int64_t T = total_terms(f);
+    Layout L;
+    const size_t o_enc = L.take(16 * T);
+    if (!ws || ws_bytes < L.total()) return POLY_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    ensure_lds_attrs();
+    clear_u64(at<unsigned long long>(ws, 0), 1, s);
+    if (f->npolys == 0 || N == 0) {
+        LAUNCH_CHECK();
+        return POLY_OK;
+    }
+    uint64_t *enc = at<uint64_t>(ws, o_enc);
+    if (T > 0) hipLaunchKernelGGL(k_encode_support, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, f->nvars, enc);
+    EvalArgs A;
+    memset(&A, 0, sizeof(A));
+    A.rp = f->row_ptr;
+    A.exps = f->exps;
+    A.coefs = f->coefs;
+    A.n = f->nvars;
+    A.X = X;
+    A.N = N;
+    A.Q = f->npolys;
+    A.mode = OUT_EVAL;
+    A.Y = Y;
+    A.term_limit = T;
+    launch_eval_blocks(A, enc, s);
+    LAUNCH_CHECK();
+    return POLY_OK;
+}
+
+poly_status poly_grad_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)
+{
+    poly_status st = check_eval(f, nullptr, 0, nullptr);
+    if (st != POLY_OK) return st;
+    if (!ws_bytes || N < 0) return POLY_ERR_ARG;
+    Layout L;
+    plan_grad(f->npolys, total_terms(f), f->nvars, L);
+    *ws_bytes = L.total();
+    return POLY_OK;
+}
+
+poly_status poly_grad(const poly_csr *f, const double *X, int64_t N, double *G, void *ws, size_t ws_bytes,
+                      void *stream)
+{
+    poly_status st = check_eval(f, X, N, G);
+    if (st != POLY_OK) return st;
+    Layout L;
+    const GradPlan g = plan_grad(f->npolys, total_terms(f), f->nvars, L);
+    if (!ws || ws_bytes < L.total()) return POLY_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    ensure_lds_attrs();
+    clear_u64(at<unsigned long long>(ws, 0), 1, s);
+    if (f->npolys == 0 || N == 0) {
+        LAUNCH_CHECK();
+        return POLY_OK;
+    }
+    return run_grad(f, X, N, G, ws, g, s);
+}
+
+poly_status poly_hess_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)
+{
+    poly_status st = check_eval(f, nullptr, 0, nullptr);
+    if (st != POLY_OK) return st;
+    if (!ws_bytes || N < 0) return POLY_ERR_ARG;
+    const int n = f->nvars;
+    const int64_t P = f->npolys, T = total_terms(f);
+    const int64_t npairs = (int64_t)n * (n + 1) / 2;
+    const int64_t nb = std::min<int64_t>(npairs, HESS_BATCH);
+    const int64_t cap = hess_terms_bound(T, nb);
+    Layout L;
+    L.take(4 * npairs);
+    L.take(8 * P * nb);
+    L.take(8 * (P * nb + 1));
+    L.take((size_t)cap * n);
+    L.take(8 * cap);
+    L.take(16 * cap);
+    *ws_bytes = L.total();
+    return POLY_OK;
+}
+
+poly_status poly_hess(const poly_csr *f, const double *X, int64_t N, double *H, void *ws, size_t ws_bytes,
+                      void *stream)
+{
+    poly_status st = check_eval(f, X, N, H);
+    if (st != POLY_OK) return st;
+    const int n = f->nvars;
+    const int64_t P = f->npolys, T = total_terms(f);
+    const int64_t npairs = (int64_t)n * (n + 1) / 2;
+    const int64_t nbmax = std::min<int64_t>(npairs, HESS_BATCH);
+    const int64_t cap = hess_terms_bound(T, nbmax);
+    Layout L;
+    const size_t o_pairs = L.take(4 * npairs);
+    const size_t o_counts = L.take(8 * P * nbmax);
+    const size_t o_rp = L.take(8 * (P * nbmax + 1));
+    const size_t o_exps = L.take((size_t)cap * n);
+    const size_t o_coefs = L.take(8 * cap);
+    const size_t o_enc = L.take(16 * cap);
+    if (!ws || ws_bytes < L.total()) return POLY_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    ensure_lds_attrs();
+    int32_t *status = at<int32_t>(ws, 0);
+    clear_u64(at<unsigned long long>(ws, 0), 1, s);
+    if (P == 0 || N == 0) {
+        LAUNCH_CHECK();
+        return POLY_OK;
+    }
+    uint32_t *pairs = at<uint32_t>(ws, o_pairs);
+    int64_t *counts = at<int64_t>(ws, o_counts);
+    int64_t *hrp = at<int64_t>(ws, o_rp);
+    uint8_t *hexps = at<uint8_t>(ws, o_exps);
+    double *hcoefs = at<double>(ws, o_coefs);
+    uint64_t *henc = at<uint64_t>(ws, o_enc);
+    hipLaunchKernelGGL(k_pair_table, dim3(grid1(n, 256)), dim3(256), 0, s, n, pairs);
+    for (int64_t pb0 = 0; pb0 < npairs; pb0 += nbmax) {
+        const int64_t nb = std::min<int64_t>(nbmax, npairs - pb0);
+        const dim3 g((unsigned)P, (unsigned)ceil_div(nb, HES_PAIRS_PER_BLOCK));
+        hipLaunchKernelGGL(k_hes_count, g, dim3(JAC_THREADS), 0, s, f->row_ptr, f->exps, n, pb0, nb, pairs, counts);
+        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, counts, P * nb, hrp);
+        hipLaunchKernelGGL(k_hes_write, g, dim3(JAC_THREADS), 0, s, f->row_ptr, f->exps, f->coefs, n, pb0, nb, pairs,
+                           hrp, hexps, hcoefs, cap, status);
+        hipLaunchKernelGGL(k_encode_support, dim3(grid1(cap, 256)), dim3(256), 0, s, hexps, cap, n, henc);
+        EvalArgs A;
+        memset(&A, 0, sizeof(A));
+        A.rp = hrp;
+        A.exps = hexps;
+        A.coefs = hcoefs;
+        A.n = n;
+        A.X = X;
+        A.N = N;
+        A.Q = P * nb;
+        A.mode = OUT_HESS;
+        A.pair_base = pb0;
+        A.pairs_in_batch = nb;
+        A.pair_jk = pairs;
+        A.Y = H;
+        A.term_limit = cap;
+        launch_eval_blocks(A, henc, s);
+        LAUNCH_CHECK();
+    }
+    return POLY_OK;
+}
+
+poly_status poly_eval_backward_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)
+{
+    poly_status st = check_eval(f, nullptr, 0, nullptr);
+    if (st != POLY_OK) return st;
+    if (!ws_bytes || N < 0) return POLY_ERR_ARG;
+    const int n = f->nvars;
+    const int64_t P = f->npolys, T = total_terms(f);
+    Layout L;
+    plan_grad(P, T, n, L);
+    L.take(8 * P * N * n);   // G
+    L.take(16 * T);          // encoded support of f
+    const int cp = std::max(1, std::min(BWC_POINTS, 8192 / n));
+    L.take(8 * T * ceil_div(N, cp));
+    *ws_bytes = L.total();
+    return POLY_OK;
+}
+
+poly_status poly_eval_backward(const poly_csr *f, const double *X, int64_t N, const double *gY, double *dX,
+                               double *dC, void *ws, size_t ws_bytes, void *stream)
+{
+    poly_status st = check_eval(f, X, N, gY);
+    if (st != POLY_OK) return st;
+    const int n = f->nvars;
+    const int64_t P = f->npolys, T = total_terms(f);
+    Layout L;
+    const GradPlan g = plan_grad(P, T, n, L);
+    const size_t o_G = L.take(8 * P * N * n);
+    const size_t o_enc = L.take(16 * T);
+    const int cp = std::max(1, std::min(BWC_POINTS, 8192 / n));
+    const int64_t nchunks = ceil_div(N, cp);
+    const size_t o_part = L.take(8 * T * nchunks);
+    if (!ws || ws_bytes < L.total()) return POLY_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    ensure_lds_attrs();
+    clear_u64(at<unsigned long long>(ws, 0), 1, s);
+    if (P == 0) {
+        LAUNCH_CHECK();
+        return POLY_OK;
+    }
+    if (dX && N > 0) {
+        double *G = at<double>(ws, o_G);
+        st = run_grad(f, X, N, G, ws, g, s);
+        if (st != POLY_OK) return st;
+        hipLaunchKernelGGL(k_backward_dx, dim3(grid1(N * n, 256)), dim3(256), 0, s, G, gY, P, N, n, dX);
+    } else if (dX && N == 0) {
+        // nothing to write
+    }
+    if (dC && T > 0) {
+        if (N == 0) {
+            clear_u64((unsigned long long *)dC, T, s);
+        } else {
+            uint64_t *enc = at<uint64_t>(ws, o_enc);
+            double *part = at<double>(ws, o_part);
+            hipLaunchKernelGGL(k_encode_support, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, enc);
+            const size_t lds = (size_t)cp * n * sizeof(double);
+            hipLaunchKernelGGL(k_backward_dc, dim3(grid1(T, BWC_THREADS), (unsigned)nchunks), dim3(BWC_THREADS), lds,
+                               s, f->row_ptr, P, f->exps, n, T, X, N, gY, part, nchunks, (const uint64_t *)enc, cp);
+            hipLaunchKernelGGL(k_backward_dc_reduce, dim3(grid1(T, 256)), dim3(256), 0, s, part, T, nchunks, dC);
+        }
+    }
+    LAUNCH_CHECK();
+    return POLY_OK;
+}
+
+// ----------------------------------------------------------- dense (shared set)
+
+poly_status poly_eval_dense_workspace(int32_t n, int64_t K, int64_t P, int64_t N, poly_prec prec, int32_t nslices,
+                                      size_t *ws_bytes)
+{
+    return dense_workspace(n, K, P, N, prec, nslices, ws_bytes);
+}
+
+poly_status poly_eval_dense(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp, int64_t P,
+                            const double *C, int64_t N, const double *X, double *Y, poly_prec prec,
+                            int32_t nslices, void *ws, size_t ws_bytes, void *stream)
+{
+    return dense_run(n, K, basis, max_exp, P, C, N, X, Y, prec, nslices, ws, ws_bytes, (hipStream_t)stream);
+}
+
+}  // extern "C"

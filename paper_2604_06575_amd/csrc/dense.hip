@@ -1,0 +1,420 @@
+// Evaluation of P polynomials over one shared monomial set: Y = C V with
+// C [P x K] the coefficient matrix and V [K x N] the monomial values
+// V[k][pt] = prod_i x_pt,i ^ e_k,i (Section 3.3 eval, applied to a polynomial
+// matrix whose entries share a basis as produced by monolist, Section 3.1).
+// This is the one dense contraction of the path, so it runs on MFMA.  V is
+// never stored: each workgroup builds its K-slice of V from the points'
+// coordinates in LDS.
+//
+// FP64 path: v_mfma_f64_16x16x4f64, FP64 V.
+//
+// Split path (error-free splitting in the style of Ozaki, Ogita, Oishi and
+// Rump): within each K-block of 128 monomials every row of C and every
+// column of V gets a power-of-two scale 2^sigma above its largest magnitude.
+// Each value x is cut into S integer digits m_1..m_S (|m_1| <= 256,
+// |m_s| <= 128 after), x = sum_s m_s 2^(sigma - 8 s) + r, |r| <= 2^(sigma - 8S - 1).
+// A digit carried with its scale is an exact BF16 number.  Digit products of
+// one diagonal d = s + t share the scale 2^(sigma_C + sigma_V - 8d), and their
+// integer sum over a K-block stays below 2^24, so BF16 MFMA with FP32
+// accumulation adds them exactly; each diagonal's FP32 sum is moved to an
+// FP64 accumulator after every K-block.  Pairs with s + t > S + 1 are
+// dropped; the result's error relative to sum_k |C v| is about 2^-(8S-10).
+#include <string.h>
+
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace polyhip {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef short s8v __attribute__((ext_vector_type(8)));
+
+constexpr int DN_KB = 128;      // K-block of the split scheme (exact FP32 sums)
+
+// ---------------------------------------------------------------- helpers
+
+__device__ inline double powi_d(double x, uint32_t e)
+{
+    double p = x;
+    for (uint32_t k = 1; k < e; ++k) p = p * x;
+    return p;
+}
+
+// Monomial value for basis term k (encoded support) at a point whose
+// coordinates are x[i * xs].
+__device__ inline double basis_value(const uint64_t *enc, const uint8_t *basis, int n, int64_t k, const double *x,
+                                     int xs)
+{
+    const uint64_t w0 = enc[2 * k];
+    const uint64_t w1 = enc[2 * k + 1];
+    double v = 1.0;
+    if ((w0 & 0xffffull) == 0xffffull) {
+        const uint8_t *row = basis + k * n;
+        for (int i = 0; i < n; ++i)
+            if (row[i]) v = v * powi_d(x[i * xs], row[i]);
+        return v;
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const uint32_t ent = (uint32_t)(((s < 4 ? w0 : w1) >> (16 * (s & 3))) & 0xffffu);
+        const uint32_t e = ent >> 8;
+        if (e == 0) break;
+        v = v * powi_d(x[(ent & 0xffu) * xs], e);
+    }
+    return v;
+}
+
+// exponent sigma with |x| < 2^sigma for the largest |x| of a block (x = 0 -> -1100)
+__device__ inline int scale_exp(double amax)
+{
+    if (!(amax > 0.0)) return -1100;
+    int e;
+    (void)frexp(amax, &e);
+    return e;
+}
+
+__device__ inline unsigned short bf16_bits_exact(float f)
+{
+    return (unsigned short)(__float_as_uint(f) >> 16);
+}
+
+// ------------------------------------------------------------ FP64 kernel
+
+constexpr int D64_BM = 64, D64_BN = 128, D64_KS = 16, D64_THREADS = 256;
+
+// grid: x = N tiles (fastest, so concurrently running workgroups share a C
+// row panel), y = P tiles.  Dynamic LDS: n * D64_BN doubles for the points.
+__global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, const uint8_t *basis,
+                                                           const uint64_t *enc, int64_t P, const double *C,
+                                                           int64_t N, const double *X, double *Y)
+{
+    extern __shared__ double s_x[];                    // [n][D64_BN]
+    __shared__ double s_c[D64_BM][D64_KS + 1];
+    __shared__ double s_v[D64_KS][D64_BN + 2];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1;                 // wave: 32 rows x 64 points
+    const int64_t r0 = (int64_t)blockIdx.y * D64_BM;
+    const int64_t n0 = (int64_t)blockIdx.x * D64_BN;
+    for (int idx = tid; idx < n * D64_BN; idx += D64_THREADS) {
+        const int i = idx / D64_BN, c = idx % D64_BN;
+        const int64_t pt = n0 + c;
+        s_x[idx] = pt < N ? X[pt * n + i] : 0.0;
+    }
+    d4v acc[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
+    __syncthreads();
+    for (int64_t k0 = 0; k0 < K; k0 += D64_KS) {
+        // C tile: 64 rows x 16 k, 4 per thread
+        {
+            const int row = tid >> 2, kk = (tid & 3) * 4;
+            const int64_t r = r0 + row;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t k = k0 + kk + q;
+                s_c[row][kk + q] = (r < P && k < K) ? C[r * K + k] : 0.0;
+            }
+        }
+        // V tile: 16 k x 128 points, 8 per thread
+        {
+            const int c = tid & (D64_BN - 1), kb = (tid >> 7) * 8;
+#pragma unroll 2
+            for (int q = 0; q < 8; ++q) {
+                const int64_t k = k0 + kb + q;
+                s_v[kb + q][c] = k < K ? basis_value(enc, basis, n, k, s_x + c, D64_BN) : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k4 = 0; k4 < D64_KS; k4 += 4) {
+            double a[2], b[4];
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) a[rt] = s_c[wr * 32 + rt * 16 + (lane & 15)][k4 + (lane >> 4)];
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) b[ct] = s_v[k4 + (lane >> 4)][wc * 64 + ct * 16 + (lane & 15)];
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct)
+                    acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b[ct], acc[rt][ct], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t r = r0 + wr * 32 + rt * 16 + 4 * (lane >> 4) + v;
+                const int64_t c = n0 + wc * 64 + ct * 16 + (lane & 15);
+                if (r < P && c < N) Y[r * N + c] = acc[rt][ct][v];
+            }
+}
+
+// ------------------------------------------------------------ split kernels
+
+// Row scales of C per K-block and the BF16 digit planes of C with their
+// scale folded in: Cs[s][r][k] (k fastest).  One thread per (row, K-block).
+__global__ void k_split_c(const double *C, int64_t P, int64_t K, int S, unsigned short *Cs)
+{
+    const int64_t nkb = ceil_div(K, DN_KB);
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= P * nkb) return;
+    const int64_t r = id / nkb, kb = id % nkb;
+    const int64_t k0 = kb * DN_KB;
+    const int64_t k1 = std::min<int64_t>(K, k0 + DN_KB);
+    double amax = 0.0;
+    for (int64_t k = k0; k < k1; ++k) amax = fmax(amax, fabs(C[r * K + k]));
+    const int sig = scale_exp(amax);
+    for (int64_t k = k0; k < k1; ++k) {
+        double y = amax > 0.0 ? ldexp(C[r * K + k], -sig) : 0.0;
+        for (int s = 1; s <= S; ++s) {
+            y = y * 256.0;
+            const double m = rint(y);
+            y = y - m;
+            const float f = ldexpf((float)m, sig - 8 * s);
+            Cs[((int64_t)(s - 1) * P + r) * K + k] = bf16_bits_exact(f);
+        }
+    }
+}
+
+// Column scales of V per K-block: sig_v[kb * N + pt].  One thread per
+// (K-block, point).
+__global__ void k_split_vscale(int n, int64_t K, const uint8_t *basis, const uint64_t *enc, int64_t N,
+                               const double *X, int32_t *sig_v)
+{
+    const int64_t nkb = ceil_div(K, DN_KB);
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nkb * N) return;
+    const int64_t kb = id / N, pt = id % N;
+    const int64_t k0 = kb * DN_KB;
+    const int64_t k1 = std::min<int64_t>(K, k0 + DN_KB);
+    double amax = 0.0;
+    for (int64_t k = k0; k < k1; ++k) amax = fmax(amax, fabs(basis_value(enc, basis, n, k, X + pt * n, 1)));
+    sig_v[id] = scale_exp(amax);
+}
+
+constexpr int SP_BM = 128, SP_BN = 64, SP_KS = 32, SP_THREADS = 512;
+constexpr int SP_LDK = SP_KS + 8;    // padded k stride (bf16 elements) of the LDS digit planes
+
+// grid: x = N tiles, y = P tiles.  Waves: 4 row tiles of 32 x 2 column
+// tiles of 32 (one 32 x 32 MFMA tile each).  Dynamic LDS: points [n][SP_BN]
+// doubles, then C digits [S][SP_BM][SP_LDK] and V digits [S][SP_BN][SP_LDK].
+template <int S>
+__global__ void __launch_bounds__(SP_THREADS) k_dense_split(int n, int64_t K, const uint8_t *basis,
+                                                            const uint64_t *enc, int64_t P,
+                                                            const unsigned short *Cs, int64_t N, const double *X,
+                                                            const int32_t *sig_v, double *Y)
+{
+    extern __shared__ double s_dyn[];
+    double *s_x = s_dyn;                                              // [n][SP_BN]
+    unsigned short *s_cd = (unsigned short *)(s_x + n * SP_BN);       // [S][SP_BM][SP_LDK]
+    unsigned short *s_vd = s_cd + S * SP_BM * SP_LDK;                 // [S][SP_BN][SP_LDK]
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int64_t r0 = (int64_t)blockIdx.y * SP_BM;
+    const int64_t n0 = (int64_t)blockIdx.x * SP_BN;
+    for (int idx = tid; idx < n * SP_BN; idx += SP_THREADS) {
+        const int i = idx / SP_BN, c = idx % SP_BN;
+        const int64_t pt = n0 + c;
+        s_x[idx] = pt < N ? X[pt * n + i] : 0.0;
+    }
+    // FP64 accumulators for the wave's 32 x 32 tile, FP32 per diagonal
+    double out[16];
+    f16v acc[S];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) out[v] = 0.0;
+#pragma unroll
+    for (int d = 0; d < S; ++d)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[d][v] = 0.0f;
+    __syncthreads();
+    for (int64_t k0 = 0; k0 < K; k0 += SP_KS) {
+        // C digit planes: S x 128 rows x 32 k; 16 bf16 per (slice,row) => 4 x 8-byte loads
+        for (int idx = tid; idx < S * SP_BM * (SP_KS / 4); idx += SP_THREADS) {
+            const int s = idx / (SP_BM * (SP_KS / 4));
+            const int rem = idx % (SP_BM * (SP_KS / 4));
+            const int row = rem / (SP_KS / 4), kq = (rem % (SP_KS / 4)) * 4;
+            const int64_t r = r0 + row;
+            unsigned short v4[4] = {0, 0, 0, 0};
+            if (r < P) {
+                const unsigned short *src = Cs + ((int64_t)s * P + r) * K + k0 + kq;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v4[q] = (k0 + kq + q < K) ? src[q] : (unsigned short)0;
+            }
+            unsigned short *dst = s_cd + (s * SP_BM + row) * SP_LDK + kq;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dst[q] = v4[q];
+        }
+        // V digit planes: 32 k x 64 points -> 4 values per thread
+        {
+            const int c = tid & (SP_BN - 1);
+            const int kq = (tid >> 6) * 4;
+            const int64_t pt = n0 + c;
+            const int64_t kb = k0 / DN_KB;
+            const int sig = pt < N ? sig_v[kb * N + pt] : 0;
+#pragma unroll 2
+            for (int q = 0; q < 4; ++q) {
+                const int64_t k = k0 + kq + q;
+                double y = 0.0;
+                if (k < K && pt < N && sig > -1100) y = ldexp(basis_value(enc, basis, n, k, s_x + c, SP_BN), -sig);
+#pragma unroll
+                for (int t = 1; t <= S; ++t) {
+                    y = y * 256.0;
+                    const double m = rint(y);
+                    y = y - m;
+                    s_vd[((t - 1) * SP_BN + c) * SP_LDK + kq + q] = bf16_bits_exact(ldexpf((float)m, sig - 8 * t));
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < SP_KS; ks += 16) {
+            s8v a[S], b[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                a[s] = *(const s8v *)(s_cd + (s * SP_BM + wr * 32 + (lane & 31)) * SP_LDK + ks + 8 * (lane >> 5));
+#pragma unroll
+            for (int t = 0; t < S; ++t)
+                b[t] = *(const s8v *)(s_vd + (t * SP_BN + wc * 32 + (lane & 31)) * SP_LDK + ks + 8 * (lane >> 5));
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+#pragma unroll
+                for (int t = 0; t < S - s; ++t)
+                    acc[s + t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf8v, a[s]), __builtin_bit_cast(bf8v, b[t]), acc[s + t], 0, 0, 0);
+        }
+        __syncthreads();
+        // drain every K-block (or at the end)
+        if (((k0 + SP_KS) % DN_KB) == 0 || k0 + SP_KS >= K) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                double t = 0.0;
+#pragma unroll
+                for (int d = S - 1; d >= 0; --d) {
+                    t += (double)acc[d][v];
+                    acc[d][v] = 0.0f;
+                }
+                out[v] += t;
+            }
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int64_t r = r0 + wr * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int64_t c = n0 + wc * 32 + (lane & 31);
+        if (r < P && c < N) Y[r * N + c] = out[v];
+    }
+}
+
+// ---------------------------------------------------------------- host side
+
+namespace {
+
+struct DensePlan {
+    size_t enc, cs, sigv, total;
+};
+
+DensePlan plan_dense(int32_t n, int64_t K, int64_t P, int64_t N, poly_prec prec, int32_t S)
+{
+    size_t off = kWsHeadBytes;
+    auto take = [&](size_t b) {
+        const size_t o = align_up(off, 256);
+        off = o + b;
+        return o;
+    };
+    DensePlan d;
+    d.enc = take(16 * (size_t)K);
+    d.cs = 0;
+    d.sigv = 0;
+    if (prec == POLY_SPLIT_BF16) {
+        d.cs = take((size_t)S * P * K * 2);
+        d.sigv = take((size_t)ceil_div(K, DN_KB) * N * 4);
+    }
+    d.total = align_up(off, 256);
+    return d;
+}
+
+template <int S>
+void launch_split(int n, int64_t K, const uint8_t *basis, const uint64_t *enc, int64_t P, const unsigned short *Cs,
+                  int64_t N, const double *X, const int32_t *sig_v, double *Y, hipStream_t s)
+{
+    const size_t lds = (size_t)n * SP_BN * 8 + (size_t)S * (SP_BM + SP_BN) * SP_LDK * 2;
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_dense_split<S>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
+    }
+    const dim3 grid((unsigned)ceil_div(N, SP_BN), (unsigned)ceil_div(P, SP_BM));
+    hipLaunchKernelGGL(k_dense_split<S>, grid, dim3(SP_THREADS), lds, s, n, K, basis, enc, P, Cs, N, X, sig_v, Y);
+}
+
+}  // namespace
+
+poly_status dense_workspace(int32_t n, int64_t K, int64_t P, int64_t N, poly_prec prec, int32_t S, size_t *ws_bytes)
+{
+    if (!ws_bytes || n < 1 || n > 255 || K < 0 || P < 0 || N < 0) return POLY_ERR_ARG;
+    if (prec != POLY_FP64 && prec != POLY_SPLIT_BF16) return POLY_ERR_ARG;
+    if (prec == POLY_SPLIT_BF16 && (S < 3 || S > 6)) return POLY_ERR_ARG;
+    *ws_bytes = plan_dense(n, K, P, N, prec, S).total;
+    return POLY_OK;
+}
+
+poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp, int64_t P, const double *C,
+                      int64_t N, const double *X, double *Y, poly_prec prec, int32_t S, void *ws, size_t ws_bytes,
+                      hipStream_t s)
+{
+    size_t need = 0;
+    poly_status st = dense_workspace(n, K, P, N, prec, S, &need);
+    if (st != POLY_OK) return st;
+    if (max_exp < 0 || max_exp > 255) return POLY_ERR_ARG;
+    if ((K > 0 && (!basis || (P > 0 && !C))) || (N > 0 && !X) || (P > 0 && N > 0 && !Y)) return POLY_ERR_ARG;
+    if (!ws || ws_bytes < need) return POLY_ERR_WORKSPACE;
+    if (prec == POLY_FP64 && (size_t)n * D64_BN * 8 > 96 * 1024) return POLY_ERR_UNSUPPORTED;
+    if (prec == POLY_SPLIT_BF16 && (size_t)n * SP_BN * 8 + (size_t)S * (SP_BM + SP_BN) * SP_LDK * 2 > 160 * 1024)
+        return POLY_ERR_UNSUPPORTED;
+    const DensePlan d = plan_dense(n, K, P, N, prec, S);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (unsigned long long *)ws, 0ull, (int64_t)1);
+    if (P == 0 || N == 0) return hipGetLastError() == hipSuccess ? POLY_OK : POLY_ERR_HIP;
+    uint64_t *enc = (uint64_t *)((char *)ws + d.enc);
+    if (K > 0)
+        hipLaunchKernelGGL(k_encode_support, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, s, basis, K, n, enc);
+    if (prec == POLY_FP64) {
+        static bool attr = false;
+        if (!attr) {
+            (void)hipFuncSetAttribute((const void *)k_dense_f64, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+            attr = true;
+        }
+        const dim3 grid((unsigned)ceil_div(N, D64_BN), (unsigned)ceil_div(P, D64_BM));
+        hipLaunchKernelGGL(k_dense_f64, grid, dim3(D64_THREADS), (size_t)n * D64_BN * 8, s, n, K, basis, enc, P, C, N,
+                           X, Y);
+    } else {
+        unsigned short *Cs = (unsigned short *)((char *)ws + d.cs);
+        int32_t *sig_v = (int32_t *)((char *)ws + d.sigv);
+        const int64_t nkb = ceil_div(K, DN_KB);
+        if (K > 0) {
+            hipLaunchKernelGGL(k_split_c, dim3((unsigned)ceil_div(P * nkb, 256)), dim3(256), 0, s, C, P, K, S, Cs);
+            hipLaunchKernelGGL(k_split_vscale, dim3((unsigned)ceil_div(nkb * N, 256)), dim3(256), 0, s, n, K, basis,
+                               enc, N, X, sig_v);
+        }
+        switch (S) {
+        case 3: launch_split<3>(n, K, basis, enc, P, Cs, N, X, sig_v, Y, s); break;
+        case 4: launch_split<4>(n, K, basis, enc, P, Cs, N, X, sig_v, Y, s); break;
+        case 5: launch_split<5>(n, K, basis, enc, P, Cs, N, X, sig_v, Y, s); break;
+        default: launch_split<6>(n, K, basis, enc, P, Cs, N, X, sig_v, Y, s); break;
+        }
+    }
+    return hipGetLastError() == hipSuccess ? POLY_OK : POLY_ERR_HIP;
+}
+
+}  // namespace polyhip

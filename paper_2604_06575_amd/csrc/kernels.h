@@ -1,0 +1,126 @@
+// Kernel declarations shared between the HIP translation units.
+#pragma once
+
+#include "internal.h"
+
+namespace polyhip {
+
+// ------------------------------------------------------------ simplify / sort
+constexpr int SEG_THREADS = 256;
+constexpr int SEG_CAP = 4096;  // terms held in LDS by one tile
+
+struct SegArgs {
+    const int64_t *rp;          // [P+1] CSR of the segments
+    const uint64_t *keys;       // packed keys at input positions
+    const double *coefs;        // input coefficients (merge mode)
+    const int64_t *order;       // [P] processing order (largest first)
+    int64_t P;
+    unsigned long long *queue;  // job counter, zero before launch
+    uint64_t *st_key;           // staging keys, written at input positions
+    double *st_coef;            // staging merged coefficients (merge mode)
+    uint32_t *st_idx;           // staging local term index (sort-only mode)
+    int64_t *seg_count;         // [P] terms written per segment
+    double tol;
+};
+
+__global__ void k_pack(const uint8_t *__restrict__ exps, int64_t T, int n, int bits, int max_exp,
+                       uint64_t *__restrict__ keys, int32_t *status);
+__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t count);
+__global__ void k_order_by_size(const int64_t *rp, int64_t P, int64_t *order);
+__global__ void k_seg_merge(SegArgs A);
+__global__ void k_seg_sort(SegArgs A);
+__global__ void k_scan_counts(const int64_t *counts, int64_t S, int64_t *out);
+__global__ void k_compact(const int64_t *stage_off, const int64_t *seg_count, const int64_t *out_off,
+                          const uint64_t *st_key, const double *st_coef, int n, int bits,
+                          uint8_t *out_exps, double *out_coefs, int64_t capacity, int32_t *status);
+
+// ------------------------------------------------------------------------ mul
+constexpr int MUL_THREADS = 256;
+constexpr int MUL_CAP = 4096;
+constexpr int64_t MUL_TARGET = 3072;       // raw terms per bucket, on average
+constexpr int MUL_SAMPLE = 16384;          // splitter sample per pair
+constexpr int64_t MUL_MAX_BUCKETS = 8192;  // per pair
+
+__host__ __device__ inline int64_t mul_buckets_for(int64_t raw)
+{
+    if (raw <= MUL_CAP) return 1;
+    int64_t b = (raw + MUL_TARGET - 1) / MUL_TARGET;
+    return b > MUL_MAX_BUCKETS ? MUL_MAX_BUCKETS : b;
+}
+
+struct MulArgs {
+    int64_t P;
+    const int64_t *a_rp, *b_rp;
+    const double *a_c, *b_c;
+    const uint64_t *ka, *kb;        // packed keys, storage order
+    const uint64_t *ka_s, *kb_s;    // keys sorted per polynomial
+    const uint32_t *perm_a, *perm_b;  // local index of each sorted position
+    const int64_t *pb_start;        // [P+1] first bucket of each pair
+    int32_t *bk_pair;
+    uint64_t *bk_lo, *bk_hi;        // inclusive key range of each bucket
+    int64_t *bk_stage_off, *bk_count;
+    unsigned long long *stage_cursor;
+    uint64_t *st_key;
+    double *st_coef;
+    double tol;
+    int64_t nbuckets;               // buckets allocated (host plan)
+    int64_t st_capacity;            // staging slots allocated
+    int32_t *status;
+};
+
+__global__ void k_mul_init_buckets(MulArgs A);
+__global__ void k_mul_plan(const int64_t *a_rp, const int64_t *b_rp, int64_t P, int64_t *pb_count);
+__global__ void k_mul_splitters(MulArgs A);
+__global__ void k_mul_buckets(MulArgs A);
+__global__ void k_mul_rowptr(const int64_t *out_off, const int64_t *pb_start, int64_t P, int64_t *out_rp,
+                             int64_t nbuckets);
+
+// ---------------------------------------------------------------- derivatives
+constexpr int JAC_THREADS = 256;
+__global__ void k_jac_count(const int64_t *rp, const uint8_t *exps, int n, int64_t *counts);
+__global__ void k_jac_write(const int64_t *rp, const uint8_t *exps, const double *coefs, int n,
+                            const int64_t *out_rp, uint8_t *out_exps, double *out_coefs, int64_t capacity,
+                            int32_t *status, int32_t overflow_code);
+constexpr int HES_PAIRS_PER_BLOCK = 64;
+// Hessian pair batch [pair_base, pair_base + nb): formed polynomial p * nb + (pair - pair_base)
+__global__ void k_hes_count(const int64_t *rp, const uint8_t *exps, int n, int64_t pair_base, int64_t nb,
+                            const uint32_t *pair_jk, int64_t *counts);
+__global__ void k_hes_write(const int64_t *rp, const uint8_t *exps, const double *coefs, int n, int64_t pair_base,
+                            int64_t nb, const uint32_t *pair_jk, const int64_t *out_rp, uint8_t *out_exps,
+                            double *out_coefs, int64_t capacity, int32_t *status);
+__global__ void k_pair_table(int n, uint32_t *pair_jk);
+
+// ----------------------------------------------------------------- sparse eval
+constexpr int EV_WAVES = 8;
+constexpr int EV_THREADS = EV_WAVES * kWave;  // 8 waves share 64 points
+
+enum OutMode { OUT_EVAL = 0, OUT_GRAD = 1, OUT_HESS = 2 };
+
+struct EvalArgs {
+    const int64_t *rp;            // [Q+1]
+    const uint8_t *exps;          // [T * n] exponent rows
+    const double *coefs;          // [T]
+    int n;
+    const double *X;              // [N * n]
+    int64_t N;
+    int64_t Q;                    // polynomials
+    int mode;                     // OutMode
+    int64_t pair_base;            // hess: first pair index of this batch
+    int64_t pairs_in_batch;       // hess: pairs per source polynomial in this batch
+    const uint32_t *pair_jk;      // hess: (j << 16) | k
+    double *Y;                    // output
+    int64_t term_limit;           // terms at or beyond this index are never read
+};
+
+__global__ void k_encode_support(const uint8_t *exps, int64_t T, int n, uint64_t *enc);
+__global__ void k_eval_blocks(EvalArgs A, const uint64_t *enc);
+
+__global__ void k_backward_dx(const double *G, const double *gY, int64_t P, int64_t N, int n, double *dX);
+constexpr int BWC_THREADS = 256;
+constexpr int BWC_POINTS = 512;   // points per chunk
+__global__ void k_backward_dc(const int64_t *rp, int64_t P, const uint8_t *exps, int n, int64_t T, const double *X,
+                              int64_t N, const double *gY, double *partial, int64_t nchunks,
+                              const uint64_t *enc, int cp);
+__global__ void k_backward_dc_reduce(const double *partial, int64_t T, int64_t nchunks, double *dC);
+
+}  // namespace polyhip

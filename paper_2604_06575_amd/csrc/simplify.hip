@@ -1,0 +1,306 @@
+// simplify (Table "coresemantics": merge repeated monomials, drop small
+// coefficients) as a persistent segmented sort-and-merge over a CSR batch.
+//
+// Every exponent row is packed into a 64-bit key (b bits per variable, x1 in
+// the most significant field), so ascending key order is the canonical
+// lexicographic order.  One workgroup takes one entry at a time from an
+// atomic job counter (entries ordered largest first).  An entry that fits in
+// LDS is sorted there as (key, local index) pairs, which orders equal keys by
+// their position in the input; each run of equal keys is then summed left to
+// right by one lane, exactly the order of a sequential merge.  Larger entries
+// are cut into key ranges by bisection until each range fits in LDS.
+#pragma clang fp contract(off)
+
+#include "kernels.h"
+#include "lds_sort.h"
+
+namespace polyhip {
+
+__global__ void k_pack(const uint8_t *__restrict__ exps, int64_t T, int n, int bits, int max_exp,
+                       uint64_t *__restrict__ keys, int32_t *status)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const uint8_t *row = exps + t * n;
+    uint64_t k = 0;
+    int bad = 0;
+    for (int i = 0; i < n; ++i) {
+        const uint32_t e = row[i];
+        bad |= (int)(e > (uint32_t)max_exp);
+        k = (k << bits) | (uint64_t)e;
+    }
+    keys[t] = k;
+    if (bad) set_status(status, POLY_ERR_EXPONENT);
+}
+
+__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+// Entries ordered by decreasing size class (floor(log2(size))); one block.
+__global__ void __launch_bounds__(1024) k_order_by_size(const int64_t *rp, int64_t P, int64_t *order)
+{
+    __shared__ int64_t s_hist[66];
+    __shared__ int64_t s_cur[66];
+    for (int i = threadIdx.x; i < 66; i += blockDim.x) s_hist[i] = 0;
+    __syncthreads();
+    for (int64_t p = threadIdx.x; p < P; p += blockDim.x) {
+        const int64_t sz = rp[p + 1] - rp[p];
+        const int cls = sz <= 0 ? 0 : 64 - __clzll((unsigned long long)sz);  // 1..64
+        atomicAdd((unsigned long long *)&s_hist[65 - cls], 1ull);              // largest class first
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int c = 0; c < 66; ++c) {
+            s_cur[c] = run;
+            run += s_hist[c];
+        }
+    }
+    __syncthreads();
+    for (int64_t p = threadIdx.x; p < P; p += blockDim.x) {
+        const int64_t sz = rp[p + 1] - rp[p];
+        const int cls = sz <= 0 ? 0 : 64 - __clzll((unsigned long long)sz);
+        const int64_t pos = (int64_t)atomicAdd((unsigned long long *)&s_cur[65 - cls], 1ull);
+        order[pos] = p;
+    }
+}
+
+namespace {
+
+struct SegShared {
+    uint64_t key[SEG_CAP];
+    uint32_t val[SEG_CAP];
+    int64_t scan[SEG_THREADS / kWave];
+    uint64_t red[SEG_THREADS / kWave];
+    uint64_t stk_lo[72];
+    uint64_t stk_hi[72];
+    int64_t stk_cnt[72];
+    int64_t job;
+    double bcast;
+    int64_t bcast_i;
+};
+
+// Emit the sorted tile: merged runs (merge mode) or every element (sort mode)
+// to staging positions base + out .. ; returns the number written.
+template <bool SORT_ONLY>
+__device__ int64_t emit_tile(const SegArgs &A, SegShared &S, int m, int64_t base, int64_t out)
+{
+    if (SORT_ONLY) {
+        for (int i = threadIdx.x; i < m; i += SEG_THREADS) {
+            A.st_key[base + out + i] = S.key[i];
+            A.st_idx[base + out + i] = S.val[i];
+        }
+        __syncthreads();
+        return m;
+    }
+    int64_t written = 0;
+    for (int c0 = 0; c0 < m; c0 += SEG_THREADS) {
+        const int i = c0 + threadIdx.x;
+        int64_t keep = 0;
+        double s = 0.0;
+        uint64_t k = 0;
+        if (i < m) {
+            k = S.key[i];
+            const bool head = (i == 0) || (S.key[i - 1] != k);
+            if (head) {
+                s = A.coefs[base + S.val[i]];
+                for (int q = i + 1; q < m && S.key[q] == k; ++q) s = s + A.coefs[base + S.val[q]];
+                keep = !(fabs(s) <= A.tol);
+            }
+        }
+        int64_t tot;
+        const int64_t pos = block_exclusive_scan<SEG_THREADS>(keep, S.scan, tot);
+        if (keep) {
+            A.st_key[base + out + written + pos] = k;
+            A.st_coef[base + out + written + pos] = s;
+        }
+        written += tot;
+    }
+    return written;
+}
+
+template <bool SORT_ONLY>
+__device__ void seg_process(const SegArgs &A, SegShared &S)
+{
+    for (;;) {
+        if (threadIdx.x == 0) S.job = (int64_t)atomicAdd(A.queue, 1ull);
+        __syncthreads();
+        const int64_t job = S.job;
+        __syncthreads();
+        if (job >= A.P) break;
+        const int64_t p = A.order[job];
+        const int64_t base = A.rp[p];
+        const int64_t T = A.rp[p + 1] - base;
+        int64_t written = 0;
+        if (T <= SEG_CAP) {
+            for (int i = threadIdx.x; i < T; i += SEG_THREADS) {
+                S.key[i] = A.keys[base + i];
+                S.val[i] = (uint32_t)i;
+            }
+            __syncthreads();
+            lds_sort_kv<SEG_THREADS>(S.key, S.val, (int)T);
+            written = emit_tile<SORT_ONLY>(A, S, (int)T, base, 0);
+        } else {
+            uint64_t lmin = ~0ull, lmax = 0;
+            for (int64_t i = threadIdx.x; i < T; i += SEG_THREADS) {
+                const uint64_t k = A.keys[base + i];
+                lmin = k < lmin ? k : lmin;
+                lmax = k > lmax ? k : lmax;
+            }
+            const uint64_t kmin = block_min_u64<SEG_THREADS>(lmin, S.red);
+            const uint64_t kmax = block_max_u64<SEG_THREADS>(lmax, S.red);
+            if (threadIdx.x == 0) {
+                S.stk_lo[0] = kmin;
+                S.stk_hi[0] = kmax;
+                S.stk_cnt[0] = T;
+            }
+            int sp = 1;
+            while (sp > 0) {
+                __syncthreads();
+                --sp;
+                const uint64_t lo = S.stk_lo[sp], hi = S.stk_hi[sp];
+                const int64_t cnt = S.stk_cnt[sp];
+                __syncthreads();
+                if (cnt == 0) continue;
+                if (cnt <= SEG_CAP) {
+                    // stable gather of the range into LDS
+                    int64_t got = 0;
+                    for (int64_t c0 = 0; c0 < T; c0 += SEG_THREADS) {
+                        const int64_t i = c0 + threadIdx.x;
+                        int64_t f = 0;
+                        uint64_t k = 0;
+                        if (i < T) {
+                            k = A.keys[base + i];
+                            f = (k >= lo && k <= hi) ? 1 : 0;
+                        }
+                        int64_t tot;
+                        const int64_t pos = block_exclusive_scan<SEG_THREADS>(f, S.scan, tot);
+                        if (f && got + pos < SEG_CAP) {
+                            S.key[got + pos] = k;
+                            S.val[got + pos] = (uint32_t)i;
+                        }
+                        got += tot;
+                    }
+                    const int m = (int)(got < SEG_CAP ? got : SEG_CAP);
+                    __syncthreads();
+                    lds_sort_kv<SEG_THREADS>(S.key, S.val, m);
+                    written += emit_tile<SORT_ONLY>(A, S, m, base, written);
+                } else if (lo == hi) {
+                    // one key repeated more often than a tile holds
+                    if (SORT_ONLY) {
+                        int64_t got = 0;
+                        for (int64_t c0 = 0; c0 < T; c0 += SEG_THREADS) {
+                            const int64_t i = c0 + threadIdx.x;
+                            int64_t f = (i < T && A.keys[base + i] == lo) ? 1 : 0;
+                            int64_t tot;
+                            const int64_t pos = block_exclusive_scan<SEG_THREADS>(f, S.scan, tot);
+                            if (f) {
+                                A.st_key[base + written + got + pos] = lo;
+                                A.st_idx[base + written + got + pos] = (uint32_t)i;
+                            }
+                            got += tot;
+                        }
+                        written += got;
+                    } else {
+                        if (threadIdx.x == 0) {
+                            double s = 0.0;
+                            bool first = true;
+                            for (int64_t i = 0; i < T; ++i) {
+                                if (A.keys[base + i] != lo) continue;
+                                const double c = A.coefs[base + i];
+                                s = first ? c : s + c;
+                                first = false;
+                            }
+                            const bool keep = !(fabs(s) <= A.tol);
+                            if (keep) {
+                                A.st_key[base + written] = lo;
+                                A.st_coef[base + written] = s;
+                            }
+                            S.bcast_i = keep ? 1 : 0;
+                        }
+                        __syncthreads();
+                        written += S.bcast_i;
+                        __syncthreads();
+                    }
+                } else {
+                    const uint64_t mid = lo + (hi - lo) / 2;
+                    int64_t c = 0;
+                    for (int64_t i = threadIdx.x; i < T; i += SEG_THREADS) {
+                        const uint64_t k = A.keys[base + i];
+                        c += (k >= lo && k <= mid) ? 1 : 0;
+                    }
+                    const int64_t left = block_sum<SEG_THREADS>(c, S.scan);
+                    if (threadIdx.x == 0) {
+                        S.stk_lo[sp] = mid + 1;
+                        S.stk_hi[sp] = hi;
+                        S.stk_cnt[sp] = cnt - left;
+                        S.stk_lo[sp + 1] = lo;
+                        S.stk_hi[sp + 1] = mid;
+                        S.stk_cnt[sp + 1] = left;
+                    }
+                    sp += 2;
+                }
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) A.seg_count[p] = written;
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(SEG_THREADS) k_seg_merge(SegArgs A)
+{
+    __shared__ SegShared S;
+    seg_process<false>(A, S);
+}
+
+__global__ void __launch_bounds__(SEG_THREADS) k_seg_sort(SegArgs A)
+{
+    __shared__ SegShared S;
+    seg_process<true>(A, S);
+}
+
+// Exclusive scan of S counts into out[0..S]; one block of 1024 threads.
+__global__ void __launch_bounds__(1024) k_scan_counts(const int64_t *counts, int64_t S, int64_t *out)
+{
+    __shared__ int64_t s_scan[1024 / kWave];
+    int64_t run = 0;
+    for (int64_t c0 = 0; c0 < S; c0 += 1024) {
+        const int64_t i = c0 + threadIdx.x;
+        const int64_t v = i < S ? counts[i] : 0;
+        int64_t tot;
+        const int64_t pos = block_exclusive_scan<1024>(v, s_scan, tot);
+        if (i < S) out[i] = run + pos;
+        run += tot;
+    }
+    if (threadIdx.x == 0) out[S] = run;
+}
+
+// One block per segment: staged (key, coef) -> CSR output rows.
+__global__ void __launch_bounds__(256) k_compact(const int64_t *stage_off, const int64_t *seg_count,
+                                                 const int64_t *out_off, const uint64_t *st_key,
+                                                 const double *st_coef, int n, int bits, uint8_t *out_exps,
+                                                 double *out_coefs, int64_t capacity, int32_t *status)
+{
+    const int64_t s = blockIdx.x;
+    const int64_t cnt = seg_count[s];
+    const int64_t src = stage_off[s];
+    const int64_t dst = out_off[s];
+    if (threadIdx.x == 0 && dst + cnt > capacity) set_status(status, POLY_ERR_CAPACITY);
+    const uint64_t mask = (bits >= 64) ? ~0ull : ((1ull << bits) - 1ull);
+    for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const int64_t d = dst + i;
+        if (d >= capacity) break;
+        const uint64_t k = st_key[src + i];
+        uint8_t *row = out_exps + d * n;
+        for (int v = 0; v < n; ++v) row[v] = (uint8_t)((k >> (bits * (n - 1 - v))) & mask);
+        out_coefs[d] = st_coef[src + i];
+    }
+}
+
+}  // namespace polyhip

@@ -1,0 +1,72 @@
+"""CPU-side checks of the boundary: the shared library loads and exports
+every symbol the header declares; host argument checks reject bad input
+without touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "polyhip.h")).read()
+    return sorted(set(re.findall(r"\b(poly_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2604_06575_amd as ph
+    if not os.path.exists(ph.library_path()):
+        pytest.skip("library not built")
+    L = ctypes.CDLL(ph.library_path())
+    syms = header_symbols()
+    assert len(syms) == 18
+    for s in syms:
+        assert hasattr(L, s), s
+    assert sorted(ph.EXPORTS) == syms
+
+
+def test_strerror_and_host_argument_checks():
+    import paper_2604_06575_amd as ph
+    if not os.path.exists(ph.library_path()):
+        pytest.skip("library not built")
+    L = ph.lib()
+    for code in range(0, 9):
+        assert L.poly_strerror(code)
+    # host checks: null / inconsistent CSR are rejected before any launch
+    c = ph.PolyCSR()
+    c.nvars = 0
+    size = ctypes.c_size_t()
+    assert L.poly_simplify_workspace(ctypes.byref(c), ctypes.byref(size)) == 1
+    rp = np.array([0, 3, 2], np.int64)        # decreasing row pointer
+    c.nvars = 2
+    c.max_exp = 3
+    c.npolys = 2
+    c.capacity = 3
+    c.row_ptr_host = rp.ctypes.data_as(ctypes.c_void_p)
+    c.row_ptr = ctypes.c_void_p(1)
+    c.exps = ctypes.c_void_p(1)
+    c.coefs = ctypes.c_void_p(1)
+    assert L.poly_simplify_workspace(ctypes.byref(c), ctypes.byref(size)) == 1
+    rp2 = np.array([0, 2, 3], np.int64)
+    c.row_ptr_host = rp2.ctypes.data_as(ctypes.c_void_p)
+    assert L.poly_simplify_workspace(ctypes.byref(c), ctypes.byref(size)) == 0
+    assert size.value > 0
+    # key overflow: 40 variables * 3 bits > 64
+    c.nvars = 40
+    raw = ctypes.c_int64()
+    assert L.poly_mul_workspace(ctypes.byref(c), ctypes.byref(c), ctypes.byref(size), ctypes.byref(raw)) == 0
+    assert raw.value == 2 * 2 + 1 * 1
+    # dense workspace sizes
+    assert L.poly_eval_dense_workspace(30, 1000, 10, 10, 1, 9, ctypes.byref(size)) == 1   # nslices out of range
+    assert L.poly_eval_dense_workspace(30, 1000, 10, 10, 1, 5, ctypes.byref(size)) == 0
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    import paper_2604_06575_amd as ph
+    monkeypatch.setattr(ph, "_LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(ph, "_lib", None)
+    with pytest.raises(RuntimeError):
+        ph.lib()

@@ -1,0 +1,342 @@
+"""HIP path vs the CPU oracle, element by element, through the C ABI.
+
+Integer work (exponent rows, term counts, order) is compared bit for bit;
+coefficients of simplify/times are bit-exact too, because the merge sums every
+run of equal monomials in the raw term order, the oracle's order.
+Evaluation results are compared within |d| <= 1e-12 * sum_t |c_t v_t|
+(FP64 rounding of a sum in a different order), and exactly at small integer
+points with integer coefficients.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ph():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_06575_amd as ph
+    ph.lib()
+    return ph
+
+
+def dev_batch(ph, polys, n, max_exp=None):
+    rp, E, C = W.csr_from_list(polys, n)
+    return ph.batch_from_numpy(rp, E, C, n=n, max_exp=max_exp)
+
+
+def assert_csr_bitwise(got, exp_rp, exp_E, exp_C):
+    rp, E, C = got
+    assert np.array_equal(rp, exp_rp), "row pointers differ"
+    assert np.array_equal(E, exp_E), "exponent rows differ"
+    assert C.view(np.uint64).tolist() == np.asarray(exp_C, dtype=np.float64).view(np.uint64).tolist(), \
+        "coefficients differ bitwise"
+
+
+def eval_tol(rp, E, C, X):
+    """1e-12 * sum_t |c_t v_t| (condition-scaled bound)."""
+    A = oracle.eval_batch(rp, E, np.abs(C), np.abs(X))
+    return 1e-12 * A + 1e-300
+
+
+# ------------------------------------------------------------------ simplify
+
+def test_simplify_worked_examples(ph, golden):
+    from conftest import poly_from_json
+    g = golden["W5_mixed_simplify"]
+    pe, pc = poly_from_json(g["p"], 4)
+    qe, qc = poly_from_json(g["q"], 4)
+    say("simplify W5")
+    b = dev_batch(ph, [(np.vstack([pe, qe]), np.concatenate([pc, qc]))], 4)
+    out = ph.batch_to_numpy(ph.simplify(b))
+    xe, xc = poly_from_json(g["simplified"], 4)
+    assert_csr_bitwise(out, np.array([0, xe.shape[0]]), xe, xc)
+    g = golden["W1_scalar_workflow"]
+    e, c = poly_from_json(g["input"], 3)
+    say("simplify W1")
+    out = ph.batch_to_numpy(ph.simplify(dev_batch(ph, [(e, c)], 3)))
+    xe, xc = poly_from_json(g["simplified"], 3)
+    assert_csr_bitwise(out, np.array([0, 4]), xe, xc)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_simplify_random_batches(ph, seed):
+    rng = W.rng_for(500 + seed)
+    n = int(rng.integers(1, 9))
+    d = int(rng.integers(1, 7))
+    P = int(rng.integers(1, 40))
+    polys = [W.random_poly(rng, n, d, int(rng.integers(0, 300)), integer=bool(seed % 2)) for _ in range(P)]
+    tol = 0.0 if seed < 4 else 0.3
+    rp, E, C = W.csr_from_list(polys, n)
+    say(f"simplify random seed={seed} n={n} d={d} P={P} T={rp[-1]}")
+    out = ph.batch_to_numpy(ph.simplify(ph.batch_from_numpy(rp, E, C, n=n, max_exp=d), tol))
+    assert_csr_bitwise(out, *oracle.simplify_batch(rp, E, C, tol, n=n))
+
+
+def test_simplify_batch_matrix_small(ph):
+    """Polynomial-matrix batch with log-uniform entry sizes, including entries
+    larger than one LDS tile (the key-range bisection path)."""
+    wl = W.batch_matrix(seed=W.SEED_BASE + 30, entries=48, tmin=10, tmax=20000, npts=0)
+    say(f"simplify matrix entries=48 T={wl.row_ptr[-1]} max entry={np.diff(wl.row_ptr).max()}")
+    b = ph.batch_from_numpy(wl.row_ptr, wl.exps, wl.coefs, n=wl.n, max_exp=wl.max_exp)
+    out = ph.batch_to_numpy(ph.simplify(b))
+    assert_csr_bitwise(out, *oracle.simplify_batch(wl.row_ptr, wl.exps, wl.coefs))
+
+
+def test_simplify_giant_run(ph):
+    """One monomial repeated far beyond a tile, plus a cancelling entry."""
+    rng = W.rng_for(77)
+    e = np.tile(np.array([[1, 2, 0]], np.uint8), (9000, 1))
+    c = rng.standard_normal(9000)
+    e2 = np.vstack([e[:5000], W.random_poly(rng, 3, 3, 3000)[0]])
+    c2 = np.concatenate([c[:5000], rng.standard_normal(3000)])
+    e3 = np.array([[1, 1, 1], [1, 1, 1]], np.uint8)
+    c3 = np.array([2.5, -2.5])
+    polys = [(e, c), (e2, c2), (e3, c3), (np.zeros((0, 3), np.uint8), np.zeros(0))]
+    rp, E, C = W.csr_from_list(polys, 3)
+    say("simplify giant run")
+    out = ph.batch_to_numpy(ph.simplify(ph.batch_from_numpy(rp, E, C, n=3, max_exp=3)))
+    assert_csr_bitwise(out, *oracle.simplify_batch(rp, E, C))
+    assert out[0][3] - out[0][2] == 0    # cancelled entry is the structural zero
+
+
+# ----------------------------------------------------------------------- mul
+
+def test_mul_worked_examples(ph, golden):
+    from conftest import poly_from_json
+    g = golden["XY_square"]
+    p = poly_from_json(g["p"], 2)
+    say("mul (x+y)^2")
+    out = ph.batch_to_numpy(ph.mul(dev_batch(ph, [p], 2), dev_batch(ph, [p], 2)))
+    xe, xc = poly_from_json(g["square"], 2)
+    assert_csr_bitwise(out, np.array([0, 3]), xe, xc)
+    g = golden["W6_matrix_ops"]
+    A = [poly_from_json(t, 2) for t in g["A"]]
+    say("mul A.^2")
+    ba = dev_batch(ph, A, 2, max_exp=1)
+    out = ph.batch_to_numpy(ph.mul(ba, ba))
+    exp = W.csr_from_list([oracle.mul(*a, *a, n=2) for a in A], 2)
+    assert_csr_bitwise(out, *exp)
+    assert out[0][3] - out[0][2] == 0
+
+
+def test_mul_plain_small(ph):
+    wl = W.plain_small()
+    say("mul plain small (n=4, 200x200)")
+    a = ph.batch_from_numpy([0, 200], wl.a_exps, wl.a_coefs, n=4, max_exp=6)
+    b = ph.batch_from_numpy([0, 200], wl.b_exps, wl.b_coefs, n=4, max_exp=6)
+    out = ph.batch_to_numpy(ph.mul(a, b))
+    oe, oc = oracle.mul(wl.a_exps, wl.a_coefs, wl.b_exps, wl.b_coefs)
+    assert_csr_bitwise(out, np.array([0, oe.shape[0]]), oe, oc)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_mul_random_pairs(ph, seed):
+    rng = W.rng_for(600 + seed)
+    n = int(rng.integers(1, 7))
+    d = int(rng.integers(1, 5))
+    P = int(rng.integers(1, 12))
+    A, B = [], []
+    for _ in range(P):
+        A.append(W.random_poly(rng, n, d, int(rng.integers(0, 120)), integer=bool(seed % 2)))
+        B.append(W.random_poly(rng, n, d, int(rng.integers(0, 120)), integer=bool(seed % 2)))
+    arp, aE, aC = W.csr_from_list(A, n)
+    brp, bE, bC = W.csr_from_list(B, n)
+    say(f"mul random seed={seed} n={n} P={P}")
+    out = ph.batch_to_numpy(ph.mul(ph.batch_from_numpy(arp, aE, aC, n=n, max_exp=d),
+                                   ph.batch_from_numpy(brp, bE, bC, n=n, max_exp=d)))
+    assert_csr_bitwise(out, *oracle.mul_batch(arp, aE, aC, brp, bE, bC, n=n))
+
+
+def test_mul_many_buckets(ph):
+    """A pair with several hundred thousand raw terms (many key buckets),
+    Gaussian coefficients: still bit-exact because runs are summed in (i, j)
+    order."""
+    wl = W.plain_large(seed=W.SEED_BASE + 40, terms=700, n=6, d=6)
+    say("mul 700x700 n=6")
+    a = ph.batch_from_numpy([0, 700], wl.a_exps, wl.a_coefs, n=6, max_exp=6)
+    b = ph.batch_from_numpy([0, 700], wl.b_exps, wl.b_coefs, n=6, max_exp=6)
+    out = ph.batch_to_numpy(ph.mul(a, b))
+    oe, oc = oracle.mul(wl.a_exps, wl.a_coefs, wl.b_exps, wl.b_coefs)
+    assert_csr_bitwise(out, np.array([0, oe.shape[0]]), oe, oc)
+
+
+def test_mul_swapped_and_giant_run(ph):
+    rng = W.rng_for(41)
+    # |a| > |b| (rows become b's terms) with duplicates in a
+    a = W.random_poly(rng, 3, 3, 900)
+    b = W.random_poly(rng, 3, 3, 25)
+    # a giant run: 3000 copies of x1 times 5 copies of x2 -> 15000 raw terms of x1*x2
+    ga = (np.tile(np.array([[1, 0, 0]], np.uint8), (3000, 1)), rng.standard_normal(3000))
+    gb = (np.tile(np.array([[0, 1, 0]], np.uint8), (5, 1)), rng.standard_normal(5))
+    arp, aE, aC = W.csr_from_list([a, ga], 3)
+    brp, bE, bC = W.csr_from_list([b, gb], 3)
+    say("mul swapped + giant run")
+    out = ph.batch_to_numpy(ph.mul(ph.batch_from_numpy(arp, aE, aC, n=3, max_exp=3),
+                                   ph.batch_from_numpy(brp, bE, bC, n=3, max_exp=3)))
+    rp, E, C = oracle.mul_batch(arp, aE, aC, brp, bE, bC, n=3)
+    assert np.array_equal(out[0], rp) and np.array_equal(out[1], E)
+    # pair 0 (integer coefficients) is bit-exact in any summation order
+    assert np.array_equal(out[2][rp[0]:rp[1]], C[rp[0]:rp[1]])
+    # pair 1 (one run of 15000 Gaussian products, summed in (i, j) order)
+    assert out[2][rp[1]:rp[2]].view(np.uint64).tolist() == C[rp[1]:rp[2]].view(np.uint64).tolist()
+
+
+def test_mul_errors(ph):
+    a = dev_batch(ph, [(np.array([[200, 0]], np.uint8), np.array([1.0]))], 2, max_exp=200)
+    with pytest.raises(ph.PolyError):
+        ph.mul(a, a)            # 400 > 255 cannot be stored
+    wide = dev_batch(ph, [(np.ones((1, 40), np.uint8), np.array([1.0]))], 40, max_exp=3)
+    with pytest.raises(ph.PolyError) as ei:
+        ph.mul(wide, wide)      # 40 * 3 bits > 64
+    assert ei.value.code == 2
+    lie = dev_batch(ph, [(np.array([[5, 0]], np.uint8), np.array([1.0]))], 2, max_exp=2)
+    with pytest.raises(ph.PolyError) as ei:
+        ph.mul(lie, lie)        # exponent above the declared bound: device-detected
+    assert ei.value.code == 5
+
+
+# ------------------------------------------------------------------ jacobian
+
+@pytest.mark.parametrize("seed", range(3))
+def test_jacobian_bitwise(ph, seed):
+    rng = W.rng_for(700 + seed)
+    n = int(rng.integers(1, 12))
+    polys = [W.random_poly(rng, n, 5, int(rng.integers(0, 700)), integer=False) for _ in range(int(rng.integers(1, 20)))]
+    rp, E, C = W.csr_from_list(polys, n)
+    say(f"jacobian seed={seed} n={n} P={len(polys)}")
+    out = ph.batch_to_numpy(ph.jacobian(ph.batch_from_numpy(rp, E, C, n=n, max_exp=5)))
+    assert_csr_bitwise(out, *oracle.jacobian_batch(rp, E, C, n=n))
+
+
+# ---------------------------------------------------------------------- eval
+
+@pytest.mark.parametrize("seed", range(3))
+def test_eval_random(ph, seed):
+    rng = W.rng_for(800 + seed)
+    n = int(rng.integers(1, 20))
+    polys = [W.random_poly(rng, n, 6, int(rng.integers(0, 3000)), integer=False) for _ in range(int(rng.integers(1, 9)))]
+    rp, E, C = W.csr_from_list(polys, n)
+    X = W.points(801 + seed, int(rng.integers(1, 300)), n)
+    say(f"eval seed={seed} n={n} P={len(polys)} N={X.shape[0]}")
+    Y = ph.eval(ph.batch_from_numpy(rp, E, C, n=n, max_exp=6), torch.from_numpy(X).cuda()).cpu().numpy()
+    Yo = oracle.eval_batch(rp, E, C, X)
+    assert (np.abs(Y - Yo) <= eval_tol(rp, E, C, X)).all()
+
+
+def test_eval_integer_exact(ph):
+    rng = W.rng_for(850)
+    polys = [W.random_poly(rng, 4, 5, 50) for _ in range(5)] + [(np.zeros((0, 4), np.uint8), np.zeros(0))]
+    rp, E, C = W.csr_from_list(polys, 4)
+    X = W.integer_points(851, 70, 4, -2, 2)
+    X[0] = 0.0                                       # 0^0 = 1
+    say("eval integer exact")
+    Y = ph.eval(ph.batch_from_numpy(rp, E, C, n=4, max_exp=5), torch.from_numpy(X).cuda()).cpu().numpy()
+    assert np.array_equal(Y, oracle.eval_batch(rp, E, C, X))
+    assert (Y[-1] == 0).all()
+
+
+def test_eval_wide_support_and_long_poly(ph):
+    """Terms with more than eight variables (dense fallback) and one long
+    polynomial split across the waves of a workgroup."""
+    rng = W.rng_for(860)
+    n = 12
+    e = rng.integers(0, 3, size=(9000, n)).astype(np.uint8)
+    c = rng.standard_normal(9000)
+    rp = np.array([0, 9000], np.int64)
+    X = W.points(861, 130, n)
+    say("eval wide support")
+    Y = ph.eval(ph.batch_from_numpy(rp, e, c, n=n, max_exp=2), torch.from_numpy(X).cuda()).cpu().numpy()
+    Yo = oracle.eval_batch(rp, e, c, X)
+    assert (np.abs(Y - Yo) <= eval_tol(rp, e, c, X)).all()
+
+
+def test_grad_hess(ph):
+    rng = W.rng_for(870)
+    n = 5
+    polys = [W.random_poly(rng, n, 4, int(rng.integers(1, 400)), integer=False) for _ in range(4)]
+    rp, E, C = W.csr_from_list(polys, n)
+    X = W.points(871, 100, n)
+    b = ph.batch_from_numpy(rp, E, C, n=n, max_exp=4)
+    Xd = torch.from_numpy(X).cuda()
+    say("grad")
+    G = ph.grad(b, Xd, check=True).cpu().numpy()
+    Go = oracle.grad_batch(rp, E, C, X)
+    scale = 1e-12 * (np.abs(Go).max() + 1) * 50
+    assert np.abs(G - Go).max() <= scale
+    say("hess")
+    H = ph.hess(b, Xd, check=True).cpu().numpy()
+    Ho = oracle.hess_batch(rp, E, C, X)
+    assert np.abs(H - Ho).max() <= 1e-12 * (np.abs(Ho).max() + 1) * 200
+    assert np.array_equal(H, np.swapaxes(H, 2, 3))   # bitwise symmetric
+
+
+def test_grad_hess_integer_exact(ph):
+    rng = W.rng_for(880)
+    n = 4
+    polys = [W.random_poly(rng, n, 4, 60) for _ in range(3)]
+    rp, E, C = W.csr_from_list(polys, n)
+    X = W.integer_points(881, 40, n)
+    b = ph.batch_from_numpy(rp, E, C, n=n, max_exp=4)
+    Xd = torch.from_numpy(X).cuda()
+    say("grad/hess integer")
+    assert np.array_equal(ph.grad(b, Xd).cpu().numpy(), oracle.grad_batch(rp, E, C, X))
+    assert np.array_equal(ph.hess(b, Xd).cpu().numpy(), oracle.hess_batch(rp, E, C, X))
+
+
+def test_eval_backward(ph):
+    rng = W.rng_for(890)
+    n = 4
+    polys = [W.random_poly(rng, n, 4, int(rng.integers(1, 300)), integer=False) for _ in range(3)]
+    rp, E, C = W.csr_from_list(polys, n)
+    X = W.points(891, 700, n)
+    gY = rng.standard_normal((3, 700))
+    say("eval backward")
+    dX, dC = ph.eval_backward(ph.batch_from_numpy(rp, E, C, n=n, max_exp=4), torch.from_numpy(X).cuda(),
+                              torch.from_numpy(gY).cuda(), check=True)
+    dXo, dCo = oracle.eval_backward(rp, E, C, X, gY)
+    assert np.allclose(dX.cpu().numpy(), dXo, rtol=1e-11, atol=1e-11)
+    assert np.allclose(dC.cpu().numpy(), dCo, rtol=1e-11, atol=1e-11)
+
+
+# --------------------------------------------------------------------- dense
+
+@pytest.mark.parametrize("P,K,N", [(37, 300, 150), (130, 1000, 70)])
+def test_dense_fp64(ph, P, K, N):
+    wl = W.dense_shared(seed=900 + P, P=P, N=N, n=7, d=4, K=K)
+    say(f"dense fp64 P={P} K={K} N={N}")
+    Y = ph.eval_dense(torch.from_numpy(wl.basis).cuda(), torch.from_numpy(wl.C).cuda(),
+                      torch.from_numpy(wl.X).cuda(), prec=ph.POLY_FP64).cpu().numpy()
+    Yo = oracle.eval_dense(wl.basis, wl.C, wl.X)
+    A = oracle.eval_dense(wl.basis, np.abs(wl.C), np.abs(wl.X))
+    assert (np.abs(Y - Yo) <= 1e-12 * A).all()
+
+
+@pytest.mark.parametrize("S", [4, 5, 6])
+def test_dense_split(ph, S):
+    wl = W.dense_shared(seed=950, P=70, N=90, n=8, d=4, K=400)
+    say(f"dense split S={S}")
+    Y = ph.eval_dense(torch.from_numpy(wl.basis).cuda(), torch.from_numpy(wl.C).cuda(),
+                      torch.from_numpy(wl.X).cuda(), prec=ph.POLY_SPLIT_BF16, nslices=S).cpu().numpy()
+    Yo = oracle.eval_dense(wl.basis, wl.C, wl.X)
+    A = oracle.eval_dense(wl.basis, np.abs(wl.C), np.abs(wl.X))
+    err = np.abs(Y - Yo) / A
+    say(f"  S={S} max condition-scaled error {err.max():.3e}")
+    bound = 2.0 ** -(8 * S - 12)
+    assert err.max() <= bound
+    if S >= 5:
+        assert err.max() <= 1e-10
