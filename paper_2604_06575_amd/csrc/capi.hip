@@ -125,7 +125,9 @@ SimplifyPlan plan_simplify(int64_t P, int64_t T)
 struct MulPlan {
     size_t ka, kb, ka_s, kb_s, perm_a, perm_b, cnt_tmp, order_a, order_b, queues, pb_count, pb_start;
     size_t bk_pair, bk_lo, bk_hi, bk_stage_off, bk_count, out_off, cursor, st_key, st_coef;
-    int64_t raw, nbuckets;
+    int64_t raw, nbuckets, target;
+    bool lds_mode;          // partner and row keys of every pair fit in LDS
+    size_t lds_dyn;         // dynamic LDS bytes of the LDS bucket kernel
     size_t total;
 };
 
@@ -134,13 +136,26 @@ poly_status plan_mul(const poly_csr *a, const poly_csr *b, MulPlan &m)
     const int64_t P = a->npolys;
     const int64_t Ta = total_terms(a), Tb = total_terms(b);
     int64_t raw = 0, nb = 0;
+    size_t lds_max = 0;
+    int64_t rows_max = 0, ns_max = 0;
     for (int64_t p = 0; p < P; ++p) {
         const int64_t ta = a->row_ptr_host[p + 1] - a->row_ptr_host[p];
         const int64_t tb = b->row_ptr_host[p + 1] - b->row_ptr_host[p];
         const int64_t r = ta * tb;
         if (r >= (int64_t(1) << 32)) return POLY_ERR_UNSUPPORTED;
         raw += r;
-        nb += mul_buckets_for(r);
+        const int64_t nrows = std::min(ta, tb), ns = std::max(ta, tb);
+        lds_max = std::max(lds_max, mb_lds_bytes(ns, nrows));
+        rows_max = std::max(rows_max, nrows);
+        ns_max = std::max(ns_max, ns);
+    }
+    m.lds_mode = lds_max <= MB_LDS_LIMIT && rows_max <= MB_MAX_ROWS && ns_max <= MB_MAX_PARTNERS;
+    m.lds_dyn = std::max<size_t>(lds_max, 16);
+    m.target = m.lds_mode ? MB_TARGET : MUL_TARGET;
+    for (int64_t p = 0; p < P; ++p) {
+        const int64_t ta = a->row_ptr_host[p + 1] - a->row_ptr_host[p];
+        const int64_t tb = b->row_ptr_host[p + 1] - b->row_ptr_host[p];
+        nb += mul_buckets_for(ta * tb, m.target);
     }
     if (nb >= (int64_t(1) << 31)) return POLY_ERR_UNSUPPORTED;
     Layout L;
@@ -171,8 +186,8 @@ poly_status plan_mul(const poly_csr *a, const poly_csr *b, MulPlan &m)
     return POLY_OK;
 }
 
-void launch_presort(const poly_csr *c, uint64_t *keys, uint64_t *sorted, uint32_t *perm, int64_t *cnt_tmp,
-                    int64_t *order, unsigned long long *queue, hipStream_t s)
+SegArgs presort_args(const poly_csr *c, uint64_t *keys, uint64_t *sorted, uint32_t *perm, int64_t *cnt_tmp,
+                     int64_t *order, unsigned long long *queue, hipStream_t s)
 {
     const int64_t P = c->npolys;
     hipLaunchKernelGGL(k_order_by_size, dim3(1), dim3(1024), 0, s, c->row_ptr, P, order);
@@ -188,8 +203,7 @@ void launch_presort(const poly_csr *c, uint64_t *keys, uint64_t *sorted, uint32_
     A.st_idx = perm;
     A.seg_count = cnt_tmp;
     A.tol = 0.0;
-    const int64_t grid = std::min<int64_t>(P, (int64_t)device_cus() * 3);
-    hipLaunchKernelGGL(k_seg_sort, dim3((unsigned)grid), dim3(SEG_THREADS), 0, s, A);
+    return A;
 }
 
 // ----------------------------------------------------------- eval helpers
@@ -219,6 +233,8 @@ void ensure_lds_attrs()
     if (lds_attr_done) return;
     (void)hipFuncSetAttribute((const void *)k_eval_blocks, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
     (void)hipFuncSetAttribute((const void *)k_backward_dc, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
+    (void)hipFuncSetAttribute((const void *)k_mul_buckets_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)MB_LDS_LIMIT);
     lds_attr_done = true;
 }
 
@@ -451,15 +467,23 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
         hipLaunchKernelGGL(k_pack, dim3(grid1(Tb, 256)), dim3(256), 0, s, b->exps, Tb, n, bits, b->max_exp,
                            (uint64_t *)A.kb, status);
     int64_t *cnt_tmp = at<int64_t>(ws, m.cnt_tmp);
-    launch_presort(a, (uint64_t *)A.ka, (uint64_t *)A.ka_s, (uint32_t *)A.perm_a, cnt_tmp,
-                   at<int64_t>(ws, m.order_a), queues + 0, s);
-    launch_presort(b, (uint64_t *)A.kb, (uint64_t *)A.kb_s, (uint32_t *)A.perm_b, cnt_tmp,
-                   at<int64_t>(ws, m.order_b), queues + 1, s);
+    const SegArgs sa = presort_args(a, (uint64_t *)A.ka, (uint64_t *)A.ka_s, (uint32_t *)A.perm_a, cnt_tmp,
+                                    at<int64_t>(ws, m.order_a), queues + 0, s);
+    const SegArgs sb = presort_args(b, (uint64_t *)A.kb, (uint64_t *)A.kb_s, (uint32_t *)A.perm_b, cnt_tmp,
+                                    at<int64_t>(ws, m.order_b), queues + 1, s);
+    const int64_t pgrid = std::min<int64_t>(P, (int64_t)device_cus() * 2);
+    hipLaunchKernelGGL(k_seg_sort2, dim3((unsigned)(2 * pgrid)), dim3(SEG_THREADS), 0, s, sa, sb);
     int64_t *pb_count = at<int64_t>(ws, m.pb_count);
-    hipLaunchKernelGGL(k_mul_plan, dim3(grid1(P, 256)), dim3(256), 0, s, a->row_ptr, b->row_ptr, P, pb_count);
+    hipLaunchKernelGGL(k_mul_plan, dim3(grid1(P, 256)), dim3(256), 0, s, a->row_ptr, b->row_ptr, P, pb_count,
+                       m.target);
     hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, pb_count, P, (int64_t *)A.pb_start);
-    hipLaunchKernelGGL(k_mul_splitters, dim3((unsigned)P), dim3(1024), 0, s, A);
-    hipLaunchKernelGGL(k_mul_buckets, dim3((unsigned)m.nbuckets), dim3(MUL_THREADS), 0, s, A);
+    hipLaunchKernelGGL(k_mul_splitters, dim3((unsigned)P), dim3(512), 0, s, A);
+    if (m.lds_mode) {
+        ensure_lds_attrs();
+        hipLaunchKernelGGL(k_mul_buckets_lds, dim3((unsigned)m.nbuckets), dim3(MB_THREADS), m.lds_dyn, s, A);
+    } else {
+        hipLaunchKernelGGL(k_mul_buckets, dim3((unsigned)m.nbuckets), dim3(MUL_THREADS), 0, s, A);
+    }
     int64_t *out_off = at<int64_t>(ws, m.out_off);
     hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, A.bk_count, m.nbuckets, out_off);
     hipLaunchKernelGGL(k_compact, dim3((unsigned)m.nbuckets), dim3(256), 0, s, A.bk_stage_off, A.bk_count,

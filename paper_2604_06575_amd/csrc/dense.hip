@@ -153,7 +153,9 @@ __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, con
         for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t r = r0 + wr * 32 + rt * 16 + 4 * (lane >> 4) + v;
+                // v_mfma_f64_16x16x4f64 result: lane l, register v holds
+                // row (l / 16) + 4 v, column l % 16 of the 16 x 16 tile
+                const int64_t r = r0 + wr * 32 + rt * 16 + (lane >> 4) + 4 * v;
                 const int64_t c = n0 + wc * 64 + ct * 16 + (lane & 15);
                 if (r < P && c < N) Y[r * N + c] = acc[rt][ct][v];
             }

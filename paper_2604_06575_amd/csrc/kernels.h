@@ -6,8 +6,9 @@
 namespace polyhip {
 
 // ------------------------------------------------------------ simplify / sort
-constexpr int SEG_THREADS = 256;
-constexpr int SEG_CAP = 4096;  // terms held in LDS by one tile
+constexpr int SEG_THREADS = 512;
+constexpr int SEG_ITEMS = 8;
+constexpr int SEG_CAP = SEG_THREADS * SEG_ITEMS;  // terms held in LDS by one tile
 
 struct SegArgs {
     const int64_t *rp;          // [P+1] CSR of the segments
@@ -29,6 +30,7 @@ __global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t 
 __global__ void k_order_by_size(const int64_t *rp, int64_t P, int64_t *order);
 __global__ void k_seg_merge(SegArgs A);
 __global__ void k_seg_sort(SegArgs A);
+__global__ void k_seg_sort2(SegArgs A, SegArgs B);
 __global__ void k_scan_counts(const int64_t *counts, int64_t S, int64_t *out);
 __global__ void k_compact(const int64_t *stage_off, const int64_t *seg_count, const int64_t *out_off,
                           const uint64_t *st_key, const double *st_coef, int n, int bits,
@@ -37,14 +39,15 @@ __global__ void k_compact(const int64_t *stage_off, const int64_t *seg_count, co
 // ------------------------------------------------------------------------ mul
 constexpr int MUL_THREADS = 256;
 constexpr int MUL_CAP = 4096;
-constexpr int64_t MUL_TARGET = 3072;       // raw terms per bucket, on average
-constexpr int MUL_SAMPLE = 16384;          // splitter sample per pair
-constexpr int64_t MUL_MAX_BUCKETS = 8192;  // per pair
+constexpr int64_t MUL_TARGET = 3072;       // raw terms per bucket, global-memory bucket kernel
+constexpr int64_t MB_TARGET = 16384;       // raw terms per bucket, LDS bucket kernel
+constexpr int MUL_SAMPLE = 8192;           // splitter sample per pair
+constexpr int64_t MUL_MAX_BUCKETS = 4096;  // per pair
 
-__host__ __device__ inline int64_t mul_buckets_for(int64_t raw)
+__host__ __device__ inline int64_t mul_buckets_for(int64_t raw, int64_t target)
 {
-    if (raw <= MUL_CAP) return 1;
-    int64_t b = (raw + MUL_TARGET - 1) / MUL_TARGET;
+    if (raw <= target) return 1;
+    int64_t b = (raw + target - 1) / target;
     return b > MUL_MAX_BUCKETS ? MUL_MAX_BUCKETS : b;
 }
 
@@ -69,9 +72,23 @@ struct MulArgs {
 };
 
 __global__ void k_mul_init_buckets(MulArgs A);
-__global__ void k_mul_plan(const int64_t *a_rp, const int64_t *b_rp, int64_t P, int64_t *pb_count);
+__global__ void k_mul_plan(const int64_t *a_rp, const int64_t *b_rp, int64_t P, int64_t *pb_count, int64_t target);
 __global__ void k_mul_splitters(MulArgs A);
 __global__ void k_mul_buckets(MulArgs A);
+// Cursor-based bucket kernel: partner keys (and row keys) resident in LDS.
+constexpr int MB_THREADS = 512;
+constexpr int MB_ITEMS = 8;
+constexpr int MB_CAP = MB_THREADS * MB_ITEMS;
+constexpr int MB_RPT = 16;                     // rows per thread -> at most 8192 rows
+constexpr int MB_MAX_ROWS = MB_THREADS * MB_RPT;
+// dynamic LDS of the LDS bucket kernel: partner keys, row keys, 16-bit row cursors
+__host__ __device__ inline size_t mb_lds_bytes(int64_t ns, int64_t nrows)
+{
+    return (size_t)(ns + nrows) * 8 + (size_t)nrows * 2;
+}
+constexpr size_t MB_LDS_LIMIT = 100 * 1024;    // with the static part, within 160 KB
+constexpr int64_t MB_MAX_PARTNERS = 65535;     // cursors are 16-bit
+__global__ void k_mul_buckets_lds(MulArgs A);
 __global__ void k_mul_rowptr(const int64_t *out_off, const int64_t *pb_start, int64_t P, int64_t *out_rp,
                              int64_t nbuckets);
 

@@ -24,12 +24,12 @@
 
 namespace polyhip {
 
-__global__ void k_mul_plan(const int64_t *a_rp, const int64_t *b_rp, int64_t P, int64_t *pb_count)
+__global__ void k_mul_plan(const int64_t *a_rp, const int64_t *b_rp, int64_t P, int64_t *pb_count, int64_t target)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     const int64_t raw = (a_rp[p + 1] - a_rp[p]) * (b_rp[p + 1] - b_rp[p]);
-    pb_count[p] = mul_buckets_for(raw);
+    pb_count[p] = mul_buckets_for(raw, target);
 }
 
 __global__ void k_mul_rowptr(const int64_t *out_off, const int64_t *pb_start, int64_t P, int64_t *out_rp,
@@ -53,13 +53,22 @@ __global__ void k_mul_init_buckets(MulArgs A)
     A.bk_hi[b] = 0;
 }
 
-// One block per pair; buckets [s_q, s_{q+1} - 1] from a sorted sample.
-__global__ void __launch_bounds__(1024) k_mul_splitters(MulArgs A)
+// One block per pair; buckets [s_q, s_{q+1} - 1] at quantiles of a sample
+// of raw product keys.  A splitter only has to be some key value, so the
+// sample is sorted on its 24 most significant varying bits and the splitters
+// are those truncated values.
+constexpr int SPL_THREADS = 512;
+constexpr int SPL_ITEMS = MUL_SAMPLE / SPL_THREADS;
+
+__global__ void __launch_bounds__(SPL_THREADS) k_mul_splitters(MulArgs A)
 {
     __shared__ uint64_t s_smp[MUL_SAMPLE];
+    __shared__ uint32_t s_cnt[(SPL_THREADS / kWave) * 256];
+    __shared__ uint32_t s_scan[SPL_THREADS / kWave];
+    __shared__ uint64_t s_red[SPL_THREADS / kWave];
     const int64_t p = blockIdx.x;
     const int64_t b0 = A.pb_start[p];
-    int64_t nb = A.pb_start[p + 1] - b0;
+    const int64_t nb = A.pb_start[p + 1] - b0;
     if (b0 + nb > A.nbuckets) {
         if (threadIdx.x == 0) set_status(A.status, POLY_ERR_ARG);
         return;
@@ -74,21 +83,29 @@ __global__ void __launch_bounds__(1024) k_mul_splitters(MulArgs A)
     }
     const int64_t a0 = A.a_rp[p], ta = A.a_rp[p + 1] - a0;
     const int64_t bb = A.b_rp[p], tb = A.b_rp[p + 1] - bb;
-    int M = 256;
-    while (M < MUL_SAMPLE && (int64_t)M < 8 * nb) M <<= 1;
-    for (int k = threadIdx.x; k < M; k += blockDim.x) {
+    const int M = MUL_SAMPLE;
+    uint64_t lmin = ~0ull, lmax = 0;
+    for (int k = threadIdx.x; k < M; k += SPL_THREADS) {
         const int64_t i = ((int64_t)k * ta) / M;
         const int64_t j = (int64_t)(hash32((uint32_t)k * 2654435761u ^ (uint32_t)p) % (uint32_t)tb);
-        s_smp[k] = A.ka[a0 + i] + A.kb[bb + j];
+        const uint64_t key = A.ka[a0 + i] + A.kb[bb + j];
+        s_smp[k] = key;
+        lmin = key < lmin ? key : lmin;
+        lmax = key > lmax ? key : lmax;
     }
+    const uint64_t kmin = block_min_u64<SPL_THREADS>(lmin, s_red);
+    const uint64_t kmax = block_max_u64<SPL_THREADS>(lmax, s_red);
+    const int vbits = kmax > kmin ? 64 - __clzll((unsigned long long)(kmax - kmin)) : 0;
+    const int shift = vbits > 24 ? vbits - 24 : 0;
+    for (int k = threadIdx.x; k < M; k += SPL_THREADS) s_smp[k] = (s_smp[k] - kmin) >> shift;
     __syncthreads();
-    lds_sort_keys<1024>(s_smp, M);
-    for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) {
-        uint64_t lo = q == 0 ? 0ull : s_smp[(q * M) / nb];
+    lds_radix_sort_keys<SPL_THREADS, SPL_ITEMS>(s_smp, M, vbits - shift, s_cnt, s_scan);
+    for (int64_t q = threadIdx.x; q < nb; q += SPL_THREADS) {
+        uint64_t lo = q == 0 ? 0ull : (s_smp[(q * M) / nb] << shift) + kmin;
         uint64_t hi = ~0ull;
         bool empty = false;
         if (q < nb - 1) {
-            const uint64_t nxt = s_smp[((q + 1) * M) / nb];
+            const uint64_t nxt = (s_smp[((q + 1) * M) / nb] << shift) + kmin;
             if (nxt == 0) empty = true;
             else hi = nxt - 1;
         }
@@ -349,6 +366,279 @@ __global__ void __launch_bounds__(MUL_THREADS) k_mul_buckets(MulArgs A)
         }
     }
     if (threadIdx.x == 0) {
+        A.bk_count[b] = written;
+        A.bk_stage_off[b] = stage;
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Cursor-based bucket kernel.
+//
+// The partner keys (the sorted operand) and the row keys of the pair sit in
+// LDS.  Each row keeps a cursor at its first partner whose product key is not
+// below the current piece's lower bound; pieces are taken in ascending key
+// order, so a piece [lo, hi] is exactly the partners between each row's
+// cursor and the first product key above hi, found by galloping.  A piece
+// holding more than MB_CAP raw terms is bisected by key value.  Each piece is
+// generated row by row in (row, partner) order, sorted by a stable LDS radix
+// sort on its key (relative to the piece minimum), and every run of equal
+// keys is summed left to right -- the raw (i, j) order.  When the row operand
+// is b (|a| > |b|), the index i*|b| + j is appended below the key bits so the
+// sort itself produces (key, i, j) order.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct MbShared {
+    uint64_t key[MB_CAP];
+    uint32_t val[MB_CAP];
+    uint32_t cnt[(MB_THREADS / kWave) * 256];
+    uint32_t scan32[MB_THREADS / kWave];
+    int64_t scan[MB_THREADS / kWave];
+    uint64_t red[MB_THREADS / kWave];
+    uint64_t stk_lo[72];
+    uint64_t stk_hi[72];
+    int64_t stk_cnt[72];
+    int64_t bcast;
+};
+
+// Number of partners t >= c with s[t] + kr <= hi (galloping from c).
+__device__ inline uint32_t advance_count(const uint64_t *s, uint32_t ns, uint32_t c, uint64_t kr, uint64_t hi)
+{
+    if (hi < kr) return 0;
+    const uint64_t lim = hi - kr;   // s[t] <= lim
+    if (c >= ns || s[c] > lim) return 0;
+    uint32_t lo = c, step = 1;      // s[lo] <= lim
+    uint32_t hi_i = c + 1;
+    while (hi_i < ns && s[hi_i] <= lim) {
+        lo = hi_i;
+        step <<= 1;
+        hi_i = c + step;
+    }
+    if (hi_i > ns) hi_i = ns;
+    // answer index in (lo, hi_i]: first t with s[t] > lim
+    uint32_t a = lo + 1, b = hi_i;
+    while (a < b) {
+        const uint32_t mid = (a + b) >> 1;
+        if (s[mid] <= lim) a = mid + 1;
+        else b = mid;
+    }
+    return a - c;
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(MB_THREADS) k_mul_buckets_lds(MulArgs A)
+{
+    extern __shared__ uint64_t s_dyn[];
+    __shared__ MbShared S;
+    const int64_t b = blockIdx.x;
+    const int64_t p = A.bk_pair[b];
+    const uint64_t lo0 = A.bk_lo[b], hi0 = A.bk_hi[b];
+    const int64_t a0 = A.a_rp[p], ta = A.a_rp[p + 1] - a0;
+    const int64_t bb = A.b_rp[p], tb = A.b_rp[p + 1] - bb;
+    const int tid = threadIdx.x;
+    if (lo0 > hi0 || ta == 0 || tb == 0) {
+        if (tid == 0) {
+            A.bk_count[b] = 0;
+            A.bk_stage_off[b] = 0;
+        }
+        return;
+    }
+    const bool swapped = ta > tb;
+    const uint32_t nrows = (uint32_t)(swapped ? tb : ta);
+    const uint32_t ns = (uint32_t)(swapped ? ta : tb);
+    const uint64_t *g_rows = swapped ? A.kb + bb : A.ka + a0;
+    const uint64_t *g_srt = swapped ? A.ka_s + a0 : A.kb_s + bb;
+    const uint32_t *perm = swapped ? A.perm_a + a0 : A.perm_b + bb;
+    const double *ca = A.a_c + a0;
+    const double *cb = A.b_c + bb;
+    const uint32_t utb = (uint32_t)tb;
+    // ij needs ij_bits bits; in the swapped case it is sorted below the key
+    const int ij_bits = swapped ? 64 - __clzll((unsigned long long)(ta * tb - 1) | 1ull) : 0;
+
+    uint64_t *s_srt = s_dyn;                                   // [ns]
+    uint64_t *s_rows = s_dyn + ns;                             // [nrows]
+    uint16_t *s_cur = (uint16_t *)(s_dyn + ns + nrows);        // [nrows]
+    for (uint32_t i = tid; i < ns; i += MB_THREADS) s_srt[i] = g_srt[i];
+    for (uint32_t i = tid; i < nrows; i += MB_THREADS) s_rows[i] = g_rows[i];
+    __syncthreads();
+
+    // rows of this thread: [r0, r1)
+    const uint32_t rpt = (nrows + MB_THREADS - 1) / MB_THREADS;
+    const uint32_t r0 = tid * rpt < nrows ? tid * rpt : nrows;
+    const uint32_t r1 = r0 + rpt < nrows ? r0 + rpt : nrows;
+
+    // cursors at lo0 and the bucket's raw count
+    int64_t mine = 0;
+    for (uint32_t r = r0; r < r1; ++r) {
+        const uint64_t kr = s_rows[r];
+        const uint32_t c = lo0 <= kr ? 0u : (uint32_t)lower_bound_u64(s_srt, ns, lo0 - kr);
+        s_cur[r] = (uint16_t)c;
+        mine += advance_count(s_srt, ns, c, kr, hi0);
+    }
+    const int64_t root = block_sum<MB_THREADS>(mine, S.scan);
+    if (root == 0) {
+        if (tid == 0) {
+            A.bk_count[b] = 0;
+            A.bk_stage_off[b] = 0;
+        }
+        return;
+    }
+    if (tid == 0) {
+        S.bcast = (int64_t)atomicAdd(A.stage_cursor, (unsigned long long)root);
+        S.stk_lo[0] = lo0;
+        S.stk_hi[0] = hi0;
+        S.stk_cnt[0] = root;
+    }
+    __syncthreads();
+    const int64_t stage = S.bcast;
+    if (stage + root > A.st_capacity) {
+        if (tid == 0) {
+            set_status(A.status, POLY_ERR_ARG);
+            A.bk_count[b] = 0;
+            A.bk_stage_off[b] = 0;
+        }
+        return;
+    }
+    int64_t written = 0;
+    int sp = 1;
+    while (sp > 0) {
+        __syncthreads();
+        --sp;
+        const uint64_t lo = S.stk_lo[sp], hi = S.stk_hi[sp];
+        const int64_t cnt = S.stk_cnt[sp];
+        __syncthreads();
+        if (cnt == 0) continue;
+        const uint64_t width = hi - lo;
+        const int wbits = width ? 64 - __clzll((unsigned long long)width) : 0;
+        const bool fits = cnt <= MB_CAP && wbits + ij_bits <= 64;
+        if (fits) {
+            // ---- generate the piece in (row, partner) order
+            uint32_t cr[MB_RPT];
+            int64_t c = 0;
+#pragma unroll
+            for (int q = 0; q < MB_RPT; ++q) {
+                const uint32_t r = r0 + q;
+                cr[q] = 0;
+                if (r < r1) {
+                    cr[q] = advance_count(s_srt, ns, s_cur[r], s_rows[r], hi);
+                    c += cr[q];
+                }
+            }
+            int64_t tot;
+            int64_t pos = block_exclusive_scan<MB_THREADS>(c, S.scan, tot);
+            uint64_t kmax = 0;
+#pragma unroll
+            for (int q = 0; q < MB_RPT; ++q) {
+                const uint32_t r = r0 + q;
+                if (r < r1 && cr[q]) {
+                    const uint64_t kr = s_rows[r];
+                    const uint32_t c0 = s_cur[r];
+                    for (uint32_t t = c0; t < c0 + cr[q]; ++t, ++pos) {
+                        const uint64_t rel = kr + s_srt[t] - lo;
+                        const uint32_t o = perm[t];
+                        const uint32_t ij = swapped ? o * utb + r : r * utb + o;
+                        kmax = rel > kmax ? rel : kmax;
+                        if (pos < MB_CAP) {
+                            S.key[pos] = swapped ? ((rel << ij_bits) | ij) : rel;
+                            S.val[pos] = ij;
+                        }
+                    }
+                    s_cur[r] = (uint16_t)(c0 + cr[q]);
+                }
+            }
+            const uint64_t relmax = block_max_u64<MB_THREADS>(kmax, S.red);
+            const int m = (int)(tot < MB_CAP ? tot : MB_CAP);
+            const int rbits = relmax ? 64 - __clzll((unsigned long long)relmax) : 0;
+            lds_radix_sort<MB_THREADS, MB_ITEMS>(S.key, S.val, m, rbits + ij_bits, S.cnt, S.scan32);
+            // ---- merge runs: thread owns sorted elements [tid*ITEMS, tid*ITEMS + ITEMS)
+            const int e0 = tid * MB_ITEMS;
+            double sums[MB_ITEMS];
+            int64_t keepc = 0;
+            uint32_t keepmask = 0;
+#pragma unroll
+            for (int q = 0; q < MB_ITEMS; ++q) {
+                const int e = e0 + q;
+                sums[q] = 0.0;
+                if (e < m) {
+                    const uint64_t k = S.key[e] >> ij_bits;
+                    if (e == 0 || (S.key[e - 1] >> ij_bits) != k) {
+                        uint32_t v = S.val[e];
+                        double s = ca[v / utb] * cb[v % utb];
+                        for (int f = e + 1; f < m && (S.key[f] >> ij_bits) == k; ++f) {
+                            v = S.val[f];
+                            s = s + ca[v / utb] * cb[v % utb];
+                        }
+                        sums[q] = s;
+                        if (!(fabs(s) <= A.tol)) {
+                            keepmask |= 1u << q;
+                            ++keepc;
+                        }
+                    }
+                }
+            }
+            int64_t ktot;
+            int64_t kpos = block_exclusive_scan<MB_THREADS>(keepc, S.scan, ktot);
+#pragma unroll
+            for (int q = 0; q < MB_ITEMS; ++q) {
+                if (keepmask & (1u << q)) {
+                    const int64_t d = stage + written + kpos;
+                    A.st_key[d] = lo + (S.key[e0 + q] >> ij_bits);
+                    A.st_coef[d] = sums[q];
+                    ++kpos;
+                }
+            }
+            written += ktot;
+            __syncthreads();
+        } else if (lo == hi) {
+            // one product key with more raw terms than a tile: sum in (i, j)
+            // order (a's terms in storage order, partners in b's stable order)
+            if (tid == 0) {
+                const uint64_t *kbs = A.kb_s + bb;
+                const uint32_t *pb = A.perm_b + bb;
+                double s = 0.0;
+                bool first = true;
+                for (int64_t i = 0; i < ta; ++i) {
+                    const uint64_t kai = A.ka[a0 + i];
+                    if (kai > lo) continue;
+                    const int64_t l = lower_bound_u64(kbs, tb, lo - kai);
+                    const int64_t u = upper_bound_u64(kbs, tb, lo - kai);
+                    for (int64_t q = l; q < u; ++q) {
+                        const double t = ca[i] * cb[pb[q]];
+                        s = first ? t : s + t;
+                        first = false;
+                    }
+                }
+                const bool keep = !(fabs(s) <= A.tol);
+                if (keep) {
+                    A.st_key[stage + written] = lo;
+                    A.st_coef[stage + written] = s;
+                }
+                S.bcast = keep ? 1 : 0;
+            }
+            for (uint32_t r = r0; r < r1; ++r)
+                s_cur[r] = (uint16_t)(s_cur[r] + advance_count(s_srt, ns, s_cur[r], s_rows[r], hi));
+            __syncthreads();
+            written += S.bcast;
+        } else {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            int64_t c = 0;
+            for (uint32_t r = r0; r < r1; ++r) c += advance_count(s_srt, ns, s_cur[r], s_rows[r], mid);
+            const int64_t left = block_sum<MB_THREADS>(c, S.scan);
+            if (tid == 0) {
+                S.stk_lo[sp] = mid + 1;
+                S.stk_hi[sp] = hi;
+                S.stk_cnt[sp] = cnt - left;
+                S.stk_lo[sp + 1] = lo;
+                S.stk_hi[sp + 1] = mid;
+                S.stk_cnt[sp + 1] = left;
+            }
+            sp += 2;
+        }
+    }
+    if (tid == 0) {
         A.bk_count[b] = written;
         A.bk_stage_off[b] = stage;
     }

@@ -73,6 +73,8 @@ namespace {
 struct SegShared {
     uint64_t key[SEG_CAP];
     uint32_t val[SEG_CAP];
+    uint32_t cnt[(SEG_THREADS / kWave) * 256];
+    uint32_t scan32[SEG_THREADS / kWave];
     int64_t scan[SEG_THREADS / kWave];
     uint64_t red[SEG_THREADS / kWave];
     uint64_t stk_lo[72];
@@ -82,6 +84,29 @@ struct SegShared {
     double bcast;
     int64_t bcast_i;
 };
+
+// Sort the tile's m (key, local index) pairs by key.  The elements are in
+// storage order, and the radix sort is stable, so equal keys stay in storage
+// order.  Keys are made relative to the tile minimum so that only the bits
+// that actually vary are sorted.
+__device__ void sort_tile(SegShared &S, int m)
+{
+    uint64_t lmin = ~0ull, lmax = 0;
+    for (int i = threadIdx.x; i < m; i += SEG_THREADS) {
+        const uint64_t k = S.key[i];
+        lmin = k < lmin ? k : lmin;
+        lmax = k > lmax ? k : lmax;
+    }
+    const uint64_t kmin = block_min_u64<SEG_THREADS>(lmin, S.red);
+    const uint64_t kmax = block_max_u64<SEG_THREADS>(lmax, S.red);
+    if (m == 0) return;
+    for (int i = threadIdx.x; i < m; i += SEG_THREADS) S.key[i] -= kmin;
+    __syncthreads();
+    const int bits = kmax > kmin ? 64 - __clzll((unsigned long long)(kmax - kmin)) : 0;
+    lds_radix_sort<SEG_THREADS, SEG_ITEMS>(S.key, S.val, m, bits, S.cnt, S.scan32);
+    for (int i = threadIdx.x; i < m; i += SEG_THREADS) S.key[i] += kmin;
+    __syncthreads();
+}
 
 // Emit the sorted tile: merged runs (merge mode) or every element (sort mode)
 // to staging positions base + out .. ; returns the number written.
@@ -141,7 +166,7 @@ __device__ void seg_process(const SegArgs &A, SegShared &S)
                 S.val[i] = (uint32_t)i;
             }
             __syncthreads();
-            lds_sort_kv<SEG_THREADS>(S.key, S.val, (int)T);
+            sort_tile(S, (int)T);
             written = emit_tile<SORT_ONLY>(A, S, (int)T, base, 0);
         } else {
             uint64_t lmin = ~0ull, lmax = 0;
@@ -186,7 +211,7 @@ __device__ void seg_process(const SegArgs &A, SegShared &S)
                     }
                     const int m = (int)(got < SEG_CAP ? got : SEG_CAP);
                     __syncthreads();
-                    lds_sort_kv<SEG_THREADS>(S.key, S.val, m);
+                    sort_tile(S, m);
                     written += emit_tile<SORT_ONLY>(A, S, m, base, written);
                 } else if (lo == hi) {
                     // one key repeated more often than a tile holds
@@ -263,6 +288,15 @@ __global__ void __launch_bounds__(SEG_THREADS) k_seg_sort(SegArgs A)
 {
     __shared__ SegShared S;
     seg_process<true>(A, S);
+}
+
+// Two independent segment sets in one launch (both operands of a product);
+// the blocks split the machine between them.
+__global__ void __launch_bounds__(SEG_THREADS) k_seg_sort2(SegArgs A, SegArgs B)
+{
+    __shared__ SegShared S;
+    if (blockIdx.x & 1) seg_process<true>(B, S);
+    else seg_process<true>(A, S);
 }
 
 // Exclusive scan of S counts into out[0..S]; one block of 1024 threads.
