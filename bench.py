@@ -48,7 +48,10 @@ def parse():
     ap.add_argument("--eval-polys", type=int, default=4096)
     ap.add_argument("--nslices", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-terms", type=int, default=2500, help="q terms in the CPU baseline sample")
+    ap.add_argument("--cpu-terms", type=int, default=5000, help="q terms in the CPU baseline sample")
+    ap.add_argument("--no-batch", action="store_true", help="skip the polynomial-matrix workload")
+    ap.add_argument("--no-deriv", action="store_true", help="skip the quartic derivative workload")
+    ap.add_argument("--graph", action="store_true", help="also time the times+simplify step as a captured HIP graph")
     return ap.parse_args()
 
 
@@ -143,6 +146,76 @@ def bench_eval(args):
     return res
 
 
+def bench_batch(args):
+    """64x64 polynomial matrix, n=20: one persistent simplify launch, the
+    64x64x20 Jacobian, and its evaluation at 4,096 points."""
+    import torch
+    import paper_2604_06575_amd as ph
+    import workloads as W
+
+    wl = W.batch_matrix()
+    b = ph.batch_from_numpy(wl.row_ptr, wl.exps, wl.coefs, n=wl.n, max_exp=wl.max_exp)
+    X = torch.from_numpy(wl.X).cuda()
+    s = ph.simplify(b)
+    J = ph.jacobian(s)
+    t_simp, _ = time_events(lambda: ph.simplify(b, trim=False), 3, 1)
+    t_jac, _ = time_events(lambda: ph.jacobian(s, trim=False), 3, 1)
+    t_eval, _ = time_events(lambda: ph.eval(J, X), 2, 1)
+    t_grad, _ = time_events(lambda: ph.grad(s, X), 2, 1)
+    T_in, T_s, T_j = int(wl.row_ptr[-1]), s.nterms, J.nterms
+    term_points = T_j * X.shape[0]
+    return {"entries": 4096, "raw_terms": T_in, "simplified_terms": T_s, "jacobian_terms": T_j, "points": X.shape[0],
+            "simplify_ms": t_simp * 1e3, "simplify_terms_per_s": T_in / t_simp,
+            "jacobian_ms": t_jac * 1e3, "jacobian_terms_per_s": T_j / t_jac,
+            "jacobian_eval_ms": t_eval * 1e3, "jacobian_eval_term_points_per_s": term_points / t_eval,
+            "grad_fused_ms": t_grad * 1e3,
+            "note": "simplify/jacobian times include the host readback of the output row pointer"}
+
+
+def bench_deriv(args):
+    """Random quartic, n=100, 100,000 terms, 8,192 points: value, gradient
+    through the reverse-mode kernel (unit cotangent), Hessian."""
+    import torch
+    import paper_2604_06575_amd as ph
+    import workloads as W
+
+    wl = W.quartic()
+    b = ph.batch_from_numpy([0, wl.exps.shape[0]], wl.exps, wl.coefs, n=wl.n, max_exp=4)
+    X = torch.from_numpy(wl.X).cuda()
+    gY = torch.ones((1, X.shape[0]), dtype=torch.float64, device="cuda")
+    t_eval, _ = time_events(lambda: ph.eval(b, X), 3, 1)
+    t_bwd, _ = time_events(lambda: ph.eval_backward(b, X, gY), 2, 1)
+    t_hess, _ = time_events(lambda: ph.hess(b, X), 1, 1)
+    N = X.shape[0]
+    return {"terms": wl.exps.shape[0], "n": wl.n, "points": N,
+            "eval_ms": t_eval * 1e3, "backward_dx_dc_ms": t_bwd * 1e3, "hessian_ms": t_hess * 1e3,
+            "dtype": {"f": "f64", "grad": "f64", "hessian": "f64 (100x100 per point, both triangles)"}}
+
+
+def bench_graph(args, m):
+    """The times+simplify step captured once into a HIP graph and replayed."""
+    import torch
+    import paper_2604_06575_amd as ph
+    import workloads as W
+
+    wl = W.plain_large(terms=args.terms)
+    rp = [0, args.terms]
+    a = ph.batch_from_numpy(rp, wl.a_exps, wl.a_coefs, n=wl.n, max_exp=wl.max_exp)
+    b = ph.batch_from_numpy(rp, wl.b_exps, wl.b_coefs, n=wl.n, max_exp=wl.max_exp)
+    ws_bytes, raw = ph.mul_workspace(a, b)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    out = ph._empty_out(wl.n, 1, raw, 2 * wl.max_exp, "cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ph.mul(a, b, ws=ws, out=out, finish=False)   # warm-up outside capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        ph.mul(a, b, ws=ws, out=out, finish=False)
+    t, _ = time_events(g.replay, args.steps, 1)
+    return {"ms_per_step": t * 1e3, "merged_terms_per_s": raw / t}
+
+
 def cpu_baseline(args):
     import oracle
     import workloads as W
@@ -192,8 +265,14 @@ def main():
                      "algorithmic_bytes": BYTES_PER_RAW_TERM * m["raw"]},
         "wall_ms_per_step": m["t_wall"] * 1e3,
     }
+    if args.graph:
+        line["graph"] = bench_graph(args, m)
     if not args.no_eval:
         line["eval"] = bench_eval(args)
+    if not args.no_batch:
+        line["batch_matrix"] = bench_batch(args)
+    if not args.no_deriv:
+        line["quartic_derivatives"] = bench_deriv(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(line), flush=True)

@@ -100,6 +100,17 @@ const char *poly_strerror(int32_t status);
  * the workspace `ws` by the last call that used it (POLY_OK if none). */
 poly_status poly_read_status(const void *ws, void *stream);
 
+/* -------------------------------------------------------------- tunables
+ * Launch parameters chosen by the project's autotuner
+ * (paper_2604_06575_amd/autotune.py, cache in paper_2604_06575_amd/tuning/).
+ * Names: "mul_bucket_terms"  raw product terms per bucket workgroup (times)
+ *        "seg_blocks_per_cu" persistent workgroups per CU (simplify, sort)
+ *        "eval_blocks_per_cu" point-tile workgroups per CU (sparse eval)
+ * poly_tune_set returns POLY_ERR_ARG for an unknown name or a value outside
+ * the tunable's range; values are process-wide and apply to later calls. */
+poly_status poly_tune_set(const char *name, int64_t value);
+poly_status poly_tune_get(const char *name, int64_t *value);
+
 /* ---------------------------------------------------------------- simplify
  * out_p = simplify(in_p, zero_tol) for every p (Table "coresemantics").
  * Inputs may hold repeated monomials in any order.  All P entries are

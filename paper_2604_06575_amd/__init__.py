@@ -28,7 +28,7 @@ POLY_FP64 = 0
 POLY_SPLIT_BF16 = 1
 
 EXPORTS = [
-    "poly_strerror", "poly_read_status",
+    "poly_strerror", "poly_read_status", "poly_tune_set", "poly_tune_get",
     "poly_simplify_workspace", "poly_simplify",
     "poly_mul_workspace", "poly_mul",
     "poly_jacobian_workspace", "poly_jacobian",
@@ -82,6 +82,8 @@ def lib():
     sig = {
         "poly_strerror": ([i32], ctypes.c_char_p),
         "poly_read_status": ([P, P], i32),
+        "poly_tune_set": ([ctypes.c_char_p, i64], i32),
+        "poly_tune_get": ([ctypes.c_char_p, ctypes.POINTER(i64)], i32),
         "poly_simplify_workspace": ([pcsr, psz], i32),
         "poly_simplify": ([pcsr, pcsr, d, P, ctypes.c_size_t, P], i32),
         "poly_mul_workspace": ([pcsr, pcsr, psz, ctypes.POINTER(i64)], i32),
@@ -104,7 +106,34 @@ def lib():
         f.argtypes = args
         f.restype = res
     _lib = L
+    _load_tuning(L)
     return L
+
+
+TUNING_DIR = os.path.join(_HERE, "tuning")
+
+
+def _load_tuning(L):
+    """Apply the autotuner's cache (``tuning/<arch>.json`` or the file named
+    by POLYHIP_TUNE_FILE) to the library's launch parameters."""
+    import json
+    path = os.environ.get("POLYHIP_TUNE_FILE") or os.path.join(TUNING_DIR, "gfx950.json")
+    if not os.path.exists(path):
+        return
+    with open(path) as f:
+        data = json.load(f)
+    for name, value in data.get("tunables", {}).items():
+        _check(L.poly_tune_set(name.encode(), int(value)), f"poly_tune_set({name})")
+
+
+def tune_set(name: str, value: int):
+    _check(lib().poly_tune_set(name.encode(), int(value)), f"poly_tune_set({name})")
+
+
+def tune_get(name: str) -> int:
+    v = ctypes.c_int64()
+    _check(lib().poly_tune_get(name.encode(), ctypes.byref(v)), f"poly_tune_get({name})")
+    return int(v.value)
 
 
 def _check(code: int, where: str):
@@ -204,17 +233,30 @@ def _finish(out: Batch, ws: torch.Tensor, where: str, trim: bool) -> Batch:
 
 # ------------------------------------------------------------------ operations
 
-def simplify(b: Batch, tol: float = 0.0, trim: bool = True) -> Batch:
-    """simplify(p, zeroprec) for every entry of the batch."""
+def simplify_workspace(b: Batch) -> int:
+    ws_bytes = ctypes.c_size_t()
+    cin = b.csr()
+    _check(lib().poly_simplify_workspace(ctypes.byref(cin), ctypes.byref(ws_bytes)), "poly_simplify_workspace")
+    return int(ws_bytes.value)
+
+
+def simplify(b: Batch, tol: float = 0.0, trim: bool = True, ws: torch.Tensor | None = None,
+             out: Batch | None = None, finish: bool = True) -> Batch:
+    """simplify(p, zeroprec) for every entry of the batch.  With finish=False
+    nothing is read back (the call only enqueues kernels, e.g. under graph
+    capture); the output row pointer stays on the device."""
     L = lib()
     cin = b.csr()
-    ws_bytes = ctypes.c_size_t()
-    _check(L.poly_simplify_workspace(ctypes.byref(cin), ctypes.byref(ws_bytes)), "poly_simplify_workspace")
-    ws = _workspace(ws_bytes.value, b.coefs.device)
-    out = _empty_out(b.n, b.npolys, b.nterms, b.max_exp, b.coefs.device)
+    need = simplify_workspace(b)
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, b.coefs.device)
+    if out is None:
+        out = _empty_out(b.n, b.npolys, b.nterms, b.max_exp, b.coefs.device)
     cout = out.csr()
     _check(L.poly_simplify(ctypes.byref(cin), ctypes.byref(cout), float(tol), ctypes.c_void_p(ws.data_ptr()),
                            ws.numel(), _stream()), "poly_simplify")
+    if not finish:
+        return out
     return _finish(out, ws, "poly_simplify", trim)
 
 

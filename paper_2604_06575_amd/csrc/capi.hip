@@ -3,12 +3,39 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <vector>
 
 #include "kernels.h"
 
 using namespace polyhip;
+
+namespace polyhip {
+
+namespace {
+std::atomic<int64_t> g_mul_bucket_terms{MB_TARGET};
+std::atomic<int64_t> g_seg_blocks_per_cu{2};
+std::atomic<int64_t> g_eval_blocks_per_cu{8};
+
+struct TuneEntry {
+    const char *name;
+    std::atomic<int64_t> *value;
+    int64_t lo, hi;
+};
+const TuneEntry kTune[] = {
+    {"mul_bucket_terms", &g_mul_bucket_terms, 1024, 1 << 22},
+    {"seg_blocks_per_cu", &g_seg_blocks_per_cu, 1, 16},
+    {"eval_blocks_per_cu", &g_eval_blocks_per_cu, 1, 64},
+};
+}  // namespace
+
+Tunables tunables()
+{
+    return Tunables{g_mul_bucket_terms.load(), g_seg_blocks_per_cu.load(), g_eval_blocks_per_cu.load()};
+}
+
+}  // namespace polyhip
 
 namespace polyhip {
 poly_status dense_workspace(int32_t n, int64_t K, int64_t P, int64_t N, poly_prec prec, int32_t nslices,
@@ -138,6 +165,7 @@ poly_status plan_mul(const poly_csr *a, const poly_csr *b, MulPlan &m)
     int64_t raw = 0, nb = 0;
     size_t lds_max = 0;
     int64_t rows_max = 0, ns_max = 0;
+    bool codes_fit = true;   // (i << bits(|b|-1)) | j fits 32 bits for every pair
     for (int64_t p = 0; p < P; ++p) {
         const int64_t ta = a->row_ptr_host[p + 1] - a->row_ptr_host[p];
         const int64_t tb = b->row_ptr_host[p + 1] - b->row_ptr_host[p];
@@ -148,10 +176,12 @@ poly_status plan_mul(const poly_csr *a, const poly_csr *b, MulPlan &m)
         lds_max = std::max(lds_max, mb_lds_bytes(ns, nrows));
         rows_max = std::max(rows_max, nrows);
         ns_max = std::max(ns_max, ns);
+        auto bw = [](int64_t v) { return v > 0 ? 64 - __builtin_clzll((unsigned long long)v) : 0; };
+        if (bw(ta - 1) + bw(tb - 1) > 32) codes_fit = false;
     }
-    m.lds_mode = lds_max <= MB_LDS_LIMIT && rows_max <= MB_MAX_ROWS && ns_max <= MB_MAX_PARTNERS;
+    m.lds_mode = lds_max <= MB_LDS_LIMIT && rows_max <= MB_MAX_ROWS && ns_max <= MB_MAX_PARTNERS && codes_fit;
     m.lds_dyn = std::max<size_t>(lds_max, 16);
-    m.target = m.lds_mode ? MB_TARGET : MUL_TARGET;
+    m.target = m.lds_mode ? tunables().mul_bucket_terms : MUL_TARGET;
     for (int64_t p = 0; p < P; ++p) {
         const int64_t ta = a->row_ptr_host[p + 1] - a->row_ptr_host[p];
         const int64_t tb = b->row_ptr_host[p + 1] - b->row_ptr_host[p];
@@ -219,7 +249,7 @@ void launch_eval_blocks(const EvalArgs &A, const uint64_t *enc, hipStream_t s)
     const unsigned gx = (unsigned)ceil_div(A.N, kWave);
     // enough blocks to fill the machine several times over, each looping
     // over polynomials so that its point tile is loaded once.
-    int64_t want = std::max<int64_t>(1, ((int64_t)device_cus() * 8 + gx - 1) / gx);
+    int64_t want = std::max<int64_t>(1, ((int64_t)device_cus() * tunables().eval_blocks_per_cu + gx - 1) / gx);
     const unsigned gy = (unsigned)std::min<int64_t>(std::min<int64_t>(A.Q, want * 4), 65535);
     const size_t lds = (size_t)A.n * kWave * sizeof(double);
     hipLaunchKernelGGL(k_eval_blocks, dim3(gx, gy), dim3(EV_THREADS), lds, s, A, enc);
@@ -317,6 +347,31 @@ const char *poly_strerror(int32_t status)
     }
 }
 
+poly_status poly_tune_set(const char *name, int64_t value)
+{
+    if (!name) return POLY_ERR_ARG;
+    for (const TuneEntry &e : kTune) {
+        if (strcmp(e.name, name) == 0) {
+            if (value < e.lo || value > e.hi) return POLY_ERR_ARG;
+            e.value->store(value);
+            return POLY_OK;
+        }
+    }
+    return POLY_ERR_ARG;
+}
+
+poly_status poly_tune_get(const char *name, int64_t *value)
+{
+    if (!name || !value) return POLY_ERR_ARG;
+    for (const TuneEntry &e : kTune) {
+        if (strcmp(e.name, name) == 0) {
+            *value = e.value->load();
+            return POLY_OK;
+        }
+    }
+    return POLY_ERR_ARG;
+}
+
 poly_status poly_read_status(const void *ws, void *stream)
 {
     if (!ws) return POLY_ERR_ARG;
@@ -380,7 +435,7 @@ poly_status poly_simplify(const poly_csr *in, poly_csr *out, double zero_tol, vo
     A.st_idx = nullptr;
     A.seg_count = at<int64_t>(ws, pl.seg_count);
     A.tol = zero_tol;
-    const int64_t grid = std::min<int64_t>(P, (int64_t)device_cus() * 3);
+    const int64_t grid = std::min<int64_t>(P, (int64_t)device_cus() * tunables().seg_blocks_per_cu);
     hipLaunchKernelGGL(k_seg_merge, dim3((unsigned)grid), dim3(SEG_THREADS), 0, s, A);
     hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, A.seg_count, P, out->row_ptr);
     hipLaunchKernelGGL(k_compact, dim3((unsigned)P), dim3(256), 0, s, in->row_ptr, A.seg_count, out->row_ptr,
@@ -471,7 +526,7 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
                                     at<int64_t>(ws, m.order_a), queues + 0, s);
     const SegArgs sb = presort_args(b, (uint64_t *)A.kb, (uint64_t *)A.kb_s, (uint32_t *)A.perm_b, cnt_tmp,
                                     at<int64_t>(ws, m.order_b), queues + 1, s);
-    const int64_t pgrid = std::min<int64_t>(P, (int64_t)device_cus() * 2);
+    const int64_t pgrid = std::min<int64_t>(P, (int64_t)device_cus() * tunables().seg_blocks_per_cu);
     hipLaunchKernelGGL(k_seg_sort2, dim3((unsigned)(2 * pgrid)), dim3(SEG_THREADS), 0, s, sa, sb);
     int64_t *pb_count = at<int64_t>(ws, m.pb_count);
     hipLaunchKernelGGL(k_mul_plan, dim3(grid1(P, 256)), dim3(256), 0, s, a->row_ptr, b->row_ptr, P, pb_count,

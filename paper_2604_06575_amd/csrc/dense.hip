@@ -110,28 +110,30 @@ __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, con
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
+    // load roles: C tile row/k of this thread, V tile point/k of this thread
+    const int crow = tid >> 2, ckk = (tid & 3) * 4;
+    const int64_t cr = r0 + crow;
+    const int vcol = tid & (D64_BN - 1), vkb = (tid >> 7) * 8;
+    double creg[4], vreg[8];
     __syncthreads();
-    for (int64_t k0 = 0; k0 < K; k0 += D64_KS) {
-        // C tile: 64 rows x 16 k, 4 per thread
-        {
-            const int row = tid >> 2, kk = (tid & 3) * 4;
-            const int64_t r = r0 + row;
+    // stage 0 operands
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t k = k0 + kk + q;
-                s_c[row][kk + q] = (r < P && k < K) ? C[r * K + k] : 0.0;
-            }
-        }
-        // V tile: 16 k x 128 points, 8 per thread
-        {
-            const int c = tid & (D64_BN - 1), kb = (tid >> 7) * 8;
-#pragma unroll 2
-            for (int q = 0; q < 8; ++q) {
-                const int64_t k = k0 + kb + q;
-                s_v[kb + q][c] = k < K ? basis_value(enc, basis, n, k, s_x + c, D64_BN) : 0.0;
-            }
-        }
+    for (int q = 0; q < 4; ++q) creg[q] = (cr < P && ckk + q < K) ? C[cr * K + ckk + q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) vreg[q] = vkb + q < K ? basis_value(enc, basis, n, vkb + q, s_x + vcol, D64_BN) : 0.0;
+    for (int64_t k0 = 0; k0 < K; k0 += D64_KS) {
         __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s_c[crow][ckk + q] = creg[q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s_v[vkb + q][vcol] = vreg[q];
+        __syncthreads();
+        const int64_t k1 = k0 + D64_KS;
+        // next stage's C tile: loads in flight while the MFMAs run
+        if (k1 < K) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) creg[q] = (cr < P && k1 + ckk + q < K) ? C[cr * K + k1 + ckk + q] : 0.0;
+        }
 #pragma unroll
         for (int k4 = 0; k4 < D64_KS; k4 += 4) {
             double a[2], b[4];
@@ -145,7 +147,12 @@ __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, con
                 for (int ct = 0; ct < 4; ++ct)
                     acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b[ct], acc[rt][ct], 0, 0, 0);
         }
-        __syncthreads();
+        // next stage's V tile (VALU work beside the MFMAs)
+        if (k1 < K) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                vreg[q] = k1 + vkb + q < K ? basis_value(enc, basis, n, k1 + vkb + q, s_x + vcol, D64_BN) : 0.0;
+        }
     }
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
@@ -163,55 +170,78 @@ __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, con
 
 // ------------------------------------------------------------ split kernels
 
-// Row scales of C per K-block and the BF16 digit planes of C with their
-// scale folded in: Cs[s][r][k] (k fastest).  One thread per (row, K-block).
-__global__ void k_split_c(const double *C, int64_t P, int64_t K, int S, unsigned short *Cs)
+// BF16 digit planes of C with their scale folded in: Cs[s][r][k] over a
+// K stride Kp (multiple of SP_KS, zero padded).  One block per (row, K-block):
+// thread k of the block owns column k0 + k.
+__global__ void __launch_bounds__(DN_KB) k_split_c(const double *C, int64_t P, int64_t K, int64_t Kp, int S,
+                                                   unsigned short *Cs)
 {
-    const int64_t nkb = ceil_div(K, DN_KB);
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= P * nkb) return;
-    const int64_t r = id / nkb, kb = id % nkb;
-    const int64_t k0 = kb * DN_KB;
-    const int64_t k1 = std::min<int64_t>(K, k0 + DN_KB);
-    double amax = 0.0;
-    for (int64_t k = k0; k < k1; ++k) amax = fmax(amax, fabs(C[r * K + k]));
+    __shared__ double s_red[DN_KB / kWave];
+    const int64_t nkb = ceil_div(Kp, DN_KB);
+    const int64_t r = blockIdx.x / nkb, kb = blockIdx.x % nkb;
+    const int64_t k = kb * DN_KB + threadIdx.x;
+    const double x = k < K ? C[r * K + k] : 0.0;
+    double a = fabs(x);
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) a = fmax(a, __shfl_xor(a, o, kWave));
+    if (lane_id() == 0) s_red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    double amax = s_red[0];
+#pragma unroll
+    for (int i = 1; i < DN_KB / kWave; ++i) amax = fmax(amax, s_red[i]);
+    if (k >= Kp) return;
     const int sig = scale_exp(amax);
-    for (int64_t k = k0; k < k1; ++k) {
-        double y = amax > 0.0 ? ldexp(C[r * K + k], -sig) : 0.0;
-        for (int s = 1; s <= S; ++s) {
-            y = y * 256.0;
-            const double m = rint(y);
-            y = y - m;
-            const float f = ldexpf((float)m, sig - 8 * s);
-            Cs[((int64_t)(s - 1) * P + r) * K + k] = bf16_bits_exact(f);
-        }
+    double y = amax > 0.0 ? ldexp(x, -sig) : 0.0;
+    for (int s = 1; s <= S; ++s) {
+        y = y * 256.0;
+        const double m = rint(y);
+        y = y - m;
+        Cs[((int64_t)(s - 1) * P + r) * Kp + k] = bf16_bits_exact(ldexpf((float)m, sig - 8 * s));
     }
 }
 
-// Column scales of V per K-block: sig_v[kb * N + pt].  One thread per
-// (K-block, point).
-__global__ void k_split_vscale(int n, int64_t K, const uint8_t *basis, const uint64_t *enc, int64_t N,
-                               const double *X, int32_t *sig_v)
+// Column scales of V per K-block: sig_v[kb * N + pt].  One block per
+// (K-block, 64 points); thread (point, group) scans 32 monomials.
+__global__ void __launch_bounds__(256) k_split_vscale(int n, int64_t K, const uint8_t *basis, const uint64_t *enc,
+                                                      int64_t N, const double *X, int32_t *sig_v)
 {
-    const int64_t nkb = ceil_div(K, DN_KB);
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= nkb * N) return;
-    const int64_t kb = id / N, pt = id % N;
-    const int64_t k0 = kb * DN_KB;
-    const int64_t k1 = std::min<int64_t>(K, k0 + DN_KB);
+    extern __shared__ double s_xv[];               // [n][64]
+    __shared__ double s_m[4][64];
+    const int64_t ntile = ceil_div(N, 64);
+    const int64_t kb = blockIdx.x / ntile, pt0 = (blockIdx.x % ntile) * 64;
+    for (int idx = threadIdx.x; idx < n * 64; idx += 256) {
+        const int i = idx / 64, c = idx % 64;
+        s_xv[idx] = pt0 + c < N ? X[(pt0 + c) * n + i] : 0.0;
+    }
+    __syncthreads();
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
     double amax = 0.0;
-    for (int64_t k = k0; k < k1; ++k) amax = fmax(amax, fabs(basis_value(enc, basis, n, k, X + pt * n, 1)));
-    sig_v[id] = scale_exp(amax);
+    for (int q = 0; q < DN_KB / 4; ++q) {
+        const int64_t k = kb * DN_KB + g * (DN_KB / 4) + q;
+        if (k < K) amax = fmax(amax, fabs(basis_value(enc, basis, n, k, s_xv + c, 64)));
+    }
+    s_m[g][c] = amax;
+    __syncthreads();
+    if (g == 0 && pt0 + c < N)
+        sig_v[kb * N + pt0 + c] = scale_exp(fmax(fmax(s_m[0][c], s_m[1][c]), fmax(s_m[2][c], s_m[3][c])));
 }
 
-constexpr int SP_BM = 128, SP_BN = 64, SP_KS = 32, SP_THREADS = 512;
+constexpr int SP_BM = 128, SP_BN = 128, SP_KS = 32, SP_THREADS = 512;
 constexpr int SP_LDK = SP_KS + 8;    // padded k stride (bf16 elements) of the LDS digit planes
 
+__device__ inline uint32_t pack_bf16x2(float lo, float hi)
+{
+    return (__float_as_uint(lo) >> 16) | (__float_as_uint(hi) & 0xffff0000u);
+}
+
 // grid: x = N tiles, y = P tiles.  Waves: 4 row tiles of 32 x 2 column
-// tiles of 32 (one 32 x 32 MFMA tile each).  Dynamic LDS: points [n][SP_BN]
-// doubles, then C digits [S][SP_BM][SP_LDK] and V digits [S][SP_BN][SP_LDK].
+// halves of 64 (two 32 x 32 MFMA tiles each).  Three FP32 accumulator groups
+// per tile: diagonal 2 and diagonal 3 are exact integer sums; diagonals >= 4
+// (at most 2^-16 of the leading term) share one FP32 accumulator, whose
+// rounding stays near 2^-40 of the result.  Dynamic LDS: points [n][SP_BN]
+// doubles, C digits [S][SP_BM][SP_LDK], V digits [S][SP_BN][SP_LDK] (bf16).
 template <int S>
-__global__ void __launch_bounds__(SP_THREADS) k_dense_split(int n, int64_t K, const uint8_t *basis,
+__global__ void __launch_bounds__(SP_THREADS) k_dense_split(int n, int64_t K, int64_t Kp, const uint8_t *basis,
                                                             const uint64_t *enc, int64_t P,
                                                             const unsigned short *Cs, int64_t N, const double *X,
                                                             const int32_t *sig_v, double *Y)
@@ -231,92 +261,130 @@ __global__ void __launch_bounds__(SP_THREADS) k_dense_split(int n, int64_t K, co
         const int64_t pt = n0 + c;
         s_x[idx] = pt < N ? X[pt * n + i] : 0.0;
     }
-    // FP64 accumulators for the wave's 32 x 32 tile, FP32 per diagonal
-    double out[16];
-    f16v acc[S];
+    double out[2][16];
+    f16v acc[3][2];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) out[v] = 0.0;
+    for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-    for (int d = 0; d < S; ++d)
+        for (int v = 0; v < 16; ++v) out[ct][v] = 0.0;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) acc[d][v] = 0.0f;
-    __syncthreads();
-    for (int64_t k0 = 0; k0 < K; k0 += SP_KS) {
-        // C digit planes: S x 128 rows x 32 k; 16 bf16 per (slice,row) => 4 x 8-byte loads
-        for (int idx = tid; idx < S * SP_BM * (SP_KS / 4); idx += SP_THREADS) {
-            const int s = idx / (SP_BM * (SP_KS / 4));
-            const int rem = idx % (SP_BM * (SP_KS / 4));
-            const int row = rem / (SP_KS / 4), kq = (rem % (SP_KS / 4)) * 4;
+    for (int g = 0; g < 3; ++g)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[g][ct][v] = 0.0f;
+    // V generation role of this thread: one point, 8 consecutive k
+    const int vc = tid & (SP_BN - 1);
+    const int vkq = (tid >> 7) * 8;
+    const int64_t vpt = n0 + vc;
+    uint4 creg[(S * SP_BM * (SP_KS / 8)) / SP_THREADS];
+    uint32_t dig[S][4];
+    auto load_c = [&](int64_t kk) {
+#pragma unroll
+        for (int j = 0; j < (S * SP_BM * (SP_KS / 8)) / SP_THREADS; ++j) {
+            const int idx = tid + j * SP_THREADS;
+            const int sl = idx / (SP_BM * (SP_KS / 8));
+            const int rem = idx % (SP_BM * (SP_KS / 8));
+            const int row = rem / (SP_KS / 8), part = rem % (SP_KS / 8);
             const int64_t r = r0 + row;
-            unsigned short v4[4] = {0, 0, 0, 0};
-            if (r < P) {
-                const unsigned short *src = Cs + ((int64_t)s * P + r) * K + k0 + kq;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) v4[q] = (k0 + kq + q < K) ? src[q] : (unsigned short)0;
-            }
-            unsigned short *dst = s_cd + (s * SP_BM + row) * SP_LDK + kq;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) dst[q] = v4[q];
+            creg[j] = r < P ? *(const uint4 *)(Cs + ((int64_t)sl * P + r) * Kp + kk + part * 8)
+                            : make_uint4(0, 0, 0, 0);
         }
-        // V digit planes: 32 k x 64 points -> 4 values per thread
-        {
-            const int c = tid & (SP_BN - 1);
-            const int kq = (tid >> 6) * 4;
-            const int64_t pt = n0 + c;
-            const int64_t kb = k0 / DN_KB;
-            const int sig = pt < N ? sig_v[kb * N + pt] : 0;
-#pragma unroll 2
-            for (int q = 0; q < 4; ++q) {
-                const int64_t k = k0 + kq + q;
-                double y = 0.0;
-                if (k < K && pt < N && sig > -1100) y = ldexp(basis_value(enc, basis, n, k, s_x + c, SP_BN), -sig);
+    };
+    auto gen_v = [&](int64_t kk) {
+        const int64_t kb = kk / DN_KB;
+        const int sig = vpt < N ? sig_v[kb * N + vpt] : -1100;
+        const bool live = vpt < N && sig > -1100;
+        float scale[S];
 #pragma unroll
-                for (int t = 1; t <= S; ++t) {
-                    y = y * 256.0;
-                    const double m = rint(y);
-                    y = y - m;
-                    s_vd[((t - 1) * SP_BN + c) * SP_LDK + kq + q] = bf16_bits_exact(ldexpf((float)m, sig - 8 * t));
-                }
+        for (int t = 0; t < S; ++t) scale[t] = live ? ldexpf(1.0f, sig - 8 * (t + 1)) : 0.0f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t k = kk + vkq + q;
+            double y = 0.0;
+            if (live && k < K) y = ldexp(basis_value(enc, basis, n, k, s_x + vc, SP_BN), -sig);
+            // y = yh + yl to 48 bits; digits extracted in FP32
+            const float yh = (float)y;
+            const float yl = (float)(y - (double)yh);
+            float t = yh;
+            float m[S];
+#pragma unroll
+            for (int d = 0; d < S; ++d) {
+                if (d == 3) t = t + yl * 16777216.0f;   // yl in the frame of digit 4
+                t = t * 256.0f;
+                m[d] = rintf(t);
+                t = t - m[d];
+            }
+#pragma unroll
+            for (int d = 0; d < S; ++d) {
+                const float f = m[d] * scale[d];
+                if (q & 1) dig[d][q >> 1] = (dig[d][q >> 1] & 0xffffu) | (__float_as_uint(f) & 0xffff0000u);
+                else dig[d][q >> 1] = __float_as_uint(f) >> 16;
             }
         }
+#pragma unroll
+        for (int d = 0; d < S; ++d)
+            *(uint4 *)(s_vd + (d * SP_BN + vc) * SP_LDK + vkq) = make_uint4(dig[d][0], dig[d][1], dig[d][2], dig[d][3]);
+    };
+    __syncthreads();
+    load_c(0);
+    for (int64_t k0 = 0; k0 < Kp; k0 += SP_KS) {
         __syncthreads();
 #pragma unroll
+        for (int j = 0; j < (S * SP_BM * (SP_KS / 8)) / SP_THREADS; ++j) {
+            const int idx = tid + j * SP_THREADS;
+            const int sl = idx / (SP_BM * (SP_KS / 8));
+            const int rem = idx % (SP_BM * (SP_KS / 8));
+            const int row = rem / (SP_KS / 8), part = rem % (SP_KS / 8);
+            *(uint4 *)(s_cd + (sl * SP_BM + row) * SP_LDK + part * 8) = creg[j];
+        }
+        gen_v(k0);
+        __syncthreads();
+        const int64_t k1 = k0 + SP_KS;
+        if (k1 < Kp) load_c(k1);
+#pragma unroll
         for (int ks = 0; ks < SP_KS; ks += 16) {
-            s8v a[S], b[S];
+            s8v a[S];
 #pragma unroll
             for (int s = 0; s < S; ++s)
                 a[s] = *(const s8v *)(s_cd + (s * SP_BM + wr * 32 + (lane & 31)) * SP_LDK + ks + 8 * (lane >> 5));
 #pragma unroll
-            for (int t = 0; t < S; ++t)
-                b[t] = *(const s8v *)(s_vd + (t * SP_BN + wc * 32 + (lane & 31)) * SP_LDK + ks + 8 * (lane >> 5));
+            for (int t = 0; t < S; ++t) {
+                s8v b[2];
 #pragma unroll
-            for (int s = 0; s < S; ++s)
+                for (int ct = 0; ct < 2; ++ct)
+                    b[ct] = *(const s8v *)(s_vd + (t * SP_BN + wc * 64 + ct * 32 + (lane & 31)) * SP_LDK + ks +
+                                           8 * (lane >> 5));
 #pragma unroll
-                for (int t = 0; t < S - s; ++t)
-                    acc[s + t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                        __builtin_bit_cast(bf8v, a[s]), __builtin_bit_cast(bf8v, b[t]), acc[s + t], 0, 0, 0);
-        }
-        __syncthreads();
-        // drain every K-block (or at the end)
-        if (((k0 + SP_KS) % DN_KB) == 0 || k0 + SP_KS >= K) {
+                for (int s = 0; s < S - t; ++s) {
+                    const int g = (s + t) < 2 ? (s + t) : 2;
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                double t = 0.0;
-#pragma unroll
-                for (int d = S - 1; d >= 0; --d) {
-                    t += (double)acc[d][v];
-                    acc[d][v] = 0.0f;
+                    for (int ct = 0; ct < 2; ++ct)
+                        acc[g][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(bf8v, a[s]), __builtin_bit_cast(bf8v, b[ct]), acc[g][ct], 0, 0, 0);
                 }
-                out[v] += t;
             }
         }
+        if (((k0 + SP_KS) % DN_KB) == 0 || k0 + SP_KS >= Kp) {
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    out[ct][v] += ((double)acc[2][ct][v] + (double)acc[1][ct][v]) + (double)acc[0][ct][v];
+                    acc[0][ct][v] = 0.0f;
+                    acc[1][ct][v] = 0.0f;
+                    acc[2][ct][v] = 0.0f;
+                }
+        }
     }
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int64_t r = r0 + wr * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const int64_t c = n0 + wc * 32 + (lane & 31);
-        if (r < P && c < N) Y[r * N + c] = out[v];
-    }
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int64_t r = r0 + wr * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            const int64_t c = n0 + wc * 64 + ct * 32 + (lane & 31);
+            if (r < P && c < N) Y[r * N + c] = out[ct][v];
+        }
 }
 
 // ---------------------------------------------------------------- host side
@@ -340,16 +408,17 @@ DensePlan plan_dense(int32_t n, int64_t K, int64_t P, int64_t N, poly_prec prec,
     d.cs = 0;
     d.sigv = 0;
     if (prec == POLY_SPLIT_BF16) {
-        d.cs = take((size_t)S * P * K * 2);
-        d.sigv = take((size_t)ceil_div(K, DN_KB) * N * 4);
+        const int64_t Kp = align_up((size_t)K, 32);
+        d.cs = take((size_t)S * P * Kp * 2);
+        d.sigv = take((size_t)ceil_div(Kp, DN_KB) * N * 4);
     }
     d.total = align_up(off, 256);
     return d;
 }
 
 template <int S>
-void launch_split(int n, int64_t K, const uint8_t *basis, const uint64_t *enc, int64_t P, const unsigned short *Cs,
-                  int64_t N, const double *X, const int32_t *sig_v, double *Y, hipStream_t s)
+void launch_split(int n, int64_t K, int64_t Kp, const uint8_t *basis, const uint64_t *enc, int64_t P,
+                  const unsigned short *Cs, int64_t N, const double *X, const int32_t *sig_v, double *Y, hipStream_t s)
 {
     const size_t lds = (size_t)n * SP_BN * 8 + (size_t)S * (SP_BM + SP_BN) * SP_LDK * 2;
     static bool attr = false;
@@ -358,7 +427,8 @@ void launch_split(int n, int64_t K, const uint8_t *basis, const uint64_t *enc, i
         attr = true;
     }
     const dim3 grid((unsigned)ceil_div(N, SP_BN), (unsigned)ceil_div(P, SP_BM));
-    hipLaunchKernelGGL(k_dense_split<S>, grid, dim3(SP_THREADS), lds, s, n, K, basis, enc, P, Cs, N, X, sig_v, Y);
+    hipLaunchKernelGGL(k_dense_split<S>, grid, dim3(SP_THREADS), lds, s, n, K, Kp, basis, enc, P, Cs, N, X, sig_v,
+                       Y);
 }
 
 }  // namespace
@@ -403,17 +473,18 @@ poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_ex
     } else {
         unsigned short *Cs = (unsigned short *)((char *)ws + d.cs);
         int32_t *sig_v = (int32_t *)((char *)ws + d.sigv);
-        const int64_t nkb = ceil_div(K, DN_KB);
+        const int64_t Kp = align_up((size_t)K, 32);
+        const int64_t nkb = ceil_div(Kp, DN_KB);
         if (K > 0) {
-            hipLaunchKernelGGL(k_split_c, dim3((unsigned)ceil_div(P * nkb, 256)), dim3(256), 0, s, C, P, K, S, Cs);
-            hipLaunchKernelGGL(k_split_vscale, dim3((unsigned)ceil_div(nkb * N, 256)), dim3(256), 0, s, n, K, basis,
-                               enc, N, X, sig_v);
+            hipLaunchKernelGGL(k_split_c, dim3((unsigned)(P * nkb)), dim3(DN_KB), 0, s, C, P, K, Kp, S, Cs);
+            hipLaunchKernelGGL(k_split_vscale, dim3((unsigned)(nkb * ceil_div(N, 64))), dim3(256),
+                               (size_t)n * 64 * 8, s, n, K, basis, enc, N, X, sig_v);
         }
         switch (S) {
-        case 3: launch_split<3>(n, K, basis, enc, P, Cs, N, X, sig_v, Y, s); break;
-        case 4: launch_split<4>(n, K, basis, enc, P, Cs, N, X, sig_v, Y, s); break;
-        case 5: launch_split<5>(n, K, basis, enc, P, Cs, N, X, sig_v, Y, s); break;
-        default: launch_split<6>(n, K, basis, enc, P, Cs, N, X, sig_v, Y, s); break;
+        case 3: launch_split<3>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, s); break;
+        case 4: launch_split<4>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, s); break;
+        case 5: launch_split<5>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, s); break;
+        default: launch_split<6>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, s); break;
         }
     }
     return hipGetLastError() == hipSuccess ? POLY_OK : POLY_ERR_HIP;

@@ -5,6 +5,14 @@
 
 namespace polyhip {
 
+// Launch parameters set by the autotuner (process-wide; see poly_tune_set).
+struct Tunables {
+    int64_t mul_bucket_terms;
+    int64_t seg_blocks_per_cu;
+    int64_t eval_blocks_per_cu;
+};
+Tunables tunables();
+
 // ------------------------------------------------------------ simplify / sort
 constexpr int SEG_THREADS = 512;
 constexpr int SEG_ITEMS = 8;

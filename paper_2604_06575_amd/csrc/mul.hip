@@ -454,9 +454,12 @@ __global__ void __launch_bounds__(MB_THREADS) k_mul_buckets_lds(MulArgs A)
     const uint32_t *perm = swapped ? A.perm_a + a0 : A.perm_b + bb;
     const double *ca = A.a_c + a0;
     const double *cb = A.b_c + bb;
-    const uint32_t utb = (uint32_t)tb;
-    // ij needs ij_bits bits; in the swapped case it is sorted below the key
-    const int ij_bits = swapped ? 64 - __clzll((unsigned long long)(ta * tb - 1) | 1ull) : 0;
+    // term pair (i, j) encoded as (i << jbits) | j, so ascending codes are
+    // ascending (i, j); in the swapped case the code is sorted below the key
+    const int jbits = tb > 1 ? 64 - __clzll((unsigned long long)(tb - 1)) : 0;
+    const int ibits = ta > 1 ? 64 - __clzll((unsigned long long)(ta - 1)) : 0;
+    const uint32_t jmask = (uint32_t)((1ull << jbits) - 1ull);
+    const int ij_bits = swapped ? ibits + jbits : 0;
 
     uint64_t *s_srt = s_dyn;                                   // [ns]
     uint64_t *s_rows = s_dyn + ns;                             // [nrows]
@@ -539,7 +542,7 @@ __global__ void __launch_bounds__(MB_THREADS) k_mul_buckets_lds(MulArgs A)
                     for (uint32_t t = c0; t < c0 + cr[q]; ++t, ++pos) {
                         const uint64_t rel = kr + s_srt[t] - lo;
                         const uint32_t o = perm[t];
-                        const uint32_t ij = swapped ? o * utb + r : r * utb + o;
+                        const uint32_t ij = swapped ? ((o << jbits) | r) : ((r << jbits) | o);
                         kmax = rel > kmax ? rel : kmax;
                         if (pos < MB_CAP) {
                             S.key[pos] = swapped ? ((rel << ij_bits) | ij) : rel;
@@ -566,10 +569,10 @@ __global__ void __launch_bounds__(MB_THREADS) k_mul_buckets_lds(MulArgs A)
                     const uint64_t k = S.key[e] >> ij_bits;
                     if (e == 0 || (S.key[e - 1] >> ij_bits) != k) {
                         uint32_t v = S.val[e];
-                        double s = ca[v / utb] * cb[v % utb];
+                        double s = ca[v >> jbits] * cb[v & jmask];
                         for (int f = e + 1; f < m && (S.key[f] >> ij_bits) == k; ++f) {
                             v = S.val[f];
-                            s = s + ca[v / utb] * cb[v % utb];
+                            s = s + ca[v >> jbits] * cb[v & jmask];
                         }
                         sums[q] = s;
                         if (!(fabs(s) <= A.tol)) {

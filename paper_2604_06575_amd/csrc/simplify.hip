@@ -315,7 +315,11 @@ __global__ void __launch_bounds__(1024) k_scan_counts(const int64_t *counts, int
     if (threadIdx.x == 0) out[S] = run;
 }
 
-// One block per segment: staged (key, coef) -> CSR output rows.
+// One block per segment: staged (key, coef) -> CSR output rows.  A segment's
+// output rows are contiguous, so its exponent bytes form one contiguous
+// range; the block writes that range as aligned 32-bit words (each byte
+// unpacked from its row's key), with the unaligned head and tail bytes
+// written singly, so neighbouring segments never share a store.
 __global__ void __launch_bounds__(256) k_compact(const int64_t *stage_off, const int64_t *seg_count,
                                                  const int64_t *out_off, const uint64_t *st_key,
                                                  const double *st_coef, int n, int bits, uint8_t *out_exps,
@@ -326,14 +330,41 @@ __global__ void __launch_bounds__(256) k_compact(const int64_t *stage_off, const
     const int64_t src = stage_off[s];
     const int64_t dst = out_off[s];
     if (threadIdx.x == 0 && dst + cnt > capacity) set_status(status, POLY_ERR_CAPACITY);
+    const int64_t end = dst + cnt < capacity ? dst + cnt : capacity;
+    if (end <= dst) return;
+    for (int64_t i = dst + threadIdx.x; i < end; i += blockDim.x) out_coefs[i] = st_coef[src + (i - dst)];
     const uint64_t mask = (bits >= 64) ? ~0ull : ((1ull << bits) - 1ull);
-    for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-        const int64_t d = dst + i;
-        if (d >= capacity) break;
-        const uint64_t k = st_key[src + i];
-        uint8_t *row = out_exps + d * n;
-        for (int v = 0; v < n; ++v) row[v] = (uint8_t)((k >> (bits * (n - 1 - v))) & mask);
-        out_coefs[d] = st_coef[src + i];
+    const int64_t b0 = dst * n, b1 = end * n;
+    int64_t w0 = (b0 + 3) & ~(int64_t)3, w1 = b1 & ~(int64_t)3;
+    if (w0 > b1) w0 = b1;
+    if (w1 < w0) w1 = w0;
+    auto byte_at = [&](int64_t bi) -> uint32_t {
+        const int64_t row = bi / n;
+        const int f = (int)(bi - row * n);
+        const uint64_t k = st_key[src + (row - dst)];
+        return (uint32_t)((k >> (bits * (n - 1 - f))) & mask);
+    };
+    // unaligned head and tail bytes
+    for (int64_t bi = b0 + threadIdx.x; bi < w0; bi += blockDim.x) out_exps[bi] = (uint8_t)byte_at(bi);
+    for (int64_t bi = w1 + threadIdx.x; bi < b1; bi += blockDim.x) out_exps[bi] = (uint8_t)byte_at(bi);
+    uint32_t *words = (uint32_t *)out_exps;
+    for (int64_t w = w0 / 4 + threadIdx.x; w < w1 / 4; w += blockDim.x) {
+        const int64_t bi = w * 4;
+        int64_t row = bi / n;
+        int f = (int)(bi - row * n);
+        uint64_t k = st_key[src + (row - dst)];
+        uint32_t v = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (f == n) {
+                f = 0;
+                ++row;
+                k = st_key[src + (row - dst)];
+            }
+            v |= (uint32_t)((k >> (bits * (n - 1 - f))) & mask) << (8 * q);
+            ++f;
+        }
+        words[w] = v;
     }
 }
 

@@ -22,7 +22,7 @@ def test_library_exports_every_declared_symbol():
         pytest.skip("library not built")
     L = ctypes.CDLL(ph.library_path())
     syms = header_symbols()
-    assert len(syms) == 18
+    assert len(syms) == 20
     for s in syms:
         assert hasattr(L, s), s
     assert sorted(ph.EXPORTS) == syms
@@ -62,6 +62,20 @@ def test_strerror_and_host_argument_checks():
     # dense workspace sizes
     assert L.poly_eval_dense_workspace(30, 1000, 10, 10, 1, 9, ctypes.byref(size)) == 1   # nslices out of range
     assert L.poly_eval_dense_workspace(30, 1000, 10, 10, 1, 5, ctypes.byref(size)) == 0
+
+
+def test_tunables_roundtrip():
+    import paper_2604_06575_amd as ph
+    if not os.path.exists(ph.library_path()):
+        pytest.skip("library not built")
+    old = ph.tune_get("mul_bucket_terms")
+    ph.tune_set("mul_bucket_terms", 8192)
+    assert ph.tune_get("mul_bucket_terms") == 8192
+    ph.tune_set("mul_bucket_terms", old)
+    with pytest.raises(ph.PolyError):
+        ph.tune_set("no_such_knob", 1)
+    with pytest.raises(ph.PolyError):
+        ph.tune_set("seg_blocks_per_cu", 0)
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
