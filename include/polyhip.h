@@ -184,11 +184,14 @@ poly_status poly_eval_backward(const poly_csr *f, const double *X, int64_t N,
  * built on the fly from per-point power tables.
  *   prec = POLY_FP64:       V and the products in FP64 (FP64 MFMA).
  *   prec = POLY_SPLIT_BF16: C and V are split into `nslices` BF16 slices
- *       with a power-of-two scale per (row, K-block) and (point, K-block);
- *       slice products are accumulated exactly in FP32 by BF16 MFMA within
- *       each K-block and recombined in FP64.  nslices in [2, 8]; pairs with
- *       s + t > nslices + 1 are skipped.
- * Error of the split result relative to sum_k |C v| is about 2^-(8*nslices - 10). */
+ *       with a power-of-two scale per (row, K-block of 128) and (point,
+ *       K-block); slice products of diagonals s + t = 2 and 3 are summed
+ *       exactly in FP32 by BF16 MFMA within each K-block, diagonals >= 4
+ *       share one FP32 accumulator, and each K-block is recombined in FP64.
+ *       nslices in [3, 6]; pairs with s + t > nslices + 1 are skipped.
+ * Error of the split result relative to sum_k |C v| is about
+ * max(2^-(8*nslices - 10), 2^-34): digit truncation, or the FP32 rounding of
+ * the accumulator shared by digit diagonals s + t >= 4. */
 poly_status poly_eval_dense_workspace(int32_t n, int64_t K, int64_t P, int64_t N,
                                       poly_prec prec, int32_t nslices, size_t *ws_bytes);
 poly_status poly_eval_dense(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp,

@@ -227,6 +227,12 @@ __global__ void __launch_bounds__(256) k_split_vscale(int n, int64_t K, const ui
 }
 
 constexpr int SP_BM = 128, SP_BN = 128, SP_KS = 32, SP_THREADS = 512;
+// FP32 accumulator groups per tile: diagonals 2 and 3 (exact integer sums on
+// their own scale) and one shared group for diagonals >= 4 (at most 2^-16 of
+// the leading term), whose FP32 rounding sets an error floor near 2^-34 of
+// sum |C v| per K-block whatever the digit count; a fourth exact group would
+// lower it but does not fit the register budget of this tile shape.
+constexpr int SP_GROUPS = 3;
 constexpr int SP_LDK = SP_KS + 8;    // padded k stride (bf16 elements) of the LDS digit planes
 
 __device__ inline uint32_t pack_bf16x2(float lo, float hi)
@@ -235,10 +241,8 @@ __device__ inline uint32_t pack_bf16x2(float lo, float hi)
 }
 
 // grid: x = N tiles, y = P tiles.  Waves: 4 row tiles of 32 x 2 column
-// halves of 64 (two 32 x 32 MFMA tiles each).  Three FP32 accumulator groups
-// per tile: diagonal 2 and diagonal 3 are exact integer sums; diagonals >= 4
-// (at most 2^-16 of the leading term) share one FP32 accumulator, whose
-// rounding stays near 2^-40 of the result.  Dynamic LDS: points [n][SP_BN]
+// halves of 64 (two 32 x 32 MFMA tiles each), SP_GROUPS accumulator groups
+// per tile.  Dynamic LDS: points [n][SP_BN]
 // doubles, C digits [S][SP_BM][SP_LDK], V digits [S][SP_BN][SP_LDK] (bf16).
 template <int S>
 __global__ void __launch_bounds__(SP_THREADS) k_dense_split(int n, int64_t K, int64_t Kp, const uint8_t *basis,
@@ -262,13 +266,13 @@ __global__ void __launch_bounds__(SP_THREADS) k_dense_split(int n, int64_t K, in
         s_x[idx] = pt < N ? X[pt * n + i] : 0.0;
     }
     double out[2][16];
-    f16v acc[3][2];
+    f16v acc[SP_GROUPS][2];
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
         for (int v = 0; v < 16; ++v) out[ct][v] = 0.0;
 #pragma unroll
-    for (int g = 0; g < 3; ++g)
+    for (int g = 0; g < SP_GROUPS; ++g)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
@@ -357,7 +361,7 @@ __global__ void __launch_bounds__(SP_THREADS) k_dense_split(int n, int64_t K, in
                                            8 * (lane >> 5));
 #pragma unroll
                 for (int s = 0; s < S - t; ++s) {
-                    const int g = (s + t) < 2 ? (s + t) : 2;
+                    const int g = (s + t) < SP_GROUPS - 1 ? (s + t) : SP_GROUPS - 1;
 #pragma unroll
                     for (int ct = 0; ct < 2; ++ct)
                         acc[g][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
@@ -370,10 +374,13 @@ __global__ void __launch_bounds__(SP_THREADS) k_dense_split(int n, int64_t K, in
             for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
-                    out[ct][v] += ((double)acc[2][ct][v] + (double)acc[1][ct][v]) + (double)acc[0][ct][v];
-                    acc[0][ct][v] = 0.0f;
-                    acc[1][ct][v] = 0.0f;
-                    acc[2][ct][v] = 0.0f;
+                    double t = 0.0;
+#pragma unroll
+                    for (int g = SP_GROUPS - 1; g >= 0; --g) {
+                        t += (double)acc[g][ct][v];
+                        acc[g][ct][v] = 0.0f;
+                    }
+                    out[ct][v] += t;
                 }
         }
     }

@@ -85,16 +85,18 @@ __global__ void k_mul_splitters(MulArgs A);
 __global__ void k_mul_buckets(MulArgs A);
 // Cursor-based bucket kernel: partner keys (and row keys) resident in LDS.
 constexpr int MB_THREADS = 512;
-constexpr int MB_ITEMS = 8;
-constexpr int MB_CAP = MB_THREADS * MB_ITEMS;
-constexpr int MB_RPT = 16;                     // rows per thread -> at most 8192 rows
+constexpr int MB_ITEMS = 6;
+constexpr int MB_CAP = MB_THREADS * MB_ITEMS;  // raw terms sorted per piece
+constexpr int MB_SAMPLE = 2048;                // sampled raw keys per bucket (piece boundaries)
+constexpr int MB_STACK = 112;                  // pending key ranges (pieces + bisection)
+constexpr int MB_RPT = 10;                     // rows per thread -> at most 5120 rows
 constexpr int MB_MAX_ROWS = MB_THREADS * MB_RPT;
-// dynamic LDS of the LDS bucket kernel: partner keys, row keys, 16-bit row cursors
+// dynamic LDS of the LDS bucket kernel: partner keys and coefficients, 16-bit row cursors
 __host__ __device__ inline size_t mb_lds_bytes(int64_t ns, int64_t nrows)
 {
-    return (size_t)(ns + nrows) * 8 + (size_t)nrows * 2;
+    return (size_t)ns * 16 + (size_t)nrows * 2;
 }
-constexpr size_t MB_LDS_LIMIT = 100 * 1024;    // with the static part, within 160 KB
+constexpr size_t MB_LDS_LIMIT = 96 * 1024;     // with the static part, within 160 KB
 constexpr int64_t MB_MAX_PARTNERS = 65535;     // cursors are 16-bit
 __global__ void k_mul_buckets_lds(MulArgs A);
 __global__ void k_mul_rowptr(const int64_t *out_off, const int64_t *pb_start, int64_t P, int64_t *out_rp,

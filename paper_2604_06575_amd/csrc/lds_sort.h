@@ -92,9 +92,8 @@ namespace polyhip {
 // that order (lane ranks from wavefront ballots, earlier rounds and waves from
 // LDS counters), which makes every pass stable.
 // s_cnt holds (THREADS/64) * 256 counters; s_scan THREADS/64 words.
-template <int THREADS, int ITEMS>
-__device__ void lds_radix_sort(uint64_t *keys, uint32_t *vals, int m, int key_bits, uint32_t *s_cnt,
-                               uint32_t *s_scan)
+template <int THREADS, int ITEMS, class V = uint32_t>
+__device__ void lds_radix_sort(uint64_t *keys, V *vals, int m, int key_bits, uint32_t *s_cnt, uint32_t *s_scan)
 {
     constexpr int W = THREADS / kWave;
     const int lane = threadIdx.x & (kWave - 1);
@@ -102,7 +101,7 @@ __device__ void lds_radix_sort(uint64_t *keys, uint32_t *vals, int m, int key_bi
     const unsigned long long lt = lane ? (~0ull >> (kWave - lane)) : 0ull;
     for (int sh = 0; sh < key_bits; sh += 8) {
         uint64_t k[ITEMS];
-        uint32_t v[ITEMS];
+        V v[ITEMS];
         uint32_t pos[ITEMS];
         uint32_t dg[ITEMS];
 #pragma unroll
@@ -113,7 +112,7 @@ __device__ void lds_radix_sort(uint64_t *keys, uint32_t *vals, int m, int key_bi
                 v[it] = vals[e];
             } else {
                 k[it] = ~0ull;
-                v[it] = ~0u;
+                v[it] = V(0);
             }
             dg[it] = (uint32_t)((k[it] >> sh) & 0xffu);
         }

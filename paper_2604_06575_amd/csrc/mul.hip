@@ -375,32 +375,34 @@ __global__ void __launch_bounds__(MUL_THREADS) k_mul_buckets(MulArgs A)
 // ---------------------------------------------------------------------------
 // Cursor-based bucket kernel.
 //
-// The partner keys (the sorted operand) and the row keys of the pair sit in
-// LDS.  Each row keeps a cursor at its first partner whose product key is not
-// below the current piece's lower bound; pieces are taken in ascending key
-// order, so a piece [lo, hi] is exactly the partners between each row's
-// cursor and the first product key above hi, found by galloping.  A piece
-// holding more than MB_CAP raw terms is bisected by key value.  Each piece is
-// generated row by row in (row, partner) order, sorted by a stable LDS radix
-// sort on its key (relative to the piece minimum), and every run of equal
-// keys is summed left to right -- the raw (i, j) order.  When the row operand
-// is b (|a| > |b|), the index i*|b| + j is appended below the key bits so the
-// sort itself produces (key, i, j) order.
+// The partner keys (the sorted operand) and the partner coefficients in the
+// same sorted order sit in LDS.  Each row keeps a cursor at its first
+// partner whose product key is not below the current piece's lower bound;
+// pieces are taken in ascending key order, so a piece [lo, hi] is exactly the
+// partners between each row's cursor and the first product key above hi,
+// found by galloping.  Piece boundaries come from a sorted sample of the
+// bucket's raw keys (every SR-th raw term in (row, partner) order); a piece
+// that still holds more than MB_CAP raw terms is bisected by key value.  Each
+// piece is generated row by row with its coefficient products c_i * c_j,
+// sorted by a stable LDS radix sort on its key (relative to the piece start),
+// and every run of equal keys is summed left to right -- the raw (i, j)
+// order.  When the row operand is b (|a| > |b|), the code (i << jbits) | j is
+// appended below the key bits so the sort itself produces (key, i, j) order.
 // ---------------------------------------------------------------------------
 
 namespace {
 
 struct MbShared {
     uint64_t key[MB_CAP];
-    uint32_t val[MB_CAP];
+    double val[MB_CAP];
     uint32_t cnt[(MB_THREADS / kWave) * 256];
     uint32_t scan32[MB_THREADS / kWave];
     int64_t scan[MB_THREADS / kWave];
     uint64_t red[MB_THREADS / kWave];
-    uint64_t stk_lo[72];
-    uint64_t stk_hi[72];
-    int64_t stk_cnt[72];
+    uint64_t stk_lo[MB_STACK];
+    uint64_t stk_hi[MB_STACK];
     int64_t bcast;
+    int sp;
 };
 
 // Number of partners t >= c with s[t] + kr <= hi (galloping from c).
@@ -417,8 +419,7 @@ __device__ inline uint32_t advance_count(const uint64_t *s, uint32_t ns, uint32_
         hi_i = c + step;
     }
     if (hi_i > ns) hi_i = ns;
-    // answer index in (lo, hi_i]: first t with s[t] > lim
-    uint32_t a = lo + 1, b = hi_i;
+    uint32_t a = lo + 1, b = hi_i;   // first t in (lo, hi_i] with s[t] > lim
     while (a < b) {
         const uint32_t mid = (a + b) >> 1;
         if (s[mid] <= lim) a = mid + 1;
@@ -426,6 +427,8 @@ __device__ inline uint32_t advance_count(const uint64_t *s, uint32_t ns, uint32_
     }
     return a - c;
 }
+
+__device__ inline int bitw(uint64_t v) { return v ? 64 - __clzll((unsigned long long)v) : 0; }
 
 }  // namespace
 
@@ -450,38 +453,63 @@ __global__ void __launch_bounds__(MB_THREADS) k_mul_buckets_lds(MulArgs A)
     const uint32_t nrows = (uint32_t)(swapped ? tb : ta);
     const uint32_t ns = (uint32_t)(swapped ? ta : tb);
     const uint64_t *g_rows = swapped ? A.kb + bb : A.ka + a0;
+    const double *g_rcf = swapped ? A.b_c + bb : A.a_c + a0;
     const uint64_t *g_srt = swapped ? A.ka_s + a0 : A.kb_s + bb;
     const uint32_t *perm = swapped ? A.perm_a + a0 : A.perm_b + bb;
-    const double *ca = A.a_c + a0;
-    const double *cb = A.b_c + bb;
-    // term pair (i, j) encoded as (i << jbits) | j, so ascending codes are
-    // ascending (i, j); in the swapped case the code is sorted below the key
-    const int jbits = tb > 1 ? 64 - __clzll((unsigned long long)(tb - 1)) : 0;
-    const int ibits = ta > 1 ? 64 - __clzll((unsigned long long)(ta - 1)) : 0;
-    const uint32_t jmask = (uint32_t)((1ull << jbits) - 1ull);
-    const int ij_bits = swapped ? ibits + jbits : 0;
+    const double *g_pcf = swapped ? A.a_c + a0 : A.b_c + bb;
+    // term pair (i, j) coded as (i << jbits) | j; sorted below the key when swapped
+    const int jbits = bitw((uint64_t)(tb - 1));
+    const int ij_bits = swapped ? bitw((uint64_t)(ta - 1)) + jbits : 0;
 
-    uint64_t *s_srt = s_dyn;                                   // [ns]
-    uint64_t *s_rows = s_dyn + ns;                             // [nrows]
-    uint16_t *s_cur = (uint16_t *)(s_dyn + ns + nrows);        // [nrows]
-    for (uint32_t i = tid; i < ns; i += MB_THREADS) s_srt[i] = g_srt[i];
-    for (uint32_t i = tid; i < nrows; i += MB_THREADS) s_rows[i] = g_rows[i];
+    uint64_t *s_srt = s_dyn;                                   // [ns] partner keys, sorted
+    double *s_scf = (double *)(s_dyn + ns);                    // [ns] partner coefficients, same order
+    uint16_t *s_cur = (uint16_t *)(s_dyn + 2 * (size_t)ns);    // [nrows] cursors
+    // partner keys and coefficients: all index loads of a batch first, then
+    // the dependent coefficient loads, so the two latencies are paid once
+    for (uint32_t i0 = 0; i0 < ns; i0 += MB_THREADS * 8) {
+        uint32_t pi[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t i = i0 + u * MB_THREADS + tid;
+            pi[u] = i < ns ? perm[i] : 0u;
+            if (i < ns) s_srt[i] = g_srt[i];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t i = i0 + u * MB_THREADS + tid;
+            if (i < ns) s_scf[i] = g_pcf[pi[u]];
+        }
+    }
     __syncthreads();
 
-    // rows of this thread: [r0, r1)
+    // this thread's rows [r0, r1), their keys in registers
     const uint32_t rpt = (nrows + MB_THREADS - 1) / MB_THREADS;
     const uint32_t r0 = tid * rpt < nrows ? tid * rpt : nrows;
     const uint32_t r1 = r0 + rpt < nrows ? r0 + rpt : nrows;
-
-    // cursors at lo0 and the bucket's raw count
+    uint64_t rk[MB_RPT];
+    double rcf[MB_RPT];
+    uint32_t cr[MB_RPT];
     int64_t mine = 0;
-    for (uint32_t r = r0; r < r1; ++r) {
-        const uint64_t kr = s_rows[r];
-        const uint32_t c = lo0 <= kr ? 0u : (uint32_t)lower_bound_u64(s_srt, ns, lo0 - kr);
-        s_cur[r] = (uint16_t)c;
-        mine += advance_count(s_srt, ns, c, kr, hi0);
+#pragma unroll
+    for (int q = 0; q < MB_RPT; ++q) {
+        const uint32_t r = r0 + q;
+        rk[q] = r < r1 ? g_rows[r] : 0;
+        rcf[q] = r < r1 ? g_rcf[r] : 0.0;
     }
-    const int64_t root = block_sum<MB_THREADS>(mine, S.scan);
+#pragma unroll
+    for (int q = 0; q < MB_RPT; ++q) {
+        const uint32_t r = r0 + q;
+        cr[q] = 0;
+        if (r < r1) {
+            const uint64_t kr = rk[q];
+            const uint32_t c = lo0 <= kr ? 0u : (uint32_t)lower_bound_u64(s_srt, ns, lo0 - kr);
+            s_cur[r] = (uint16_t)c;
+            cr[q] = advance_count(s_srt, ns, c, kr, hi0);
+            mine += cr[q];
+        }
+    }
+    int64_t root;
+    const int64_t ebase = block_exclusive_scan<MB_THREADS>(mine, S.scan, root);
     if (root == 0) {
         if (tid == 0) {
             A.bk_count[b] = 0;
@@ -489,12 +517,7 @@ __global__ void __launch_bounds__(MB_THREADS) k_mul_buckets_lds(MulArgs A)
         }
         return;
     }
-    if (tid == 0) {
-        S.bcast = (int64_t)atomicAdd(A.stage_cursor, (unsigned long long)root);
-        S.stk_lo[0] = lo0;
-        S.stk_hi[0] = hi0;
-        S.stk_cnt[0] = root;
-    }
+    if (tid == 0) S.bcast = (int64_t)atomicAdd(A.stage_cursor, (unsigned long long)root);
     __syncthreads();
     const int64_t stage = S.bcast;
     if (stage + root > A.st_capacity) {
@@ -505,57 +528,107 @@ __global__ void __launch_bounds__(MB_THREADS) k_mul_buckets_lds(MulArgs A)
         }
         return;
     }
+
+    // ---- piece boundaries from a sorted sample of the bucket's raw keys
+    if (root > MB_CAP) {
+        const int64_t SR = (root + MB_SAMPLE - 1) / MB_SAMPLE;          // sample rate
+        const int nsamp = (int)((root + SR - 1) / SR);
+        int64_t e = ebase;
+        uint64_t smax = 0;
+#pragma unroll
+        for (int q = 0; q < MB_RPT; ++q) {
+            const uint32_t r = r0 + q;
+            if (r < r1) {
+                const uint32_t c0 = s_cur[r];
+                // first element of this row that falls on the sample grid
+                int64_t first = ((e + SR - 1) / SR) * SR;
+                for (int64_t f = first; f < e + cr[q]; f += SR) {
+                    const uint64_t rel = rk[q] + s_srt[c0 + (uint32_t)(f - e)] - lo0;
+                    S.key[f / SR] = rel;
+                    smax = rel > smax ? rel : smax;
+                }
+                e += cr[q];
+            }
+        }
+        const uint64_t sm = block_max_u64<MB_THREADS>(smax, S.red);
+        lds_radix_sort_keys<MB_THREADS, MB_ITEMS>(S.key, nsamp, bitw(sm), S.cnt, S.scan32);
+        int64_t step = (MB_CAP * 3 / 4) / SR;
+        if (step < 1) step = 1;
+        int64_t npieces = (nsamp + step - 1) / step;
+        if (npieces > MB_STACK - 66) {
+            npieces = MB_STACK - 66;
+            step = (nsamp + npieces - 1) / npieces;
+            npieces = (nsamp + step - 1) / step;
+        }
+        // pieces [B_q, B_{q+1} - 1] with B_0 = lo0, B_q = lo0 + sample[q*step]; pushed last-first
+        if (tid == 0) {
+            int sp = 0;
+            uint64_t hi = hi0;
+            for (int64_t q = npieces - 1; q >= 0; --q) {
+                const uint64_t lo = q == 0 ? lo0 : lo0 + S.key[q * step];
+                if (lo <= hi) {
+                    S.stk_lo[sp] = lo;
+                    S.stk_hi[sp] = hi;
+                    ++sp;
+                }
+                if (lo == 0) break;
+                hi = lo - 1;
+                if (hi < lo0) break;
+            }
+            S.sp = sp;
+        }
+    } else if (tid == 0) {
+        S.stk_lo[0] = lo0;
+        S.stk_hi[0] = hi0;
+        S.sp = 1;
+    }
+    __syncthreads();
+    int sp = S.sp;
+
     int64_t written = 0;
-    int sp = 1;
     while (sp > 0) {
         __syncthreads();
         --sp;
         const uint64_t lo = S.stk_lo[sp], hi = S.stk_hi[sp];
-        const int64_t cnt = S.stk_cnt[sp];
         __syncthreads();
-        if (cnt == 0) continue;
-        const uint64_t width = hi - lo;
-        const int wbits = width ? 64 - __clzll((unsigned long long)width) : 0;
-        const bool fits = cnt <= MB_CAP && wbits + ij_bits <= 64;
-        if (fits) {
-            // ---- generate the piece in (row, partner) order
-            uint32_t cr[MB_RPT];
-            int64_t c = 0;
+        int64_t c = 0;
 #pragma unroll
-            for (int q = 0; q < MB_RPT; ++q) {
-                const uint32_t r = r0 + q;
-                cr[q] = 0;
-                if (r < r1) {
-                    cr[q] = advance_count(s_srt, ns, s_cur[r], s_rows[r], hi);
-                    c += cr[q];
-                }
+        for (int q = 0; q < MB_RPT; ++q) {
+            const uint32_t r = r0 + q;
+            cr[q] = 0;
+            if (r < r1) {
+                cr[q] = advance_count(s_srt, ns, s_cur[r], rk[q], hi);
+                c += cr[q];
             }
-            int64_t tot;
-            int64_t pos = block_exclusive_scan<MB_THREADS>(c, S.scan, tot);
+        }
+        int64_t tot;
+        int64_t pos = block_exclusive_scan<MB_THREADS>(c, S.scan, tot);
+        if (tot == 0) continue;
+        const int wbits = bitw(hi - lo);
+        if (tot <= MB_CAP && wbits + ij_bits <= 64) {
+            // ---- generate the piece in (row, partner) order with its products
             uint64_t kmax = 0;
 #pragma unroll
             for (int q = 0; q < MB_RPT; ++q) {
                 const uint32_t r = r0 + q;
                 if (r < r1 && cr[q]) {
-                    const uint64_t kr = s_rows[r];
+                    const double rc = rcf[q];
                     const uint32_t c0 = s_cur[r];
                     for (uint32_t t = c0; t < c0 + cr[q]; ++t, ++pos) {
-                        const uint64_t rel = kr + s_srt[t] - lo;
-                        const uint32_t o = perm[t];
-                        const uint32_t ij = swapped ? ((o << jbits) | r) : ((r << jbits) | o);
+                        const uint64_t rel = rk[q] + s_srt[t] - lo;
                         kmax = rel > kmax ? rel : kmax;
-                        if (pos < MB_CAP) {
-                            S.key[pos] = swapped ? ((rel << ij_bits) | ij) : rel;
-                            S.val[pos] = ij;
-                        }
+                        uint64_t key = rel;
+                        if (swapped) key = (rel << ij_bits) | (((uint64_t)perm[t] << jbits) | r);
+                        S.key[pos] = key;
+                        S.val[pos] = swapped ? s_scf[t] * rc : rc * s_scf[t];
                     }
                     s_cur[r] = (uint16_t)(c0 + cr[q]);
                 }
             }
             const uint64_t relmax = block_max_u64<MB_THREADS>(kmax, S.red);
-            const int m = (int)(tot < MB_CAP ? tot : MB_CAP);
-            const int rbits = relmax ? 64 - __clzll((unsigned long long)relmax) : 0;
-            lds_radix_sort<MB_THREADS, MB_ITEMS>(S.key, S.val, m, rbits + ij_bits, S.cnt, S.scan32);
+            const int m = (int)tot;
+            lds_radix_sort<MB_THREADS, MB_ITEMS, double>(S.key, S.val, m, bitw(relmax) + ij_bits, S.cnt,
+                                                          S.scan32);
             // ---- merge runs: thread owns sorted elements [tid*ITEMS, tid*ITEMS + ITEMS)
             const int e0 = tid * MB_ITEMS;
             double sums[MB_ITEMS];
@@ -568,12 +641,8 @@ __global__ void __launch_bounds__(MB_THREADS) k_mul_buckets_lds(MulArgs A)
                 if (e < m) {
                     const uint64_t k = S.key[e] >> ij_bits;
                     if (e == 0 || (S.key[e - 1] >> ij_bits) != k) {
-                        uint32_t v = S.val[e];
-                        double s = ca[v >> jbits] * cb[v & jmask];
-                        for (int f = e + 1; f < m && (S.key[f] >> ij_bits) == k; ++f) {
-                            v = S.val[f];
-                            s = s + ca[v >> jbits] * cb[v & jmask];
-                        }
+                        double s = S.val[e];
+                        for (int f = e + 1; f < m && (S.key[f] >> ij_bits) == k; ++f) s = s + S.val[f];
                         sums[q] = s;
                         if (!(fabs(s) <= A.tol)) {
                             keepmask |= 1u << q;
@@ -609,7 +678,7 @@ __global__ void __launch_bounds__(MB_THREADS) k_mul_buckets_lds(MulArgs A)
                     const int64_t l = lower_bound_u64(kbs, tb, lo - kai);
                     const int64_t u = upper_bound_u64(kbs, tb, lo - kai);
                     for (int64_t q = l; q < u; ++q) {
-                        const double t = ca[i] * cb[pb[q]];
+                        const double t = A.a_c[a0 + i] * A.b_c[bb + pb[q]];
                         s = first ? t : s + t;
                         first = false;
                     }
@@ -621,22 +690,20 @@ __global__ void __launch_bounds__(MB_THREADS) k_mul_buckets_lds(MulArgs A)
                 }
                 S.bcast = keep ? 1 : 0;
             }
-            for (uint32_t r = r0; r < r1; ++r)
-                s_cur[r] = (uint16_t)(s_cur[r] + advance_count(s_srt, ns, s_cur[r], s_rows[r], hi));
+#pragma unroll
+            for (int q = 0; q < MB_RPT; ++q) {
+                const uint32_t r = r0 + q;
+                if (r < r1) s_cur[r] = (uint16_t)(s_cur[r] + cr[q]);
+            }
             __syncthreads();
             written += S.bcast;
         } else {
             const uint64_t mid = lo + (hi - lo) / 2;
-            int64_t c = 0;
-            for (uint32_t r = r0; r < r1; ++r) c += advance_count(s_srt, ns, s_cur[r], s_rows[r], mid);
-            const int64_t left = block_sum<MB_THREADS>(c, S.scan);
             if (tid == 0) {
                 S.stk_lo[sp] = mid + 1;
                 S.stk_hi[sp] = hi;
-                S.stk_cnt[sp] = cnt - left;
                 S.stk_lo[sp + 1] = lo;
                 S.stk_hi[sp + 1] = mid;
-                S.stk_cnt[sp + 1] = left;
             }
             sp += 2;
         }

@@ -338,30 +338,31 @@ __global__ void __launch_bounds__(256) k_compact(const int64_t *stage_off, const
     int64_t w0 = (b0 + 3) & ~(int64_t)3, w1 = b1 & ~(int64_t)3;
     if (w0 > b1) w0 = b1;
     if (w1 < w0) w1 = w0;
+    const uint32_t un = (uint32_t)n;
+    const uint64_t *keys = st_key + src;
+    // byte bi (absolute) -> row (bi - b0) / n of this segment, field (bi - b0) % n
     auto byte_at = [&](int64_t bi) -> uint32_t {
-        const int64_t row = bi / n;
-        const int f = (int)(bi - row * n);
-        const uint64_t k = st_key[src + (row - dst)];
-        return (uint32_t)((k >> (bits * (n - 1 - f))) & mask);
+        const uint32_t rel = (uint32_t)(bi - b0);
+        const uint32_t row = rel / un, f = rel - row * un;
+        return (uint32_t)((keys[row] >> (bits * (n - 1 - (int)f))) & mask);
     };
-    // unaligned head and tail bytes
     for (int64_t bi = b0 + threadIdx.x; bi < w0; bi += blockDim.x) out_exps[bi] = (uint8_t)byte_at(bi);
     for (int64_t bi = w1 + threadIdx.x; bi < b1; bi += blockDim.x) out_exps[bi] = (uint8_t)byte_at(bi);
     uint32_t *words = (uint32_t *)out_exps;
     for (int64_t w = w0 / 4 + threadIdx.x; w < w1 / 4; w += blockDim.x) {
-        const int64_t bi = w * 4;
-        int64_t row = bi / n;
-        int f = (int)(bi - row * n);
-        uint64_t k = st_key[src + (row - dst)];
+        const uint32_t rel = (uint32_t)(w * 4 - b0);
+        uint32_t row = rel / un;
+        uint32_t f = rel - row * un;
+        uint64_t k = keys[row];
         uint32_t v = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            if (f == n) {
+            if (f == un) {
                 f = 0;
                 ++row;
-                k = st_key[src + (row - dst)];
+                k = keys[row];
             }
-            v |= (uint32_t)((k >> (bits * (n - 1 - f))) & mask) << (8 * q);
+            v |= (uint32_t)((k >> (bits * (n - 1 - (int)f))) & mask) << (8 * q);
             ++f;
         }
         words[w] = v;

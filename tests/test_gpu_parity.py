@@ -336,7 +336,9 @@ def test_dense_split(ph, S):
     A = oracle.eval_dense(wl.basis, np.abs(wl.C), np.abs(wl.X))
     err = np.abs(Y - Yo) / A
     say(f"  S={S} max condition-scaled error {err.max():.3e}")
-    bound = 2.0 ** -(8 * S - 12)
+    # truncation after S digits, or the rounding floor of the shared FP32
+    # group of diagonals >= 4 (about 2^-34 per 128-deep K-block)
+    bound = max(2.0 ** -(8 * S - 12), 2.0 ** -33)
     assert err.max() <= bound
     if S >= 5:
         assert err.max() <= 1e-10
