@@ -243,16 +243,102 @@ struct EvalPlan {
     size_t total;
 };
 
-void launch_eval_blocks(const EvalArgs &A, const uint64_t *enc, hipStream_t s)
+// Segments per polynomial for the term-streaming kernel: polynomials are cut
+// into term segments only when there are too few (polynomial, point block)
+// pairs to fill the machine.  Depends on sizes only (workspace queries call
+// it too).
+inline int64_t eval_segments(int64_t Q, int64_t N, int64_t T)
+{
+    if (Q <= 0 || N <= 0) return 1;
+    const int64_t units = ceil_div(EV_TARGET_BLOCKS, ceil_div(N, kWave));
+    if (Q >= units) return 1;
+    int64_t S = ceil_div(units, Q);
+    S = std::min<int64_t>(S, std::max<int64_t>(1, T / (Q * EV_MIN_SEGMENT)));
+    return std::max<int64_t>(1, std::min<int64_t>(S, EV_MAX_SEGMENTS));
+}
+
+inline size_t eval_partial_bytes(int64_t Q, int64_t N, int64_t S) { return S > 1 ? (size_t)(8 * S * Q * N) : 0; }
+
+void launch_eval_blocks(const EvalArgs &A, const uint64_t *enc, double *partial, int64_t S, hipStream_t s)
 {
     if (A.Q <= 0 || A.N <= 0) return;
     const unsigned gx = (unsigned)ceil_div(A.N, kWave);
     // enough blocks to fill the machine several times over, each looping
-    // over polynomials so that its point tile is loaded once.
-    int64_t want = std::max<int64_t>(1, ((int64_t)device_cus() * tunables().eval_blocks_per_cu + gx - 1) / gx);
-    const unsigned gy = (unsigned)std::min<int64_t>(std::min<int64_t>(A.Q, want * 4), 65535);
-    const size_t lds = (size_t)A.n * kWave * sizeof(double);
-    hipLaunchKernelGGL(k_eval_blocks, dim3(gx, gy), dim3(EV_THREADS), lds, s, A, enc);
+    // over work units
+    const int64_t want = std::max<int64_t>(1, ((int64_t)device_cus() * tunables().eval_blocks_per_cu + gx - 1) / gx);
+    const unsigned gy = (unsigned)std::min<int64_t>(std::min<int64_t>(A.Q * S, want * 4), 65535);
+    if (A.n <= 16) {
+        hipLaunchKernelGGL(k_eval_terms<16>, dim3(gx, gy), dim3(EV_THREADS), 0, s, A, enc, partial, S);
+    } else if (A.n <= 32) {
+        hipLaunchKernelGGL(k_eval_terms<32>, dim3(gx, gy), dim3(EV_THREADS), 0, s, A, enc, partial, S);
+    } else {
+        const size_t lds = (size_t)A.n * kWave * sizeof(double);
+        hipLaunchKernelGGL(k_eval_terms<0>, dim3(gx, gy), dim3(EV_THREADS), lds, s, A, enc, partial, S);
+    }
+    if (S > 1) hipLaunchKernelGGL(k_eval_reduce, dim3(grid1(A.Q * A.N, 256)), dim3(256), 0, s, A, partial, S);
+}
+
+// ------------------------------------------------------- scans, formation
+
+inline int64_t scan_tmp_count(int64_t S) { return 2 * ceil_div(std::max<int64_t>(S, 1), SCAN_TILE) + 1; }
+
+// out[0..S] = exclusive scan of in[0..S) with out[S] = total; tmp holds
+// scan_tmp_count(S) entries.
+void launch_scan(const int64_t *in, int64_t S, int64_t *out, int64_t *tmp, hipStream_t s)
+{
+    if (S <= 8 * SCAN_TILE) {
+        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, in, S, out);
+        return;
+    }
+    const int64_t nt = ceil_div(S, SCAN_TILE);
+    int64_t *sums = tmp, *tile_off = tmp + nt;
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)nt), dim3(SCAN_THREADS), 0, s, in, S, sums);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, sums, nt, tile_off);
+    hipLaunchKernelGGL(k_scan_tile_apply, dim3((unsigned)nt), dim3(SCAN_THREADS), 0, s, in, S, tile_off, out);
+}
+
+// Derivative formation over (polynomial, chunk) work items.  The chunk size
+// depends on the total term count only, so workspace queries need no device.
+struct FormPlan {
+    int64_t chunk = 0, W = 0, G = 0;
+    size_t items = 0, item_start = 0, cnt = 0, off = 0, tmp = 0;
+};
+
+FormPlan plan_form(const poly_csr *f, int64_t G, Layout &L)
+{
+    FormPlan fp;
+    const int64_t P = f->npolys, T = total_terms(f);
+    fp.G = G;
+    fp.chunk = std::min<int64_t>(4096, std::max<int64_t>(256, align_up(ceil_div(T, 2048), 256)));
+    for (int64_t p = 0; p < P; ++p) {
+        const int64_t tp = f->row_ptr_host[p + 1] - f->row_ptr_host[p];
+        fp.W += tp <= 0 ? 1 : ceil_div(tp, fp.chunk);
+    }
+    fp.items = L.take(8 * P);
+    fp.item_start = L.take(8 * (P + 1));
+    fp.cnt = L.take(8 * fp.W * G);
+    fp.off = L.take(8 * (fp.W * G + 1));
+    fp.tmp = L.take(8 * scan_tmp_count(std::max<int64_t>(P, fp.W * G)));
+    return fp;
+}
+
+// Forms the G polynomials of every source polynomial (A's mode, pair batch,
+// outputs and capacity set by the caller) with out_rp of P*G + 1 entries.
+void run_form(const FormPlan &fp, FormArgs A, void *ws, hipStream_t s)
+{
+    int64_t *items = at<int64_t>(ws, fp.items);
+    int64_t *tmp = at<int64_t>(ws, fp.tmp);
+    A.item_start = at<int64_t>(ws, fp.item_start);
+    A.cnt = at<int64_t>(ws, fp.cnt);
+    A.chunk = fp.chunk;
+    A.ngroups = fp.G;
+    int64_t *off = at<int64_t>(ws, fp.off);
+    hipLaunchKernelGGL(k_item_count, dim3(grid1(A.P, 256)), dim3(256), 0, s, A.rp, A.P, fp.chunk, items);
+    launch_scan(items, A.P, const_cast<int64_t *>(A.item_start), tmp, s);
+    hipLaunchKernelGGL(k_form_count, dim3((unsigned)fp.W), dim3(JAC_THREADS), 0, s, A);
+    launch_scan(A.cnt, fp.W * fp.G, off, tmp, s);
+    hipLaunchKernelGGL(k_form_rowptr, dim3(grid1(A.P * fp.G + 1, 256)), dim3(256), 0, s, A, (const int64_t *)off);
+    hipLaunchKernelGGL(k_form_write, dim3((unsigned)fp.W), dim3(JAC_THREADS), 0, s, A, (const int64_t *)off);
 }
 
 bool lds_attr_done = false;
@@ -261,7 +347,7 @@ void ensure_lds_attrs()
 {
     std::lock_guard<std::mutex> g(lds_mu);
     if (lds_attr_done) return;
-    (void)hipFuncSetAttribute((const void *)k_eval_blocks, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
+    (void)hipFuncSetAttribute((const void *)k_eval_terms<0>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
     (void)hipFuncSetAttribute((const void *)k_backward_dc, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
     (void)hipFuncSetAttribute((const void *)k_mul_buckets_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)MB_LDS_LIMIT);
@@ -276,22 +362,51 @@ inline int64_t grad_terms_bound(int64_t T, int n) { return T * std::min<int64_t>
 constexpr int64_t HESS_BATCH = 256;   // pairs formed and evaluated per pass
 inline int64_t hess_terms_bound(int64_t T, int64_t nb) { return T * std::min<int64_t>(nb, 36); }
 
+// Segment partials for the Hessian passes: the largest over the full batches
+// and the last, possibly smaller, one.
+inline size_t hess_partial_bytes(int64_t P, int64_t N, int64_t T, int64_t npairs, int64_t nbmax)
+{
+    const int64_t nlast = npairs - (npairs - 1) / nbmax * nbmax;
+    const size_t a = eval_partial_bytes(P * nbmax, N, eval_segments(P * nbmax, N, T));
+    const size_t b = eval_partial_bytes(P * nlast, N, eval_segments(P * nlast, N, T));
+    return std::max(a, b);
+}
+
 struct GradPlan {
-    size_t counts, jrp, jexps, jcoefs, jenc;
-    int64_t cap;
-    size_t total;
+    FormPlan form;
+    size_t jrp, jexps, jcoefs, jenc, part;
+    int64_t cap, S;
 };
 
-GradPlan plan_grad(int64_t P, int64_t T, int n, Layout &L)
+GradPlan plan_grad(const poly_csr *f, int64_t N, Layout &L)
 {
     GradPlan g;
+    const int n = f->nvars;
+    const int64_t P = f->npolys, T = total_terms(f);
     g.cap = grad_terms_bound(T, n);
-    g.counts = L.take(8 * P * n);
+    g.form = plan_form(f, n, L);
     g.jrp = L.take(8 * (P * n + 1));
     g.jexps = L.take((size_t)g.cap * n);
     g.jcoefs = L.take(8 * g.cap);
     g.jenc = L.take(16 * g.cap);
+    g.S = eval_segments(P * n, N, T);
+    g.part = L.take(eval_partial_bytes(P * n, N, g.S));
     return g;
+}
+
+FormArgs form_args(const poly_csr *f, int mode, int32_t *status, int32_t overflow_code)
+{
+    FormArgs A;
+    memset(&A, 0, sizeof(A));
+    A.rp = f->row_ptr;
+    A.exps = f->exps;
+    A.coefs = f->coefs;
+    A.n = f->nvars;
+    A.mode = mode;
+    A.P = f->npolys;
+    A.status = status;
+    A.overflow_code = overflow_code;
+    return A;
 }
 
 poly_status run_grad(const poly_csr *f, const double *X, int64_t N, double *G, void *ws, const GradPlan &g,
@@ -300,16 +415,18 @@ poly_status run_grad(const poly_csr *f, const double *X, int64_t N, double *G, v
     const int64_t P = f->npolys;
     const int n = f->nvars;
     int32_t *status = at<int32_t>(ws, 0);
-    int64_t *counts = at<int64_t>(ws, g.counts);
     int64_t *jrp = at<int64_t>(ws, g.jrp);
     uint8_t *jexps = at<uint8_t>(ws, g.jexps);
     double *jcoefs = at<double>(ws, g.jcoefs);
     uint64_t *jenc = at<uint64_t>(ws, g.jenc);
-    hipLaunchKernelGGL(k_jac_count, dim3((unsigned)P), dim3(JAC_THREADS), 0, s, f->row_ptr, f->exps, n, counts);
-    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, counts, P * n, jrp);
-    hipLaunchKernelGGL(k_jac_write, dim3((unsigned)P), dim3(JAC_THREADS), 0, s, f->row_ptr, f->exps, f->coefs, n,
-                       jrp, jexps, jcoefs, g.cap, status, (int32_t)POLY_ERR_WORKSPACE);
-    hipLaunchKernelGGL(k_encode_support, dim3(grid1(g.cap, 256)), dim3(256), 0, s, jexps, g.cap, n, jenc);
+    FormArgs F = form_args(f, 0, status, (int32_t)POLY_ERR_WORKSPACE);
+    F.out_rp = jrp;
+    F.out_exps = jexps;
+    F.out_coefs = jcoefs;
+    F.capacity = g.cap;
+    run_form(g.form, F, ws, s);
+    hipLaunchKernelGGL(k_encode_support, dim3(grid1(g.cap, 256)), dim3(256), 0, s, jexps, g.cap, n, jenc,
+                       (const int64_t *)(jrp + P * n));
     LAUNCH_CHECK();
     EvalArgs A;
     memset(&A, 0, sizeof(A));
@@ -323,7 +440,7 @@ poly_status run_grad(const poly_csr *f, const double *X, int64_t N, double *G, v
     A.mode = OUT_GRAD;
     A.Y = G;
     A.term_limit = g.cap;
-    launch_eval_blocks(A, jenc, s);
+    launch_eval_blocks(A, jenc, at<double>(ws, g.part), g.S, s);
     LAUNCH_CHECK();
     return POLY_OK;
 }
@@ -557,7 +674,7 @@ poly_status poly_jacobian_workspace(const poly_csr *in, size_t *ws_bytes)
     if (st != POLY_OK) return st;
     if (!ws_bytes) return POLY_ERR_ARG;
     Layout L;
-    L.take(8 * in->npolys * in->nvars);
+    plan_form(in, in->nvars, L);
     *ws_bytes = L.total();
     return POLY_OK;
 }
@@ -571,7 +688,7 @@ poly_status poly_jacobian(const poly_csr *in, poly_csr *out, void *ws, size_t ws
     const int64_t P = in->npolys;
     if (out->nvars != n || out->npolys != P * n) return POLY_ERR_ARG;
     Layout L;
-    const size_t o_counts = L.take(8 * P * n);
+    const FormPlan fp = plan_form(in, n, L);
     if (!ws || ws_bytes < L.total()) return POLY_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     int32_t *status = at<int32_t>(ws, 0);
@@ -581,11 +698,12 @@ poly_status poly_jacobian(const poly_csr *in, poly_csr *out, void *ws, size_t ws
         LAUNCH_CHECK();
         return POLY_OK;
     }
-    int64_t *counts = at<int64_t>(ws, o_counts);
-    hipLaunchKernelGGL(k_jac_count, dim3((unsigned)P), dim3(JAC_THREADS), 0, s, in->row_ptr, in->exps, n, counts);
-    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, counts, P * n, out->row_ptr);
-    hipLaunchKernelGGL(k_jac_write, dim3((unsigned)P), dim3(JAC_THREADS), 0, s, in->row_ptr, in->exps, in->coefs, n,
-                       out->row_ptr, out->exps, out->coefs, out->capacity, status, (int32_t)POLY_ERR_CAPACITY);
+    FormArgs F = form_args(in, 0, status, (int32_t)POLY_ERR_CAPACITY);
+    F.out_rp = out->row_ptr;
+    F.out_exps = out->exps;
+    F.out_coefs = out->coefs;
+    F.capacity = out->capacity;
+    run_form(fp, F, ws, s);
     LAUNCH_CHECK();
     return POLY_OK;
 }
@@ -608,6 +726,7 @@ poly_status poly_eval_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)
     if (!ws_bytes || N < 0) return POLY_ERR_ARG;
     Layout L;
     L.take(16 * total_terms(f));
+    L.take(eval_partial_bytes(f->npolys, N, eval_segments(f->npolys, N, total_terms(f))));
     *ws_bytes = L.total();
     return POLY_OK;
 }
@@ -620,6 +739,8 @@ poly_status poly_eval(const poly_csr *f, const double *X, int64_t N, double *Y, 
     const int64_t T = total_terms(f);
     Layout L;
     const size_t o_enc = L.take(16 * T);
+    const int64_t S = eval_segments(f->npolys, N, T);
+    const size_t o_part = L.take(eval_partial_bytes(f->npolys, N, S));
     if (!ws || ws_bytes < L.total()) return POLY_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     ensure_lds_attrs();
@@ -629,7 +750,8 @@ poly_status poly_eval(const poly_csr *f, const double *X, int64_t N, double *Y, 
         return POLY_OK;
     }
     uint64_t *enc = at<uint64_t>(ws, o_enc);
-    if (T > 0) hipLaunchKernelGGL(k_encode_support, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, f->nvars, enc);
+    if (T > 0) hipLaunchKernelGGL(k_encode_support, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, f->nvars, enc,
+                                  (const int64_t *)nullptr);
     EvalArgs A;
     memset(&A, 0, sizeof(A));
     A.rp = f->row_ptr;
@@ -642,7 +764,7 @@ poly_status poly_eval(const poly_csr *f, const double *X, int64_t N, double *Y, 
     A.mode = OUT_EVAL;
     A.Y = Y;
     A.term_limit = T;
-    launch_eval_blocks(A, enc, s);
+    launch_eval_blocks(A, enc, at<double>(ws, o_part), S, s);
     LAUNCH_CHECK();
     return POLY_OK;
 }
@@ -653,7 +775,7 @@ poly_status poly_grad_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)
     if (st != POLY_OK) return st;
     if (!ws_bytes || N < 0) return POLY_ERR_ARG;
     Layout L;
-    plan_grad(f->npolys, total_terms(f), f->nvars, L);
+    plan_grad(f, N, L);
     *ws_bytes = L.total();
     return POLY_OK;
 }
@@ -664,7 +786,7 @@ poly_status poly_grad(const poly_csr *f, const double *X, int64_t N, double *G, 
     poly_status st = check_eval(f, X, N, G);
     if (st != POLY_OK) return st;
     Layout L;
-    const GradPlan g = plan_grad(f->npolys, total_terms(f), f->nvars, L);
+    const GradPlan g = plan_grad(f, N, L);
     if (!ws || ws_bytes < L.total()) return POLY_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     ensure_lds_attrs();
@@ -688,11 +810,12 @@ poly_status poly_hess_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)
     const int64_t cap = hess_terms_bound(T, nb);
     Layout L;
     L.take(4 * npairs);
-    L.take(8 * P * nb);
+    plan_form(f, nb, L);
     L.take(8 * (P * nb + 1));
     L.take((size_t)cap * n);
     L.take(8 * cap);
     L.take(16 * cap);
+    L.take(hess_partial_bytes(P, N, T, npairs, nb));
     *ws_bytes = L.total();
     return POLY_OK;
 }
@@ -709,11 +832,12 @@ poly_status poly_hess(const poly_csr *f, const double *X, int64_t N, double *H, 
     const int64_t cap = hess_terms_bound(T, nbmax);
     Layout L;
     const size_t o_pairs = L.take(4 * npairs);
-    const size_t o_counts = L.take(8 * P * nbmax);
+    const FormPlan fmax = plan_form(f, nbmax, L);
     const size_t o_rp = L.take(8 * (P * nbmax + 1));
     const size_t o_exps = L.take((size_t)cap * n);
     const size_t o_coefs = L.take(8 * cap);
     const size_t o_enc = L.take(16 * cap);
+    const size_t o_part = L.take(hess_partial_bytes(P, N, T, npairs, nbmax));
     if (!ws || ws_bytes < L.total()) return POLY_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     ensure_lds_attrs();
@@ -724,7 +848,6 @@ poly_status poly_hess(const poly_csr *f, const double *X, int64_t N, double *H, 
         return POLY_OK;
     }
     uint32_t *pairs = at<uint32_t>(ws, o_pairs);
-    int64_t *counts = at<int64_t>(ws, o_counts);
     int64_t *hrp = at<int64_t>(ws, o_rp);
     uint8_t *hexps = at<uint8_t>(ws, o_exps);
     double *hcoefs = at<double>(ws, o_coefs);
@@ -732,12 +855,18 @@ poly_status poly_hess(const poly_csr *f, const double *X, int64_t N, double *H, 
     hipLaunchKernelGGL(k_pair_table, dim3(grid1(n, 256)), dim3(256), 0, s, n, pairs);
     for (int64_t pb0 = 0; pb0 < npairs; pb0 += nbmax) {
         const int64_t nb = std::min<int64_t>(nbmax, npairs - pb0);
-        const dim3 g((unsigned)P, (unsigned)ceil_div(nb, HES_PAIRS_PER_BLOCK));
-        hipLaunchKernelGGL(k_hes_count, g, dim3(JAC_THREADS), 0, s, f->row_ptr, f->exps, n, pb0, nb, pairs, counts);
-        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, counts, P * nb, hrp);
-        hipLaunchKernelGGL(k_hes_write, g, dim3(JAC_THREADS), 0, s, f->row_ptr, f->exps, f->coefs, n, pb0, nb, pairs,
-                           hrp, hexps, hcoefs, cap, status);
-        hipLaunchKernelGGL(k_encode_support, dim3(grid1(cap, 256)), dim3(256), 0, s, hexps, cap, n, henc);
+        FormPlan fp = fmax;   // the last batch may be smaller: same layout, fewer groups
+        fp.G = nb;
+        FormArgs F = form_args(f, 1, status, (int32_t)POLY_ERR_WORKSPACE);
+        F.pair_base = pb0;
+        F.pair_jk = pairs;
+        F.out_rp = hrp;
+        F.out_exps = hexps;
+        F.out_coefs = hcoefs;
+        F.capacity = cap;
+        run_form(fp, F, ws, s);
+        hipLaunchKernelGGL(k_encode_support, dim3(grid1(cap, 256)), dim3(256), 0, s, hexps, cap, n, henc,
+                           (const int64_t *)(hrp + P * nb));
         EvalArgs A;
         memset(&A, 0, sizeof(A));
         A.rp = hrp;
@@ -753,7 +882,7 @@ poly_status poly_hess(const poly_csr *f, const double *X, int64_t N, double *H, 
         A.pair_jk = pairs;
         A.Y = H;
         A.term_limit = cap;
-        launch_eval_blocks(A, henc, s);
+        launch_eval_blocks(A, henc, at<double>(ws, o_part), eval_segments(P * nb, N, T), s);
         LAUNCH_CHECK();
     }
     return POLY_OK;
@@ -767,7 +896,7 @@ poly_status poly_eval_backward_workspace(const poly_csr *f, int64_t N, size_t *w
     const int n = f->nvars;
     const int64_t P = f->npolys, T = total_terms(f);
     Layout L;
-    plan_grad(P, T, n, L);
+    plan_grad(f, N, L);
     L.take(8 * P * N * n);   // G
     L.take(16 * T);          // encoded support of f
     const int cp = std::max(1, std::min(BWC_POINTS, 8192 / n));
@@ -784,7 +913,7 @@ poly_status poly_eval_backward(const poly_csr *f, const double *X, int64_t N, co
     const int n = f->nvars;
     const int64_t P = f->npolys, T = total_terms(f);
     Layout L;
-    const GradPlan g = plan_grad(P, T, n, L);
+    const GradPlan g = plan_grad(f, N, L);
     const size_t o_G = L.take(8 * P * N * n);
     const size_t o_enc = L.take(16 * T);
     const int cp = std::max(1, std::min(BWC_POINTS, 8192 / n));
@@ -812,7 +941,8 @@ poly_status poly_eval_backward(const poly_csr *f, const double *X, int64_t N, co
         } else {
             uint64_t *enc = at<uint64_t>(ws, o_enc);
             double *part = at<double>(ws, o_part);
-            hipLaunchKernelGGL(k_encode_support, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, enc);
+            hipLaunchKernelGGL(k_encode_support, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, enc,
+                               (const int64_t *)nullptr);
             const size_t lds = (size_t)cp * n * sizeof(double);
             hipLaunchKernelGGL(k_backward_dc, dim3(grid1(T, BWC_THREADS), (unsigned)nchunks), dim3(BWC_THREADS), lds,
                                s, f->row_ptr, P, f->exps, n, T, X, N, gY, part, nchunks, (const uint64_t *)enc, cp);

@@ -467,7 +467,8 @@ poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_ex
     if (P == 0 || N == 0) return hipGetLastError() == hipSuccess ? POLY_OK : POLY_ERR_HIP;
     uint64_t *enc = (uint64_t *)((char *)ws + d.enc);
     if (K > 0)
-        hipLaunchKernelGGL(k_encode_support, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, s, basis, K, n, enc);
+        hipLaunchKernelGGL(k_encode_support, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, s, basis, K, n, enc,
+                           (const int64_t *)nullptr);
     if (prec == POLY_FP64) {
         static bool attr = false;
         if (!attr) {

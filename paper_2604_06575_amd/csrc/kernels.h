@@ -40,6 +40,11 @@ __global__ void k_seg_merge(SegArgs A);
 __global__ void k_seg_sort(SegArgs A);
 __global__ void k_seg_sort2(SegArgs A, SegArgs B);
 __global__ void k_scan_counts(const int64_t *counts, int64_t S, int64_t *out);
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int64_t SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+__global__ void k_scan_tile_sums(const int64_t *in, int64_t S, int64_t *sums);
+__global__ void k_scan_tile_apply(const int64_t *in, int64_t S, const int64_t *tile_off, int64_t *out);
 __global__ void k_compact(const int64_t *stage_off, const int64_t *seg_count, const int64_t *out_off,
                           const uint64_t *st_key, const double *st_coef, int n, int bits,
                           uint8_t *out_exps, double *out_coefs, int64_t capacity, int32_t *status);
@@ -104,17 +109,33 @@ __global__ void k_mul_rowptr(const int64_t *out_off, const int64_t *pb_start, in
 
 // ---------------------------------------------------------------- derivatives
 constexpr int JAC_THREADS = 256;
-__global__ void k_jac_count(const int64_t *rp, const uint8_t *exps, int n, int64_t *counts);
-__global__ void k_jac_write(const int64_t *rp, const uint8_t *exps, const double *coefs, int n,
-                            const int64_t *out_rp, uint8_t *out_exps, double *out_coefs, int64_t capacity,
-                            int32_t *status, int32_t overflow_code);
-constexpr int HES_PAIRS_PER_BLOCK = 64;
-// Hessian pair batch [pair_base, pair_base + nb): formed polynomial p * nb + (pair - pair_base)
-__global__ void k_hes_count(const int64_t *rp, const uint8_t *exps, int n, int64_t pair_base, int64_t nb,
-                            const uint32_t *pair_jk, int64_t *counts);
-__global__ void k_hes_write(const int64_t *rp, const uint8_t *exps, const double *coefs, int n, int64_t pair_base,
-                            int64_t nb, const uint32_t *pair_jk, const int64_t *out_rp, uint8_t *out_exps,
-                            double *out_coefs, int64_t capacity, int32_t *status);
+constexpr int DF_MAX_GROUPS = 256;       // groups (variables or pairs) per formation pass
+
+struct FormArgs {
+    const int64_t *rp;          // [P+1] source CSR
+    const uint8_t *exps;
+    const double *coefs;
+    int n;
+    int mode;                   // 0: jacobian (group = variable), 1: hessian pair batch
+    int64_t ngroups;            // n, or the pairs in this batch
+    int64_t pair_base;
+    const uint32_t *pair_jk;
+    const int64_t *item_start;  // [P+1] first work item of each source polynomial
+    int64_t P;
+    int64_t chunk;              // source terms per work item
+    int64_t *cnt;               // per p: [group][chunk] survivor counts
+    int64_t *out_rp;            // [P*ngroups + 1]
+    uint8_t *out_exps;
+    double *out_coefs;
+    int64_t capacity;
+    int32_t *status;
+    int32_t overflow_code;
+};
+
+__global__ void k_item_count(const int64_t *rp, int64_t P, int64_t chunk, int64_t *items);
+__global__ void k_form_count(FormArgs A);
+__global__ void k_form_rowptr(FormArgs A, const int64_t *off);
+__global__ void k_form_write(FormArgs A, const int64_t *off);
 __global__ void k_pair_table(int n, uint32_t *pair_jk);
 
 // ----------------------------------------------------------------- sparse eval
@@ -139,8 +160,13 @@ struct EvalArgs {
     int64_t term_limit;           // terms at or beyond this index are never read
 };
 
-__global__ void k_encode_support(const uint8_t *exps, int64_t T, int n, uint64_t *enc);
-__global__ void k_eval_blocks(EvalArgs A, const uint64_t *enc);
+__global__ void k_encode_support(const uint8_t *exps, int64_t T, int n, uint64_t *enc, const int64_t *used);
+template <int XMODE>
+__global__ void k_eval_terms(EvalArgs A, const uint64_t *enc, double *partial, int64_t S);
+__global__ void k_eval_reduce(EvalArgs A, const double *partial, int64_t S);
+constexpr int64_t EV_TARGET_BLOCKS = 2048;   // blocks wanted before polynomials are cut into segments
+constexpr int64_t EV_MIN_SEGMENT = 512;      // fewest terms per segment
+constexpr int64_t EV_MAX_SEGMENTS = 64;
 
 __global__ void k_backward_dx(const double *G, const double *gY, int64_t P, int64_t N, int n, double *dX);
 constexpr int BWC_THREADS = 256;

@@ -315,6 +315,45 @@ __global__ void __launch_bounds__(1024) k_scan_counts(const int64_t *counts, int
     if (threadIdx.x == 0) out[S] = run;
 }
 
+// Multi-block exclusive scan for long count arrays: tile sums, one
+// k_scan_counts over the sums, then each tile rescans itself from its offset.
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_tile_sums(const int64_t *in, int64_t S, int64_t *sums)
+{
+    __shared__ int64_t s_scan[SCAN_THREADS / kWave];
+    const int64_t t0 = (int64_t)blockIdx.x * SCAN_TILE;
+    int64_t v = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int64_t i = t0 + (int64_t)k * SCAN_THREADS + threadIdx.x;
+        if (i < S) v += in[i];
+    }
+    const int64_t tot = block_sum<SCAN_THREADS>(v, s_scan);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_tile_apply(const int64_t *in, int64_t S,
+                                                                  const int64_t *tile_off, int64_t *out)
+{
+    __shared__ int64_t s_scan[SCAN_THREADS / kWave];
+    const int64_t t0 = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int64_t v[SCAN_ITEMS];
+    int64_t loc = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int64_t i = t0 + k;
+        v[k] = i < S ? in[i] : 0;
+        loc += v[k];
+    }
+    int64_t tot;
+    int64_t run = tile_off[blockIdx.x] + block_exclusive_scan<SCAN_THREADS>(loc, s_scan, tot);
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int64_t i = t0 + k;
+        if (i < S) out[i] = run;
+        run += v[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[S] = tile_off[gridDim.x];
+}
+
 // One block per segment: staged (key, coef) -> CSR output rows.  A segment's
 // output rows are contiguous, so its exponent bytes form one contiguous
 // range; the block writes that range as aligned 32-bit words (each byte
