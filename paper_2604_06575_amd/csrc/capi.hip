@@ -16,7 +16,7 @@ namespace polyhip {
 namespace {
 std::atomic<int64_t> g_mul_bucket_terms{MB_TARGET};
 std::atomic<int64_t> g_seg_blocks_per_cu{2};
-std::atomic<int64_t> g_eval_blocks_per_cu{8};
+std::atomic<int64_t> g_eval_blocks_per_cu{16};
 
 struct TuneEntry {
     const char *name;
@@ -245,12 +245,12 @@ struct EvalPlan {
 
 // Segments per polynomial for the term-streaming kernel: polynomials are cut
 // into term segments only when there are too few (polynomial, point block)
-// pairs to fill the machine.  Depends on sizes only (workspace queries call
-// it too).
+// pairs to give every wave of a full machine its own unit.  Depends on sizes
+// only (workspace queries call it too).
 inline int64_t eval_segments(int64_t Q, int64_t N, int64_t T)
 {
     if (Q <= 0 || N <= 0) return 1;
-    const int64_t units = ceil_div(EV_TARGET_BLOCKS, ceil_div(N, kWave));
+    const int64_t units = ceil_div(EV_TARGET_WAVES, ceil_div(N, kWave));
     if (Q >= units) return 1;
     int64_t S = ceil_div(units, Q);
     S = std::min<int64_t>(S, std::max<int64_t>(1, T / (Q * EV_MIN_SEGMENT)));
@@ -259,22 +259,16 @@ inline int64_t eval_segments(int64_t Q, int64_t N, int64_t T)
 
 inline size_t eval_partial_bytes(int64_t Q, int64_t N, int64_t S) { return S > 1 ? (size_t)(8 * S * Q * N) : 0; }
 
-void launch_eval_blocks(const EvalArgs &A, const uint64_t *enc, double *partial, int64_t S, hipStream_t s)
+void launch_eval_blocks(const EvalArgs &A, const uint32_t *enc, double *partial, int64_t S, hipStream_t s)
 {
     if (A.Q <= 0 || A.N <= 0) return;
     const unsigned gx = (unsigned)ceil_div(A.N, kWave);
-    // enough blocks to fill the machine several times over, each looping
-    // over work units
+    // eval_blocks_per_cu workgroups per CU, each looping over work units, so
+    // that the block's points are staged in LDS once for many polynomials
     const int64_t want = std::max<int64_t>(1, ((int64_t)device_cus() * tunables().eval_blocks_per_cu + gx - 1) / gx);
-    const unsigned gy = (unsigned)std::min<int64_t>(std::min<int64_t>(A.Q * S, want * 4), 65535);
-    if (A.n <= 16) {
-        hipLaunchKernelGGL(k_eval_terms<16>, dim3(gx, gy), dim3(EV_THREADS), 0, s, A, enc, partial, S);
-    } else if (A.n <= 32) {
-        hipLaunchKernelGGL(k_eval_terms<32>, dim3(gx, gy), dim3(EV_THREADS), 0, s, A, enc, partial, S);
-    } else {
-        const size_t lds = (size_t)A.n * kWave * sizeof(double);
-        hipLaunchKernelGGL(k_eval_terms<0>, dim3(gx, gy), dim3(EV_THREADS), lds, s, A, enc, partial, S);
-    }
+    const unsigned gy = (unsigned)std::min<int64_t>(std::min<int64_t>(ceil_div(A.Q * S, EV_WAVES), want), 65535);
+    const size_t lds = (size_t)(A.n + 1) * kWave * sizeof(double);
+    hipLaunchKernelGGL(k_eval_terms, dim3(gx, gy), dim3(EV_THREADS), lds, s, A, enc, partial, S);
     if (S > 1) hipLaunchKernelGGL(k_eval_reduce, dim3(grid1(A.Q * A.N, 256)), dim3(256), 0, s, A, partial, S);
 }
 
@@ -298,22 +292,26 @@ void launch_scan(const int64_t *in, int64_t S, int64_t *out, int64_t *tmp, hipSt
 }
 
 // Derivative formation over (polynomial, chunk) work items.  The chunk size
-// depends on the total term count only, so workspace queries need no device.
+// depends on the term count only, so workspace queries need no device.
 struct FormPlan {
-    int64_t chunk = 0, W = 0, G = 0;
+    int64_t chunk = 0, W = 0, G = 0, P = 0;
+    bool bounded = false;   // W is an upper bound (source sizes known only on the device)
     size_t items = 0, item_start = 0, cnt = 0, off = 0, tmp = 0;
 };
 
-FormPlan plan_form(const poly_csr *f, int64_t G, Layout &L)
+inline int64_t form_chunk(int64_t T)
+{
+    return std::min<int64_t>(4096, std::max<int64_t>(256, align_up(ceil_div(T, 2048), 256)));
+}
+
+FormPlan plan_form_sized(int64_t P, int64_t T, int64_t W, bool bounded, int64_t G, Layout &L)
 {
     FormPlan fp;
-    const int64_t P = f->npolys, T = total_terms(f);
+    fp.P = P;
     fp.G = G;
-    fp.chunk = std::min<int64_t>(4096, std::max<int64_t>(256, align_up(ceil_div(T, 2048), 256)));
-    for (int64_t p = 0; p < P; ++p) {
-        const int64_t tp = f->row_ptr_host[p + 1] - f->row_ptr_host[p];
-        fp.W += tp <= 0 ? 1 : ceil_div(tp, fp.chunk);
-    }
+    fp.chunk = form_chunk(T);
+    fp.W = W;
+    fp.bounded = bounded;
     fp.items = L.take(8 * P);
     fp.item_start = L.take(8 * (P + 1));
     fp.cnt = L.take(8 * fp.W * G);
@@ -322,17 +320,40 @@ FormPlan plan_form(const poly_csr *f, int64_t G, Layout &L)
     return fp;
 }
 
-// Forms the G polynomials of every source polynomial (A's mode, pair batch,
+// Source polynomials with sizes known on the host.
+FormPlan plan_form(const poly_csr *f, int64_t G, Layout &L)
+{
+    const int64_t P = f->npolys, T = total_terms(f);
+    const int64_t chunk = form_chunk(T);
+    int64_t W = 0;
+    for (int64_t p = 0; p < P; ++p) {
+        const int64_t tp = f->row_ptr_host[p + 1] - f->row_ptr_host[p];
+        W += tp <= 0 ? 1 : ceil_div(tp, chunk);
+    }
+    return plan_form_sized(P, T, W, false, G, L);
+}
+
+// Source polynomials formed on the device: at most T_bound terms in P polys.
+FormPlan plan_form_bound(int64_t P, int64_t T_bound, int64_t G, Layout &L)
+{
+    return plan_form_sized(P, T_bound, P + ceil_div(T_bound, form_chunk(T_bound)), true, G, L);
+}
+
+// Forms the G polynomials of every source polynomial (mode, coefficient rule,
 // outputs and capacity set by the caller) with out_rp of P*G + 1 entries.
 void run_form(const FormPlan &fp, FormArgs A, void *ws, hipStream_t s)
 {
     int64_t *items = at<int64_t>(ws, fp.items);
     int64_t *tmp = at<int64_t>(ws, fp.tmp);
+    A.P = fp.P;
     A.item_start = at<int64_t>(ws, fp.item_start);
     A.cnt = at<int64_t>(ws, fp.cnt);
     A.chunk = fp.chunk;
     A.ngroups = fp.G;
     int64_t *off = at<int64_t>(ws, fp.off);
+    // with a bounded grid the counts past the real work items are never
+    // written: clear them so the scan reads defined values
+    if (fp.bounded) clear_u64((unsigned long long *)A.cnt, fp.W * fp.G, s);
     hipLaunchKernelGGL(k_item_count, dim3(grid1(A.P, 256)), dim3(256), 0, s, A.rp, A.P, fp.chunk, items);
     launch_scan(items, A.P, const_cast<int64_t *>(A.item_start), tmp, s);
     hipLaunchKernelGGL(k_form_count, dim3((unsigned)fp.W), dim3(JAC_THREADS), 0, s, A);
@@ -347,7 +368,7 @@ void ensure_lds_attrs()
 {
     std::lock_guard<std::mutex> g(lds_mu);
     if (lds_attr_done) return;
-    (void)hipFuncSetAttribute((const void *)k_eval_terms<0>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
+    (void)hipFuncSetAttribute((const void *)k_eval_terms, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
     (void)hipFuncSetAttribute((const void *)k_backward_dc, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
     (void)hipFuncSetAttribute((const void *)k_mul_buckets_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)MB_LDS_LIMIT);
@@ -359,18 +380,8 @@ void ensure_lds_attrs()
 // entries (j <= k).  Terms beyond that are still handled; if the formed
 // polynomials outgrow the workspace the device reports POLY_ERR_WORKSPACE.
 inline int64_t grad_terms_bound(int64_t T, int n) { return T * std::min<int64_t>(n, 8); }
-constexpr int64_t HESS_BATCH = 256;   // pairs formed and evaluated per pass
 inline int64_t hess_terms_bound(int64_t T, int64_t nb) { return T * std::min<int64_t>(nb, 36); }
 
-// Segment partials for the Hessian passes: the largest over the full batches
-// and the last, possibly smaller, one.
-inline size_t hess_partial_bytes(int64_t P, int64_t N, int64_t T, int64_t npairs, int64_t nbmax)
-{
-    const int64_t nlast = npairs - (npairs - 1) / nbmax * nbmax;
-    const size_t a = eval_partial_bytes(P * nbmax, N, eval_segments(P * nbmax, N, T));
-    const size_t b = eval_partial_bytes(P * nlast, N, eval_segments(P * nlast, N, T));
-    return std::max(a, b);
-}
 
 struct GradPlan {
     FormPlan form;
@@ -394,16 +405,17 @@ GradPlan plan_grad(const poly_csr *f, int64_t N, Layout &L)
     return g;
 }
 
-FormArgs form_args(const poly_csr *f, int mode, int32_t *status, int32_t overflow_code)
+FormArgs form_args(const int64_t *rp, const uint8_t *exps, const double *coefs, int n, int mode, int keep_coefs,
+                   int32_t *status, int32_t overflow_code)
 {
     FormArgs A;
     memset(&A, 0, sizeof(A));
-    A.rp = f->row_ptr;
-    A.exps = f->exps;
-    A.coefs = f->coefs;
-    A.n = f->nvars;
+    A.rp = rp;
+    A.exps = exps;
+    A.coefs = coefs;
+    A.n = n;
     A.mode = mode;
-    A.P = f->npolys;
+    A.keep_coefs = keep_coefs;
     A.status = status;
     A.overflow_code = overflow_code;
     return A;
@@ -418,14 +430,14 @@ poly_status run_grad(const poly_csr *f, const double *X, int64_t N, double *G, v
     int64_t *jrp = at<int64_t>(ws, g.jrp);
     uint8_t *jexps = at<uint8_t>(ws, g.jexps);
     double *jcoefs = at<double>(ws, g.jcoefs);
-    uint64_t *jenc = at<uint64_t>(ws, g.jenc);
-    FormArgs F = form_args(f, 0, status, (int32_t)POLY_ERR_WORKSPACE);
+    uint32_t *jenc = at<uint32_t>(ws, g.jenc);
+    FormArgs F = form_args(f->row_ptr, f->exps, f->coefs, n, 0, 0, status, (int32_t)POLY_ERR_WORKSPACE);
     F.out_rp = jrp;
     F.out_exps = jexps;
     F.out_coefs = jcoefs;
     F.capacity = g.cap;
     run_form(g.form, F, ws, s);
-    hipLaunchKernelGGL(k_encode_support, dim3(grid1(g.cap, 256)), dim3(256), 0, s, jexps, g.cap, n, jenc,
+    hipLaunchKernelGGL(k_encode_factors, dim3(grid1(g.cap, 256)), dim3(256), 0, s, jexps, g.cap, n, jenc,
                        (const int64_t *)(jrp + P * n));
     LAUNCH_CHECK();
     EvalArgs A;
@@ -698,7 +710,7 @@ poly_status poly_jacobian(const poly_csr *in, poly_csr *out, void *ws, size_t ws
         LAUNCH_CHECK();
         return POLY_OK;
     }
-    FormArgs F = form_args(in, 0, status, (int32_t)POLY_ERR_CAPACITY);
+    FormArgs F = form_args(in->row_ptr, in->exps, in->coefs, n, 0, 0, status, (int32_t)POLY_ERR_CAPACITY);
     F.out_rp = out->row_ptr;
     F.out_exps = out->exps;
     F.out_coefs = out->coefs;
@@ -749,8 +761,8 @@ poly_status poly_eval(const poly_csr *f, const double *X, int64_t N, double *Y, 
         LAUNCH_CHECK();
         return POLY_OK;
     }
-    uint64_t *enc = at<uint64_t>(ws, o_enc);
-    if (T > 0) hipLaunchKernelGGL(k_encode_support, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, f->nvars, enc,
+    uint32_t *enc = at<uint32_t>(ws, o_enc);
+    if (T > 0) hipLaunchKernelGGL(k_encode_factors, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, f->nvars, enc,
                                   (const int64_t *)nullptr);
     EvalArgs A;
     memset(&A, 0, sizeof(A));
@@ -798,24 +810,43 @@ poly_status poly_grad(const poly_csr *f, const double *X, int64_t N, double *G, 
     return run_grad(f, X, N, G, ws, g, s);
 }
 
+// Hessian: the Jacobian with original coefficients, then the entries (j, k),
+// j <= k, formed from it (mode 1), encoded and evaluated in one pass.
+struct HessPlan {
+    FormPlan jform, hform;
+    size_t jrp, jexps, jcoefs, hrp, hexps, hcoefs, henc, part;
+    int64_t jcap, hcap, S;
+};
+
+HessPlan plan_hess(const poly_csr *f, int64_t N, Layout &L)
+{
+    HessPlan h;
+    const int n = f->nvars;
+    const int64_t P = f->npolys, T = total_terms(f);
+    const int64_t npairs = (int64_t)n * (n + 1) / 2;
+    h.jcap = grad_terms_bound(T, n);
+    h.hcap = hess_terms_bound(T, npairs);
+    h.jform = plan_form(f, n, L);
+    h.jrp = L.take(8 * (P * n + 1));
+    h.jexps = L.take((size_t)h.jcap * n);
+    h.jcoefs = L.take(8 * h.jcap);
+    h.hform = plan_form_bound(P * n, h.jcap, n, L);
+    h.hrp = L.take(8 * (P * n * n + 1));
+    h.hexps = L.take((size_t)h.hcap * n);
+    h.hcoefs = L.take(8 * h.hcap);
+    h.henc = L.take(16 * h.hcap);
+    h.S = eval_segments(P * n * n, N, T);
+    h.part = L.take(eval_partial_bytes(P * n * n, N, h.S));
+    return h;
+}
+
 poly_status poly_hess_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)
 {
     poly_status st = check_eval(f, nullptr, 0, nullptr);
     if (st != POLY_OK) return st;
     if (!ws_bytes || N < 0) return POLY_ERR_ARG;
-    const int n = f->nvars;
-    const int64_t P = f->npolys, T = total_terms(f);
-    const int64_t npairs = (int64_t)n * (n + 1) / 2;
-    const int64_t nb = std::min<int64_t>(npairs, HESS_BATCH);
-    const int64_t cap = hess_terms_bound(T, nb);
     Layout L;
-    L.take(4 * npairs);
-    plan_form(f, nb, L);
-    L.take(8 * (P * nb + 1));
-    L.take((size_t)cap * n);
-    L.take(8 * cap);
-    L.take(16 * cap);
-    L.take(hess_partial_bytes(P, N, T, npairs, nb));
+    plan_hess(f, N, L);
     *ws_bytes = L.total();
     return POLY_OK;
 }
@@ -826,18 +857,9 @@ poly_status poly_hess(const poly_csr *f, const double *X, int64_t N, double *H, 
     poly_status st = check_eval(f, X, N, H);
     if (st != POLY_OK) return st;
     const int n = f->nvars;
-    const int64_t P = f->npolys, T = total_terms(f);
-    const int64_t npairs = (int64_t)n * (n + 1) / 2;
-    const int64_t nbmax = std::min<int64_t>(npairs, HESS_BATCH);
-    const int64_t cap = hess_terms_bound(T, nbmax);
+    const int64_t P = f->npolys;
     Layout L;
-    const size_t o_pairs = L.take(4 * npairs);
-    const FormPlan fmax = plan_form(f, nbmax, L);
-    const size_t o_rp = L.take(8 * (P * nbmax + 1));
-    const size_t o_exps = L.take((size_t)cap * n);
-    const size_t o_coefs = L.take(8 * cap);
-    const size_t o_enc = L.take(16 * cap);
-    const size_t o_part = L.take(hess_partial_bytes(P, N, T, npairs, nbmax));
+    const HessPlan h = plan_hess(f, N, L);
     if (!ws || ws_bytes < L.total()) return POLY_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     ensure_lds_attrs();
@@ -847,44 +869,41 @@ poly_status poly_hess(const poly_csr *f, const double *X, int64_t N, double *H, 
         LAUNCH_CHECK();
         return POLY_OK;
     }
-    uint32_t *pairs = at<uint32_t>(ws, o_pairs);
-    int64_t *hrp = at<int64_t>(ws, o_rp);
-    uint8_t *hexps = at<uint8_t>(ws, o_exps);
-    double *hcoefs = at<double>(ws, o_coefs);
-    uint64_t *henc = at<uint64_t>(ws, o_enc);
-    hipLaunchKernelGGL(k_pair_table, dim3(grid1(n, 256)), dim3(256), 0, s, n, pairs);
-    for (int64_t pb0 = 0; pb0 < npairs; pb0 += nbmax) {
-        const int64_t nb = std::min<int64_t>(nbmax, npairs - pb0);
-        FormPlan fp = fmax;   // the last batch may be smaller: same layout, fewer groups
-        fp.G = nb;
-        FormArgs F = form_args(f, 1, status, (int32_t)POLY_ERR_WORKSPACE);
-        F.pair_base = pb0;
-        F.pair_jk = pairs;
-        F.out_rp = hrp;
-        F.out_exps = hexps;
-        F.out_coefs = hcoefs;
-        F.capacity = cap;
-        run_form(fp, F, ws, s);
-        hipLaunchKernelGGL(k_encode_support, dim3(grid1(cap, 256)), dim3(256), 0, s, hexps, cap, n, henc,
-                           (const int64_t *)(hrp + P * nb));
-        EvalArgs A;
-        memset(&A, 0, sizeof(A));
-        A.rp = hrp;
-        A.exps = hexps;
-        A.coefs = hcoefs;
-        A.n = n;
-        A.X = X;
-        A.N = N;
-        A.Q = P * nb;
-        A.mode = OUT_HESS;
-        A.pair_base = pb0;
-        A.pairs_in_batch = nb;
-        A.pair_jk = pairs;
-        A.Y = H;
-        A.term_limit = cap;
-        launch_eval_blocks(A, henc, at<double>(ws, o_part), eval_segments(P * nb, N, T), s);
-        LAUNCH_CHECK();
-    }
+    int64_t *jrp = at<int64_t>(ws, h.jrp);
+    uint8_t *jexps = at<uint8_t>(ws, h.jexps);
+    double *jcoefs = at<double>(ws, h.jcoefs);
+    int64_t *hrp = at<int64_t>(ws, h.hrp);
+    uint8_t *hexps = at<uint8_t>(ws, h.hexps);
+    double *hcoefs = at<double>(ws, h.hcoefs);
+    uint32_t *henc = at<uint32_t>(ws, h.henc);
+    FormArgs J = form_args(f->row_ptr, f->exps, f->coefs, n, 0, 1, status, (int32_t)POLY_ERR_WORKSPACE);
+    J.out_rp = jrp;
+    J.out_exps = jexps;
+    J.out_coefs = jcoefs;
+    J.capacity = h.jcap;
+    run_form(h.jform, J, ws, s);
+    FormArgs F = form_args(jrp, jexps, jcoefs, n, 1, 0, status, (int32_t)POLY_ERR_WORKSPACE);
+    F.out_rp = hrp;
+    F.out_exps = hexps;
+    F.out_coefs = hcoefs;
+    F.capacity = h.hcap;
+    run_form(h.hform, F, ws, s);
+    hipLaunchKernelGGL(k_encode_factors, dim3(grid1(h.hcap, 256)), dim3(256), 0, s, hexps, h.hcap, n, henc,
+                       (const int64_t *)(hrp + P * n * n));
+    EvalArgs A;
+    memset(&A, 0, sizeof(A));
+    A.rp = hrp;
+    A.exps = hexps;
+    A.coefs = hcoefs;
+    A.n = n;
+    A.X = X;
+    A.N = N;
+    A.Q = P * n * n;
+    A.mode = OUT_HESS;
+    A.Y = H;
+    A.term_limit = h.hcap;
+    launch_eval_blocks(A, henc, at<double>(ws, h.part), h.S, s);
+    LAUNCH_CHECK();
     return POLY_OK;
 }
 

@@ -1,17 +1,18 @@
 // Symbolic derivatives and sparse term-streaming evaluation.
 //
 //  * diff / jacobian (Section 3.3): a term with e_j > 0 becomes
-//    (e - u_j, c * e_j), order preserved.  One workgroup per entry ranks the
-//    surviving terms of each variable with wavefront ballots, so the output
-//    keeps storage order without any sort.
-//  * Hessian entries (jacobian(jacobian(p))): the (j, k) entry, j <= k, is the
-//    polynomial with coefficient c * m, m = e_j (e_k - [j == k]) formed as an
-//    integer first; it is evaluated once and stored to both (j, k) and (k, j).
+//    (e - u_j, c * e_j), order preserved.  Work items of (polynomial, term
+//    chunk) rank the surviving terms of each variable with wavefront ballots,
+//    so the output keeps storage order without any sort.
+//  * Hessian entries (jacobian(jacobian(p))): the (j, k) entry, j <= k, is
+//    formed from the Jacobian with coefficient c * m, m = e_j (e_k - [j == k])
+//    taken as an integer first; it is evaluated once and stored to both (j, k)
+//    and (k, j).
 //  * evaluation (Section 3.3, p.eval(x0)): points in lanes, terms streamed
-//    wave-uniformly.  Each term's support is pre-encoded as up to eight
-//    (variable, exponent) pairs in 16 bytes, read with scalar loads; the
-//    lane's point coordinates sit in LDS; x^e is formed by repeated
-//    multiplication.  The waves of a workgroup share 64 points and split a
+//    wave-uniformly.  Each term is pre-encoded as the list of its factors
+//    (variable indices with repetition, 16 bytes); the lane's point
+//    coordinates sit in LDS, and a monomial is the left-to-right product of
+//    its factors.  The waves of a workgroup share 64 points and split a
 //    polynomial's terms; their partial sums are added in a fixed order.
 #include "kernels.h"
 
@@ -19,9 +20,14 @@ namespace polyhip {
 
 // ------------------------------------------------- derivative formation
 //
-// Formed polynomial (p, g): group g of source polynomial p -- variable j for
-// the Jacobian, pair (j, k) of the current pair batch for the Hessian.  The
-// terms of p are cut into chunks of A.chunk terms; work item (p, chunk) counts,
+// Formed polynomial (p, g): group g of source polynomial p.  Mode 0 forms
+// d/dx_g of every source polynomial (the Jacobian).  Mode 1 takes as source
+// the Jacobian of f, formed with the original coefficients kept, where source
+// polynomial p = (r, j) holds d/dx_j f_r; group g = k >= j forms the Hessian
+// entry (j, k) with the multiplier e_j (e_k - [j = k]) of the original term,
+// recovered from the Jacobian row as (e'_j + 1) e'_k, so the coefficient is
+// rounded once, as in a direct second derivative.  The terms of p are cut into
+// chunks of A.chunk terms; work item (p, chunk) counts,
 // for every group, how many of its terms survive (wavefront ballots), the
 // counts laid out per p as [group][chunk] are scanned into output offsets, and
 // the same item writes its survivors in term order.  So every formed
@@ -41,18 +47,13 @@ __device__ inline int64_t item_poly(const int64_t *item_start, int64_t P, int64_
     return lo;
 }
 
-// multiplier of term row `row` in group g (0 = term vanishes)
-__device__ inline int group_mult(const FormArgs &A, const uint8_t *row, int64_t g, int &j, int &k)
+// multiplier of term row `row` of source polynomial p in group g (0 = the
+// term vanishes); the formed row is `row` with exponent g decremented
+__device__ inline int group_mult(const FormArgs &A, const uint8_t *row, int64_t p, int64_t g)
 {
-    if (A.mode == 0) {
-        j = (int)g;
-        k = -1;
-        return row[j];
-    }
-    const uint32_t jk = A.pair_jk[A.pair_base + g];
-    j = (int)(jk >> 16);
-    k = (int)(jk & 0xffff);
-    return (int)row[j] * ((int)row[k] - (j == k ? 1 : 0));
+    if (A.mode == 0) return row[g];
+    const int jj = (int)(p % A.n);
+    return g >= jj ? ((int)row[jj] + 1) * (int)row[g] : 0;
 }
 
 }  // namespace
@@ -84,8 +85,7 @@ __global__ void __launch_bounds__(JAC_THREADS) k_form_count(FormArgs A)
         const int64_t t = c0 + threadIdx.x;
         const uint8_t *row = A.exps + (base + t) * A.n;
         for (int64_t g = 0; g < A.ngroups; ++g) {
-            int j, k;
-            const int m = t < t1 ? group_mult(A, row, g, j, k) : 0;
+            const int m = t < t1 ? group_mult(A, row, p, g) : 0;
             const unsigned long long bal = __ballot(m > 0);
             if (lane_id() == 0) s_wc[w][g] += __popcll(bal);
         }
@@ -132,6 +132,7 @@ __global__ void __launch_bounds__(JAC_THREADS) k_form_write(FormArgs A, const in
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t cb = A.item_start[p] * A.ngroups;
     const int n = A.n;
+    const bool words = (n & 3) == 0 && ((reinterpret_cast<uintptr_t>(A.exps) | reinterpret_cast<uintptr_t>(A.out_exps)) & 3) == 0;
     for (int64_t g = threadIdx.x; g < A.ngroups; g += JAC_THREADS) s_run[g] = off[cb + g * nch + chunk];
     __syncthreads();
     for (int64_t c0 = t0; c0 < t1; c0 += JAC_THREADS) {
@@ -139,26 +140,33 @@ __global__ void __launch_bounds__(JAC_THREADS) k_form_write(FormArgs A, const in
         const bool valid = t < t1;
         const uint8_t *row = A.exps + (base + t) * n;
         for (int64_t g = 0; g < A.ngroups; ++g) {
-            int j, k;
-            const int m = valid ? group_mult(A, row, g, j, k) : 0;
+            const int m = valid ? group_mult(A, row, p, g) : 0;
             const unsigned long long bal = __ballot(m > 0);
             if (lane == 0) s_wc[w][g] = __popcll(bal);
         }
         __syncthreads();
         const double c = valid ? A.coefs[base + t] : 0.0;
         for (int64_t g = 0; g < A.ngroups; ++g) {
-            int j = 0, k = -1;
-            const int m = valid ? group_mult(A, row, g, j, k) : 0;
+            const int j = (int)g;
+            const int m = valid ? group_mult(A, row, p, g) : 0;
             const unsigned long long bal = __ballot(m > 0);
             if (m > 0) {
                 int64_t o = s_run[g] + __popcll(bal & lt);
                 for (int q = 0; q < w; ++q) o += s_wc[q][g];
                 if (o < A.capacity) {
                     uint8_t *orow = A.out_exps + o * n;
-                    for (int v = 0; v < n; ++v) orow[v] = row[v];
-                    orow[j] = (uint8_t)(orow[j] - 1);
-                    if (k >= 0) orow[k] = (uint8_t)(orow[k] - 1);
-                    A.out_coefs[o] = c * (double)m;
+                    if (words) {   // 4-byte rows: copy words, decrement byte j in place (it is >= 1)
+                        const uint32_t *r32 = reinterpret_cast<const uint32_t *>(row);
+                        uint32_t *o32 = reinterpret_cast<uint32_t *>(orow);
+                        for (int v = 0; v < (n >> 2); ++v) {
+                            uint32_t x = r32[v];
+                            if (v == (j >> 2)) x -= 1u << (8 * (j & 3));
+                            o32[v] = x;
+                        }
+                    } else {
+                        for (int v = 0; v < n; ++v) orow[v] = (uint8_t)(row[v] - (v == j ? 1 : 0));
+                    }
+                    A.out_coefs[o] = A.keep_coefs ? c : c * (double)m;
                 } else {
                     set_status(A.status, A.overflow_code);
                 }
@@ -174,15 +182,6 @@ __global__ void __launch_bounds__(JAC_THREADS) k_form_write(FormArgs A, const in
     }
 }
 
-// ------------------------------------------------------------------- hessian
-
-__global__ void k_pair_table(int n, uint32_t *pair_jk)
-{
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    int idx = j * n - (j * (j - 1)) / 2;   // pairs before row j: sum_{r<j} (n - r)
-    for (int k = j; k < n; ++k) pair_jk[idx++] = ((uint32_t)j << 16) | (uint32_t)k;
-}
 
 // ---------------------------------------------------------- support encoding
 
@@ -210,6 +209,35 @@ __global__ void k_encode_support(const uint8_t *exps, int64_t T, int n, uint64_t
     }
     enc[2 * t] = w[0];
     enc[2 * t + 1] = w[1];
+}
+
+// Factor-list encoding for the term-streaming evaluator: a term of total
+// degree d <= EV_MAX_DEG is the list of its d variable indices with
+// repetition, in variable order (x1^2 x3 -> 0, 0, 2), bytes 0..11, the rest
+// of the list padded with n (an LDS row of ones); byte 12 holds d.  A term of
+// higher degree has byte 12 = 0xFF and is evaluated from its dense row.
+__global__ void k_encode_factors(const uint8_t *exps, int64_t T, int n, uint32_t *enc, const int64_t *used)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T || (used && t >= *used)) return;
+    const uint8_t *row = exps + t * n;
+    uint32_t w[4] = {0, 0, 0, 0};
+    int d = 0;
+    for (int i = 0; i < n && d <= EV_MAX_DEG; ++i) {
+        for (uint32_t e = row[i]; e > 0 && d <= EV_MAX_DEG; --e) {
+            if (d < EV_MAX_DEG) w[d >> 2] |= (uint32_t)i << (8 * (d & 3));
+            ++d;
+        }
+    }
+    if (d > EV_MAX_DEG) {
+        w[0] = w[1] = w[2] = 0;
+        w[3] = 0xFFu;
+    } else {
+        for (int k = d; k < EV_MAX_DEG; ++k) w[k >> 2] |= (uint32_t)n << (8 * (k & 3));
+        w[3] = (uint32_t)d;
+    }
+    uint4 *o = reinterpret_cast<uint4 *>(enc) + t;
+    *o = make_uint4(w[0], w[1], w[2], w[3]);
 }
 
 // ------------------------------------------------------------- evaluation
@@ -256,11 +284,10 @@ __device__ inline void store_out(const EvalArgs &A, int64_t q, int64_t pt, doubl
     } else if (A.mode == OUT_GRAD) {
         const int64_t p = q / A.n, j = q % A.n;
         A.Y[(p * A.N + pt) * A.n + j] = y;
-    } else {
-        const int64_t p = q / A.pairs_in_batch;
-        const int64_t pi = A.pair_base + q % A.pairs_in_batch;
-        const uint32_t jk = A.pair_jk[pi];
-        const int64_t j = jk >> 16, k = jk & 0xffff;
+    } else {   // q = (p * n + j) * n + k; entries k < j are written by their mirror
+        const int64_t k = q % A.n, pj = q / A.n;
+        const int64_t j = pj % A.n, p = pj / A.n;
+        if (k < j) return;
         const int64_t b = (p * A.N + pt) * A.n;
         A.Y[(b + j) * A.n + k] = y;
         if (j != k) A.Y[(b + k) * A.n + j] = y;
@@ -271,114 +298,78 @@ __device__ inline void store_out(const EvalArgs &A, int64_t q, int64_t pt, doubl
 
 namespace {
 
-// Term data is read through the constant address space: the addresses are
-// wave-uniform and the arrays are not written during the launch, so the loads
-// become scalar loads into SGPRs.
-typedef const __attribute__((address_space(4))) uint64_t cu64;
-typedef const __attribute__((address_space(4))) double cf64;
-typedef double xvec16 __attribute__((ext_vector_type(16)));
-
-// The lane's point coordinates, held in VGPRs and read with a wave-uniform
-// index (indexed register moves).
-struct PointRegs16 {
-    xvec16 a;
-    __device__ void load(const double *x, int n)
-    {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) a[i] = i < n ? x[i] : 0.0;
-    }
-    __device__ double get(uint32_t i) const { return a[i & 15]; }
-};
-
-struct PointRegs32 {
-    xvec16 a, b;
-    __device__ void load(const double *x, int n)
-    {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            a[i] = i < n ? x[i] : 0.0;
-            b[i] = 16 + i < n ? x[16 + i] : 0.0;
-        }
-    }
-    __device__ double get(uint32_t i) const
-    {
-        double v;
-        if (i < 16) v = a[i];
-        else v = b[i & 15];
-        return v;
-    }
-};
-
-// The block's points in LDS, variable-major (n > 32).
-struct PointLds {
-    const double *s;
-    __device__ double get(uint32_t i) const { return s[i * kWave]; }
-};
-
-template <class XS>
-__device__ inline double monomial(uint64_t w0, uint64_t w1, const XS &xs, const uint8_t *row, int n)
+// Monomial from its dense exponent row (terms of degree > EV_MAX_DEG).
+__device__ inline double monomial_dense(const uint8_t *row, int n, const double *xl)
 {
     double v = 1.0;
-    if ((w0 & 0xffffull) == 0xffffull) {   // more than eight factors: dense row
-        for (int i = 0; i < n; ++i) {
-            const uint32_t e = row[i];
-            if (e) v = v * powi(xs.get((uint32_t)i), e);
-        }
-        return v;
-    }
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        const uint32_t ent = (uint32_t)(((s < 4 ? w0 : w1) >> (16 * (s & 3))) & 0xffffu);
-        const uint32_t e = ent >> 8;
-        if (e == 0) break;
-        v = v * powi(xs.get(ent & 0xffu), e);
+    for (int i = 0; i < n; ++i) {
+        const uint32_t e = row[i];
+        if (e) v = v * powi(xl[i * kWave], e);
     }
     return v;
 }
 
-constexpr int EV_GROUP = 4;   // terms per scalar-load group
+// One chunk of four factors: four variable indices packed in a word (padding
+// indices point at the row of ones).  The four LDS reads are issued before
+// the multiplications; the product runs left to right.
+__device__ inline double chunk4(double v, uint32_t word, const double *xl)
+{
+    const double x0 = xl[(word & 0xffu) * kWave];
+    const double x1 = xl[((word >> 8) & 0xffu) * kWave];
+    const double x2 = xl[((word >> 16) & 0xffu) * kWave];
+    const double x3 = xl[(word >> 24) * kWave];
+    return (((v * x0) * x1) * x2) * x3;
+}
 
-// acc += sum of c_t * m_t(x) over terms [ta, tb), in term order.  Loads of
-// the next group are issued before the current group is evaluated; since
-// scalar loads complete out of order, the current group is forced resident
-// first (the empty asm), so that evaluating it never waits on the next loads.
-template <class XS>
-__device__ inline double term_range(const EvalArgs &A, const uint64_t *enc, int64_t ta, int64_t tb, const XS &xs)
+constexpr int EV_GROUP = 2;   // terms per load group
+
+// Sum of c_t * m_t(x) over terms [ta, tb), in term order.  Term records are
+// fetched with vector loads from an offset the compiler cannot see to be
+// uniform, so they are tracked by the in-order vector-memory counter and the
+// next group's loads stay in flight while the current group is evaluated.
+__device__ inline double term_range(const EvalArgs &A, const uint32_t *enc, int64_t ta, int64_t tb,
+                                    const double *xl, int vz)
 {
     double acc = 0.0;
     if (ta >= tb) return acc;
-    cu64 *ec = (cu64 *)enc;
-    cf64 *cc = (cf64 *)A.coefs;
-    uint64_t w0[EV_GROUP], w1[EV_GROUP];
+    const uint4 *ev = reinterpret_cast<const uint4 *>(enc);
+    uint4 w[EV_GROUP];
     double c[EV_GROUP];
 #pragma unroll
     for (int k = 0; k < EV_GROUP; ++k) {
-        const int64_t t = ta + k < tb ? ta + k : tb - 1;
-        w0[k] = ec[2 * t];
-        w1[k] = ec[2 * t + 1];
-        c[k] = cc[t];
+        const int64_t t = (ta + k < tb ? ta + k : tb - 1) + vz;
+        w[k] = ev[t];
+        c[k] = A.coefs[t];
     }
     for (int64_t t0 = ta; t0 < tb; t0 += EV_GROUP) {
-#pragma unroll
-        for (int k = 0; k < EV_GROUP; ++k) asm volatile("" ::"s"(w0[k]), "s"(w1[k]), "s"(c[k]) : "memory");
-        uint64_t n0[EV_GROUP], n1[EV_GROUP];
+        uint4 nw[EV_GROUP];
         double nc[EV_GROUP];
         const int64_t tn = t0 + EV_GROUP;
 #pragma unroll
         for (int k = 0; k < EV_GROUP; ++k) {
-            int64_t t = tn + k < tb ? tn + k : tb - 1;
-            n0[k] = ec[2 * t];
-            n1[k] = ec[2 * t + 1];
-            nc[k] = cc[t];
+            const int64_t t = (tn + k < tb ? tn + k : tb - 1) + vz;
+            nw[k] = ev[t];
+            nc[k] = A.coefs[t];
         }
 #pragma unroll
         for (int k = 0; k < EV_GROUP; ++k) {
-            if (t0 + k < tb) acc += c[k] * monomial(w0[k], w1[k], xs, A.exps + (t0 + k) * A.n, A.n);
+            if (t0 + k < tb) {
+                const uint32_t d = __builtin_amdgcn_readfirstlane(w[k].w);
+                double v;
+                if (d <= (uint32_t)EV_MAX_DEG) {
+                    v = 1.0;
+                    if (d > 0) v = chunk4(v, __builtin_amdgcn_readfirstlane(w[k].x), xl);
+                    if (d > 4) v = chunk4(v, __builtin_amdgcn_readfirstlane(w[k].y), xl);
+                    if (d > 8) v = chunk4(v, __builtin_amdgcn_readfirstlane(w[k].z), xl);
+                } else {
+                    v = monomial_dense(A.exps + (t0 + k) * A.n, A.n, xl);
+                }
+                acc += c[k] * v;
+            }
         }
 #pragma unroll
         for (int k = 0; k < EV_GROUP; ++k) {
-            w0[k] = n0[k];
-            w1[k] = n1[k];
+            w[k] = nw[k];
             c[k] = nc[k];
         }
     }
@@ -387,69 +378,58 @@ __device__ inline double term_range(const EvalArgs &A, const uint64_t *enc, int6
 
 }  // namespace
 
-// grid: x = blocks of 64 points (one point per lane), y = work units
-// u = (q, s) looped with stride gridDim.y: polynomial q, term segment s of S.
-// The block's EV_WAVES waves cut the segment into contiguous term ranges;
-// their sums are added in wave order through LDS, then over segments in
-// k_eval_reduce (S > 1), so results do not depend on scheduling.
-// XMODE 16 / 32: coordinates in registers (n <= XMODE); 0: in LDS
-// (n * 64 doubles of dynamic LDS).
-template <int XMODE>
-__global__ void __launch_bounds__(EV_THREADS) k_eval_terms(EvalArgs A, const uint64_t *enc, double *partial,
+// grid: x = blocks of 64 points (one point per lane), y = groups of work
+// units.  Unit u = (q, s): term segment s of S of polynomial q.  Each wave
+// takes its own units (u = blockIdx.y * EV_WAVES + wave, then strides of
+// gridDim.y * EV_WAVES), sums its segment in term order and stores it
+// (S == 1) or leaves it for k_eval_reduce, which adds the segments in order;
+// results therefore do not depend on scheduling.  The next unit's row
+// pointers are fetched while the current unit is evaluated.  The block's
+// waves share the point tile in LDS: (n + 1) * 64 doubles, variable-major,
+// plus a row of ones that the factor lists use as padding.
+__global__ void __launch_bounds__(EV_THREADS) k_eval_terms(EvalArgs A, const uint32_t *enc, double *partial,
                                                            int64_t S)
 {
     extern __shared__ double s_x[];
-    __shared__ double s_part[EV_WAVES][kWave];
     const int lane = lane_id();
     const int w = wave_id();
     const int64_t pt0 = (int64_t)blockIdx.x * kWave;
     const int64_t pt = pt0 + lane;
-    PointRegs16 r16;
-    PointRegs32 r32;
-    PointLds xl;
-    if (XMODE == 16) r16.load(A.X + (pt < A.N ? pt : 0) * A.n, A.n);
-    if (XMODE == 32) r32.load(A.X + (pt < A.N ? pt : 0) * A.n, A.n);
-    if (XMODE == 0) {
-        for (int idx = threadIdx.x; idx < A.n * kWave; idx += EV_THREADS) {
-            const int i = idx / kWave, l = idx % kWave;
-            const int64_t p = pt0 + l;
-            s_x[idx] = p < A.N ? A.X[p * A.n + i] : 0.0;
-        }
-        __syncthreads();
-        xl.s = s_x + lane;
+    for (int idx = threadIdx.x; idx < (A.n + 1) * kWave; idx += EV_THREADS) {
+        const int i = idx / kWave, l = idx % kWave;
+        const int64_t p = pt0 + l;
+        s_x[idx] = i == A.n ? 1.0 : (p < A.N ? A.X[p * A.n + i] : 0.0);
     }
+    __syncthreads();   // the only barrier: waves run independently from here
+    const double *xl = s_x + lane;
+    int vz;   // a zero the compiler treats as per-lane
+    asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
     const int64_t units = A.Q * S;
-    for (int64_t u = blockIdx.y; u < units; u += gridDim.y) {
+    const int64_t ustride = (int64_t)gridDim.y * EV_WAVES;
+    int64_t u = (int64_t)blockIdx.y * EV_WAVES + w;
+    if (u >= units) return;
+    int64_t r0 = A.rp[u / S + vz], r1 = A.rp[u / S + 1 + vz];
+    for (; u < units; u += ustride) {
+        const int64_t un = u + ustride;
+        int64_t n0 = 0, n1 = 0;
+        if (un < units) {
+            n0 = A.rp[un / S + vz];
+            n1 = A.rp[un / S + 1 + vz];
+        }
         const int64_t q = u / S, sg = u % S;
-        const int64_t b0 = A.rp[q];
-        int64_t b1 = A.rp[q + 1];
-        if (b1 > A.term_limit) b1 = A.term_limit;
+        const int64_t b0 = r0;
+        const int64_t b1 = r1 < A.term_limit ? r1 : A.term_limit;
         const int64_t len = b1 > b0 ? b1 - b0 : 0;
         const int64_t sa = b0 + len * sg / S, sb = b0 + len * (sg + 1) / S;
-        const int64_t sl = sb - sa;
-        const int64_t ta = sa + sl * w / EV_WAVES, tb = sa + sl * (w + 1) / EV_WAVES;
-        double acc;
-        if (XMODE == 16) acc = term_range(A, enc, ta, tb, r16);
-        else if (XMODE == 32) acc = term_range(A, enc, ta, tb, r32);
-        else acc = term_range(A, enc, ta, tb, xl);
-        s_part[w][lane] = acc;
-        __syncthreads();
-        if (w == 0) {
-            double sum = s_part[0][lane];
-#pragma unroll
-            for (int r = 1; r < EV_WAVES; ++r) sum += s_part[r][lane];
-            if (pt < A.N) {
-                if (S == 1) store_out(A, q, pt, sum);
-                else partial[(sg * A.Q + q) * A.N + pt] = sum;
-            }
+        const double acc = term_range(A, enc, sa, sb, xl, vz);
+        if (pt < A.N) {
+            if (S == 1) store_out(A, q, pt, acc);
+            else partial[(sg * A.Q + q) * A.N + pt] = acc;
         }
-        __syncthreads();
+        r0 = n0;
+        r1 = n1;
     }
 }
-
-template __global__ void k_eval_terms<0>(EvalArgs, const uint64_t *, double *, int64_t);
-template __global__ void k_eval_terms<16>(EvalArgs, const uint64_t *, double *, int64_t);
-template __global__ void k_eval_terms<32>(EvalArgs, const uint64_t *, double *, int64_t);
 
 // Sum of the S segment partials of (q, pt) in segment order, stored in the
 // output layout of A.mode.

@@ -116,10 +116,9 @@ struct FormArgs {
     const uint8_t *exps;
     const double *coefs;
     int n;
-    int mode;                   // 0: jacobian (group = variable), 1: hessian pair batch
-    int64_t ngroups;            // n, or the pairs in this batch
-    int64_t pair_base;
-    const uint32_t *pair_jk;
+    int mode;                   // 0: jacobian, 1: hessian entries from a jacobian (group = variable)
+    int keep_coefs;             // 1: formed terms keep the source coefficient
+    int64_t ngroups;            // n
     const int64_t *item_start;  // [P+1] first work item of each source polynomial
     int64_t P;
     int64_t chunk;              // source terms per work item
@@ -136,12 +135,12 @@ __global__ void k_item_count(const int64_t *rp, int64_t P, int64_t chunk, int64_
 __global__ void k_form_count(FormArgs A);
 __global__ void k_form_rowptr(FormArgs A, const int64_t *off);
 __global__ void k_form_write(FormArgs A, const int64_t *off);
-__global__ void k_pair_table(int n, uint32_t *pair_jk);
 
 // ----------------------------------------------------------------- sparse eval
 constexpr int EV_WAVES = 8;
 constexpr int EV_THREADS = EV_WAVES * kWave;  // 8 waves share 64 points
 
+// OUT_HESS: polynomial q = (p * n + j) * n + k is the Hessian entry (j, k) of f_p
 enum OutMode { OUT_EVAL = 0, OUT_GRAD = 1, OUT_HESS = 2 };
 
 struct EvalArgs {
@@ -153,20 +152,18 @@ struct EvalArgs {
     int64_t N;
     int64_t Q;                    // polynomials
     int mode;                     // OutMode
-    int64_t pair_base;            // hess: first pair index of this batch
-    int64_t pairs_in_batch;       // hess: pairs per source polynomial in this batch
-    const uint32_t *pair_jk;      // hess: (j << 16) | k
     double *Y;                    // output
     int64_t term_limit;           // terms at or beyond this index are never read
 };
 
 __global__ void k_encode_support(const uint8_t *exps, int64_t T, int n, uint64_t *enc, const int64_t *used);
-template <int XMODE>
-__global__ void k_eval_terms(EvalArgs A, const uint64_t *enc, double *partial, int64_t S);
+constexpr int EV_MAX_DEG = 12;   // total degree handled by the factor-list encoding
+__global__ void k_encode_factors(const uint8_t *exps, int64_t T, int n, uint32_t *enc, const int64_t *used);
+__global__ void k_eval_terms(EvalArgs A, const uint32_t *enc, double *partial, int64_t S);
 __global__ void k_eval_reduce(EvalArgs A, const double *partial, int64_t S);
-constexpr int64_t EV_TARGET_BLOCKS = 2048;   // blocks wanted before polynomials are cut into segments
-constexpr int64_t EV_MIN_SEGMENT = 512;      // fewest terms per segment
-constexpr int64_t EV_MAX_SEGMENTS = 64;
+constexpr int64_t EV_TARGET_WAVES = 16384;   // waves wanted before polynomials are cut into segments
+constexpr int64_t EV_MIN_SEGMENT = 256;      // fewest terms per segment
+constexpr int64_t EV_MAX_SEGMENTS = 256;
 
 __global__ void k_backward_dx(const double *G, const double *gY, int64_t P, int64_t N, int n, double *dX);
 constexpr int BWC_THREADS = 256;
