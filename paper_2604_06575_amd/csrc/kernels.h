@@ -53,7 +53,7 @@ __global__ void k_compact(const int64_t *stage_off, const int64_t *seg_count, co
 constexpr int MUL_THREADS = 256;
 constexpr int MUL_CAP = 4096;
 constexpr int64_t MUL_TARGET = 3072;       // raw terms per bucket, global-memory bucket kernel
-constexpr int64_t MB_TARGET = 16384;       // raw terms per bucket, LDS bucket kernel
+constexpr int64_t MB_TARGET = 32768;       // raw terms per bucket, LDS bucket kernel
 constexpr int MUL_SAMPLE = 8192;           // splitter sample per pair
 constexpr int64_t MUL_MAX_BUCKETS = 4096;  // per pair
 
@@ -89,19 +89,19 @@ __global__ void k_mul_plan(const int64_t *a_rp, const int64_t *b_rp, int64_t P, 
 __global__ void k_mul_splitters(MulArgs A);
 __global__ void k_mul_buckets(MulArgs A);
 // Cursor-based bucket kernel: partner keys (and row keys) resident in LDS.
-constexpr int MB_THREADS = 512;
-constexpr int MB_ITEMS = 6;
+constexpr int MB_THREADS = 1024;
+constexpr int MB_ITEMS = 3;
 constexpr int MB_CAP = MB_THREADS * MB_ITEMS;  // raw terms sorted per piece
 constexpr int MB_SAMPLE = 2048;                // sampled raw keys per bucket (piece boundaries)
 constexpr int MB_STACK = 112;                  // pending key ranges (pieces + bisection)
-constexpr int MB_RPT = 10;                     // rows per thread -> at most 5120 rows
+constexpr int MB_RPT = 5;                     // rows per thread -> at most 5120 rows
 constexpr int MB_MAX_ROWS = MB_THREADS * MB_RPT;
 // dynamic LDS of the LDS bucket kernel: partner keys and coefficients, 16-bit row cursors
 __host__ __device__ inline size_t mb_lds_bytes(int64_t ns, int64_t nrows)
 {
     return (size_t)ns * 16 + (size_t)nrows * 2;
 }
-constexpr size_t MB_LDS_LIMIT = 96 * 1024;     // with the static part, within 160 KB
+constexpr size_t MB_LDS_LIMIT = 92 * 1024;     // with the static part, within 160 KB
 constexpr int64_t MB_MAX_PARTNERS = 65535;     // cursors are 16-bit
 __global__ void k_mul_buckets_lds(MulArgs A);
 __global__ void k_mul_rowptr(const int64_t *out_off, const int64_t *pb_start, int64_t P, int64_t *out_rp,
