@@ -111,6 +111,23 @@ poly_status poly_read_status(const void *ws, void *stream);
 poly_status poly_tune_set(const char *name, int64_t value);
 poly_status poly_tune_get(const char *name, int64_t *value);
 
+/* ----------------------------------------------------------- kernel timing
+ * Measurement hook for benchmarks.  While enabled, the library records a
+ * pair of HIP events on the caller's stream around the dominant kernel of an
+ * entry point, in slots:
+ *   POLY_TIMING_MUL   the bucketed expand + sort + merge kernel of poly_mul
+ *   POLY_TIMING_DENSE the contraction kernel of poly_eval_dense
+ *   POLY_TIMING_TERMS the term-streaming kernel of poly_eval / grad / hess
+ * poly_timing_enable(1) clears every slot and starts recording; (0) stops.
+ * poly_timing_read waits for the recorded events of `slot` (at most the last
+ * 1024 launches are kept) and returns their summed duration in milliseconds
+ * and the launch count.  Off by default; recording adds two event records per
+ * launch and is not meant for graph capture.  Not thread-safe with concurrent
+ * entry-point calls from other host threads. */
+enum { POLY_TIMING_MUL = 0, POLY_TIMING_DENSE = 1, POLY_TIMING_TERMS = 2 };
+poly_status poly_timing_enable(int32_t enable);
+poly_status poly_timing_read(int32_t slot, double *total_ms, int64_t *launches);
+
 /* ---------------------------------------------------------------- simplify
  * out_p = simplify(in_p, zero_tol) for every p (Table "coresemantics").
  * Inputs may hold repeated monomials in any order.  All P entries are

@@ -29,6 +29,7 @@ POLY_SPLIT_BF16 = 1
 
 EXPORTS = [
     "poly_strerror", "poly_read_status", "poly_tune_set", "poly_tune_get",
+    "poly_timing_enable", "poly_timing_read",
     "poly_simplify_workspace", "poly_simplify",
     "poly_mul_workspace", "poly_mul",
     "poly_jacobian_workspace", "poly_jacobian",
@@ -84,6 +85,8 @@ def lib():
         "poly_read_status": ([P, P], i32),
         "poly_tune_set": ([ctypes.c_char_p, i64], i32),
         "poly_tune_get": ([ctypes.c_char_p, ctypes.POINTER(i64)], i32),
+        "poly_timing_enable": ([i32], i32),
+        "poly_timing_read": ([i32, ctypes.POINTER(d), ctypes.POINTER(i64)], i32),
         "poly_simplify_workspace": ([pcsr, psz], i32),
         "poly_simplify": ([pcsr, pcsr, d, P, ctypes.c_size_t, P], i32),
         "poly_mul_workspace": ([pcsr, pcsr, psz, ctypes.POINTER(i64)], i32),
@@ -134,6 +137,23 @@ def tune_get(name: str) -> int:
     v = ctypes.c_int64()
     _check(lib().poly_tune_get(name.encode(), ctypes.byref(v)), f"poly_tune_get({name})")
     return int(v.value)
+
+
+TIMING_MUL, TIMING_DENSE, TIMING_TERMS = 0, 1, 2
+
+
+def timing_enable(on: bool = True):
+    """Start (clearing earlier records) or stop recording HIP events around
+    the dominant kernel of each entry point (see poly_timing_enable)."""
+    _check(lib().poly_timing_enable(1 if on else 0), "poly_timing_enable")
+
+
+def timing_read(slot: int) -> tuple[float, int]:
+    """(summed kernel milliseconds, launches) recorded in `slot`."""
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    _check(lib().poly_timing_read(int(slot), ctypes.byref(ms), ctypes.byref(cnt)), "poly_timing_read")
+    return float(ms.value), int(cnt.value)
 
 
 def _check(code: int, where: str):

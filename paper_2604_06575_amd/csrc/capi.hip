@@ -17,6 +17,7 @@ namespace {
 std::atomic<int64_t> g_mul_bucket_terms{MB_TARGET};
 std::atomic<int64_t> g_seg_blocks_per_cu{2};
 std::atomic<int64_t> g_eval_blocks_per_cu{16};
+std::atomic<int64_t> g_mul_sort_min_raw{int64_t(1) << 20};
 
 struct TuneEntry {
     const char *name;
@@ -27,12 +28,14 @@ const TuneEntry kTune[] = {
     {"mul_bucket_terms", &g_mul_bucket_terms, 1024, 1 << 22},
     {"seg_blocks_per_cu", &g_seg_blocks_per_cu, 1, 16},
     {"eval_blocks_per_cu", &g_eval_blocks_per_cu, 1, 64},
+    {"mul_sort_min_raw", &g_mul_sort_min_raw, 0, int64_t(1) << 62},
 };
 }  // namespace
 
 Tunables tunables()
 {
-    return Tunables{g_mul_bucket_terms.load(), g_seg_blocks_per_cu.load(), g_eval_blocks_per_cu.load()};
+    return Tunables{g_mul_bucket_terms.load(), g_seg_blocks_per_cu.load(), g_eval_blocks_per_cu.load(),
+                    g_mul_sort_min_raw.load()};
 }
 
 }  // namespace polyhip
@@ -147,12 +150,34 @@ SimplifyPlan plan_simplify(int64_t P, int64_t T)
     return s;
 }
 
+// --------------------------------------------------------------- scans
+
+inline int64_t scan_tmp_count(int64_t S) { return 2 * ceil_div(std::max<int64_t>(S, 1), SCAN_TILE) + 1; }
+
+// out[0..S] = exclusive scan of in[0..S) with out[S] = total; tmp holds
+// scan_tmp_count(S) entries.
+void launch_scan(const int64_t *in, int64_t S, int64_t *out, int64_t *tmp, hipStream_t s)
+{
+    if (S <= 8 * SCAN_TILE) {
+        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, in, S, out);
+        return;
+    }
+    const int64_t nt = ceil_div(S, SCAN_TILE);
+    int64_t *sums = tmp, *tile_off = tmp + nt;
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)nt), dim3(SCAN_THREADS), 0, s, in, S, sums);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, sums, nt, tile_off);
+    hipLaunchKernelGGL(k_scan_tile_apply, dim3((unsigned)nt), dim3(SCAN_THREADS), 0, s, in, S, tile_off, out);
+}
+
 // ---------------------------------------------------------------- mul plan
 
 struct MulPlan {
-    size_t ka, kb, ka_s, kb_s, perm_a, perm_b, cnt_tmp, order_a, order_b, queues, pb_count, pb_start;
+    size_t ka, kb, ka_s, kb_s, perm_a, perm_b, ca_s, cb_s, cnt_tmp, order_a, order_b, queues, pb_count, pb_start;
     size_t bk_pair, bk_lo, bk_hi, bk_stage_off, bk_count, out_off, cursor, st_key, st_coef;
     int64_t raw, nbuckets, target;
+    bool sort_mode;         // one pair, raw product sorted globally (mulsort.hip)
+    size_t gs_keys0, gs_keys1, gs_vals0, gs_vals1, gs_hist, gs_hoff, gs_tmp, gs_count, gs_soff, gs_ooff;
+    int64_t gs_blocks;
     bool lds_mode;          // partner and row keys of every pair fit in LDS
     size_t lds_dyn;         // dynamic LDS bytes of the LDS bucket kernel
     size_t total;
@@ -179,6 +204,8 @@ poly_status plan_mul(const poly_csr *a, const poly_csr *b, MulPlan &m)
         auto bw = [](int64_t v) { return v > 0 ? 64 - __builtin_clzll((unsigned long long)v) : 0; };
         if (bw(ta - 1) + bw(tb - 1) > 32) codes_fit = false;
     }
+    // one large pair: global radix sort of the raw product (raw indices are 32-bit)
+    m.sort_mode = P == 1 && raw >= tunables().mul_sort_min_raw && raw < (int64_t(1) << 32) && raw > 0;
     m.lds_mode = lds_max <= MB_LDS_LIMIT && rows_max <= MB_MAX_ROWS && ns_max <= MB_MAX_PARTNERS && codes_fit;
     m.lds_dyn = std::max<size_t>(lds_max, 16);
     m.target = m.lds_mode ? tunables().mul_bucket_terms : MUL_TARGET;
@@ -195,6 +222,8 @@ poly_status plan_mul(const poly_csr *a, const poly_csr *b, MulPlan &m)
     m.kb_s = L.take(8 * Tb);
     m.perm_a = L.take(4 * Ta);
     m.perm_b = L.take(4 * Tb);
+    m.ca_s = L.take(8 * Ta);
+    m.cb_s = L.take(8 * Tb);
     m.cnt_tmp = L.take(8 * P);
     m.order_a = L.take(8 * P);
     m.order_b = L.take(8 * P);
@@ -210,6 +239,19 @@ poly_status plan_mul(const poly_csr *a, const poly_csr *b, MulPlan &m)
     m.cursor = L.take(8);
     m.st_key = L.take(8 * raw);
     m.st_coef = L.take(8 * raw);
+    if (m.sort_mode) {
+        m.gs_blocks = ceil_div(raw, GS_TILE);
+        m.gs_keys0 = L.take(8 * raw);
+        m.gs_keys1 = L.take(8 * raw);
+        m.gs_vals0 = L.take(4 * raw);
+        m.gs_vals1 = L.take(4 * raw);
+        m.gs_hist = L.take(8 * GS_BINS * m.gs_blocks);
+        m.gs_hoff = L.take(8 * (GS_BINS * m.gs_blocks + 1));
+        m.gs_tmp = L.take(8 * scan_tmp_count(GS_BINS * m.gs_blocks));
+        m.gs_count = L.take(8 * m.gs_blocks);
+        m.gs_soff = L.take(8 * m.gs_blocks);
+        m.gs_ooff = L.take(8 * (m.gs_blocks + 1));
+    }
     m.raw = raw;
     m.nbuckets = nb;
     m.total = L.total();
@@ -268,28 +310,13 @@ void launch_eval_blocks(const EvalArgs &A, const uint32_t *enc, double *partial,
     const int64_t want = std::max<int64_t>(1, ((int64_t)device_cus() * tunables().eval_blocks_per_cu + gx - 1) / gx);
     const unsigned gy = (unsigned)std::min<int64_t>(std::min<int64_t>(ceil_div(A.Q * S, EV_WAVES), want), 65535);
     const size_t lds = (size_t)(A.n + 1) * kWave * sizeof(double);
+    TimedLaunch tl(POLY_TIMING_TERMS, s);
     hipLaunchKernelGGL(k_eval_terms, dim3(gx, gy), dim3(EV_THREADS), lds, s, A, enc, partial, S);
+    tl.done(s);
     if (S > 1) hipLaunchKernelGGL(k_eval_reduce, dim3(grid1(A.Q * A.N, 256)), dim3(256), 0, s, A, partial, S);
 }
 
 // ------------------------------------------------------- scans, formation
-
-inline int64_t scan_tmp_count(int64_t S) { return 2 * ceil_div(std::max<int64_t>(S, 1), SCAN_TILE) + 1; }
-
-// out[0..S] = exclusive scan of in[0..S) with out[S] = total; tmp holds
-// scan_tmp_count(S) entries.
-void launch_scan(const int64_t *in, int64_t S, int64_t *out, int64_t *tmp, hipStream_t s)
-{
-    if (S <= 8 * SCAN_TILE) {
-        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, in, S, out);
-        return;
-    }
-    const int64_t nt = ceil_div(S, SCAN_TILE);
-    int64_t *sums = tmp, *tile_off = tmp + nt;
-    hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)nt), dim3(SCAN_THREADS), 0, s, in, S, sums);
-    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, sums, nt, tile_off);
-    hipLaunchKernelGGL(k_scan_tile_apply, dim3((unsigned)nt), dim3(SCAN_THREADS), 0, s, in, S, tile_off, out);
-}
 
 // Derivative formation over (polynomial, chunk) work items.  The chunk size
 // depends on the term count only, so workspace queries need no device.
@@ -362,6 +389,19 @@ void run_form(const FormPlan &fp, FormArgs A, void *ws, hipStream_t s)
     hipLaunchKernelGGL(k_form_write, dim3((unsigned)fp.W), dim3(JAC_THREADS), 0, s, A, (const int64_t *)off);
 }
 
+// --------------------------------------------------------- kernel timing
+
+constexpr int kTimingSlots = 3;
+constexpr int kTimingRing = 1024;
+struct TimingState {
+    std::mutex mu;
+    std::atomic<bool> on{false};
+    bool created = false;
+    hipEvent_t ev[kTimingSlots][kTimingRing][2];
+    int64_t count[kTimingSlots] = {0, 0, 0};
+};
+TimingState g_timing;
+
 bool lds_attr_done = false;
 std::mutex lds_mu;
 void ensure_lds_attrs()
@@ -370,6 +410,8 @@ void ensure_lds_attrs()
     if (lds_attr_done) return;
     (void)hipFuncSetAttribute((const void *)k_eval_terms, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
     (void)hipFuncSetAttribute((const void *)k_backward_dc, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
+    (void)hipFuncSetAttribute((const void *)k_gs_merge, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(GS_MERGE_COEFS * sizeof(double)));
     (void)hipFuncSetAttribute((const void *)k_mul_buckets_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)MB_LDS_LIMIT);
     lds_attr_done = true;
@@ -459,6 +501,25 @@ poly_status run_grad(const poly_csr *f, const double *X, int64_t N, double *G, v
 
 }  // namespace
 
+namespace polyhip {
+
+TimedLaunch::TimedLaunch(int slot, hipStream_t s)
+{
+    if (!g_timing.on.load()) return;
+    std::lock_guard<std::mutex> g(g_timing.mu);
+    if (!g_timing.on.load() || slot < 0 || slot >= kTimingSlots) return;
+    const int64_t i = g_timing.count[slot]++ % kTimingRing;
+    e1 = g_timing.ev[slot][i][1];
+    (void)hipEventRecord(g_timing.ev[slot][i][0], s);
+}
+
+void TimedLaunch::done(hipStream_t s)
+{
+    if (e1) (void)hipEventRecord(e1, s);
+}
+
+}  // namespace polyhip
+
 extern "C" {
 
 const char *poly_strerror(int32_t status)
@@ -487,6 +548,40 @@ poly_status poly_tune_set(const char *name, int64_t value)
         }
     }
     return POLY_ERR_ARG;
+}
+
+poly_status poly_timing_enable(int32_t enable)
+{
+    std::lock_guard<std::mutex> g(g_timing.mu);
+    if (enable && !g_timing.created) {
+        for (int sl = 0; sl < kTimingSlots; ++sl)
+            for (int i = 0; i < kTimingRing; ++i)
+                for (int k = 0; k < 2; ++k)
+                    if (hipEventCreate(&g_timing.ev[sl][i][k]) != hipSuccess) return POLY_ERR_HIP;
+        g_timing.created = true;
+    }
+    for (int sl = 0; sl < kTimingSlots; ++sl) g_timing.count[sl] = 0;
+    g_timing.on.store(enable != 0);
+    return POLY_OK;
+}
+
+poly_status poly_timing_read(int32_t slot, double *total_ms, int64_t *launches)
+{
+    if (slot < 0 || slot >= kTimingSlots || !total_ms || !launches) return POLY_ERR_ARG;
+    std::lock_guard<std::mutex> g(g_timing.mu);
+    *total_ms = 0.0;
+    *launches = 0;
+    if (!g_timing.created) return POLY_OK;
+    const int64_t n = std::min<int64_t>(g_timing.count[slot], kTimingRing);
+    for (int64_t i = 0; i < n; ++i) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(g_timing.ev[slot][i][1]) != hipSuccess) return POLY_ERR_HIP;
+        if (hipEventElapsedTime(&ms, g_timing.ev[slot][i][0], g_timing.ev[slot][i][1]) != hipSuccess)
+            return POLY_ERR_HIP;
+        *total_ms += ms;
+    }
+    *launches = n;
+    return POLY_OK;
 }
 
 poly_status poly_tune_get(const char *name, int64_t *value)
@@ -630,6 +725,8 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
     A.kb_s = at<uint64_t>(ws, m.kb_s);
     A.perm_a = at<uint32_t>(ws, m.perm_a);
     A.perm_b = at<uint32_t>(ws, m.perm_b);
+    A.ca_s = at<double>(ws, m.ca_s);
+    A.cb_s = at<double>(ws, m.cb_s);
     A.pb_start = at<int64_t>(ws, m.pb_start);
     A.bk_pair = at<int32_t>(ws, m.bk_pair);
     A.bk_lo = at<uint64_t>(ws, m.bk_lo);
@@ -657,6 +754,47 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
                                     at<int64_t>(ws, m.order_b), queues + 1, s);
     const int64_t pgrid = std::min<int64_t>(P, (int64_t)device_cus() * tunables().seg_blocks_per_cu);
     hipLaunchKernelGGL(k_seg_sort2, dim3((unsigned)(2 * pgrid)), dim3(SEG_THREADS), 0, s, sa, sb);
+    hipLaunchKernelGGL(k_mul_sorted_coefs, dim3((unsigned)P), dim3(256), 0, s, a->row_ptr, A.perm_a, a->coefs,
+                       (double *)A.ca_s);
+    hipLaunchKernelGGL(k_mul_sorted_coefs, dim3((unsigned)P), dim3(256), 0, s, b->row_ptr, A.perm_b, b->coefs,
+                       (double *)A.cb_s);
+    if (m.sort_mode) {
+        // ---- one pair: generate the raw product, radix sort it, merge runs
+        ensure_lds_attrs();
+        const int64_t R = m.raw, nb = m.gs_blocks;
+        uint64_t *kcur = at<uint64_t>(ws, m.gs_keys0), *knext = at<uint64_t>(ws, m.gs_keys1);
+        uint32_t *vcur = at<uint32_t>(ws, m.gs_vals0), *vnext = at<uint32_t>(ws, m.gs_vals1);
+        int64_t *hist = at<int64_t>(ws, m.gs_hist), *hoff = at<int64_t>(ws, m.gs_hoff);
+        int64_t *tmp = at<int64_t>(ws, m.gs_tmp);
+        hipLaunchKernelGGL(k_gs_generate, dim3((unsigned)std::min<int64_t>(Ta, 65535)), dim3(GS_THREADS), 0, s,
+                           A.ka, A.kb_s, Ta, Tb, kcur, vcur);
+        const int key_bits = n * bits;
+        for (int sh = 0; sh < key_bits; sh += GS_BITS) {
+            hipLaunchKernelGGL(k_gs_hist, dim3((unsigned)nb), dim3(GS_HIST_THREADS), 0, s, (const uint64_t *)kcur,
+                               R, sh, nb, hist);
+            launch_scan(hist, GS_BINS * nb, hoff, tmp, s);
+            TimedLaunch tl(POLY_TIMING_MUL, s);
+            hipLaunchKernelGGL(k_gs_scatter, dim3((unsigned)nb), dim3(GS_THREADS), 0, s, (const uint64_t *)kcur,
+                               (const uint32_t *)vcur, R, sh, nb, (const int64_t *)hoff, knext, vnext);
+            tl.done(s);
+            std::swap(kcur, knext);
+            std::swap(vcur, vnext);
+        }
+        int64_t *cnt = at<int64_t>(ws, m.gs_count), *soff = at<int64_t>(ws, m.gs_soff);
+        int64_t *ooff = at<int64_t>(ws, m.gs_ooff);
+        const size_t coef_lds = Ta + Tb <= GS_MERGE_COEFS ? (size_t)(Ta + Tb) * sizeof(double) : 0;
+        const int64_t mgrid = std::min<int64_t>(nb, (int64_t)device_cus() * (coef_lds ? 1 : 2));
+        hipLaunchKernelGGL(k_gs_merge, dim3((unsigned)mgrid), dim3(GS_THREADS), coef_lds, s, (const uint64_t *)kcur,
+                           (const uint32_t *)vcur, R, Ta, Tb, a->coefs, A.cb_s, zero_tol, A.st_key, A.st_coef, cnt,
+                           soff);
+        launch_scan(cnt, nb, ooff, tmp, s);
+        hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(256), 0, s, (const int64_t *)soff,
+                           (const int64_t *)cnt, (const int64_t *)ooff, (const uint64_t *)A.st_key,
+                           (const double *)A.st_coef, n, bits, out->exps, out->coefs, out->capacity, status);
+        hipLaunchKernelGGL(k_gs_rowptr, dim3(1), dim3(64), 0, s, (const int64_t *)ooff, nb, out->row_ptr);
+        LAUNCH_CHECK();
+        return POLY_OK;
+    }
     int64_t *pb_count = at<int64_t>(ws, m.pb_count);
     hipLaunchKernelGGL(k_mul_plan, dim3(grid1(P, 256)), dim3(256), 0, s, a->row_ptr, b->row_ptr, P, pb_count,
                        m.target);
@@ -664,7 +802,9 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
     hipLaunchKernelGGL(k_mul_splitters, dim3((unsigned)P), dim3(512), 0, s, A);
     if (m.lds_mode) {
         ensure_lds_attrs();
+        TimedLaunch tl(POLY_TIMING_MUL, s);
         hipLaunchKernelGGL(k_mul_buckets_lds, dim3((unsigned)m.nbuckets), dim3(MB_THREADS), m.lds_dyn, s, A);
+        tl.done(s);
     } else {
         hipLaunchKernelGGL(k_mul_buckets, dim3((unsigned)m.nbuckets), dim3(MUL_THREADS), 0, s, A);
     }

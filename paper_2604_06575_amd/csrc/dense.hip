@@ -434,8 +434,10 @@ void launch_split(int n, int64_t K, int64_t Kp, const uint8_t *basis, const uint
         attr = true;
     }
     const dim3 grid((unsigned)ceil_div(N, SP_BN), (unsigned)ceil_div(P, SP_BM));
+    TimedLaunch tl(POLY_TIMING_DENSE, s);
     hipLaunchKernelGGL(k_dense_split<S>, grid, dim3(SP_THREADS), lds, s, n, K, Kp, basis, enc, P, Cs, N, X, sig_v,
                        Y);
+    tl.done(s);
 }
 
 }  // namespace
@@ -476,8 +478,10 @@ poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_ex
             attr = true;
         }
         const dim3 grid((unsigned)ceil_div(N, D64_BN), (unsigned)ceil_div(P, D64_BM));
+        TimedLaunch tl(POLY_TIMING_DENSE, s);
         hipLaunchKernelGGL(k_dense_f64, grid, dim3(D64_THREADS), (size_t)n * D64_BN * 8, s, n, K, basis, enc, P, C, N,
                            X, Y);
+        tl.done(s);
     } else {
         unsigned short *Cs = (unsigned short *)((char *)ws + d.cs);
         int32_t *sig_v = (int32_t *)((char *)ws + d.sigv);

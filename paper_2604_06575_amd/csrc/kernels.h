@@ -10,6 +10,7 @@ struct Tunables {
     int64_t mul_bucket_terms;
     int64_t seg_blocks_per_cu;
     int64_t eval_blocks_per_cu;
+    int64_t mul_sort_min_raw;
 };
 Tunables tunables();
 
@@ -71,6 +72,7 @@ struct MulArgs {
     const uint64_t *ka, *kb;        // packed keys, storage order
     const uint64_t *ka_s, *kb_s;    // keys sorted per polynomial
     const uint32_t *perm_a, *perm_b;  // local index of each sorted position
+    const double *ca_s, *cb_s;      // coefficients in sorted order
     const int64_t *pb_start;        // [P+1] first bucket of each pair
     int32_t *bk_pair;
     uint64_t *bk_lo, *bk_hi;        // inclusive key range of each bucket
@@ -90,22 +92,49 @@ __global__ void k_mul_splitters(MulArgs A);
 __global__ void k_mul_buckets(MulArgs A);
 // Cursor-based bucket kernel: partner keys (and row keys) resident in LDS.
 constexpr int MB_THREADS = 1024;
-constexpr int MB_ITEMS = 3;
+constexpr int MB_ITEMS = 4;
 constexpr int MB_CAP = MB_THREADS * MB_ITEMS;  // raw terms sorted per piece
 constexpr int MB_SAMPLE = 2048;                // sampled raw keys per bucket (piece boundaries)
 constexpr int MB_STACK = 112;                  // pending key ranges (pieces + bisection)
 constexpr int MB_RPT = 5;                     // rows per thread -> at most 5120 rows
 constexpr int MB_MAX_ROWS = MB_THREADS * MB_RPT;
-// dynamic LDS of the LDS bucket kernel: partner keys and coefficients, 16-bit row cursors
+// dynamic LDS of the LDS bucket kernel: the partner keys
 __host__ __device__ inline size_t mb_lds_bytes(int64_t ns, int64_t nrows)
 {
-    return (size_t)ns * 16 + (size_t)nrows * 2;
+    (void)nrows;
+    return (size_t)ns * 8;
 }
-constexpr size_t MB_LDS_LIMIT = 92 * 1024;     // with the static part, within 160 KB
-constexpr int64_t MB_MAX_PARTNERS = 65535;     // cursors are 16-bit
+constexpr size_t MB_LDS_LIMIT = 72 * 1024;     // with the static part, within 160 KB
+constexpr int64_t MB_MAX_PARTNERS = 1 << 30;
 __global__ void k_mul_buckets_lds(MulArgs A);
+__global__ void k_mul_sorted_coefs(const int64_t *rp, const uint32_t *perm, const double *c, double *out);
+// Global radix-sort path for one large pair (mulsort.hip).
+constexpr int GS_THREADS = 1024;
+constexpr int GS_ITEMS = 4;
+constexpr int GS_TILE = GS_THREADS * GS_ITEMS;   // elements per workgroup and pass
+constexpr int GS_BITS = 8;                       // digit width
+constexpr int GS_BINS = 1 << GS_BITS;
+constexpr int GS_HIST_THREADS = 1024;
+constexpr int64_t GS_MERGE_COEFS = 10240;        // coefficients staged in LDS by the merge (80 KB)
+__global__ void k_gs_generate(const uint64_t *ka, const uint64_t *kb_s, int64_t ta, int64_t tb, uint64_t *keys,
+                              uint32_t *vals);
+__global__ void k_gs_hist(const uint64_t *keys, int64_t R, int shift, int64_t nblocks, int64_t *hist);
+__global__ void k_gs_scatter(const uint64_t *keys_in, const uint32_t *vals_in, int64_t R, int shift,
+                             int64_t nblocks, const int64_t *hist_off, uint64_t *keys_out, uint32_t *vals_out);
+__global__ void k_gs_merge(const uint64_t *keys, const uint32_t *vals, int64_t R, int64_t ta, int64_t tb,
+                           const double *ca, const double *cb_s, double tol, uint64_t *st_key, double *st_coef,
+                           int64_t *seg_count, int64_t *stage_off);
+__global__ void k_gs_rowptr(const int64_t *out_off, int64_t nblocks, int64_t *row_ptr);
 __global__ void k_mul_rowptr(const int64_t *out_off, const int64_t *pb_start, int64_t P, int64_t *out_rp,
                              int64_t nbuckets);
+
+// Host-side measurement hook (poly_timing_*): records HIP events on the
+// launch stream around a kernel when timing is enabled.
+struct TimedLaunch {
+    hipEvent_t e1 = nullptr;
+    TimedLaunch(int slot, hipStream_t s);
+    void done(hipStream_t s);
+};
 
 // ---------------------------------------------------------------- derivatives
 constexpr int JAC_THREADS = 256;

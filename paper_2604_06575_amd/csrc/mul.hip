@@ -372,11 +372,20 @@ __global__ void __launch_bounds__(MUL_THREADS) k_mul_buckets(MulArgs A)
 }
 
 
+// Coefficients of each polynomial in its sorted key order: one block per
+// polynomial, out[base + t] = c[base + perm[base + t]].
+__global__ void k_mul_sorted_coefs(const int64_t *rp, const uint32_t *perm, const double *c, double *out)
+{
+    const int64_t base = rp[blockIdx.x], T = rp[blockIdx.x + 1] - base;
+    for (int64_t t = threadIdx.x; t < T; t += blockDim.x) out[base + t] = c[base + perm[base + t]];
+}
+
 // ---------------------------------------------------------------------------
 // Cursor-based bucket kernel.
 //
-// The partner keys (the sorted operand) and the partner coefficients in the
-// same sorted order sit in LDS.  Each row keeps a cursor at its first
+// The partner keys (the sorted operand) sit in LDS; the partner coefficients
+// in the same sorted order are read from a global copy.  Each row keeps a
+// cursor (in registers) at its first
 // partner whose product key is not below the current piece's lower bound;
 // pieces are taken in ascending key order, so a piece [lo, hi] is exactly the
 // partners between each row's cursor and the first product key above hi,
@@ -456,30 +465,13 @@ __global__ void __launch_bounds__(MB_THREADS) k_mul_buckets_lds(MulArgs A)
     const double *g_rcf = swapped ? A.b_c + bb : A.a_c + a0;
     const uint64_t *g_srt = swapped ? A.ka_s + a0 : A.kb_s + bb;
     const uint32_t *perm = swapped ? A.perm_a + a0 : A.perm_b + bb;
-    const double *g_pcf = swapped ? A.a_c + a0 : A.b_c + bb;
+    const double *g_scf = swapped ? A.ca_s + a0 : A.cb_s + bb;   // partner coefficients, sorted order
     // term pair (i, j) coded as (i << jbits) | j; sorted below the key when swapped
     const int jbits = bitw((uint64_t)(tb - 1));
     const int ij_bits = swapped ? bitw((uint64_t)(ta - 1)) + jbits : 0;
 
-    uint64_t *s_srt = s_dyn;                                   // [ns] partner keys, sorted
-    double *s_scf = (double *)(s_dyn + ns);                    // [ns] partner coefficients, same order
-    uint16_t *s_cur = (uint16_t *)(s_dyn + 2 * (size_t)ns);    // [nrows] cursors
-    // partner keys and coefficients: all index loads of a batch first, then
-    // the dependent coefficient loads, so the two latencies are paid once
-    for (uint32_t i0 = 0; i0 < ns; i0 += MB_THREADS * 8) {
-        uint32_t pi[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const uint32_t i = i0 + u * MB_THREADS + tid;
-            pi[u] = i < ns ? perm[i] : 0u;
-            if (i < ns) s_srt[i] = g_srt[i];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const uint32_t i = i0 + u * MB_THREADS + tid;
-            if (i < ns) s_scf[i] = g_pcf[pi[u]];
-        }
-    }
+    uint64_t *s_srt = s_dyn;   // [ns] partner keys, sorted
+    for (uint32_t i = tid; i < ns; i += MB_THREADS) s_srt[i] = g_srt[i];
     __syncthreads();
 
     // this thread's rows [r0, r1), their keys in registers
@@ -489,6 +481,7 @@ __global__ void __launch_bounds__(MB_THREADS) k_mul_buckets_lds(MulArgs A)
     uint64_t rk[MB_RPT];
     double rcf[MB_RPT];
     uint32_t cr[MB_RPT];
+    uint32_t cur[MB_RPT];   // first partner of each row not yet consumed
     int64_t mine = 0;
 #pragma unroll
     for (int q = 0; q < MB_RPT; ++q) {
@@ -500,10 +493,11 @@ __global__ void __launch_bounds__(MB_THREADS) k_mul_buckets_lds(MulArgs A)
     for (int q = 0; q < MB_RPT; ++q) {
         const uint32_t r = r0 + q;
         cr[q] = 0;
+        cur[q] = 0;
         if (r < r1) {
             const uint64_t kr = rk[q];
             const uint32_t c = lo0 <= kr ? 0u : (uint32_t)lower_bound_u64(s_srt, ns, lo0 - kr);
-            s_cur[r] = (uint16_t)c;
+            cur[q] = c;
             cr[q] = advance_count(s_srt, ns, c, kr, hi0);
             mine += cr[q];
         }
@@ -539,7 +533,7 @@ __global__ void __launch_bounds__(MB_THREADS) k_mul_buckets_lds(MulArgs A)
         for (int q = 0; q < MB_RPT; ++q) {
             const uint32_t r = r0 + q;
             if (r < r1) {
-                const uint32_t c0 = s_cur[r];
+                const uint32_t c0 = cur[q];
                 // first element of this row that falls on the sample grid
                 int64_t first = ((e + SR - 1) / SR) * SR;
                 for (int64_t f = first; f < e + cr[q]; f += SR) {
@@ -597,7 +591,7 @@ __global__ void __launch_bounds__(MB_THREADS) k_mul_buckets_lds(MulArgs A)
             const uint32_t r = r0 + q;
             cr[q] = 0;
             if (r < r1) {
-                cr[q] = advance_count(s_srt, ns, s_cur[r], rk[q], hi);
+                cr[q] = advance_count(s_srt, ns, cur[q], rk[q], hi);
                 c += cr[q];
             }
         }
@@ -613,16 +607,16 @@ __global__ void __launch_bounds__(MB_THREADS) k_mul_buckets_lds(MulArgs A)
                 const uint32_t r = r0 + q;
                 if (r < r1 && cr[q]) {
                     const double rc = rcf[q];
-                    const uint32_t c0 = s_cur[r];
+                    const uint32_t c0 = cur[q];
                     for (uint32_t t = c0; t < c0 + cr[q]; ++t, ++pos) {
                         const uint64_t rel = rk[q] + s_srt[t] - lo;
                         kmax = rel > kmax ? rel : kmax;
                         uint64_t key = rel;
                         if (swapped) key = (rel << ij_bits) | (((uint64_t)perm[t] << jbits) | r);
                         S.key[pos] = key;
-                        S.val[pos] = swapped ? s_scf[t] * rc : rc * s_scf[t];
+                        S.val[pos] = swapped ? g_scf[t] * rc : rc * g_scf[t];
                     }
-                    s_cur[r] = (uint16_t)(c0 + cr[q]);
+                    cur[q] = c0 + cr[q];
                 }
             }
             const uint64_t relmax = block_max_u64<MB_THREADS>(kmax, S.red);
@@ -693,7 +687,7 @@ __global__ void __launch_bounds__(MB_THREADS) k_mul_buckets_lds(MulArgs A)
 #pragma unroll
             for (int q = 0; q < MB_RPT; ++q) {
                 const uint32_t r = r0 + q;
-                if (r < r1) s_cur[r] = (uint16_t)(s_cur[r] + cr[q]);
+                if (r < r1) cur[q] += cr[q];
             }
             __syncthreads();
             written += S.bcast;

@@ -22,7 +22,7 @@ def test_library_exports_every_declared_symbol():
         pytest.skip("library not built")
     L = ctypes.CDLL(ph.library_path())
     syms = header_symbols()
-    assert len(syms) == 20
+    assert len(syms) == 22
     for s in syms:
         assert hasattr(L, s), s
     assert sorted(ph.EXPORTS) == syms
@@ -84,3 +84,18 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(ph, "_lib", None)
     with pytest.raises(RuntimeError):
         ph.lib()
+
+
+def test_timing_hooks_host_checks():
+    """poly_timing_read rejects bad slots and null outputs without a GPU."""
+    import ctypes
+    import paper_2604_06575_amd as ph
+    L = ph.lib()
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    assert L.poly_timing_read(3, ctypes.byref(ms), ctypes.byref(cnt)) == 1
+    assert L.poly_timing_read(-1, ctypes.byref(ms), ctypes.byref(cnt)) == 1
+    assert L.poly_timing_read(0, None, ctypes.byref(cnt)) == 1
+    # nothing recorded yet: zero launches, no device access
+    assert L.poly_timing_read(0, ctypes.byref(ms), ctypes.byref(cnt)) == 0
+    assert cnt.value == 0 and ms.value == 0.0
