@@ -410,8 +410,6 @@ void ensure_lds_attrs()
     if (lds_attr_done) return;
     (void)hipFuncSetAttribute((const void *)k_eval_terms, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
     (void)hipFuncSetAttribute((const void *)k_backward_dc, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
-    (void)hipFuncSetAttribute((const void *)k_gs_merge, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(GS_MERGE_COEFS * sizeof(double)));
     (void)hipFuncSetAttribute((const void *)k_mul_buckets_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)MB_LDS_LIMIT);
     lds_attr_done = true;
@@ -769,8 +767,9 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
         hipLaunchKernelGGL(k_gs_generate, dim3((unsigned)std::min<int64_t>(Ta, 65535)), dim3(GS_THREADS), 0, s,
                            A.ka, A.kb_s, Ta, Tb, kcur, vcur);
         const int key_bits = n * bits;
+        const int64_t hgrid = std::min<int64_t>(ceil_div(nb, GS_HIST_THREADS / kWave), (int64_t)device_cus() * 8);
         for (int sh = 0; sh < key_bits; sh += GS_BITS) {
-            hipLaunchKernelGGL(k_gs_hist, dim3((unsigned)nb), dim3(GS_HIST_THREADS), 0, s, (const uint64_t *)kcur,
+            hipLaunchKernelGGL(k_gs_hist, dim3((unsigned)hgrid), dim3(GS_HIST_THREADS), 0, s, (const uint64_t *)kcur,
                                R, sh, nb, hist);
             launch_scan(hist, GS_BINS * nb, hoff, tmp, s);
             TimedLaunch tl(POLY_TIMING_MUL, s);
@@ -782,9 +781,8 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
         }
         int64_t *cnt = at<int64_t>(ws, m.gs_count), *soff = at<int64_t>(ws, m.gs_soff);
         int64_t *ooff = at<int64_t>(ws, m.gs_ooff);
-        const size_t coef_lds = Ta + Tb <= GS_MERGE_COEFS ? (size_t)(Ta + Tb) * sizeof(double) : 0;
-        const int64_t mgrid = std::min<int64_t>(nb, (int64_t)device_cus() * (coef_lds ? 1 : 2));
-        hipLaunchKernelGGL(k_gs_merge, dim3((unsigned)mgrid), dim3(GS_THREADS), coef_lds, s, (const uint64_t *)kcur,
+        const int64_t mgrid = std::min<int64_t>(nb, (int64_t)device_cus() * 2);
+        hipLaunchKernelGGL(k_gs_merge, dim3((unsigned)mgrid), dim3(GS_THREADS), 0, s, (const uint64_t *)kcur,
                            (const uint32_t *)vcur, R, Ta, Tb, a->coefs, A.cb_s, zero_tol, A.st_key, A.st_coef, cnt,
                            soff);
         launch_scan(cnt, nb, ooff, tmp, s);

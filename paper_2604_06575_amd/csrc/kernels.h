@@ -114,8 +114,7 @@ constexpr int GS_ITEMS = 4;
 constexpr int GS_TILE = GS_THREADS * GS_ITEMS;   // elements per workgroup and pass
 constexpr int GS_BITS = 8;                       // digit width
 constexpr int GS_BINS = 1 << GS_BITS;
-constexpr int GS_HIST_THREADS = 1024;
-constexpr int64_t GS_MERGE_COEFS = 10240;        // coefficients staged in LDS by the merge (80 KB)
+constexpr int GS_HIST_THREADS = 256;
 __global__ void k_gs_generate(const uint64_t *ka, const uint64_t *kb_s, int64_t ta, int64_t tb, uint64_t *keys,
                               uint32_t *vals);
 __global__ void k_gs_hist(const uint64_t *keys, int64_t R, int shift, int64_t nblocks, int64_t *hist);

@@ -33,35 +33,47 @@ __global__ void __launch_bounds__(GS_THREADS) k_gs_generate(const uint64_t *ka, 
     }
 }
 
-// Per-tile digit counts, digit-major: hist[d * nblocks + b].  Small
-// workgroups (GS_HIST_THREADS) with all of a lane's key loads issued before
-// its counting, so many tiles are in flight per CU; each wave counts into
-// its own LDS histogram, then the wave histograms are added.
+// Per-tile digit counts, digit-major: hist[d * nblocks + b].  One wave
+// counts a whole tile into its own LDS histogram, with no barrier: lanes
+// holding the same digit are found with wavefront ballots and their lowest
+// lane adds the group size.  Waves take tiles wave_id, wave_id + total
+// waves, ... (few, long-lived workgroups rather than one per tile).
 __global__ void __launch_bounds__(GS_HIST_THREADS) k_gs_hist(const uint64_t *keys, int64_t R, int shift,
                                                             int64_t nblocks, int64_t *hist)
 {
     constexpr int W = GS_HIST_THREADS / kWave;
-    constexpr int PER = GS_TILE / GS_HIST_THREADS;
+    constexpr int UN = 8;   // key loads in flight per lane
     __shared__ uint32_t s_cnt[W][GS_BINS];
-    for (int i = threadIdx.x; i < W * GS_BINS; i += GS_HIST_THREADS) (&s_cnt[0][0])[i] = 0;
     const int w = threadIdx.x >> 6;
-    const int64_t t0 = (int64_t)blockIdx.x * GS_TILE;
-    const int m = (int)(R - t0 < GS_TILE ? R - t0 : GS_TILE);
-    uint32_t dg[PER];
+    const int lane = lane_id();
+    const unsigned long long lt = lane ? (~0ull >> (kWave - lane)) : 0ull;
+    uint32_t *cnt = s_cnt[w];
+    const int64_t nwaves = (int64_t)gridDim.x * W;
+    for (int64_t tile = (int64_t)blockIdx.x * W + w; tile < nblocks; tile += nwaves) {
+        for (int d = lane; d < GS_BINS; d += kWave) cnt[d] = 0;
+        const int64_t t0 = tile * GS_TILE;
+        const int m = (int)(R - t0 < GS_TILE ? R - t0 : GS_TILE);
+        for (int c0 = 0; c0 < m; c0 += UN * kWave) {
+            uint32_t dg[UN];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int l = q * GS_HIST_THREADS + threadIdx.x;
-        dg[q] = l < m ? (uint32_t)(keys[t0 + l] >> shift) & (GS_BINS - 1) : 0xFFFFFFFFu;
-    }
-    __syncthreads();
+            for (int u = 0; u < UN; ++u) {
+                const int l = c0 + u * kWave + lane;
+                dg[u] = l < m ? (uint32_t)(keys[t0 + l] >> shift) & (GS_BINS - 1) : (uint32_t)GS_BINS;
+            }
 #pragma unroll
-    for (int q = 0; q < PER; ++q)
-        if (dg[q] != 0xFFFFFFFFu) atomicAdd(&s_cnt[w][dg[q]], 1u);
-    __syncthreads();
-    for (int d = threadIdx.x; d < GS_BINS; d += GS_HIST_THREADS) {
-        uint32_t c = 0;
-        for (int ww = 0; ww < W; ++ww) c += s_cnt[ww][d];
-        hist[(int64_t)d * nblocks + blockIdx.x] = c;
+            for (int u = 0; u < UN; ++u) {
+                const uint32_t d = dg[u];
+                unsigned long long peer = __ballot(d < (uint32_t)GS_BINS);   // padding lanes are in no group
+#pragma unroll
+                for (int bit = 0; bit < GS_BITS; ++bit) {
+                    const bool set = (d >> bit) & 1u;
+                    const unsigned long long bb = __ballot(set);
+                    peer &= set ? bb : ~bb;
+                }
+                if (d < (uint32_t)GS_BINS && (peer & lt) == 0) cnt[d] += (uint32_t)__popcll(peer);
+            }
+        }
+        for (int d = lane; d < GS_BINS; d += kWave) hist[(int64_t)d * nblocks + tile] = cnt[d];
     }
 }
 
@@ -148,34 +160,28 @@ __global__ void __launch_bounds__(GS_THREADS) k_gs_scatter(const uint64_t *keys_
     }
 }
 
-// Runs of equal keys in the sorted stream.  Persistent workgroups take
-// tiles b = blockIdx.x, blockIdx.x + gridDim.x, ...  When both coefficient
-// arrays fit (ta + tb <= GS_MERGE_COEFS) they are staged in LDS once per
-// workgroup, so forming a product costs two LDS reads.  Per tile, the keys
-// are staged in LDS and every lane forms the products c_i * c_j of its
-// elements from the raw indices, (i, j) = (r / tb, r % tb); the lane holding
-// a run's first element then sums the run left to right from LDS (and from
-// global memory for the part of a run past the tile).  Kept sums are staged
-// in element order at [b * GS_TILE, ...).
+// Runs of equal keys in the sorted stream.  Per tile of GS_TILE elements:
+// the keys are staged in LDS and every lane forms the products c_i * c_j of
+// its elements from the raw indices, (i, j) = (r / tb, r % tb), into LDS, so
+// all coefficient gathers are in flight at once; the run heads (first
+// elements of runs) are compacted in element order, and lane k then sums
+// run k left to right from LDS -- one run per lane, so every lane has work
+// -- continuing from global memory when the tile's last run runs past the
+// tile.  Kept sums are staged in element order at [b * GS_TILE, ...).
+// Persistent workgroups take tiles b = blockIdx.x, blockIdx.x + gridDim.x, ...
 __global__ void __launch_bounds__(GS_THREADS) k_gs_merge(const uint64_t *keys, const uint32_t *vals, int64_t R,
                                                         int64_t ta, int64_t tb, const double *ca,
                                                         const double *cb_s, double tol, uint64_t *st_key,
                                                         double *st_coef, int64_t *seg_count, int64_t *stage_off)
 {
-    extern __shared__ double s_coef[];   // [ta] then [tb] when staged
     __shared__ uint64_t s_key[GS_TILE];
     __shared__ double s_prod[GS_TILE];
+    __shared__ uint32_t s_head[GS_TILE + 1];
     __shared__ uint64_t s_scan[GS_THREADS / kWave];
     constexpr int MI = GS_TILE / GS_THREADS;
-    static_assert(MI <= 4 && GS_THREADS < 65536, "keep flags are packed 16 bits per round");
+    static_assert(MI <= 4 && GS_THREADS < 65536, "flags are packed 16 bits per round");
+    (void)ta;
     const int64_t nb = (R + GS_TILE - 1) / GS_TILE;
-    const bool staged = ta + tb <= GS_MERGE_COEFS;
-    if (staged) {
-        for (int64_t i = threadIdx.x; i < ta; i += GS_THREADS) s_coef[i] = ca[i];
-        for (int64_t j = threadIdx.x; j < tb; j += GS_THREADS) s_coef[ta + j] = cb_s[j];
-    }
-    const double *pa = staged ? s_coef : ca;
-    const double *pb = staged ? s_coef + ta : cb_s;
     const uint32_t tb32 = (uint32_t)tb;
     const double inv_tb = 1.0 / (double)tb;
     auto product = [&](uint32_t r) {
@@ -184,54 +190,84 @@ __global__ void __launch_bounds__(GS_THREADS) k_gs_merge(const uint64_t *keys, c
         if (i * (uint64_t)tb32 > r) --i;
         else if ((uint64_t)(i + 1) * tb32 <= r) ++i;
         const uint32_t j = r - i * tb32;
-        return pa[i] * pb[j];
+        return ca[i] * cb_s[j];
     };
     for (int64_t blk = blockIdx.x; blk < nb; blk += gridDim.x) {
         const int64_t t0 = blk * GS_TILE;
         const int m = (int)(R - t0 < GS_TILE ? R - t0 : GS_TILE);
-        __syncthreads();   // coefficient staging done / previous tile's LDS reads done
-        for (int l = threadIdx.x; l < m; l += GS_THREADS) s_key[l] = keys[t0 + l];
-        for (int l = threadIdx.x; l < m; l += GS_THREADS) s_prod[l] = product(vals[t0 + l]);
-        const uint64_t before = t0 > 0 ? keys[t0 - 1] : 0ull;
-        __syncthreads();
-        // lane t takes elements t, t + GS_THREADS, ... (conflict-free LDS reads);
-        // keep flags of the MI rounds are scanned together, packed 16 bits each
-        uint64_t hk[MI];
-        double hs[MI];
-        uint64_t flags = 0;
+        __syncthreads();   // the previous tile's LDS reads are done
+        uint32_t vr[MI];
 #pragma unroll
         for (int q = 0; q < MI; ++q) {
             const int l = q * GS_THREADS + threadIdx.x;
-            hk[q] = 0;
-            hs[q] = 0.0;
+            if (l < m) {
+                s_key[l] = keys[t0 + l];
+                vr[q] = vals[t0 + l];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < MI; ++q) {
+            const int l = q * GS_THREADS + threadIdx.x;
+            if (l < m) s_prod[l] = product(vr[q]);
+        }
+        const uint64_t before = t0 > 0 ? keys[t0 - 1] : 0ull;
+        __syncthreads();
+        // ---- compact the run heads in element order
+        uint64_t hflags = 0;
+#pragma unroll
+        for (int q = 0; q < MI; ++q) {
+            const int l = q * GS_THREADS + threadIdx.x;
             if (l < m) {
                 const uint64_t key = s_key[l];
                 const bool head = l > 0 ? s_key[l - 1] != key : (t0 == 0 || before != key);
-                if (head) {
-                    double s = s_prod[l];
-                    int f = l + 1;
-                    for (; f < m && s_key[f] == key; ++f) s = s + s_prod[f];
-                    if (f == m)
-                        for (int64_t g = t0 + m; g < R && keys[g] == key; ++g) s = s + product(vals[g]);
-                    if (!(fabs(s) <= tol)) {
-                        hk[q] = key;
-                        hs[q] = s;
-                        flags |= 1ull << (16 * q);
-                    }
+                if (head) hflags |= 1ull << (16 * q);
+            }
+        }
+        uint64_t htot;
+        const uint64_t hpre = block_exclusive_scan<GS_THREADS>(hflags, s_scan, htot);
+        int nh = 0;
+#pragma unroll
+        for (int q = 0; q < MI; ++q) {
+            if ((hflags >> (16 * q)) & 1u)
+                s_head[nh + (int)((hpre >> (16 * q)) & 0xffffu)] = (uint32_t)(q * GS_THREADS + threadIdx.x);
+            nh += (int)((htot >> (16 * q)) & 0xffffu);
+        }
+        if (threadIdx.x == 0) s_head[nh] = (uint32_t)m;
+        __syncthreads();
+        // ---- one run per lane
+        uint64_t hk[MI];
+        double hs[MI];
+        uint64_t kflags = 0;
+#pragma unroll
+        for (int q = 0; q < MI; ++q) {
+            const int k = q * GS_THREADS + threadIdx.x;
+            hk[q] = 0;
+            hs[q] = 0.0;
+            if (k < nh) {
+                const int l = (int)s_head[k], e = (int)s_head[k + 1];
+                const uint64_t key = s_key[l];
+                double s = s_prod[l];
+                for (int f = l + 1; f < e; ++f) s = s + s_prod[f];
+                if (k == nh - 1)
+                    for (int64_t g = t0 + m; g < R && keys[g] == key; ++g) s = s + product(vals[g]);
+                if (!(fabs(s) <= tol)) {
+                    hk[q] = key;
+                    hs[q] = s;
+                    kflags |= 1ull << (16 * q);
                 }
             }
         }
-        uint64_t totals;
-        const uint64_t pre = block_exclusive_scan<GS_THREADS>(flags, s_scan, totals);
+        uint64_t ktot;
+        const uint64_t kpre = block_exclusive_scan<GS_THREADS>(kflags, s_scan, ktot);
         int64_t tot = 0;
 #pragma unroll
         for (int q = 0; q < MI; ++q) {
-            const int64_t rq = (int64_t)((pre >> (16 * q)) & 0xffffu);
-            if ((flags >> (16 * q)) & 1u) {
-                st_key[t0 + tot + rq] = hk[q];
-                st_coef[t0 + tot + rq] = hs[q];
+            if ((kflags >> (16 * q)) & 1u) {
+                const int64_t d = t0 + tot + (int64_t)((kpre >> (16 * q)) & 0xffffu);
+                st_key[d] = hk[q];
+                st_coef[d] = hs[q];
             }
-            tot += (int64_t)((totals >> (16 * q)) & 0xffffu);
+            tot += (int64_t)((ktot >> (16 * q)) & 0xffffu);
         }
         if (threadIdx.x == 0) {
             seg_count[blk] = tot;
