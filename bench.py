@@ -3,9 +3,14 @@
 Default workload (the expand + simplify metric): p and q in n=10 variables,
 degree <= 8, 5,000 distinct terms each, N(0,1) coefficients, exponents packed
 at 5 bits per variable -- 25,000,000 raw product terms per step.  A step is
-one poly_mul call (pack, per-polynomial sort, splitter sampling, bucketed
-expand + sort + merge, scan, unpack); inputs are resident in HBM before the
-timed region and the output/workspace buffers are allocated once.
+one poly_mul call (pack, operand sort, raw product generation, stable radix
+sort of (key, raw index) pairs, in-order run sums with zero drop, scan,
+unpack); inputs are resident in HBM before the timed region and the
+output/workspace buffers are allocated once.  `value` is raw product terms
+merged per second.  The roofline object describes the dominant kernel (one
+radix pass), timed live with HIP events the library records around each of
+its launches; its `traffic` comes from the committed rocprofv3 counter
+summary when that summary was taken on the current kernel sources.
 
 It also measures the evaluation metric: 4,096 polynomials over the full
 degree <= 4 monomial set in n=30 variables (46,376 monomials) at 65,536
@@ -52,6 +57,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the polynomial-matrix workload")
     ap.add_argument("--no-deriv", action="store_true", help="skip the quartic derivative workload")
     ap.add_argument("--graph", action="store_true", help="also time the times+simplify step as a captured HIP graph")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 256 MiB device copy (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
 
 
@@ -93,7 +100,9 @@ def bench_mul(args):
     # the dominant kernel's own duration: HIP events recorded by the library
     # on its launch stream around every bucket-kernel launch of K more steps
     k_ms, k_n = kernel_ms(ph.TIMING_MUL, step, args.steps)
-    return dict(raw=raw, unique=uniq, t=t_ev, t_wall=t_wall, ws_bytes=ws_bytes, wl=wl, k_ms=k_ms, k_n=k_n)
+    sort_path = raw >= ph.tune_get("mul_sort_min_raw")
+    return dict(raw=raw, unique=uniq, t=t_ev, t_wall=t_wall, ws_bytes=ws_bytes, wl=wl, k_ms=k_ms, k_n=k_n,
+                sort_path=sort_path)
 
 
 def kernel_ms(slot, fn, steps):
@@ -111,9 +120,9 @@ def kernel_ms(slot, fn, steps):
     return (ms / n if n else float("nan")), n
 
 
-KERNEL_SOURCES = ["paper_2604_06575_amd/csrc/mul.hip", "paper_2604_06575_amd/csrc/kernels.h",
-                  "paper_2604_06575_amd/csrc/lds_sort.h", "paper_2604_06575_amd/csrc/internal.h"]
-TRAFFIC_FILE = "profiles/k_mul_buckets_lds_n10_5000x5000_traffic.txt"
+KERNEL_SOURCES = ["paper_2604_06575_amd/csrc/mulsort.hip", "paper_2604_06575_amd/csrc/mulsort.h",
+                  "paper_2604_06575_amd/csrc/internal.h"]
+TRAFFIC_FILE = "profiles/k_gs_scatter_times_n10_5000x5000_traffic.txt"
 
 
 def kernel_source_hash():
@@ -268,6 +277,19 @@ def bench_graph(args, m):
     return {"ms_per_step": t * 1e3, "merged_terms_per_s": raw / t}
 
 
+def copy_probe():
+    """A plain device copy of known size (256 MiB, three times): the
+    reference against which the HBM byte counters are scaled."""
+    import torch
+    n = 256 * 1024 * 1024 // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 8, "copies": 3}))
+
+
 def cpu_baseline(args):
     import oracle
     import workloads as W
@@ -292,6 +314,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if args.copy_probe:
+        copy_probe()
+        return
     m = bench_mul(args)
     value = m["raw"] / m["t"]
     # algorithmic bytes of one bucket-kernel launch / its measured duration
@@ -313,9 +338,13 @@ def main():
                                f"N(0,1) coefficients, 5-bit fields",
                    "raw_terms": m["raw"], "merged_terms_out": m["unique"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "k_mul_buckets_lds", "kernel_ms": m["k_ms"], "kernel_launches_timed": m["k_n"],
-                     "algorithmic_bytes": BYTES_PER_RAW_TERM * m["raw"]},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if m["sort_path"] else None,
+                     "kernel": "k_gs_scatter" if m["sort_path"] else "k_mul_buckets_lds",
+                     "kernel_ms": m["k_ms"], "kernel_launches_timed": m["k_n"],
+                     "algorithmic_bytes": BYTES_PER_RAW_TERM * m["raw"],
+                     "algorithmic_bytes_note": "per launch: every (64-bit key, 32-bit raw index) pair read once "
+                                               "and written once (one radix pass) = 24 B x raw terms"},
         "wall_ms_per_step": m["t_wall"] * 1e3,
     }
     if args.graph:

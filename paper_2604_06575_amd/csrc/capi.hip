@@ -410,6 +410,8 @@ void ensure_lds_attrs()
     if (lds_attr_done) return;
     (void)hipFuncSetAttribute((const void *)k_eval_terms, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
     (void)hipFuncSetAttribute((const void *)k_backward_dc, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
+    (void)hipFuncSetAttribute((const void *)k_gs_sort_partner, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(GS_SORT1_CAP * 12));
     (void)hipFuncSetAttribute((const void *)k_mul_buckets_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)MB_LDS_LIMIT);
     lds_attr_done = true;
@@ -746,16 +748,24 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
         hipLaunchKernelGGL(k_pack, dim3(grid1(Tb, 256)), dim3(256), 0, s, b->exps, Tb, n, bits, b->max_exp,
                            (uint64_t *)A.kb, status);
     int64_t *cnt_tmp = at<int64_t>(ws, m.cnt_tmp);
-    const SegArgs sa = presort_args(a, (uint64_t *)A.ka, (uint64_t *)A.ka_s, (uint32_t *)A.perm_a, cnt_tmp,
-                                    at<int64_t>(ws, m.order_a), queues + 0, s);
-    const SegArgs sb = presort_args(b, (uint64_t *)A.kb, (uint64_t *)A.kb_s, (uint32_t *)A.perm_b, cnt_tmp,
-                                    at<int64_t>(ws, m.order_b), queues + 1, s);
-    const int64_t pgrid = std::min<int64_t>(P, (int64_t)device_cus() * tunables().seg_blocks_per_cu);
-    hipLaunchKernelGGL(k_seg_sort2, dim3((unsigned)(2 * pgrid)), dim3(SEG_THREADS), 0, s, sa, sb);
-    hipLaunchKernelGGL(k_mul_sorted_coefs, dim3((unsigned)P), dim3(256), 0, s, a->row_ptr, A.perm_a, a->coefs,
-                       (double *)A.ca_s);
-    hipLaunchKernelGGL(k_mul_sorted_coefs, dim3((unsigned)P), dim3(256), 0, s, b->row_ptr, A.perm_b, b->coefs,
-                       (double *)A.cb_s);
+    if (m.sort_mode && Tb <= GS_SORT1_CAP) {
+        // one pair: only the partner operand needs sorting
+        ensure_lds_attrs();
+        hipLaunchKernelGGL(k_gs_sort_partner, dim3(1), dim3(GS_THREADS), (size_t)GS_SORT1_CAP * 12, s,
+                           (const uint64_t *)A.kb, b->coefs, Tb, (uint64_t *)A.kb_s, (uint32_t *)A.perm_b,
+                           (double *)A.cb_s);
+    } else {
+        const SegArgs sa = presort_args(a, (uint64_t *)A.ka, (uint64_t *)A.ka_s, (uint32_t *)A.perm_a, cnt_tmp,
+                                        at<int64_t>(ws, m.order_a), queues + 0, s);
+        const SegArgs sb = presort_args(b, (uint64_t *)A.kb, (uint64_t *)A.kb_s, (uint32_t *)A.perm_b, cnt_tmp,
+                                        at<int64_t>(ws, m.order_b), queues + 1, s);
+        const int64_t pgrid = std::min<int64_t>(P, (int64_t)device_cus() * tunables().seg_blocks_per_cu);
+        hipLaunchKernelGGL(k_seg_sort2, dim3((unsigned)(2 * pgrid)), dim3(SEG_THREADS), 0, s, sa, sb);
+        hipLaunchKernelGGL(k_mul_sorted_coefs, dim3((unsigned)P), dim3(256), 0, s, a->row_ptr, A.perm_a, a->coefs,
+                           (double *)A.ca_s);
+        hipLaunchKernelGGL(k_mul_sorted_coefs, dim3((unsigned)P), dim3(256), 0, s, b->row_ptr, A.perm_b, b->coefs,
+                           (double *)A.cb_s);
+    }
     if (m.sort_mode) {
         // ---- one pair: generate the raw product, radix sort it, merge runs
         ensure_lds_attrs();

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "internal.h"
+#include "mulsort.h"
 
 namespace polyhip {
 
@@ -108,22 +109,6 @@ constexpr size_t MB_LDS_LIMIT = 72 * 1024;     // with the static part, within 1
 constexpr int64_t MB_MAX_PARTNERS = 1 << 30;
 __global__ void k_mul_buckets_lds(MulArgs A);
 __global__ void k_mul_sorted_coefs(const int64_t *rp, const uint32_t *perm, const double *c, double *out);
-// Global radix-sort path for one large pair (mulsort.hip).
-constexpr int GS_THREADS = 1024;
-constexpr int GS_ITEMS = 4;
-constexpr int GS_TILE = GS_THREADS * GS_ITEMS;   // elements per workgroup and pass
-constexpr int GS_BITS = 8;                       // digit width
-constexpr int GS_BINS = 1 << GS_BITS;
-constexpr int GS_HIST_THREADS = 256;
-__global__ void k_gs_generate(const uint64_t *ka, const uint64_t *kb_s, int64_t ta, int64_t tb, uint64_t *keys,
-                              uint32_t *vals);
-__global__ void k_gs_hist(const uint64_t *keys, int64_t R, int shift, int64_t nblocks, int64_t *hist);
-__global__ void k_gs_scatter(const uint64_t *keys_in, const uint32_t *vals_in, int64_t R, int shift,
-                             int64_t nblocks, const int64_t *hist_off, uint64_t *keys_out, uint32_t *vals_out);
-__global__ void k_gs_merge(const uint64_t *keys, const uint32_t *vals, int64_t R, int64_t ta, int64_t tb,
-                           const double *ca, const double *cb_s, double tol, uint64_t *st_key, double *st_coef,
-                           int64_t *seg_count, int64_t *stage_off);
-__global__ void k_gs_rowptr(const int64_t *out_off, int64_t nblocks, int64_t *row_ptr);
 __global__ void k_mul_rowptr(const int64_t *out_off, const int64_t *pb_start, int64_t P, int64_t *out_rp,
                              int64_t nbuckets);
 

@@ -13,11 +13,48 @@
 // shared unpack kernel.  All traffic is streaming HBM traffic: the sort is
 // bandwidth-bound, with no per-row state on chip.
 #include "kernels.h"
+#include "lds_sort.h"
 
 // products and sums are rounded separately, as in the definition (no FMA)
 #pragma clang fp contract(off)
 
 namespace polyhip {
+
+// The partner operand in ascending key order, stably (equal keys keep
+// storage order), in one workgroup (T <= GS_SORT1_CAP): sorted keys, the
+// storage index of each sorted position, and the coefficients in sorted
+// order.  Keys are sorted relative to their minimum, on the occupied bits.
+// Dynamic LDS: GS_SORT1_CAP * 12 bytes.
+__global__ void __launch_bounds__(GS_THREADS) k_gs_sort_partner(const uint64_t *keys, const double *coefs, int64_t T,
+                                                               uint64_t *keys_s, uint32_t *perm, double *coefs_s)
+{
+    extern __shared__ uint64_t s_dyn[];
+    uint64_t *sk = s_dyn;
+    uint32_t *sv = reinterpret_cast<uint32_t *>(s_dyn + GS_SORT1_CAP);
+    __shared__ uint32_t s_cnt[(GS_THREADS / kWave) * 256];
+    __shared__ uint32_t s_scan[GS_THREADS / kWave];
+    __shared__ uint64_t s_red[GS_THREADS / kWave];
+    const int m = (int)T;
+    uint64_t lmin = ~0ull, lmax = 0;
+    for (int i = threadIdx.x; i < m; i += GS_THREADS) {
+        const uint64_t k = keys[i];
+        sk[i] = k;
+        sv[i] = (uint32_t)i;
+        lmin = k < lmin ? k : lmin;
+        lmax = k > lmax ? k : lmax;
+    }
+    const uint64_t kmin = block_min_u64<GS_THREADS>(lmin, s_red);
+    const uint64_t kmax = block_max_u64<GS_THREADS>(lmax, s_red);
+    for (int i = threadIdx.x; i < m; i += GS_THREADS) sk[i] -= kmin;
+    __syncthreads();
+    const int bits = kmax > kmin ? 64 - __clzll((unsigned long long)(kmax - kmin)) : 0;
+    lds_radix_sort<GS_THREADS, GS_SORT1_CAP / GS_THREADS, uint32_t>(sk, sv, m, bits, s_cnt, s_scan);
+    for (int i = threadIdx.x; i < m; i += GS_THREADS) {
+        keys_s[i] = sk[i] + kmin;
+        perm[i] = sv[i];
+        coefs_s[i] = coefs[sv[i]];
+    }
+}
 
 // raw pair (i, j) -> (key, i * tb + j), one block row per term of p
 __global__ void __launch_bounds__(GS_THREADS) k_gs_generate(const uint64_t *ka, const uint64_t *kb_s, int64_t ta,
