@@ -14,6 +14,7 @@ import os
 import sys
 import time
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -59,15 +60,36 @@ def main():
     args = ap.parse_args()
     ph.lib()
     log = {}
-    # times + simplify: raw terms per bucket workgroup
-    wl = W.plain_large()
-    a = ph.batch_from_numpy([0, 5000], wl.a_exps, wl.a_coefs, n=10, max_exp=8)
-    b = ph.batch_from_numpy([0, 5000], wl.b_exps, wl.b_coefs, n=10, max_exp=8)
+    # times + simplify of batches (bucket path): raw terms per bucket workgroup
+    pairs = [W.plain_large(seed=W.SEED_BASE + 70 + k, terms=1200, n=8, d=8) for k in range(8)]
+    rp = np.arange(9, dtype=np.int64) * 1200
+    a = ph.batch_from_numpy(rp, np.concatenate([w.a_exps for w in pairs]), np.concatenate([w.a_coefs for w in pairs]),
+                            n=8, max_exp=8)
+    b = ph.batch_from_numpy(rp, np.concatenate([w.b_exps for w in pairs]), np.concatenate([w.b_coefs for w in pairs]),
+                            n=8, max_exp=8)
     ws_bytes, raw = ph.mul_workspace(a, b)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
-    out = ph._empty_out(10, 1, raw, 16, "cuda")
-    sweep("mul_bucket_terms", [4096, 8192, 12288, 16384, 24576, 32768, 65536],
+    out = ph._empty_out(8, 8, raw, 16, "cuda")
+    sweep("mul_bucket_terms", [8192, 16384, 32768, 65536],
           lambda: ph.mul(a, b, ws=ws, out=out, finish=False), log)
+    del ws, out
+    # one pair: the raw size from which the radix-sort path beats the bucket path
+    rows, threshold = [], None
+    for terms in (300, 700, 1500, 3000):
+        w = W.plain_large(seed=W.SEED_BASE + 80, terms=terms, n=8, d=8)
+        a1 = ph.batch_from_numpy([0, terms], w.a_exps, w.a_coefs, n=8, max_exp=8)
+        b1 = ph.batch_from_numpy([0, terms], w.b_exps, w.b_coefs, n=8, max_exp=8)
+        ph.tune_set("mul_sort_min_raw", 0)
+        t_sort = _time(lambda: ph.mul(a1, b1))
+        ph.tune_set("mul_sort_min_raw", 1 << 62)
+        t_bucket = _time(lambda: ph.mul(a1, b1))
+        rows.append({"raw": terms * terms, "sort_ms": t_sort, "bucket_ms": t_bucket})
+        print(f"one pair raw={terms * terms}: sort {t_sort:.3f} ms, bucket {t_bucket:.3f} ms", flush=True)
+        if threshold is None and t_sort < t_bucket:
+            threshold = terms * terms
+    threshold = threshold if threshold is not None else 1 << 62
+    ph.tune_set("mul_sort_min_raw", threshold)
+    log["mul_sort_min_raw"] = {"best": threshold, "sweep": rows}
     # batched simplify: persistent workgroups per CU
     bm = W.batch_matrix(npts=0)
     bb = ph.batch_from_numpy(bm.row_ptr, bm.exps, bm.coefs, n=bm.n, max_exp=bm.max_exp)
