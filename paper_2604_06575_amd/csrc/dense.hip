@@ -43,27 +43,33 @@ __device__ inline double powi_d(double x, uint32_t e)
     return p;
 }
 
-// Monomial value for basis term k (encoded support) at a point whose
-// coordinates are x[i * xs].
-__device__ inline double basis_value(const uint64_t *enc, const uint8_t *basis, int n, int64_t k, const double *x,
-                                     int xs)
+// Monomial value of a basis term from its factor list (k_encode_factors
+// layout: up to EV_MAX_DEG variable indices, padded with n, degree in the
+// last word) at the point x[i * xs], i = variable; the point tile holds a row
+// of ones at i = n.  The reads of a chunk of four factors are issued before
+// its multiplications; the product runs left to right.  Terms of higher
+// degree are evaluated from their exponent row.
+__device__ inline double factor_chunk(double v, uint32_t word, const double *x, int xs)
 {
-    const uint64_t w0 = enc[2 * k];
-    const uint64_t w1 = enc[2 * k + 1];
+    const double x0 = x[(word & 0xffu) * xs];
+    const double x1 = x[((word >> 8) & 0xffu) * xs];
+    const double x2 = x[((word >> 16) & 0xffu) * xs];
+    const double x3 = x[(word >> 24) * xs];
+    return (((v * x0) * x1) * x2) * x3;
+}
+
+__device__ inline double factor_value(const uint4 &w, const uint8_t *row, int n, const double *x, int xs)
+{
+    const uint32_t d = w.w;
     double v = 1.0;
-    if ((w0 & 0xffffull) == 0xffffull) {
-        const uint8_t *row = basis + k * n;
+    if (d > (uint32_t)EV_MAX_DEG) {
         for (int i = 0; i < n; ++i)
             if (row[i]) v = v * powi_d(x[i * xs], row[i]);
         return v;
     }
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        const uint32_t ent = (uint32_t)(((s < 4 ? w0 : w1) >> (16 * (s & 3))) & 0xffffu);
-        const uint32_t e = ent >> 8;
-        if (e == 0) break;
-        v = v * powi_d(x[(ent & 0xffu) * xs], e);
-    }
+    if (d > 0) v = factor_chunk(v, w.x, x, xs);
+    if (d > 4) v = factor_chunk(v, w.y, x, xs);
+    if (d > 8) v = factor_chunk(v, w.z, x, xs);
     return v;
 }
 
@@ -86,12 +92,13 @@ __device__ inline unsigned short bf16_bits_exact(float f)
 constexpr int D64_BM = 64, D64_BN = 128, D64_KS = 16, D64_THREADS = 256;
 
 // grid: x = N tiles (fastest, so concurrently running workgroups share a C
-// row panel), y = P tiles.  Dynamic LDS: n * D64_BN doubles for the points.
+// row panel), y = P tiles.  Dynamic LDS: (n + 1) * D64_BN doubles for the
+// points and a row of ones.
 __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, const uint8_t *basis,
-                                                           const uint64_t *enc, int64_t P, const double *C,
+                                                           const uint4 *enc, int64_t P, const double *C,
                                                            int64_t N, const double *X, double *Y)
 {
-    extern __shared__ double s_x[];                    // [n][D64_BN]
+    extern __shared__ double s_x[];                    // [n + 1][D64_BN], last row ones
     __shared__ double s_c[D64_BM][D64_KS + 1];
     __shared__ double s_v[D64_KS][D64_BN + 2];
     const int tid = threadIdx.x;
@@ -100,10 +107,10 @@ __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, con
     const int wr = w >> 1, wc = w & 1;                 // wave: 32 rows x 64 points
     const int64_t r0 = (int64_t)blockIdx.y * D64_BM;
     const int64_t n0 = (int64_t)blockIdx.x * D64_BN;
-    for (int idx = tid; idx < n * D64_BN; idx += D64_THREADS) {
+    for (int idx = tid; idx < (n + 1) * D64_BN; idx += D64_THREADS) {
         const int i = idx / D64_BN, c = idx % D64_BN;
         const int64_t pt = n0 + c;
-        s_x[idx] = pt < N ? X[pt * n + i] : 0.0;
+        s_x[idx] = i == n ? 1.0 : (pt < N ? X[pt * n + i] : 0.0);
     }
     d4v acc[2][4];
 #pragma unroll
@@ -120,7 +127,8 @@ __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, con
 #pragma unroll
     for (int q = 0; q < 4; ++q) creg[q] = (cr < P && ckk + q < K) ? C[cr * K + ckk + q] : 0.0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) vreg[q] = vkb + q < K ? basis_value(enc, basis, n, vkb + q, s_x + vcol, D64_BN) : 0.0;
+    for (int q = 0; q < 8; ++q)
+        vreg[q] = vkb + q < K ? factor_value(enc[vkb + q], basis + (int64_t)(vkb + q) * n, n, s_x + vcol, D64_BN) : 0.0;
     for (int64_t k0 = 0; k0 < K; k0 += D64_KS) {
         __syncthreads();
 #pragma unroll
@@ -151,7 +159,9 @@ __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, con
         if (k1 < K) {
 #pragma unroll
             for (int q = 0; q < 8; ++q)
-                vreg[q] = k1 + vkb + q < K ? basis_value(enc, basis, n, k1 + vkb + q, s_x + vcol, D64_BN) : 0.0;
+                vreg[q] = k1 + vkb + q < K
+                              ? factor_value(enc[k1 + vkb + q], basis + (k1 + vkb + q) * n, n, s_x + vcol, D64_BN)
+                              : 0.0;
         }
     }
 #pragma unroll
@@ -202,23 +212,23 @@ __global__ void __launch_bounds__(DN_KB) k_split_c(const double *C, int64_t P, i
 
 // Column scales of V per K-block: sig_v[kb * N + pt].  One block per
 // (K-block, 64 points); thread (point, group) scans 32 monomials.
-__global__ void __launch_bounds__(256) k_split_vscale(int n, int64_t K, const uint8_t *basis, const uint64_t *enc,
+__global__ void __launch_bounds__(256) k_split_vscale(int n, int64_t K, const uint8_t *basis, const uint4 *enc,
                                                       int64_t N, const double *X, int32_t *sig_v)
 {
-    extern __shared__ double s_xv[];               // [n][64]
+    extern __shared__ double s_xv[];               // [n + 1][64], last row ones
     __shared__ double s_m[4][64];
     const int64_t ntile = ceil_div(N, 64);
     const int64_t kb = blockIdx.x / ntile, pt0 = (blockIdx.x % ntile) * 64;
-    for (int idx = threadIdx.x; idx < n * 64; idx += 256) {
+    for (int idx = threadIdx.x; idx < (n + 1) * 64; idx += 256) {
         const int i = idx / 64, c = idx % 64;
-        s_xv[idx] = pt0 + c < N ? X[(pt0 + c) * n + i] : 0.0;
+        s_xv[idx] = i == n ? 1.0 : (pt0 + c < N ? X[(pt0 + c) * n + i] : 0.0);
     }
     __syncthreads();
     const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
     double amax = 0.0;
     for (int q = 0; q < DN_KB / 4; ++q) {
         const int64_t k = kb * DN_KB + g * (DN_KB / 4) + q;
-        if (k < K) amax = fmax(amax, fabs(basis_value(enc, basis, n, k, s_xv + c, 64)));
+        if (k < K) amax = fmax(amax, fabs(factor_value(enc[k], basis + k * n, n, s_xv + c, 64)));
     }
     s_m[g][c] = amax;
     __syncthreads();
@@ -226,7 +236,7 @@ __global__ void __launch_bounds__(256) k_split_vscale(int n, int64_t K, const ui
         sig_v[kb * N + pt0 + c] = scale_exp(fmax(fmax(s_m[0][c], s_m[1][c]), fmax(s_m[2][c], s_m[3][c])));
 }
 
-constexpr int SP_BM = 128, SP_BN = 128, SP_KS = 32, SP_THREADS = 512;
+constexpr int SP_KS = 32, SP_THREADS = 512;
 // FP32 accumulator groups per tile: diagonals 2 and 3 (exact integer sums on
 // their own scale) and one shared group for diagonals >= 4 (at most 2^-16 of
 // the leading term), whose FP32 rounding sets an error floor near 2^-34 of
@@ -240,30 +250,45 @@ __device__ inline uint32_t pack_bf16x2(float lo, float hi)
     return (__float_as_uint(lo) >> 16) | (__float_as_uint(hi) & 0xffff0000u);
 }
 
-// grid: x = N tiles, y = P tiles.  Waves: 4 row tiles of 32 x 2 column
+__host__ __device__ constexpr size_t split_lds_bytes(int n, int S, int BM, int BN)
+{
+    return (size_t)(n + 1) * BN * 8 + (size_t)S * (BM + BN) * SP_LDK * 2 + (size_t)SP_KS * 16;
+}
+
+// grid: x = N tiles of BN, y = P tiles of BM (BM x BN = 256 x 64 or 128 x
+// 128).  The 8 waves tile the block as (BM/32) row tiles x (BN/64) column
 // halves of 64 (two 32 x 32 MFMA tiles each), SP_GROUPS accumulator groups
-// per tile.  Dynamic LDS: points [n][SP_BN]
-// doubles, C digits [S][SP_BM][SP_LDK], V digits [S][SP_BN][SP_LDK] (bf16).
-template <int S>
+// per tile.  Every K step, each thread forms the V digits of one point for
+// VK consecutive k; a V tile feeds BM rows of C, so the taller tile halves the
+// digit-generation work per MFMA.  Dynamic LDS: points [n][BN] doubles, C
+// digits [S][BM][SP_LDK], V digits [S][BN][SP_LDK] (bf16).
+template <int S, int BM, int BN>
 __global__ void __launch_bounds__(SP_THREADS) k_dense_split(int n, int64_t K, int64_t Kp, const uint8_t *basis,
-                                                            const uint64_t *enc, int64_t P,
+                                                            const uint4 *enc, int64_t P,
                                                             const unsigned short *Cs, int64_t N, const double *X,
                                                             const int32_t *sig_v, double *Y)
 {
+    constexpr int WR = BM / 32;                       // row tiles
+    static_assert(WR * (BN / 64) == SP_THREADS / 64, "one 32 x 64 tile per wave");
+    constexpr int VK = SP_KS * BN / SP_THREADS;       // V values per thread per K step
+    static_assert(VK == 4 || VK == 8, "V digits are stored as 2 or 4 words");
+    constexpr int CL = (S * BM * (SP_KS / 8)) / SP_THREADS;   // 16-byte C loads per thread per K step
+    static_assert(CL * SP_THREADS == S * BM * (SP_KS / 8), "C tile split evenly");
     extern __shared__ double s_dyn[];
-    double *s_x = s_dyn;                                              // [n][SP_BN]
-    unsigned short *s_cd = (unsigned short *)(s_x + n * SP_BN);       // [S][SP_BM][SP_LDK]
-    unsigned short *s_vd = s_cd + S * SP_BM * SP_LDK;                 // [S][SP_BN][SP_LDK]
+    double *s_x = s_dyn;                                              // [n + 1][BN], last row ones
+    unsigned short *s_cd = (unsigned short *)(s_x + (n + 1) * BN);    // [S][BM][SP_LDK]
+    unsigned short *s_vd = s_cd + S * BM * SP_LDK;                    // [S][BN][SP_LDK]
+    uint4 *s_enc = (uint4 *)(s_vd + S * BN * SP_LDK);                 // [SP_KS] factor lists of the K step
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = tid >> 6;
-    const int wr = w >> 1, wc = w & 1;
-    const int64_t r0 = (int64_t)blockIdx.y * SP_BM;
-    const int64_t n0 = (int64_t)blockIdx.x * SP_BN;
-    for (int idx = tid; idx < n * SP_BN; idx += SP_THREADS) {
-        const int i = idx / SP_BN, c = idx % SP_BN;
+    const int wr = w % WR, wc = w / WR;
+    const int64_t r0 = (int64_t)blockIdx.y * BM;
+    const int64_t n0 = (int64_t)blockIdx.x * BN;
+    for (int idx = tid; idx < (n + 1) * BN; idx += SP_THREADS) {
+        const int i = idx / BN, c = idx % BN;
         const int64_t pt = n0 + c;
-        s_x[idx] = pt < N ? X[pt * n + i] : 0.0;
+        s_x[idx] = i == n ? 1.0 : (pt < N ? X[pt * n + i] : 0.0);
     }
     double out[2][16];
     f16v acc[SP_GROUPS][2];
@@ -277,36 +302,38 @@ __global__ void __launch_bounds__(SP_THREADS) k_dense_split(int n, int64_t K, in
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[g][ct][v] = 0.0f;
-    // V generation role of this thread: one point, 8 consecutive k
-    const int vc = tid & (SP_BN - 1);
-    const int vkq = (tid >> 7) * 8;
+    // V generation role of this thread: one point, VK consecutive k
+    const int vc = tid % BN;
+    const int vkq = (tid / BN) * VK;
     const int64_t vpt = n0 + vc;
-    uint4 creg[(S * SP_BM * (SP_KS / 8)) / SP_THREADS];
-    uint32_t dig[S][4];
+    uint4 creg[CL];
+    uint4 ereg = make_uint4(0, 0, 0, 0);   // factor list of k = kk + tid (lanes tid < SP_KS)
+    int sig_next = -1100;
+    uint32_t dig[S][VK / 2];
     auto load_c = [&](int64_t kk) {
+        if (tid < SP_KS) ereg = kk + tid < K ? enc[kk + tid] : make_uint4(0, 0, 0, 0);
+        sig_next = vpt < N ? sig_v[(kk / DN_KB) * N + vpt] : -1100;
 #pragma unroll
-        for (int j = 0; j < (S * SP_BM * (SP_KS / 8)) / SP_THREADS; ++j) {
+        for (int j = 0; j < CL; ++j) {
             const int idx = tid + j * SP_THREADS;
-            const int sl = idx / (SP_BM * (SP_KS / 8));
-            const int rem = idx % (SP_BM * (SP_KS / 8));
+            const int sl = idx / (BM * (SP_KS / 8));
+            const int rem = idx % (BM * (SP_KS / 8));
             const int row = rem / (SP_KS / 8), part = rem % (SP_KS / 8);
             const int64_t r = r0 + row;
             creg[j] = r < P ? *(const uint4 *)(Cs + ((int64_t)sl * P + r) * Kp + kk + part * 8)
                             : make_uint4(0, 0, 0, 0);
         }
     };
-    auto gen_v = [&](int64_t kk) {
-        const int64_t kb = kk / DN_KB;
-        const int sig = vpt < N ? sig_v[kb * N + vpt] : -1100;
+    auto gen_v = [&](int64_t kk, int sig) {
         const bool live = vpt < N && sig > -1100;
         float scale[S];
 #pragma unroll
         for (int t = 0; t < S; ++t) scale[t] = live ? ldexpf(1.0f, sig - 8 * (t + 1)) : 0.0f;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < VK; ++q) {
             const int64_t k = kk + vkq + q;
             double y = 0.0;
-            if (live && k < K) y = ldexp(basis_value(enc, basis, n, k, s_x + vc, SP_BN), -sig);
+            if (live && k < K) y = ldexp(factor_value(s_enc[vkq + q], basis + k * n, n, s_x + vc, BN), -sig);
             // y = yh + yl to 48 bits; digits extracted in FP32
             const float yh = (float)y;
             const float yl = (float)(y - (double)yh);
@@ -327,22 +354,28 @@ __global__ void __launch_bounds__(SP_THREADS) k_dense_split(int n, int64_t K, in
             }
         }
 #pragma unroll
-        for (int d = 0; d < S; ++d)
-            *(uint4 *)(s_vd + (d * SP_BN + vc) * SP_LDK + vkq) = make_uint4(dig[d][0], dig[d][1], dig[d][2], dig[d][3]);
+        for (int d = 0; d < S; ++d) {
+            unsigned short *dst = s_vd + (d * BN + vc) * SP_LDK + vkq;
+            if (VK == 8) *(uint4 *)dst = make_uint4(dig[d][0], dig[d][1], dig[d][2 % (VK / 2)], dig[d][3 % (VK / 2)]);
+            else *(uint2 *)dst = make_uint2(dig[d][0], dig[d][1]);
+        }
     };
     __syncthreads();
     load_c(0);
     for (int64_t k0 = 0; k0 < Kp; k0 += SP_KS) {
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < (S * SP_BM * (SP_KS / 8)) / SP_THREADS; ++j) {
+        for (int j = 0; j < CL; ++j) {
             const int idx = tid + j * SP_THREADS;
-            const int sl = idx / (SP_BM * (SP_KS / 8));
-            const int rem = idx % (SP_BM * (SP_KS / 8));
+            const int sl = idx / (BM * (SP_KS / 8));
+            const int rem = idx % (BM * (SP_KS / 8));
             const int row = rem / (SP_KS / 8), part = rem % (SP_KS / 8);
-            *(uint4 *)(s_cd + (sl * SP_BM + row) * SP_LDK + part * 8) = creg[j];
+            *(uint4 *)(s_cd + (sl * BM + row) * SP_LDK + part * 8) = creg[j];
         }
-        gen_v(k0);
+        if (tid < SP_KS) s_enc[tid] = ereg;
+        const int sig = sig_next;
+        __syncthreads();
+        gen_v(k0, sig);
         __syncthreads();
         const int64_t k1 = k0 + SP_KS;
         if (k1 < Kp) load_c(k1);
@@ -351,13 +384,13 @@ __global__ void __launch_bounds__(SP_THREADS) k_dense_split(int n, int64_t K, in
             s8v a[S];
 #pragma unroll
             for (int s = 0; s < S; ++s)
-                a[s] = *(const s8v *)(s_cd + (s * SP_BM + wr * 32 + (lane & 31)) * SP_LDK + ks + 8 * (lane >> 5));
+                a[s] = *(const s8v *)(s_cd + (s * BM + wr * 32 + (lane & 31)) * SP_LDK + ks + 8 * (lane >> 5));
 #pragma unroll
             for (int t = 0; t < S; ++t) {
                 s8v b[2];
 #pragma unroll
                 for (int ct = 0; ct < 2; ++ct)
-                    b[ct] = *(const s8v *)(s_vd + (t * SP_BN + wc * 64 + ct * 32 + (lane & 31)) * SP_LDK + ks +
+                    b[ct] = *(const s8v *)(s_vd + (t * BN + wc * 64 + ct * 32 + (lane & 31)) * SP_LDK + ks +
                                            8 * (lane >> 5));
 #pragma unroll
                 for (int s = 0; s < S - t; ++s) {
@@ -423,21 +456,35 @@ DensePlan plan_dense(int32_t n, int64_t K, int64_t P, int64_t N, poly_prec prec,
     return d;
 }
 
-template <int S>
-void launch_split(int n, int64_t K, int64_t Kp, const uint8_t *basis, const uint64_t *enc, int64_t P,
-                  const unsigned short *Cs, int64_t N, const double *X, const int32_t *sig_v, double *Y, hipStream_t s)
+template <int S, int BM, int BN>
+void launch_split_tile(int n, int64_t K, int64_t Kp, const uint8_t *basis, const uint4 *enc, int64_t P,
+                       const unsigned short *Cs, int64_t N, const double *X, const int32_t *sig_v, double *Y,
+                       hipStream_t s)
 {
-    const size_t lds = (size_t)n * SP_BN * 8 + (size_t)S * (SP_BM + SP_BN) * SP_LDK * 2;
+    const size_t lds = split_lds_bytes(n, S, BM, BN);
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void *)k_dense_split<S>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipFuncSetAttribute((const void *)k_dense_split<S, BM, BN>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
         attr = true;
     }
-    const dim3 grid((unsigned)ceil_div(N, SP_BN), (unsigned)ceil_div(P, SP_BM));
+    const dim3 grid((unsigned)ceil_div(N, BN), (unsigned)ceil_div(P, BM));
     TimedLaunch tl(POLY_TIMING_DENSE, s);
-    hipLaunchKernelGGL(k_dense_split<S>, grid, dim3(SP_THREADS), lds, s, n, K, Kp, basis, enc, P, Cs, N, X, sig_v,
-                       Y);
+    hipLaunchKernelGGL((k_dense_split<S, BM, BN>), grid, dim3(SP_THREADS), lds, s, n, K, Kp, basis, enc, P, Cs, N, X,
+                       sig_v, Y);
     tl.done(s);
+}
+
+// The 256 x 64 tile (half the digit generation per MFMA) when its LDS fits,
+// else 128 x 128.
+template <int S>
+void launch_split(int n, int64_t K, int64_t Kp, const uint8_t *basis, const uint4 *enc, int64_t P,
+                  const unsigned short *Cs, int64_t N, const double *X, const int32_t *sig_v, double *Y, hipStream_t s)
+{
+    if (split_lds_bytes(n, S, 256, 64) <= 160 * 1024)
+        launch_split_tile<S, 256, 64>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, s);
+    else
+        launch_split_tile<S, 128, 128>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, s);
 }
 
 }  // namespace
@@ -461,16 +508,16 @@ poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_ex
     if (max_exp < 0 || max_exp > 255) return POLY_ERR_ARG;
     if ((K > 0 && (!basis || (P > 0 && !C))) || (N > 0 && !X) || (P > 0 && N > 0 && !Y)) return POLY_ERR_ARG;
     if (!ws || ws_bytes < need) return POLY_ERR_WORKSPACE;
-    if (prec == POLY_FP64 && (size_t)n * D64_BN * 8 > 96 * 1024) return POLY_ERR_UNSUPPORTED;
-    if (prec == POLY_SPLIT_BF16 && (size_t)n * SP_BN * 8 + (size_t)S * (SP_BM + SP_BN) * SP_LDK * 2 > 160 * 1024)
+    if (prec == POLY_FP64 && (size_t)(n + 1) * D64_BN * 8 > 96 * 1024) return POLY_ERR_UNSUPPORTED;
+    if (prec == POLY_SPLIT_BF16 && split_lds_bytes(n, S, 128, 128) > 160 * 1024)
         return POLY_ERR_UNSUPPORTED;
     const DensePlan d = plan_dense(n, K, P, N, prec, S);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (unsigned long long *)ws, 0ull, (int64_t)1);
     if (P == 0 || N == 0) return hipGetLastError() == hipSuccess ? POLY_OK : POLY_ERR_HIP;
-    uint64_t *enc = (uint64_t *)((char *)ws + d.enc);
+    uint4 *enc = (uint4 *)((char *)ws + d.enc);
     if (K > 0)
-        hipLaunchKernelGGL(k_encode_support, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, s, basis, K, n, enc,
-                           (const int64_t *)nullptr);
+        hipLaunchKernelGGL(k_encode_factors, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, s, basis, K, n,
+                           (uint32_t *)enc, (const int64_t *)nullptr);
     if (prec == POLY_FP64) {
         static bool attr = false;
         if (!attr) {
@@ -479,8 +526,8 @@ poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_ex
         }
         const dim3 grid((unsigned)ceil_div(N, D64_BN), (unsigned)ceil_div(P, D64_BM));
         TimedLaunch tl(POLY_TIMING_DENSE, s);
-        hipLaunchKernelGGL(k_dense_f64, grid, dim3(D64_THREADS), (size_t)n * D64_BN * 8, s, n, K, basis, enc, P, C, N,
-                           X, Y);
+        hipLaunchKernelGGL(k_dense_f64, grid, dim3(D64_THREADS), (size_t)(n + 1) * D64_BN * 8, s, n, K, basis,
+                           (const uint4 *)enc, P, C, N, X, Y);
         tl.done(s);
     } else {
         unsigned short *Cs = (unsigned short *)((char *)ws + d.cs);
@@ -490,7 +537,7 @@ poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_ex
         if (K > 0) {
             hipLaunchKernelGGL(k_split_c, dim3((unsigned)(P * nkb)), dim3(DN_KB), 0, s, C, P, K, Kp, S, Cs);
             hipLaunchKernelGGL(k_split_vscale, dim3((unsigned)(nkb * ceil_div(N, 64))), dim3(256),
-                               (size_t)n * 64 * 8, s, n, K, basis, enc, N, X, sig_v);
+                               (size_t)(n + 1) * 64 * 8, s, n, K, basis, (const uint4 *)enc, N, X, sig_v);
         }
         switch (S) {
         case 3: launch_split<3>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, s); break;
