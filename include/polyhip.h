@@ -104,6 +104,8 @@ poly_status poly_read_status(const void *ws, void *stream);
  * Launch parameters chosen by the project's autotuner
  * (paper_2604_06575_amd/autotune.py, cache in paper_2604_06575_amd/tuning/).
  * Names: "mul_bucket_terms"  raw product terms per bucket workgroup (times)
+ *        "mul_sort_min_raw"  raw terms from which a single pair is multiplied
+ *                            by the global radix-sort path instead
  *        "seg_blocks_per_cu" persistent workgroups per CU (simplify, sort)
  *        "eval_blocks_per_cu" point-tile workgroups per CU (sparse eval)
  * poly_tune_set returns POLY_ERR_ARG for an unknown name or a value outside
@@ -115,7 +117,8 @@ poly_status poly_tune_get(const char *name, int64_t *value);
  * Measurement hook for benchmarks.  While enabled, the library records a
  * pair of HIP events on the caller's stream around the dominant kernel of an
  * entry point, in slots:
- *   POLY_TIMING_MUL   the bucketed expand + sort + merge kernel of poly_mul
+ *   POLY_TIMING_MUL   poly_mul: the bucketed expand + sort + merge kernel, or
+ *                     on the radix-sort path each scatter pass
  *   POLY_TIMING_DENSE the contraction kernel of poly_eval_dense
  *   POLY_TIMING_TERMS the term-streaming kernel of poly_eval / grad / hess
  * poly_timing_enable(1) clears every slot and starts recording; (0) stops.
@@ -206,9 +209,16 @@ poly_status poly_eval_backward(const poly_csr *f, const double *X, int64_t N,
  *       exactly in FP32 by BF16 MFMA within each K-block, diagonals >= 4
  *       share one FP32 accumulator, and each K-block is recombined in FP64.
  *       nslices in [3, 6]; pairs with s + t > nslices + 1 are skipped.
- * Error of the split result relative to sum_k |C v| is about
- * max(2^-(8*nslices - 10), 2^-34): digit truncation, or the FP32 rounding of
- * the accumulator shared by digit diagonals s + t >= 4. */
+ * Error of the split result is about max(2^-(8*nslices - 10), 2^-34)
+ * relative to sum over K-blocks b of (sum_{k in b} |C[p,k]|) * max_{k in b}
+ * |v_k(x)| (digits are relative to the block's largest monomial value; this
+ * equals sum_k |C v| when the values of a block share a binade): digit
+ * truncation, or the FP32 rounding of the accumulator shared by digit
+ * diagonals s + t >= 4.
+ * Limits (POLY_ERR_UNSUPPORTED beyond them): the points of one tile and a
+ * row of ones fit in LDS (n <= 94 for FP64, n <= 89 for the split
+ * path at nslices = 5), and K <= 4,194,272 (one workgroup's rows of C, or
+ * of one BF16 slice of C, are addressed with 32-bit byte offsets). */
 poly_status poly_eval_dense_workspace(int32_t n, int64_t K, int64_t P, int64_t N,
                                       poly_prec prec, int32_t nslices, size_t *ws_bytes);
 poly_status poly_eval_dense(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp,

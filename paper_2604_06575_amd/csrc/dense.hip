@@ -31,6 +31,7 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef short s8v __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int DN_KB = 128;      // K-block of the split scheme (exact FP32 sums)
 
@@ -93,7 +94,11 @@ constexpr int D64_BM = 64, D64_BN = 128, D64_KS = 16, D64_THREADS = 256;
 
 // grid: x = N tiles (fastest, so concurrently running workgroups share a C
 // row panel), y = P tiles.  Dynamic LDS: (n + 1) * D64_BN doubles for the
-// points and a row of ones.
+// points and a row of ones.  Each K step: the C tile and the factor lists of
+// the step after next are loaded into registers (buffer loads, so the only
+// per-thread addresses are 32-bit offsets and no load waits on another),
+// the MFMAs of this step run, and the V tile of the next step is formed from
+// factor lists staged in LDS one step ahead.
 __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, const uint8_t *basis,
                                                            const uint4 *enc, int64_t P, const double *C,
                                                            int64_t N, const double *X, double *Y)
@@ -101,6 +106,7 @@ __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, con
     extern __shared__ double s_x[];                    // [n + 1][D64_BN], last row ones
     __shared__ double s_c[D64_BM][D64_KS + 1];
     __shared__ double s_v[D64_KS][D64_BN + 2];
+    __shared__ uint4 s_enc[2][D64_KS];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = tid >> 6;
@@ -119,28 +125,56 @@ __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, con
         for (int b = 0; b < 4; ++b) acc[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
     // load roles: C tile row/k of this thread, V tile point/k of this thread
     const int crow = tid >> 2, ckk = (tid & 3) * 4;
-    const int64_t cr = r0 + crow;
     const int vcol = tid & (D64_BN - 1), vkb = (tid >> 7) * 8;
+    // this block's rows of C as one buffer: rows past P read as zero; the
+    // host keeps D64_BM * K * 8 bytes below 2^31
+    const int rows_here = (int)(P - r0 < D64_BM ? P - r0 : D64_BM);
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc((void *)(C + r0 * K), (short)0,
+                                                                       rows_here * (int)K * 8, 0x00020000);
+    const int cbase = (crow * (int)K + ckk) * 8;
     double creg[4], vreg[8];
+    uint4 ereg = make_uint4(0, 0, 0, 0);
+    auto load_c = [&](int64_t kk) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)   // entries past K (next row's) are masked when stored
+            creg[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rc, cbase + ((int)kk + q) * 8, 0, 0));
+    };
+    auto load_enc = [&](int64_t kk) {   // factor lists of k = kk + tid, tid < D64_KS (zero past K)
+        if (tid < D64_KS) {
+            const __amdgpu_buffer_rsrc_t re = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(enc + kk), (short)0, (int)((K - kk) * 16 > 0 ? (K - kk) * 16 : 0), 0x00020000);
+            const u32x4 e = __builtin_amdgcn_raw_buffer_load_b128(re, tid * 16, 0, 0);
+            ereg = make_uint4(e[0], e[1], e[2], e[3]);
+        }
+    };
+    auto form_v = [&](int64_t kk, const uint4 *le) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            vreg[q] = kk + vkb + q < K ? factor_value(le[vkb + q], basis + (kk + vkb + q) * n, n, s_x + vcol, D64_BN)
+                                       : 0.0;
+    };
+    // stage 0 operands; factor lists of step 1 in flight
+    load_enc(0);
+    load_c(0);
     __syncthreads();
-    // stage 0 operands
-#pragma unroll
-    for (int q = 0; q < 4; ++q) creg[q] = (cr < P && ckk + q < K) ? C[cr * K + ckk + q] : 0.0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-        vreg[q] = vkb + q < K ? factor_value(enc[vkb + q], basis + (int64_t)(vkb + q) * n, n, s_x + vcol, D64_BN) : 0.0;
+    if (tid < D64_KS) s_enc[0][tid] = ereg;
+    load_enc(D64_KS);
+    __syncthreads();
+    form_v(0, s_enc[0]);
+    int par = 1;   // s_enc buffer of the next step's factor lists
     for (int64_t k0 = 0; k0 < K; k0 += D64_KS) {
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s_c[crow][ckk + q] = creg[q];
+        for (int q = 0; q < 4; ++q) s_c[crow][ckk + q] = k0 + ckk + q < K ? creg[q] : 0.0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) s_v[vkb + q][vcol] = vreg[q];
+        if (tid < D64_KS) s_enc[par][tid] = ereg;
         __syncthreads();
         const int64_t k1 = k0 + D64_KS;
-        // next stage's C tile: loads in flight while the MFMAs run
+        // next stage's C tile and the factor lists after it: in flight while the MFMAs run
         if (k1 < K) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) creg[q] = (cr < P && k1 + ckk + q < K) ? C[cr * K + k1 + ckk + q] : 0.0;
+            load_c(k1);
+            load_enc(k1 + D64_KS);
         }
 #pragma unroll
         for (int k4 = 0; k4 < D64_KS; k4 += 4) {
@@ -156,13 +190,8 @@ __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, con
                     acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b[ct], acc[rt][ct], 0, 0, 0);
         }
         // next stage's V tile (VALU work beside the MFMAs)
-        if (k1 < K) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                vreg[q] = k1 + vkb + q < K
-                              ? factor_value(enc[k1 + vkb + q], basis + (k1 + vkb + q) * n, n, s_x + vcol, D64_BN)
-                              : 0.0;
-        }
+        if (k1 < K) form_v(k1, s_enc[par]);
+        par ^= 1;
     }
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
@@ -180,17 +209,28 @@ __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, con
 
 // ------------------------------------------------------------ split kernels
 
-// BF16 digit planes of C with their scale folded in: Cs[s][r][k] over a
-// K stride Kp (multiple of SP_KS, zero padded).  One block per (row, K-block):
-// thread k of the block owns column k0 + k.
+// BF16 digit planes of C with their scale folded in, stored in the operand
+// order of the 32 x 32 x 16 BF16 MFMA: plane s, row block rb = r / 32, k
+// chunk kc = k / 16 form one 1 KB record in which lane l = r % 32 + 32 *
+// ((k % 16) / 8) holds k % 8 = 0..7 as 16 contiguous bytes.  Rows are padded
+// to a multiple of 32 and k to Kp (multiple of SP_KS) with zero digits, so a
+// wave loads its A operand as one coalesced 1 KB read.  One block per (row,
+// K-block): thread k of the block owns column k0 + k.
+__host__ __device__ inline int64_t split_c_index(int64_t s, int64_t r, int64_t k, int64_t RB, int64_t Kp)
+{
+    const int64_t lane = (r & 31) + 32 * ((k & 15) >> 3);
+    return ((((s * RB + (r >> 5)) * (Kp >> 4) + (k >> 4)) * 64 + lane) << 3) + (k & 7);
+}
+
 __global__ void __launch_bounds__(DN_KB) k_split_c(const double *C, int64_t P, int64_t K, int64_t Kp, int S,
                                                    unsigned short *Cs)
 {
     __shared__ double s_red[DN_KB / kWave];
     const int64_t nkb = ceil_div(Kp, DN_KB);
+    const int64_t RB = ceil_div(P, 32);
     const int64_t r = blockIdx.x / nkb, kb = blockIdx.x % nkb;
     const int64_t k = kb * DN_KB + threadIdx.x;
-    const double x = k < K ? C[r * K + k] : 0.0;
+    const double x = (r < P && k < K) ? C[r * K + k] : 0.0;
     double a = fabs(x);
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) a = fmax(a, __shfl_xor(a, o, kWave));
@@ -206,7 +246,7 @@ __global__ void __launch_bounds__(DN_KB) k_split_c(const double *C, int64_t P, i
         y = y * 256.0;
         const double m = rint(y);
         y = y - m;
-        Cs[((int64_t)(s - 1) * P + r) * Kp + k] = bf16_bits_exact(ldexpf((float)m, sig - 8 * s));
+        Cs[split_c_index(s - 1, r, k, RB, Kp)] = bf16_bits_exact(ldexpf((float)m, sig - 8 * s));
     }
 }
 
@@ -237,6 +277,7 @@ __global__ void __launch_bounds__(256) k_split_vscale(int n, int64_t K, const ui
 }
 
 constexpr int SP_KS = 32, SP_THREADS = 512;
+constexpr int SP_BM = 256, SP_BN = 64;   // workgroup tile: 8 waves x (32 rows x 64 points)
 // FP32 accumulator groups per tile: diagonals 2 and 3 (exact integer sums on
 // their own scale) and one shared group for diagonals >= 4 (at most 2^-16 of
 // the leading term), whose FP32 rounding sets an error floor near 2^-34 of
@@ -244,96 +285,129 @@ constexpr int SP_KS = 32, SP_THREADS = 512;
 // lower it but does not fit the register budget of this tile shape.
 constexpr int SP_GROUPS = 3;
 constexpr int SP_LDK = SP_KS + 8;    // padded k stride (bf16 elements) of the LDS digit planes
+constexpr int SP_VK = SP_KS * SP_BN / SP_THREADS;   // V values per thread per K step
 
-__device__ inline uint32_t pack_bf16x2(float lo, float hi)
+__host__ __device__ constexpr size_t split_lds_bytes(int n, int S)
 {
-    return (__float_as_uint(lo) >> 16) | (__float_as_uint(hi) & 0xffff0000u);
+    return (size_t)SP_THREADS * 16 * 8 + (size_t)(n + 1) * SP_BN * 8 + (size_t)2 * S * SP_BN * SP_LDK * 2 +
+           (size_t)2 * SP_KS * 16;
 }
 
-__host__ __device__ constexpr size_t split_lds_bytes(int n, int S, int BM, int BN)
-{
-    return (size_t)(n + 1) * BN * 8 + (size_t)S * (BM + BN) * SP_LDK * 2 + (size_t)SP_KS * 16;
-}
-
-// grid: x = N tiles of BN, y = P tiles of BM (BM x BN = 256 x 64 or 128 x
-// 128).  The 8 waves tile the block as (BM/32) row tiles x (BN/64) column
-// halves of 64 (two 32 x 32 MFMA tiles each), SP_GROUPS accumulator groups
-// per tile.  Every K step, each thread forms the V digits of one point for
-// VK consecutive k; a V tile feeds BM rows of C, so the taller tile halves the
-// digit-generation work per MFMA.  Dynamic LDS: points [n][BN] doubles, C
-// digits [S][BM][SP_LDK], V digits [S][BN][SP_LDK] (bf16).
-template <int S, int BM, int BN>
+// grid: x = N tiles of SP_BN, y = P tiles of SP_BM.  Wave w owns rows
+// r0 + 32 w .. + 31 and all SP_BN points (two 32 x 32 MFMA tiles, SP_GROUPS
+// accumulator groups each).  Its C digits arrive straight from the
+// MFMA-ordered planes into registers (buffer loads, issued as soon as the
+// step's MFMAs have consumed the previous ones); the V digits of a K step are
+// formed once per workgroup into LDS and feed all 8 waves.  V digits and the
+// step's factor lists are double-buffered, so a K step needs one barrier, and
+// the MFMAs of step i and the digit formation of step i + 1 sit in one
+// straight-line block: the formation assumes degree <= 4 (one factor word,
+// no branches), so its VALU and LDS work can issue between the MFMAs; a
+// thread whose monomials have higher degree redoes its values afterwards.
+// The FP64 sums of the first MFMA tile stay in registers, those of the second
+// in LDS (register budget of two waves per SIMD).  Dynamic LDS: FP64 sums
+// [8 waves][16][64 lanes], points [n + 1][BN] doubles (last row ones), V
+// digits [2][S][BN][SP_LDK] bf16, factor lists [2][SP_KS].
+template <int S>
 __global__ void __launch_bounds__(SP_THREADS) k_dense_split(int n, int64_t K, int64_t Kp, const uint8_t *basis,
                                                             const uint4 *enc, int64_t P,
                                                             const unsigned short *Cs, int64_t N, const double *X,
                                                             const int32_t *sig_v, double *Y)
 {
-    constexpr int WR = BM / 32;                       // row tiles
-    static_assert(WR * (BN / 64) == SP_THREADS / 64, "one 32 x 64 tile per wave");
-    constexpr int VK = SP_KS * BN / SP_THREADS;       // V values per thread per K step
-    static_assert(VK == 4 || VK == 8, "V digits are stored as 2 or 4 words");
-    constexpr int CL = (S * BM * (SP_KS / 8)) / SP_THREADS;   // 16-byte C loads per thread per K step
-    static_assert(CL * SP_THREADS == S * BM * (SP_KS / 8), "C tile split evenly");
+    static_assert(SP_VK == 4, "V digits are stored as 2 words per plane");
     extern __shared__ double s_dyn[];
-    double *s_x = s_dyn;                                              // [n + 1][BN], last row ones
-    unsigned short *s_cd = (unsigned short *)(s_x + (n + 1) * BN);    // [S][BM][SP_LDK]
-    unsigned short *s_vd = s_cd + S * BM * SP_LDK;                    // [S][BN][SP_LDK]
-    uint4 *s_enc = (uint4 *)(s_vd + S * BN * SP_LDK);                 // [SP_KS] factor lists of the K step
+    double *s_out = s_dyn;                                            // [8][16][64]
+    double *s_x = s_out + SP_THREADS * 16;                            // [n + 1][BN], last row ones
+    unsigned short *s_vd = (unsigned short *)(s_x + (n + 1) * SP_BN); // [2][S][BN][SP_LDK]
+    uint4 *s_enc = (uint4 *)(s_vd + 2 * S * SP_BN * SP_LDK);         // [2][SP_KS]
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = tid >> 6;
-    const int wr = w % WR, wc = w / WR;
-    const int64_t r0 = (int64_t)blockIdx.y * BM;
-    const int64_t n0 = (int64_t)blockIdx.x * BN;
-    for (int idx = tid; idx < (n + 1) * BN; idx += SP_THREADS) {
-        const int i = idx / BN, c = idx % BN;
+    const int64_t r0 = (int64_t)blockIdx.y * SP_BM;
+    const int64_t n0 = (int64_t)blockIdx.x * SP_BN;
+    const int64_t RB = ceil_div(P, 32);
+    const int64_t KC = Kp >> 4;
+    for (int idx = tid; idx < (n + 1) * SP_BN; idx += SP_THREADS) {
+        const int i = idx / SP_BN, c = idx % SP_BN;
         const int64_t pt = n0 + c;
         s_x[idx] = i == n ? 1.0 : (pt < N ? X[pt * n + i] : 0.0);
     }
-    double out[2][16];
+    double out[16];                                 // tile 0 sums; tile 1 sums in s_out
+    double *my_out = s_out + w * 16 * 64 + lane;    // element v at my_out[64 v]
     f16v acc[SP_GROUPS][2];
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) out[ct][v] = 0.0;
+    for (int v = 0; v < 16; ++v) {
+        out[v] = 0.0;
+        my_out[64 * v] = 0.0;
+    }
 #pragma unroll
     for (int g = 0; g < SP_GROUPS; ++g)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[g][ct][v] = 0.0f;
-    // V generation role of this thread: one point, VK consecutive k
-    const int vc = tid % BN;
-    const int vkq = (tid / BN) * VK;
-    const int64_t vpt = n0 + vc;
-    uint4 creg[CL];
-    uint4 ereg = make_uint4(0, 0, 0, 0);   // factor list of k = kk + tid (lanes tid < SP_KS)
-    int sig_next = -1100;
-    uint32_t dig[S][VK / 2];
-    auto load_c = [&](int64_t kk) {
-        if (tid < SP_KS) ereg = kk + tid < K ? enc[kk + tid] : make_uint4(0, 0, 0, 0);
-        sig_next = vpt < N ? sig_v[(kk / DN_KB) * N + vpt] : -1100;
+
+    // C digits of this wave: plane s, row block r0 / 32 + w.  One buffer per
+    // plane over the workgroup's row blocks that exist (waves past P read
+    // zeros; a load past Kp reads the next row block or zeros, never used);
+    // byte offsets stay below 2^31 (host check on Kp).
+    const int64_t rb0 = r0 >> 5;
+    const int nrb = (int)(RB - rb0 < SP_BM / 32 ? RB - rb0 : SP_BM / 32);
+    const int aoff = ((w * (int)KC) * 64 + lane) * 16;
+    u32x4 A[2][S];
+    auto load_a = [&](int64_t kk) {
 #pragma unroll
-        for (int j = 0; j < CL; ++j) {
-            const int idx = tid + j * SP_THREADS;
-            const int sl = idx / (BM * (SP_KS / 8));
-            const int rem = idx % (BM * (SP_KS / 8));
-            const int row = rem / (SP_KS / 8), part = rem % (SP_KS / 8);
-            const int64_t r = r0 + row;
-            creg[j] = r < P ? *(const uint4 *)(Cs + ((int64_t)sl * P + r) * Kp + kk + part * 8)
-                            : make_uint4(0, 0, 0, 0);
+        for (int s = 0; s < S; ++s) {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(Cs + ((s * RB + rb0) * KC << 9)), (short)0, nrb * (int)KC * 1024, 0x00020000);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                A[j][s] = __builtin_amdgcn_raw_buffer_load_b128(rs, aoff + (int)((kk >> 4) + j) * 1024, 0, 0);
         }
     };
-    auto gen_v = [&](int64_t kk, int sig) {
+    // factor lists of step kk (lanes tid < SP_KS; zero past K) and the scale
+    // exponent of this thread's point for the K-block of step kk
+    uint4 ereg = make_uint4(0, 0, 0, 0);
+    auto load_enc = [&](int64_t kk) {
+        if (tid < SP_KS) {
+            const __amdgpu_buffer_rsrc_t re = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(enc + kk), (short)0, (int)((K - kk) * 16 > 0 ? (K - kk) * 16 : 0), 0x00020000);
+            const u32x4 e = __builtin_amdgcn_raw_buffer_load_b128(re, tid * 16, 0, 0);
+            ereg = make_uint4(e[0], e[1], e[2], e[3]);
+        }
+    };
+    const int vc = tid % SP_BN;
+    const int vkq = (tid / SP_BN) * SP_VK;
+    const int64_t vpt = n0 + vc;
+    auto load_sig = [&](int64_t kk) -> int {   // points past N, steps past Kp read zero; never used
+        const int nrec = kk < Kp ? (int)((N - n0 < SP_BN ? N - n0 : SP_BN) * 4) : 0;
+        const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(sig_v + (kk < Kp ? (kk / DN_KB) * N + n0 : 0)), (short)0, nrec, 0x00020000);
+        return (int)__builtin_amdgcn_raw_buffer_load_b32(rg, vc * 4, 0, 0);
+    };
+    // V digits of step kk (this thread: point vc, k = kk + vkq .. + 3) into
+    // buffer vb.  general = false: one factor word (exact for degree <= 4).
+    auto gen_v = [&](int64_t kk, int sig, int vb, bool general) {
         const bool live = vpt < N && sig > -1100;
+        const uint4 *le = s_enc + vb * SP_KS;
         float scale[S];
 #pragma unroll
         for (int t = 0; t < S; ++t) scale[t] = live ? ldexpf(1.0f, sig - 8 * (t + 1)) : 0.0f;
+        uint32_t dig[S][SP_VK / 2];
 #pragma unroll
-        for (int q = 0; q < VK; ++q) {
+        for (int q = 0; q < SP_VK; ++q) {
             const int64_t k = kk + vkq + q;
-            double y = 0.0;
-            if (live && k < K) y = ldexp(factor_value(s_enc[vkq + q], basis + k * n, n, s_x + vc, BN), -sig);
+            double y;
+            if (general) {
+                y = 0.0;
+                if (live && k < K) y = ldexp(factor_value(le[vkq + q], basis + k * n, n, s_x + vc, SP_BN), -sig);
+            } else {
+                // masked by bits, not by a branch or a product, so the block
+                // stays straight-line and a masked value is exactly 0
+                const double v = factor_chunk(1.0, le[vkq + q].x, s_x + vc, SP_BN);
+                const uint64_t keep = (live && k < K) ? ~0ull : 0ull;
+                y = ldexp(__builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) & keep), -sig);
+            }
             // y = yh + yl to 48 bits; digits extracted in FP32
             const float yh = (float)y;
             const float yl = (float)(y - (double)yh);
@@ -354,43 +428,25 @@ __global__ void __launch_bounds__(SP_THREADS) k_dense_split(int n, int64_t K, in
             }
         }
 #pragma unroll
-        for (int d = 0; d < S; ++d) {
-            unsigned short *dst = s_vd + (d * BN + vc) * SP_LDK + vkq;
-            if (VK == 8) *(uint4 *)dst = make_uint4(dig[d][0], dig[d][1], dig[d][2 % (VK / 2)], dig[d][3 % (VK / 2)]);
-            else *(uint2 *)dst = make_uint2(dig[d][0], dig[d][1]);
-        }
+        for (int d = 0; d < S; ++d)
+            *(uint2 *)(s_vd + ((vb * S + d) * SP_BN + vc) * SP_LDK + vkq) = make_uint2(dig[d][0], dig[d][1]);
     };
-    __syncthreads();
-    load_c(0);
-    for (int64_t k0 = 0; k0 < Kp; k0 += SP_KS) {
-        __syncthreads();
+    auto redo_high_degree = [&](int64_t kk, int sig, int vb) {
+        const uint4 *le = s_enc + vb * SP_KS;
+        bool high = false;
 #pragma unroll
-        for (int j = 0; j < CL; ++j) {
-            const int idx = tid + j * SP_THREADS;
-            const int sl = idx / (BM * (SP_KS / 8));
-            const int rem = idx % (BM * (SP_KS / 8));
-            const int row = rem / (SP_KS / 8), part = rem % (SP_KS / 8);
-            *(uint4 *)(s_cd + (sl * BM + row) * SP_LDK + part * 8) = creg[j];
-        }
-        if (tid < SP_KS) s_enc[tid] = ereg;
-        const int sig = sig_next;
-        __syncthreads();
-        gen_v(k0, sig);
-        __syncthreads();
-        const int64_t k1 = k0 + SP_KS;
-        if (k1 < Kp) load_c(k1);
+        for (int q = 0; q < SP_VK; ++q) high |= le[vkq + q].w > 4u && kk + vkq + q < K;
+        if (high) gen_v(kk, sig, vb, true);
+    };
+    auto mfma_step = [&](int vb) {
 #pragma unroll
-        for (int ks = 0; ks < SP_KS; ks += 16) {
-            s8v a[S];
-#pragma unroll
-            for (int s = 0; s < S; ++s)
-                a[s] = *(const s8v *)(s_cd + (s * BM + wr * 32 + (lane & 31)) * SP_LDK + ks + 8 * (lane >> 5));
+        for (int j = 0; j < 2; ++j) {
 #pragma unroll
             for (int t = 0; t < S; ++t) {
                 s8v b[2];
 #pragma unroll
                 for (int ct = 0; ct < 2; ++ct)
-                    b[ct] = *(const s8v *)(s_vd + (t * BN + wc * 64 + ct * 32 + (lane & 31)) * SP_LDK + ks +
+                    b[ct] = *(const s8v *)(s_vd + ((vb * S + t) * SP_BN + ct * 32 + (lane & 31)) * SP_LDK + 16 * j +
                                            8 * (lane >> 5));
 #pragma unroll
                 for (int s = 0; s < S - t; ++s) {
@@ -398,32 +454,64 @@ __global__ void __launch_bounds__(SP_THREADS) k_dense_split(int n, int64_t K, in
 #pragma unroll
                     for (int ct = 0; ct < 2; ++ct)
                         acc[g][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            __builtin_bit_cast(bf8v, a[s]), __builtin_bit_cast(bf8v, b[ct]), acc[g][ct], 0, 0, 0);
+                            __builtin_bit_cast(bf8v, A[j][s]), __builtin_bit_cast(bf8v, b[ct]), acc[g][ct], 0, 0, 0);
                 }
             }
         }
-        if (((k0 + SP_KS) % DN_KB) == 0 || k0 + SP_KS >= Kp) {
+    };
+    auto fold = [&]() {   // close a K-block: FP32 groups into the FP64 sums
 #pragma unroll
-            for (int ct = 0; ct < 2; ++ct)
+        for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    double t = 0.0;
+            for (int v = 0; v < 16; ++v) {
+                double t = 0.0;
 #pragma unroll
-                    for (int g = SP_GROUPS - 1; g >= 0; --g) {
-                        t += (double)acc[g][ct][v];
-                        acc[g][ct][v] = 0.0f;
-                    }
-                    out[ct][v] += t;
+                for (int g = SP_GROUPS - 1; g >= 0; --g) {
+                    t += (double)acc[g][ct][v];
+                    acc[g][ct][v] = 0.0f;
                 }
-        }
+                if (ct == 0) out[v] += t;
+                else my_out[64 * v] += t;
+            }
+    };
+
+    // prologue: factor lists of steps 0 and 1 staged, V tile of step 0 formed
+    load_a(0);
+    load_enc(0);
+    int sg = load_sig(0);
+    __syncthreads();
+    if (tid < SP_KS) s_enc[tid] = ereg;
+    load_enc(SP_KS);
+    __syncthreads();
+    gen_v(0, sg, 0, false);
+    redo_high_degree(0, sg, 0);
+    if (tid < SP_KS) s_enc[SP_KS + tid] = ereg;
+    load_enc(2 * SP_KS);
+    sg = load_sig(SP_KS);   // during step i: the scale of step i + 1
+    __syncthreads();
+    const int64_t nsteps = Kp / SP_KS;
+    for (int64_t i = 0; i < nsteps; ++i) {
+        const int64_t k1 = (i + 1) * SP_KS;
+        const int vb = (int)(i & 1);
+        mfma_step(vb);
+        load_a(k1);
+        gen_v(k1, sg, vb ^ 1, false);
+        redo_high_degree(k1, sg, vb ^ 1);
+        if ((k1 % DN_KB) == 0 || i + 1 == nsteps) fold();
+        // factor lists of step i + 2 into the buffer step i's lists leave
+        // (those of step i + 3 in flight), and the scale of step i + 2
+        if (tid < SP_KS) s_enc[vb * SP_KS + tid] = ereg;
+        load_enc(k1 + 2 * SP_KS);
+        sg = load_sig(k1 + SP_KS);
+        __syncthreads();
     }
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            const int64_t r = r0 + wr * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-            const int64_t c = n0 + wc * 64 + ct * 32 + (lane & 31);
-            if (r < P && c < N) Y[r * N + c] = out[ct][v];
+            const int64_t r = r0 + w * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            const int64_t c = n0 + ct * 32 + (lane & 31);
+            if (r < P && c < N) Y[r * N + c] = ct == 0 ? out[v] : my_out[64 * v];
         }
 }
 
@@ -449,42 +537,29 @@ DensePlan plan_dense(int32_t n, int64_t K, int64_t P, int64_t N, poly_prec prec,
     d.sigv = 0;
     if (prec == POLY_SPLIT_BF16) {
         const int64_t Kp = align_up((size_t)K, 32);
-        d.cs = take((size_t)S * P * Kp * 2);
+        d.cs = take((size_t)S * ceil_div(P, 32) * 32 * Kp * 2);
         d.sigv = take((size_t)ceil_div(Kp, DN_KB) * N * 4);
     }
     d.total = align_up(off, 256);
     return d;
 }
 
-template <int S, int BM, int BN>
-void launch_split_tile(int n, int64_t K, int64_t Kp, const uint8_t *basis, const uint4 *enc, int64_t P,
-                       const unsigned short *Cs, int64_t N, const double *X, const int32_t *sig_v, double *Y,
-                       hipStream_t s)
-{
-    const size_t lds = split_lds_bytes(n, S, BM, BN);
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void *)k_dense_split<S, BM, BN>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
-        attr = true;
-    }
-    const dim3 grid((unsigned)ceil_div(N, BN), (unsigned)ceil_div(P, BM));
-    TimedLaunch tl(POLY_TIMING_DENSE, s);
-    hipLaunchKernelGGL((k_dense_split<S, BM, BN>), grid, dim3(SP_THREADS), lds, s, n, K, Kp, basis, enc, P, Cs, N, X,
-                       sig_v, Y);
-    tl.done(s);
-}
-
-// The 256 x 64 tile (half the digit generation per MFMA) when its LDS fits,
-// else 128 x 128.
 template <int S>
 void launch_split(int n, int64_t K, int64_t Kp, const uint8_t *basis, const uint4 *enc, int64_t P,
                   const unsigned short *Cs, int64_t N, const double *X, const int32_t *sig_v, double *Y, hipStream_t s)
 {
-    if (split_lds_bytes(n, S, 256, 64) <= 160 * 1024)
-        launch_split_tile<S, 256, 64>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, s);
-    else
-        launch_split_tile<S, 128, 128>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, s);
+    const size_t lds = split_lds_bytes(n, S);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_dense_split<S>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        attr = true;
+    }
+    const dim3 grid((unsigned)ceil_div(N, SP_BN), (unsigned)ceil_div(P, SP_BM));
+    TimedLaunch tl(POLY_TIMING_DENSE, s);
+    hipLaunchKernelGGL((k_dense_split<S>), grid, dim3(SP_THREADS), lds, s, n, K, Kp, basis, enc, P, Cs, N, X, sig_v,
+                       Y);
+    tl.done(s);
 }
 
 }  // namespace
@@ -509,8 +584,10 @@ poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_ex
     if ((K > 0 && (!basis || (P > 0 && !C))) || (N > 0 && !X) || (P > 0 && N > 0 && !Y)) return POLY_ERR_ARG;
     if (!ws || ws_bytes < need) return POLY_ERR_WORKSPACE;
     if (prec == POLY_FP64 && (size_t)(n + 1) * D64_BN * 8 > 96 * 1024) return POLY_ERR_UNSUPPORTED;
-    if (prec == POLY_SPLIT_BF16 && split_lds_bytes(n, S, 128, 128) > 160 * 1024)
-        return POLY_ERR_UNSUPPORTED;
+    if (prec == POLY_SPLIT_BF16 && split_lds_bytes(n, S) > 160 * 1024) return POLY_ERR_UNSUPPORTED;
+    // both kernels address one block's rows of C (64 x K doubles, or 256 x Kp
+    // BF16 digits of one plane) with 32-bit byte offsets
+    if ((int64_t)align_up((size_t)K, 32) * 512 + 256 > INT32_MAX) return POLY_ERR_UNSUPPORTED;
     const DensePlan d = plan_dense(n, K, P, N, prec, S);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (unsigned long long *)ws, 0ull, (int64_t)1);
     if (P == 0 || N == 0) return hipGetLastError() == hipSuccess ? POLY_OK : POLY_ERR_HIP;
@@ -535,7 +612,8 @@ poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_ex
         const int64_t Kp = align_up((size_t)K, 32);
         const int64_t nkb = ceil_div(Kp, DN_KB);
         if (K > 0) {
-            hipLaunchKernelGGL(k_split_c, dim3((unsigned)(P * nkb)), dim3(DN_KB), 0, s, C, P, K, Kp, S, Cs);
+            hipLaunchKernelGGL(k_split_c, dim3((unsigned)(ceil_div(P, 32) * 32 * nkb)), dim3(DN_KB), 0, s, C, P, K,
+                               Kp, S, Cs);
             hipLaunchKernelGGL(k_split_vscale, dim3((unsigned)(nkb * ceil_div(N, 64))), dim3(256),
                                (size_t)(n + 1) * 64 * 8, s, n, K, basis, (const uint4 *)enc, N, X, sig_v);
         }

@@ -342,3 +342,65 @@ def test_dense_split(ph, S):
     assert err.max() <= bound
     if S >= 5:
         assert err.max() <= 1e-10
+
+
+def _dense_case(ph, wl, prec, S=5):
+    Y = ph.eval_dense(torch.from_numpy(wl.basis).cuda(), torch.from_numpy(wl.C).cuda(),
+                      torch.from_numpy(wl.X).cuda(), prec=prec, nslices=S).cpu().numpy()
+    Yo = oracle.eval_dense(wl.basis, wl.C, wl.X)
+    A = oracle.eval_dense(wl.basis, np.abs(wl.C), np.abs(wl.X))
+    return np.abs(Y - Yo) / A
+
+
+def _block_scaled_reference(wl, kb=128):
+    """sum over 128-deep K-blocks b of (sum_{k in b} |c_pk|) * max_{k in b} |v_k(x)|:
+    the quantity the split path's truncation error is proportional to (its
+    digits are relative to the largest monomial value of a block)."""
+    V = oracle.eval_dense(wl.basis, np.eye(wl.basis.shape[0]), wl.X)    # [K, N] monomial values
+    K = V.shape[0]
+    ref = np.zeros((wl.C.shape[0], V.shape[1]))
+    for k0 in range(0, K, kb):
+        ref += np.abs(wl.C[:, k0:k0 + kb]).sum(1)[:, None] * np.abs(V[k0:k0 + kb]).max(0)[None, :]
+    return ref
+
+
+@pytest.mark.parametrize("split", [False, True])
+def test_dense_high_degree(ph, split):
+    """Degrees 0..14 in two variables: monomials of one factor word (<= 4),
+    of up to three words (<= 12) and beyond the factor lists (exponent-row
+    fallback) in the same K steps.  Monomial values span many binades inside
+    a K-block, so the split result is held to its bound relative to the
+    block-scaled reference."""
+    wl = W.dense_shared(seed=960, P=45, N=77, n=2, d=14)
+    say(f"dense high degree split={split}")
+    prec = ph.POLY_SPLIT_BF16 if split else ph.POLY_FP64
+    Y = ph.eval_dense(torch.from_numpy(wl.basis).cuda(), torch.from_numpy(wl.C).cuda(),
+                      torch.from_numpy(wl.X).cuda(), prec=prec, nslices=5).cpu().numpy()
+    Yo = oracle.eval_dense(wl.basis, wl.C, wl.X)
+    if split:
+        err = np.abs(Y - Yo) / _block_scaled_reference(wl)
+        assert err.max() <= max(2.0 ** -(8 * 5 - 12), 2.0 ** -33)
+    else:
+        A = oracle.eval_dense(wl.basis, np.abs(wl.C), np.abs(wl.X))
+        assert (np.abs(Y - Yo) <= 1e-12 * A).all()
+
+
+@pytest.mark.parametrize("split", [False, True])
+def test_dense_several_workgroup_tiles(ph, split):
+    """P = 300 (two row workgroups of the split tile, a partial 32-row block),
+    K = 700 (six 128-deep K-blocks, ragged last step), N = 130 (ragged
+    point tile)."""
+    wl = W.dense_shared(seed=961, P=300, N=130, n=9, d=4, K=700)
+    say(f"dense tiles split={split}")
+    err = _dense_case(ph, wl, ph.POLY_SPLIT_BF16 if split else ph.POLY_FP64)
+    assert err.max() <= (1e-10 if split else 1e-12)
+
+
+def test_dense_empty_basis(ph):
+    """K = 0: every output is the empty sum, 0."""
+    basis = torch.zeros((0, 3), dtype=torch.uint8, device="cuda")
+    C = torch.zeros((5, 0), dtype=torch.float64, device="cuda")
+    X = torch.rand((9, 3), dtype=torch.float64, device="cuda")
+    for prec in (ph.POLY_FP64, ph.POLY_SPLIT_BF16):
+        Y = ph.eval_dense(basis, C, X, prec=prec).cpu().numpy()
+        assert Y.shape == (5, 9) and not Y.any()
