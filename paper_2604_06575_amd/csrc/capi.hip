@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <atomic>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.h"
@@ -177,7 +178,7 @@ struct MulPlan {
     int64_t raw, nbuckets, target;
     bool sort_mode;         // one pair, raw product sorted globally (mulsort.hip)
     size_t gs_keys0, gs_keys1, gs_vals0, gs_vals1, gs_hist, gs_hoff, gs_tmp, gs_count, gs_soff, gs_ooff;
-    int64_t gs_blocks;
+    int64_t gs_blocks, gs_mblocks;   // radix-pass tiles, merge tiles
     bool lds_mode;          // partner and row keys of every pair fit in LDS
     size_t lds_dyn;         // dynamic LDS bytes of the LDS bucket kernel
     size_t total;
@@ -247,10 +248,11 @@ poly_status plan_mul(const poly_csr *a, const poly_csr *b, MulPlan &m)
         m.gs_vals1 = L.take(4 * raw);
         m.gs_hist = L.take(8 * GS_BINS * m.gs_blocks);
         m.gs_hoff = L.take(8 * (GS_BINS * m.gs_blocks + 1));
-        m.gs_tmp = L.take(8 * scan_tmp_count(GS_BINS * m.gs_blocks));
-        m.gs_count = L.take(8 * m.gs_blocks);
-        m.gs_soff = L.take(8 * m.gs_blocks);
-        m.gs_ooff = L.take(8 * (m.gs_blocks + 1));
+        m.gs_tmp = L.take(8 * scan_tmp_count(std::max<int64_t>(GS_BINS * m.gs_blocks, ceil_div(raw, MG_TILE))));
+        m.gs_mblocks = ceil_div(raw, MG_TILE);
+        m.gs_count = L.take(8 * m.gs_mblocks);
+        m.gs_soff = L.take(8 * m.gs_mblocks);
+        m.gs_ooff = L.take(8 * (m.gs_mblocks + 1));
     }
     m.raw = raw;
     m.nbuckets = nb;
@@ -741,12 +743,24 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
     A.st_capacity = m.raw;
     A.status = status;
     hipLaunchKernelGGL(k_mul_init_buckets, dim3(grid1(m.nbuckets, 256)), dim3(256), 0, s, A);
-    if (Ta > 0)
-        hipLaunchKernelGGL(k_pack, dim3(grid1(Ta, 256)), dim3(256), 0, s, a->exps, Ta, n, bits, a->max_exp,
-                           (uint64_t *)A.ka, status);
-    if (Tb > 0)
-        hipLaunchKernelGGL(k_pack, dim3(grid1(Tb, 256)), dim3(256), 0, s, b->exps, Tb, n, bits, b->max_exp,
-                           (uint64_t *)A.kb, status);
+    // the sort path orders mixed-radix keys (radix max_exp(a) + max_exp(b) + 1),
+    // the bucket paths bit-field keys
+    const uint64_t radix = (uint64_t)a->max_exp + (uint64_t)b->max_exp + 1;
+    if (m.sort_mode) {
+        if (Ta > 0)
+            hipLaunchKernelGGL(k_gs_pack_radix, dim3(grid1(Ta, 256)), dim3(256), 0, s, a->exps, Ta, n, radix,
+                               a->max_exp, (uint64_t *)A.ka, status);
+        if (Tb > 0)
+            hipLaunchKernelGGL(k_gs_pack_radix, dim3(grid1(Tb, 256)), dim3(256), 0, s, b->exps, Tb, n, radix,
+                               b->max_exp, (uint64_t *)A.kb, status);
+    } else {
+        if (Ta > 0)
+            hipLaunchKernelGGL(k_pack, dim3(grid1(Ta, 256)), dim3(256), 0, s, a->exps, Ta, n, bits, a->max_exp,
+                               (uint64_t *)A.ka, status);
+        if (Tb > 0)
+            hipLaunchKernelGGL(k_pack, dim3(grid1(Tb, 256)), dim3(256), 0, s, b->exps, Tb, n, bits, b->max_exp,
+                               (uint64_t *)A.kb, status);
+    }
     int64_t *cnt_tmp = at<int64_t>(ws, m.cnt_tmp);
     if (m.sort_mode && Tb <= GS_SORT1_CAP) {
         // one pair: only the partner operand needs sorting
@@ -776,30 +790,83 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
         int64_t *tmp = at<int64_t>(ws, m.gs_tmp);
         hipLaunchKernelGGL(k_gs_generate, dim3((unsigned)std::min<int64_t>(Ta, 65535)), dim3(GS_THREADS), 0, s,
                            A.ka, A.kb_s, Ta, Tb, kcur, vcur);
-        const int key_bits = n * bits;
+        // key range r^n (at most 2^(n * bits), so it fits 64 bits); as few
+        // passes of at most GS_BITS bits as it needs, digits as even as possible
+        unsigned __int128 span = 1;
+        for (int i = 0; i < n; ++i) span *= radix;
+        const uint64_t kmax = (uint64_t)(span - 1);
+        const int key_bits = kmax ? 64 - __builtin_clzll((unsigned long long)kmax) : 0;
+        const int passes = (key_bits + GS_BITS - 1) / GS_BITS;
+        const int db = std::max(passes ? (key_bits + passes - 1) / passes : GS_MIN_BITS, GS_MIN_BITS);
+        // after the first pass, the digits still to sort and the raw index
+        // share one 64-bit word when they fit: 8 bytes per element per pass
+        // instead of 12, keys rebuilt from raw indices by the merge
+        const int raw_bits = R > 1 ? 64 - __builtin_clzll((unsigned long long)(R - 1)) : 0;
+        const bool packed = passes >= 2 && key_bits - db + raw_bits <= 64;
         const int64_t hgrid = std::min<int64_t>(ceil_div(nb, GS_HIST_THREADS / kWave), (int64_t)device_cus() * 8);
-        for (int sh = 0; sh < key_bits; sh += GS_BITS) {
-            hipLaunchKernelGGL(k_gs_hist, dim3((unsigned)hgrid), dim3(GS_HIST_THREADS), 0, s, (const uint64_t *)kcur,
-                               R, sh, nb, hist);
-            launch_scan(hist, GS_BINS * nb, hoff, tmp, s);
+        auto pass = [&](auto dbc, int p) {
+            constexpr int DB = decltype(dbc)::value;
+            const int shift = packed && p > 0 ? raw_bits + (p - 1) * DB : p * DB;
+            hipLaunchKernelGGL(k_gs_hist<DB>, dim3((unsigned)hgrid), dim3(GS_HIST_THREADS), 0, s,
+                               (const uint64_t *)kcur, R, shift, nb, hist);
+            launch_scan(hist, ((int64_t)1 << DB) * nb, hoff, tmp, s);
             TimedLaunch tl(POLY_TIMING_MUL, s);
-            hipLaunchKernelGGL(k_gs_scatter, dim3((unsigned)nb), dim3(GS_THREADS), 0, s, (const uint64_t *)kcur,
-                               (const uint32_t *)vcur, R, sh, nb, (const int64_t *)hoff, knext, vnext);
+            if (!packed)
+                hipLaunchKernelGGL((k_gs_scatter<DB, GS_KV>), dim3((unsigned)nb), dim3(GS_THREADS), 0, s,
+                                   (const uint64_t *)kcur, (const uint32_t *)vcur, R, shift, nb,
+                                   (const int64_t *)hoff, knext, vnext, raw_bits);
+            else if (p == 0)
+                hipLaunchKernelGGL((k_gs_scatter<DB, GS_KV_TO_PACKED>), dim3((unsigned)nb), dim3(GS_THREADS), 0, s,
+                                   (const uint64_t *)kcur, (const uint32_t *)vcur, R, shift, nb,
+                                   (const int64_t *)hoff, knext, vnext, raw_bits);
+            else
+                hipLaunchKernelGGL((k_gs_scatter<DB, GS_PACKED>), dim3((unsigned)nb), dim3(GS_THREADS), 0, s,
+                                   (const uint64_t *)kcur, (const uint32_t *)vcur, R, shift, nb,
+                                   (const int64_t *)hoff, knext, vnext, raw_bits);
             tl.done(s);
+        };
+        for (int p = 0; p < passes; ++p) {
+            switch (db) {
+            case 4: pass(std::integral_constant<int, 4>(), p); break;
+            case 5: pass(std::integral_constant<int, 5>(), p); break;
+            case 6: pass(std::integral_constant<int, 6>(), p); break;
+            case 7: pass(std::integral_constant<int, 7>(), p); break;
+            default: pass(std::integral_constant<int, 8>(), p); break;
+            }
             std::swap(kcur, knext);
             std::swap(vcur, vnext);
         }
         int64_t *cnt = at<int64_t>(ws, m.gs_count), *soff = at<int64_t>(ws, m.gs_soff);
         int64_t *ooff = at<int64_t>(ws, m.gs_ooff);
-        const int64_t mgrid = std::min<int64_t>(nb, (int64_t)device_cus() * 2);
-        hipLaunchKernelGGL(k_gs_merge, dim3((unsigned)mgrid), dim3(GS_THREADS), 0, s, (const uint64_t *)kcur,
-                           (const uint32_t *)vcur, R, Ta, Tb, a->coefs, A.cb_s, zero_tol, A.st_key, A.st_coef, cnt,
-                           soff);
-        launch_scan(cnt, nb, ooff, tmp, s);
-        hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(256), 0, s, (const int64_t *)soff,
+        RadixDecode dec;
+        dec.radix = radix;
+        dec.n = n;
+        dec.bits = bits;
+        dec.chunk = 1;
+        dec.div = radix;
+        while (dec.chunk < n && dec.div * radix <= 0xffffffffull) {
+            dec.div *= radix;
+            ++dec.chunk;
+        }
+        dec.div_magic = ~0ull / dec.div;
+        dec.digit_magic = (uint32_t)(0xffffffffull / radix);
+        const int64_t mb = m.gs_mblocks;
+        const int64_t mgrid = std::min<int64_t>(mb, (int64_t)device_cus() * MG_BLOCKS_PER_CU);
+        if (packed)
+            hipLaunchKernelGGL(k_gs_merge<true>, dim3((unsigned)mgrid), dim3(MG_THREADS), 0, s,
+                               (const uint64_t *)kcur, (const uint32_t *)vcur, R, Ta, Tb, (const uint64_t *)A.ka,
+                               (const uint64_t *)A.kb_s, raw_bits, a->coefs, A.cb_s, zero_tol, dec, A.st_key,
+                               A.st_coef, cnt, soff);
+        else
+            hipLaunchKernelGGL(k_gs_merge<false>, dim3((unsigned)mgrid), dim3(MG_THREADS), 0, s,
+                               (const uint64_t *)kcur, (const uint32_t *)vcur, R, Ta, Tb, (const uint64_t *)A.ka,
+                               (const uint64_t *)A.kb_s, raw_bits, a->coefs, A.cb_s, zero_tol, dec, A.st_key,
+                               A.st_coef, cnt, soff);
+        launch_scan(cnt, mb, ooff, tmp, s);
+        hipLaunchKernelGGL(k_compact, dim3((unsigned)mb), dim3(256), 0, s, (const int64_t *)soff,
                            (const int64_t *)cnt, (const int64_t *)ooff, (const uint64_t *)A.st_key,
                            (const double *)A.st_coef, n, bits, out->exps, out->coefs, out->capacity, status);
-        hipLaunchKernelGGL(k_gs_rowptr, dim3(1), dim3(64), 0, s, (const int64_t *)ooff, nb, out->row_ptr);
+        hipLaunchKernelGGL(k_gs_rowptr, dim3(1), dim3(64), 0, s, (const int64_t *)ooff, mb, out->row_ptr);
         LAUNCH_CHECK();
         return POLY_OK;
     }

@@ -8,19 +8,42 @@ namespace polyhip {
 constexpr int GS_THREADS = 1024;
 constexpr int GS_ITEMS = 4;
 constexpr int GS_TILE = GS_THREADS * GS_ITEMS;   // elements per workgroup and pass
-constexpr int GS_BITS = 8;                       // digit width
+constexpr int GS_BITS = 8;                       // widest digit
 constexpr int GS_BINS = 1 << GS_BITS;
+constexpr int GS_MIN_BITS = 4;                   // narrowest digit instantiated
 constexpr int GS_HIST_THREADS = 256;
 constexpr int GS_SORT1_CAP = 8192;               // partner terms sorted by one workgroup
+constexpr int MG_THREADS = 512;                  // merge workgroup
+constexpr int MG_TILE = MG_THREADS * 4;          // merge elements per tile
+constexpr int MG_BLOCKS_PER_CU = 4;              // persistent merge workgroups per CU
+constexpr int GS_HALO = 64;                      // elements past a tile staged by the merge
+__global__ void k_gs_pack_radix(const uint8_t *exps, int64_t T, int n, uint64_t radix, int max_exp,
+                                uint64_t *keys, int32_t *status);
 __global__ void k_gs_sort_partner(const uint64_t *keys, const double *coefs, int64_t T, uint64_t *keys_s,
                                   uint32_t *perm, double *coefs_s);
 __global__ void k_gs_generate(const uint64_t *ka, const uint64_t *kb_s, int64_t ta, int64_t tb, uint64_t *keys,
                               uint32_t *vals);
+template <int DB>
 __global__ void k_gs_hist(const uint64_t *keys, int64_t R, int shift, int64_t nblocks, int64_t *hist);
+enum { GS_KV = 0, GS_KV_TO_PACKED = 1, GS_PACKED = 2 };   // element formats of a radix pass
+template <int DB, int MODE>
 __global__ void k_gs_scatter(const uint64_t *keys_in, const uint32_t *vals_in, int64_t R, int shift,
-                             int64_t nblocks, const int64_t *hist_off, uint64_t *keys_out, uint32_t *vals_out);
+                             int64_t nblocks, const int64_t *hist_off, uint64_t *keys_out, uint32_t *vals_out,
+                             int raw_bits);
+// Division constants for turning mixed-radix keys back into bit fields.
+struct RadixDecode {
+    uint64_t radix;         // r
+    uint64_t div;           // r^chunk (< 2^32)
+    uint64_t div_magic;     // floor((2^64 - 1) / div)
+    uint32_t digit_magic;   // floor((2^32 - 1) / r)
+    int chunk;              // digits per 64-bit division, 1 <= chunk <= n
+    int n;                  // digits (variables)
+    int bits;               // output field width
+};
+template <bool PACKED>
 __global__ void k_gs_merge(const uint64_t *keys, const uint32_t *vals, int64_t R, int64_t ta, int64_t tb,
-                           const double *ca, const double *cb_s, double tol, uint64_t *st_key, double *st_coef,
+                           const uint64_t *ka, const uint64_t *kb_s, int raw_bits, const double *ca,
+                           const double *cb_s, double tol, RadixDecode dec, uint64_t *st_key, double *st_coef,
                            int64_t *seg_count, int64_t *stage_off);
 __global__ void k_gs_rowptr(const int64_t *out_off, int64_t nblocks, int64_t *row_ptr);
 
