@@ -153,21 +153,23 @@ SimplifyPlan plan_simplify(int64_t P, int64_t T)
 
 // --------------------------------------------------------------- scans
 
-inline int64_t scan_tmp_count(int64_t S) { return 2 * ceil_div(std::max<int64_t>(S, 1), SCAN_TILE) + 1; }
+inline int64_t scan_tmp_count(int64_t S) { return ceil_div(std::max<int64_t>(S, 1), LB_TILE) + 2; }
 
 // out[0..S] = exclusive scan of in[0..S) with out[S] = total; tmp holds
 // scan_tmp_count(S) entries.
-void launch_scan(const int64_t *in, int64_t S, int64_t *out, int64_t *tmp, hipStream_t s)
+void launch_scan(const int64_t *in, int64_t S, int64_t *out, int64_t *tmp, int32_t *status, hipStream_t s,
+                 bool tmp_clear = false)
 {
-    if (S <= 8 * SCAN_TILE) {
+    if (S <= 2048) {
         hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, in, S, out);
         return;
     }
-    const int64_t nt = ceil_div(S, SCAN_TILE);
-    int64_t *sums = tmp, *tile_off = tmp + nt;
-    hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)nt), dim3(SCAN_THREADS), 0, s, in, S, sums);
-    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, sums, nt, tile_off);
-    hipLaunchKernelGGL(k_scan_tile_apply, dim3((unsigned)nt), dim3(SCAN_THREADS), 0, s, in, S, tile_off, out);
+    // single pass with decoupled look-back; its state (tmp) must be zero on
+    // entry: cleared here unless the caller has (tmp_clear), and left dirty
+    const int64_t nt = ceil_div(S, LB_TILE);
+    if (!tmp_clear) clear_u64((unsigned long long *)tmp, nt + 2, s);
+    hipLaunchKernelGGL(k_scan_lookback, dim3((unsigned)nt), dim3(LB_THREADS), 0, s, in, S, out,
+                       (unsigned long long *)tmp, status);
 }
 
 // ---------------------------------------------------------------- mul plan
@@ -384,9 +386,9 @@ void run_form(const FormPlan &fp, FormArgs A, void *ws, hipStream_t s)
     // written: clear them so the scan reads defined values
     if (fp.bounded) clear_u64((unsigned long long *)A.cnt, fp.W * fp.G, s);
     hipLaunchKernelGGL(k_item_count, dim3(grid1(A.P, 256)), dim3(256), 0, s, A.rp, A.P, fp.chunk, items);
-    launch_scan(items, A.P, const_cast<int64_t *>(A.item_start), tmp, s);
+    launch_scan(items, A.P, const_cast<int64_t *>(A.item_start), tmp, A.status, s);
     hipLaunchKernelGGL(k_form_count, dim3((unsigned)fp.W), dim3(JAC_THREADS), 0, s, A);
-    launch_scan(A.cnt, fp.W * fp.G, off, tmp, s);
+    launch_scan(A.cnt, fp.W * fp.G, off, tmp, A.status, s);
     hipLaunchKernelGGL(k_form_rowptr, dim3(grid1(A.P * fp.G + 1, 256)), dim3(256), 0, s, A, (const int64_t *)off);
     hipLaunchKernelGGL(k_form_write, dim3((unsigned)fp.W), dim3(JAC_THREADS), 0, s, A, (const int64_t *)off);
 }
@@ -788,6 +790,10 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
         uint32_t *vcur = at<uint32_t>(ws, m.gs_vals0), *vnext = at<uint32_t>(ws, m.gs_vals1);
         int64_t *hist = at<int64_t>(ws, m.gs_hist), *hoff = at<int64_t>(ws, m.gs_hoff);
         int64_t *tmp = at<int64_t>(ws, m.gs_tmp);
+        // scan state: cleared here for the first pass, then by each pass's
+        // scatter (after its scan has finished) for the next scan
+        const int64_t scan_state = scan_tmp_count(std::max<int64_t>(GS_BINS * m.gs_blocks, ceil_div(R, MG_TILE)));
+        clear_u64((unsigned long long *)tmp, scan_state, s);
         hipLaunchKernelGGL(k_gs_generate, dim3((unsigned)std::min<int64_t>(Ta, 65535)), dim3(GS_THREADS), 0, s,
                            A.ka, A.kb_s, Ta, Tb, kcur, vcur);
         // key range r^n (at most 2^(n * bits), so it fits 64 bits); as few
@@ -809,20 +815,24 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
             const int shift = packed && p > 0 ? raw_bits + (p - 1) * DB : p * DB;
             hipLaunchKernelGGL(k_gs_hist<DB>, dim3((unsigned)hgrid), dim3(GS_HIST_THREADS), 0, s,
                                (const uint64_t *)kcur, R, shift, nb, hist);
-            launch_scan(hist, ((int64_t)1 << DB) * nb, hoff, tmp, s);
+            launch_scan(hist, ((int64_t)1 << DB) * nb, hoff, tmp, status, s, true);
             TimedLaunch tl(POLY_TIMING_MUL, s);
             if (!packed)
-                hipLaunchKernelGGL((k_gs_scatter<DB, GS_KV>), dim3((unsigned)nb), dim3(GS_THREADS), 0, s,
+                hipLaunchKernelGGL((k_gs_scatter<DB, GS_KV>), dim3((unsigned)nb), dim3(GS_SC_THREADS), 0, s,
                                    (const uint64_t *)kcur, (const uint32_t *)vcur, R, shift, nb,
-                                   (const int64_t *)hoff, knext, vnext, raw_bits);
+                                   (const int64_t *)hoff, knext, vnext, raw_bits,
+                                   (unsigned long long *)tmp, scan_state);
             else if (p == 0)
-                hipLaunchKernelGGL((k_gs_scatter<DB, GS_KV_TO_PACKED>), dim3((unsigned)nb), dim3(GS_THREADS), 0, s,
+                hipLaunchKernelGGL((k_gs_scatter<DB, GS_KV_TO_PACKED>), dim3((unsigned)nb), dim3(GS_SC_THREADS), 0,
+                                   s,
                                    (const uint64_t *)kcur, (const uint32_t *)vcur, R, shift, nb,
-                                   (const int64_t *)hoff, knext, vnext, raw_bits);
+                                   (const int64_t *)hoff, knext, vnext, raw_bits,
+                                   (unsigned long long *)tmp, scan_state);
             else
-                hipLaunchKernelGGL((k_gs_scatter<DB, GS_PACKED>), dim3((unsigned)nb), dim3(GS_THREADS), 0, s,
+                hipLaunchKernelGGL((k_gs_scatter<DB, GS_PACKED>), dim3((unsigned)nb), dim3(GS_SC_THREADS), 0, s,
                                    (const uint64_t *)kcur, (const uint32_t *)vcur, R, shift, nb,
-                                   (const int64_t *)hoff, knext, vnext, raw_bits);
+                                   (const int64_t *)hoff, knext, vnext, raw_bits,
+                                   (unsigned long long *)tmp, scan_state);
             tl.done(s);
         };
         for (int p = 0; p < passes; ++p) {
@@ -862,7 +872,7 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
                                (const uint64_t *)kcur, (const uint32_t *)vcur, R, Ta, Tb, (const uint64_t *)A.ka,
                                (const uint64_t *)A.kb_s, raw_bits, a->coefs, A.cb_s, zero_tol, dec, A.st_key,
                                A.st_coef, cnt, soff);
-        launch_scan(cnt, mb, ooff, tmp, s);
+        launch_scan(cnt, mb, ooff, tmp, status, s, true);
         hipLaunchKernelGGL(k_compact, dim3((unsigned)mb), dim3(256), 0, s, (const int64_t *)soff,
                            (const int64_t *)cnt, (const int64_t *)ooff, (const uint64_t *)A.st_key,
                            (const double *)A.st_coef, n, bits, out->exps, out->coefs, out->capacity, status);

@@ -42,11 +42,13 @@ __global__ void k_seg_merge(SegArgs A);
 __global__ void k_seg_sort(SegArgs A);
 __global__ void k_seg_sort2(SegArgs A, SegArgs B);
 __global__ void k_scan_counts(const int64_t *counts, int64_t S, int64_t *out);
-constexpr int SCAN_THREADS = 256;
-constexpr int SCAN_ITEMS = 16;
-constexpr int64_t SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
-__global__ void k_scan_tile_sums(const int64_t *in, int64_t S, int64_t *sums);
-__global__ void k_scan_tile_apply(const int64_t *in, int64_t S, const int64_t *tile_off, int64_t *out);
+// Single-pass exclusive scan (decoupled look-back).  `state` holds 2 +
+// ceil(S / LB_TILE) words that must be zero on entry; they are not on exit.
+constexpr int LB_THREADS = 256;
+constexpr int LB_ITEMS = 16;
+constexpr int64_t LB_TILE = LB_THREADS * LB_ITEMS;
+__global__ void k_scan_lookback(const int64_t *in, int64_t S, int64_t *out, unsigned long long *state,
+                                int32_t *status);
 __global__ void k_compact(const int64_t *stage_off, const int64_t *seg_count, const int64_t *out_off,
                           const uint64_t *st_key, const double *st_coef, int n, int bits,
                           uint8_t *out_exps, double *out_coefs, int64_t capacity, int32_t *status);

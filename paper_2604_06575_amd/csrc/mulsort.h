@@ -5,9 +5,10 @@
 
 namespace polyhip {
 
-constexpr int GS_THREADS = 1024;
-constexpr int GS_ITEMS = 4;
-constexpr int GS_TILE = GS_THREADS * GS_ITEMS;   // elements per workgroup and pass
+constexpr int GS_THREADS = 1024;                 // operand sort, raw product generation
+constexpr int GS_SC_THREADS = 512;               // radix-pass (scatter) workgroup
+constexpr int GS_ITEMS = 8;
+constexpr int GS_TILE = GS_SC_THREADS * GS_ITEMS;   // elements per scatter workgroup and pass
 constexpr int GS_BITS = 8;                       // widest digit
 constexpr int GS_BINS = 1 << GS_BITS;
 constexpr int GS_MIN_BITS = 4;                   // narrowest digit instantiated
@@ -29,7 +30,7 @@ enum { GS_KV = 0, GS_KV_TO_PACKED = 1, GS_PACKED = 2 };   // element formats of 
 template <int DB, int MODE>
 __global__ void k_gs_scatter(const uint64_t *keys_in, const uint32_t *vals_in, int64_t R, int shift,
                              int64_t nblocks, const int64_t *hist_off, uint64_t *keys_out, uint32_t *vals_out,
-                             int raw_bits);
+                             int raw_bits, unsigned long long *clear, int64_t clear_n);
 // Division constants for turning mixed-radix keys back into bit fields.
 struct RadixDecode {
     uint64_t radix;         // r

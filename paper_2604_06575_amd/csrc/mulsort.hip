@@ -156,18 +156,25 @@ __global__ void __launch_bounds__(GS_HIST_THREADS) k_gs_hist(const uint64_t *key
 // that each digit's elements leave as one contiguous run at
 // hist_off[d * nblocks + b].
 //
+// Block 0 also zeroes `clear` (clear_n words): the state of the scan that
+// produced hist_off, ready for the next pass.
+//
 // MODE selects the element format: GS_KV (key array + raw index array, in
 // and out), GS_KV_TO_PACKED (key + raw index in; out one word per element,
 // (key >> DB) << raw_bits | raw index: the digits still to sort above the
 // raw index -- the first pass of a sort whose remaining digits and raw index
 // fit 64 bits), GS_PACKED (packed words in and out).
 template <int DB, int MODE>
-__global__ void __launch_bounds__(GS_THREADS) k_gs_scatter(const uint64_t *keys_in, const uint32_t *vals_in,
+__global__ void __launch_bounds__(GS_SC_THREADS) k_gs_scatter(const uint64_t *keys_in, const uint32_t *vals_in,
                                                           int64_t R, int shift, int64_t nblocks,
                                                           const int64_t *hist_off, uint64_t *keys_out,
-                                                          uint32_t *vals_out, int raw_bits)
+                                                          uint32_t *vals_out, int raw_bits,
+                                                          unsigned long long *clear, int64_t clear_n)
 {
-    constexpr int W = GS_THREADS / kWave;
+    // the scan that produced hist_off is done: reset its state for the next one
+    if (blockIdx.x == 0)
+        for (int64_t i = threadIdx.x; i < clear_n; i += GS_SC_THREADS) clear[i] = 0ull;
+    constexpr int W = GS_SC_THREADS / kWave;
     constexpr int NB = 1 << DB;
     constexpr bool HAS_VALS = MODE != GS_PACKED;
     __shared__ uint64_t s_key[GS_TILE];
@@ -198,7 +205,7 @@ __global__ void __launch_bounds__(GS_THREADS) k_gs_scatter(const uint64_t *keys_
         k[it] = valid ? k[it] : ~0ull;   // padding sorts after every valid element
         dg[it] = valid ? (uint32_t)(k[it] >> shift) & (NB - 1) : (uint32_t)(NB - 1);
     }
-    for (int i = threadIdx.x; i < W * NB; i += GS_THREADS) (&s_cnt[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < W * NB; i += GS_SC_THREADS) (&s_cnt[0][0])[i] = 0;
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < GS_ITEMS; ++it) {
@@ -216,7 +223,7 @@ __global__ void __launch_bounds__(GS_THREADS) k_gs_scatter(const uint64_t *keys_
     }
     __syncthreads();
     // wave prefixes per digit (in place) and digit totals of the tile
-    for (int d = threadIdx.x; d < NB; d += GS_THREADS) {
+    for (int d = threadIdx.x; d < NB; d += GS_SC_THREADS) {
         uint32_t run = 0;
         for (int ww = 0; ww < W; ++ww) {
             const uint32_t c = s_cnt[ww][d];
@@ -229,7 +236,7 @@ __global__ void __launch_bounds__(GS_THREADS) k_gs_scatter(const uint64_t *keys_
     {
         uint32_t tot;
         const uint32_t x = threadIdx.x < NB ? s_tot[threadIdx.x] : 0u;
-        const uint32_t ex = block_exclusive_scan<GS_THREADS>(x, s_scan, tot);
+        const uint32_t ex = block_exclusive_scan<GS_SC_THREADS>(x, s_scan, tot);
         if (threadIdx.x < NB) s_start[threadIdx.x] = ex;
     }
     __syncthreads();
@@ -241,7 +248,7 @@ __global__ void __launch_bounds__(GS_THREADS) k_gs_scatter(const uint64_t *keys_
         if (HAS_VALS) s_val[lp] = v[it];
     }
     __syncthreads();
-    for (int l = threadIdx.x; l < m; l += GS_THREADS) {
+    for (int l = threadIdx.x; l < m; l += GS_SC_THREADS) {
         const uint64_t key = s_key[l];
         const uint32_t d = (uint32_t)(key >> shift) & (NB - 1);
         const int64_t gpos = hist_off[(int64_t)d * nblocks + blockIdx.x] + (l - (int64_t)s_start[d]);
@@ -489,35 +496,50 @@ template __global__ void k_gs_hist<6>(const uint64_t *, int64_t, int, int64_t, i
 template __global__ void k_gs_hist<7>(const uint64_t *, int64_t, int, int64_t, int64_t *);
 template __global__ void k_gs_hist<8>(const uint64_t *, int64_t, int, int64_t, int64_t *);
 template __global__ void k_gs_scatter<4, GS_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int);
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t);
 template __global__ void k_gs_scatter<4, GS_KV_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int);
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t);
 template __global__ void k_gs_scatter<4, GS_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int);
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t);
 template __global__ void k_gs_scatter<5, GS_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int);
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t);
 template __global__ void k_gs_scatter<5, GS_KV_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int);
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t);
 template __global__ void k_gs_scatter<5, GS_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int);
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t);
 template __global__ void k_gs_scatter<6, GS_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int);
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t);
 template __global__ void k_gs_scatter<6, GS_KV_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int);
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t);
 template __global__ void k_gs_scatter<6, GS_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int);
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t);
 template __global__ void k_gs_scatter<7, GS_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int);
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t);
 template __global__ void k_gs_scatter<7, GS_KV_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int);
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t);
 template __global__ void k_gs_scatter<7, GS_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int);
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t);
 template __global__ void k_gs_scatter<8, GS_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int);
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t);
 template __global__ void k_gs_scatter<8, GS_KV_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int);
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t);
 template __global__ void k_gs_scatter<8, GS_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int);
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t);
 template __global__ void k_gs_merge<false>(const uint64_t *, const uint32_t *, int64_t, int64_t, int64_t,
                                            const uint64_t *, const uint64_t *, int, const double *,
                                            const double *, double, RadixDecode, uint64_t *, double *,

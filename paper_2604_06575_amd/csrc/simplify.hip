@@ -315,43 +315,96 @@ __global__ void __launch_bounds__(1024) k_scan_counts(const int64_t *counts, int
     if (threadIdx.x == 0) out[S] = run;
 }
 
-// Multi-block exclusive scan for long count arrays: tile sums, one
-// k_scan_counts over the sums, then each tile rescans itself from its offset.
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan_tile_sums(const int64_t *in, int64_t S, int64_t *sums)
-{
-    __shared__ int64_t s_scan[SCAN_THREADS / kWave];
-    const int64_t t0 = (int64_t)blockIdx.x * SCAN_TILE;
-    int64_t v = 0;
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        const int64_t i = t0 + (int64_t)k * SCAN_THREADS + threadIdx.x;
-        if (i < S) v += in[i];
-    }
-    const int64_t tot = block_sum<SCAN_THREADS>(v, s_scan);
-    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+// Single-pass exclusive scan with decoupled look-back (Merrill and Garland).
+// Tiles are taken in the order workgroups start (a ticket), so every tile's
+// predecessors are running or done and the look-back always ends.  A tile
+// publishes its sum as soon as it is known (status AGG), then its inclusive
+// prefix (status PFX) once its look-back is done; the look-back reads 64
+// predecessors per round, one per lane, and adds them up to the nearest PFX.
+// Status and value share one 64-bit word.  out[S] = total.  The state must be
+// zero on entry; the scan leaves it dirty (the caller clears it, in a later
+// kernel, before the next scan).
+namespace {
+constexpr unsigned long long LB_AGG = 1ull << 62, LB_PFX = 2ull << 62, LB_VAL = (1ull << 62) - 1;
 }
 
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan_tile_apply(const int64_t *in, int64_t S,
-                                                                  const int64_t *tile_off, int64_t *out)
+__global__ void __launch_bounds__(LB_THREADS) k_scan_lookback(const int64_t *in, int64_t S, int64_t *out,
+                                                                unsigned long long *state, int32_t *status)
 {
-    __shared__ int64_t s_scan[SCAN_THREADS / kWave];
-    const int64_t t0 = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
-    int64_t v[SCAN_ITEMS];
+    __shared__ int64_t s_scan[LB_THREADS / kWave];
+    __shared__ int64_t s_excl;
+    __shared__ int64_t s_tile;
+    unsigned long long *flag = state + 2;
+    const int64_t nt = (S + LB_TILE - 1) / LB_TILE;
+    if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(&state[0], 1ull);
+    __syncthreads();
+    const int64_t t = s_tile;
+    if (t >= nt) {   // state not zero on entry: a caller bug, reported rather than waited on
+        if (threadIdx.x == 0) set_status(status, POLY_ERR_HIP);
+        return;
+    }
+    const int64_t i0 = t * LB_TILE + (int64_t)threadIdx.x * LB_ITEMS;
+    int64_t v[LB_ITEMS];
     int64_t loc = 0;
 #pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        const int64_t i = t0 + k;
-        v[k] = i < S ? in[i] : 0;
+    for (int k = 0; k < LB_ITEMS; ++k) {
+        const int64_t i = i0 + k;
+        v[k] = in[i < S ? i : S - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < LB_ITEMS; ++k) {
+        v[k] = i0 + k < S ? v[k] : 0;
         loc += v[k];
     }
     int64_t tot;
-    int64_t run = tile_off[blockIdx.x] + block_exclusive_scan<SCAN_THREADS>(loc, s_scan, tot);
+    const int64_t pos = block_exclusive_scan<LB_THREADS>(loc, s_scan, tot);
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&flag[t], (t == 0 ? LB_PFX : LB_AGG) | (unsigned long long)tot, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < kWave) {
+        const int lane = (int)threadIdx.x;
+        int64_t excl = 0;
+        int64_t j = t - 1;   // nearest predecessor not yet added
+        uint32_t spins = 0;  // bounded: predecessors never wait on this tile, so a limit means a bug
+        while (j >= 0) {
+            const int64_t jj = j - lane;
+            const unsigned long long f =
+                jj >= 0 ? __hip_atomic_load(&flag[jj], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : LB_PFX;
+            const unsigned long long pfx = __ballot((f >> 62) == 2ull);
+            const unsigned long long none = __ballot((f >> 62) == 0ull);
+            // lanes up to the nearest PFX lane must all have published
+            const int stop = pfx ? __ffsll((long long)pfx) - 1 : kWave - 1;
+            const unsigned long long upto = stop == kWave - 1 ? ~0ull : ((1ull << (stop + 1)) - 1);
+            if (none & upto) {   // a predecessor still working: read again
+                if (++spins > (1u << 22)) {
+                    if (lane == 0) set_status(status, POLY_ERR_HIP);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            int64_t part = lane <= stop ? (int64_t)(f & LB_VAL) : 0;
+            part = wave_sum(part);
+            excl += part;
+            if (pfx) break;
+            j -= kWave;
+        }
+        if (lane == 0) {
+            s_excl = excl;
+            if (t > 0)
+                __hip_atomic_store(&flag[t], LB_PFX | (unsigned long long)(excl + tot), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    __syncthreads();
+    int64_t run = s_excl + pos;
 #pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        const int64_t i = t0 + k;
+    for (int k = 0; k < LB_ITEMS; ++k) {
+        const int64_t i = i0 + k;
         if (i < S) out[i] = run;
         run += v[k];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[S] = tile_off[gridDim.x];
+    if (t == nt - 1 && threadIdx.x == 0) out[S] = s_excl + tot;
 }
 
 // One block per segment: staged (key, coef) -> CSR output rows.  A segment's
