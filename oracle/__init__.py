@@ -6,7 +6,8 @@ library and its Python binding) never imports, links or calls it, and the two
 share no code: this package wraps ``poly_oracle.c`` (the plain definitions of
 simplify, times, eval, diff and the reverse mode of eval) through ctypes, and
 adds a brute-force simplify built on a Python dict as a second, independent
-data structure for self-checks.
+data structure for self-checks, and the affine-normal direction of Section 5
+written out in NumPy from the symbolic derivatives (the reference route).
 
 Each function states the passage of the paper it follows; conventions where
 the paper is silent are documented in ``poly_oracle.c``.
@@ -327,3 +328,77 @@ def eval_backward(row_ptr, exps, coefs, X, gY, want_dX: bool = True, want_dC: bo
     dC = np.empty(e.shape[0]) if want_dC else None
     _check(_load().orc_eval_backward(n, P, _p(rp), _p(e), _p(c), X.shape[0], _p(X), _p(gY), _p(dX), _p(dC)))
     return dX, dC
+
+
+# ------------------------------------------------------------- affine normal
+
+def derivatives_at(exps, coefs, x, n: int | None = None):
+    """Gradient g[j], Hessian H[j, k] and third-derivative tensor T[j, k, l]
+    of one polynomial at one point, each entry the evaluation of the
+    symbolically differentiated polynomial (diff, diff2 and a further diff:
+    the automatic-differentiation reference route of Section 5)."""
+    x = np.asarray(x, dtype=np.float64)
+    n = n if n is not None else x.shape[0]
+    X = x[None, :]
+    g = np.empty(n)
+    H = np.empty((n, n))
+    T = np.empty((n, n, n))
+    for j in range(n):
+        e1, c1 = diff(exps, coefs, j, n)
+        g[j] = eval_points(e1, c1, X, n)[0] if e1.shape[0] else 0.0
+        for k in range(n):
+            e2, c2 = diff2(exps, coefs, j, k, n)
+            H[j, k] = eval_points(e2, c2, X, n)[0] if e2.shape[0] else 0.0
+            for l in range(n):
+                e3, c3 = diff(e2, c2, l, n) if e2.shape[0] else (e2, c2)
+                T[j, k, l] = eval_points(e3, c3, X, n)[0] if e3.shape[0] else 0.0
+    return g, H, T
+
+
+def tangent_frame(g):
+    """An orthonormal frame Q = [Q_T, e] with last column e = g / |g| (any
+    completion: the direction does not depend on it)."""
+    g = np.asarray(g, dtype=np.float64)
+    n = g.shape[0]
+    e = g / np.linalg.norm(g)
+    # QR of [e, I] gives an orthonormal basis whose first vector is +-e
+    Qf, _ = np.linalg.qr(np.column_stack([e, np.eye(n)]))
+    Qf = Qf[:, :n]
+    if Qf[:, 0] @ e < 0:
+        Qf[:, 0] = -Qf[:, 0]
+    return np.column_stack([Qf[:, 1:], Qf[:, 0]])
+
+
+def affine_normal_from_derivatives(g, H, T, reg: float = 0.0, Q=None):
+    """Affine-normal direction of Section 5 from the derivatives at a point:
+    e = g/|g|, Q = [Q_T, e], H_T = Q_T' H Q_T + reg I (the regularized
+    tangent block, used in every tangent solve), h = Q_T' H e,
+    a_i = tr(H_T^-1 d_{t_i} H_T) with d_{t_i} H_T = Q_T' D^3f[t_i] Q_T and
+    t_i = Q_T e_i, tau = H_T^-1 (h - |g| / (n + 1) a), nu = Q [tau; -1]."""
+    g = np.asarray(g, dtype=np.float64)
+    n = g.shape[0]
+    gn = np.linalg.norm(g)
+    if Q is None:
+        Q = tangent_frame(g)
+    QT, e = Q[:, :n - 1], Q[:, n - 1]
+    HT = QT.T @ H @ QT + reg * np.eye(n - 1)
+    h = QT.T @ H @ e
+    a = np.empty(n - 1)
+    for i in range(n - 1):
+        D3 = np.tensordot(T, QT[:, i], axes=([2], [0]))    # D^3 f [t_i], an n x n matrix
+        a[i] = np.trace(np.linalg.solve(HT, QT.T @ D3 @ QT))
+    tau = np.linalg.solve(HT, h - gn / (n + 1) * a)
+    return Q @ np.concatenate([tau, [-1.0]]), gn
+
+
+def affine_normal(exps, coefs, X, reg: float = 0.0):
+    """D[pt] = affine-normal direction of one polynomial at each point of X
+    (Section 5, the 'ad' reference route); also |grad f| per point."""
+    X = np.asarray(X, dtype=np.float64)
+    N, n = X.shape
+    D = np.empty((N, n))
+    gn = np.empty(N)
+    for p in range(N):
+        g, H, T = derivatives_at(exps, coefs, X[p], n)
+        D[p], gn[p] = affine_normal_from_derivatives(g, H, T, reg)
+    return D, gn

@@ -409,3 +409,94 @@ def test_jacobian_batch_layout():
             de, dc = oracle.diff(*polys[p], j)
             assert np.array_equal(jE[jrp[k]:jrp[k + 1]], de)
             assert np.array_equal(jC[jrp[k]:jrp[k + 1]], dc)
+
+
+# ------------------------------------------------------------- affine normal
+
+def _poly(entry):
+    E = np.array([t[1] for t in entry["f"]], np.uint8)
+    C = np.array([t[0] for t in entry["f"]], float)
+    return E, C
+
+
+def test_affine_normal_paper_example(golden):
+    """Section 5's printed direction (7 significant digits) at x0 with
+    regularization 1e-8.  The third component, -1.01e-9, exists only through
+    the regularized tangent solves, and the first, second and fourth depend on
+    the |g| / (n + 1) weight of the log-det correction, so the example pins
+    both readings."""
+    g = golden["W11_affine_example_direction"]
+    E, C = _poly(g)
+    D, gn = oracle.affine_normal(E, C, np.array([g["x0"]]), reg=g["regularization"])
+    for got, want in zip(D[0], g["d"]):
+        assert abs(got - want) <= 0.5e-6 * abs(want) + 1e-22
+    assert abs(gn[0] - g["grad_norm"]) <= 0.5e-6 * g["grad_norm"]
+
+
+def _random_quartic(seed, n, terms):
+    rng = W.rng_for(seed)
+    E, C = W.random_poly(rng, n, 4, terms)
+    # a convex quadratic part keeps the tangent block well conditioned
+    E = np.vstack([E, 2 * np.eye(n, dtype=np.uint8)])
+    C = np.concatenate([C, 3.0 * np.ones(n)])
+    x = rng.uniform(-0.5, 0.5, n)
+    return E, C, x, rng
+
+
+def test_affine_normal_quadric_closed_form():
+    """For a quadratic f the third derivatives vanish and the direction is
+    -H^-1 e / (e' H^-1 e) (its affine normal line passes through the
+    centre), computed here from the full Hessian with no tangent frame."""
+    rng = W.rng_for(3101)
+    n = 6
+    B = rng.standard_normal((n, n))
+    A = B @ B.T + n * np.eye(n)          # f = 1/2 x'Ax + b'x
+    b = rng.standard_normal(n)
+    E, C = [], []
+    for j in range(n):
+        for k in range(j, n):
+            e = np.zeros(n, np.uint8)
+            e[j] += 1
+            e[k] += 1
+            E.append(e)
+            C.append(A[j, j] / 2 if j == k else A[j, k])
+        e = np.zeros(n, np.uint8)
+        e[j] = 1
+        E.append(e)
+        C.append(b[j])
+    x = rng.uniform(-1, 1, n)
+    D, _ = oracle.affine_normal(np.array(E), np.array(C), x[None, :], reg=0.0)
+    g = A @ x + b
+    e = g / np.linalg.norm(g)
+    u = np.linalg.solve(A, e)
+    assert np.allclose(D[0], -u / (e @ u), rtol=1e-11, atol=1e-12)
+
+
+def test_affine_normal_frame_invariance():
+    """Any orthonormal completion of e gives the same direction."""
+    E, C, x, rng = _random_quartic(3102, 5, 25)
+    g, H, T = oracle.derivatives_at(E, C, x, 5)
+    Q = oracle.tangent_frame(g)
+    R, _ = np.linalg.qr(rng.standard_normal((4, 4)))
+    Q2 = np.column_stack([Q[:, :4] @ R, Q[:, 4]])
+    nu1, _ = oracle.affine_normal_from_derivatives(g, H, T, 0.0, Q)
+    nu2, _ = oracle.affine_normal_from_derivatives(g, H, T, 0.0, Q2)
+    assert np.allclose(nu1, nu2, rtol=1e-10, atol=1e-12)
+
+
+def test_affine_normal_equiaffine_covariance():
+    """For y = A x with det A = 1, the derivatives of f(A^-1 y) are the
+    tensors of f transformed by A^-1 in every index, and the affine normal
+    there is A times the affine normal of f (the normalisation e'nu = -1 only
+    rescales it): a transposed frame or a wrong contraction breaks this."""
+    E, C, x, rng = _random_quartic(3103, 5, 25)
+    g, H, T = oracle.derivatives_at(E, C, x, 5)
+    nu, _ = oracle.affine_normal_from_derivatives(g, H, T, 0.0)
+    A = rng.standard_normal((5, 5))
+    A /= np.sign(np.linalg.det(A)) * abs(np.linalg.det(A)) ** 0.2
+    Ai = np.linalg.inv(A)
+    g2, H2 = Ai.T @ g, Ai.T @ H @ Ai
+    T2 = np.einsum("jkl,ja,kb,lc->abc", T, Ai, Ai, Ai)
+    nu2, _ = oracle.affine_normal_from_derivatives(g2, H2, T2, 0.0)
+    r = nu2 / (A @ nu)
+    assert (r > 0).all() and np.ptp(r) <= 1e-9 * r.mean()
