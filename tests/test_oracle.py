@@ -413,7 +413,7 @@ def test_jacobian_batch_layout():
 
 # ------------------------------------------------------------- affine normal
 
-def _poly(entry):
+def _golden_poly(entry):
     E = np.array([t[1] for t in entry["f"]], np.uint8)
     C = np.array([t[0] for t in entry["f"]], float)
     return E, C
@@ -426,7 +426,7 @@ def test_affine_normal_paper_example(golden):
     the |g| / (n + 1) weight of the log-det correction, so the example pins
     both readings."""
     g = golden["W11_affine_example_direction"]
-    E, C = _poly(g)
+    E, C = _golden_poly(g)
     D, gn = oracle.affine_normal(E, C, np.array([g["x0"]]), reg=g["regularization"])
     for got, want in zip(D[0], g["d"]):
         assert abs(got - want) <= 0.5e-6 * abs(want) + 1e-22
