@@ -121,13 +121,14 @@ poly_status poly_tune_get(const char *name, int64_t *value);
  *                     on the radix-sort path each scatter pass
  *   POLY_TIMING_DENSE the contraction kernel of poly_eval_dense
  *   POLY_TIMING_TERMS the term-streaming kernel of poly_eval / grad / hess
+ *   POLY_TIMING_AFFINE the per-point kernel of poly_affine_normal
  * poly_timing_enable(1) clears every slot and starts recording; (0) stops.
  * poly_timing_read waits for the recorded events of `slot` (at most the last
  * 1024 launches are kept) and returns their summed duration in milliseconds
  * and the launch count.  Off by default; recording adds two event records per
  * launch and is not meant for graph capture.  Not thread-safe with concurrent
  * entry-point calls from other host threads. */
-enum { POLY_TIMING_MUL = 0, POLY_TIMING_DENSE = 1, POLY_TIMING_TERMS = 2 };
+enum { POLY_TIMING_MUL = 0, POLY_TIMING_DENSE = 1, POLY_TIMING_TERMS = 2, POLY_TIMING_AFFINE = 3 };
 poly_status poly_timing_enable(int32_t enable);
 poly_status poly_timing_read(int32_t slot, double *total_ms, int64_t *launches);
 
@@ -196,6 +197,24 @@ poly_status poly_eval_backward_workspace(const poly_csr *f, int64_t N, size_t *w
 poly_status poly_eval_backward(const poly_csr *f, const double *X, int64_t N,
                                const double *gY, double *dX, double *dC,
                                void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------- affine normal
+ * Affine-normal direction of one polynomial (f->npolys == 1, 2 <= n <= 128)
+ * at N points (Section 5, the exact log-determinant method): with
+ * g = grad f(x), e = g / |g|, an orthonormal frame Q = [Q_T, e],
+ * A = Q_T' Hess f(x) Q_T + reg I, h = Q_T' Hess f(x) e and
+ * a_i = tr(A^-1 Q_T' D^3 f(x)[Q_T e_i] Q_T) (i = 1..n-1):
+ *   D[pt*n + i] = (Q [A^-1 (h - |g| / (n + 1) a); -1])_i
+ * (independent of the choice of Q_T; the regularization reg >= 0 enters
+ * every tangent solve), and gnorm[pt] = |g| (gnorm may be NULL).
+ * The gradient and Hessian come from the poly_grad / poly_hess paths; the
+ * third-order term is contracted per monomial, so no n^3 tensor is formed.
+ * Terms of total degree above 12 are not supported (device status
+ * POLY_ERR_UNSUPPORTED).  A singular regularized tangent block, or g = 0,
+ * gives non-finite output for that point.  X [N*n] row-major; D [N*n]. */
+poly_status poly_affine_normal_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes);
+poly_status poly_affine_normal(const poly_csr *f, const double *X, int64_t N, double reg,
+                               double *D, double *gnorm, void *ws, size_t ws_bytes, void *stream);
 
 /* ----------------------------------------------------- shared monomial set
  * Y[p*N + pt] = sum_k C[p*K + k] * prod_i X[pt*n + i]^basis[k*n + i]:

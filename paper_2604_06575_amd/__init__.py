@@ -38,6 +38,7 @@ EXPORTS = [
     "poly_hess_workspace", "poly_hess",
     "poly_eval_backward_workspace", "poly_eval_backward",
     "poly_eval_dense_workspace", "poly_eval_dense",
+    "poly_affine_normal_workspace", "poly_affine_normal",
 ]
 
 
@@ -102,6 +103,8 @@ def lib():
         "poly_eval_backward_workspace": ([pcsr, i64, psz], i32),
         "poly_eval_backward": ([pcsr, P, i64, P, P, P, P, ctypes.c_size_t, P], i32),
         "poly_eval_dense_workspace": ([i32, i64, i64, i64, i32, i32, psz], i32),
+        "poly_affine_normal_workspace": ([pcsr, i64, psz], i32),
+        "poly_affine_normal": ([pcsr, P, i64, d, P, P, P, ctypes.c_size_t, P], i32),
         "poly_eval_dense": ([i32, i64, P, i32, i64, P, i64, P, P, i32, i32, P, ctypes.c_size_t, P], i32),
     }
     for name, (args, res) in sig.items():
@@ -139,7 +142,7 @@ def tune_get(name: str) -> int:
     return int(v.value)
 
 
-TIMING_MUL, TIMING_DENSE, TIMING_TERMS = 0, 1, 2
+TIMING_MUL, TIMING_DENSE, TIMING_TERMS, TIMING_AFFINE = 0, 1, 2, 3
 
 
 def timing_enable(on: bool = True):
@@ -374,6 +377,35 @@ def eval_backward(b: Batch, X: torch.Tensor, gY: torch.Tensor, want_dX: bool = T
     if check:
         _check(L.poly_read_status(ctypes.c_void_p(ws.data_ptr()), _stream()), "poly_eval_backward")
     return dX, dC
+
+
+def affine_normal(b: Batch, X: torch.Tensor, reg: float = 1e-6, check: bool = False, ws: torch.Tensor | None = None):
+    """Affine-normal directions of one polynomial at the rows of X:
+    (D [N, n], |grad f| [N])."""
+    L = lib()
+    X = X.contiguous()
+    assert X.dtype == torch.float64 and X.dim() == 2 and X.shape[1] == b.n
+    N = X.shape[0]
+    cin = b.csr()
+    ws_bytes = ctypes.c_size_t()
+    _check(L.poly_affine_normal_workspace(ctypes.byref(cin), N, ctypes.byref(ws_bytes)),
+           "poly_affine_normal_workspace")
+    if ws is None or ws.numel() < ws_bytes.value:
+        ws = _workspace(ws_bytes.value, b.coefs.device)
+    D = torch.empty((N, b.n), dtype=torch.float64, device=b.coefs.device)
+    gn = torch.empty(N, dtype=torch.float64, device=b.coefs.device)
+    _check(L.poly_affine_normal(ctypes.byref(cin), _ptr(X), N, float(reg), _ptr(D), _ptr(gn),
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "poly_affine_normal")
+    if check:
+        _check(L.poly_read_status(ctypes.c_void_p(ws.data_ptr()), _stream()), "poly_affine_normal")
+    return D, gn
+
+
+def affine_normal_workspace(b: Batch, N: int) -> int:
+    ws_bytes = ctypes.c_size_t()
+    _check(lib().poly_affine_normal_workspace(ctypes.byref(b.csr()), N, ctypes.byref(ws_bytes)),
+           "poly_affine_normal_workspace")
+    return int(ws_bytes.value)
 
 
 def eval_dense_workspace(n: int, K: int, P: int, N: int, prec: int = POLY_FP64, nslices: int = 5) -> int:

@@ -395,14 +395,14 @@ void run_form(const FormPlan &fp, FormArgs A, void *ws, hipStream_t s)
 
 // --------------------------------------------------------- kernel timing
 
-constexpr int kTimingSlots = 3;
+constexpr int kTimingSlots = 4;
 constexpr int kTimingRing = 1024;
 struct TimingState {
     std::mutex mu;
     std::atomic<bool> on{false};
     bool created = false;
     hipEvent_t ev[kTimingSlots][kTimingRing][2];
-    int64_t count[kTimingSlots] = {0, 0, 0};
+    int64_t count[kTimingSlots] = {0, 0, 0, 0};
 };
 TimingState g_timing;
 
@@ -418,6 +418,8 @@ void ensure_lds_attrs()
                               (int)(GS_SORT1_CAP * 12));
     (void)hipFuncSetAttribute((const void *)k_mul_buckets_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)MB_LDS_LIMIT);
+    (void)hipFuncSetAttribute((const void *)k_affine_normal, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)affine_lds_bytes(AN_MAX_N));
     lds_attr_done = true;
 }
 
@@ -1076,24 +1078,12 @@ poly_status poly_hess_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)
     return POLY_OK;
 }
 
-poly_status poly_hess(const poly_csr *f, const double *X, int64_t N, double *H, void *ws, size_t ws_bytes,
-                      void *stream)
+poly_status run_hess(const poly_csr *f, const double *X, int64_t N, double *H, void *ws, const HessPlan &h,
+                     hipStream_t s)
 {
-    poly_status st = check_eval(f, X, N, H);
-    if (st != POLY_OK) return st;
     const int n = f->nvars;
     const int64_t P = f->npolys;
-    Layout L;
-    const HessPlan h = plan_hess(f, N, L);
-    if (!ws || ws_bytes < L.total()) return POLY_ERR_WORKSPACE;
-    hipStream_t s = (hipStream_t)stream;
-    ensure_lds_attrs();
     int32_t *status = at<int32_t>(ws, 0);
-    clear_u64(at<unsigned long long>(ws, 0), 1, s);
-    if (P == 0 || N == 0) {
-        LAUNCH_CHECK();
-        return POLY_OK;
-    }
     int64_t *jrp = at<int64_t>(ws, h.jrp);
     uint8_t *jexps = at<uint8_t>(ws, h.jexps);
     double *jcoefs = at<double>(ws, h.jcoefs);
@@ -1128,6 +1118,100 @@ poly_status poly_hess(const poly_csr *f, const double *X, int64_t N, double *H, 
     A.Y = H;
     A.term_limit = h.hcap;
     launch_eval_blocks(A, henc, at<double>(ws, h.part), h.S, s);
+    LAUNCH_CHECK();
+    return POLY_OK;
+}
+
+poly_status poly_hess(const poly_csr *f, const double *X, int64_t N, double *H, void *ws, size_t ws_bytes,
+                      void *stream)
+{
+    poly_status st = check_eval(f, X, N, H);
+    if (st != POLY_OK) return st;
+    Layout L;
+    const HessPlan h = plan_hess(f, N, L);
+    if (!ws || ws_bytes < L.total()) return POLY_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    ensure_lds_attrs();
+    clear_u64(at<unsigned long long>(ws, 0), 1, s);
+    if (f->npolys == 0 || N == 0) {
+        LAUNCH_CHECK();
+        return POLY_OK;
+    }
+    return run_hess(f, X, N, H, ws, h, s);
+}
+
+// ------------------------------------------------------------ affine normal
+
+// The gradient and Hessian paths, then one workgroup per point.
+struct AffinePlan {
+    GradPlan g;
+    HessPlan h;
+    size_t G, H, enc;
+};
+
+AffinePlan plan_affine(const poly_csr *f, int64_t N, Layout &L)
+{
+    AffinePlan a;
+    const int n = f->nvars;
+    a.g = plan_grad(f, N, L);
+    a.h = plan_hess(f, N, L);
+    a.G = L.take(8 * (size_t)N * n);
+    a.H = L.take(8 * (size_t)N * n * n);
+    a.enc = L.take(16 * (size_t)std::max<int64_t>(total_terms(f), 1));
+    return a;
+}
+
+poly_status check_affine(const poly_csr *f, const double *X, int64_t N, const double *D, double reg)
+{
+    poly_status st = check_eval(f, X, N, D);
+    if (st != POLY_OK) return st;
+    if (f->npolys != 1 || f->nvars < 2 || f->nvars > AN_MAX_N || !(reg >= 0.0) || reg > 1e300)
+        return f->nvars > AN_MAX_N ? POLY_ERR_UNSUPPORTED : POLY_ERR_ARG;
+    return POLY_OK;
+}
+
+poly_status poly_affine_normal_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)
+{
+    poly_status st = check_affine(f, nullptr, 0, nullptr, 0.0);
+    if (st != POLY_OK) return st;
+    if (!ws_bytes || N < 0) return POLY_ERR_ARG;
+    Layout L;
+    plan_affine(f, N, L);
+    *ws_bytes = L.total();
+    return POLY_OK;
+}
+
+poly_status poly_affine_normal(const poly_csr *f, const double *X, int64_t N, double reg, double *D, double *gnorm,
+                               void *ws, size_t ws_bytes, void *stream)
+{
+    poly_status st = check_affine(f, X, N, D, reg);
+    if (st != POLY_OK) return st;
+    Layout L;
+    const AffinePlan a = plan_affine(f, N, L);
+    if (!ws || ws_bytes < L.total()) return POLY_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    ensure_lds_attrs();
+    int32_t *status = at<int32_t>(ws, 0);
+    clear_u64(at<unsigned long long>(ws, 0), 1, s);
+    if (N == 0) {
+        LAUNCH_CHECK();
+        return POLY_OK;
+    }
+    const int n = f->nvars;
+    const int64_t T = total_terms(f);
+    double *G = at<double>(ws, a.G);
+    double *H = at<double>(ws, a.H);
+    uint32_t *enc = at<uint32_t>(ws, a.enc);
+    if ((st = run_grad(f, X, N, G, ws, a.g, s)) != POLY_OK) return st;
+    if ((st = run_hess(f, X, N, H, ws, a.h, s)) != POLY_OK) return st;
+    if (T > 0)
+        hipLaunchKernelGGL(k_encode_factors, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, enc,
+                           (const int64_t *)nullptr);
+    TimedLaunch tl(POLY_TIMING_AFFINE, s);
+    hipLaunchKernelGGL(k_affine_normal, dim3((unsigned)N), dim3(AN_THREADS), affine_lds_bytes(n), s, n,
+                       (const uint4 *)enc, f->coefs, T, X, (const double *)G, (const double *)H, reg, D, gnorm,
+                       status);
+    tl.done(s);
     LAUNCH_CHECK();
     return POLY_OK;
 }

@@ -174,6 +174,17 @@ struct EvalArgs {
 __global__ void k_encode_support(const uint8_t *exps, int64_t T, int n, uint64_t *enc, const int64_t *used);
 constexpr int EV_MAX_DEG = 12;   // total degree handled by the factor-list encoding
 __global__ void k_encode_factors(const uint8_t *exps, int64_t T, int n, uint32_t *enc, const int64_t *used);
+
+// affine-normal direction (affine.hip): one workgroup per point
+constexpr int AN_THREADS = 256;
+constexpr int AN_MAX_N = 128;
+__host__ __device__ constexpr size_t affine_lds_bytes(int n)
+{
+    return ((size_t)n * (n + 1) + 8 * (size_t)n + (size_t)n * (EV_MAX_DEG + 1)) * sizeof(double);
+}
+__global__ void k_affine_normal(int n, const uint4 *enc, const double *coefs, int64_t T, const double *X,
+                                const double *G, const double *H, double reg, double *D, double *gnorm,
+                                int32_t *status);
 __global__ void k_eval_terms(EvalArgs A, const uint32_t *enc, double *partial, int64_t S);
 __global__ void k_eval_reduce(EvalArgs A, const double *partial, int64_t S);
 constexpr int64_t EV_TARGET_WAVES = 16384;   // waves wanted before polynomials are cut into segments

@@ -22,7 +22,7 @@ def test_library_exports_every_declared_symbol():
         pytest.skip("library not built")
     L = ctypes.CDLL(ph.library_path())
     syms = header_symbols()
-    assert len(syms) == 22
+    assert len(syms) == 24
     for s in syms:
         assert hasattr(L, s), s
     assert sorted(ph.EXPORTS) == syms
@@ -62,6 +62,19 @@ def test_strerror_and_host_argument_checks():
     # dense workspace sizes
     assert L.poly_eval_dense_workspace(30, 1000, 10, 10, 1, 9, ctypes.byref(size)) == 1   # nslices out of range
     assert L.poly_eval_dense_workspace(30, 1000, 10, 10, 1, 5, ctypes.byref(size)) == 0
+    # affine normal: one polynomial, 2 <= n <= 128
+    c.nvars = 2
+    c.npolys = 2
+    assert L.poly_affine_normal_workspace(ctypes.byref(c), 10, ctypes.byref(size)) == 1   # two polynomials
+    one = np.array([0, 3], np.int64)
+    c.npolys = 1
+    c.row_ptr_host = one.ctypes.data_as(ctypes.c_void_p)
+    assert L.poly_affine_normal_workspace(ctypes.byref(c), 10, ctypes.byref(size)) == 0
+    assert size.value > 0
+    c.nvars = 1
+    assert L.poly_affine_normal_workspace(ctypes.byref(c), 10, ctypes.byref(size)) == 1   # no tangent space
+    c.nvars = 129
+    assert L.poly_affine_normal_workspace(ctypes.byref(c), 10, ctypes.byref(size)) == 6   # beyond the LDS tile
 
 
 def test_tunables_roundtrip():
@@ -93,7 +106,7 @@ def test_timing_hooks_host_checks():
     L = ph.lib()
     ms = ctypes.c_double()
     cnt = ctypes.c_int64()
-    assert L.poly_timing_read(3, ctypes.byref(ms), ctypes.byref(cnt)) == 1
+    assert L.poly_timing_read(4, ctypes.byref(ms), ctypes.byref(cnt)) == 1
     assert L.poly_timing_read(-1, ctypes.byref(ms), ctypes.byref(cnt)) == 1
     assert L.poly_timing_read(0, None, ctypes.byref(cnt)) == 1
     # nothing recorded yet: zero launches, no device access

@@ -227,6 +227,28 @@ def quartic(seed: int = SEED_BASE + 5, n: int = 100, terms: int = 100_000, npts:
     return ScalarWorkload(n, e, c, X)
 
 
+def sparse_quartic(seed: int = SEED_BASE + 6, n: int = 64, npts: int = 4096, m: int | None = None) -> ScalarWorkload:
+    """The affine-normal timing family: ``m`` (default 4n) distinct quartic
+    monomials of support size 3 (exponents a permutation of (2, 1, 1) on
+    three distinct variables), N(0,1) coefficients, plus sum_i x_i^2 so the
+    tangent Hessian blocks stay nonsingular; points uniform in [-1,1]^n."""
+    rng = rng_for(seed)
+    m = 4 * n if m is None else m
+    rows, seen = [], set()
+    while len(rows) < m:
+        v = rng.choice(n, size=3, replace=False)
+        e = np.zeros(n, dtype=np.uint8)
+        e[v] = (2, 1, 1)
+        key = e.tobytes()
+        if key not in seen:
+            seen.add(key)
+            rows.append(e)
+    E = np.vstack(rows + [2 * np.eye(n, dtype=np.uint8)])
+    C = np.concatenate([rng.standard_normal(m), np.ones(n)])
+    X = rng.uniform(-1.0, 1.0, size=(npts, n))
+    return ScalarWorkload(n, E, C, X)
+
+
 def homogeneous(seed: int, n: int, d: int, terms: int, coef_range: int = 5) -> tuple[np.ndarray, np.ndarray]:
     """Distinct monomials of total degree exactly ``d`` with small integer
     coefficients (for Euler-identity checks)."""
