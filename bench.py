@@ -16,7 +16,8 @@ It also measures the evaluation metric: 4,096 polynomials over the full
 degree <= 4 monomial set in n=30 variables (46,376 monomials) at 65,536
 points, in plain FP64 (FP64 MFMA) and split BF16 (BF16 MFMA, FP32
 accumulation, FP64 recombination), each with its error against an FP64
-reference on sampled outputs.
+reference on sampled outputs; and the sparse derivative paths and the
+affine-normal direction of a sparse quartic at a batch of points.
 
 Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
 """
@@ -77,6 +78,9 @@ def parse():
     ap.add_argument("--cpu-terms", type=int, default=5000, help="q terms in the CPU baseline sample")
     ap.add_argument("--no-batch", action="store_true", help="skip the polynomial-matrix workload")
     ap.add_argument("--no-deriv", action="store_true", help="skip the quartic derivative workload")
+    ap.add_argument("--no-affine", action="store_true", help="skip the affine-normal workload")
+    ap.add_argument("--affine-n", type=int, default=64)
+    ap.add_argument("--affine-points", type=int, default=4096)
     ap.add_argument("--graph", action="store_true", help="also time the times+simplify step as a captured HIP graph")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -176,11 +180,17 @@ def measured_traffic():
         return None
 
 
+def dense_reference(basis, C, Xs):
+    """Y = C V and |C| |V| at a few points in plain NumPy FP64, V[k, pt] the
+    product of x_i ** e_ki: the error yardstick for the dense timings."""
+    V = np.prod(Xs[None, :, :] ** basis.astype(np.float64)[:, None, :], axis=2)
+    return C @ V, np.abs(C) @ np.abs(V)
+
+
 def bench_eval(args):
     import torch
     import paper_2604_06575_amd as ph
     import workloads as W
-    import oracle
 
     P, N = args.eval_polys, args.eval_points
     wl = W.dense_shared(P=P, N=N)
@@ -190,11 +200,10 @@ def bench_eval(args):
     X = torch.from_numpy(wl.X).cuda()
     Y = torch.empty((P, N), dtype=torch.float64, device="cuda")
     res = {}
-    # FP64 reference values on a sample of outputs (oracle, CPU): 8 points x all polys
+    # FP64 reference values on a sample of outputs (NumPy, CPU): 8 points x all polys
     rng = np.random.default_rng(7)
     pts = np.sort(rng.choice(N, size=8, replace=False))
-    Yref = oracle.eval_dense(wl.basis, wl.C, wl.X[pts])
-    Aref = oracle.eval_dense(wl.basis, np.abs(wl.C), np.abs(wl.X[pts]))
+    Yref, Aref = dense_reference(wl.basis, wl.C, wl.X[pts])
     for name, prec, S in (("fp64", ph.POLY_FP64, 0), ("split_bf16", ph.POLY_SPLIT_BF16, args.nslices)):
         need = ph.eval_dense_workspace(wl.n, K, P, N, prec, S if S else 5)
         ws = torch.empty(need, dtype=torch.uint8, device="cuda")
@@ -222,7 +231,7 @@ def bench_eval(args):
             "mfma_frac": mfma_flops / t_ev / 1e12 / peak,
             "kernel_ms": k_ms,
             "kernel_mfma_frac": mfma_flops / (k_ms / 1e3) / 1e12 / peak,
-            "error_sample": "8 points x all polynomials vs the FP64 oracle",
+            "error_sample": "8 points x all polynomials vs a NumPy FP64 reference (C V)",
         }
         del ws
     res["workload"] = {"polys": P, "monomials": K, "points": N, "n": wl.n, "degree": 4}
@@ -273,6 +282,36 @@ def bench_deriv(args):
     return {"terms": wl.exps.shape[0], "n": wl.n, "points": N,
             "eval_ms": t_eval * 1e3, "backward_dx_dc_ms": t_bwd * 1e3, "hessian_ms": t_hess * 1e3,
             "dtype": {"f": "f64", "grad": "f64", "hessian": "f64 (100x100 per point, both triangles)"}}
+
+
+def bench_affine(args):
+    """Affine-normal directions (exact log-det route) of a sparse quartic in
+    n=64 variables (support 3, 4n monomials, plus sum x_i^2) at 4,096 points:
+    gradient and Hessian paths, then one workgroup per point."""
+    import torch
+    import paper_2604_06575_amd as ph
+    import workloads as W
+
+    wl = W.sparse_quartic(n=args.affine_n, npts=args.affine_points)
+    n, N = wl.n, wl.X.shape[0]
+    b = ph.batch_from_numpy([0, wl.exps.shape[0]], wl.exps, wl.coefs, n=n, max_exp=4)
+    X = torch.from_numpy(wl.X).cuda()
+    ws = torch.empty(ph.affine_normal_workspace(b, N), dtype=torch.uint8, device="cuda")
+    step = lambda: ph.affine_normal(b, X, reg=1e-8, ws=ws)  # noqa: E731
+    D, _ = ph.affine_normal(b, X, reg=1e-8, ws=ws, check=True)
+    finite = bool(torch.isfinite(D).all().item())
+    t, _ = time_events(step, 5, 2)
+    k_ms, k_n = kernel_ms(ph.TIMING_AFFINE, step, 5)
+    m = n - 1
+    # per point: Gauss-Jordan inverse of the (n-1)^2 tangent block (2 m^3),
+    # two rank-two frame updates and three matrix-vector products (~18 n^2)
+    flops = N * (2.0 * m ** 3 + 18.0 * n * n)
+    return {"n": n, "terms": int(wl.exps.shape[0]), "points": N, "ms": t * 1e3,
+            "points_per_s": N / t, "kernel_ms": k_ms, "kernel_launches_timed": k_n,
+            "kernel_fp64_tflops": flops / (k_ms / 1e3) / 1e12, "fp64_vector_peak_tflops": 78.6,
+            "kernel_fp64_frac": flops / (k_ms / 1e3) / 1e12 / 78.6,
+            "flops_note": "2 (n-1)^3 + 18 n^2 FP64 flops per point (tangent-block inverse, frame updates)",
+            "all_finite": finite, "regularization": 1e-8}
 
 
 def bench_graph(args, m):
@@ -387,6 +426,8 @@ def main():
         line["batch_matrix"] = bench_batch(args)
     if not args.no_deriv:
         line["quartic_derivatives"] = bench_deriv(args)
+    if not args.no_affine:
+        line["affine_normal"] = bench_affine(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(line), flush=True)

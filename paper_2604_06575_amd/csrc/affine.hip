@@ -57,10 +57,14 @@ __global__ void __launch_bounds__(AN_THREADS) k_affine_normal(int n, const uint4
     __shared__ int s_piv[AN_MAX_N];
     __shared__ int s_ip;
     const int tid = threadIdx.x;
+    // matrix loops: rows by wave, columns by lane (no index division)
+    const int ty = tid / kWave, tx = tid % kWave;
+    constexpr int NW = AN_THREADS / kWave;
     const int64_t pt = blockIdx.x;
     const int m = n - 1;
     const double *Hp = H + (size_t)pt * n * n;
-    for (int idx = tid; idx < n * n; idx += AN_THREADS) S[(idx / n) * ld + idx % n] = Hp[idx];
+    for (int i = ty; i < n; i += NW)
+        for (int j = tx; j < n; j += kWave) S[i * ld + j] = Hp[i * n + j];
     for (int i = tid; i < n; i += AN_THREADS) {
         const double xi = X[pt * n + i];
         double p = 1.0;
@@ -103,12 +107,12 @@ __global__ void __launch_bounds__(AN_THREADS) k_affine_normal(int n, const uint4
     const double beta = 2.0 / vv;
     // P H P = H - beta (v t' + t v') + beta^2 (v'Hv) v v', in place; then the
     // regularized tangent block A in the leading (n-1) x (n-1) corner
-    for (int idx = tid; idx < n * n; idx += AN_THREADS) {
-        const int i = idx / n, j = idx % n;
-        double b = S[i * ld + j] - beta * (v[i] * t[j] + t[i] * v[j]) + beta * beta * vhv * v[i] * v[j];
-        if (i == j && i < m) b += reg;
-        S[i * ld + j] = b;
-    }
+    for (int i = ty; i < n; i += NW)
+        for (int j = tx; j < n; j += kWave) {
+            double b = S[i * ld + j] - beta * (v[i] * t[j] + t[i] * v[j]) + beta * beta * vhv * v[i] * v[j];
+            if (i == j && i < m) b += reg;
+            S[i * ld + j] = b;
+        }
     __syncthreads();
     // ---- A^-1 in place: Gauss-Jordan with partial (row) pivoting
     for (int k = 0; k < m; ++k) {
@@ -150,10 +154,11 @@ __global__ void __launch_bounds__(AN_THREADS) k_affine_normal(int n, const uint4
         __syncthreads();
         for (int j = tid; j < m; j += AN_THREADS) S[k * ld + j] = j == k ? pinv : S[k * ld + j] * pinv;
         __syncthreads();
-        for (int idx = tid; idx < m * m; idx += AN_THREADS) {
-            const int i = idx / m, j = idx % m;
+        for (int i = ty; i < m; i += NW) {
             if (i == k) continue;
-            S[i * ld + j] = j == k ? -col[i] * pinv : S[i * ld + j] - col[i] * S[k * ld + j];
+            const double ci = col[i];
+            for (int j = tx; j < m; j += kWave)
+                S[i * ld + j] = j == k ? -ci * pinv : S[i * ld + j] - ci * S[k * ld + j];
         }
         __syncthreads();
     }
@@ -186,10 +191,9 @@ __global__ void __launch_bounds__(AN_THREADS) k_affine_normal(int n, const uint4
     part = 0.0;
     for (int i = tid; i < n; i += AN_THREADS) part += v[i] * t[i];
     const double vkv = block_sum_d<AN_THREADS>(part, s_red);
-    for (int idx = tid; idx < n * n; idx += AN_THREADS) {
-        const int i = idx / n, j = idx % n;
-        S[i * ld + j] = S[i * ld + j] - beta * (t[i] * v[j] + v[i] * u[j]) + beta * beta * vkv * v[i] * v[j];
-    }
+    for (int i = ty; i < n; i += NW)
+        for (int j = tx; j < n; j += kWave)
+            S[i * ld + j] = S[i * ld + j] - beta * (t[i] * v[j] + v[i] * u[j]) + beta * beta * vkv * v[i] * v[j];
     __syncthreads();
     // ---- w_l = sum_jk M_jk f_jkl(x), term by term
     for (int64_t q = tid; q < T; q += AN_THREADS) {
