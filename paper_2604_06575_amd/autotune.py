@@ -75,7 +75,7 @@ def main():
     del ws, out
     # one pair: the raw size from which the radix-sort path beats the bucket path
     rows, threshold = [], None
-    for terms in (300, 700, 1500, 3000):
+    for terms in (100, 150, 200, 300, 700, 1500, 3000):
         w = W.plain_large(seed=W.SEED_BASE + 80, terms=terms, n=8, d=8)
         a1 = ph.batch_from_numpy([0, terms], w.a_exps, w.a_coefs, n=8, max_exp=8)
         b1 = ph.batch_from_numpy([0, terms], w.b_exps, w.b_coefs, n=8, max_exp=8)
