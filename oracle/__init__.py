@@ -402,3 +402,32 @@ def affine_normal(exps, coefs, X, reg: float = 0.0):
         g, H, T = derivatives_at(exps, coefs, X[p], n)
         D[p], gn[p] = affine_normal_from_derivatives(g, H, T, reg)
     return D, gn
+
+
+# ------------------------------------------------------- polynomial matrices
+
+def mtimes(a_rp, a_e, a_c, b_rp, b_e, b_c, I: int, K: int, J: int, tol: float = 0.0, n: int | None = None):
+    """Matrix product of polynomial matrices (Section 3.3: mtimes follows
+    matrix semantics; entries row-major in CSR batches, A is I x K, B is
+    K x J).  Entry (i, j) is simplify of the raw products of A_ik and B_kj
+    concatenated over k = 0..K-1, each in (term of A_ik, term of B_kj)
+    order; one rounding per product, the sums of simplify in that order."""
+    a_rp = np.asarray(a_rp, np.int64)
+    b_rp = np.asarray(b_rp, np.int64)
+    n = n if n is not None else np.asarray(a_e).shape[1]
+    a_e, a_c = _u8(a_e, n), _f64(a_c)
+    b_e, b_c = _u8(b_e, n), _f64(b_c)
+    outs = []
+    for i in range(I):
+        for j in range(J):
+            es, cs = [], []
+            for k in range(K):
+                pa, pb = i * K + k, k * J + j
+                e, c = expand(a_e[a_rp[pa]:a_rp[pa + 1]], a_c[a_rp[pa]:a_rp[pa + 1]],
+                              b_e[b_rp[pb]:b_rp[pb + 1]], b_c[b_rp[pb]:b_rp[pb + 1]], n)
+                es.append(e)
+                cs.append(c)
+            e = np.vstack(es) if es else np.zeros((0, n), np.uint8)
+            c = np.concatenate(cs) if cs else np.zeros(0)
+            outs.append(simplify(e, c, tol, n) if e.shape[0] else (e, c))
+    return _csr(outs, n)

@@ -500,3 +500,58 @@ def test_affine_normal_equiaffine_covariance():
     nu2, _ = oracle.affine_normal_from_derivatives(g2, H2, T2, 0.0)
     r = nu2 / (A @ nu)
     assert (r > 0).all() and np.ptp(r) <= 1e-9 * r.mean()
+
+
+# ------------------------------------------------------- polynomial matrices
+
+def _mat(polys, n):
+    rp, E, C = W.csr_from_list(polys, n)
+    return rp, E, C
+
+
+def test_mtimes_paper_matrix_square(golden):
+    """Section 3.3: A = [x1, 1; 0, x2], A^2 = [x1^2, x1 + x2; 0, x2^2]."""
+    g = golden["W6_matrix_ops"]
+    n = g["n"]
+    A = [poly_from_json(t, n) for t in g["A"]]
+    rp, E, C = _mat(A, n)
+    orp, oe, oc = oracle.mtimes(rp, E, C, rp, E, C, 2, 2, 2, n=n)
+    for q in range(4):
+        got = (oe[orp[q]:orp[q + 1]], oc[orp[q]:orp[q + 1]])
+        assert as_termset(*got) == as_termset(*poly_from_json(g["matrix_square"][q], n))
+    assert orp[3] == orp[2]                          # the (2,1) entry is the structural zero
+
+
+def test_mtimes_identity_and_scalar_case():
+    """A I = A bitwise for simplified entries (products by 1 are exact), and
+    a 1 x 1 product is the entrywise times."""
+    rng = W.rng_for(3401)
+    n = 3
+    A = [oracle.simplify(*W.random_poly(rng, n, 3, 12, integer=False), n=n) for _ in range(6)]   # 2 x 3
+    one = (np.zeros((1, n), np.uint8), np.array([1.0]))
+    zero = (np.zeros((0, n), np.uint8), np.zeros(0))
+    Id = [one if i == j else zero for i in range(3) for j in range(3)]
+    arp, ae, ac = _mat(A, n)
+    irp, ie, ic = _mat(Id, n)
+    orp, oe, oc = oracle.mtimes(arp, ae, ac, irp, ie, ic, 2, 3, 3, n=n)
+    assert np.array_equal(orp, arp) and np.array_equal(oe, ae)
+    assert oc.view(np.uint64).tolist() == ac.view(np.uint64).tolist()
+    p, q = A[0], A[1]
+    _, e1, c1 = oracle.mtimes([0, p[0].shape[0]], p[0], p[1], [0, q[0].shape[0]], q[0], q[1], 1, 1, 1, n=n)
+    e2, c2 = oracle.mul(p[0], p[1], q[0], q[1], n=n)
+    assert np.array_equal(e1, e2) and np.array_equal(c1, c2)
+
+
+def test_mtimes_associative_on_integers():
+    """(A B) C = A (B C) exactly when every coefficient is a small integer."""
+    rng = W.rng_for(3402)
+    n = 3
+    A = [W.random_poly(rng, n, 2, 5) for _ in range(2 * 3)]
+    B = [W.random_poly(rng, n, 2, 5) for _ in range(3 * 2)]
+    Cm = [W.random_poly(rng, n, 2, 5) for _ in range(2 * 2)]
+    a, b, c = _mat(A, n), _mat(B, n), _mat(Cm, n)
+    ab = oracle.mtimes(*a, *b, 2, 3, 2, n=n)
+    left = oracle.mtimes(*ab, *c, 2, 2, 2, n=n)
+    bc = oracle.mtimes(*b, *c, 3, 2, 2, n=n)
+    right = oracle.mtimes(*a, *bc, 2, 3, 2, n=n)
+    assert all(np.array_equal(x, y) for x, y in zip(left, right))
