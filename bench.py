@@ -16,8 +16,9 @@ It also measures the evaluation metric: 4,096 polynomials over the full
 degree <= 4 monomial set in n=30 variables (46,376 monomials) at 65,536
 points, in plain FP64 (FP64 MFMA) and split BF16 (BF16 MFMA, FP32
 accumulation, FP64 recombination), each with its error against an FP64
-reference on sampled outputs; and the sparse derivative paths and the
-affine-normal direction of a sparse quartic at a batch of points.
+reference on sampled outputs; the sparse derivative paths, the
+affine-normal direction of a sparse quartic at a batch of points, and the
+square of a 3 x 3 polynomial matrix.
 
 Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
 """
@@ -79,6 +80,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the polynomial-matrix workload")
     ap.add_argument("--no-deriv", action="store_true", help="skip the quartic derivative workload")
     ap.add_argument("--no-affine", action="store_true", help="skip the affine-normal workload")
+    ap.add_argument("--no-mtimes", action="store_true", help="skip the polynomial-matrix product workload")
     ap.add_argument("--affine-n", type=int, default=64)
     ap.add_argument("--affine-points", type=int, default=4096)
     ap.add_argument("--graph", action="store_true", help="also time the times+simplify step as a captured HIP graph")
@@ -314,6 +316,30 @@ def bench_affine(args):
             "all_finite": finite, "regularization": 1e-8}
 
 
+def bench_mtimes(args):
+    """A^2 for a 3 x 3 polynomial matrix whose entries are random degree-4
+    polynomials in n=8 with 300 distinct monomials (N(0,1) coefficients):
+    27 entry products, 2,430,000 raw terms."""
+    import torch
+    import paper_2604_06575_amd as ph
+    import workloads as W
+
+    rng = W.rng_for(W.SEED_BASE + 95)
+    n, d, terms, I = 8, 4, 300, 3
+    ents = [W.random_poly(rng, n, d, terms, integer=False, distinct=True) for _ in range(I * I)]
+    rp, E, C = W.csr_from_list(ents, n)
+    a = ph.batch_from_numpy(rp, E, C, n=n, max_exp=d)
+    ws_bytes, raw = ph.mtimes_workspace(a, a, I, I, I)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    out = ph._empty_out(n, I * I, raw, 2 * d, "cuda")
+    step = lambda: ph.mtimes(a, a, I, I, I, ws=ws, out=out, finish=False)  # noqa: E731
+    ph.mtimes(a, a, I, I, I, ws=ws, out=out, finish=True, trim=False)
+    merged = int(out.row_ptr_host[-1])
+    t, _ = time_events(step, 10, 2)
+    return {"matrix": f"{I}x{I}", "n": n, "terms_per_entry": terms, "raw_terms": raw, "merged_terms_out": merged,
+            "ms": t * 1e3, "raw_terms_per_s": raw / t}
+
+
 def bench_graph(args, m):
     """The times+simplify step captured once into a HIP graph and replayed."""
     import torch
@@ -428,6 +454,8 @@ def main():
         line["quartic_derivatives"] = bench_deriv(args)
     if not args.no_affine:
         line["affine_normal"] = bench_affine(args)
+    if not args.no_mtimes:
+        line["mtimes"] = bench_mtimes(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(line), flush=True)

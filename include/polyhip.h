@@ -198,6 +198,21 @@ poly_status poly_eval_backward(const poly_csr *f, const double *X, int64_t N,
                                const double *gY, double *dX, double *dC,
                                void *ws, size_t ws_bytes, void *stream);
 
+/* --------------------------------------------------- polynomial matrices
+ * out = A * B for polynomial matrices (Section 3.3, mtimes: matrix
+ * semantics): A is I x K and B is K x J CSR batches with entries in
+ * row-major order (A->npolys == I*K, B->npolys == K*J, same nvars);
+ * out->npolys == I*J.  Entry (i, j) is simplify(R_ij, zero_tol) where R_ij
+ * concatenates, for k = 0..K-1, the raw products of A_ik and B_kj in
+ * (term of A_ik, term of B_kj) order (exponent rows added, coefficients
+ * multiplied and rounded once).  out->max_exp >= A->max_exp + B->max_exp
+ * (at most 255); out->capacity >= the raw term count returned by the query
+ * (device-checked, POLY_ERR_CAPACITY).  Matrix powers are repeated products. */
+poly_status poly_mtimes_workspace(const poly_csr *A, const poly_csr *B, int64_t I, int64_t K, int64_t J,
+                                  size_t *ws_bytes, int64_t *raw_terms);
+poly_status poly_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t K, int64_t J,
+                        poly_csr *out, double zero_tol, void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------- affine normal
  * Affine-normal direction of one polynomial (f->npolys == 1, 2 <= n <= 128)
  * at N points (Section 5, the exact log-determinant method): with

@@ -39,6 +39,7 @@ EXPORTS = [
     "poly_eval_backward_workspace", "poly_eval_backward",
     "poly_eval_dense_workspace", "poly_eval_dense",
     "poly_affine_normal_workspace", "poly_affine_normal",
+    "poly_mtimes_workspace", "poly_mtimes",
 ]
 
 
@@ -104,6 +105,8 @@ def lib():
         "poly_eval_backward": ([pcsr, P, i64, P, P, P, P, ctypes.c_size_t, P], i32),
         "poly_eval_dense_workspace": ([i32, i64, i64, i64, i32, i32, psz], i32),
         "poly_affine_normal_workspace": ([pcsr, i64, psz], i32),
+        "poly_mtimes_workspace": ([pcsr, pcsr, i64, i64, i64, psz, ctypes.POINTER(i64)], i32),
+        "poly_mtimes": ([pcsr, pcsr, i64, i64, i64, pcsr, d, P, ctypes.c_size_t, P], i32),
         "poly_affine_normal": ([pcsr, P, i64, d, P, P, P, ctypes.c_size_t, P], i32),
         "poly_eval_dense": ([i32, i64, P, i32, i64, P, i64, P, P, i32, i32, P, ctypes.c_size_t, P], i32),
     }
@@ -309,6 +312,41 @@ def mul(a: Batch, b: Batch, tol: float = 0.0, trim: bool = True, ws: torch.Tenso
     if not finish:
         return out
     return _finish(out, ws, "poly_mul", trim)
+
+
+def mtimes_workspace(a: Batch, b: Batch, I: int, K: int, J: int) -> tuple[int, int]:
+    ws_bytes = ctypes.c_size_t()
+    raw = ctypes.c_int64()
+    _check(lib().poly_mtimes_workspace(ctypes.byref(a.csr()), ctypes.byref(b.csr()), I, K, J,
+                                       ctypes.byref(ws_bytes), ctypes.byref(raw)), "poly_mtimes_workspace")
+    return int(ws_bytes.value), int(raw.value)
+
+
+def mtimes(a: Batch, b: Batch, I: int, K: int, J: int, tol: float = 0.0, trim: bool = True,
+           ws: torch.Tensor | None = None, out: Batch | None = None, finish: bool = True) -> Batch:
+    """Matrix product of polynomial matrices: a is I x K, b is K x J, both
+    with entries in row-major order; returns the I x J product."""
+    L = lib()
+    ws_bytes, raw = mtimes_workspace(a, b, I, K, J)
+    if ws is None or ws.numel() < ws_bytes:
+        ws = _workspace(ws_bytes, a.coefs.device)
+    if out is None:
+        out = _empty_out(a.n, I * J, raw, a.max_exp + b.max_exp, a.coefs.device)
+    _check(L.poly_mtimes(ctypes.byref(a.csr()), ctypes.byref(b.csr()), I, K, J, ctypes.byref(out.csr()),
+                         float(tol), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "poly_mtimes")
+    if not finish:
+        return out
+    return _finish(out, ws, "poly_mtimes", trim)
+
+
+def mpower(a: Batch, I: int, p: int, tol: float = 0.0) -> Batch:
+    """a^p for a square I x I polynomial matrix (p >= 1): p - 1 products
+    a * (a * (... a)), each one library call."""
+    assert p >= 1
+    r = a
+    for _ in range(p - 1):
+        r = mtimes(a, r, I, I, I, tol)
+    return r
 
 
 def jacobian(b: Batch, trim: bool = True) -> Batch:

@@ -137,6 +137,9 @@ struct SimplifyPlan {
     size_t total;
 };
 
+poly_status run_simplify(const poly_csr *in, poly_csr *out, double zero_tol, void *ws, const struct SimplifyPlan &pl,
+                         hipStream_t s);
+
 SimplifyPlan plan_simplify(int64_t P, int64_t T)
 {
     Layout L;
@@ -638,13 +641,24 @@ poly_status poly_simplify(const poly_csr *in, poly_csr *out, double zero_tol, vo
     const SimplifyPlan pl = plan_simplify(P, T);
     if (!ws || ws_bytes < pl.total) return POLY_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
-    int32_t *status = at<int32_t>(ws, 0);
     clear_u64(at<unsigned long long>(ws, 0), 1, s);
     if (P == 0) {
         clear_u64((unsigned long long *)out->row_ptr, 1, s);
         LAUNCH_CHECK();
         return POLY_OK;
     }
+    return run_simplify(in, out, zero_tol, ws, pl, s);
+}
+
+namespace {
+
+poly_status run_simplify(const poly_csr *in, poly_csr *out, double zero_tol, void *ws, const SimplifyPlan &pl,
+                         hipStream_t s)
+{
+    const int n = in->nvars;
+    const int bits = bit_width_u32((uint32_t)in->max_exp);
+    const int64_t P = in->npolys, T = total_terms(in);
+    int32_t *status = at<int32_t>(ws, 0);
     uint64_t *keys = at<uint64_t>(ws, pl.keys);
     unsigned long long *queue = at<unsigned long long>(ws, pl.queue);
     clear_u64(queue, 1, s);
@@ -673,6 +687,8 @@ poly_status poly_simplify(const poly_csr *in, poly_csr *out, double zero_tol, vo
     LAUNCH_CHECK();
     return POLY_OK;
 }
+
+}  // namespace
 
 // ----------------------------------------------------------------------- mul
 
@@ -1168,6 +1184,114 @@ poly_status check_affine(const poly_csr *f, const double *X, int64_t N, const do
     if (f->npolys != 1 || f->nvars < 2 || f->nvars > AN_MAX_N || !(reg >= 0.0) || reg > 1e300)
         return f->nvars > AN_MAX_N ? POLY_ERR_UNSUPPORTED : POLY_ERR_ARG;
     return POLY_OK;
+}
+
+namespace {
+
+// Products of polynomial matrices: the raw batch (sizes and offsets from
+// the row pointers, then one workgroup per output entry), then the batched
+// simplify.  The simplify workspace comes first; the raw batch after it.
+struct MtimesPlan {
+    SimplifyPlan sp;
+    size_t rrp, re, rc, sizes, tmp, total;
+    int64_t raw;
+};
+
+poly_status check_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t K, int64_t J)
+{
+    poly_status st;
+    if ((st = check_csr(A, true)) != POLY_OK) return st;
+    if ((st = check_csr(B, true)) != POLY_OK) return st;
+    if (I < 0 || K < 0 || J < 0 || A->nvars != B->nvars || A->npolys != I * K || B->npolys != K * J)
+        return POLY_ERR_ARG;
+    if (A->max_exp + B->max_exp > 255) return POLY_ERR_ARG;
+    if ((int64_t)A->nvars * bit_width_u32((uint32_t)(A->max_exp + B->max_exp)) > 64) return POLY_ERR_KEY_OVERFLOW;
+    return POLY_OK;
+}
+
+poly_status plan_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t K, int64_t J,
+                        std::vector<int64_t> &rph, MtimesPlan &m)
+{
+    const int64_t Q = I * J;
+    rph.assign(Q + 1, 0);
+    for (int64_t i = 0; i < I; ++i)
+        for (int64_t j = 0; j < J; ++j) {
+            int64_t r = 0;
+            for (int64_t k = 0; k < K; ++k)
+                r += (A->row_ptr_host[i * K + k + 1] - A->row_ptr_host[i * K + k]) *
+                     (B->row_ptr_host[k * J + j + 1] - B->row_ptr_host[k * J + j]);
+            rph[i * J + j + 1] = rph[i * J + j] + r;
+        }
+    m.raw = rph[Q];
+    if (m.raw >= (int64_t(1) << 32)) return POLY_ERR_UNSUPPORTED;
+    m.sp = plan_simplify(Q, m.raw);
+    Layout L;
+    L.off = m.sp.total;
+    m.rrp = L.take(8 * (Q + 1));
+    m.re = L.take((size_t)m.raw * A->nvars);
+    m.rc = L.take(8 * m.raw);
+    m.sizes = L.take(8 * Q);
+    m.tmp = L.take(8 * scan_tmp_count(Q));
+    m.total = L.total();
+    return POLY_OK;
+}
+
+}  // namespace
+
+poly_status poly_mtimes_workspace(const poly_csr *A, const poly_csr *B, int64_t I, int64_t K, int64_t J,
+                                  size_t *ws_bytes, int64_t *raw_terms)
+{
+    poly_status st = check_mtimes(A, B, I, K, J);
+    if (st != POLY_OK) return st;
+    if (!ws_bytes || !raw_terms) return POLY_ERR_ARG;
+    std::vector<int64_t> rph;
+    MtimesPlan m;
+    if ((st = plan_mtimes(A, B, I, K, J, rph, m)) != POLY_OK) return st;
+    *ws_bytes = m.total;
+    *raw_terms = m.raw;
+    return POLY_OK;
+}
+
+poly_status poly_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t K, int64_t J, poly_csr *out,
+                        double zero_tol, void *ws, size_t ws_bytes, void *stream)
+{
+    poly_status st = check_mtimes(A, B, I, K, J);
+    if (st != POLY_OK) return st;
+    if ((st = check_csr(out, false)) != POLY_OK) return st;
+    const int n = A->nvars;
+    if (out->nvars != n || out->npolys != I * J || out->max_exp < A->max_exp + B->max_exp) return POLY_ERR_ARG;
+    if (!(zero_tol >= 0.0)) return POLY_ERR_ARG;
+    std::vector<int64_t> rph;
+    MtimesPlan m;
+    if ((st = plan_mtimes(A, B, I, K, J, rph, m)) != POLY_OK) return st;
+    if (!ws || ws_bytes < m.total) return POLY_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t *status = at<int32_t>(ws, 0);
+    clear_u64(at<unsigned long long>(ws, 0), 1, s);
+    const int64_t Q = I * J;
+    if (Q == 0) {
+        clear_u64((unsigned long long *)out->row_ptr, 1, s);
+        LAUNCH_CHECK();
+        return POLY_OK;
+    }
+    int64_t *sizes = at<int64_t>(ws, m.sizes);
+    int64_t *rrp = at<int64_t>(ws, m.rrp);
+    uint8_t *re = at<uint8_t>(ws, m.re);
+    double *rc = at<double>(ws, m.rc);
+    hipLaunchKernelGGL(k_mat_raw_sizes, dim3(grid1(Q, 256)), dim3(256), 0, s, A->row_ptr, B->row_ptr, I, K, J, sizes);
+    launch_scan(sizes, Q, rrp, at<int64_t>(ws, m.tmp), status, s);
+    hipLaunchKernelGGL(k_mat_expand, dim3((unsigned)Q), dim3(MAT_THREADS), 0, s, A->row_ptr, A->exps, A->coefs,
+                       B->row_ptr, B->exps, B->coefs, I, K, J, n, (const int64_t *)rrp, re, rc);
+    poly_csr R;
+    R.nvars = n;
+    R.max_exp = A->max_exp + B->max_exp;
+    R.npolys = Q;
+    R.capacity = m.raw;
+    R.row_ptr_host = rph.data();
+    R.row_ptr = rrp;
+    R.exps = re;
+    R.coefs = rc;
+    return run_simplify(&R, out, zero_tol, ws, m.sp, s);
 }
 
 poly_status poly_affine_normal_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)

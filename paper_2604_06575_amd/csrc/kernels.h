@@ -175,6 +175,14 @@ __global__ void k_encode_support(const uint8_t *exps, int64_t T, int n, uint64_t
 constexpr int EV_MAX_DEG = 12;   // total degree handled by the factor-list encoding
 __global__ void k_encode_factors(const uint8_t *exps, int64_t T, int n, uint32_t *enc, const int64_t *used);
 
+// products of polynomial matrices (matrix.hip)
+constexpr int MAT_THREADS = 256;
+__global__ void k_mat_raw_sizes(const int64_t *a_rp, const int64_t *b_rp, int64_t I, int64_t K, int64_t J,
+                                int64_t *sizes);
+__global__ void k_mat_expand(const int64_t *a_rp, const uint8_t *a_e, const double *a_c, const int64_t *b_rp,
+                             const uint8_t *b_e, const double *b_c, int64_t I, int64_t K, int64_t J, int n,
+                             const int64_t *r_rp, uint8_t *r_e, double *r_c);
+
 // affine-normal direction (affine.hip): one workgroup per point
 constexpr int AN_THREADS = 256;
 constexpr int AN_MAX_N = 128;

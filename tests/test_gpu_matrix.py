@@ -1,0 +1,101 @@
+"""Products of polynomial matrices (Section 3.3, mtimes) through the C-ABI,
+bit-exact against the oracle: the raw products of A_ik and B_kj
+concatenated over k, then simplify."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ph():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_06575_amd as ph
+    ph.lib()
+    return ph
+
+
+def _batch(ph, polys, n, max_exp):
+    rp, E, C = W.csr_from_list(polys, n)
+    return ph.batch_from_numpy(rp, E, C, n=n, max_exp=max_exp), (rp, E, C)
+
+
+def _same(ph, got, want):
+    grp, gE, gC = ph.batch_to_numpy(got)
+    rp, E, C = want
+    assert np.array_equal(grp, rp), "row pointers differ"
+    assert np.array_equal(gE, E), "exponent rows differ"
+    assert gC.view(np.uint64).tolist() == np.asarray(C, np.float64).view(np.uint64).tolist(), "coefficients differ"
+
+
+def _case(ph, A, B, I, K, J, n, d, tol=0.0):
+    a, ra = _batch(ph, A, n, d)
+    b, rb = _batch(ph, B, n, d)
+    got = ph.mtimes(a, b, I, K, J, tol=tol)
+    _same(ph, got, oracle.mtimes(*ra, *rb, I, K, J, tol=tol, n=n))
+    return got
+
+
+def test_paper_matrix_square(ph):
+    g = json.load(open(os.path.join(HERE, "golden", "worked_examples.json")))["W6_matrix_ops"]
+    n = g["n"]
+    A = [(np.array([t[1] for t in e], np.uint8).reshape(-1, n), np.array([t[0] for t in e], float)) for e in g["A"]]
+    say("mtimes: A^2 of Section 3.3")
+    _case(ph, A, A, 2, 2, 2, n, 1)
+
+
+@pytest.mark.parametrize("I,K,J", [(3, 4, 2), (1, 5, 1), (4, 1, 3), (2, 2, 2)])
+def test_random_shapes(ph, I, K, J):
+    """Gaussian coefficients (so only the defined summation order matches),
+    repeated and cancelling terms, some zero entries."""
+    rng = W.rng_for(3500 + 100 * I + 10 * K + J)
+    n, d = 3, 3
+    A = [W.random_poly(rng, n, d, int(rng.integers(0, 15)), integer=False) for _ in range(I * K)]
+    B = [W.random_poly(rng, n, d, int(rng.integers(0, 15)), integer=False) for _ in range(K * J)]
+    say(f"mtimes: {I}x{K} by {K}x{J}")
+    _case(ph, A, B, I, K, J, n, d)
+
+
+def test_several_tiles(ph):
+    """8 x 8 matrices of 40-term entries: 12,800 raw terms per output entry."""
+    rng = W.rng_for(3601)
+    n, d = 5, 4
+    A = [W.random_poly(rng, n, d, 40, integer=False) for _ in range(64)]
+    B = [W.random_poly(rng, n, d, 40, integer=False) for _ in range(64)]
+    say("mtimes: 8x8 by 8x8, 40 terms per entry")
+    _case(ph, A, B, 8, 8, 8, n, d)
+
+
+def test_tolerance_and_mpower(ph):
+    rng = W.rng_for(3602)
+    n, d = 2, 2
+    A = [W.random_poly(rng, n, d, 4) for _ in range(9)]
+    a, ra = _batch(ph, A, n, d)
+    say("mpower: A^3, 3x3")
+    got = ph.mpower(a, 3, 3)
+    want = oracle.mtimes(*ra, *oracle.mtimes(*ra, *ra, 3, 3, 3, n=n), 3, 3, 3, n=n)
+    _same(ph, got, want)
+    _case(ph, A, A, 3, 3, 3, n, d, tol=50.0)
+
+
+def test_empty(ph):
+    n = 2
+    a, _ = _batch(ph, [], n, 1)
+    b, _ = _batch(ph, [(np.array([[1, 0]], np.uint8), np.array([2.0]))] * 3, n, 1)
+    got = ph.mtimes(a, b, 0, 1, 3)
+    assert got.npolys == 0
