@@ -48,10 +48,11 @@ def sort_plan(n, max_exp_a, max_exp_b, raw):
     rule): mixed-radix keys in [0, r^n) with r = max_exp_a + max_exp_b + 1,
     as few passes of at most 8 bits as that range needs, and -- when the
     digits left after the first pass and the raw index fit one 64-bit word --
-    packed 8-byte elements after the first pass.  Returns (passes, digit
+    packed 8-byte elements from the first pass on.  Returns (passes, digit
     bits, packed, average algorithmic bytes per raw term per scatter launch):
     a pass reads and writes every element once, 12 B each way unpacked, 8 B
-    packed, the first packed pass reading 12 and writing 8."""
+    packed; the first pass generates its elements from the operands (reads
+    nothing per raw term) and writes 8 B packed or 12 B unpacked."""
     r = max_exp_a + max_exp_b + 1
     key_bits = (r ** n - 1).bit_length()
     passes = -(-key_bits // 8)
@@ -60,7 +61,7 @@ def sort_plan(n, max_exp_a, max_exp_b, raw):
     packed = passes >= 2 and key_bits - db + raw_bits <= 64
     if not passes:
         return 0, db, packed, 0.0
-    per_term = (20 + 16 * (passes - 1)) / passes if packed else float(BYTES_PER_RAW_TERM)
+    per_term = (8 + 16 * (passes - 1)) / passes if packed else (12 + 24 * (passes - 1)) / passes
     return passes, db, packed, per_term
 
 
@@ -411,10 +412,11 @@ def main():
         passes, db, packed, per_term = m["plan"]
         alg_bytes = per_term * m["raw"]
         alg_note = (f"average per launch over the {passes} radix passes of {db}-bit digits: every element read "
-                    f"once and written once; (key 8 B, raw index 4 B) pairs"
-                    + (", packed into one 8-byte word after the first pass (that pass reads 12 B, writes 8 B; "
-                       f"the others 8 B each way) = {per_term:.2f} B x raw terms" if packed else
-                       " = 24 B x raw terms"))
+                    f"once and written once, except that the first pass generates its elements from the operands "
+                    f"(no per-term read); (key 8 B, raw index 4 B) pairs"
+                    + (", packed into one 8-byte word from the first pass on (first pass writes 8 B, the others "
+                       f"read and write 8 B) = {per_term:.2f} B x raw terms" if packed else
+                       f" (first pass writes 12 B, the others read and write 12 B) = {per_term:.2f} B x raw terms"))
     else:
         alg_bytes = BYTES_PER_RAW_TERM * m["raw"]
         alg_note = "per launch: every raw product term as a 64-bit key and a 32-bit payload, written and read once"

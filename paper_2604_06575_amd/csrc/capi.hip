@@ -812,8 +812,7 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
         // scatter (after its scan has finished) for the next scan
         const int64_t scan_state = scan_tmp_count(std::max<int64_t>(GS_BINS * m.gs_blocks, ceil_div(R, MG_TILE)));
         clear_u64((unsigned long long *)tmp, scan_state, s);
-        hipLaunchKernelGGL(k_gs_generate, dim3((unsigned)std::min<int64_t>(Ta, 65535)), dim3(GS_THREADS), 0, s,
-                           A.ka, A.kb_s, Ta, Tb, kcur, vcur);
+
         // key range r^n (at most 2^(n * bits), so it fits 64 bits); as few
         // passes of at most GS_BITS bits as it needs, digits as even as possible
         unsigned __int128 span = 1;
@@ -828,31 +827,40 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
         const int raw_bits = R > 1 ? 64 - __builtin_clzll((unsigned long long)(R - 1)) : 0;
         const bool packed = passes >= 2 && key_bits - db + raw_bits <= 64;
         const int64_t hgrid = std::min<int64_t>(ceil_div(nb, GS_HIST_THREADS / kWave), (int64_t)device_cus() * 8);
+        // the first pass generates the raw product from the operands (keys
+        // ka[i] + kb_s[j] in raw order): it is never written to memory
+        GsGen gen;
+        gen.ka = (const uint64_t *)A.ka;
+        gen.kb_s = (const uint64_t *)A.kb_s;
+        gen.tb = (uint32_t)Tb;
+        gen.inv_tb = 1.0 / (double)Tb;
         auto pass = [&](auto dbc, int p) {
             constexpr int DB = decltype(dbc)::value;
             const int shift = packed && p > 0 ? raw_bits + (p - 1) * DB : p * DB;
-            hipLaunchKernelGGL(k_gs_hist<DB>, dim3((unsigned)hgrid), dim3(GS_HIST_THREADS), 0, s,
-                               (const uint64_t *)kcur, R, shift, nb, hist);
+            if (p == 0)
+                hipLaunchKernelGGL((k_gs_hist<DB, true>), dim3((unsigned)hgrid), dim3(GS_HIST_THREADS), 0, s,
+                                   (const uint64_t *)kcur, R, shift, nb, hist, gen);
+            else
+                hipLaunchKernelGGL((k_gs_hist<DB, false>), dim3((unsigned)hgrid), dim3(GS_HIST_THREADS), 0, s,
+                                   (const uint64_t *)kcur, R, shift, nb, hist, gen);
             launch_scan(hist, ((int64_t)1 << DB) * nb, hoff, tmp, status, s, true);
             TimedLaunch tl(POLY_TIMING_MUL, s);
-            if (!packed)
-                hipLaunchKernelGGL((k_gs_scatter<DB, GS_KV>), dim3((unsigned)nb), dim3(GS_SC_THREADS), 0, s,
+            auto scatter = [&](auto modec) {
+                constexpr int MODE = decltype(modec)::value;
+                hipLaunchKernelGGL((k_gs_scatter<DB, MODE>), dim3((unsigned)nb), dim3(GS_SC_THREADS), 0, s,
                                    (const uint64_t *)kcur, (const uint32_t *)vcur, R, shift, nb,
-                                   (const int64_t *)hoff, knext, vnext, raw_bits,
-                                   (unsigned long long *)tmp, scan_state);
-            else if (p == 0)
-                hipLaunchKernelGGL((k_gs_scatter<DB, GS_KV_TO_PACKED>), dim3((unsigned)nb), dim3(GS_SC_THREADS), 0,
-                                   s,
-                                   (const uint64_t *)kcur, (const uint32_t *)vcur, R, shift, nb,
-                                   (const int64_t *)hoff, knext, vnext, raw_bits,
-                                   (unsigned long long *)tmp, scan_state);
-            else
-                hipLaunchKernelGGL((k_gs_scatter<DB, GS_PACKED>), dim3((unsigned)nb), dim3(GS_SC_THREADS), 0, s,
-                                   (const uint64_t *)kcur, (const uint32_t *)vcur, R, shift, nb,
-                                   (const int64_t *)hoff, knext, vnext, raw_bits,
-                                   (unsigned long long *)tmp, scan_state);
+                                   (const int64_t *)hoff, knext, vnext, raw_bits, (unsigned long long *)tmp,
+                                   scan_state, gen);
+            };
+            if (p == 0 && packed) scatter(std::integral_constant<int, GS_GEN_TO_PACKED>());
+            else if (p == 0) scatter(std::integral_constant<int, GS_GEN_KV>());
+            else if (packed) scatter(std::integral_constant<int, GS_PACKED>());
+            else scatter(std::integral_constant<int, GS_KV>());
             tl.done(s);
         };
+        if (passes == 0)   // a single key value: the raw product unsorted
+            hipLaunchKernelGGL(k_gs_generate, dim3((unsigned)std::min<int64_t>(Ta, 65535)), dim3(GS_THREADS), 0, s,
+                               A.ka, A.kb_s, Ta, Tb, kcur, vcur);
         for (int p = 0; p < passes; ++p) {
             switch (db) {
             case 4: pass(std::integral_constant<int, 4>(), p); break;

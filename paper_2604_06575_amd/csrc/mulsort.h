@@ -24,13 +24,33 @@ __global__ void k_gs_sort_partner(const uint64_t *keys, const double *coefs, int
                                   uint32_t *perm, double *coefs_s);
 __global__ void k_gs_generate(const uint64_t *ka, const uint64_t *kb_s, int64_t ta, int64_t tb, uint64_t *keys,
                               uint32_t *vals);
-template <int DB>
-__global__ void k_gs_hist(const uint64_t *keys, int64_t R, int shift, int64_t nblocks, int64_t *hist);
-enum { GS_KV = 0, GS_KV_TO_PACKED = 1, GS_PACKED = 2 };   // element formats of a radix pass
+// Elements of the raw product in raw order, generated instead of read: the
+// element with raw index r = i * tb + j has key ka[i] + kb_s[j].  The first
+// radix pass and its histogram read the product this way, so it is never
+// written to memory.
+struct GsGen {
+    const uint64_t *ka;
+    const uint64_t *kb_s;
+    uint32_t tb;
+    double inv_tb;   // 1 / tb
+    __device__ uint64_t key(uint32_t r) const
+    {
+        // r / tb in double precision (within one of the quotient for 32-bit r), then corrected
+        uint32_t i = (uint32_t)((double)r * inv_tb);
+        if (i * (uint64_t)tb > r) --i;
+        else if ((uint64_t)(i + 1) * tb <= r) ++i;
+        return ka[i] + kb_s[r - i * tb];
+    }
+};
+
+template <int DB, bool GEN>
+__global__ void k_gs_hist(const uint64_t *keys, int64_t R, int shift, int64_t nblocks, int64_t *hist, GsGen gen);
+// element formats of a radix pass
+enum { GS_KV = 0, GS_KV_TO_PACKED = 1, GS_PACKED = 2, GS_GEN_KV = 3, GS_GEN_TO_PACKED = 4 };
 template <int DB, int MODE>
 __global__ void k_gs_scatter(const uint64_t *keys_in, const uint32_t *vals_in, int64_t R, int shift,
                              int64_t nblocks, const int64_t *hist_off, uint64_t *keys_out, uint32_t *vals_out,
-                             int raw_bits, unsigned long long *clear, int64_t clear_n);
+                             int raw_bits, unsigned long long *clear, int64_t clear_n, GsGen gen);
 // Division constants for turning mixed-radix keys back into bit fields.
 struct RadixDecode {
     uint64_t radix;         // r

@@ -102,9 +102,9 @@ __global__ void __launch_bounds__(GS_THREADS) k_gs_generate(const uint64_t *ka, 
 // holding the same digit are found with wavefront ballots and their lowest
 // lane adds the group size.  Waves take tiles wave_id, wave_id + total
 // waves, ... (few, long-lived workgroups rather than one per tile).
-template <int DB>
+template <int DB, bool GEN>
 __global__ void __launch_bounds__(GS_HIST_THREADS) k_gs_hist(const uint64_t *keys, int64_t R, int shift,
-                                                            int64_t nblocks, int64_t *hist)
+                                                            int64_t nblocks, int64_t *hist, GsGen gen)
 {
     constexpr int W = GS_HIST_THREADS / kWave;
     constexpr int UN = 8;   // key loads in flight per lane
@@ -126,7 +126,8 @@ __global__ void __launch_bounds__(GS_HIST_THREADS) k_gs_hist(const uint64_t *key
 #pragma unroll
             for (int u = 0; u < UN; ++u) {
                 const int l = c0 + u * kWave + lane;
-                kv[u] = keys[t0 + (l < m ? l : m - 1)];
+                const int64_t g = t0 + (l < m ? l : m - 1);
+                kv[u] = GEN ? gen.key((uint32_t)g) : keys[g];
             }
             uint32_t dg[UN];
 #pragma unroll
@@ -160,7 +161,9 @@ __global__ void __launch_bounds__(GS_HIST_THREADS) k_gs_hist(const uint64_t *key
 // produced hist_off, ready for the next pass.
 //
 // MODE selects the element format: GS_KV (key array + raw index array, in
-// and out), GS_KV_TO_PACKED (key + raw index in; out one word per element,
+// and out), GS_GEN_KV / GS_GEN_TO_PACKED (the first pass: elements generated
+// from the operands, out as GS_KV / as GS_KV_TO_PACKED), GS_KV_TO_PACKED
+// (key + raw index in; out one word per element,
 // (key >> DB) << raw_bits | raw index: the digits still to sort above the
 // raw index -- the first pass of a sort whose remaining digits and raw index
 // fit 64 bits), GS_PACKED (packed words in and out).
@@ -169,7 +172,7 @@ __global__ void __launch_bounds__(GS_SC_THREADS) k_gs_scatter(const uint64_t *ke
                                                           int64_t R, int shift, int64_t nblocks,
                                                           const int64_t *hist_off, uint64_t *keys_out,
                                                           uint32_t *vals_out, int raw_bits,
-                                                          unsigned long long *clear, int64_t clear_n)
+                                                          unsigned long long *clear, int64_t clear_n, GsGen gen)
 {
     // the scan that produced hist_off is done: reset its state for the next one
     if (blockIdx.x == 0)
@@ -177,6 +180,7 @@ __global__ void __launch_bounds__(GS_SC_THREADS) k_gs_scatter(const uint64_t *ke
     constexpr int W = GS_SC_THREADS / kWave;
     constexpr int NB = 1 << DB;
     constexpr bool HAS_VALS = MODE != GS_PACKED;
+    constexpr bool GEN = MODE == GS_GEN_KV || MODE == GS_GEN_TO_PACKED;
     __shared__ uint64_t s_key[GS_TILE];
     __shared__ uint32_t s_val[HAS_VALS ? GS_TILE : 1];
     __shared__ uint32_t s_cnt[W][NB];
@@ -195,8 +199,13 @@ __global__ void __launch_bounds__(GS_SC_THREADS) k_gs_scatter(const uint64_t *ke
     for (int it = 0; it < GS_ITEMS; ++it) {
         const int e = (w * GS_ITEMS + it) * kWave + lane;
         const int ec = e < m ? e : m - 1;
-        k[it] = keys_in[t0 + ec];
-        v[it] = HAS_VALS ? vals_in[t0 + ec] : 0u;
+        if (GEN) {
+            v[it] = (uint32_t)(t0 + ec);
+            k[it] = gen.key(v[it]);
+        } else {
+            k[it] = keys_in[t0 + ec];
+            v[it] = HAS_VALS ? vals_in[t0 + ec] : 0u;
+        }
     }
 #pragma unroll
     for (int it = 0; it < GS_ITEMS; ++it) {
@@ -252,10 +261,10 @@ __global__ void __launch_bounds__(GS_SC_THREADS) k_gs_scatter(const uint64_t *ke
         const uint64_t key = s_key[l];
         const uint32_t d = (uint32_t)(key >> shift) & (NB - 1);
         const int64_t gpos = hist_off[(int64_t)d * nblocks + blockIdx.x] + (l - (int64_t)s_start[d]);
-        if (MODE == GS_KV) {
+        if (MODE == GS_KV || MODE == GS_GEN_KV) {
             keys_out[gpos] = key;
             vals_out[gpos] = s_val[l];
-        } else if (MODE == GS_KV_TO_PACKED) {
+        } else if (MODE == GS_KV_TO_PACKED || MODE == GS_GEN_TO_PACKED) {
             keys_out[gpos] = ((key >> DB) << raw_bits) | (uint64_t)s_val[l];
         } else {
             keys_out[gpos] = key;
@@ -490,56 +499,91 @@ __global__ void __launch_bounds__(MG_THREADS) k_gs_merge(const uint64_t *keys, c
     }
 }
 
-template __global__ void k_gs_hist<4>(const uint64_t *, int64_t, int, int64_t, int64_t *);
-template __global__ void k_gs_hist<5>(const uint64_t *, int64_t, int, int64_t, int64_t *);
-template __global__ void k_gs_hist<6>(const uint64_t *, int64_t, int, int64_t, int64_t *);
-template __global__ void k_gs_hist<7>(const uint64_t *, int64_t, int, int64_t, int64_t *);
-template __global__ void k_gs_hist<8>(const uint64_t *, int64_t, int, int64_t, int64_t *);
+template __global__ void k_gs_hist<4, false>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
+template __global__ void k_gs_hist<4, true>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
+template __global__ void k_gs_hist<5, false>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
+template __global__ void k_gs_hist<5, true>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
+template __global__ void k_gs_hist<6, false>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
+template __global__ void k_gs_hist<6, true>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
+template __global__ void k_gs_hist<7, false>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
+template __global__ void k_gs_hist<7, true>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
+template __global__ void k_gs_hist<8, false>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
+template __global__ void k_gs_hist<8, true>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
 template __global__ void k_gs_scatter<4, GS_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
                                                     const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t);
+                                                    unsigned long long *, int64_t, GsGen);
 template __global__ void k_gs_scatter<4, GS_KV_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
                                                     const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t);
+                                                    unsigned long long *, int64_t, GsGen);
 template __global__ void k_gs_scatter<4, GS_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
                                                     const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t);
+                                                    unsigned long long *, int64_t, GsGen);
+template __global__ void k_gs_scatter<4, GS_GEN_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t, GsGen);
+template __global__ void k_gs_scatter<4, GS_GEN_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t, GsGen);
 template __global__ void k_gs_scatter<5, GS_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
                                                     const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t);
+                                                    unsigned long long *, int64_t, GsGen);
 template __global__ void k_gs_scatter<5, GS_KV_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
                                                     const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t);
+                                                    unsigned long long *, int64_t, GsGen);
 template __global__ void k_gs_scatter<5, GS_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
                                                     const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t);
+                                                    unsigned long long *, int64_t, GsGen);
+template __global__ void k_gs_scatter<5, GS_GEN_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t, GsGen);
+template __global__ void k_gs_scatter<5, GS_GEN_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t, GsGen);
 template __global__ void k_gs_scatter<6, GS_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
                                                     const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t);
+                                                    unsigned long long *, int64_t, GsGen);
 template __global__ void k_gs_scatter<6, GS_KV_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
                                                     const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t);
+                                                    unsigned long long *, int64_t, GsGen);
 template __global__ void k_gs_scatter<6, GS_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
                                                     const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t);
+                                                    unsigned long long *, int64_t, GsGen);
+template __global__ void k_gs_scatter<6, GS_GEN_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t, GsGen);
+template __global__ void k_gs_scatter<6, GS_GEN_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t, GsGen);
 template __global__ void k_gs_scatter<7, GS_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
                                                     const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t);
+                                                    unsigned long long *, int64_t, GsGen);
 template __global__ void k_gs_scatter<7, GS_KV_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
                                                     const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t);
+                                                    unsigned long long *, int64_t, GsGen);
 template __global__ void k_gs_scatter<7, GS_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
                                                     const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t);
+                                                    unsigned long long *, int64_t, GsGen);
+template __global__ void k_gs_scatter<7, GS_GEN_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t, GsGen);
+template __global__ void k_gs_scatter<7, GS_GEN_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t, GsGen);
 template __global__ void k_gs_scatter<8, GS_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
                                                     const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t);
+                                                    unsigned long long *, int64_t, GsGen);
 template __global__ void k_gs_scatter<8, GS_KV_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
                                                     const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t);
+                                                    unsigned long long *, int64_t, GsGen);
 template __global__ void k_gs_scatter<8, GS_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
                                                     const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t);
+                                                    unsigned long long *, int64_t, GsGen);
+template __global__ void k_gs_scatter<8, GS_GEN_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t, GsGen);
+template __global__ void k_gs_scatter<8, GS_GEN_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
+                                                    const int64_t *, uint64_t *, uint32_t *, int,
+                                                    unsigned long long *, int64_t, GsGen);
 template __global__ void k_gs_merge<false>(const uint64_t *, const uint32_t *, int64_t, int64_t, int64_t,
                                            const uint64_t *, const uint64_t *, int, const double *,
                                            const double *, double, RadixDecode, uint64_t *, double *,
