@@ -182,7 +182,7 @@ struct MulPlan {
     size_t bk_pair, bk_lo, bk_hi, bk_stage_off, bk_count, out_off, cursor, st_key, st_coef;
     int64_t raw, nbuckets, target;
     bool sort_mode;         // one pair, raw product sorted globally (mulsort.hip)
-    size_t gs_keys0, gs_keys1, gs_vals0, gs_vals1, gs_hist, gs_hoff, gs_tmp, gs_count, gs_soff, gs_ooff;
+    size_t gs_keys0, gs_keys1, gs_vals0, gs_vals1, gs_hist, gs_hoff, gs_tmp, gs_count, gs_soff, gs_ooff, gs_pa, gs_pb;
     int64_t gs_blocks, gs_mblocks;   // radix-pass tiles, merge tiles
     bool lds_mode;          // partner and row keys of every pair fit in LDS
     size_t lds_dyn;         // dynamic LDS bytes of the LDS bucket kernel
@@ -254,6 +254,8 @@ poly_status plan_mul(const poly_csr *a, const poly_csr *b, MulPlan &m)
         m.gs_hist = L.take(8 * GS_BINS * m.gs_blocks);
         m.gs_hoff = L.take(8 * (GS_BINS * m.gs_blocks + 1));
         m.gs_tmp = L.take(8 * scan_tmp_count(std::max<int64_t>(GS_BINS * m.gs_blocks, ceil_div(raw, MG_TILE))));
+        m.gs_pa = L.take(16 * Ta);
+        m.gs_pb = L.take(16 * Tb);
         m.gs_mblocks = ceil_div(raw, MG_TILE);
         m.gs_count = L.take(8 * m.gs_mblocks);
         m.gs_soff = L.take(8 * m.gs_mblocks);
@@ -888,16 +890,22 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
         dec.digit_magic = (uint32_t)(0xffffffffull / radix);
         const int64_t mb = m.gs_mblocks;
         const int64_t mgrid = std::min<int64_t>(mb, (int64_t)device_cus() * MG_BLOCKS_PER_CU);
-        if (packed)
+        GsKC *pa = at<GsKC>(ws, m.gs_pa), *pb = at<GsKC>(ws, m.gs_pb);
+        if (packed) {
+            hipLaunchKernelGGL(k_gs_pairs, dim3(grid1(Ta, 256)), dim3(256), 0, s, (const uint64_t *)A.ka, a->coefs, Ta,
+                               pa);
+            hipLaunchKernelGGL(k_gs_pairs, dim3(grid1(Tb, 256)), dim3(256), 0, s, (const uint64_t *)A.kb_s, A.cb_s,
+                               Tb, pb);
             hipLaunchKernelGGL(k_gs_merge<true>, dim3((unsigned)mgrid), dim3(MG_THREADS), 0, s,
                                (const uint64_t *)kcur, (const uint32_t *)vcur, R, Ta, Tb, (const uint64_t *)A.ka,
-                               (const uint64_t *)A.kb_s, raw_bits, a->coefs, A.cb_s, zero_tol, dec, A.st_key,
-                               A.st_coef, cnt, soff);
-        else
+                               (const uint64_t *)A.kb_s, raw_bits, a->coefs, A.cb_s, (const GsKC *)pa,
+                               (const GsKC *)pb, zero_tol, dec, A.st_key, A.st_coef, cnt, soff);
+        } else {
             hipLaunchKernelGGL(k_gs_merge<false>, dim3((unsigned)mgrid), dim3(MG_THREADS), 0, s,
                                (const uint64_t *)kcur, (const uint32_t *)vcur, R, Ta, Tb, (const uint64_t *)A.ka,
-                               (const uint64_t *)A.kb_s, raw_bits, a->coefs, A.cb_s, zero_tol, dec, A.st_key,
-                               A.st_coef, cnt, soff);
+                               (const uint64_t *)A.kb_s, raw_bits, a->coefs, A.cb_s, (const GsKC *)pa,
+                               (const GsKC *)pb, zero_tol, dec, A.st_key, A.st_coef, cnt, soff);
+        }
         launch_scan(cnt, mb, ooff, tmp, status, s, true);
         hipLaunchKernelGGL(k_compact, dim3((unsigned)mb), dim3(256), 0, s, (const int64_t *)soff,
                            (const int64_t *)cnt, (const int64_t *)ooff, (const uint64_t *)A.st_key,

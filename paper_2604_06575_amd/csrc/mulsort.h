@@ -61,11 +61,17 @@ struct RadixDecode {
     int n;                  // digits (variables)
     int bits;               // output field width
 };
+// an operand term's key and coefficient side by side (one 16-byte gather)
+struct __align__(16) GsKC {
+    uint64_t k;
+    double c;
+};
+__global__ void k_gs_pairs(const uint64_t *keys, const double *coefs, int64_t T, GsKC *out);
 template <bool PACKED>
 __global__ void k_gs_merge(const uint64_t *keys, const uint32_t *vals, int64_t R, int64_t ta, int64_t tb,
                            const uint64_t *ka, const uint64_t *kb_s, int raw_bits, const double *ca,
-                           const double *cb_s, double tol, RadixDecode dec, uint64_t *st_key, double *st_coef,
-                           int64_t *seg_count, int64_t *stage_off);
+                           const double *cb_s, const GsKC *pa, const GsKC *pb, double tol, RadixDecode dec,
+                           uint64_t *st_key, double *st_coef, int64_t *seg_count, int64_t *stage_off);
 __global__ void k_gs_rowptr(const int64_t *out_off, int64_t nblocks, int64_t *row_ptr);
 
 }  // namespace polyhip

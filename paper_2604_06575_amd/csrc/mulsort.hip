@@ -289,9 +289,9 @@ template <bool PACKED>
 __global__ void __launch_bounds__(MG_THREADS) k_gs_merge(const uint64_t *keys, const uint32_t *vals, int64_t R,
                                                         int64_t ta, int64_t tb, const uint64_t *ka,
                                                         const uint64_t *kb_s, int raw_bits, const double *ca,
-                                                        const double *cb_s, double tol, RadixDecode dec,
-                                                        uint64_t *st_key, double *st_coef, int64_t *seg_count,
-                                                        int64_t *stage_off)
+                                                        const double *cb_s, const GsKC *pa, const GsKC *pb,
+                                                        double tol, RadixDecode dec, uint64_t *st_key,
+                                                        double *st_coef, int64_t *seg_count, int64_t *stage_off)
 {
     __shared__ uint64_t s_key[MG_TILE + GS_HALO];
     __shared__ double s_prod[MG_TILE + GS_HALO];
@@ -407,9 +407,15 @@ __global__ void __launch_bounds__(MG_THREADS) k_gs_merge(const uint64_t *keys, c
             if (q == MI && threadIdx.x >= kWave) break;   // the halo is the first wave's
             if (PACKED) vr[q] = (uint32_t)(kr[q] & rmask);
             const uint2 ij = split_raw(vr[q]);
-            ci[q] = ca[ij.x];
-            cj[q] = cb_s[ij.y];
-            if (PACKED) kr[q] = ka[ij.x] + kb_s[ij.y];
+            if (PACKED) {   // key and coefficient of each factor in one gather
+                const GsKC x = pa[ij.x], y = pb[ij.y];
+                ci[q] = x.c;
+                cj[q] = y.c;
+                kr[q] = x.k + y.k;
+            } else {
+                ci[q] = ca[ij.x];
+                cj[q] = cb_s[ij.y];
+            }
         }
         if (blk + (int64_t)gridDim.x < nb) load_tile(blk + gridDim.x);
 #pragma unroll
@@ -586,12 +592,18 @@ template __global__ void k_gs_scatter<8, GS_GEN_TO_PACKED>(const uint64_t *, con
                                                     unsigned long long *, int64_t, GsGen);
 template __global__ void k_gs_merge<false>(const uint64_t *, const uint32_t *, int64_t, int64_t, int64_t,
                                            const uint64_t *, const uint64_t *, int, const double *,
-                                           const double *, double, RadixDecode, uint64_t *, double *,
-                                           int64_t *, int64_t *);
+                                           const double *, const GsKC *, const GsKC *, double, RadixDecode,
+                                           uint64_t *, double *, int64_t *, int64_t *);
 template __global__ void k_gs_merge<true>(const uint64_t *, const uint32_t *, int64_t, int64_t, int64_t,
                                           const uint64_t *, const uint64_t *, int, const double *,
-                                          const double *, double, RadixDecode, uint64_t *, double *,
-                                          int64_t *, int64_t *);
+                                          const double *, const GsKC *, const GsKC *, double, RadixDecode,
+                                          uint64_t *, double *, int64_t *, int64_t *);
+
+__global__ void k_gs_pairs(const uint64_t *keys, const double *coefs, int64_t T, GsKC *out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < T) out[t] = GsKC{keys[t], coefs[t]};
+}
 
 // row_ptr of the single output polynomial: [0, total]
 __global__ void k_gs_rowptr(const int64_t *out_off, int64_t nblocks, int64_t *row_ptr)
