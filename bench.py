@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--affine-n", type=int, default=64)
     ap.add_argument("--affine-points", type=int, default=4096)
     ap.add_argument("--graph", action="store_true", help="also time the times+simplify step as a captured HIP graph")
+    ap.add_argument("--tune", action="append", default=[], metavar="NAME=VALUE",
+                    help="set a library tunable before measuring (repeatable)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
@@ -405,6 +407,12 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
+    if args.tune:
+        import paper_2604_06575_amd as ph
+        ph.lib()
+        for kv in args.tune:
+            name, value = kv.split("=", 1)
+            ph.tune_set(name, int(value))
     m = bench_mul(args)
     value = m["raw"] / m["t"]
     # algorithmic bytes of the dominant kernel's average launch / its average duration

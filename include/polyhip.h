@@ -107,9 +107,12 @@ poly_status poly_read_status(const void *ws, void *stream);
  *        "mul_sort_min_raw"  raw terms from which a single pair is multiplied
  *                            by the global radix-sort path instead
  *        "seg_blocks_per_cu" persistent workgroups per CU (simplify, sort)
+ *        "simplify_wide_min" largest-entry size from which simplify and mtimes
+ *                            merge through the device-wide sort
  *        "eval_blocks_per_cu" point-tile workgroups per CU (sparse eval)
  * poly_tune_set returns POLY_ERR_ARG for an unknown name or a value outside
- * the tunable's range; values are process-wide and apply to later calls. */
+ * the tunable's range; values are process-wide and apply to later calls.
+ * Workspace sizes depend on them: query the workspace again after a change. */
 poly_status poly_tune_set(const char *name, int64_t value);
 poly_status poly_tune_get(const char *name, int64_t *value);
 
@@ -134,8 +137,12 @@ poly_status poly_timing_read(int32_t slot, double *total_ms, int64_t *launches);
 
 /* ---------------------------------------------------------------- simplify
  * out_p = simplify(in_p, zero_tol) for every p (Table "coresemantics").
- * Inputs may hold repeated monomials in any order.  All P entries are
- * processed by one persistent launch that takes entries largest first.
+ * Inputs may hold repeated monomials in any order.  Batches whose largest
+ * entry has fewer than "simplify_wide_min" terms are processed by one
+ * persistent launch that takes entries largest first; otherwise, when
+ * n*b + bit width of (npolys - 1) <= 64, by one device-wide radix sort of
+ * (entry, monomial) keys and a tiled merge of equal-key runs.  Both sum each
+ * run left to right in input order, so they give bit-identical results.
  * out->npolys must equal in->npolys, out->nvars in->nvars; out->capacity >=
  * total input terms always suffices.  zero_tol >= 0 (NaN sums are kept).
  * Exponent rows are packed into 64-bit keys with b = bit width of max_exp
@@ -207,7 +214,9 @@ poly_status poly_eval_backward(const poly_csr *f, const double *X, int64_t N,
  * (term of A_ik, term of B_kj) order (exponent rows added, coefficients
  * multiplied and rounded once).  out->max_exp >= A->max_exp + B->max_exp
  * (at most 255); out->capacity >= the raw term count returned by the query
- * (device-checked, POLY_ERR_CAPACITY).  Matrix powers are repeated products. */
+ * (device-checked, POLY_ERR_CAPACITY).  Matrix powers are repeated products.
+ * When an output entry has at least "simplify_wide_min" raw terms, the raw
+ * products go straight to the device-wide simplify as packed keys. */
 poly_status poly_mtimes_workspace(const poly_csr *A, const poly_csr *B, int64_t I, int64_t K, int64_t J,
                                   size_t *ws_bytes, int64_t *raw_terms);
 poly_status poly_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t K, int64_t J,

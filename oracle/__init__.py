@@ -6,8 +6,10 @@ library and its Python binding) never imports, links or calls it, and the two
 share no code: this package wraps ``poly_oracle.c`` (the plain definitions of
 simplify, times, eval, diff and the reverse mode of eval) through ctypes, and
 adds a brute-force simplify built on a Python dict as a second, independent
-data structure for self-checks, and the affine-normal direction of Section 5
-written out in NumPy from the symbolic derivatives (the reference route).
+data structure for self-checks, the affine-normal direction of Section 5
+written out in NumPy from the symbolic derivatives (the reference route), and
+the polynomial-matrix operations of Section 3.3 (mtimes, sum and prod along a
+dimension) composed from simplify and times.
 
 Each function states the passage of the paper it follows; conventions where
 the paper is silent are documented in ``poly_oracle.c``.
@@ -430,4 +432,57 @@ def mtimes(a_rp, a_e, a_c, b_rp, b_e, b_c, I: int, K: int, J: int, tol: float = 
             e = np.vstack(es) if es else np.zeros((0, n), np.uint8)
             c = np.concatenate(cs) if cs else np.zeros(0)
             outs.append(simplify(e, c, tol, n) if e.shape[0] else (e, c))
+    return _csr(outs, n)
+
+
+def _entries(rp, e, c, n):
+    rp = np.asarray(rp, np.int64)
+    e, c = _u8(e, n), _f64(c)
+    return [(e[rp[p]:rp[p + 1]], c[rp[p]:rp[p + 1]]) for p in range(rp.shape[0] - 1)]
+
+
+def _along(R: int, C: int, dim: int):
+    """Index lists of the entries reduced into each output entry of an R x C
+    matrix (row-major): dim 1 gives a 1 x C result (down each column), dim 2
+    an R x 1 result (along each row)."""
+    if dim == 1:
+        return [[i * C + j for i in range(R)] for j in range(C)]
+    if dim == 2:
+        return [[i * C + j for j in range(C)] for i in range(R)]
+    raise ValueError("dim must be 1 or 2")
+
+
+def msum(rp, e, c, R: int, C: int, dim: int, tol: float = 0.0, n: int | None = None):
+    """sum(A, dim) of an R x C polynomial matrix (Section 3.3): each output
+    entry is simplify of the terms of the reduced entries concatenated in
+    index order (entries as stored); an empty dimension gives structural
+    zeros."""
+    n = n if n is not None else np.asarray(e).shape[1]
+    ents = _entries(rp, e, c, n)
+    outs = []
+    for idx in _along(R, C, dim):
+        es = [ents[q][0] for q in idx]
+        cs = [ents[q][1] for q in idx]
+        ee = np.vstack(es) if es else np.zeros((0, n), np.uint8)
+        cc = np.concatenate(cs) if cs else np.zeros(0)
+        outs.append(simplify(ee, cc, tol, n) if ee.shape[0] else (ee, cc))
+    return _csr(outs, n)
+
+
+def mprod(rp, e, c, R: int, C: int, dim: int, tol: float = 0.0, n: int | None = None):
+    """prod(A, dim) of an R x C polynomial matrix (Section 3.3): each output
+    entry is the left fold of times (expand, then simplify) over the
+    simplified reduced entries in index order, ((A_1 A_2) A_3) ...; one
+    entry gives its simplified self, an empty dimension the constant 1."""
+    n = n if n is not None else np.asarray(e).shape[1]
+    ents = _entries(rp, e, c, n)
+    outs = []
+    for idx in _along(R, C, dim):
+        if not idx:
+            outs.append((np.zeros((1, n), np.uint8), np.ones(1)))
+            continue
+        acc = simplify(*ents[idx[0]], tol, n)
+        for q in idx[1:]:
+            acc = mul(acc[0], acc[1], *simplify(*ents[q], tol, n), tol=tol, n=n)
+        outs.append(acc)
     return _csr(outs, n)

@@ -16,7 +16,8 @@ import torch
 
 __all__ = [
     "Batch", "PolyError", "PolyEval", "batch_from_numpy", "batch_to_numpy", "mul", "simplify", "jacobian",
-    "eval", "grad", "hess", "eval_backward", "eval_dense", "library_path", "lib",
+    "eval", "grad", "hess", "eval_backward", "eval_dense", "mtimes", "mpower", "msum", "mprod", "affine_normal",
+    "library_path", "lib",
     "POLY_FP64", "POLY_SPLIT_BF16",
 ]
 
@@ -347,6 +348,54 @@ def mpower(a: Batch, I: int, p: int, tol: float = 0.0) -> Batch:
     for _ in range(p - 1):
         r = mtimes(a, r, I, I, I, tol)
     return r
+
+
+def _selector(n: int, rows: int, cols: int, hot, device) -> Batch:
+    """rows x cols matrix (row-major) of constant polynomials: 1 where
+    hot(i, j), the structural zero elsewhere."""
+    flags = np.array([bool(hot(i, j)) for i in range(rows) for j in range(cols)], dtype=bool)
+    rp = np.zeros(rows * cols + 1, np.int64)
+    np.cumsum(flags, out=rp[1:])
+    k = int(rp[-1])
+    return batch_from_numpy(rp, np.zeros((k, n), np.uint8), np.ones(k), n=n, max_exp=0, device=device)
+
+
+def msum(a: Batch, R: int, C: int, dim: int, tol: float = 0.0) -> Batch:
+    """sum(A, dim) of an R x C polynomial matrix (entries row-major): dim 1
+    gives 1 x C, dim 2 gives R x 1.  Each entry is simplify of the reduced
+    entries' terms concatenated in index order: the product with a vector of
+    constant ones (one mtimes call; products by 1 are exact)."""
+    dev = a.coefs.device
+    if dim == 1:
+        return mtimes(_selector(a.n, 1, R, lambda i, j: True, dev), a, 1, R, C, tol)
+    if dim == 2:
+        return mtimes(a, _selector(a.n, C, 1, lambda i, j: True, dev), R, C, 1, tol)
+    raise ValueError("dim must be 1 or 2")
+
+
+def mprod(a: Batch, R: int, C: int, dim: int, tol: float = 0.0) -> Batch:
+    """prod(A, dim) of an R x C polynomial matrix: the left fold of times over
+    the simplified entries along dim, ((A_1 .* A_2) .* A_3) ...  Each line
+    along dim is picked out (and simplified) by a product with a 0/1
+    selector, and each fold step is one batched times call.  An empty
+    dimension gives the constant 1."""
+    if dim not in (1, 2):
+        raise ValueError("dim must be 1 or 2")
+    dev = a.coefs.device
+    length, count = (C, R) if dim == 2 else (R, C)
+    if length == 0 or count == 0:
+        return batch_from_numpy(np.arange(count + 1, dtype=np.int64), np.zeros((count, a.n), np.uint8),
+                                np.ones(count), n=a.n, max_exp=0, device=dev)
+
+    def line(k):
+        if dim == 2:
+            return mtimes(a, _selector(a.n, C, 1, lambda i, j: i == k, dev), R, C, 1, tol)
+        return mtimes(_selector(a.n, 1, R, lambda i, j: j == k, dev), a, 1, R, C, tol)
+
+    acc = line(0)
+    for k in range(1, length):
+        acc = mul(acc, line(k), tol)
+    return acc
 
 
 def jacobian(b: Batch, trim: bool = True) -> Batch:

@@ -90,6 +90,24 @@ def main():
     threshold = threshold if threshold is not None else 1 << 62
     ph.tune_set("mul_sort_min_raw", threshold)
     log["mul_sort_min_raw"] = {"best": threshold, "sweep": rows}
+    # batched simplify: the largest-entry size from which the device-wide sort
+    # beats one workgroup per entry (16 entries of that size)
+    rows, threshold = [], None
+    for size in (1024, 2048, 4096, 8192, 16384, 32768):
+        polys = [W.random_poly(W.rng_for(W.SEED_BASE + 90 + k), 6, 4, size) for k in range(16)]
+        rp, E, C = W.csr_from_list(polys, 6)
+        sb = ph.batch_from_numpy(rp, E, C, n=6, max_exp=4)
+        ph.tune_set("simplify_wide_min", 1)
+        t_wide = _time(lambda: ph.simplify(sb))
+        ph.tune_set("simplify_wide_min", 1 << 62)
+        t_seg = _time(lambda: ph.simplify(sb))
+        rows.append({"entry_terms": size, "wide_ms": t_wide, "per_entry_ms": t_seg})
+        print(f"simplify 16 x {size}: device-wide {t_wide:.3f} ms, per entry {t_seg:.3f} ms", flush=True)
+        if threshold is None and t_wide < t_seg:
+            threshold = size
+    threshold = threshold if threshold is not None else 1 << 62
+    ph.tune_set("simplify_wide_min", threshold)
+    log["simplify_wide_min"] = {"best": threshold, "sweep": rows}
     # batched simplify: persistent workgroups per CU
     bm = W.batch_matrix(npts=0)
     bb = ph.batch_from_numpy(bm.row_ptr, bm.exps, bm.coefs, n=bm.n, max_exp=bm.max_exp)

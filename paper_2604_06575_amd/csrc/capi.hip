@@ -19,6 +19,7 @@ std::atomic<int64_t> g_mul_bucket_terms{MB_TARGET};
 std::atomic<int64_t> g_seg_blocks_per_cu{2};
 std::atomic<int64_t> g_eval_blocks_per_cu{16};
 std::atomic<int64_t> g_mul_sort_min_raw{int64_t(1) << 20};
+std::atomic<int64_t> g_simplify_wide_min{SEG_CAP + 1};
 
 struct TuneEntry {
     const char *name;
@@ -30,13 +31,14 @@ const TuneEntry kTune[] = {
     {"seg_blocks_per_cu", &g_seg_blocks_per_cu, 1, 16},
     {"eval_blocks_per_cu", &g_eval_blocks_per_cu, 1, 64},
     {"mul_sort_min_raw", &g_mul_sort_min_raw, 0, int64_t(1) << 62},
+    {"simplify_wide_min", &g_simplify_wide_min, 1, int64_t(1) << 62},
 };
 }  // namespace
 
 Tunables tunables()
 {
     return Tunables{g_mul_bucket_terms.load(), g_seg_blocks_per_cu.load(), g_eval_blocks_per_cu.load(),
-                    g_mul_sort_min_raw.load()};
+                    g_mul_sort_min_raw.load(), g_simplify_wide_min.load()};
 }
 
 }  // namespace polyhip
@@ -132,18 +134,74 @@ inline void set_u64(unsigned long long *p, unsigned long long v, hipStream_t s)
 
 // ------------------------------------------------------------ simplify plan
 
+// Device-wide simplify (batches holding a polynomial larger than the
+// simplify_wide_min tunable): keys (polynomial, monomial) of key_bits bits
+// radix-sorted with their value indices, runs merged by tiles.
+struct WidePlan {
+    bool on = false;
+    int key_bits = 0;
+    int64_t nbs = 0, nbm = 0;   // radix-pass tiles, merge tiles
+    size_t keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, hist = 0, hoff = 0, tmp = 0;
+    size_t st_key = 0, st_coef = 0, cnt = 0, soff = 0, ooff = 0;
+};
+
+inline int64_t max_segment(const int64_t *rph, int64_t P)
+{
+    int64_t m = 0;
+    for (int64_t p = 0; p < P; ++p) m = std::max(m, rph[p + 1] - rph[p]);
+    return m;
+}
+
+// Whether the device-wide path takes a batch of P polynomials, R terms in
+// all, the largest of max_seg terms, with kb-bit monomial keys.
+inline bool wide_wanted(int64_t P, int64_t R, int64_t max_seg, int kb)
+{
+    const int segbits = P > 1 ? 64 - __builtin_clzll((unsigned long long)(P - 1)) : 0;
+    return R > 0 && R < (int64_t(1) << 32) && kb + segbits <= 64 && max_seg >= tunables().simplify_wide_min;
+}
+
+void plan_wide(WidePlan &w, Layout &L, int64_t P, int64_t R, int kb)
+{
+    w.on = true;
+    w.key_bits = kb + (P > 1 ? 64 - __builtin_clzll((unsigned long long)(P - 1)) : 0);
+    w.nbs = ceil_div(R, GS_TILE);
+    w.nbm = ceil_div(R, MG_TILE);
+    w.keys0 = L.take(8 * R);
+    w.keys1 = L.take(8 * R);
+    w.vals0 = L.take(4 * R);
+    w.vals1 = L.take(4 * R);
+    w.hist = L.take(8 * GS_BINS * w.nbs);
+    w.hoff = L.take(8 * (GS_BINS * w.nbs + 1));
+    w.tmp = L.take(8 * (ceil_div(std::max<int64_t>(GS_BINS * w.nbs, w.nbm), LB_TILE) + 2));
+    w.st_key = L.take(8 * R);
+    w.st_coef = L.take(8 * R);
+    w.cnt = L.take(8 * w.nbm);
+    w.soff = L.take(8 * w.nbm);
+    w.ooff = L.take(8 * (w.nbm + 1));
+}
+
 struct SimplifyPlan {
     size_t keys, st_key, st_coef, seg_count, order, queue;
+    WidePlan wide;
     size_t total;
 };
 
 poly_status run_simplify(const poly_csr *in, poly_csr *out, double zero_tol, void *ws, const struct SimplifyPlan &pl,
                          hipStream_t s);
+poly_status run_wide(const WidePlan &w, void *ws, int64_t P, int64_t R, int n, int bits, const double *coefs,
+                     double zero_tol, poly_csr *out, hipStream_t s);
 
-SimplifyPlan plan_simplify(int64_t P, int64_t T)
+// T terms in P polynomials (row offsets rph on the host), kb-bit monomial keys
+SimplifyPlan plan_simplify(int64_t P, int64_t T, const int64_t *rph, int kb)
 {
     Layout L;
     SimplifyPlan s;
+    if (wide_wanted(P, T, max_segment(rph, P), kb)) {
+        s.keys = s.st_key = s.st_coef = s.seg_count = s.order = s.queue = 0;
+        plan_wide(s.wide, L, P, T, kb);
+        s.total = L.total();
+        return s;
+    }
     s.keys = L.take(8 * T);
     s.st_key = L.take(8 * T);
     s.st_coef = L.take(8 * T);
@@ -624,7 +682,8 @@ poly_status poly_simplify_workspace(const poly_csr *in, size_t *ws_bytes)
     poly_status st = check_csr(in, true);
     if (st != POLY_OK) return st;
     if (!ws_bytes) return POLY_ERR_ARG;
-    *ws_bytes = plan_simplify(in->npolys, total_terms(in)).total;
+    const int kb = in->nvars * bit_width_u32((uint32_t)in->max_exp);
+    *ws_bytes = plan_simplify(in->npolys, total_terms(in), in->row_ptr_host, kb).total;
     return POLY_OK;
 }
 
@@ -640,7 +699,7 @@ poly_status poly_simplify(const poly_csr *in, poly_csr *out, double zero_tol, vo
     const int bits = bit_width_u32((uint32_t)in->max_exp);
     if ((int64_t)n * bits > 64) return POLY_ERR_KEY_OVERFLOW;
     const int64_t P = in->npolys, T = total_terms(in);
-    const SimplifyPlan pl = plan_simplify(P, T);
+    const SimplifyPlan pl = plan_simplify(P, T, in->row_ptr_host, n * bits);
     if (!ws || ws_bytes < pl.total) return POLY_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     clear_u64(at<unsigned long long>(ws, 0), 1, s);
@@ -661,6 +720,12 @@ poly_status run_simplify(const poly_csr *in, poly_csr *out, double zero_tol, voi
     const int bits = bit_width_u32((uint32_t)in->max_exp);
     const int64_t P = in->npolys, T = total_terms(in);
     int32_t *status = at<int32_t>(ws, 0);
+    if (pl.wide.on) {
+        hipLaunchKernelGGL(k_ws_keys, dim3(grid1(T, 256)), dim3(256), 0, s, in->exps, T, n, bits, in->max_exp,
+                           in->row_ptr, P, at<uint64_t>(ws, pl.wide.keys0), at<uint32_t>(ws, pl.wide.vals0),
+                           status);
+        return run_wide(pl.wide, ws, P, T, n, bits, in->coefs, zero_tol, out, s);
+    }
     uint64_t *keys = at<uint64_t>(ws, pl.keys);
     unsigned long long *queue = at<unsigned long long>(ws, pl.queue);
     clear_u64(queue, 1, s);
@@ -686,6 +751,61 @@ poly_status run_simplify(const poly_csr *in, poly_csr *out, double zero_tol, voi
     hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, A.seg_count, P, out->row_ptr);
     hipLaunchKernelGGL(k_compact, dim3((unsigned)P), dim3(256), 0, s, in->row_ptr, A.seg_count, out->row_ptr,
                        A.st_key, A.st_coef, n, bits, out->exps, out->coefs, out->capacity, status);
+    LAUNCH_CHECK();
+    return POLY_OK;
+}
+
+// The sorted half of the device-wide simplify: keys0 / vals0 hold the R
+// composite keys and value indices (coefficient of element g: coefs[vals[g]]).
+poly_status run_wide(const WidePlan &w, void *ws, int64_t P, int64_t R, int n, int bits, const double *coefs,
+                     double zero_tol, poly_csr *out, hipStream_t s)
+{
+    int32_t *status = at<int32_t>(ws, 0);
+    uint64_t *kcur = at<uint64_t>(ws, w.keys0), *knext = at<uint64_t>(ws, w.keys1);
+    uint32_t *vcur = at<uint32_t>(ws, w.vals0), *vnext = at<uint32_t>(ws, w.vals1);
+    int64_t *hist = at<int64_t>(ws, w.hist), *hoff = at<int64_t>(ws, w.hoff), *tmp = at<int64_t>(ws, w.tmp);
+    const int64_t nb = w.nbs;
+    // scan state: cleared once, then by each pass's scatter for the next scan
+    const int64_t scan_state = ceil_div(std::max<int64_t>(GS_BINS * nb, w.nbm), LB_TILE) + 2;
+    clear_u64((unsigned long long *)tmp, scan_state, s);
+    const int passes = (w.key_bits + GS_BITS - 1) / GS_BITS;
+    const int db = std::max(passes ? (w.key_bits + passes - 1) / passes : GS_MIN_BITS, GS_MIN_BITS);
+    const int64_t hgrid = std::min<int64_t>(ceil_div(nb, GS_HIST_THREADS / kWave), (int64_t)device_cus() * 8);
+    const GsGen gen{};   // the stream is read, not generated
+    auto pass = [&](auto dbc, int p) {
+        constexpr int DB = decltype(dbc)::value;
+        const int shift = p * DB;
+        hipLaunchKernelGGL((k_gs_hist<DB, false>), dim3((unsigned)hgrid), dim3(GS_HIST_THREADS), 0, s,
+                           (const uint64_t *)kcur, R, shift, nb, hist, gen);
+        launch_scan(hist, ((int64_t)1 << DB) * nb, hoff, tmp, status, s, true);
+        hipLaunchKernelGGL((k_gs_scatter<DB, GS_KV>), dim3((unsigned)nb), dim3(GS_SC_THREADS), 0, s,
+                           (const uint64_t *)kcur, (const uint32_t *)vcur, R, shift, nb, (const int64_t *)hoff,
+                           knext, vnext, 0, (unsigned long long *)tmp, scan_state, gen);
+    };
+    for (int p = 0; p < passes; ++p) {
+        switch (db) {
+        case 4: pass(std::integral_constant<int, 4>(), p); break;
+        case 5: pass(std::integral_constant<int, 5>(), p); break;
+        case 6: pass(std::integral_constant<int, 6>(), p); break;
+        case 7: pass(std::integral_constant<int, 7>(), p); break;
+        default: pass(std::integral_constant<int, 8>(), p); break;
+        }
+        std::swap(kcur, knext);
+        std::swap(vcur, vnext);
+    }
+    int64_t *cnt = at<int64_t>(ws, w.cnt), *soff = at<int64_t>(ws, w.soff), *ooff = at<int64_t>(ws, w.ooff);
+    uint64_t *st_key = at<uint64_t>(ws, w.st_key);
+    double *st_coef = at<double>(ws, w.st_coef);
+    const int64_t mgrid = std::min<int64_t>(w.nbm, (int64_t)device_cus() * MG_BLOCKS_PER_CU);
+    hipLaunchKernelGGL(k_ws_merge, dim3((unsigned)mgrid), dim3(MG_THREADS), 0, s, (const uint64_t *)kcur,
+                       (const uint32_t *)vcur, R, coefs, zero_tol, st_key, st_coef, cnt, soff);
+    launch_scan(cnt, w.nbm, ooff, tmp, status, s, true);
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)w.nbm), dim3(256), 0, s, (const int64_t *)soff,
+                       (const int64_t *)cnt, (const int64_t *)ooff, (const uint64_t *)st_key,
+                       (const double *)st_coef, n, bits, out->exps, out->coefs, out->capacity, status);
+    hipLaunchKernelGGL(k_ws_rowptr, dim3(grid1(P + 1, 256)), dim3(256), 0, s, P, n * bits, (const uint64_t *)kcur,
+                       R, (const int64_t *)soff, (const int64_t *)cnt, (const int64_t *)ooff, w.nbm,
+                       (const uint64_t *)st_key, out->row_ptr);
     LAUNCH_CHECK();
     return POLY_OK;
 }
@@ -1207,10 +1327,15 @@ namespace {
 // Products of polynomial matrices: the raw batch (sizes and offsets from
 // the row pointers, then one workgroup per output entry), then the batched
 // simplify.  The simplify workspace comes first; the raw batch after it.
+// When an output entry has at least simplify_wide_min raw terms, the raw
+// products are written as device-wide simplify keys instead (one thread per
+// raw term, operand monomials packed once).
 struct MtimesPlan {
     SimplifyPlan sp;
-    size_t rrp, re, rc, sizes, tmp, total;
+    WidePlan wide;
+    size_t rrp, re, rc, sizes, tmp, ka, kb, total;
     int64_t raw;
+    int bits;
 };
 
 poly_status check_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t K, int64_t J)
@@ -1240,11 +1365,21 @@ poly_status plan_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t
         }
     m.raw = rph[Q];
     if (m.raw >= (int64_t(1) << 32)) return POLY_ERR_UNSUPPORTED;
-    m.sp = plan_simplify(Q, m.raw);
+    m.bits = bit_width_u32((uint32_t)(A->max_exp + B->max_exp));
+    const int kb = A->nvars * m.bits;
     Layout L;
-    L.off = m.sp.total;
+    if (wide_wanted(Q, m.raw, max_segment(rph.data(), Q), kb)) {
+        plan_wide(m.wide, L, Q, m.raw, kb);
+        m.ka = L.take(8 * total_terms(A));
+        m.kb = L.take(8 * total_terms(B));
+        m.re = 0;
+    } else {
+        m.sp = plan_simplify(Q, m.raw, rph.data(), kb);
+        L.off = m.sp.total;
+        m.re = L.take((size_t)m.raw * A->nvars);
+        m.ka = m.kb = 0;
+    }
     m.rrp = L.take(8 * (Q + 1));
-    m.re = L.take((size_t)m.raw * A->nvars);
     m.rc = L.take(8 * m.raw);
     m.sizes = L.take(8 * Q);
     m.tmp = L.take(8 * scan_tmp_count(Q));
@@ -1296,6 +1431,20 @@ poly_status poly_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t
     double *rc = at<double>(ws, m.rc);
     hipLaunchKernelGGL(k_mat_raw_sizes, dim3(grid1(Q, 256)), dim3(256), 0, s, A->row_ptr, B->row_ptr, I, K, J, sizes);
     launch_scan(sizes, Q, rrp, at<int64_t>(ws, m.tmp), status, s);
+    if (m.wide.on) {
+        const int64_t TA = total_terms(A), TB = total_terms(B);
+        uint64_t *ka = at<uint64_t>(ws, m.ka), *kb = at<uint64_t>(ws, m.kb);
+        if (TA > 0)
+            hipLaunchKernelGGL(k_pack, dim3(grid1(TA, 256)), dim3(256), 0, s, A->exps, TA, n, m.bits, A->max_exp, ka,
+                               status);
+        if (TB > 0)
+            hipLaunchKernelGGL(k_pack, dim3(grid1(TB, 256)), dim3(256), 0, s, B->exps, TB, n, m.bits, B->max_exp, kb,
+                               status);
+        hipLaunchKernelGGL(k_mat_keys, dim3(grid1(m.raw, 256)), dim3(256), 0, s, A->row_ptr, (const uint64_t *)ka,
+                           A->coefs, B->row_ptr, (const uint64_t *)kb, B->coefs, I, K, J, (const int64_t *)rrp,
+                           m.raw, n * m.bits, at<uint64_t>(ws, m.wide.keys0), at<uint32_t>(ws, m.wide.vals0), rc);
+        return run_wide(m.wide, ws, Q, m.raw, n, m.bits, rc, zero_tol, out, s);
+    }
     hipLaunchKernelGGL(k_mat_expand, dim3((unsigned)Q), dim3(MAT_THREADS), 0, s, A->row_ptr, A->exps, A->coefs,
                        B->row_ptr, B->exps, B->coefs, I, K, J, n, (const int64_t *)rrp, re, rc);
     poly_csr R;

@@ -12,6 +12,7 @@ struct Tunables {
     int64_t seg_blocks_per_cu;
     int64_t eval_blocks_per_cu;
     int64_t mul_sort_min_raw;
+    int64_t simplify_wide_min;
 };
 Tunables tunables();
 
@@ -182,6 +183,18 @@ __global__ void k_mat_raw_sizes(const int64_t *a_rp, const int64_t *b_rp, int64_
 __global__ void k_mat_expand(const int64_t *a_rp, const uint8_t *a_e, const double *a_c, const int64_t *b_rp,
                              const uint8_t *b_e, const double *b_c, int64_t I, int64_t K, int64_t J, int n,
                              const int64_t *r_rp, uint8_t *r_e, double *r_c);
+__global__ void k_mat_keys(const int64_t *a_rp, const uint64_t *ka, const double *a_c, const int64_t *b_rp,
+                           const uint64_t *kb, const double *b_c, int64_t I, int64_t K, int64_t J,
+                           const int64_t *r_rp, int64_t R, int kbits, uint64_t *keys, uint32_t *vals, double *r_c);
+
+// device-wide simplify of batches with large polynomials (wide.hip)
+__global__ void k_ws_keys(const uint8_t *exps, int64_t T, int n, int bits, int max_exp, const int64_t *row_ptr,
+                          int64_t P, uint64_t *keys, uint32_t *vals, int32_t *status);
+__global__ void k_ws_merge(const uint64_t *keys, const uint32_t *vals, int64_t R, const double *coefs, double tol,
+                           uint64_t *st_key, double *st_coef, int64_t *seg_count, int64_t *stage_off);
+__global__ void k_ws_rowptr(int64_t P, int kb, const uint64_t *keys, int64_t R, const int64_t *stage_off,
+                            const int64_t *seg_count, const int64_t *out_off, int64_t nb, const uint64_t *st_key,
+                            int64_t *row_ptr);
 
 // affine-normal direction (affine.hip): one workgroup per point
 constexpr int AN_THREADS = 256;

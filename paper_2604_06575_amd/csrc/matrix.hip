@@ -53,3 +53,46 @@ __global__ void __launch_bounds__(MAT_THREADS) k_mat_expand(const int64_t *a_rp,
 }
 
 }  // namespace polyhip
+
+namespace polyhip {
+
+// The same raw products for the device-wide simplify, one thread per raw
+// term r: the output entry q holding r (a binary search of r_rp), then k and
+// the factor pair; the term's key is (q << kbits) | (ka + kb) -- bit-field
+// monomial keys add without carries because each field is wide enough for
+// the sum of the two exponents -- its value index r, its coefficient the
+// product.
+__global__ void k_mat_keys(const int64_t *__restrict__ a_rp, const uint64_t *__restrict__ ka,
+                           const double *__restrict__ a_c, const int64_t *__restrict__ b_rp,
+                           const uint64_t *__restrict__ kb, const double *__restrict__ b_c, int64_t I, int64_t K,
+                           int64_t J, const int64_t *__restrict__ r_rp, int64_t R, int kbits,
+                           uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, double *__restrict__ r_c)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const int64_t Q = I * J;
+    int64_t lo = 0, hi = Q;   // the last q < Q with r_rp[q] <= r
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (r_rp[mid] <= r) lo = mid;
+        else hi = mid;
+    }
+    const int64_t q = lo, i = q / J, j = q % J;
+    int64_t x = r - r_rp[q];
+    int64_t a0 = 0, b0 = 0, tb = 1;
+    for (int64_t k = 0; k < K; ++k) {
+        a0 = a_rp[i * K + k];
+        b0 = b_rp[k * J + j];
+        const int64_t ta = a_rp[i * K + k + 1] - a0;
+        tb = b_rp[k * J + j + 1] - b0;
+        if (x < ta * tb) break;
+        x -= ta * tb;
+    }
+    const int64_t a = x / tb, b = x - (x / tb) * tb;
+    const uint64_t key = ka[a0 + a] + kb[b0 + b];
+    keys[r] = kbits < 64 ? ((uint64_t)q << kbits) | key : key;
+    vals[r] = (uint32_t)r;
+    r_c[r] = a_c[a0 + a] * b_c[b0 + b];
+}
+
+}  // namespace polyhip

@@ -85,6 +85,12 @@ def test_tunables_roundtrip():
     ph.tune_set("mul_bucket_terms", 8192)
     assert ph.tune_get("mul_bucket_terms") == 8192
     ph.tune_set("mul_bucket_terms", old)
+    old = ph.tune_get("simplify_wide_min")
+    ph.tune_set("simplify_wide_min", 1)
+    assert ph.tune_get("simplify_wide_min") == 1
+    ph.tune_set("simplify_wide_min", old)
+    with pytest.raises(ph.PolyError):
+        ph.tune_set("simplify_wide_min", 0)
     with pytest.raises(ph.PolyError):
         ph.tune_set("no_such_knob", 1)
     with pytest.raises(ph.PolyError):

@@ -99,3 +99,44 @@ def test_empty(ph):
     b, _ = _batch(ph, [(np.array([[1, 0]], np.uint8), np.array([2.0]))] * 3, n, 1)
     got = ph.mtimes(a, b, 0, 1, 3)
     assert got.npolys == 0
+
+
+def test_paper_sum_and_prod(ph):
+    """Section 3.3: sum(A, 1) = [x1, 1 + x2], prod(A, 2) = [x1; 0]."""
+    g = json.load(open(os.path.join(HERE, "golden", "worked_examples.json")))["W6_matrix_ops"]
+    n = g["n"]
+    A = [(np.array([t[1] for t in e], np.uint8).reshape(-1, n), np.array([t[0] for t in e], float)) for e in g["A"]]
+    a, ra = _batch(ph, A, n, 1)
+    say("msum / mprod: Section 3.3 example")
+    _same(ph, ph.msum(a, 2, 2, 1), oracle.msum(*ra, 2, 2, 1, n=n))
+    _same(ph, ph.mprod(a, 2, 2, 2), oracle.mprod(*ra, 2, 2, 2, n=n))
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_sum_and_prod_random(ph, dim):
+    """3 x 4 matrices of unsimplified entries with Gaussian coefficients (the
+    summation order matters), some zero entries, with and without tol."""
+    rng = W.rng_for(3700 + dim)
+    n, d, R, C = 3, 2, 3, 4
+    A = [W.random_poly(rng, n, d, int(rng.integers(0, 25)), integer=False) for _ in range(R * C)]
+    a, ra = _batch(ph, A, n, d)
+    for tol in (0.0, 0.5):
+        say(f"msum / mprod: 3x4 along dim {dim}, tol {tol}")
+        _same(ph, ph.msum(a, R, C, dim, tol=tol), oracle.msum(*ra, R, C, dim, tol=tol, n=n))
+        _same(ph, ph.mprod(a, R, C, dim, tol=tol), oracle.mprod(*ra, R, C, dim, tol=tol, n=n))
+
+
+def test_sum_and_prod_degenerate(ph):
+    """An empty dimension (structural zeros / constant 1) and a dimension of
+    length one (the simplified entries)."""
+    n = 2
+    a, ra = _batch(ph, [], n, 1)
+    say("msum / mprod: empty dimension")
+    _same(ph, ph.msum(a, 3, 0, 2), oracle.msum(*ra, 3, 0, 2, n=n))
+    _same(ph, ph.mprod(a, 3, 0, 2), oracle.mprod(*ra, 3, 0, 2, n=n))
+    rng = W.rng_for(3710)
+    A = [W.random_poly(rng, n, 3, 8, integer=False) for _ in range(3)]
+    a, ra = _batch(ph, A, n, 3)
+    say("msum / mprod: one column")
+    _same(ph, ph.msum(a, 3, 1, 2), oracle.msum(*ra, 3, 1, 2, n=n))
+    _same(ph, ph.mprod(a, 3, 1, 2), oracle.mprod(*ra, 3, 1, 2, n=n))

@@ -555,3 +555,59 @@ def test_mtimes_associative_on_integers():
     bc = oracle.mtimes(*b, *c, 3, 2, 2, n=n)
     right = oracle.mtimes(*a, *bc, 2, 3, 2, n=n)
     assert all(np.array_equal(x, y) for x, y in zip(left, right))
+
+
+def test_msum_mprod_paper_example(golden):
+    """Section 3.3: sum(A, 1) = [x1, 1 + x2] and prod(A, 2) = [x1; 0] for
+    A = [x1, 1; 0, x2]."""
+    g = golden["W6_matrix_ops"]
+    n = g["n"]
+    rp, E, C = _mat([poly_from_json(t, n) for t in g["A"]], n)
+    srp, se, sc = oracle.msum(rp, E, C, 2, 2, 1, n=n)
+    for q in range(2):
+        assert as_termset(se[srp[q]:srp[q + 1]], sc[srp[q]:srp[q + 1]]) == \
+            as_termset(*poly_from_json(g["sum_dim1"][q], n))
+    prp, pe, pc = oracle.mprod(rp, E, C, 2, 2, 2, n=n)
+    assert as_termset(pe[prp[0]:prp[1]], pc[prp[0]:prp[1]]) == as_termset(*poly_from_json(g["prod_dim2"][0], n))
+    assert prp[2] == prp[1]                          # 0 * x2 is the structural zero
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_msum_mprod_eval_identities(dim):
+    """At integer points with small integer coefficients every value is exact:
+    eval(sum(A, dim)) is the sum and eval(prod(A, dim)) the product of the
+    entries' values along dim, taken independently of the oracle's simplify
+    (values of the unsimplified entries)."""
+    rng = W.rng_for(3410 + dim)
+    n, R, Cc = 3, 3, 4
+    A = [W.random_poly(rng, n, 2, int(rng.integers(0, 6))) for _ in range(R * Cc)]
+    rp, E, C = _mat(A, n)
+    X = rng.integers(-2, 3, size=(5, n)).astype(np.float64)
+    vals = np.array([[sum(c * np.prod(x ** e.astype(np.float64)) for e, c in zip(*A[q])) for x in X]
+                     for q in range(R * Cc)]).reshape(R, Cc, -1)
+    srp, se, sc = oracle.msum(rp, E, C, R, Cc, dim, n=n)
+    prp, pe, pc = oracle.mprod(rp, E, C, R, Cc, dim, n=n)
+    want_s = vals.sum(axis=dim - 1)
+    want_p = vals.prod(axis=dim - 1)
+    got_s = oracle.eval_batch(srp, se, sc, X)
+    got_p = oracle.eval_batch(prp, pe, pc, X)
+    assert np.array_equal(got_s.reshape(want_s.shape), want_s)
+    assert np.array_equal(got_p.reshape(want_p.shape), want_p)
+
+
+def test_msum_mprod_degenerate():
+    """Empty dimension: sum gives structural zeros, prod the constant 1; a
+    dimension of length one gives the simplified entries themselves."""
+    n = 2
+    rp, E, C = _mat([], n)
+    srp, _, _ = oracle.msum(rp, E, C, 3, 0, 2, n=n)
+    assert srp.tolist() == [0, 0, 0, 0]
+    prp, pe, pc = oracle.mprod(rp, E, C, 3, 0, 2, n=n)
+    assert prp.tolist() == [0, 1, 2, 3] and not pe.any() and pc.tolist() == [1.0, 1.0, 1.0]
+    rng = W.rng_for(3420)
+    A = [W.random_poly(rng, n, 3, 8, integer=False) for _ in range(3)]
+    rp, E, C = _mat(A, n)
+    want = oracle.simplify_batch(rp, E, C, n=n)
+    for f in (oracle.msum, oracle.mprod):
+        got = f(rp, E, C, 3, 1, 2, n=n)
+        assert all(np.array_equal(x, y) for x, y in zip(got, want))
