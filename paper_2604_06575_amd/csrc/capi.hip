@@ -135,14 +135,17 @@ inline void set_u64(unsigned long long *p, unsigned long long v, hipStream_t s)
 // ------------------------------------------------------------ simplify plan
 
 // Device-wide simplify (batches holding a polynomial larger than the
-// simplify_wide_min tunable): keys (polynomial, monomial) of key_bits bits
-// radix-sorted with their value indices, runs merged by tiles.
+// simplify_wide_min tunable): keys p * radix^n + (mixed-radix monomial key)
+// of key_bits bits radix-sorted with their value indices, runs merged by
+// tiles.  span = radix^n, or 0 for a single polynomial (key = monomial key).
 struct WidePlan {
     bool on = false;
     int key_bits = 0;
+    uint32_t radix = 0;
+    uint64_t span = 0;
     int64_t nbs = 0, nbm = 0;   // radix-pass tiles, merge tiles
     size_t keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, hist = 0, hoff = 0, tmp = 0;
-    size_t st_key = 0, st_coef = 0, cnt = 0, soff = 0, ooff = 0;
+    size_t st_key = 0, st_ckey = 0, st_coef = 0, cnt = 0, soff = 0, ooff = 0;
 };
 
 inline int64_t max_segment(const int64_t *rph, int64_t P)
@@ -152,18 +155,30 @@ inline int64_t max_segment(const int64_t *rph, int64_t P)
     return m;
 }
 
-// Whether the device-wide path takes a batch of P polynomials, R terms in
-// all, the largest of max_seg terms, with kb-bit monomial keys.
-inline bool wide_wanted(int64_t P, int64_t R, int64_t max_seg, int kb)
+// P * radix^n: the range of the composite keys, or 0 past 2^64
+inline unsigned __int128 wide_range(int64_t P, int n, uint32_t radix)
 {
-    const int segbits = P > 1 ? 64 - __builtin_clzll((unsigned long long)(P - 1)) : 0;
-    return R > 0 && R < (int64_t(1) << 32) && kb + segbits <= 64 && max_seg >= tunables().simplify_wide_min;
+    unsigned __int128 r = (unsigned __int128)P;
+    for (int i = 0; i < n && r <= ((unsigned __int128)1 << 64); ++i) r *= radix;
+    return r <= ((unsigned __int128)1 << 64) ? r : 0;
 }
 
-void plan_wide(WidePlan &w, Layout &L, int64_t P, int64_t R, int kb)
+// Whether the device-wide path takes a batch of P polynomials, R terms in
+// all, the largest of max_seg terms, in n variables with exponents below radix.
+inline bool wide_wanted(int64_t P, int64_t R, int64_t max_seg, int n, uint32_t radix)
+{
+    return R > 0 && R < (int64_t(1) << 32) && wide_range(P, n, radix) != 0 &&
+           max_seg >= tunables().simplify_wide_min;
+}
+
+void plan_wide(WidePlan &w, Layout &L, int64_t P, int64_t R, int n, uint32_t radix)
 {
     w.on = true;
-    w.key_bits = kb + (P > 1 ? 64 - __builtin_clzll((unsigned long long)(P - 1)) : 0);
+    const unsigned __int128 range = wide_range(P, n, radix);
+    const uint64_t kmax = (uint64_t)(range - 1);
+    w.key_bits = kmax ? 64 - __builtin_clzll((unsigned long long)kmax) : 0;
+    w.radix = radix;
+    w.span = P > 1 ? (uint64_t)(range / (unsigned __int128)P) : 0;
     w.nbs = ceil_div(R, GS_TILE);
     w.nbm = ceil_div(R, MG_TILE);
     w.keys0 = L.take(8 * R);
@@ -174,6 +189,7 @@ void plan_wide(WidePlan &w, Layout &L, int64_t P, int64_t R, int kb)
     w.hoff = L.take(8 * (GS_BINS * w.nbs + 1));
     w.tmp = L.take(8 * (ceil_div(std::max<int64_t>(GS_BINS * w.nbs, w.nbm), LB_TILE) + 2));
     w.st_key = L.take(8 * R);
+    w.st_ckey = L.take(8 * R);
     w.st_coef = L.take(8 * R);
     w.cnt = L.take(8 * w.nbm);
     w.soff = L.take(8 * w.nbm);
@@ -191,14 +207,15 @@ poly_status run_simplify(const poly_csr *in, poly_csr *out, double zero_tol, voi
 poly_status run_wide(const WidePlan &w, void *ws, int64_t P, int64_t R, int n, int bits, const double *coefs,
                      double zero_tol, poly_csr *out, hipStream_t s);
 
-// T terms in P polynomials (row offsets rph on the host), kb-bit monomial keys
-SimplifyPlan plan_simplify(int64_t P, int64_t T, const int64_t *rph, int kb)
+// T terms in P polynomials (row offsets rph on the host), n variables with
+// exponents below radix
+SimplifyPlan plan_simplify(int64_t P, int64_t T, const int64_t *rph, int n, uint32_t radix)
 {
     Layout L;
     SimplifyPlan s;
-    if (wide_wanted(P, T, max_segment(rph, P), kb)) {
+    if (wide_wanted(P, T, max_segment(rph, P), n, radix)) {
         s.keys = s.st_key = s.st_coef = s.seg_count = s.order = s.queue = 0;
-        plan_wide(s.wide, L, P, T, kb);
+        plan_wide(s.wide, L, P, T, n, radix);
         s.total = L.total();
         return s;
     }
@@ -477,8 +494,6 @@ void ensure_lds_attrs()
     if (lds_attr_done) return;
     (void)hipFuncSetAttribute((const void *)k_eval_terms, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
     (void)hipFuncSetAttribute((const void *)k_backward_dc, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
-    (void)hipFuncSetAttribute((const void *)k_gs_sort_partner, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(GS_SORT1_CAP * 12));
     (void)hipFuncSetAttribute((const void *)k_mul_buckets_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)MB_LDS_LIMIT);
     (void)hipFuncSetAttribute((const void *)k_affine_normal, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -682,8 +697,8 @@ poly_status poly_simplify_workspace(const poly_csr *in, size_t *ws_bytes)
     poly_status st = check_csr(in, true);
     if (st != POLY_OK) return st;
     if (!ws_bytes) return POLY_ERR_ARG;
-    const int kb = in->nvars * bit_width_u32((uint32_t)in->max_exp);
-    *ws_bytes = plan_simplify(in->npolys, total_terms(in), in->row_ptr_host, kb).total;
+    *ws_bytes =
+        plan_simplify(in->npolys, total_terms(in), in->row_ptr_host, in->nvars, (uint32_t)in->max_exp + 1).total;
     return POLY_OK;
 }
 
@@ -699,7 +714,7 @@ poly_status poly_simplify(const poly_csr *in, poly_csr *out, double zero_tol, vo
     const int bits = bit_width_u32((uint32_t)in->max_exp);
     if ((int64_t)n * bits > 64) return POLY_ERR_KEY_OVERFLOW;
     const int64_t P = in->npolys, T = total_terms(in);
-    const SimplifyPlan pl = plan_simplify(P, T, in->row_ptr_host, n * bits);
+    const SimplifyPlan pl = plan_simplify(P, T, in->row_ptr_host, n, (uint32_t)in->max_exp + 1);
     if (!ws || ws_bytes < pl.total) return POLY_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     clear_u64(at<unsigned long long>(ws, 0), 1, s);
@@ -721,9 +736,9 @@ poly_status run_simplify(const poly_csr *in, poly_csr *out, double zero_tol, voi
     const int64_t P = in->npolys, T = total_terms(in);
     int32_t *status = at<int32_t>(ws, 0);
     if (pl.wide.on) {
-        hipLaunchKernelGGL(k_ws_keys, dim3(grid1(T, 256)), dim3(256), 0, s, in->exps, T, n, bits, in->max_exp,
-                           in->row_ptr, P, at<uint64_t>(ws, pl.wide.keys0), at<uint32_t>(ws, pl.wide.vals0),
-                           status);
+        hipLaunchKernelGGL(k_ws_keys, dim3(grid1(T, 256)), dim3(256), 0, s, in->exps, T, n, pl.wide.radix,
+                           in->max_exp, in->row_ptr, P, pl.wide.span, at<uint64_t>(ws, pl.wide.keys0),
+                           at<uint32_t>(ws, pl.wide.vals0), status);
         return run_wide(pl.wide, ws, P, T, n, bits, in->coefs, zero_tol, out, s);
     }
     uint64_t *keys = at<uint64_t>(ws, pl.keys);
@@ -797,15 +812,17 @@ poly_status run_wide(const WidePlan &w, void *ws, int64_t P, int64_t R, int n, i
     uint64_t *st_key = at<uint64_t>(ws, w.st_key);
     double *st_coef = at<double>(ws, w.st_coef);
     const int64_t mgrid = std::min<int64_t>(w.nbm, (int64_t)device_cus() * MG_BLOCKS_PER_CU);
+    uint64_t *st_ckey = at<uint64_t>(ws, w.st_ckey);
     hipLaunchKernelGGL(k_ws_merge, dim3((unsigned)mgrid), dim3(MG_THREADS), 0, s, (const uint64_t *)kcur,
-                       (const uint32_t *)vcur, R, coefs, zero_tol, st_key, st_coef, cnt, soff);
+                       (const uint32_t *)vcur, R, coefs, zero_tol, w.span, w.radix, n, bits, st_key, st_ckey,
+                       st_coef, cnt, soff);
     launch_scan(cnt, w.nbm, ooff, tmp, status, s, true);
     hipLaunchKernelGGL(k_compact, dim3((unsigned)w.nbm), dim3(256), 0, s, (const int64_t *)soff,
                        (const int64_t *)cnt, (const int64_t *)ooff, (const uint64_t *)st_key,
                        (const double *)st_coef, n, bits, out->exps, out->coefs, out->capacity, status);
-    hipLaunchKernelGGL(k_ws_rowptr, dim3(grid1(P + 1, 256)), dim3(256), 0, s, P, n * bits, (const uint64_t *)kcur,
+    hipLaunchKernelGGL(k_ws_rowptr, dim3(grid1(P + 1, 256)), dim3(256), 0, s, P, w.span, (const uint64_t *)kcur,
                        R, (const int64_t *)soff, (const int64_t *)cnt, (const int64_t *)ooff, w.nbm,
-                       (const uint64_t *)st_key, out->row_ptr);
+                       (const uint64_t *)st_ckey, out->row_ptr);
     LAUNCH_CHECK();
     return POLY_OK;
 }
@@ -904,13 +921,8 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
                                (uint64_t *)A.kb, status);
     }
     int64_t *cnt_tmp = at<int64_t>(ws, m.cnt_tmp);
-    if (m.sort_mode && Tb <= GS_SORT1_CAP) {
-        // one pair: only the partner operand needs sorting
-        ensure_lds_attrs();
-        hipLaunchKernelGGL(k_gs_sort_partner, dim3(1), dim3(GS_THREADS), (size_t)GS_SORT1_CAP * 12, s,
-                           (const uint64_t *)A.kb, b->coefs, Tb, (uint64_t *)A.kb_s, (uint32_t *)A.perm_b,
-                           (double *)A.cb_s);
-    } else {
+    if (!m.sort_mode) {
+        // the bucket paths take both operands in key order
         const SegArgs sa = presort_args(a, (uint64_t *)A.ka, (uint64_t *)A.ka_s, (uint32_t *)A.perm_a, cnt_tmp,
                                         at<int64_t>(ws, m.order_a), queues + 0, s);
         const SegArgs sb = presort_args(b, (uint64_t *)A.kb, (uint64_t *)A.kb_s, (uint32_t *)A.perm_b, cnt_tmp,
@@ -953,7 +965,7 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
         // ka[i] + kb_s[j] in raw order): it is never written to memory
         GsGen gen;
         gen.ka = (const uint64_t *)A.ka;
-        gen.kb_s = (const uint64_t *)A.kb_s;
+        gen.kb = (const uint64_t *)A.kb;
         gen.tb = (uint32_t)Tb;
         gen.inv_tb = 1.0 / (double)Tb;
         auto pass = [&](auto dbc, int p) {
@@ -982,7 +994,7 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
         };
         if (passes == 0)   // a single key value: the raw product unsorted
             hipLaunchKernelGGL(k_gs_generate, dim3((unsigned)std::min<int64_t>(Ta, 65535)), dim3(GS_THREADS), 0, s,
-                               A.ka, A.kb_s, Ta, Tb, kcur, vcur);
+                               A.ka, A.kb, Ta, Tb, kcur, vcur);
         for (int p = 0; p < passes; ++p) {
             switch (db) {
             case 4: pass(std::integral_constant<int, 4>(), p); break;
@@ -1014,16 +1026,16 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
         if (packed) {
             hipLaunchKernelGGL(k_gs_pairs, dim3(grid1(Ta, 256)), dim3(256), 0, s, (const uint64_t *)A.ka, a->coefs, Ta,
                                pa);
-            hipLaunchKernelGGL(k_gs_pairs, dim3(grid1(Tb, 256)), dim3(256), 0, s, (const uint64_t *)A.kb_s, A.cb_s,
+            hipLaunchKernelGGL(k_gs_pairs, dim3(grid1(Tb, 256)), dim3(256), 0, s, (const uint64_t *)A.kb, b->coefs,
                                Tb, pb);
             hipLaunchKernelGGL(k_gs_merge<true>, dim3((unsigned)mgrid), dim3(MG_THREADS), 0, s,
                                (const uint64_t *)kcur, (const uint32_t *)vcur, R, Ta, Tb, (const uint64_t *)A.ka,
-                               (const uint64_t *)A.kb_s, raw_bits, a->coefs, A.cb_s, (const GsKC *)pa,
+                               (const uint64_t *)A.kb, raw_bits, a->coefs, b->coefs, (const GsKC *)pa,
                                (const GsKC *)pb, zero_tol, dec, A.st_key, A.st_coef, cnt, soff);
         } else {
             hipLaunchKernelGGL(k_gs_merge<false>, dim3((unsigned)mgrid), dim3(MG_THREADS), 0, s,
                                (const uint64_t *)kcur, (const uint32_t *)vcur, R, Ta, Tb, (const uint64_t *)A.ka,
-                               (const uint64_t *)A.kb_s, raw_bits, a->coefs, A.cb_s, (const GsKC *)pa,
+                               (const uint64_t *)A.kb, raw_bits, a->coefs, b->coefs, (const GsKC *)pa,
                                (const GsKC *)pb, zero_tol, dec, A.st_key, A.st_coef, cnt, soff);
         }
         launch_scan(cnt, mb, ooff, tmp, status, s, true);
@@ -1366,15 +1378,15 @@ poly_status plan_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t
     m.raw = rph[Q];
     if (m.raw >= (int64_t(1) << 32)) return POLY_ERR_UNSUPPORTED;
     m.bits = bit_width_u32((uint32_t)(A->max_exp + B->max_exp));
-    const int kb = A->nvars * m.bits;
+    const uint32_t radix = (uint32_t)(A->max_exp + B->max_exp) + 1;
     Layout L;
-    if (wide_wanted(Q, m.raw, max_segment(rph.data(), Q), kb)) {
-        plan_wide(m.wide, L, Q, m.raw, kb);
+    if (wide_wanted(Q, m.raw, max_segment(rph.data(), Q), A->nvars, radix)) {
+        plan_wide(m.wide, L, Q, m.raw, A->nvars, radix);
         m.ka = L.take(8 * total_terms(A));
         m.kb = L.take(8 * total_terms(B));
         m.re = 0;
     } else {
-        m.sp = plan_simplify(Q, m.raw, rph.data(), kb);
+        m.sp = plan_simplify(Q, m.raw, rph.data(), A->nvars, radix);
         L.off = m.sp.total;
         m.re = L.take((size_t)m.raw * A->nvars);
         m.ka = m.kb = 0;
@@ -1434,15 +1446,16 @@ poly_status poly_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t
     if (m.wide.on) {
         const int64_t TA = total_terms(A), TB = total_terms(B);
         uint64_t *ka = at<uint64_t>(ws, m.ka), *kb = at<uint64_t>(ws, m.kb);
+        const uint64_t radix = m.wide.radix;
         if (TA > 0)
-            hipLaunchKernelGGL(k_pack, dim3(grid1(TA, 256)), dim3(256), 0, s, A->exps, TA, n, m.bits, A->max_exp, ka,
-                               status);
+            hipLaunchKernelGGL(k_gs_pack_radix, dim3(grid1(TA, 256)), dim3(256), 0, s, A->exps, TA, n, radix,
+                               A->max_exp, ka, status);
         if (TB > 0)
-            hipLaunchKernelGGL(k_pack, dim3(grid1(TB, 256)), dim3(256), 0, s, B->exps, TB, n, m.bits, B->max_exp, kb,
-                               status);
+            hipLaunchKernelGGL(k_gs_pack_radix, dim3(grid1(TB, 256)), dim3(256), 0, s, B->exps, TB, n, radix,
+                               B->max_exp, kb, status);
         hipLaunchKernelGGL(k_mat_keys, dim3(grid1(m.raw, 256)), dim3(256), 0, s, A->row_ptr, (const uint64_t *)ka,
                            A->coefs, B->row_ptr, (const uint64_t *)kb, B->coefs, I, K, J, (const int64_t *)rrp,
-                           m.raw, n * m.bits, at<uint64_t>(ws, m.wide.keys0), at<uint32_t>(ws, m.wide.vals0), rc);
+                           m.raw, m.wide.span, at<uint64_t>(ws, m.wide.keys0), at<uint32_t>(ws, m.wide.vals0), rc);
         return run_wide(m.wide, ws, Q, m.raw, n, m.bits, rc, zero_tol, out, s);
     }
     hipLaunchKernelGGL(k_mat_expand, dim3((unsigned)Q), dim3(MAT_THREADS), 0, s, A->row_ptr, A->exps, A->coefs,

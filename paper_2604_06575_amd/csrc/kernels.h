@@ -185,15 +185,18 @@ __global__ void k_mat_expand(const int64_t *a_rp, const uint8_t *a_e, const doub
                              const int64_t *r_rp, uint8_t *r_e, double *r_c);
 __global__ void k_mat_keys(const int64_t *a_rp, const uint64_t *ka, const double *a_c, const int64_t *b_rp,
                            const uint64_t *kb, const double *b_c, int64_t I, int64_t K, int64_t J,
-                           const int64_t *r_rp, int64_t R, int kbits, uint64_t *keys, uint32_t *vals, double *r_c);
+                           const int64_t *r_rp, int64_t R, uint64_t span, uint64_t *keys, uint32_t *vals,
+                           double *r_c);
 
 // device-wide simplify of batches with large polynomials (wide.hip)
-__global__ void k_ws_keys(const uint8_t *exps, int64_t T, int n, int bits, int max_exp, const int64_t *row_ptr,
-                          int64_t P, uint64_t *keys, uint32_t *vals, int32_t *status);
+__global__ void k_ws_keys(const uint8_t *exps, int64_t T, int n, uint32_t radix, int max_exp,
+                          const int64_t *row_ptr, int64_t P, uint64_t span, uint64_t *keys, uint32_t *vals,
+                          int32_t *status);
 __global__ void k_ws_merge(const uint64_t *keys, const uint32_t *vals, int64_t R, const double *coefs, double tol,
-                           uint64_t *st_key, double *st_coef, int64_t *seg_count, int64_t *stage_off);
-__global__ void k_ws_rowptr(int64_t P, int kb, const uint64_t *keys, int64_t R, const int64_t *stage_off,
-                            const int64_t *seg_count, const int64_t *out_off, int64_t nb, const uint64_t *st_key,
+                           uint64_t span, uint32_t radix, int n, int bits, uint64_t *st_key, uint64_t *st_ckey,
+                           double *st_coef, int64_t *seg_count, int64_t *stage_off);
+__global__ void k_ws_rowptr(int64_t P, uint64_t span, const uint64_t *keys, int64_t R, const int64_t *stage_off,
+                            const int64_t *seg_count, const int64_t *out_off, int64_t nb, const uint64_t *st_ckey,
                             int64_t *row_ptr);
 
 // affine-normal direction (affine.hip): one workgroup per point

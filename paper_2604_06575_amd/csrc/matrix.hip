@@ -58,14 +58,14 @@ namespace polyhip {
 
 // The same raw products for the device-wide simplify, one thread per raw
 // term r: the output entry q holding r (a binary search of r_rp), then k and
-// the factor pair; the term's key is (q << kbits) | (ka + kb) -- bit-field
-// monomial keys add without carries because each field is wide enough for
-// the sum of the two exponents -- its value index r, its coefficient the
-// product.
+// the factor pair; the term's key is q * span + ka + kb -- mixed-radix
+// monomial keys with radix max_exp(A) + max_exp(B) + 1 add without carries --
+// its value index r, its coefficient the product (span = radix^n, or 0 for
+// a single output entry).
 __global__ void k_mat_keys(const int64_t *__restrict__ a_rp, const uint64_t *__restrict__ ka,
                            const double *__restrict__ a_c, const int64_t *__restrict__ b_rp,
                            const uint64_t *__restrict__ kb, const double *__restrict__ b_c, int64_t I, int64_t K,
-                           int64_t J, const int64_t *__restrict__ r_rp, int64_t R, int kbits,
+                           int64_t J, const int64_t *__restrict__ r_rp, int64_t R, uint64_t span,
                            uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, double *__restrict__ r_c)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -90,7 +90,7 @@ __global__ void k_mat_keys(const int64_t *__restrict__ a_rp, const uint64_t *__r
     }
     const int64_t a = x / tb, b = x - (x / tb) * tb;
     const uint64_t key = ka[a0 + a] + kb[b0 + b];
-    keys[r] = kbits < 64 ? ((uint64_t)q << kbits) | key : key;
+    keys[r] = (uint64_t)q * span + key;
     vals[r] = (uint32_t)r;
     r_c[r] = a_c[a0 + a] * b_c[b0 + b];
 }

@@ -13,24 +13,21 @@ constexpr int GS_BITS = 8;                       // widest digit
 constexpr int GS_BINS = 1 << GS_BITS;
 constexpr int GS_MIN_BITS = 4;                   // narrowest digit instantiated
 constexpr int GS_HIST_THREADS = 256;
-constexpr int GS_SORT1_CAP = 8192;               // partner terms sorted by one workgroup
 constexpr int MG_THREADS = 512;                  // merge workgroup
 constexpr int MG_TILE = MG_THREADS * 4;          // merge elements per tile
 constexpr int MG_BLOCKS_PER_CU = 4;              // persistent merge workgroups per CU
 constexpr int GS_HALO = 64;                      // elements past a tile staged by the merge
 __global__ void k_gs_pack_radix(const uint8_t *exps, int64_t T, int n, uint64_t radix, int max_exp,
                                 uint64_t *keys, int32_t *status);
-__global__ void k_gs_sort_partner(const uint64_t *keys, const double *coefs, int64_t T, uint64_t *keys_s,
-                                  uint32_t *perm, double *coefs_s);
-__global__ void k_gs_generate(const uint64_t *ka, const uint64_t *kb_s, int64_t ta, int64_t tb, uint64_t *keys,
+__global__ void k_gs_generate(const uint64_t *ka, const uint64_t *kb, int64_t ta, int64_t tb, uint64_t *keys,
                               uint32_t *vals);
 // Elements of the raw product in raw order, generated instead of read: the
-// element with raw index r = i * tb + j has key ka[i] + kb_s[j].  The first
+// element with raw index r = i * tb + j has key ka[i] + kb[j].  The first
 // radix pass and its histogram read the product this way, so it is never
 // written to memory.
 struct GsGen {
     const uint64_t *ka;
-    const uint64_t *kb_s;
+    const uint64_t *kb;
     uint32_t tb;
     double inv_tb;   // 1 / tb
     __device__ uint64_t key(uint32_t r) const
@@ -39,7 +36,7 @@ struct GsGen {
         uint32_t i = (uint32_t)((double)r * inv_tb);
         if (i * (uint64_t)tb > r) --i;
         else if ((uint64_t)(i + 1) * tb <= r) ++i;
-        return ka[i] + kb_s[r - i * tb];
+        return ka[i] + kb[r - i * tb];
     }
 };
 
@@ -69,8 +66,8 @@ struct __align__(16) GsKC {
 __global__ void k_gs_pairs(const uint64_t *keys, const double *coefs, int64_t T, GsKC *out);
 template <bool PACKED>
 __global__ void k_gs_merge(const uint64_t *keys, const uint32_t *vals, int64_t R, int64_t ta, int64_t tb,
-                           const uint64_t *ka, const uint64_t *kb_s, int raw_bits, const double *ca,
-                           const double *cb_s, const GsKC *pa, const GsKC *pb, double tol, RadixDecode dec,
+                           const uint64_t *ka, const uint64_t *kb, int raw_bits, const double *ca,
+                           const double *cb, const GsKC *pa, const GsKC *pb, double tol, RadixDecode dec,
                            uint64_t *st_key, double *st_coef, int64_t *seg_count, int64_t *stage_off);
 __global__ void k_gs_rowptr(const int64_t *out_off, int64_t nblocks, int64_t *row_ptr);
 

@@ -9,8 +9,7 @@
 // (r rounded up to a power of two), so fewer digits need sorting.
 //
 // The raw product of p (ta terms) and q (tb terms) is generated in (i, j)
-// order -- i over p's terms in storage order, j over q's terms in ascending
-// key order (a stable order, so equal keys of q keep storage order) -- as
+// order -- both operands in storage order, the order of the definition -- as
 // (key k_i + k_j, raw index i * tb + j).  A least-significant-digit radix
 // sort with digits of at most GS_BITS bits (as few passes as the key range
 // needs, digits as even as possible), stable in every pass, orders the pairs
@@ -21,7 +20,6 @@
 // shared unpack kernel.  All traffic is streaming HBM traffic: the sort is
 // bandwidth-bound, with no per-row state on chip.
 #include "kernels.h"
-#include "lds_sort.h"
 
 // products and sums are rounded separately, as in the definition (no FMA)
 #pragma clang fp contract(off)
@@ -47,51 +45,15 @@ __global__ void k_gs_pack_radix(const uint8_t *exps, int64_t T, int n, uint64_t 
     if (bad) set_status(status, POLY_ERR_EXPONENT);
 }
 
-// The partner operand in ascending key order, stably (equal keys keep
-// storage order), in one workgroup (T <= GS_SORT1_CAP): sorted keys, the
-// storage index of each sorted position, and the coefficients in sorted
-// order.  Keys are sorted relative to their minimum, on the occupied bits.
-// Dynamic LDS: GS_SORT1_CAP * 12 bytes.
-__global__ void __launch_bounds__(GS_THREADS) k_gs_sort_partner(const uint64_t *keys, const double *coefs, int64_t T,
-                                                               uint64_t *keys_s, uint32_t *perm, double *coefs_s)
-{
-    extern __shared__ uint64_t s_dyn[];
-    uint64_t *sk = s_dyn;
-    uint32_t *sv = reinterpret_cast<uint32_t *>(s_dyn + GS_SORT1_CAP);
-    __shared__ uint32_t s_cnt[(GS_THREADS / kWave) * 256];
-    __shared__ uint32_t s_scan[GS_THREADS / kWave];
-    __shared__ uint64_t s_red[GS_THREADS / kWave];
-    const int m = (int)T;
-    uint64_t lmin = ~0ull, lmax = 0;
-    for (int i = threadIdx.x; i < m; i += GS_THREADS) {
-        const uint64_t k = keys[i];
-        sk[i] = k;
-        sv[i] = (uint32_t)i;
-        lmin = k < lmin ? k : lmin;
-        lmax = k > lmax ? k : lmax;
-    }
-    const uint64_t kmin = block_min_u64<GS_THREADS>(lmin, s_red);
-    const uint64_t kmax = block_max_u64<GS_THREADS>(lmax, s_red);
-    for (int i = threadIdx.x; i < m; i += GS_THREADS) sk[i] -= kmin;
-    __syncthreads();
-    const int bits = kmax > kmin ? 64 - __clzll((unsigned long long)(kmax - kmin)) : 0;
-    lds_radix_sort<GS_THREADS, GS_SORT1_CAP / GS_THREADS, uint32_t>(sk, sv, m, bits, s_cnt, s_scan);
-    for (int i = threadIdx.x; i < m; i += GS_THREADS) {
-        keys_s[i] = sk[i] + kmin;
-        perm[i] = sv[i];
-        coefs_s[i] = coefs[sv[i]];
-    }
-}
-
 // raw pair (i, j) -> (key, i * tb + j), one block row per term of p
-__global__ void __launch_bounds__(GS_THREADS) k_gs_generate(const uint64_t *ka, const uint64_t *kb_s, int64_t ta,
+__global__ void __launch_bounds__(GS_THREADS) k_gs_generate(const uint64_t *ka, const uint64_t *kb, int64_t ta,
                                                            int64_t tb, uint64_t *keys, uint32_t *vals)
 {
     for (int64_t i = blockIdx.x; i < ta; i += gridDim.x) {
         const uint64_t kr = ka[i];
         const int64_t base = i * tb;
         for (int64_t j = threadIdx.x; j < tb; j += GS_THREADS) {
-            keys[base + j] = kr + kb_s[j];
+            keys[base + j] = kr + kb[j];
             vals[base + j] = (uint32_t)(base + j);
         }
     }
@@ -284,12 +246,12 @@ __global__ void __launch_bounds__(GS_SC_THREADS) k_gs_scatter(const uint64_t *ke
 //
 // PACKED: the sorted stream holds packed words (raw index in the low
 // raw_bits bits, `vals` unused); each element's key is rebuilt exactly as
-// ka[i] + kb_s[j] from its raw index.
+// ka[i] + kb[j] from its raw index.
 template <bool PACKED>
 __global__ void __launch_bounds__(MG_THREADS) k_gs_merge(const uint64_t *keys, const uint32_t *vals, int64_t R,
                                                         int64_t ta, int64_t tb, const uint64_t *ka,
-                                                        const uint64_t *kb_s, int raw_bits, const double *ca,
-                                                        const double *cb_s, const GsKC *pa, const GsKC *pb,
+                                                        const uint64_t *kb, int raw_bits, const double *ca,
+                                                        const double *cb, const GsKC *pa, const GsKC *pb,
                                                         double tol, RadixDecode dec, uint64_t *st_key,
                                                         double *st_coef, int64_t *seg_count, int64_t *stage_off)
 {
@@ -349,7 +311,7 @@ __global__ void __launch_bounds__(MG_THREADS) k_gs_merge(const uint64_t *keys, c
     };
     auto product = [&](uint32_t r) {
         const uint2 ij = split_raw(r);
-        return ca[ij.x] * cb_s[ij.y];
+        return ca[ij.x] * cb[ij.y];
     };
     const uint64_t rmask = raw_bits >= 64 ? ~0ull : ((1ull << raw_bits) - 1ull);
     // key and raw index of element g of the sorted stream
@@ -357,7 +319,7 @@ __global__ void __launch_bounds__(MG_THREADS) k_gs_merge(const uint64_t *keys, c
         if (PACKED) {
             raw = (uint32_t)(keys[g] & rmask);
             const uint2 ij = split_raw(raw);
-            return ka[ij.x] + kb_s[ij.y];
+            return ka[ij.x] + kb[ij.y];
         }
         raw = vals[g];
         return keys[g];
@@ -414,7 +376,7 @@ __global__ void __launch_bounds__(MG_THREADS) k_gs_merge(const uint64_t *keys, c
                 kr[q] = x.k + y.k;
             } else {
                 ci[q] = ca[ij.x];
-                cj[q] = cb_s[ij.y];
+                cj[q] = cb[ij.y];
             }
         }
         if (blk + (int64_t)gridDim.x < nb) load_tile(blk + gridDim.x);

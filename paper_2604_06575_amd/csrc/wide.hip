@@ -2,19 +2,23 @@
 // terms of each polynomial by monomial, combine equal monomials, drop the
 // zeros), as one device-wide sort instead of one workgroup per polynomial.
 //
-// Each term gets the key (polynomial << n * bits) | (bit-field monomial key),
-// so one stable LSD radix sort over the whole batch orders every polynomial's
-// terms by monomial, the polynomials one after another, and equal monomials
-// in their input order.  The merge then sums each run of equal keys left to
-// right (the order of the definition, so results are bit-identical to the
-// per-polynomial path) and stages the kept terms; the row pointers come from
-// binary searches of the sorted keys.
+// Each term gets the key p * r^n + sum_i e_i r^(n-1-i) (polynomial p, radix
+// r = max_exp + 1, x1 the most significant digit), so one stable LSD radix
+// sort over the whole batch orders every polynomial's terms by monomial, the
+// polynomials one after another, and equal monomials in their input order;
+// mixed-radix digits keep the key range, and so the number of passes, as
+// small as the exponent bound allows.  The merge then sums each run of equal
+// keys left to right (the order of the definition, so results are
+// bit-identical to the per-polynomial path) and stages the kept terms with
+// their exponents as bit fields for the unpack kernel; the row pointers come
+// from binary searches of the sorted keys.
 #include "kernels.h"
 
 namespace polyhip {
 
-__global__ void k_ws_keys(const uint8_t *__restrict__ exps, int64_t T, int n, int bits, int max_exp,
-                          const int64_t *__restrict__ row_ptr, int64_t P, uint64_t *__restrict__ keys,
+// span = r^n, or 0 for a single polynomial
+__global__ void k_ws_keys(const uint8_t *__restrict__ exps, int64_t T, int n, uint32_t radix, int max_exp,
+                          const int64_t *__restrict__ row_ptr, int64_t P, uint64_t span, uint64_t *__restrict__ keys,
                           uint32_t *__restrict__ vals, int32_t *status)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -25,7 +29,7 @@ __global__ void k_ws_keys(const uint8_t *__restrict__ exps, int64_t T, int n, in
     for (int i = 0; i < n; ++i) {
         const uint32_t e = row[i];
         bad |= (int)(e > (uint32_t)max_exp);
-        k = (k << bits) | (uint64_t)e;
+        k = k * radix + e;
     }
     // the polynomial holding term t: the last p < P with row_ptr[p] <= t
     int64_t lo = 0, hi = P;
@@ -34,8 +38,7 @@ __global__ void k_ws_keys(const uint8_t *__restrict__ exps, int64_t T, int n, in
         if (row_ptr[mid] <= t) lo = mid;
         else hi = mid;
     }
-    const int kb = n * bits;
-    keys[t] = kb < 64 ? ((uint64_t)lo << kb) | k : k;
+    keys[t] = (uint64_t)lo * span + k;
     vals[t] = (uint32_t)t;
     if (bad) set_status(status, POLY_ERR_EXPONENT);
 }
@@ -46,12 +49,15 @@ __global__ void k_ws_keys(const uint8_t *__restrict__ exps, int64_t T, int n, in
 // last run continues through a halo of GS_HALO elements and, past that, the
 // sorted stream itself.  Runs whose head lies in an earlier tile belong to
 // that tile.  Kept sums are staged in element order at [b * MG_TILE, ...)
-// with their full keys (the unpack masks the polynomial bits off).
+// with their composite keys (st_ckey) and their exponents as bit fields of
+// `bits` bits, x1 in the top field (st_key, the unpack kernel's layout).
 __global__ void __launch_bounds__(MG_THREADS) k_ws_merge(const uint64_t *__restrict__ keys,
                                                         const uint32_t *__restrict__ vals, int64_t R,
                                                         const double *__restrict__ coefs, double tol,
-                                                        uint64_t *__restrict__ st_key, double *__restrict__ st_coef,
-                                                        int64_t *seg_count, int64_t *stage_off)
+                                                        uint64_t span, uint32_t radix, int n, int bits,
+                                                        uint64_t *__restrict__ st_key, uint64_t *__restrict__ st_ckey,
+                                                        double *__restrict__ st_coef, int64_t *seg_count,
+                                                        int64_t *stage_off)
 {
     __shared__ uint64_t s_key[MG_TILE + GS_HALO];
     __shared__ double s_c[MG_TILE + GS_HALO];
@@ -60,6 +66,17 @@ __global__ void __launch_bounds__(MG_THREADS) k_ws_merge(const uint64_t *__restr
     constexpr int MI = MG_TILE / MG_THREADS;
     static_assert(MI <= 4 && MG_TILE < 65536, "flags are packed 16 bits per round");
     const int64_t nb = (R + MG_TILE - 1) / MG_TILE;
+    // monomial digits of a composite key, least significant (x_n) first
+    auto to_fields = [&](uint64_t key) {
+        uint64_t x = span ? key % span : key;
+        uint64_t f = 0;
+        for (int v = n - 1; v >= 0; --v) {
+            const uint64_t q = x / radix;
+            f |= (x - q * radix) << (bits * (n - 1 - v));
+            x = q;
+        }
+        return f;
+    };
     for (int64_t blk = blockIdx.x; blk < nb; blk += gridDim.x) {
         const int64_t t0 = blk * MG_TILE;
         const int m = (int)(R - t0 < MG_TILE ? R - t0 : MG_TILE);
@@ -150,7 +167,8 @@ __global__ void __launch_bounds__(MG_THREADS) k_ws_merge(const uint64_t *__restr
         for (int q = 0; q < MI; ++q) {
             if ((kflags >> (16 * q)) & 1u) {
                 const int64_t d = t0 + tot + (int64_t)((kpre >> (16 * q)) & 0xffffu);
-                st_key[d] = hk[q];
+                st_key[d] = to_fields(hk[q]);
+                st_ckey[d] = hk[q];
                 st_coef[d] = hs[q];
             }
             tot += (int64_t)((ktot >> (16 * q)) & 0xffffu);
@@ -162,14 +180,14 @@ __global__ void __launch_bounds__(MG_THREADS) k_ws_merge(const uint64_t *__restr
     }
 }
 
-// row_ptr[p] = number of kept terms whose key is below p << kb: the first
+// row_ptr[p] = number of kept terms whose key is below p * span: the first
 // sorted element with such a key falls in merge tile b, every run staged by
 // an earlier tile has a smaller key, and the staged keys of tile b are
 // searched.  Threads p = 0..P; out_off holds nb + 1 entries (the last is the
 // total).
-__global__ void k_ws_rowptr(int64_t P, int kb, const uint64_t *__restrict__ keys, int64_t R,
+__global__ void k_ws_rowptr(int64_t P, uint64_t span, const uint64_t *__restrict__ keys, int64_t R,
                             const int64_t *__restrict__ stage_off, const int64_t *__restrict__ seg_count,
-                            const int64_t *__restrict__ out_off, int64_t nb, const uint64_t *__restrict__ st_key,
+                            const int64_t *__restrict__ out_off, int64_t nb, const uint64_t *__restrict__ st_ckey,
                             int64_t *row_ptr)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -182,7 +200,7 @@ __global__ void k_ws_rowptr(int64_t P, int kb, const uint64_t *__restrict__ keys
         row_ptr[P] = out_off[nb];
         return;
     }
-    const uint64_t v = (uint64_t)p << kb;   // 0 < p < P, so kb < 64
+    const uint64_t v = (uint64_t)p * span;   // 0 < p < P, so span > 0
     int64_t lo = 0, hi = R;                 // first element with key >= v
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
@@ -194,7 +212,7 @@ __global__ void k_ws_rowptr(int64_t P, int kb, const uint64_t *__restrict__ keys
         return;
     }
     const int64_t b = lo / MG_TILE;
-    const uint64_t *sk = st_key + stage_off[b];
+    const uint64_t *sk = st_ckey + stage_off[b];
     int64_t a = 0, c = seg_count[b];
     while (a < c) {
         const int64_t mid = (a + c) >> 1;

@@ -140,3 +140,14 @@ def test_sum_and_prod_degenerate(ph):
     say("msum / mprod: one column")
     _same(ph, ph.msum(a, 3, 1, 2), oracle.msum(*ra, 3, 1, 2, n=n))
     _same(ph, ph.mprod(a, 3, 1, 2), oracle.mprod(*ra, 3, 1, 2, n=n))
+
+
+def test_bench_workload_full_size(ph):
+    """The benchmark's matrix product at its full size: A^2 for a 3 x 3 matrix
+    of degree-4 polynomials in n=8 with 300 distinct monomials each (Gaussian
+    coefficients), 2,430,000 raw terms, every output term compared bitwise."""
+    rng = W.rng_for(W.SEED_BASE + 95)
+    n, d, terms, I = 8, 4, 300, 3
+    A = [W.random_poly(rng, n, d, terms, integer=False, distinct=True) for _ in range(I * I)]
+    say("mtimes: 3x3 A^2, 300-term entries (benchmark workload)")
+    _case(ph, A, A, I, I, I, n, d)

@@ -123,9 +123,9 @@ def test_device_detected_exponent_error(ph, path):
     assert ei.value.code == 5
 
 
-def test_partner_above_one_workgroup_sort(ph, path):
-    """q with 9,000 terms: more partners than one workgroup sorts, so the
-    sort path falls back to the segmented operand sort."""
+def test_long_partner(ph, path):
+    """q with 9,000 terms against 40: more partners than one workgroup holds
+    (the bucket path sorts its operands segment by segment)."""
     wl = W.plain_large(seed=W.SEED_BASE + 44, terms=9000, n=8, d=8)
     say(f"[{path}] 40 x 9000 n=8")
     run_pair(ph, wl.a_exps[:40], wl.a_coefs[:40], wl.b_exps, wl.b_coefs, 8, 8)
