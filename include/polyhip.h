@@ -140,9 +140,10 @@ poly_status poly_timing_read(int32_t slot, double *total_ms, int64_t *launches);
  * Inputs may hold repeated monomials in any order.  Batches whose largest
  * entry has fewer than "simplify_wide_min" terms are processed by one
  * persistent launch that takes entries largest first; otherwise, when
- * n*b + bit width of (npolys - 1) <= 64, by one device-wide radix sort of
- * (entry, monomial) keys and a tiled merge of equal-key runs.  Both sum each
- * run left to right in input order, so they give bit-identical results.
+ * npolys * (max_exp + 1)^n <= 2^64, by one device-wide radix sort of the keys
+ * entry * (max_exp + 1)^n + (mixed-radix monomial key) and a tiled merge of
+ * equal-key runs.  Both sum each run left to right in input order, so they
+ * give bit-identical results.
  * out->npolys must equal in->npolys, out->nvars in->nvars; out->capacity >=
  * total input terms always suffices.  zero_tol >= 0 (NaN sums are kept).
  * Exponent rows are packed into 64-bit keys with b = bit width of max_exp

@@ -21,11 +21,21 @@
 // in place.  w is accumulated term by term from each monomial's factor list
 // (variables in ascending order, degree <= EV_MAX_DEG) with per-point power
 // tables.
+#include <limits.h>
+
 #include "kernels.h"
 
 namespace polyhip {
 
 namespace {
+
+__device__ inline double readlane_d(double v, int lane)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 template <int THREADS>
 __device__ inline double block_sum_d(double v, double *scratch)
@@ -55,7 +65,11 @@ __global__ void __launch_bounds__(AN_THREADS) k_affine_normal(int n, const uint4
     double *xp = col + n;                         // [n][KP] powers
     __shared__ double s_red[AN_THREADS / kWave];
     __shared__ int s_piv[AN_MAX_N];
+    __shared__ int s_kinv[kWave];
     __shared__ int s_ip;
+    __shared__ double s_rowbuf[2][AN_THREADS / kWave][kWave];
+    __shared__ double s_cval[2][AN_THREADS / kWave];
+    __shared__ int s_crow[2][AN_THREADS / kWave];
     const int tid = threadIdx.x;
     // matrix loops: rows by wave, columns by lane (no index division)
     const int ty = tid / kWave, tx = tid % kWave;
@@ -115,62 +129,148 @@ __global__ void __launch_bounds__(AN_THREADS) k_affine_normal(int n, const uint4
         }
     __syncthreads();
     // ---- A^-1 in place: Gauss-Jordan with partial (row) pivoting
-    for (int k = 0; k < m; ++k) {
-        if (tid < kWave) {
-            double best = -1.0;
-            int bi = k;
-            for (int i = k + tid; i < m; i += kWave) {
-                const double a = fabs(S[i * ld + k]);
-                if (a > best) {
-                    best = a;
-                    bi = i;
+    if (m <= kWave) {
+        // Register-resident for n <= 65: lane tx holds column tx of rows
+        // ty, ty + NW, ... (RPT rows).  Rows are not swapped: each step's
+        // pivot is the unused row with the largest entry in column k (the
+        // smallest row index on ties).  Every wave offers its best row in LDS
+        // (double-buffered by step parity, so one barrier per step), and the
+        // column-k multipliers come from lane k by readlane.  Afterwards the
+        // entry in row i, column j belongs at (kinv[i], piv[j]) of the inverse,
+        // where row i was the pivot of step kinv[i] and piv[j] the pivot row of
+        // step j.
+        constexpr int RPT = kWave / NW;
+        double a[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int i = ty + NW * r;
+            a[r] = (i < m && tx < m) ? S[i * ld + tx] : 0.0;
+        }
+        uint64_t used = 0;
+        for (int k = 0; k < m; ++k) {
+            const int par = k & 1;
+            // this wave's candidate (computed on every lane, lane k's counts)
+            double bv = -1.0;
+            int br = -1;
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int i = ty + NW * r;
+                const double v = fabs(a[r]);
+                if (i < m && !((used >> i) & 1ull) && (br < 0 || v > bv)) {
+                    bv = v;
+                    br = r;
                 }
             }
+            bv = readlane_d(bv, k);
+            br = __builtin_amdgcn_readlane(br, k);
+            if (br >= 0) {
+                double v = a[0];
 #pragma unroll
-            for (int o = kWave / 2; o > 0; o >>= 1) {
-                const double ob = __shfl_xor(best, o, kWave);
-                const int oi = __shfl_xor(bi, o, kWave);
-                if (ob > best || (ob == best && oi < bi)) {
-                    best = ob;
-                    bi = oi;
+                for (int r = 1; r < RPT; ++r) v = r == br ? a[r] : v;
+                s_rowbuf[par][ty][tx] = v;
+            }
+            if (tx == 0) {
+                s_cval[par][ty] = bv;
+                s_crow[par][ty] = br >= 0 ? ty + NW * br : INT_MAX;
+            }
+            __syncthreads();
+            double best = -1.0;
+            int ip = INT_MAX, wsel = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const double c = s_cval[par][w];
+                const int ci = s_crow[par][w];
+                if (ci == INT_MAX) continue;
+                if (ip == INT_MAX || c > best || (c == best && ci < ip)) {
+                    best = c;
+                    ip = ci;
+                    wsel = w;
+                }
+            }
+            used |= 1ull << ip;
+            const double pinv = 1.0 / s_rowbuf[par][wsel][k];
+            const double pl = s_rowbuf[par][wsel][tx] * pinv;   // scaled pivot row, column tx
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int i = ty + NW * r;
+                if (i == ip) {
+                    a[r] = tx == k ? pinv : pl;
+                } else {
+                    const double c = readlane_d(a[r], k);
+                    a[r] = tx == k ? -c * pinv : a[r] - c * pl;
                 }
             }
             if (tid == 0) {
-                s_ip = bi;
-                s_piv[k] = bi;
+                s_piv[k] = ip;
+                s_kinv[ip] = k;
             }
         }
         __syncthreads();
-        const int ip = s_ip;
-        if (ip != k)
-            for (int j = tid; j < m; j += AN_THREADS) {
-                const double a = S[k * ld + j];
-                S[k * ld + j] = S[ip * ld + j];
-                S[ip * ld + j] = a;
-            }
-        __syncthreads();
-        const double pinv = 1.0 / S[k * ld + k];
-        for (int i = tid; i < m; i += AN_THREADS) col[i] = S[i * ld + k];
-        __syncthreads();
-        for (int j = tid; j < m; j += AN_THREADS) S[k * ld + j] = j == k ? pinv : S[k * ld + j] * pinv;
-        __syncthreads();
-        for (int i = ty; i < m; i += NW) {
-            if (i == k) continue;
-            const double ci = col[i];
-            for (int j = tx; j < m; j += kWave)
-                S[i * ld + j] = j == k ? -ci * pinv : S[i * ld + j] - ci * S[k * ld + j];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int i = ty + NW * r;
+            if (i < m && tx < m) S[s_kinv[i] * ld + s_piv[tx]] = a[r];
         }
         __syncthreads();
-    }
-    for (int k = m - 1; k >= 0; --k) {   // undo the row swaps as column swaps, last first
-        const int ip = s_piv[k];
-        if (ip != k)
-            for (int i = tid; i < m; i += AN_THREADS) {
-                const double a = S[i * ld + k];
-                S[i * ld + k] = S[i * ld + ip];
-                S[i * ld + ip] = a;
+    } else {
+        // larger n: the matrix stays in LDS, rows swapped, swaps undone after
+        for (int k = 0; k < m; ++k) {
+            if (tid < kWave) {
+                double best = -1.0;
+                int bi = k;
+                for (int i = k + tid; i < m; i += kWave) {
+                    const double a = fabs(S[i * ld + k]);
+                    if (a > best) {
+                        best = a;
+                        bi = i;
+                    }
+                }
+    #pragma unroll
+                for (int o = kWave / 2; o > 0; o >>= 1) {
+                    const double ob = __shfl_xor(best, o, kWave);
+                    const int oi = __shfl_xor(bi, o, kWave);
+                    if (ob > best || (ob == best && oi < bi)) {
+                        best = ob;
+                        bi = oi;
+                    }
+                }
+                if (tid == 0) {
+                    s_ip = bi;
+                    s_piv[k] = bi;
+                }
             }
-        __syncthreads();
+            __syncthreads();
+            const int ip = s_ip;
+            if (ip != k)
+                for (int j = tid; j < m; j += AN_THREADS) {
+                    const double a = S[k * ld + j];
+                    S[k * ld + j] = S[ip * ld + j];
+                    S[ip * ld + j] = a;
+                }
+            __syncthreads();
+            const double pinv = 1.0 / S[k * ld + k];
+            for (int i = tid; i < m; i += AN_THREADS) col[i] = S[i * ld + k];
+            __syncthreads();
+            for (int j = tid; j < m; j += AN_THREADS) S[k * ld + j] = j == k ? pinv : S[k * ld + j] * pinv;
+            __syncthreads();
+            for (int i = ty; i < m; i += NW) {
+                if (i == k) continue;
+                const double ci = col[i];
+                for (int j = tx; j < m; j += kWave)
+                    S[i * ld + j] = j == k ? -ci * pinv : S[i * ld + j] - ci * S[k * ld + j];
+            }
+            __syncthreads();
+        }
+        for (int k = m - 1; k >= 0; --k) {   // undo the row swaps as column swaps, last first
+            const int ip = s_piv[k];
+            if (ip != k)
+                for (int i = tid; i < m; i += AN_THREADS) {
+                    const double a = S[i * ld + k];
+                    S[i * ld + k] = S[i * ld + ip];
+                    S[i * ld + ip] = a;
+                }
+            __syncthreads();
+        }
     }
     // ---- M = P K P with K = [A^-1 0; 0 0]
     for (int i = tid; i < n; i += AN_THREADS) {

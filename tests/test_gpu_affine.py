@@ -99,3 +99,12 @@ def test_no_points(ph):
     b = ph.batch_from_numpy([0, 1], np.array([[2, 0]], np.uint8), np.array([1.0]), n=2, max_exp=2)
     D, gn = ph.affine_normal(b, torch.zeros((0, 2), dtype=torch.float64, device="cuda"))
     assert D.shape == (0, 2) and gn.shape == (0,)
+
+
+@pytest.mark.parametrize("n", [65, 70])
+def test_register_and_lds_inversion(ph, n):
+    """n = 65 is the largest tangent block (64 x 64) inverted in registers;
+    n = 70 takes the LDS Gauss-Jordan with row swaps."""
+    wl = W.sparse_quartic(seed=W.SEED_BASE + 91 + n, n=n, npts=2)
+    say(f"affine normal: sparse quartic n={n}")
+    _check(ph, wl.exps, wl.coefs, wl.X, 1e-8, tol=1e-8)
