@@ -20,7 +20,7 @@ reference on sampled outputs; the sparse derivative paths, the
 affine-normal direction of a sparse quartic at a batch of points, and the
 square of a 3 x 3 polynomial matrix.
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -397,7 +397,7 @@ def cpu_baseline(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark measures one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
