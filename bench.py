@@ -3,9 +3,8 @@
 Default workload (the expand + simplify metric): p and q in n=10 variables,
 degree <= 8, 5,000 distinct terms each, N(0,1) coefficients, exponents packed
 at 5 bits per variable -- 25,000,000 raw product terms per step.  A step is
-one poly_mul call (pack, operand sort, raw product generation, stable radix
-sort of (key, raw index) pairs, in-order run sums with zero drop, scan,
-unpack); inputs are resident in HBM before the timed region and the
+one poly_mul call (pack, raw product generation, stable radix sort of
+(key, raw index) pairs, in-order run sums with zero drop, scan, unpack); inputs are resident in HBM before the timed region and the
 output/workspace buffers are allocated once.  `value` is raw product terms
 merged per second.  The roofline object describes the dominant kernel (one
 radix pass), timed live with HIP events the library records around each of
@@ -17,8 +16,9 @@ degree <= 4 monomial set in n=30 variables (46,376 monomials) at 65,536
 points, in plain FP64 (FP64 MFMA) and split BF16 (BF16 MFMA, FP32
 accumulation, FP64 recombination), each with its error against an FP64
 reference on sampled outputs; the sparse derivative paths, the
-affine-normal direction of a sparse quartic at a batch of points, and the
-square of a 3 x 3 polynomial matrix.
+affine-normal direction of a sparse quartic at a batch of points, the
+square of a 3 x 3 polynomial matrix, and the paper's heavy-simplify family
+simplify(p_d^3).
 
 Prints one JSON line.  --gpus N with N > 1 exits: the benchmark runs on one GPU.
 """
@@ -82,6 +82,7 @@ def parse():
     ap.add_argument("--no-deriv", action="store_true", help="skip the quartic derivative workload")
     ap.add_argument("--no-affine", action="store_true", help="skip the affine-normal workload")
     ap.add_argument("--no-mtimes", action="store_true", help="skip the polynomial-matrix product workload")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper's simplify(p_d^3) family")
     ap.add_argument("--affine-n", type=int, default=64)
     ap.add_argument("--affine-points", type=int, default=4096)
     ap.add_argument("--graph", action="store_true", help="also time the times+simplify step as a captured HIP graph")
@@ -343,6 +344,34 @@ def bench_mtimes(args):
             "ms": t * 1e3, "raw_terms_per_s": raw / t}
 
 
+def bench_paper_family(args):
+    """simplify(p_d^3) for p_d = the sum of all monomials of degree <= d in
+    five variables with coefficients 1 (the heavy-simplify family of
+    Section 6.3, d = 2, 3, 4: 21, 56, 126 base monomials), as the two
+    products p_d * p_d and (p_d^2) * p_d; the host reads the size of p_d^2
+    back between them."""
+    import torch
+    import paper_2604_06575_amd as ph
+    import workloads as W
+
+    res = {}
+    for d in (2, 3, 4):
+        e, c = W.all_ones_family(5, d)
+        T = e.shape[0]
+        p = ph.batch_from_numpy([0, T], e, c, n=5, max_exp=d)
+        box = {}
+
+        def step():
+            box["r"] = ph.mul(ph.mul(p, p), p)
+
+        t, wall = time_events(step, 20, 3)
+        res[f"d{d}"] = {"base_terms": T, "terms_out": int(box["r"].row_ptr_host[-1]),
+                        "raw_terms": T * T + int(ph.mul(p, p).row_ptr_host[-1]) * T,
+                        "ms": t * 1e3, "wall_ms": wall * 1e3}
+    torch.cuda.synchronize()
+    return res
+
+
 def bench_graph(args, m):
     """The times+simplify step captured once into a HIP graph and replayed."""
     import torch
@@ -466,6 +495,8 @@ def main():
         line["affine_normal"] = bench_affine(args)
     if not args.no_mtimes:
         line["mtimes"] = bench_mtimes(args)
+    if not args.no_paper:
+        line["paper_family"] = bench_paper_family(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(line), flush=True)
