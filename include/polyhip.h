@@ -224,7 +224,7 @@ poly_status poly_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t
                         poly_csr *out, double zero_tol, void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------- affine normal
- * Affine-normal direction of one polynomial (f->npolys == 1, 2 <= n <= 128)
+ * Affine-normal direction of one polynomial (f->npolys == 1, 2 <= n <= 255)
  * at N points (Section 5, the exact log-determinant method): with
  * g = grad f(x), e = g / |g|, an orthonormal frame Q = [Q_T, e],
  * A = Q_T' Hess f(x) Q_T + reg I, h = Q_T' Hess f(x) e and
@@ -236,7 +236,9 @@ poly_status poly_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t
  * third-order term is contracted per monomial, so no n^3 tensor is formed.
  * Terms of total degree above 12 are not supported (device status
  * POLY_ERR_UNSUPPORTED).  A singular regularized tangent block, or g = 0,
- * gives non-finite output for that point.  X [N*n] row-major; D [N*n]. */
+ * gives non-finite output for that point.  X [N*n] row-major; D [N*n].
+ * Up to n = 128 each point's n x n work matrix lives in LDS; beyond, in the
+ * point's Hessian slot of the workspace (the same results, HBM-bound). */
 poly_status poly_affine_normal_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes);
 poly_status poly_affine_normal(const poly_csr *f, const double *X, int64_t N, double reg,
                                double *D, double *gnorm, void *ws, size_t ws_bytes, void *stream);

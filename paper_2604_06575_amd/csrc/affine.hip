@@ -18,7 +18,9 @@
 //
 // One workgroup per point; H (from the Hessian path), then the tangent
 // block, its inverse (Gauss-Jordan with partial pivoting) and M live in LDS
-// in place.  w is accumulated term by term from each monomial's factor list
+// in place for n <= AN_MAX_N_LDS, and in the point's own Hessian slot in
+// global memory (row stride n, kept coherent within the workgroup by its
+// barriers) beyond that.  w is accumulated term by term from each monomial's factor list
 // (variables in ascending order, degree <= EV_MAX_DEG) with per-point power
 // tables.
 #include <limits.h>
@@ -48,14 +50,16 @@ __device__ inline double block_sum_d(double v, double *scratch)
 }  // namespace
 
 __global__ void __launch_bounds__(AN_THREADS) k_affine_normal(int n, const uint4 *enc, const double *coefs, int64_t T,
-                                                             const double *X, const double *G, const double *H,
+                                                             const double *X, const double *G, double *H,
                                                              double reg, double *D, double *gnorm, int32_t *status)
 {
     extern __shared__ double s_dyn[];
-    const int ld = n + 1;                         // padded row stride of the matrix
+    const bool in_lds = n <= AN_MAX_N_LDS;
+    const int ld = in_lds ? n + 1 : n;            // row stride of the matrix (padded in LDS)
     constexpr int KP = EV_MAX_DEG + 1;            // powers x^0 .. x^EV_MAX_DEG
-    double *S = s_dyn;                            // [n][ld]
-    double *e = S + (size_t)n * ld;               // [n] unit gradient
+    double *Hp = H + (size_t)blockIdx.x * n * n;
+    double *S = in_lds ? s_dyn : Hp;              // [n][ld]
+    double *e = in_lds ? S + (size_t)n * ld : s_dyn;   // [n] unit gradient
     double *v = e + n;                            // [n] Householder vector
     double *t = v + n;                            // [n] H v, then K v
     double *u = t + n;                            // [n] v' K
@@ -76,9 +80,9 @@ __global__ void __launch_bounds__(AN_THREADS) k_affine_normal(int n, const uint4
     constexpr int NW = AN_THREADS / kWave;
     const int64_t pt = blockIdx.x;
     const int m = n - 1;
-    const double *Hp = H + (size_t)pt * n * n;
-    for (int i = ty; i < n; i += NW)
-        for (int j = tx; j < n; j += kWave) S[i * ld + j] = Hp[i * n + j];
+    if (in_lds)
+        for (int i = ty; i < n; i += NW)
+            for (int j = tx; j < n; j += kWave) S[i * ld + j] = Hp[i * n + j];
     for (int i = tid; i < n; i += AN_THREADS) {
         const double xi = X[pt * n + i];
         double p = 1.0;

@@ -497,7 +497,7 @@ void ensure_lds_attrs()
     (void)hipFuncSetAttribute((const void *)k_mul_buckets_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)MB_LDS_LIMIT);
     (void)hipFuncSetAttribute((const void *)k_affine_normal, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)affine_lds_bytes(AN_MAX_N));
+                              (int)affine_lds_bytes(AN_MAX_N_LDS));
     lds_attr_done = true;
 }
 
@@ -1511,7 +1511,7 @@ poly_status poly_affine_normal(const poly_csr *f, const double *X, int64_t N, do
                            (const int64_t *)nullptr);
     TimedLaunch tl(POLY_TIMING_AFFINE, s);
     hipLaunchKernelGGL(k_affine_normal, dim3((unsigned)N), dim3(AN_THREADS), affine_lds_bytes(n), s, n,
-                       (const uint4 *)enc, f->coefs, T, X, (const double *)G, (const double *)H, reg, D, gnorm,
+                       (const uint4 *)enc, f->coefs, T, X, (const double *)G, H, reg, D, gnorm,
                        status);
     tl.done(s);
     LAUNCH_CHECK();

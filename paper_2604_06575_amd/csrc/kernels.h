@@ -201,13 +201,15 @@ __global__ void k_ws_rowptr(int64_t P, uint64_t span, const uint64_t *keys, int6
 
 // affine-normal direction (affine.hip): one workgroup per point
 constexpr int AN_THREADS = 256;
-constexpr int AN_MAX_N = 128;
+constexpr int AN_MAX_N = 255;       // every nvars the batches allow
+constexpr int AN_MAX_N_LDS = 128;   // largest n whose n x (n+1) matrix is kept in LDS
 __host__ __device__ constexpr size_t affine_lds_bytes(int n)
 {
-    return ((size_t)n * (n + 1) + 8 * (size_t)n + (size_t)n * (EV_MAX_DEG + 1)) * sizeof(double);
+    return ((n <= AN_MAX_N_LDS ? (size_t)n * (n + 1) : 0) + 8 * (size_t)n + (size_t)n * (EV_MAX_DEG + 1)) *
+           sizeof(double);
 }
 __global__ void k_affine_normal(int n, const uint4 *enc, const double *coefs, int64_t T, const double *X,
-                                const double *G, const double *H, double reg, double *D, double *gnorm,
+                                const double *G, double *H, double reg, double *D, double *gnorm,
                                 int32_t *status);
 __global__ void k_eval_terms(EvalArgs A, const uint32_t *enc, double *partial, int64_t S);
 __global__ void k_eval_reduce(EvalArgs A, const double *partial, int64_t S);

@@ -62,7 +62,7 @@ def test_strerror_and_host_argument_checks():
     # dense workspace sizes
     assert L.poly_eval_dense_workspace(30, 1000, 10, 10, 1, 9, ctypes.byref(size)) == 1   # nslices out of range
     assert L.poly_eval_dense_workspace(30, 1000, 10, 10, 1, 5, ctypes.byref(size)) == 0
-    # affine normal: one polynomial, 2 <= n <= 128
+    # affine normal: one polynomial, 2 <= n <= 255
     c.nvars = 2
     c.npolys = 2
     assert L.poly_affine_normal_workspace(ctypes.byref(c), 10, ctypes.byref(size)) == 1   # two polynomials
@@ -73,8 +73,9 @@ def test_strerror_and_host_argument_checks():
     assert size.value > 0
     c.nvars = 1
     assert L.poly_affine_normal_workspace(ctypes.byref(c), 10, ctypes.byref(size)) == 1   # no tangent space
-    c.nvars = 129
-    assert L.poly_affine_normal_workspace(ctypes.byref(c), 10, ctypes.byref(size)) == 6   # beyond the LDS tile
+    c.nvars = 255   # past the LDS-resident size the matrix works in the Hessian's workspace slot
+    assert L.poly_affine_normal_workspace(ctypes.byref(c), 10, ctypes.byref(size)) == 0
+    assert size.value >= 10 * 255 * 255 * 8
 
 
 def test_tunables_roundtrip():

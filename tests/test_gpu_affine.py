@@ -108,3 +108,11 @@ def test_register_and_lds_inversion(ph, n):
     wl = W.sparse_quartic(seed=W.SEED_BASE + 91 + n, n=n, npts=2)
     say(f"affine normal: sparse quartic n={n}")
     _check(ph, wl.exps, wl.coefs, wl.X, 1e-8, tol=1e-8)
+
+
+def test_matrix_in_global_memory(ph):
+    """n = 130: past the LDS-resident size, the tangent block is inverted in
+    the point's Hessian slot of the workspace."""
+    wl = W.sparse_quartic(seed=W.SEED_BASE + 221, n=130, npts=1)
+    say("affine normal: sparse quartic n=130")
+    _check(ph, wl.exps, wl.coefs, wl.X, 1e-8, tol=1e-8)
