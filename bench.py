@@ -17,8 +17,8 @@ points, in plain FP64 (FP64 MFMA) and split BF16 (BF16 MFMA, FP32
 accumulation, FP64 recombination), each with its error against an FP64
 reference on sampled outputs; the sparse derivative paths, the
 affine-normal direction of a sparse quartic at a batch of points, the
-square of a 3 x 3 polynomial matrix, and the paper's heavy-simplify family
-simplify(p_d^3).
+square of a 3 x 3 polynomial matrix, the paper's heavy-simplify family
+simplify(p_d^3), and its affine-normal scaling family up to n = 240.
 
 Prints one JSON line.  --gpus N with N > 1 exits: the benchmark runs on one GPU.
 """
@@ -83,6 +83,7 @@ def parse():
     ap.add_argument("--no-affine", action="store_true", help="skip the affine-normal workload")
     ap.add_argument("--no-mtimes", action="store_true", help="skip the polynomial-matrix product workload")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's simplify(p_d^3) family")
+    ap.add_argument("--no-affine-scaling", action="store_true", help="skip the affine-normal scaling family")
     ap.add_argument("--affine-n", type=int, default=64)
     ap.add_argument("--affine-points", type=int, default=4096)
     ap.add_argument("--graph", action="store_true", help="also time the times+simplify step as a captured HIP graph")
@@ -320,6 +321,32 @@ def bench_affine(args):
             "all_finite": finite, "regularization": 1e-8}
 
 
+def bench_affine_scaling(args):
+    """The paper's exact log-det scaling family (sparse quartics of support 3
+    with 4n monomials) at n = 20, 40, 80, 160 and 240, 256 points each: the
+    work matrix sits in registers (n <= 65), LDS (n <= 128) or the
+    workspace (larger n)."""
+    import torch
+    import paper_2604_06575_amd as ph
+    import workloads as W
+
+    res = {}
+    for n in (20, 40, 80, 160, 240):
+        wl = W.sparse_quartic(seed=W.SEED_BASE + 300 + n, n=n, npts=256)
+        N = wl.X.shape[0]
+        b = ph.batch_from_numpy([0, wl.exps.shape[0]], wl.exps, wl.coefs, n=n, max_exp=4)
+        X = torch.from_numpy(wl.X).cuda()
+        ws = torch.empty(ph.affine_normal_workspace(b, N), dtype=torch.uint8, device="cuda")
+        step = lambda: ph.affine_normal(b, X, reg=1e-8, ws=ws)  # noqa: E731
+        D, _ = ph.affine_normal(b, X, reg=1e-8, ws=ws, check=True)
+        t, _ = time_events(step, 3, 1)
+        k_ms, _ = kernel_ms(ph.TIMING_AFFINE, step, 3)
+        res[f"n{n}"] = {"points": N, "ms": t * 1e3, "points_per_s": N / t, "kernel_ms": k_ms,
+                        "all_finite": bool(torch.isfinite(D).all().item())}
+        del ws
+    return res
+
+
 def bench_mtimes(args):
     """A^2 for a 3 x 3 polynomial matrix whose entries are random degree-4
     polynomials in n=8 with 300 distinct monomials (N(0,1) coefficients):
@@ -497,6 +524,8 @@ def main():
         line["mtimes"] = bench_mtimes(args)
     if not args.no_paper:
         line["paper_family"] = bench_paper_family(args)
+    if not args.no_affine and not args.no_affine_scaling:
+        line["affine_scaling"] = bench_affine_scaling(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(line), flush=True)
