@@ -151,3 +151,28 @@ def test_bench_workload_full_size(ph):
     A = [W.random_poly(rng, n, d, terms, integer=False, distinct=True) for _ in range(I * I)]
     say("mtimes: 3x3 A^2, 300-term entries (benchmark workload)")
     _case(ph, A, A, I, I, I, n, d)
+
+
+def test_long_inner_dimension(ph):
+    """1 x 20 by 20 x 2: each output entry gathers 20 partial products
+    (18,000 raw terms, so the device-wide simplify takes them)."""
+    rng = W.rng_for(3720)
+    n, d = 4, 3
+    A = [W.random_poly(rng, n, d, 30, integer=False) for _ in range(20)]
+    B = [W.random_poly(rng, n, d, 30, integer=False) for _ in range(40)]
+    say("mtimes: 1x20 by 20x2")
+    _case(ph, A, B, 1, 20, 2, n, d)
+
+
+def test_sum_and_prod_large_entries(ph):
+    """sum along a row of four 3,000-term entries (12,000 terms per output
+    entry, device-wide simplify) and prod down a column of two (each entry
+    simplified to at most 210 monomials first, then one batched times)."""
+    rng = W.rng_for(3721)
+    n, d, R, C = 6, 4, 2, 4
+    A = [W.random_poly(rng, n, d, 3000, integer=False) for _ in range(R * C)]
+    a, ra = _batch(ph, A, n, d)
+    say("msum: 2x4 of 3,000-term entries along dim 2")
+    _same(ph, ph.msum(a, R, C, 2), oracle.msum(*ra, R, C, 2, n=n))
+    say("mprod: 2x4 of 3,000-term entries along dim 1")
+    _same(ph, ph.mprod(a, R, C, 1), oracle.mprod(*ra, R, C, 1, n=n))
