@@ -223,6 +223,15 @@ poly_status poly_mtimes_workspace(const poly_csr *A, const poly_csr *B, int64_t 
 poly_status poly_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t K, int64_t J,
                         poly_csr *out, double zero_tol, void *ws, size_t ws_bytes, void *stream);
 
+/* -------------------------------------------------------- concatenation
+ * out = the entries of ins[0], ins[1], ..., ins[nin-1] in order (a
+ * polynomial array built from the arrays of Section 3.1; the substitution
+ * of Section 3.4 gathers its power tables this way).  All inputs share
+ * out->nvars and have max_exp <= out->max_exp; out->npolys == sum of npolys;
+ * out->capacity >= total input terms (host-checked, POLY_ERR_CAPACITY).
+ * Terms are copied unchanged; no workspace. */
+poly_status poly_concat(const poly_csr *const *ins, int32_t nin, poly_csr *out, void *stream);
+
 /* ------------------------------------------------------- affine normal
  * Affine-normal direction of one polynomial (f->npolys == 1, 2 <= n <= 255)
  * at N points (Section 5, the exact log-determinant method): with

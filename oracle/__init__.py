@@ -9,7 +9,8 @@ adds a brute-force simplify built on a Python dict as a second, independent
 data structure for self-checks, the affine-normal direction of Section 5
 written out in NumPy from the symbolic derivatives (the reference route), and
 the polynomial-matrix operations of Section 3.3 (mtimes, sum and prod along a
-dimension) composed from simplify and times.
+dimension) and the substitution of Section 3.4, composed from simplify and
+times.
 
 Each function states the passage of the paper it follows; conventions where
 the paper is silent are documented in ``poly_oracle.c``.
@@ -486,3 +487,39 @@ def mprod(rp, e, c, R: int, C: int, dim: int, tol: float = 0.0, n: int | None = 
             acc = mul(acc[0], acc[1], *simplify(*ents[q], tol, n), tol=tol, n=n)
         outs.append(acc)
     return _csr(outs, n)
+
+
+def subs(pe, pc, q_rp, q_e, q_c, m: int, tol: float = 0.0):
+    """Substitution p(q_1(z), ..., q_n(z)) (Section 3.4; the worked example
+    u(z1 + 1, z2)): p is one polynomial in n variables (exponent rows pe,
+    coefficients pc), q a batch of n polynomials in m variables.  q_i^0 = 1,
+    q_i^1 = q_i and q_i^k = simplify(q_i^(k-1) q_i); each term t forms
+    acc = 1, then acc = simplify(acc * simplify(q_i^(e_ti))) for i = 1..n;
+    the result is simplify of the terms' acc, each coefficient multiplied by
+    c_t, concatenated in term order."""
+    pe = np.asarray(pe, np.uint8)
+    n = pe.shape[1]
+    pc = _f64(pc)
+    qs = _entries(q_rp, q_e, q_c, m)
+    one = (np.zeros((1, m), np.uint8), np.ones(1))
+
+    def power(i, k):
+        if k == 0:
+            return one
+        acc = qs[i]
+        for _ in range(k - 1):
+            acc = mul(acc[0], acc[1], qs[i][0], qs[i][1], tol=tol, n=m)
+        return acc
+
+    es, cs = [], []
+    for t in range(pe.shape[0]):
+        acc = one
+        for i in range(n):
+            f = simplify(*power(i, int(pe[t, i])), tol, m)
+            acc = mul(acc[0], acc[1], f[0], f[1], tol=tol, n=m)
+        es.append(acc[0])
+        cs.append(pc[t] * acc[1])
+    if not es:
+        return np.zeros((0, m), np.uint8), np.zeros(0)
+    e, c = np.vstack(es), np.concatenate(cs)
+    return simplify(e, c, tol, m) if e.shape[0] else (e, c)

@@ -16,7 +16,8 @@ import torch
 
 __all__ = [
     "Batch", "PolyError", "PolyEval", "batch_from_numpy", "batch_to_numpy", "mul", "simplify", "jacobian",
-    "eval", "grad", "hess", "eval_backward", "eval_dense", "mtimes", "mpower", "msum", "mprod", "affine_normal",
+    "eval", "grad", "hess", "eval_backward", "eval_dense", "mtimes", "mpower", "msum", "mprod", "concat", "subs",
+    "affine_normal",
     "library_path", "lib",
     "POLY_FP64", "POLY_SPLIT_BF16",
 ]
@@ -41,6 +42,7 @@ EXPORTS = [
     "poly_eval_dense_workspace", "poly_eval_dense",
     "poly_affine_normal_workspace", "poly_affine_normal",
     "poly_mtimes_workspace", "poly_mtimes",
+    "poly_concat",
 ]
 
 
@@ -109,6 +111,7 @@ def lib():
         "poly_mtimes_workspace": ([pcsr, pcsr, i64, i64, i64, psz, ctypes.POINTER(i64)], i32),
         "poly_mtimes": ([pcsr, pcsr, i64, i64, i64, pcsr, d, P, ctypes.c_size_t, P], i32),
         "poly_affine_normal": ([pcsr, P, i64, d, P, P, P, ctypes.c_size_t, P], i32),
+        "poly_concat": ([ctypes.POINTER(pcsr), i32, pcsr, P], i32),
         "poly_eval_dense": ([i32, i64, P, i32, i64, P, i64, P, P, i32, i32, P, ctypes.c_size_t, P], i32),
     }
     for name, (args, res) in sig.items():
@@ -396,6 +399,59 @@ def mprod(a: Batch, R: int, C: int, dim: int, tol: float = 0.0) -> Batch:
     for k in range(1, length):
         acc = mul(acc, line(k), tol)
     return acc
+
+
+def concat(batches, max_exp: int | None = None) -> Batch:
+    """The entries of several batches (same n) in order, as one batch."""
+    assert batches
+    n = batches[0].n
+    me = max(b.max_exp for b in batches) if max_exp is None else max_exp
+    P = sum(b.npolys for b in batches)
+    T = sum(b.nterms for b in batches)
+    dev = batches[0].coefs.device
+    out = _empty_out(n, P, T, me, dev)
+    csrs = [b.csr() for b in batches]
+    arr = (ctypes.POINTER(PolyCSR) * len(csrs))(*[ctypes.pointer(c) for c in csrs])
+    _check(lib().poly_concat(arr, len(csrs), ctypes.byref(out.csr()), _stream()), "poly_concat")
+    rp = np.zeros(P + 1, np.int64)
+    o = 0
+    for b in batches:
+        rp[o:o + b.npolys + 1] = b.row_ptr_host[:b.npolys + 1] + rp[o]
+        o += b.npolys
+    out.row_ptr_host = rp
+    return out
+
+
+def subs(p: Batch, q: Batch, tol: float = 0.0) -> Batch:
+    """Substitution p(q_1, ..., q_n) (Section 3.4): p is one polynomial in n
+    variables, q a batch of n polynomials in m variables.  Powers q_i^k are
+    left folds of times, a term's product runs over i = 1..n (acc times the
+    simplified q_i^(e_i)), and the result is simplify of the terms' products,
+    each scaled by its coefficient, in term order.  Every step is a library
+    call: batched times for the powers and products, one concatenation for
+    the power table, products with 0/1 selectors (mtimes) to gather each
+    term's factor, and a product with the coefficient row for the sum."""
+    assert p.npolys == 1 and q.npolys == p.n
+    n, m = p.n, q.n
+    dev = q.coefs.device
+    _, E, C = batch_to_numpy(p)
+    T = E.shape[0]
+    kmax = int(E.max()) if E.size else 0
+    pows = [q]
+    for _ in range(2, kmax + 1):
+        pows.append(mul(pows[-1], q, tol))
+    one = batch_from_numpy([0, 1], np.zeros((1, m), np.uint8), np.ones(1), n=m, max_exp=0, device=dev)
+    table = concat([one] + pows)
+    L = table.npolys
+    slot = lambda i, k: 0 if k == 0 else 1 + (k - 1) * n + i  # noqa: E731
+    acc = batch_from_numpy(np.arange(T + 1, dtype=np.int64), np.zeros((T, m), np.uint8), np.ones(T), n=m,
+                           max_exp=0, device=dev)
+    for i in range(n):
+        pick = _selector(m, T, L, lambda t, j: j == slot(i, int(E[t, i])), dev)
+        acc = mul(acc, mtimes(pick, table, T, L, 1, tol), tol)
+    crow = batch_from_numpy(np.arange(T + 1, dtype=np.int64), np.zeros((T, m), np.uint8), C, n=m, max_exp=0,
+                            device=dev)
+    return mtimes(crow, acc, 1, T, 1, tol)
 
 
 def jacobian(b: Batch, trim: bool = True) -> Batch:

@@ -1472,6 +1472,38 @@ poly_status poly_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t
     return run_simplify(&R, out, zero_tol, ws, m.sp, s);
 }
 
+poly_status poly_concat(const poly_csr *const *ins, int32_t nin, poly_csr *out, void *stream)
+{
+    if (nin < 0 || (nin > 0 && !ins)) return POLY_ERR_ARG;
+    poly_status st = check_csr(out, false);
+    if (st != POLY_OK) return st;
+    int64_t P = 0, T = 0;
+    for (int32_t i = 0; i < nin; ++i) {
+        if ((st = check_csr(ins[i], true)) != POLY_OK) return st;
+        if (ins[i]->nvars != out->nvars || ins[i]->max_exp > out->max_exp) return POLY_ERR_ARG;
+        P += ins[i]->npolys;
+        T += total_terms(ins[i]);
+    }
+    if (out->npolys != P) return POLY_ERR_ARG;
+    if (T > out->capacity) return POLY_ERR_CAPACITY;
+    hipStream_t s = (hipStream_t)stream;
+    clear_u64((unsigned long long *)out->row_ptr, 1, s);   // row_ptr[0] = 0, also when nothing is copied
+    const int n = out->nvars;
+    int64_t eo = 0, to = 0;
+    for (int32_t i = 0; i < nin; ++i) {
+        const poly_csr *c = ins[i];
+        const int64_t Ti = total_terms(c);
+        const int64_t work = std::max<int64_t>(c->npolys + 1, Ti * n);
+        hipLaunchKernelGGL(k_concat_copy, dim3(std::min<unsigned>(grid1(work, 256), 4096u)), dim3(256), 0, s,
+                           (const int64_t *)c->row_ptr, c->exps, c->coefs, c->npolys, Ti, n, eo, to, out->row_ptr,
+                           out->exps, out->coefs);
+        eo += c->npolys;
+        to += Ti;
+    }
+    LAUNCH_CHECK();
+    return POLY_OK;
+}
+
 poly_status poly_affine_normal_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)
 {
     poly_status st = check_affine(f, nullptr, 0, nullptr, 0.0);

@@ -188,6 +188,10 @@ __global__ void k_mat_keys(const int64_t *a_rp, const uint64_t *ka, const double
                            const int64_t *r_rp, int64_t R, uint64_t span, uint64_t *keys, uint32_t *vals,
                            double *r_c);
 
+__global__ void k_concat_copy(const int64_t *rp, const uint8_t *exps, const double *coefs, int64_t P, int64_t T,
+                              int n, int64_t entry_off, int64_t term_off, int64_t *out_rp, uint8_t *out_exps,
+                              double *out_coefs);
+
 // device-wide simplify of batches with large polynomials (wide.hip)
 __global__ void k_ws_keys(const uint8_t *exps, int64_t T, int n, uint32_t radix, int max_exp,
                           const int64_t *row_ptr, int64_t P, uint64_t span, uint64_t *keys, uint32_t *vals,

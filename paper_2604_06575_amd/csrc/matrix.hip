@@ -96,3 +96,23 @@ __global__ void k_mat_keys(const int64_t *__restrict__ a_rp, const uint64_t *__r
 }
 
 }  // namespace polyhip
+
+namespace polyhip {
+
+// One input batch of a concatenation: its P entries become output entries
+// entry_off .. entry_off + P - 1, its T terms output terms term_off .. ;
+// row pointers shifted by term_off (row_ptr[entry_off + P] is the next
+// input's first pointer, written with the same value by both).
+__global__ void k_concat_copy(const int64_t *__restrict__ rp, const uint8_t *__restrict__ exps,
+                              const double *__restrict__ coefs, int64_t P, int64_t T, int n, int64_t entry_off,
+                              int64_t term_off, int64_t *__restrict__ out_rp, uint8_t *__restrict__ out_exps,
+                              double *__restrict__ out_coefs)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t p = i0; p <= P; p += stride) out_rp[entry_off + p] = rp[p] + term_off;
+    for (int64_t t = i0; t < T; t += stride) out_coefs[term_off + t] = coefs[t];
+    for (int64_t b = i0; b < T * n; b += stride) out_exps[term_off * n + b] = exps[b];
+}
+
+}  // namespace polyhip

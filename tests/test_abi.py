@@ -22,7 +22,7 @@ def test_library_exports_every_declared_symbol():
         pytest.skip("library not built")
     L = ctypes.CDLL(ph.library_path())
     syms = header_symbols()
-    assert len(syms) == 26
+    assert len(syms) == 27
     for s in syms:
         assert hasattr(L, s), s
     assert sorted(ph.EXPORTS) == syms
@@ -76,6 +76,29 @@ def test_strerror_and_host_argument_checks():
     c.nvars = 255   # past the LDS-resident size the matrix works in the Hessian's workspace slot
     assert L.poly_affine_normal_workspace(ctypes.byref(c), 10, ctypes.byref(size)) == 0
     assert size.value >= 10 * 255 * 255 * 8
+
+
+def test_concat_host_checks():
+    import paper_2604_06575_amd as ph
+    if not os.path.exists(ph.library_path()):
+        pytest.skip("library not built")
+    L = ph.lib()
+    rp = np.array([0, 2], np.int64)
+    a = ph.PolyCSR()
+    a.nvars, a.max_exp, a.npolys, a.capacity = 2, 3, 1, 2
+    a.row_ptr_host = rp.ctypes.data_as(ctypes.c_void_p)
+    a.row_ptr = a.exps = a.coefs = ctypes.c_void_p(1)
+    out = ph.PolyCSR()
+    out.nvars, out.max_exp, out.npolys, out.capacity = 2, 3, 2, 4
+    out.row_ptr = out.exps = out.coefs = ctypes.c_void_p(1)
+    ins = (ctypes.POINTER(ph.PolyCSR) * 2)(ctypes.pointer(a), ctypes.pointer(a))
+    out.npolys = 3
+    assert L.poly_concat(ins, 2, ctypes.byref(out), None) == 1     # entry count mismatch
+    out.npolys, out.capacity = 2, 3
+    assert L.poly_concat(ins, 2, ctypes.byref(out), None) == 4     # capacity below the 4 terms
+    out.capacity, out.max_exp = 4, 2
+    assert L.poly_concat(ins, 2, ctypes.byref(out), None) == 1     # max_exp below an input's
+    assert L.poly_concat(ins, -1, ctypes.byref(out), None) == 1
 
 
 def test_tunables_roundtrip():

@@ -176,3 +176,45 @@ def test_sum_and_prod_large_entries(ph):
     _same(ph, ph.msum(a, R, C, 2), oracle.msum(*ra, R, C, 2, n=n))
     say("mprod: 2x4 of 3,000-term entries along dim 1")
     _same(ph, ph.mprod(a, R, C, 1), oracle.mprod(*ra, R, C, 1, n=n))
+
+
+def test_concat(ph):
+    """Concatenation copies every entry unchanged, empty batches included."""
+    rng = W.rng_for(3730)
+    n = 3
+    parts = [[W.random_poly(rng, n, 3, int(rng.integers(0, 20)), integer=False) for _ in range(k)]
+             for k in (3, 0, 5, 1)]
+    bs = [_batch(ph, ps, n, 3)[0] for ps in parts]
+    say("concat: four batches")
+    got = ph.concat(bs)
+    _same(ph, got, W.csr_from_list([p for ps in parts for p in ps], n))
+
+
+def test_subs_paper_example(ph):
+    """Section 3.4: u(z1 + 1, z2) = 3 + 6 z1 + 3 z1^2 + 5 z2."""
+    g = json.load(open(os.path.join(HERE, "golden", "worked_examples.json")))["W8_substitution"]
+    n = g["n"]
+    tp = lambda e: (np.array([t[1] for t in e], np.uint8).reshape(-1, n), np.array([t[0] for t in e], float))  # noqa
+    u = tp(g["u"])
+    q = [tp(g["z1_plus_1"]), (np.array([[0, 1]], np.uint8), np.array([1.0]))]
+    pb, _ = _batch(ph, [u], n, 2)
+    qb, rq = _batch(ph, q, n, 1)
+    say("subs: Section 3.4 example")
+    got = ph.subs(pb, qb)
+    _same(ph, got, W.csr_from_list([oracle.subs(*u, *rq, n)], n))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_subs_random(ph, seed):
+    """p of 15 terms in three variables (exponents up to 3) with two-variable
+    substitutes of four terms; Gaussian coefficients, tol on one seed."""
+    rng = W.rng_for(3740 + seed)
+    n, m = 3, 2
+    p = W.random_poly(rng, n, 3, 15, integer=False)
+    q = [W.random_poly(rng, m, 2, 4, integer=False) for _ in range(n)]
+    tol = 0.25 if seed == 2 else 0.0
+    pb, _ = _batch(ph, [p], n, 3)
+    qb, rq = _batch(ph, q, m, 2)
+    say(f"subs: random seed={seed}")
+    got = ph.subs(pb, qb, tol=tol)
+    _same(ph, got, W.csr_from_list([oracle.subs(*p, *rq, m, tol=tol)], m))

@@ -611,3 +611,40 @@ def test_msum_mprod_degenerate():
     for f in (oracle.msum, oracle.mprod):
         got = f(rp, E, C, 3, 1, 2, n=n)
         assert all(np.array_equal(x, y) for x, y in zip(got, want))
+
+
+def test_subs_paper_example(golden):
+    """Section 3.4: u = 3 x1^2 + 5 x2, u(z1 + 1, z2) = 3 + 6 z1 + 3 z1^2 + 5 z2."""
+    g = golden["W8_substitution"]
+    n = g["n"]
+    ue, uc = poly_from_json(g["u"], n)
+    q = [poly_from_json(g["z1_plus_1"], n), (np.array([[0, 1]], np.uint8), np.array([1.0]))]
+    rp, E, C = _mat(q, n)
+    e, c = oracle.subs(ue, uc, rp, E, C, n)
+    assert as_termset(e, c) == as_termset(*poly_from_json(g["result"], n))
+
+
+def test_subs_identity_and_values():
+    """Substituting x_i for x_i gives simplify(p) bitwise; at small integer
+    points with integer coefficients, subs(p, q)(z) = p(q_1(z), ..., q_n(z))
+    exactly (values taken directly, not through the oracle)."""
+    rng = W.rng_for(3430)
+    n, m = 3, 2
+    pe, pc = W.random_poly(rng, n, 3, 12, integer=False)
+    ids = [(np.eye(n, dtype=np.uint8)[i:i + 1], np.ones(1)) for i in range(n)]
+    rp, E, C = _mat(ids, n)
+    e, c = oracle.subs(pe, pc, rp, E, C, n)
+    se, sc = oracle.simplify(pe, pc, n=n)
+    assert np.array_equal(e, se) and c.view(np.uint64).tolist() == sc.view(np.uint64).tolist()
+    pe, pc = W.random_poly(rng, n, 3, 8)
+    q = [W.random_poly(rng, m, 2, 3) for _ in range(n)]
+    rp, E, C = _mat(q, m)
+    e, c = oracle.subs(pe, pc, rp, E, C, m)
+    Z = rng.integers(-2, 3, size=(4, m)).astype(np.float64)
+
+    def val(ee, cc, x):
+        return sum(ci * np.prod(x ** ei.astype(np.float64)) for ei, ci in zip(ee, cc))
+
+    for z in Z:
+        qz = np.array([val(*qi, z) for qi in q])
+        assert val(e, c, z) == val(pe, pc, qz)
