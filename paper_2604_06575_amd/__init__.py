@@ -210,6 +210,12 @@ class Batch:
         return int(self.row_ptr_host[-1])
 
     def csr(self) -> PolyCSR:
+        # the library trusts these sizes: check them against the tensors first
+        if (self.exps.dtype != torch.uint8 or self.coefs.dtype != torch.float64 or
+                self.row_ptr.dtype != torch.int64 or self.row_ptr.numel() != self.row_ptr_host.shape[0] or
+                self.exps.numel() < self.coefs.shape[0] * self.n):
+            raise ValueError("inconsistent batch tensors (uint8 exps [cap, n], float64 coefs [cap], "
+                             "int64 row_ptr [P+1])")
         c = PolyCSR()
         c.nvars = self.n
         c.max_exp = self.max_exp
@@ -346,7 +352,8 @@ def mtimes(a: Batch, b: Batch, I: int, K: int, J: int, tol: float = 0.0, trim: b
 def mpower(a: Batch, I: int, p: int, tol: float = 0.0) -> Batch:
     """a^p for a square I x I polynomial matrix (p >= 1): p - 1 products
     a * (a * (... a)), each one library call."""
-    assert p >= 1
+    if p < 1:
+        raise ValueError("mpower needs p >= 1")
     r = a
     for _ in range(p - 1):
         r = mtimes(a, r, I, I, I, tol)
@@ -403,7 +410,8 @@ def mprod(a: Batch, R: int, C: int, dim: int, tol: float = 0.0) -> Batch:
 
 def concat(batches, max_exp: int | None = None) -> Batch:
     """The entries of several batches (same n) in order, as one batch."""
-    assert batches
+    if not batches:
+        raise ValueError("concat needs at least one batch")
     n = batches[0].n
     me = max(b.max_exp for b in batches) if max_exp is None else max_exp
     P = sum(b.npolys for b in batches)
@@ -431,7 +439,8 @@ def subs(p: Batch, q: Batch, tol: float = 0.0) -> Batch:
     call: batched times for the powers and products, one concatenation for
     the power table, products with 0/1 selectors (mtimes) to gather each
     term's factor, and a product with the coefficient row for the sum."""
-    assert p.npolys == 1 and q.npolys == p.n
+    if p.npolys != 1 or q.npolys != p.n:
+        raise ValueError("subs takes one polynomial in n variables and a batch of n substitutes")
     n, m = p.n, q.n
     dev = q.coefs.device
     _, E, C = batch_to_numpy(p)
@@ -469,10 +478,16 @@ def jacobian(b: Batch, trim: bool = True) -> Batch:
     return _finish(out, ws, "poly_jacobian", trim)
 
 
+def _check_points(X: torch.Tensor, n: int):
+    # the kernels index X as [N, n] float64: reject anything else before a launch
+    if X.dtype != torch.float64 or X.dim() != 2 or X.shape[1] != n:
+        raise ValueError(f"points must be float64 [N, {n}], got {X.dtype} {tuple(X.shape)}")
+
+
 def _eval_like(fname: str, b: Batch, X: torch.Tensor, shape, check: bool):
     L = lib()
     X = X.contiguous()
-    assert X.dtype == torch.float64 and X.dim() == 2 and X.shape[1] == b.n
+    _check_points(X, b.n)
     N = X.shape[0]
     cin = b.csr()
     ws_bytes = ctypes.c_size_t()
@@ -527,7 +542,7 @@ def affine_normal(b: Batch, X: torch.Tensor, reg: float = 1e-6, check: bool = Fa
     (D [N, n], |grad f| [N])."""
     L = lib()
     X = X.contiguous()
-    assert X.dtype == torch.float64 and X.dim() == 2 and X.shape[1] == b.n
+    _check_points(X, b.n)
     N = X.shape[0]
     cin = b.csr()
     ws_bytes = ctypes.c_size_t()
@@ -568,12 +583,18 @@ def eval_dense(basis: torch.Tensor, C: torch.Tensor, X: torch.Tensor, prec: int 
     K, n = basis.shape
     P = C.shape[0]
     N = X.shape[0]
-    assert C.shape[1] == K and X.shape[1] == n
+    if basis.dtype != torch.uint8:
+        raise ValueError("basis must be uint8 [K, n]")
+    if C.dim() != 2 or C.shape[1] != K or C.dtype != torch.float64:
+        raise ValueError(f"C must be float64 [P, {K}]")
+    _check_points(X, n)
     need = eval_dense_workspace(n, K, P, N, prec, nslices)
     if ws is None or ws.numel() < need:
         ws = _workspace(need, C.device)
     if Y is None:
         Y = torch.empty((P, N), dtype=torch.float64, device=C.device)
+    elif Y.dtype != torch.float64 or not Y.is_contiguous() or tuple(Y.shape) != (P, N):
+        raise ValueError(f"Y must be contiguous float64 [{P}, {N}]")
     me = int(max_exp) if max_exp is not None else 255
     _check(L.poly_eval_dense(n, K, _ptr(basis), me, P, _ptr(C), N, _ptr(X), _ptr(Y), prec, nslices,
                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "poly_eval_dense")

@@ -142,3 +142,26 @@ def test_timing_hooks_host_checks():
     # nothing recorded yet: zero launches, no device access
     assert L.poly_timing_read(0, ctypes.byref(ms), ctypes.byref(cnt)) == 0
     assert cnt.value == 0 and ms.value == 0.0
+
+
+def test_binding_rejects_bad_shapes():
+    """The binding checks tensor shapes and dtypes before any launch (the
+    library trusts the sizes it is given)."""
+    import torch
+    import paper_2604_06575_amd as ph
+    if not os.path.exists(ph.library_path()):
+        pytest.skip("library not built")
+    b = ph.Batch(2, 2, torch.zeros(2, dtype=torch.int64), np.array([0, 1]), torch.zeros((1, 2), dtype=torch.uint8),
+                 torch.zeros(1, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        ph.eval(b, torch.zeros((3, 5), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        ph.eval(b, torch.zeros((3, 2), dtype=torch.float32))
+    bad = ph.Batch(2, 2, torch.zeros(2, dtype=torch.int64), np.array([0, 1]), torch.zeros((1, 1), dtype=torch.uint8),
+                   torch.zeros(1, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        bad.csr()
+    with pytest.raises(ValueError):
+        ph.mpower(b, 1, 0)
+    with pytest.raises(ValueError):
+        ph.subs(b, b)
