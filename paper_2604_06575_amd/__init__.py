@@ -171,6 +171,19 @@ def _check(code: int, where: str):
         raise PolyError(code, where)
 
 
+def _check_device(name: str, t: torch.Tensor, device=None):
+    """Every tensor handed to the library is read or written by HIP kernels
+    through its raw pointer: it must live on a GPU (the same one as the rest
+    of the call) and be contiguous, or the kernels would read a host address
+    or the wrong layout."""
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor, got device {t.device}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the other operands on {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
@@ -210,12 +223,16 @@ class Batch:
         return int(self.row_ptr_host[-1])
 
     def csr(self) -> PolyCSR:
-        # the library trusts these sizes: check them against the tensors first
+        # the library trusts these sizes and dereferences these pointers on the
+        # device: check dtypes, sizes, device and layout first
         if (self.exps.dtype != torch.uint8 or self.coefs.dtype != torch.float64 or
                 self.row_ptr.dtype != torch.int64 or self.row_ptr.numel() != self.row_ptr_host.shape[0] or
-                self.exps.numel() < self.coefs.shape[0] * self.n):
+                self.coefs.dim() != 1 or self.exps.numel() < self.coefs.shape[0] * self.n):
             raise ValueError("inconsistent batch tensors (uint8 exps [cap, n], float64 coefs [cap], "
                              "int64 row_ptr [P+1])")
+        _check_device("row_ptr", self.row_ptr)
+        _check_device("exps", self.exps, self.row_ptr.device)
+        _check_device("coefs", self.coefs, self.row_ptr.device)
         c = PolyCSR()
         c.nvars = self.n
         c.max_exp = self.max_exp
@@ -446,18 +463,29 @@ def subs(p: Batch, q: Batch, tol: float = 0.0) -> Batch:
     _, E, C = batch_to_numpy(p)
     T = E.shape[0]
     kmax = int(E.max()) if E.size else 0
+    qe = q.max_exp
+    # Declared exponent bounds follow what the products can reach, not the sum
+    # of the factors' declarations: q_i^k stays within k * max_exp(q), a
+    # term's partial product over variables 1..i within (its degree) *
+    # max_exp(q).  (The device still checks every exponent against them.)
     pows = [q]
-    for _ in range(2, kmax + 1):
-        pows.append(mul(pows[-1], q, tol))
+    for k in range(2, kmax + 1):
+        pk = mul(pows[-1], q, tol)
+        pk.max_exp = min(pk.max_exp, k * qe)
+        pows.append(pk)
     one = batch_from_numpy([0, 1], np.zeros((1, m), np.uint8), np.ones(1), n=m, max_exp=0, device=dev)
-    table = concat([one] + pows)
+    table = concat([one] + pows, max_exp=min(255, max(kmax, 1) * qe))
     L = table.npolys
     slot = lambda i, k: 0 if k == 0 else 1 + (k - 1) * n + i  # noqa: E731
     acc = batch_from_numpy(np.arange(T + 1, dtype=np.int64), np.zeros((T, m), np.uint8), np.ones(T), n=m,
                            max_exp=0, device=dev)
+    partial_deg = np.cumsum(E.astype(np.int64), axis=1) if T else np.zeros((0, n), np.int64)
     for i in range(n):
         pick = _selector(m, T, L, lambda t, j: j == slot(i, int(E[t, i])), dev)
-        acc = mul(acc, mtimes(pick, table, T, L, 1, tol), tol)
+        factor = mtimes(pick, table, T, L, 1, tol)
+        factor.max_exp = min(factor.max_exp, int(E[:, i].max()) * qe if T else 0)
+        acc = mul(acc, factor, tol)
+        acc.max_exp = min(acc.max_exp, int(partial_deg[:, i].max()) * qe if T else 0)
     crow = batch_from_numpy(np.arange(T + 1, dtype=np.int64), np.zeros((T, m), np.uint8), C, n=m, max_exp=0,
                             device=dev)
     return mtimes(crow, acc, 1, T, 1, tol)
@@ -478,18 +506,19 @@ def jacobian(b: Batch, trim: bool = True) -> Batch:
     return _finish(out, ws, "poly_jacobian", trim)
 
 
-def _check_points(X: torch.Tensor, n: int):
+def _check_points(X: torch.Tensor, n: int, device=None):
     # the kernels index X as [N, n] float64: reject anything else before a launch
     if X.dtype != torch.float64 or X.dim() != 2 or X.shape[1] != n:
         raise ValueError(f"points must be float64 [N, {n}], got {X.dtype} {tuple(X.shape)}")
+    _check_device("points", X, device)
 
 
 def _eval_like(fname: str, b: Batch, X: torch.Tensor, shape, check: bool):
     L = lib()
     X = X.contiguous()
-    _check_points(X, b.n)
-    N = X.shape[0]
     cin = b.csr()
+    _check_points(X, b.n, b.coefs.device)
+    N = X.shape[0]
     ws_bytes = ctypes.c_size_t()
     _check(getattr(L, fname + "_workspace")(ctypes.byref(cin), N, ctypes.byref(ws_bytes)), fname + "_workspace")
     ws = _workspace(ws_bytes.value, b.coefs.device)
@@ -522,8 +551,12 @@ def eval_backward(b: Batch, X: torch.Tensor, gY: torch.Tensor, want_dX: bool = T
     L = lib()
     X = X.contiguous()
     gY = gY.contiguous()
-    N = X.shape[0]
     cin = b.csr()
+    _check_points(X, b.n, b.coefs.device)
+    N = X.shape[0]
+    if gY.dtype != torch.float64 or tuple(gY.shape) != (b.npolys, N):
+        raise ValueError(f"gY must be float64 [{b.npolys}, {N}], got {gY.dtype} {tuple(gY.shape)}")
+    _check_device("gY", gY, b.coefs.device)
     ws_bytes = ctypes.c_size_t()
     _check(L.poly_eval_backward_workspace(ctypes.byref(cin), N, ctypes.byref(ws_bytes)),
            "poly_eval_backward_workspace")
@@ -542,9 +575,9 @@ def affine_normal(b: Batch, X: torch.Tensor, reg: float = 1e-6, check: bool = Fa
     (D [N, n], |grad f| [N])."""
     L = lib()
     X = X.contiguous()
-    _check_points(X, b.n)
-    N = X.shape[0]
     cin = b.csr()
+    _check_points(X, b.n, b.coefs.device)
+    N = X.shape[0]
     ws_bytes = ctypes.c_size_t()
     _check(L.poly_affine_normal_workspace(ctypes.byref(cin), N, ctypes.byref(ws_bytes)),
            "poly_affine_normal_workspace")
@@ -587,7 +620,9 @@ def eval_dense(basis: torch.Tensor, C: torch.Tensor, X: torch.Tensor, prec: int 
         raise ValueError("basis must be uint8 [K, n]")
     if C.dim() != 2 or C.shape[1] != K or C.dtype != torch.float64:
         raise ValueError(f"C must be float64 [P, {K}]")
-    _check_points(X, n)
+    _check_device("C", C)
+    _check_device("basis", basis, C.device)
+    _check_points(X, n, C.device)
     need = eval_dense_workspace(n, K, P, N, prec, nslices)
     if ws is None or ws.numel() < need:
         ws = _workspace(need, C.device)
@@ -595,6 +630,7 @@ def eval_dense(basis: torch.Tensor, C: torch.Tensor, X: torch.Tensor, prec: int 
         Y = torch.empty((P, N), dtype=torch.float64, device=C.device)
     elif Y.dtype != torch.float64 or not Y.is_contiguous() or tuple(Y.shape) != (P, N):
         raise ValueError(f"Y must be contiguous float64 [{P}, {N}]")
+    _check_device("Y", Y, C.device)
     me = int(max_exp) if max_exp is not None else 255
     _check(L.poly_eval_dense(n, K, _ptr(basis), me, P, _ptr(C), N, _ptr(X), _ptr(Y), prec, nslices,
                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "poly_eval_dense")
@@ -618,6 +654,7 @@ class PolyEval(torch.autograd.Function):
         return eval(b, X.detach())
 
     @staticmethod
+    @torch.autograd.function.once_differentiable
     def backward(ctx, gY):
         coefs, X = ctx.saved_tensors
         b = ctx.structure.with_coefs(coefs.detach().contiguous())

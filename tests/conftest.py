@@ -32,3 +32,18 @@ def poly_from_json(terms, n):
 
 def as_termset(e, c):
     return sorted((tuple(int(v) for v in row), float(x)) for row, x in zip(e.tolist(), c.tolist()))
+
+
+def oracle_over_points(fn, row_ptr, exps, coefs, X, nthreads=None):
+    """fn(row_ptr, exps, coefs, X_chunk) (an oracle evaluation returning
+    [P, pts, ...]) over row chunks of X in a thread pool.  The oracle's C
+    routines run with the GIL released, so the chunks run in parallel; every
+    output element is computed exactly as in a single call."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    nthreads = nthreads or min(16, os.cpu_count() or 1)
+    X = np.ascontiguousarray(X)
+    chunks = [c for c in np.array_split(np.arange(X.shape[0]), nthreads) if c.size]
+    with ThreadPoolExecutor(max_workers=len(chunks)) as ex:
+        parts = list(ex.map(lambda c: fn(row_ptr, exps, coefs, X[c[0]:c[-1] + 1]), chunks))
+    return np.concatenate(parts, axis=1)

@@ -165,3 +165,18 @@ def test_binding_rejects_bad_shapes():
         ph.mpower(b, 1, 0)
     with pytest.raises(ValueError):
         ph.subs(b, b)
+    # CPU tensors and strided views are rejected before their pointers reach a kernel
+    with pytest.raises(ValueError, match="GPU tensor"):
+        b.csr()
+    with pytest.raises(ValueError):
+        ph.eval_backward(b, torch.zeros((3, 2), dtype=torch.float64), torch.zeros((1, 3), dtype=torch.float64))
+    strided = ph.Batch(2, 2, torch.zeros(2, dtype=torch.int64), np.array([0, 1]),
+                       torch.zeros((2, 2), dtype=torch.uint8), torch.zeros(4, dtype=torch.float64)[::2])
+    assert not strided.coefs.is_contiguous()
+    with pytest.raises(ValueError):
+        strided.csr()
+    with pytest.raises(ValueError):
+        ph.eval_dense(torch.zeros((4, 2), dtype=torch.uint8), torch.zeros((3, 4), dtype=torch.float64),
+                      torch.zeros((5, 2), dtype=torch.float64))
+    with pytest.raises(ValueError, match="GPU tensor"):
+        ph._check_points(torch.zeros((5, 2), dtype=torch.float64), 2)

@@ -68,42 +68,40 @@ def test_paper_family_pd_cubed(ph):
 
 def test_batch_matrix_full(ph):
     """64 x 64 polynomial matrix, n=20, degree <= 6, log-uniform entry sizes
-    in [10, 20000]: one persistent simplify launch, then the 64 x 64 x 20
-    Jacobian, then its evaluation at 4,096 points (sampled entries/points
-    against the oracle)."""
+    in [10, 20000]: the simplify of all 4,096 entries and the whole 64 x 64
+    x 20 Jacobian compared bit for bit with the oracle, then the Jacobian's
+    evaluation at 4,096 points, every one of the 81,920 polynomials at 16
+    sampled points within the per-element bound."""
+    from conftest import oracle_over_points
     wl = W.batch_matrix()
     say(f"batch matrix: {wl.row_ptr[-1]} raw terms")
     b = ph.batch_from_numpy(wl.row_ptr, wl.exps, wl.coefs, n=wl.n, max_exp=wl.max_exp)
     s = ph.simplify(b)
     rp, E, C = ph.batch_to_numpy(s)
-    rng = np.random.default_rng(3)
-    entries = np.sort(rng.choice(4096, size=256, replace=False))
-    entries = np.unique(np.concatenate([entries, [int(np.argmax(np.diff(wl.row_ptr)))]]))
-    for p in entries:
-        lo, hi = wl.row_ptr[p], wl.row_ptr[p + 1]
-        oe, oc = oracle.simplify(wl.exps[lo:hi], wl.coefs[lo:hi])
-        assert np.array_equal(E[rp[p]:rp[p + 1]], oe)
-        assert C[rp[p]:rp[p + 1]].view(np.uint64).tolist() == oc.view(np.uint64).tolist()
+    say("oracle simplify of all entries")
+    orp, oE, oC = oracle.simplify_batch(wl.row_ptr, wl.exps, wl.coefs, n=wl.n)
+    assert np.array_equal(rp, orp)
+    assert np.array_equal(E, oE)
+    assert C.view(np.uint64).tolist() == oC.view(np.uint64).tolist()
     say("jacobian")
     J = ph.jacobian(s)
     jrp, jE, jC = ph.batch_to_numpy(J)
     assert jrp.shape[0] == 4096 * 20 + 1
-    for p in entries[:64]:
-        for j in range(20):
-            de, dc = oracle.diff(E[rp[p]:rp[p + 1]], C[rp[p]:rp[p + 1]], j)
-            k = p * 20 + j
-            assert np.array_equal(jE[jrp[k]:jrp[k + 1]], de)
-            assert np.array_equal(jC[jrp[k]:jrp[k + 1]], dc)
+    say("oracle jacobian of all entries")
+    ojrp, ojE, ojC = oracle.jacobian_batch(orp, oE, oC, n=wl.n)
+    assert np.array_equal(jrp, ojrp)
+    assert np.array_equal(jE, ojE)
+    assert jC.view(np.uint64).tolist() == ojC.view(np.uint64).tolist()
     say("jacobian eval")
     Y = ph.eval(J, torch.from_numpy(wl.X).cuda())
+    rng = np.random.default_rng(3)
     pts = np.sort(rng.choice(wl.X.shape[0], size=16, replace=False))
     Ys = Y[:, torch.from_numpy(pts).cuda()].cpu().numpy()
-    sel = np.array([p * 20 + j for p in entries[:32] for j in range(20)])
-    for k in sel:
-        e_, c_ = jE[jrp[k]:jrp[k + 1]], jC[jrp[k]:jrp[k + 1]]
-        yo = oracle.eval_points(e_, c_, wl.X[pts])
-        bound = 1e-12 * oracle.eval_points(e_, np.abs(c_), np.abs(wl.X[pts])) + 1e-300
-        assert (np.abs(Ys[k] - yo) <= bound).all()
+    del Y
+    say("oracle jacobian eval at 16 points")
+    Yo = oracle_over_points(oracle.eval_batch, ojrp, ojE, ojC, wl.X[pts])
+    bound = 1e-12 * oracle_over_points(oracle.eval_batch, ojrp, ojE, np.abs(ojC), np.abs(wl.X[pts])) + 1e-300
+    assert (np.abs(Ys - Yo) <= bound).all()
 
 
 def test_dense_shared_full_sampled(ph):
@@ -132,29 +130,34 @@ def test_dense_shared_full_sampled(ph):
 def test_quartic_full_sampled(ph):
     """Random quartic in 100 variables with 100,000 terms at 8,192 points:
     value, gradient (reverse-mode kernel with unit cotangent and poly_grad)
-    and Hessian (poly_hess) against the oracle's symbolic derivatives on
-    sampled points; Hessian symmetric bit for bit; gradient against central
+    and Hessian (poly_hess) against the oracle's symbolic derivatives at 64
+    sampled points, every element within 1e-12 times the same sum over
+    absolute values; Hessian symmetric bit for bit; gradient against central
     differences of the GPU's own evaluation."""
+    from conftest import oracle_over_points
     wl = W.quartic()
     b = ph.batch_from_numpy([0, wl.exps.shape[0]], wl.exps, wl.coefs, n=100, max_exp=4)
     X = torch.from_numpy(wl.X).cuda()
-    pts = np.array([0, 5, 4096, 8191])
-    rp = [0, wl.exps.shape[0]]
+    pts = np.unique(np.concatenate([[0, 8191], np.random.default_rng(5).choice(8192, size=62, replace=False)]))
+    rp = np.array([0, wl.exps.shape[0]], np.int64)
+    Xs, aC, aXs = wl.X[pts], np.abs(wl.coefs), np.abs(wl.X[pts])
     say("quartic eval")
     Y = ph.eval(b, X).cpu().numpy()[0]
-    yo = oracle.eval_batch(rp, wl.exps, wl.coefs, wl.X[pts])[0]
-    assert np.allclose(Y[pts], yo, rtol=0, atol=1e-12 * oracle.eval_batch(rp, wl.exps, np.abs(wl.coefs), np.abs(wl.X[pts]))[0].max())
+    yo = oracle.eval_batch(rp, wl.exps, wl.coefs, Xs)[0]
+    assert (np.abs(Y[pts] - yo) <= 1e-12 * oracle.eval_batch(rp, wl.exps, aC, aXs)[0] + 1e-300).all()
     say("quartic backward (gradient)")
     dX, dC = ph.eval_backward(b, X, torch.ones((1, X.shape[0]), dtype=torch.float64, device="cuda"), check=True)
     G = ph.grad(b, X, check=True).cpu().numpy()[0]
-    Go = oracle.grad_batch(rp, wl.exps, wl.coefs, wl.X[pts])[0]
-    scale = np.abs(Go).max()
-    assert np.abs(dX.cpu().numpy()[pts] - Go).max() <= 1e-11 * scale
-    assert np.abs(G[pts] - Go).max() <= 1e-11 * scale
+    say("oracle gradient at 64 points")
+    Go = oracle_over_points(oracle.grad_batch, rp, wl.exps, wl.coefs, Xs)[0]
+    gtol = 1e-12 * oracle_over_points(oracle.grad_batch, rp, wl.exps, aC, aXs)[0] + 1e-300
+    assert (np.abs(dX.cpu().numpy()[pts] - Go) <= gtol).all()
+    assert (np.abs(G[pts] - Go) <= gtol).all()
     say("quartic hessian")
     H = ph.hess(b, X[torch.from_numpy(pts).cuda()].contiguous(), check=True).cpu().numpy()[0]
-    Ho = oracle.hess_batch(rp, wl.exps, wl.coefs, wl.X[pts])[0]
-    assert np.abs(H - Ho).max() <= 1e-11 * np.abs(Ho).max()
+    say("oracle hessian at 64 points")
+    Ho = oracle_over_points(oracle.hess_batch, rp, wl.exps, wl.coefs, Xs)[0]
+    assert (np.abs(H - Ho) <= 1e-12 * oracle_over_points(oracle.hess_batch, rp, wl.exps, aC, aXs)[0] + 1e-300).all()
     assert np.array_equal(H, np.swapaxes(H, 1, 2))
     say("finite differences")
     h = 1e-6
@@ -164,3 +167,36 @@ def test_quartic_full_sampled(ph):
     Xm[:, 7] -= h
     fd = (ph.eval(b, Xp) - ph.eval(b, Xm)).cpu().numpy()[0] / (2 * h)
     assert np.allclose(fd, G[:, 7], rtol=1e-6, atol=1e-6)
+
+
+def test_quartic_integer_full_bitwise(ph):
+    """The same shape with integer coefficients in [-9, 9] at integer points in
+    {-2..2}^100: every value, gradient and Hessian entry is an integer below
+    2^53, so any summation order is exact and the GPU must agree with the
+    oracle bit for bit: values at all 8,192 points, gradients (from both
+    poly_grad and the reverse-mode kernel) at 2,048 of them, Hessians at 256."""
+    from conftest import oracle_over_points
+    wl = W.quartic()
+    C = W.rng_for(W.SEED_BASE + 55).integers(-9, 10, size=wl.coefs.shape[0]).astype(np.float64)
+    Xn = W.integer_points(W.SEED_BASE + 56, 8192, 100, -2, 2)
+    rp = np.array([0, wl.exps.shape[0]], np.int64)
+    b = ph.batch_from_numpy(rp, wl.exps, C, n=100, max_exp=4)
+    X = torch.from_numpy(Xn).cuda()
+    say("integer quartic: eval")
+    Y = ph.eval(b, X).cpu().numpy()
+    say("integer quartic: oracle eval at 8,192 points")
+    assert np.array_equal(Y, oracle_over_points(oracle.eval_batch, rp, wl.exps, C, Xn))
+    say("integer quartic: gradient (poly_grad, reverse mode)")
+    G = ph.grad(b, X, check=True).cpu().numpy()
+    dX, _ = ph.eval_backward(b, X, torch.ones((1, 8192), dtype=torch.float64, device="cuda"), want_dC=False,
+                             check=True)
+    dX = dX.cpu().numpy()
+    sel = np.arange(0, 8192, 4)
+    say("integer quartic: oracle gradient at 2,048 points")
+    Go = oracle_over_points(oracle.grad_batch, rp, wl.exps, C, Xn[sel])
+    assert np.array_equal(G[:, sel], Go)
+    assert np.array_equal(dX[sel], Go[0])
+    sel = np.arange(0, 8192, 32)
+    say("integer quartic: hessian at 256 points")
+    H = ph.hess(b, X[torch.from_numpy(sel).cuda()].contiguous(), check=True).cpu().numpy()
+    assert np.array_equal(H, oracle_over_points(oracle.hess_batch, rp, wl.exps, C, Xn[sel]))

@@ -218,3 +218,20 @@ def test_subs_random(ph, seed):
     say(f"subs: random seed={seed}")
     got = ph.subs(pb, qb, tol=tol)
     _same(ph, got, W.csr_from_list([oracle.subs(*p, *rq, m, tol=tol)], m))
+
+
+def test_subs_ten_variables(ph):
+    """n = m = 10, deg(p) = 4, deg(q_i) = 2: the result's exponents stay within
+    deg(p) * max_exp(q) = 8, so 4-bit fields suffice (40-bit keys); the
+    declared bounds of the intermediate powers and partial products follow
+    that, not the sum of the factors' declarations."""
+    rng = W.rng_for(3760)
+    n = m = 10
+    p = W.random_poly(rng, n, 4, 12)
+    q = [W.random_poly(rng, m, 2, 3) for _ in range(n)]
+    pb, _ = _batch(ph, [p], n, 4)
+    qb, rq = _batch(ph, q, m, 2)
+    say("subs: n = m = 10")
+    got = ph.subs(pb, qb)
+    assert got.max_exp <= 8
+    _same(ph, got, W.csr_from_list([oracle.subs(*p, *rq, m)], m))
