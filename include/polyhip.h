@@ -31,7 +31,8 @@
  *
  * Memory.  Every pointer is a DEVICE pointer unless its comment says [host].
  * The caller owns all memory (inputs, outputs, workspace).  The library keeps
- * no per-call state and allocates nothing on the device; every entry point
+ * no per-call state and allocates nothing on the device (its one device
+ * array is the fixed scratch of poly_simplify_noalloc); every entry point
  * enqueues its kernels on `stream` (a hipStream_t passed as void*, NULL = the
  * default stream) and returns without synchronising.
  *
@@ -60,7 +61,9 @@ typedef enum poly_status {
     POLY_ERR_CAPACITY = 4,     /* output capacity too small (device-detected)         */
     POLY_ERR_EXPONENT = 5,     /* an exponent exceeds the declared max_exp (device)   */
     POLY_ERR_UNSUPPORTED = 6,  /* shape beyond this library's limits                  */
-    POLY_ERR_HIP = 7           /* a HIP runtime call or kernel launch failed          */
+    POLY_ERR_HIP = 7,          /* a HIP runtime call or kernel launch failed          */
+    POLY_ERR_SCRATCH = 8       /* work needs more than the fixed scratch of an
+                                  allocation-free entry point (host-detected)         */
 } poly_status;
 
 typedef enum poly_prec {
@@ -280,6 +283,32 @@ poly_status poly_eval_dense(int32_t n, int64_t K, const uint8_t *basis, int32_t 
                             int64_t P, const double *C, int64_t N, const double *X,
                             double *Y, poly_prec prec, int32_t nslices,
                             void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------ allocation-free simplify
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * operation, kernels and results as poly_simplify (bit-identical outputs),
+ * but the workspace is a fixed array of POLY_NOALLOC_SCRATCH_BYTES in device
+ * memory that the library owns: one per GPU, held from the first call on
+ * that GPU until the process ends.  Nothing is allocated or freed by this
+ * call; the caller still owns `in` and `out`.
+ *   status  [device] int32 that receives the device-detected status of the
+ *           call (as poly_read_status would report it: POLY_OK,
+ *           POLY_ERR_EXPONENT, POLY_ERR_CAPACITY), written by a kernel on
+ *           `stream` after the last one of the call; may be NULL.
+ * Returns POLY_ERR_SCRATCH, before any device work, when the workspace that
+ * poly_simplify_workspace reports for `in` exceeds the fixed scratch: about
+ * 24 bytes per term and 16 per polynomial on the per-entry path (some 2.7
+ * million terms), about 49 bytes per term when the batch takes the
+ * device-wide path (an entry of at least "simplify_wide_min" terms; some 1.3
+ * million terms).
+ * Every call on a GPU shares that GPU's scratch and finds it as the last call
+ * left it; what the kernels need cleared they clear themselves.  Calls that
+ * overlap on one GPU (from several streams or host threads) race on the
+ * scratch and give undefined results: serialise them. */
+#define POLY_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+poly_status poly_simplify_noalloc(const poly_csr *in, poly_csr *out, double zero_tol, int32_t *status,
+                                  void *stream);
 
 #ifdef __cplusplus
 }

@@ -43,6 +43,7 @@ EXPORTS = [
     "poly_affine_normal_workspace", "poly_affine_normal",
     "poly_mtimes_workspace", "poly_mtimes",
     "poly_concat",
+    "poly_simplify_noalloc",
 ]
 
 
@@ -112,6 +113,7 @@ def lib():
         "poly_mtimes": ([pcsr, pcsr, i64, i64, i64, pcsr, d, P, ctypes.c_size_t, P], i32),
         "poly_affine_normal": ([pcsr, P, i64, d, P, P, P, ctypes.c_size_t, P], i32),
         "poly_concat": ([ctypes.POINTER(pcsr), i32, pcsr, P], i32),
+        "poly_simplify_noalloc": ([pcsr, pcsr, d, P, P], i32),
         "poly_eval_dense": ([i32, i64, P, i32, i64, P, i64, P, P, i32, i32, P, ctypes.c_size_t, P], i32),
     }
     for name, (args, res) in sig.items():
@@ -311,6 +313,24 @@ def simplify(b: Batch, tol: float = 0.0, trim: bool = True, ws: torch.Tensor | N
     if not finish:
         return out
     return _finish(out, ws, "poly_simplify", trim)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # POLY_NOALLOC_SCRATCH_BYTES
+
+
+def simplify_noalloc(b: Batch, out: Batch, status: torch.Tensor, tol: float = 0.0) -> Batch:
+    """simplify into a caller-provided output with the library's fixed device
+    scratch as workspace (poly_simplify_noalloc): nothing is allocated and
+    nothing is read back.  `status` (int32 [1] on the device) receives the
+    device-detected status; out.row_ptr holds the output row pointer on the
+    device (out.row_ptr_host is not updated)."""
+    if status.dtype != torch.int32 or status.numel() < 1:
+        raise ValueError("status must be an int32 tensor of at least one element")
+    _check_device("status", status, b.coefs.device)
+    cin, cout = b.csr(), out.csr()
+    _check(lib().poly_simplify_noalloc(ctypes.byref(cin), ctypes.byref(cout), float(tol),
+                                       ctypes.c_void_p(status.data_ptr()), _stream()), "poly_simplify_noalloc")
+    return out
 
 
 def mul_workspace(a: Batch, b: Batch) -> tuple[int, int]:

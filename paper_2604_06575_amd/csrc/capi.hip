@@ -617,6 +617,7 @@ const char *poly_strerror(int32_t status)
     case POLY_ERR_EXPONENT: return "an exponent exceeds the declared max_exp";
     case POLY_ERR_UNSUPPORTED: return "shape beyond the library's limits";
     case POLY_ERR_HIP: return "HIP runtime or launch failure";
+    case POLY_ERR_SCRATCH: return "work exceeds the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
     }
 }

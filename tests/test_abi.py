@@ -22,7 +22,7 @@ def test_library_exports_every_declared_symbol():
         pytest.skip("library not built")
     L = ctypes.CDLL(ph.library_path())
     syms = header_symbols()
-    assert len(syms) == 27
+    assert len(syms) == 28
     for s in syms:
         assert hasattr(L, s), s
     assert sorted(ph.EXPORTS) == syms
@@ -76,6 +76,41 @@ def test_strerror_and_host_argument_checks():
     c.nvars = 255   # past the LDS-resident size the matrix works in the Hessian's workspace slot
     assert L.poly_affine_normal_workspace(ctypes.byref(c), 10, ctypes.byref(size)) == 0
     assert size.value >= 10 * 255 * 255 * 8
+
+
+def test_noalloc_rejects_work_beyond_its_scratch():
+    """The allocation-free simplify refuses, on the host and before touching a
+    device, an input whose workspace exceeds its fixed scratch, and checks
+    its arguments like poly_simplify."""
+    import paper_2604_06575_amd as ph
+    if not os.path.exists(ph.library_path()):
+        pytest.skip("library not built")
+    L = ph.lib()
+    assert L.poly_strerror(8).decode().startswith("work exceeds the fixed scratch")
+    size = ctypes.c_size_t()
+    c = ph.PolyCSR()
+    c.nvars = 4
+    c.max_exp = 6
+    c.npolys = 1
+    big = np.array([0, 4_000_000], np.int64)
+    c.capacity = int(big[-1])
+    c.row_ptr_host = big.ctypes.data_as(ctypes.c_void_p)
+    c.row_ptr = ctypes.c_void_p(1)
+    c.exps = ctypes.c_void_p(1)
+    c.coefs = ctypes.c_void_p(1)
+    assert L.poly_simplify_workspace(ctypes.byref(c), ctypes.byref(size)) == 0
+    assert size.value > ph.NOALLOC_SCRATCH_BYTES
+    assert L.poly_simplify_noalloc(ctypes.byref(c), ctypes.byref(c), 0.0, None, None) == 8
+    # many small entries: the per-entry path, 24 bytes per term and 16 per entry
+    many = np.arange(0, 3_000_001, 3, dtype=np.int64)
+    c.npolys = many.shape[0] - 1
+    c.capacity = int(many[-1])
+    c.row_ptr_host = many.ctypes.data_as(ctypes.c_void_p)
+    assert L.poly_simplify_workspace(ctypes.byref(c), ctypes.byref(size)) == 0
+    assert size.value > ph.NOALLOC_SCRATCH_BYTES
+    assert L.poly_simplify_noalloc(ctypes.byref(c), ctypes.byref(c), 0.0, None, None) == 8
+    c.nvars = 0   # argument errors come first, as for poly_simplify
+    assert L.poly_simplify_noalloc(ctypes.byref(c), ctypes.byref(c), 0.0, None, None) == 1
 
 
 def test_concat_host_checks():
