@@ -10,6 +10,7 @@
  *   poly_grad      gradient row evaluated at points         (Table "apisignature", g = jacobian(p))
  *   poly_hess      Hessian array evaluated at points        (Table "apisignature", H = jacobian(g))
  *   poly_eval_backward  reverse mode of poly_eval w.r.t. points and coefficients
+ *   poly_eval_backward2 reverse mode of poly_eval_backward (Hessian-vector products)
  *   poly_eval_dense     P polynomials over one shared monomial set (coefficient
  *                       matrix times monomial-value matrix), in FP64 or in
  *                       split BF16 products with FP32 accumulation and FP64
@@ -208,6 +209,24 @@ poly_status poly_eval_backward_workspace(const poly_csr *f, int64_t N, size_t *w
 poly_status poly_eval_backward(const poly_csr *f, const double *X, int64_t N,
                                const double *gY, double *dX, double *dC,
                                void *ws, size_t ws_bytes, void *stream);
+
+/* Reverse mode of poly_eval_backward (second order; what a double backward
+ * of evaluation needs).  With cotangents u[N*n] of dX and w[T] of dC, and
+ * L = sum_t w[t] dC[t] + sum_{pt,j} u[pt*n + j] dX[pt*n + j]:
+ *   ggY[p*N + pt] = dL/dgY = sum_{t in p} (c_t sum_k u[pt*n+k] d m_t/dx_k (x_pt) + w[t] m_t(x_pt))
+ *   ggX[pt*n + j] = dL/dX  = sum_t gY[p(t)*N + pt] (c_t sum_k u[pt*n+k] d2 m_t/dx_j dx_k (x_pt)
+ *                                                   + w[t] d m_t/dx_j (x_pt))
+ *   ggC[t]        = dL/dc  = sum_pt gY[p(t)*N + pt] sum_k u[pt*n+k] d m_t/dx_k (x_pt)
+ * (m_t = x^{e_t}).  The first sum over k is a Hessian-vector product per
+ * point; it is computed term by term from the monomials' second derivatives,
+ * and no Hessian or derivative polynomial is formed.  u or w may be NULL
+ * (taken as zero); any output may be NULL.  Limits: n <= 105 (the points,
+ * the direction and one accumulator block per wave share the 160 KB LDS of a
+ * workgroup), else POLY_ERR_UNSUPPORTED. */
+poly_status poly_eval_backward2_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes);
+poly_status poly_eval_backward2(const poly_csr *f, const double *X, int64_t N, const double *gY,
+                                const double *u, const double *w, double *ggY, double *ggX, double *ggC,
+                                void *ws, size_t ws_bytes, void *stream);
 
 /* --------------------------------------------------- polynomial matrices
  * out = A * B for polynomial matrices (Section 3.3, mtimes: matrix

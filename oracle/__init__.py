@@ -333,6 +333,41 @@ def eval_backward(row_ptr, exps, coefs, X, gY, want_dX: bool = True, want_dC: bo
     return dX, dC
 
 
+def eval_backward2(row_ptr, exps, coefs, X, gY, u=None, w=None):
+    """Reverse mode of ``eval_backward``: for cotangents u[pt, j] of dX and
+    w[t] of dC, with L = <w, dC> + <u, dX>,
+        ggY[p, pt] = sum_j u[pt, j] df_p/dx_j (x_pt) + f_p^w(x_pt),
+        ggX[pt, j] = sum_p gY[p, pt] (sum_k d2f_p/dx_j dx_k (x_pt) u[pt, k] + df_p^w/dx_j (x_pt)),
+        ggC[t]     = sum_pt gY[p(t), pt] sum_j u[pt, j] d m_t/dx_j (x_pt),
+    where f^w is f with coefficients w and m_t the monomial of term t.  Every
+    derivative is the symbolically differentiated polynomial evaluated at the
+    point (grad_batch, hess_batch; ggC from the gradients of the one-term
+    polynomials m_t).  u or w may be None (zero)."""
+    X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+    n = X.shape[1]
+    rp = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int64))
+    e, c = _u8(exps, n), _f64(coefs)
+    gY = np.asarray(gY, dtype=np.float64)
+    P, N, T = rp.shape[0] - 1, X.shape[0], e.shape[0]
+    ggY = np.zeros((P, N))
+    ggX = np.zeros((N, n))
+    ggC = np.zeros(T)
+    if u is not None:
+        u = np.asarray(u, dtype=np.float64)
+        G = grad_batch(rp, e, c, X)                                  # [P, N, n]
+        H = hess_batch(rp, e, c, X)                                  # [P, N, n, n]
+        ggY += np.einsum("pnj,nj->pn", G, u)
+        ggX += np.einsum("pn,pnjk,nk->nj", gY, H, u)
+        Gt = grad_batch(np.arange(T + 1), e, np.ones(T), X)          # [T, N, n]: gradients of the monomials
+        owner = np.repeat(np.arange(P), np.diff(rp))
+        ggC += np.einsum("tn,tnj,nj->t", gY[owner], Gt, u)
+    if w is not None:
+        w = _f64(w)
+        ggY += eval_batch(rp, e, w, X)
+        ggX += np.einsum("pn,pnj->nj", gY, grad_batch(rp, e, w, X))
+    return ggY, ggX, ggC
+
+
 # ------------------------------------------------------------- affine normal
 
 def derivatives_at(exps, coefs, x, n: int | None = None):

@@ -39,6 +39,7 @@ EXPORTS = [
     "poly_grad_workspace", "poly_grad",
     "poly_hess_workspace", "poly_hess",
     "poly_eval_backward_workspace", "poly_eval_backward",
+    "poly_eval_backward2_workspace", "poly_eval_backward2",
     "poly_eval_dense_workspace", "poly_eval_dense",
     "poly_affine_normal_workspace", "poly_affine_normal",
     "poly_mtimes_workspace", "poly_mtimes",
@@ -107,6 +108,8 @@ def lib():
         "poly_hess": ([pcsr, P, i64, P, P, ctypes.c_size_t, P], i32),
         "poly_eval_backward_workspace": ([pcsr, i64, psz], i32),
         "poly_eval_backward": ([pcsr, P, i64, P, P, P, P, ctypes.c_size_t, P], i32),
+        "poly_eval_backward2_workspace": ([pcsr, i64, psz], i32),
+        "poly_eval_backward2": ([pcsr, P, i64, P, P, P, P, P, P, P, ctypes.c_size_t, P], i32),
         "poly_eval_dense_workspace": ([i32, i64, i64, i64, i32, i32, psz], i32),
         "poly_affine_normal_workspace": ([pcsr, i64, psz], i32),
         "poly_mtimes_workspace": ([pcsr, pcsr, i64, i64, i64, psz, ctypes.POINTER(i64)], i32),
@@ -590,6 +593,45 @@ def eval_backward(b: Batch, X: torch.Tensor, gY: torch.Tensor, want_dX: bool = T
     return dX, dC
 
 
+def eval_backward2(b: Batch, X: torch.Tensor, gY: torch.Tensor, u: torch.Tensor | None, w: torch.Tensor | None,
+                   want_gY: bool = True, want_X: bool = True, want_C: bool = True, check: bool = False):
+    """Reverse mode of eval_backward for cotangents u [N, n] (of dX) and
+    w [T] (of dC), either may be None: (ggY [P, N], ggX [N, n], ggC [T])."""
+    L = lib()
+    X = X.contiguous()
+    gY = gY.contiguous()
+    cin = b.csr()
+    dev = b.coefs.device
+    _check_points(X, b.n, dev)
+    N = X.shape[0]
+    if gY.dtype != torch.float64 or tuple(gY.shape) != (b.npolys, N):
+        raise ValueError(f"gY must be float64 [{b.npolys}, {N}], got {gY.dtype} {tuple(gY.shape)}")
+    _check_device("gY", gY, dev)
+    if u is not None:
+        u = u.contiguous()
+        if u.dtype != torch.float64 or tuple(u.shape) != (N, b.n):
+            raise ValueError(f"u must be float64 [{N}, {b.n}], got {u.dtype} {tuple(u.shape)}")
+        _check_device("u", u, dev)
+    if w is not None:
+        w = w.contiguous()
+        if w.dtype != torch.float64 or w.dim() != 1 or w.shape[0] != b.nterms:
+            raise ValueError(f"w must be float64 [{b.nterms}], got {w.dtype} {tuple(w.shape)}")
+        _check_device("w", w, dev)
+    ws_bytes = ctypes.c_size_t()
+    _check(L.poly_eval_backward2_workspace(ctypes.byref(cin), N, ctypes.byref(ws_bytes)),
+           "poly_eval_backward2_workspace")
+    ws = _workspace(ws_bytes.value, dev)
+    ggY = torch.empty((b.npolys, N), dtype=torch.float64, device=dev) if want_gY else None
+    ggX = torch.empty((N, b.n), dtype=torch.float64, device=dev) if want_X else None
+    ggC = torch.empty(b.nterms, dtype=torch.float64, device=dev) if want_C else None
+    _check(L.poly_eval_backward2(ctypes.byref(cin), _ptr(X), N, _ptr(gY), _ptr(u), _ptr(w), _ptr(ggY), _ptr(ggX),
+                                 _ptr(ggC), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()),
+           "poly_eval_backward2")
+    if check:
+        _check(L.poly_read_status(ctypes.c_void_p(ws.data_ptr()), _stream()), "poly_eval_backward2")
+    return ggY, ggX, ggC
+
+
 def affine_normal(b: Batch, X: torch.Tensor, reg: float = 1e-6, check: bool = False, ws: torch.Tensor | None = None):
     """Affine-normal directions of one polynomial at the rows of X:
     (D [N, n], |grad f| [N])."""
@@ -663,8 +705,10 @@ class PolyEval(torch.autograd.Function):
     """Y = eval(f, X) as a differentiable function of (coefs, X).
 
     The backward pass is the library's reverse-mode kernel
-    (``poly_eval_backward``): dC from the monomial values, dX from the
-    symbolic first derivatives."""
+    (``poly_eval_backward``, dC from the monomial values, dX from the
+    derivatives streamed term by term), itself differentiable through
+    :class:`PolyEvalBackward`, so double backward (Hessian-vector products,
+    Hessians) runs in the library's second-order kernel."""
 
     @staticmethod
     def forward(ctx, coefs, X, structure: Batch):
@@ -674,10 +718,37 @@ class PolyEval(torch.autograd.Function):
         return eval(b, X.detach())
 
     @staticmethod
-    @torch.autograd.function.once_differentiable
     def backward(ctx, gY):
         coefs, X = ctx.saved_tensors
-        b = ctx.structure.with_coefs(coefs.detach().contiguous())
-        dX, dC = eval_backward(b, X.detach(), gY.detach().contiguous(), want_dX=ctx.needs_input_grad[1],
-                               want_dC=ctx.needs_input_grad[0])
+        dC, dX = PolyEvalBackward.apply(coefs, X, gY, ctx.structure, ctx.needs_input_grad[0],
+                                        ctx.needs_input_grad[1])
         return dC, dX, None
+
+
+class PolyEvalBackward(torch.autograd.Function):
+    """(dC, dX) = reverse mode of eval at cotangent gY, differentiable in
+    (coefs, X, gY): its backward is ``poly_eval_backward2``."""
+
+    @staticmethod
+    def forward(ctx, coefs, X, gY, structure: Batch, want_dC: bool = True, want_dX: bool = True):
+        b = structure.with_coefs(coefs.detach().contiguous())
+        ctx.structure = structure
+        ctx.save_for_backward(coefs, X, gY)
+        dX, dC = eval_backward(b, X.detach(), gY.detach().contiguous(), want_dX=want_dX, want_dC=want_dC)
+        return dC, dX
+
+    @staticmethod
+    @torch.autograd.function.once_differentiable
+    def backward(ctx, g_dC, g_dX):
+        coefs, X, gY = ctx.saved_tensors
+        b = ctx.structure.with_coefs(coefs.detach().contiguous())
+        u = None if g_dX is None else g_dX.detach()
+        w = None if g_dC is None else g_dC.detach()
+        need_c, need_x, need_g = ctx.needs_input_grad[0], ctx.needs_input_grad[1], ctx.needs_input_grad[2]
+        if u is None and w is None:
+            return None, None, None, None, None, None
+        ggY, ggX, ggC = eval_backward2(b, X.detach(), gY.detach(), u, w, want_gY=need_g, want_X=need_x,
+                                       want_C=need_c and u is not None)
+        if need_c and u is None:
+            ggC = torch.zeros_like(coefs)
+        return ggC, ggX, ggY, None, None, None

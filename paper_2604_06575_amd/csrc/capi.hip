@@ -494,6 +494,15 @@ void ensure_lds_attrs()
     if (lds_attr_done) return;
     (void)hipFuncSetAttribute((const void *)k_eval_terms, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
     (void)hipFuncSetAttribute((const void *)k_backward_dc, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
+    (void)hipFuncSetAttribute((const void *)k_backward2_dc, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    (void)hipFuncSetAttribute((const void *)k_deriv_terms<DM_GRAD>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)DV_LDS_MAX);
+    (void)hipFuncSetAttribute((const void *)k_deriv_terms<DM_DX>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)DV_LDS_MAX);
+    (void)hipFuncSetAttribute((const void *)k_deriv_terms<DM_HVP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)DV_LDS_MAX);
+    (void)hipFuncSetAttribute((const void *)k_deriv_terms<DM_DIRD>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)DV_LDS_MAX);
     (void)hipFuncSetAttribute((const void *)k_mul_buckets_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)MB_LDS_LIMIT);
     (void)hipFuncSetAttribute((const void *)k_affine_normal, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -509,10 +518,127 @@ inline int64_t grad_terms_bound(int64_t T, int n) { return T * std::min<int64_t>
 inline int64_t hess_terms_bound(int64_t T, int64_t nb) { return T * std::min<int64_t>(nb, 36); }
 
 
+// ------------------------------------------------ fused derivative streaming
+
+// Launch shape of k_deriv_terms<mode> for n variables: waves per workgroup W
+// and the dynamic LDS they need (point tile, direction tile, one accumulator
+// block per wave), chosen for the most resident waves per CU.  Depends on
+// (mode, n) only.
+struct DerivShape {
+    bool ok = false;
+    int W = 0;
+    size_t lds = 0;
+    int64_t waves_per_cu = 0;
+};
+
+DerivShape deriv_shape(int mode, int n)
+{
+    const bool acc = mode != DM_DIRD, dir = mode == DM_HVP || mode == DM_DIRD;
+    const size_t tile = (size_t)(n + 1) * kWave * 8 + (dir ? (size_t)n * kWave * 8 : 0);
+    const size_t accb = acc ? (size_t)n * DV_ACC_PITCH * 8 : 0;
+    DerivShape best;
+    for (int W : {8, 4, 2, 1}) {
+        const size_t lds = tile + (size_t)W * accb;
+        if (lds > DV_LDS_MAX) continue;
+        const int64_t wgs = std::min<int64_t>((int64_t)(DV_LDS_MAX / lds), 24 / W);
+        const int64_t waves = W * std::max<int64_t>(wgs, 1);
+        if (!best.ok || waves > best.waves_per_cu) {
+            best.ok = true;
+            best.W = W;
+            best.lds = lds;
+            best.waves_per_cu = waves;
+        }
+    }
+    return best;
+}
+
+constexpr int64_t DV_MIN_SEGMENT = 128;   // fewest terms per segment
+constexpr int64_t DV_CUS = 256;           // segment counts are planned for a full MI355X
+
+// Term segments per work unit: enough units for two rounds of resident waves.
+int64_t deriv_segments(int mode, const DerivShape &sh, int64_t P, int64_t T, int64_t N)
+{
+    if (P <= 0 || N <= 0 || T <= 0) return 1;
+    const int64_t blocks = ceil_div(N, kWave);
+    const int64_t target = DV_CUS * sh.waves_per_cu * 2;
+    const bool weighted = mode == DM_DX || mode == DM_HVP;
+    const int64_t per = weighted ? blocks : blocks * P;
+    if (per >= target) return 1;
+    int64_t S = ceil_div(target, per);
+    S = std::min<int64_t>(S, std::max<int64_t>(1, T / ((weighted ? 1 : P) * DV_MIN_SEGMENT)));
+    return std::max<int64_t>(1, std::min<int64_t>(S, 1024));
+}
+
+// Elements of the result of a mode: G [P][N][n], dX / ggX [N][n], ggY [P][N].
+inline int64_t deriv_out_len(int mode, int64_t P, int64_t N, int n)
+{
+    if (mode == DM_GRAD) return P * N * n;
+    if (mode == DM_DIRD) return P * N;
+    return N * n;
+}
+
+struct DerivPlan {
+    DerivShape sh;
+    int64_t S = 1;
+    size_t part = 0;
+};
+
+DerivPlan plan_deriv(int mode, int n, int64_t P, int64_t T, int64_t N, Layout &L)
+{
+    DerivPlan d;
+    d.sh = deriv_shape(mode, n);
+    d.S = deriv_segments(mode, d.sh, P, T, N);
+    d.part = L.take(d.S > 1 ? (size_t)8 * d.S * deriv_out_len(mode, P, N, n) : 0);
+    return d;
+}
+
+// Launches k_deriv_terms<MODE> (and the in-order sum of segment partials).
+template <int MODE>
+void launch_deriv(DerivArgs A, const DerivPlan &d, void *ws, hipStream_t s)
+{
+    if (A.N <= 0 || A.P <= 0) return;
+    A.S = d.S;
+    A.partial = d.S > 1 ? at<double>(ws, d.part) : nullptr;
+    const unsigned gx = (unsigned)ceil_div(A.N, kWave);
+    const bool weighted = MODE == DM_DX || MODE == DM_HVP;
+    const int64_t units = weighted ? d.S : A.P * d.S;
+    const int64_t wgs_per_cu = std::max<int64_t>(1, d.sh.waves_per_cu / d.sh.W);
+    const int64_t want = std::max<int64_t>(1, ceil_div((int64_t)device_cus() * wgs_per_cu * 2, gx));
+    const unsigned gy = (unsigned)std::min<int64_t>(std::min<int64_t>(ceil_div(units, d.sh.W), want), 65535);
+    TimedLaunch tl(POLY_TIMING_TERMS, s);
+    hipLaunchKernelGGL(k_deriv_terms<MODE>, dim3(gx, gy), dim3(d.sh.W * kWave), d.sh.lds, s, A);
+    tl.done(s);
+    if (d.S > 1) {
+        const int64_t Lout = deriv_out_len(MODE, A.P, A.N, A.n);
+        hipLaunchKernelGGL(k_sum_slices, dim3(grid1(Lout, 256)), dim3(256), 0, s, (const double *)A.partial, Lout,
+                           d.S, A.out);
+    }
+}
+
+DerivArgs deriv_args(const poly_csr *f, const uint32_t *enc, const double *X, int64_t N, double *out)
+{
+    DerivArgs A;
+    memset(&A, 0, sizeof(A));
+    A.rp = f->row_ptr;
+    A.P = f->npolys;
+    A.T = total_terms(f);
+    A.exps = f->exps;
+    A.coefs = f->coefs;
+    A.enc = enc;
+    A.n = f->nvars;
+    A.X = X;
+    A.N = N;
+    A.out = out;
+    return A;
+}
+
 struct GradPlan {
     FormPlan form;
     size_t jrp, jexps, jcoefs, jenc, part;
     int64_t cap, S;
+    bool fused = false;   // k_deriv_terms straight from the source terms
+    size_t enc = 0;
+    DerivPlan dv;
 };
 
 GradPlan plan_grad(const poly_csr *f, int64_t N, Layout &L)
@@ -520,6 +646,14 @@ GradPlan plan_grad(const poly_csr *f, int64_t N, Layout &L)
     GradPlan g;
     const int n = f->nvars;
     const int64_t P = f->npolys, T = total_terms(f);
+    if (deriv_shape(DM_GRAD, n).ok) {
+        g.fused = true;
+        g.enc = L.take(16 * T);
+        g.dv = plan_deriv(DM_GRAD, n, P, T, N, L);
+        g.cap = 0;
+        g.S = g.dv.S;
+        return g;
+    }
     g.cap = grad_terms_bound(T, n);
     g.form = plan_form(f, n, L);
     g.jrp = L.take(8 * (P * n + 1));
@@ -553,6 +687,16 @@ poly_status run_grad(const poly_csr *f, const double *X, int64_t N, double *G, v
     const int64_t P = f->npolys;
     const int n = f->nvars;
     int32_t *status = at<int32_t>(ws, 0);
+    if (g.fused) {
+        const int64_t T = total_terms(f);
+        uint32_t *enc = at<uint32_t>(ws, g.enc);
+        if (T > 0)
+            hipLaunchKernelGGL(k_encode_factors, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, enc,
+                               (const int64_t *)nullptr);
+        launch_deriv<DM_GRAD>(deriv_args(f, enc, X, N, G), g.dv, ws, s);
+        LAUNCH_CHECK();
+        return POLY_OK;
+    }
     int64_t *jrp = at<int64_t>(ws, g.jrp);
     uint8_t *jexps = at<uint8_t>(ws, g.jexps);
     double *jcoefs = at<double>(ws, g.jcoefs);
@@ -1551,19 +1695,95 @@ poly_status poly_affine_normal(const poly_csr *f, const double *X, int64_t N, do
     return POLY_OK;
 }
 
+namespace {
+
+// Reverse mode of eval: dX from the fused weighted derivative stream when
+// its LDS blocks fit (otherwise the per-polynomial gradients G [P][N][n] and
+// their weighted sum), dC from the support encoding over point chunks.
+struct BackwardPlan {
+    bool fused = false;
+    size_t fenc = 0;        // factor lists (fused dX)
+    DerivPlan dv;
+    GradPlan g;             // unfused dX
+    size_t G = 0;
+    size_t senc = 0, part = 0;   // dC
+    int cp = 0;
+    int64_t nchunks = 0;
+};
+
+BackwardPlan plan_backward(const poly_csr *f, int64_t N, Layout &L)
+{
+    BackwardPlan b;
+    const int n = f->nvars;
+    const int64_t P = f->npolys, T = total_terms(f);
+    if (deriv_shape(DM_DX, n).ok) {
+        b.fused = true;
+        b.fenc = L.take(16 * T);
+        b.dv = plan_deriv(DM_DX, n, P, T, N, L);
+    } else {
+        b.g = plan_grad(f, N, L);
+        b.G = L.take(8 * P * N * n);
+    }
+    b.senc = L.take(16 * T);
+    b.cp = std::max(1, std::min(BWC_POINTS, 8192 / n));
+    b.nchunks = ceil_div(N, b.cp);
+    b.part = L.take(8 * T * b.nchunks);
+    return b;
+}
+
+// Reverse mode of the reverse mode: cotangents u (of dX) and w (of dC).
+struct Backward2Plan {
+    size_t fenc = 0, senc = 0, part = 0;
+    DerivPlan hvp, dx, dird;
+    int cp = 0;
+    int64_t nchunks = 0;
+};
+
+Backward2Plan plan_backward2(const poly_csr *f, int64_t N, Layout &L)
+{
+    Backward2Plan b;
+    const int n = f->nvars;
+    const int64_t P = f->npolys, T = total_terms(f);
+    b.fenc = L.take(16 * T);
+    b.hvp = plan_deriv(DM_HVP, n, P, T, N, L);
+    b.dx = plan_deriv(DM_DX, n, P, T, N, L);
+    b.dird = plan_deriv(DM_DIRD, n, P, T, N, L);
+    b.senc = L.take(16 * T);
+    b.cp = std::max(1, std::min(BWC_POINTS, 4096 / n));
+    b.nchunks = ceil_div(N, b.cp);
+    b.part = L.take(8 * T * b.nchunks);
+    return b;
+}
+
+// dC[t] = sum_pt gY[p(t)][pt] m_t(x_pt) over point chunks, then in chunk order
+void launch_dc(const poly_csr *f, const double *X, int64_t N, const double *gY, double *dC, uint64_t *senc,
+               double *part, int cp, int64_t nchunks, hipStream_t s)
+{
+    const int n = f->nvars;
+    const int64_t P = f->npolys, T = total_terms(f);
+    if (T <= 0) return;
+    if (N == 0) {
+        clear_u64((unsigned long long *)dC, T, s);
+        return;
+    }
+    hipLaunchKernelGGL(k_encode_support, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, senc,
+                       (const int64_t *)nullptr);
+    const size_t lds = (size_t)cp * n * sizeof(double);
+    hipLaunchKernelGGL(k_backward_dc, dim3(grid1(T, BWC_THREADS), (unsigned)nchunks), dim3(BWC_THREADS), lds, s,
+                       f->row_ptr, P, f->exps, n, T, X, N, gY, part, nchunks, (const uint64_t *)senc, cp);
+    hipLaunchKernelGGL(k_backward_dc_reduce, dim3(grid1(T, 256)), dim3(256), 0, s, (const double *)part, T, nchunks,
+                       dC);
+}
+
+}  // namespace
+
 poly_status poly_eval_backward_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)
 {
     poly_status st = check_eval(f, nullptr, 0, nullptr);
     if (st != POLY_OK) return st;
     if (!ws_bytes || N < 0) return POLY_ERR_ARG;
-    const int n = f->nvars;
-    const int64_t P = f->npolys, T = total_terms(f);
     Layout L;
-    plan_grad(f, N, L);
-    L.take(8 * P * N * n);   // G
-    L.take(16 * T);          // encoded support of f
-    const int cp = std::max(1, std::min(BWC_POINTS, 8192 / n));
-    L.take(8 * T * ceil_div(N, cp));
+    plan_backward(f, N, L);
     *ws_bytes = L.total();
     return POLY_OK;
 }
@@ -1576,12 +1796,7 @@ poly_status poly_eval_backward(const poly_csr *f, const double *X, int64_t N, co
     const int n = f->nvars;
     const int64_t P = f->npolys, T = total_terms(f);
     Layout L;
-    const GradPlan g = plan_grad(f, N, L);
-    const size_t o_G = L.take(8 * P * N * n);
-    const size_t o_enc = L.take(16 * T);
-    const int cp = std::max(1, std::min(BWC_POINTS, 8192 / n));
-    const int64_t nchunks = ceil_div(N, cp);
-    const size_t o_part = L.take(8 * T * nchunks);
+    const BackwardPlan b = plan_backward(f, N, L);
     if (!ws || ws_bytes < L.total()) return POLY_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     ensure_lds_attrs();
@@ -1591,25 +1806,101 @@ poly_status poly_eval_backward(const poly_csr *f, const double *X, int64_t N, co
         return POLY_OK;
     }
     if (dX && N > 0) {
-        double *G = at<double>(ws, o_G);
-        st = run_grad(f, X, N, G, ws, g, s);
-        if (st != POLY_OK) return st;
-        hipLaunchKernelGGL(k_backward_dx, dim3(grid1(N * n, 256)), dim3(256), 0, s, G, gY, P, N, n, dX);
-    } else if (dX && N == 0) {
-        // nothing to write
-    }
-    if (dC && T > 0) {
-        if (N == 0) {
-            clear_u64((unsigned long long *)dC, T, s);
+        if (b.fused) {
+            uint32_t *enc = at<uint32_t>(ws, b.fenc);
+            if (T > 0)
+                hipLaunchKernelGGL(k_encode_factors, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, enc,
+                                   (const int64_t *)nullptr);
+            DerivArgs A = deriv_args(f, enc, X, N, dX);
+            A.gY = gY;
+            launch_deriv<DM_DX>(A, b.dv, ws, s);
         } else {
-            uint64_t *enc = at<uint64_t>(ws, o_enc);
-            double *part = at<double>(ws, o_part);
-            hipLaunchKernelGGL(k_encode_support, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, enc,
+            double *G = at<double>(ws, b.G);
+            st = run_grad(f, X, N, G, ws, b.g, s);
+            if (st != POLY_OK) return st;
+            hipLaunchKernelGGL(k_backward_dx, dim3(grid1(N * n, 256)), dim3(256), 0, s, G, gY, P, N, n, dX);
+        }
+    }
+    if (dC) launch_dc(f, X, N, gY, dC, at<uint64_t>(ws, b.senc), at<double>(ws, b.part), b.cp, b.nchunks, s);
+    LAUNCH_CHECK();
+    return POLY_OK;
+}
+
+static poly_status check_backward2(const poly_csr *f, const double *X, int64_t N, const double *gY)
+{
+    poly_status st = check_eval(f, X, N, gY);
+    if (st != POLY_OK) return st;
+    if (!deriv_shape(DM_HVP, f->nvars).ok || !deriv_shape(DM_DIRD, f->nvars).ok) return POLY_ERR_UNSUPPORTED;
+    return POLY_OK;
+}
+
+poly_status poly_eval_backward2_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)
+{
+    poly_status st = check_backward2(f, nullptr, 0, nullptr);
+    if (st != POLY_OK) return st;
+    if (!ws_bytes || N < 0) return POLY_ERR_ARG;
+    Layout L;
+    plan_backward2(f, N, L);
+    *ws_bytes = L.total();
+    return POLY_OK;
+}
+
+poly_status poly_eval_backward2(const poly_csr *f, const double *X, int64_t N, const double *gY, const double *u,
+                                const double *w, double *ggY, double *ggX, double *ggC, void *ws, size_t ws_bytes,
+                                void *stream)
+{
+    poly_status st = check_backward2(f, X, N, gY);
+    if (st != POLY_OK) return st;
+    const int n = f->nvars;
+    const int64_t P = f->npolys, T = total_terms(f);
+    if (T > 0 && (ggX || ggY) && !f->coefs) return POLY_ERR_ARG;
+    Layout L;
+    const Backward2Plan b = plan_backward2(f, N, L);
+    if (!ws || ws_bytes < L.total()) return POLY_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    ensure_lds_attrs();
+    clear_u64(at<unsigned long long>(ws, 0), 1, s);
+    if (P == 0) {
+        LAUNCH_CHECK();
+        return POLY_OK;
+    }
+    uint32_t *enc = at<uint32_t>(ws, b.fenc);
+    if (T > 0 && N > 0 && (ggX || ggY))
+        hipLaunchKernelGGL(k_encode_factors, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, enc,
+                           (const int64_t *)nullptr);
+    if (ggX && N > 0) {
+        DerivArgs A = deriv_args(f, enc, X, N, ggX);
+        A.gY = gY;
+        if (u) {   // c_t u . Hess m_t + w_t grad m_t, weighted by gY
+            A.U = u;
+            A.coefs2 = w;
+            launch_deriv<DM_HVP>(A, b.hvp, ws, s);
+        } else if (w) {   // w_t grad m_t only: the reverse mode of eval with coefficients w
+            A.coefs = w;
+            launch_deriv<DM_DX>(A, b.dx, ws, s);
+        } else {
+            clear_u64((unsigned long long *)ggX, N * n, s);
+        }
+    }
+    if (ggY && N > 0) {
+        DerivArgs A = deriv_args(f, enc, X, N, ggY);
+        A.U = u;
+        A.coefs2 = w;
+        launch_deriv<DM_DIRD>(A, b.dird, ws, s);
+    }
+    if (ggC && T > 0) {
+        if (N == 0 || !u) {
+            clear_u64((unsigned long long *)ggC, T, s);
+        } else {
+            uint64_t *senc = at<uint64_t>(ws, b.senc);
+            double *part = at<double>(ws, b.part);
+            hipLaunchKernelGGL(k_encode_support, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, senc,
                                (const int64_t *)nullptr);
-            const size_t lds = (size_t)cp * n * sizeof(double);
-            hipLaunchKernelGGL(k_backward_dc, dim3(grid1(T, BWC_THREADS), (unsigned)nchunks), dim3(BWC_THREADS), lds,
-                               s, f->row_ptr, P, f->exps, n, T, X, N, gY, part, nchunks, (const uint64_t *)enc, cp);
-            hipLaunchKernelGGL(k_backward_dc_reduce, dim3(grid1(T, 256)), dim3(256), 0, s, part, T, nchunks, dC);
+            const size_t lds = 2 * (size_t)b.cp * n * sizeof(double);
+            hipLaunchKernelGGL(k_backward2_dc, dim3(grid1(T, BWC_THREADS), (unsigned)b.nchunks), dim3(BWC_THREADS),
+                               lds, s, f->row_ptr, P, f->exps, n, T, X, u, N, gY, part, (const uint64_t *)senc, b.cp);
+            hipLaunchKernelGGL(k_backward_dc_reduce, dim3(grid1(T, 256)), dim3(256), 0, s, (const double *)part, T,
+                               b.nchunks, ggC);
         }
     }
     LAUNCH_CHECK();

@@ -222,6 +222,34 @@ constexpr int64_t EV_MIN_SEGMENT = 256;      // fewest terms per segment
 constexpr int64_t EV_MAX_SEGMENTS = 256;
 
 __global__ void k_backward_dx(const double *G, const double *gY, int64_t P, int64_t N, int n, double *dX);
+
+// fused derivative streaming (deriv.hip)
+enum DerivMode { DM_GRAD = 0, DM_DX = 1, DM_HVP = 2, DM_DIRD = 3 };
+struct DerivArgs {
+    const int64_t *rp;        // [P+1] source CSR
+    int64_t P;
+    int64_t T;                // terms (rp[P])
+    const uint8_t *exps;      // [T * n] (terms above EV_MAX_DEG read their dense row)
+    const double *coefs;      // c
+    const double *coefs2;     // w (DM_HVP, DM_DIRD), may be null
+    const uint32_t *enc;      // factor lists (k_encode_factors)
+    int n;
+    const double *X;          // [N * n]
+    int64_t N;
+    const double *gY;         // [P * N] (DM_DX, DM_HVP)
+    const double *U;          // [N * n] direction (DM_HVP, DM_DIRD), may be null for DM_DIRD
+    int64_t S;                // term segments per unit
+    double *out;
+    double *partial;          // S > 1: S slices in the output layout
+};
+template <int MODE>
+__global__ void k_deriv_terms(DerivArgs A);
+__global__ void k_sum_slices(const double *partial, int64_t L, int64_t S, double *out);
+__global__ void k_backward2_dc(const int64_t *rp, int64_t P, const uint8_t *exps, int n, int64_t T, const double *X,
+                               const double *U, int64_t N, const double *gY, double *partial, const uint64_t *enc,
+                               int cp);
+constexpr int DV_ACC_PITCH = 65;                 // doubles per accumulator row (64 points + 1)
+constexpr size_t DV_LDS_MAX = 160 * 1024;        // LDS of one workgroup on gfx950
 constexpr int BWC_THREADS = 256;
 constexpr int BWC_POINTS = 512;   // points per chunk
 __global__ void k_backward_dc(const int64_t *rp, int64_t P, const uint8_t *exps, int n, int64_t T, const double *X,

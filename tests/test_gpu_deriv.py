@@ -1,0 +1,232 @@
+"""Derivatives streamed from the source terms (k_deriv_terms) against the
+oracle's symbolic derivatives, element by element, through the C ABI.
+
+Covered: gradients (poly_grad), the reverse mode of eval (poly_eval_backward,
+dX without per-polynomial gradients), and the reverse mode of that
+(poly_eval_backward2: Hessian-vector products, the directional derivative
+per polynomial, the coefficient cotangent), with term degrees on every branch
+of the kernel (factor lists of up to 4, 8 and 12 positions, dense rows above
+12), constant terms, empty polynomials, point counts that leave a ragged last
+tile, and term segments summed by a second kernel.  Each element must lie
+within 1e-12 times the same quantity built from |c|, |x|, |gY|, |u|, |w|
+(the condition-scaled bound of a sum in another order); with small integers
+everywhere the results are exact and compared bit for bit.  Double backward
+through torch.autograd: gradgradcheck, and Hessians assembled from
+Hessian-vector products against the oracle's Hessians."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ph():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_06575_amd as ph
+    ph.lib()
+    return ph
+
+
+def mixed_polys(rng, n, integer=False):
+    """Polynomials with terms on every degree branch: <= 4, 5..8, 9..12, > 12
+    (dense row), constants, and empty polynomials between them."""
+    polys = []
+    for d, k in ((4, 60), (8, 40), (12, 30), (20, 12), (0, 3)):
+        polys.append(W.random_poly(rng, n, d, k, integer=integer))
+        polys.append((np.zeros((0, n), np.uint8), np.zeros(0)))
+    E = np.concatenate([p[0] for p in polys[:-1:2]])
+    C = np.concatenate([p[1] for p in polys[:-1:2]])
+    perm = rng.permutation(E.shape[0])
+    polys.append((E[perm], C[perm]))   # one polynomial mixing every degree
+    return polys
+
+
+def absbound(*arrs):
+    return [np.abs(a) if a is not None else None for a in arrs]
+
+
+def test_grad_every_degree_branch(ph):
+    rng = W.rng_for(2101)
+    n = 5
+    polys = mixed_polys(rng, n)
+    rp, E, C = W.csr_from_list(polys, n)
+    X = W.points(2102, 130, n)
+    b = ph.batch_from_numpy(rp, E, C, n=n, max_exp=int(E.max()))
+    say(f"grad: {len(polys)} polys, {E.shape[0]} terms, max degree {int(E.sum(axis=1).max())}")
+    G = ph.grad(b, torch.from_numpy(X).cuda(), check=True).cpu().numpy()
+    Go = oracle.grad_batch(rp, E, C, X)
+    bound = 1e-12 * oracle.grad_batch(rp, E, np.abs(C), np.abs(X)) + 1e-300
+    assert (np.abs(G - Go) <= bound).all()
+
+
+def test_grad_segmented_single_poly(ph):
+    # one polynomial and few points: its terms are cut into segments summed in order
+    rng = W.rng_for(2103)
+    n = 7
+    e, c = W.random_poly(rng, n, 6, 6000, integer=False)
+    X = W.points(2104, 70, n)
+    b = ph.batch_from_numpy([0, e.shape[0]], e, c, n=n, max_exp=6)
+    say("grad, one polynomial of 6000 terms at 70 points")
+    G = ph.grad(b, torch.from_numpy(X).cuda(), check=True).cpu().numpy()
+    Go = oracle.grad_batch([0, e.shape[0]], e, c, X)
+    bound = 1e-12 * oracle.grad_batch([0, e.shape[0]], e, np.abs(c), np.abs(X)) + 1e-300
+    assert (np.abs(G - Go) <= bound).all()
+
+
+def test_grad_n20_matrix_entries(ph):
+    wl = W.batch_matrix(seed=2105, entries=40, tmin=5, tmax=900, npts=150)
+    b = ph.simplify(ph.batch_from_numpy(wl.row_ptr, wl.exps, wl.coefs, n=wl.n, max_exp=wl.max_exp))
+    rp, E, C = ph.batch_to_numpy(b)
+    say(f"grad n=20: {b.npolys} entries, {b.nterms} terms, 150 points")
+    G = ph.grad(b, torch.from_numpy(wl.X).cuda(), check=True).cpu().numpy()
+    Go = oracle.grad_batch(rp, E, C, wl.X)
+    bound = 1e-12 * oracle.grad_batch(rp, E, np.abs(C), np.abs(wl.X)) + 1e-300
+    assert (np.abs(G - Go) <= bound).all()
+
+
+def test_grad_past_fused_limit(ph):
+    # n = 200: the accumulator block does not fit beside the point tile; the
+    # formed-Jacobian path takes over with the same results
+    rng = W.rng_for(2106)
+    n = 200
+    polys = [W.random_poly(rng, n, 3, 50, integer=False) for _ in range(2)]
+    rp, E, C = W.csr_from_list(polys, n)
+    X = W.points(2107, 65, n)
+    say("grad n=200")
+    G = ph.grad(ph.batch_from_numpy(rp, E, C, n=n, max_exp=3), torch.from_numpy(X).cuda(), check=True)
+    Go = oracle.grad_batch(rp, E, C, X)
+    bound = 1e-12 * oracle.grad_batch(rp, E, np.abs(C), np.abs(X)) + 1e-300
+    assert (np.abs(G.cpu().numpy() - Go) <= bound).all()
+
+
+@pytest.mark.parametrize("npts", [1, 64, 300])
+def test_eval_backward_dx_weighted(ph, npts):
+    rng = W.rng_for(2110 + npts)
+    n = 4
+    polys = mixed_polys(rng, n)
+    rp, E, C = W.csr_from_list(polys, n)
+    X = W.points(2120 + npts, npts, n)
+    P = len(polys)
+    gY = rng.standard_normal((P, npts))
+    say(f"eval backward: {P} polys, {E.shape[0]} terms, {npts} points")
+    b = ph.batch_from_numpy(rp, E, C, n=n, max_exp=int(E.max()))
+    dX, dC = ph.eval_backward(b, torch.from_numpy(X).cuda(), torch.from_numpy(gY).cuda(), check=True)
+    dXo, dCo = oracle.eval_backward(rp, E, C, X, gY)
+    aX, aC = oracle.eval_backward(rp, E, np.abs(C), np.abs(X), np.abs(gY))
+    assert (np.abs(dX.cpu().numpy() - dXo) <= 1e-12 * aX + 1e-300).all()
+    assert (np.abs(dC.cpu().numpy() - dCo) <= 1e-12 * aC + 1e-300).all()
+
+
+@pytest.mark.parametrize("which", ["u_and_w", "u_only", "w_only"])
+def test_eval_backward2(ph, which):
+    rng = W.rng_for(2130)
+    n = 4
+    polys = mixed_polys(rng, n)
+    rp, E, C = W.csr_from_list(polys, n)
+    N = 150
+    X = W.points(2131, N, n)
+    P = len(polys)
+    gY = rng.standard_normal((P, N))
+    u = rng.standard_normal((N, n)) if which != "w_only" else None
+    w = rng.standard_normal(C.shape[0]) if which != "u_only" else None
+    say(f"eval backward2 ({which}): {P} polys, {E.shape[0]} terms, {N} points")
+    b = ph.batch_from_numpy(rp, E, C, n=n, max_exp=int(E.max()))
+    dev = lambda a: None if a is None else torch.from_numpy(a).cuda()  # noqa: E731
+    ggY, ggX, ggC = ph.eval_backward2(b, dev(X), dev(gY), dev(u), dev(w), check=True)
+    oY, oX, oC = oracle.eval_backward2(rp, E, C, X, gY, u, w)
+    aY, aX, aC = oracle.eval_backward2(rp, E, *absbound(C, X, gY, u, w))
+    assert (np.abs(ggY.cpu().numpy() - oY) <= 1e-12 * aY + 1e-300).all()
+    assert (np.abs(ggX.cpu().numpy() - oX) <= 1e-12 * aX + 1e-300).all()
+    assert (np.abs(ggC.cpu().numpy() - oC) <= 1e-12 * aC + 1e-300).all()
+
+
+def test_eval_backward2_integer_exact(ph):
+    rng = W.rng_for(2140)
+    n = 3
+    polys = [W.random_poly(rng, n, 4, int(k)) for k in (15, 0, 22, 9)]
+    rp, E, C = W.csr_from_list(polys, n)
+    N = 70
+    X = W.integer_points(2141, N, n, -2, 2)
+    gY = rng.integers(-2, 3, size=(4, N)).astype(np.float64)
+    u = rng.integers(-2, 3, size=(N, n)).astype(np.float64)
+    w = rng.integers(-2, 3, size=C.shape[0]).astype(np.float64)
+    say("eval backward2, integers")
+    b = ph.batch_from_numpy(rp, E, C, n=n, max_exp=4)
+    dev = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
+    got = ph.eval_backward2(b, dev(X), dev(gY), dev(u), dev(w))
+    exp = oracle.eval_backward2(rp, E, C, X, gY, u, w)
+    for g, e in zip(got, exp):
+        assert np.array_equal(g.cpu().numpy(), e)
+
+
+def test_eval_backward2_segmented_quartic(ph):
+    # one polynomial, many terms, few points: the weighted streams are cut into segments
+    wl = W.quartic(seed=2150, n=30, terms=20000, npts=100)
+    rp = [0, wl.exps.shape[0]]
+    rng = W.rng_for(2151)
+    gY = rng.standard_normal((1, 100))
+    u = rng.standard_normal((100, 30))
+    w = rng.standard_normal(wl.exps.shape[0])
+    say("eval backward2, quartic n=30, 20000 terms, 100 points")
+    b = ph.batch_from_numpy(rp, wl.exps, wl.coefs, n=30, max_exp=4)
+    dev = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
+    ggY, ggX, ggC = ph.eval_backward2(b, dev(wl.X), dev(gY), dev(u), dev(w), check=True)
+    oY, oX, oC = oracle.eval_backward2(rp, wl.exps, wl.coefs, wl.X, gY, u, w)
+    aY, aX, aC = oracle.eval_backward2(rp, wl.exps, *absbound(wl.coefs, wl.X, gY, u, w))
+    assert (np.abs(ggY.cpu().numpy() - oY) <= 1e-12 * aY + 1e-300).all()
+    assert (np.abs(ggX.cpu().numpy() - oX) <= 1e-12 * aX + 1e-300).all()
+    assert (np.abs(ggC.cpu().numpy() - oC) <= 1e-12 * aC + 1e-300).all()
+
+
+def test_gradgradcheck(ph):
+    rng = W.rng_for(2160)
+    n = 3
+    polys = [W.random_poly(rng, n, 4, 7, integer=False), W.random_poly(rng, n, 3, 5, integer=False)]
+    rp, E, C = W.csr_from_list(polys, n)
+    b = ph.batch_from_numpy(rp, E, C, n=n, max_exp=4)
+    coefs = torch.from_numpy(C).cuda().requires_grad_(True)
+    X = torch.from_numpy(W.points(2161, 4, n)).cuda().requires_grad_(True)
+    say("gradgradcheck")
+    f = lambda c, x: ph.PolyEval.apply(c, x, b)  # noqa: E731
+    assert torch.autograd.gradcheck(f, (coefs, X), eps=1e-6, atol=1e-7, rtol=1e-6)
+    assert torch.autograd.gradgradcheck(f, (coefs, X), eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
+def hessian_by_double_backward(ph, b, X):
+    """H[pt] of a single polynomial from n Hessian-vector products (double
+    backward of PolyEval with u = e_k at every point)."""
+    N, n = X.shape
+    Xr = X.clone().requires_grad_(True)
+    coefs = b.coefs.detach()
+    Y = ph.PolyEval.apply(coefs, Xr, b)
+    (dX,) = torch.autograd.grad(Y, Xr, torch.ones_like(Y), create_graph=True)
+    H = torch.empty((N, n, n), dtype=torch.float64, device=X.device)
+    for k in range(n):
+        u = torch.zeros((N, n), dtype=torch.float64, device=X.device)
+        u[:, k] = 1.0
+        (col,) = torch.autograd.grad(dX, Xr, u, retain_graph=True)
+        H[:, :, k] = col
+    return H
+
+
+def test_hessian_by_double_backward(ph):
+    wl = W.quartic(seed=2170, n=12, terms=1500, npts=200)
+    rp = [0, wl.exps.shape[0]]
+    b = ph.batch_from_numpy(rp, wl.exps, wl.coefs, n=12, max_exp=4)
+    say("Hessian by double backward, quartic n=12, 1500 terms, 200 points")
+    H = hessian_by_double_backward(ph, b, torch.from_numpy(wl.X).cuda()).cpu().numpy()
+    Ho = oracle.hess_batch(rp, wl.exps, wl.coefs, wl.X)[0]
+    Ha = oracle.hess_batch(rp, wl.exps, np.abs(wl.coefs), np.abs(wl.X))[0]
+    assert (np.abs(H - Ho) <= 1e-12 * Ha + 1e-300).all()

@@ -385,6 +385,64 @@ def test_eval_backward_dx_vs_finite_differences():
             assert abs(fd - dX[pt, j]) <= 1e-7 * (1 + abs(fd))
 
 
+def test_eval_backward2_vs_finite_differences_of_eval_backward():
+    """The second-order reverse mode is the gradient of L = <w, dC> + <u, dX>
+    with (dC, dX) from eval_backward: central differences of L in every
+    point coordinate, every cotangent entry and every coefficient."""
+    rng = W.rng_for(131)
+    n = 3
+    polys = [W.random_poly(rng, n, 4, 8, integer=False) for _ in range(2)]
+    rp, E, C = W.csr_from_list(polys, n)
+    X = W.points(132, 4, n)
+    gY = rng.standard_normal((2, 4))
+    u = rng.standard_normal((4, n))
+    w = rng.standard_normal(C.shape[0])
+    ggY, ggX, ggC = oracle.eval_backward2(rp, E, C, X, gY, u, w)
+
+    def L(C_, X_, gY_):
+        dX, dC = oracle.eval_backward(rp, E, C_, X_, gY_)
+        return (w * dC).sum() + (u * dX).sum()
+
+    h = 1e-6
+    for pt in range(4):
+        for j in range(n):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[pt, j] += h
+            Xm[pt, j] -= h
+            fd = (L(C, Xp, gY) - L(C, Xm, gY)) / (2 * h)
+            assert abs(fd - ggX[pt, j]) <= 1e-7 * (1 + abs(fd))
+    for p in range(2):
+        for pt in range(4):
+            gp, gm = gY.copy(), gY.copy()
+            gp[p, pt] += h
+            gm[p, pt] -= h
+            fd = (L(C, X, gp) - L(C, X, gm)) / (2 * h)
+            assert abs(fd - ggY[p, pt]) <= 1e-7 * (1 + abs(fd))
+    for t in range(C.shape[0]):
+        cp, cm = C.copy(), C.copy()
+        cp[t] += h
+        cm[t] -= h
+        fd = (L(cp, X, gY) - L(cm, X, gY)) / (2 * h)
+        assert abs(fd - ggC[t]) <= 1e-7 * (1 + abs(fd))
+
+
+def test_eval_backward2_closed_form():
+    """f = 3 x1^2 x2 - x2 x3^3 at (x1, x2, x3) = (1, 2, -1), gY = 2, u = (1, 0, 1),
+    w = (1, 1): Hess f = [[6 x2, 6 x1, 0], [6 x1, 0, -3 x3^2], [0, -3 x3^2, -6 x2 x3]]
+    = [[12, 6, 0], [6, 0, -3], [0, -3, 12]], so ggX = 2 (H u + grad(x1^2 x2 + x2 x3^3))
+    = 2 ([12, 3, 12] + [2 x1 x2, x1^2 + x3^3, 3 x2 x3^2]) = 2 ([12, 3, 12] + [4, 0, 6]);
+    ggY = grad f . u + (x1^2 x2 + x2 x3^3) = (6 x1 x2 - 3 x2 x3^2) + 0 = 6;
+    ggC = 2 (grad(x1^2 x2) . u, grad(x2 x3^3) . u) = 2 (2 x1 x2, 3 x2 x3^2) = (8, 12)."""
+    E = np.array([[2, 1, 0], [0, 1, 3]], np.uint8)
+    C = np.array([3.0, -1.0])
+    X = np.array([[1.0, 2.0, -1.0]])
+    ggY, ggX, ggC = oracle.eval_backward2([0, 2], E, C, X, np.array([[2.0]]), np.array([[1.0, 0.0, 1.0]]),
+                                          np.array([1.0, 1.0]))
+    assert np.array_equal(ggX, np.array([[32.0, 6.0, 36.0]]))
+    assert np.array_equal(ggY, np.array([[6.0]]))
+    assert np.array_equal(ggC, np.array([8.0, 12.0]))
+
+
 def test_fp64_eval_within_error_bound_of_long_double():
     wl = W.quartic(seed=5, n=12, terms=1500, npts=64)
     rp = [0, wl.exps.shape[0]]
