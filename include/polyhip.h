@@ -114,6 +114,10 @@ poly_status poly_read_status(const void *ws, void *stream);
  *        "simplify_wide_min" largest-entry size from which simplify and mtimes
  *                            merge through the device-wide sort
  *        "eval_blocks_per_cu" point-tile workgroups per CU (sparse eval)
+ *        "deriv_fused_max_n" largest n for which poly_grad and the dX of
+ *                            poly_eval_backward stream derivatives straight
+ *                            from the source terms (0: always through the
+ *                            formed Jacobian)
  * poly_tune_set returns POLY_ERR_ARG for an unknown name or a value outside
  * the tunable's range; values are process-wide and apply to later calls.
  * Workspace sizes depend on them: query the workspace again after a change. */

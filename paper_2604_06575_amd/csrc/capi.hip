@@ -20,6 +20,7 @@ std::atomic<int64_t> g_seg_blocks_per_cu{2};
 std::atomic<int64_t> g_eval_blocks_per_cu{16};
 std::atomic<int64_t> g_mul_sort_min_raw{int64_t(1) << 20};
 std::atomic<int64_t> g_simplify_wide_min{SEG_CAP + 1};
+std::atomic<int64_t> g_deriv_fused_max_n{0};
 
 struct TuneEntry {
     const char *name;
@@ -32,13 +33,14 @@ const TuneEntry kTune[] = {
     {"eval_blocks_per_cu", &g_eval_blocks_per_cu, 1, 64},
     {"mul_sort_min_raw", &g_mul_sort_min_raw, 0, int64_t(1) << 62},
     {"simplify_wide_min", &g_simplify_wide_min, 1, int64_t(1) << 62},
+    {"deriv_fused_max_n", &g_deriv_fused_max_n, 0, 255},
 };
 }  // namespace
 
 Tunables tunables()
 {
     return Tunables{g_mul_bucket_terms.load(), g_seg_blocks_per_cu.load(), g_eval_blocks_per_cu.load(),
-                    g_mul_sort_min_raw.load(), g_simplify_wide_min.load()};
+                    g_mul_sort_min_raw.load(), g_simplify_wide_min.load(), g_deriv_fused_max_n.load()};
 }
 
 }  // namespace polyhip
@@ -615,7 +617,7 @@ void launch_deriv(DerivArgs A, const DerivPlan &d, void *ws, hipStream_t s)
     }
 }
 
-DerivArgs deriv_args(const poly_csr *f, const uint32_t *enc, const double *X, int64_t N, double *out)
+DerivArgs deriv_args(const poly_csr *f, const uint64_t *enc, const double *X, int64_t N, double *out)
 {
     DerivArgs A;
     memset(&A, 0, sizeof(A));
@@ -641,12 +643,38 @@ struct GradPlan {
     DerivPlan dv;
 };
 
+// The Jacobian formed in the workspace (source order kept), encoded as
+// factor lists; the partials of its evaluation: per polynomial and point
+// (gradients, wsum == false) or per segment of polynomials, point and
+// variable (the weighted sum over polynomials of the reverse mode).
+GradPlan plan_grad_formed(const poly_csr *f, int64_t N, Layout &L, bool wsum)
+{
+    GradPlan g;
+    const int n = f->nvars;
+    const int64_t P = f->npolys, T = total_terms(f);
+    g.cap = grad_terms_bound(T, n);
+    g.form = plan_form(f, n, L);
+    g.jrp = L.take(8 * (P * n + 1));
+    g.jexps = L.take((size_t)g.cap * n);
+    g.jcoefs = L.take(8 * g.cap);
+    g.jenc = L.take(16 * g.cap);
+    if (wsum) {
+        const int64_t per = ceil_div(std::max<int64_t>(N, 1), kWave) * n;
+        g.S = std::max<int64_t>(1, std::min<int64_t>({ceil_div(EV_TARGET_WAVES, per), P, 256}));
+        g.part = L.take(g.S > 1 ? (size_t)8 * g.S * N * n : 0);
+    } else {
+        g.S = eval_segments(P * n, N, T);
+        g.part = L.take(eval_partial_bytes(P * n, N, g.S));
+    }
+    return g;
+}
+
 GradPlan plan_grad(const poly_csr *f, int64_t N, Layout &L)
 {
     GradPlan g;
     const int n = f->nvars;
     const int64_t P = f->npolys, T = total_terms(f);
-    if (deriv_shape(DM_GRAD, n).ok) {
+    if (n <= tunables().deriv_fused_max_n && deriv_shape(DM_GRAD, n).ok) {
         g.fused = true;
         g.enc = L.take(16 * T);
         g.dv = plan_deriv(DM_GRAD, n, P, T, N, L);
@@ -654,15 +682,7 @@ GradPlan plan_grad(const poly_csr *f, int64_t N, Layout &L)
         g.S = g.dv.S;
         return g;
     }
-    g.cap = grad_terms_bound(T, n);
-    g.form = plan_form(f, n, L);
-    g.jrp = L.take(8 * (P * n + 1));
-    g.jexps = L.take((size_t)g.cap * n);
-    g.jcoefs = L.take(8 * g.cap);
-    g.jenc = L.take(16 * g.cap);
-    g.S = eval_segments(P * n, N, T);
-    g.part = L.take(eval_partial_bytes(P * n, N, g.S));
-    return g;
+    return plan_grad_formed(f, N, L, false);
 }
 
 FormArgs form_args(const int64_t *rp, const uint8_t *exps, const double *coefs, int n, int mode, int keep_coefs,
@@ -681,22 +701,13 @@ FormArgs form_args(const int64_t *rp, const uint8_t *exps, const double *coefs, 
     return A;
 }
 
-poly_status run_grad(const poly_csr *f, const double *X, int64_t N, double *G, void *ws, const GradPlan &g,
-                     hipStream_t s)
+// Forms the Jacobian of f in the workspace and encodes it; returns the
+// evaluation arguments over it (mode and output left to the caller).
+EvalArgs form_jacobian(const poly_csr *f, const double *X, int64_t N, void *ws, const GradPlan &g, hipStream_t s)
 {
     const int64_t P = f->npolys;
     const int n = f->nvars;
     int32_t *status = at<int32_t>(ws, 0);
-    if (g.fused) {
-        const int64_t T = total_terms(f);
-        uint32_t *enc = at<uint32_t>(ws, g.enc);
-        if (T > 0)
-            hipLaunchKernelGGL(k_encode_factors, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, enc,
-                               (const int64_t *)nullptr);
-        launch_deriv<DM_GRAD>(deriv_args(f, enc, X, N, G), g.dv, ws, s);
-        LAUNCH_CHECK();
-        return POLY_OK;
-    }
     int64_t *jrp = at<int64_t>(ws, g.jrp);
     uint8_t *jexps = at<uint8_t>(ws, g.jexps);
     double *jcoefs = at<double>(ws, g.jcoefs);
@@ -709,7 +720,6 @@ poly_status run_grad(const poly_csr *f, const double *X, int64_t N, double *G, v
     run_form(g.form, F, ws, s);
     hipLaunchKernelGGL(k_encode_factors, dim3(grid1(g.cap, 256)), dim3(256), 0, s, jexps, g.cap, n, jenc,
                        (const int64_t *)(jrp + P * n));
-    LAUNCH_CHECK();
     EvalArgs A;
     memset(&A, 0, sizeof(A));
     A.rp = jrp;
@@ -719,10 +729,54 @@ poly_status run_grad(const poly_csr *f, const double *X, int64_t N, double *G, v
     A.X = X;
     A.N = N;
     A.Q = P * n;
+    A.term_limit = g.cap;
+    return A;
+}
+
+poly_status run_grad(const poly_csr *f, const double *X, int64_t N, double *G, void *ws, const GradPlan &g,
+                     hipStream_t s)
+{
+    const int64_t P = f->npolys;
+    const int n = f->nvars;
+    int32_t *status = at<int32_t>(ws, 0);
+    if (g.fused) {
+        const int64_t T = total_terms(f);
+        uint64_t *enc = at<uint64_t>(ws, g.enc);
+        if (T > 0)
+            hipLaunchKernelGGL(k_encode_support, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, enc,
+                               (const int64_t *)nullptr);
+        launch_deriv<DM_GRAD>(deriv_args(f, enc, X, N, G), g.dv, ws, s);
+        LAUNCH_CHECK();
+        return POLY_OK;
+    }
+    EvalArgs A = form_jacobian(f, X, N, ws, g, s);
     A.mode = OUT_GRAD;
     A.Y = G;
-    A.term_limit = g.cap;
-    launch_eval_blocks(A, jenc, at<double>(ws, g.part), g.S, s);
+    launch_eval_blocks(A, at<uint32_t>(ws, g.jenc), at<double>(ws, g.part), g.S, s);
+    LAUNCH_CHECK();
+    return POLY_OK;
+}
+
+// dX[pt][j] = sum_p gY[p][pt] J_{p,j}(x_pt) from the formed Jacobian (no
+// per-polynomial gradients are stored).
+poly_status run_wsum(const poly_csr *f, const double *X, int64_t N, const double *gY, double *dX, void *ws,
+                     const GradPlan &g, hipStream_t s)
+{
+    EvalArgs A = form_jacobian(f, X, N, ws, g, s);
+    const int n = f->nvars;
+    const unsigned gx = (unsigned)ceil_div(N, kWave);
+    const int64_t units = (int64_t)n * g.S;
+    const int64_t want = std::max<int64_t>(1, ((int64_t)device_cus() * tunables().eval_blocks_per_cu + gx - 1) / gx);
+    const unsigned gy = (unsigned)std::min<int64_t>(std::min<int64_t>(ceil_div(units, EV_WAVES), want), 65535);
+    const size_t lds = (size_t)(n + 1) * kWave * sizeof(double);
+    double *part = g.S > 1 ? at<double>(ws, g.part) : nullptr;
+    TimedLaunch tl(POLY_TIMING_TERMS, s);
+    hipLaunchKernelGGL(k_eval_wsum, dim3(gx, gy), dim3(EV_THREADS), lds, s, A, (const uint32_t *)at<uint32_t>(ws, g.jenc),
+                       gY, f->npolys, g.S, dX, part);
+    tl.done(s);
+    if (g.S > 1)
+        hipLaunchKernelGGL(k_sum_slices, dim3(grid1(N * n, 256)), dim3(256), 0, s, (const double *)part, N * n, g.S,
+                           dX);
     LAUNCH_CHECK();
     return POLY_OK;
 }
@@ -1697,15 +1751,15 @@ poly_status poly_affine_normal(const poly_csr *f, const double *X, int64_t N, do
 
 namespace {
 
-// Reverse mode of eval: dX from the fused weighted derivative stream when
-// its LDS blocks fit (otherwise the per-polynomial gradients G [P][N][n] and
-// their weighted sum), dC from the support encoding over point chunks.
+// Reverse mode of eval: dX from the weighted derivative stream over the
+// source terms (n up to the deriv_fused_max_n tunable) or over the formed
+// Jacobian (k_eval_wsum); neither stores per-polynomial gradients.  dC from
+// the support encoding over point chunks.
 struct BackwardPlan {
     bool fused = false;
     size_t fenc = 0;        // factor lists (fused dX)
     DerivPlan dv;
-    GradPlan g;             // unfused dX
-    size_t G = 0;
+    GradPlan g;             // dX from the formed Jacobian
     size_t senc = 0, part = 0;   // dC
     int cp = 0;
     int64_t nchunks = 0;
@@ -1716,13 +1770,12 @@ BackwardPlan plan_backward(const poly_csr *f, int64_t N, Layout &L)
     BackwardPlan b;
     const int n = f->nvars;
     const int64_t P = f->npolys, T = total_terms(f);
-    if (deriv_shape(DM_DX, n).ok) {
+    if (n <= tunables().deriv_fused_max_n && deriv_shape(DM_DX, n).ok) {
         b.fused = true;
         b.fenc = L.take(16 * T);
         b.dv = plan_deriv(DM_DX, n, P, T, N, L);
     } else {
-        b.g = plan_grad(f, N, L);
-        b.G = L.take(8 * P * N * n);
+        b.g = plan_grad_formed(f, N, L, true);
     }
     b.senc = L.take(16 * T);
     b.cp = std::max(1, std::min(BWC_POINTS, 8192 / n));
@@ -1807,18 +1860,16 @@ poly_status poly_eval_backward(const poly_csr *f, const double *X, int64_t N, co
     }
     if (dX && N > 0) {
         if (b.fused) {
-            uint32_t *enc = at<uint32_t>(ws, b.fenc);
+            uint64_t *enc = at<uint64_t>(ws, b.fenc);
             if (T > 0)
-                hipLaunchKernelGGL(k_encode_factors, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, enc,
+                hipLaunchKernelGGL(k_encode_support, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, enc,
                                    (const int64_t *)nullptr);
             DerivArgs A = deriv_args(f, enc, X, N, dX);
             A.gY = gY;
             launch_deriv<DM_DX>(A, b.dv, ws, s);
         } else {
-            double *G = at<double>(ws, b.G);
-            st = run_grad(f, X, N, G, ws, b.g, s);
+            st = run_wsum(f, X, N, gY, dX, ws, b.g, s);
             if (st != POLY_OK) return st;
-            hipLaunchKernelGGL(k_backward_dx, dim3(grid1(N * n, 256)), dim3(256), 0, s, G, gY, P, N, n, dX);
         }
     }
     if (dC) launch_dc(f, X, N, gY, dC, at<uint64_t>(ws, b.senc), at<double>(ws, b.part), b.cp, b.nchunks, s);
@@ -1864,9 +1915,9 @@ poly_status poly_eval_backward2(const poly_csr *f, const double *X, int64_t N, c
         LAUNCH_CHECK();
         return POLY_OK;
     }
-    uint32_t *enc = at<uint32_t>(ws, b.fenc);
+    uint64_t *enc = at<uint64_t>(ws, b.fenc);
     if (T > 0 && N > 0 && (ggX || ggY))
-        hipLaunchKernelGGL(k_encode_factors, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, enc,
+        hipLaunchKernelGGL(k_encode_support, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, enc,
                            (const int64_t *)nullptr);
     if (ggX && N > 0) {
         DerivArgs A = deriv_args(f, enc, X, N, ggX);

@@ -3,20 +3,19 @@
 // and its own reverse mode for autograd).
 //
 // Points sit in lanes (64 per wave, their coordinates in an LDS tile shared
-// by the workgroup); terms are streamed wave-uniformly as factor lists (the
-// variable indices of a monomial with repetition, ascending, padded with the
-// index of an LDS row of ones).  For factor values f_0..f_{d-1} of a term with
-// coefficient c, a variable j occupying e_j consecutive positions starting at
-// a has
-//     d m / d x_j = e_j * prod_{i != a} f_i,
-// and for two variables j != k starting at a < b
-//     d^2 m / dx_j dx_k = e_j e_k * prod_{i != a, b} f_i,
-//     d^2 m / dx_j^2   = e_j (e_j - 1) * prod_{i != a, a+1} f_i,
-// the products over the remaining positions taken from prefix and suffix
-// products of the list, so no derivative polynomial is formed or sorted.
+// by the workgroup); terms are streamed wave-uniformly in the support
+// encoding: up to eight (variable, exponent) slots.  For a monomial
+// m = prod_s x_{v_s}^{e_s} with p_s = x_{v_s}^{e_s} and q_s = x_{v_s}^{e_s - 1},
+//     d m / dx_{v_a} = e_a q_a prod_{s != a} p_s,
+//     d^2 m / dx_{v_a} dx_{v_b} = e_a e_b q_a q_b prod_{s != a, b} p_s      (a != b),
+//     d^2 m / dx_{v_a}^2 = e_a (e_a - 1) x_{v_a}^{e_a - 2} prod_{s != a} p_s,
+// the products over the other slots taken from prefix and suffix products,
+// so no derivative polynomial is formed or sorted and the per-term
+// bookkeeping is a handful of scalar instructions per slot.
 // Per-point results that are n-vectors (gradients, dX, Hessian-vector
 // products) accumulate in a wave-private LDS block [n][65] (lane = point
-// column) and leave in output order with whole-wave contiguous stores.
+// column) by LDS adds, and leave in output order with whole-wave contiguous
+// stores.
 //
 // Modes:
 //   DM_GRAD  G[p][pt][j]  = sum_{t in p} c_t d m_t / dx_j            (poly_grad)
@@ -24,7 +23,7 @@
 //   DM_HVP   ggX[pt][j]   = sum_t gY[p(t)][pt] (c_t sum_k u[pt][k] d2 m_t / dx_j dx_k
 //                                               + w_t d m_t / dx_j)  (poly_eval_backward2)
 //   DM_DIRD  ggY[p][pt]   = sum_{t in p} (c_t sum_k u[pt][k] d m_t / dx_k + w_t m_t)
-// Terms of degree above EV_MAX_DEG are handled from their dense exponent row.
+// Terms with more than eight variables are handled from their dense exponent row.
 #include "kernels.h"
 
 namespace polyhip {
@@ -47,92 +46,108 @@ struct ModeTraits {
     static constexpr bool dir = MODE == DM_HVP || MODE == DM_DIRD;      // reads the direction u
 };
 
-// Contribution of one term of degree d <= NP (NP = 4, 8 or 12 list positions,
-// positions >= d hold the padding index, whose value is 1.0).
-template <int NP, int MODE>
-__device__ inline void term_fact(const DerivArgs &A, const uint32_t wd[3], int d, double c, double w2, double wgt,
-                                 const double *xl, const double *ul, double *al, double &sacc)
+// acc += v at a wave-private LDS slot (no value returned; the LDS applies the
+// adds of one wave in program order, so sums do not depend on scheduling)
+__device__ inline void lds_add(double *p, double v)
 {
-    int var[NP];
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// Contribution of one term with at most NS (4 or 8) variables, given as
+// (variable, exponent) slots in the words of its support encoding (unused
+// slots are zero: exponent 0, read as x^0 = 1).  Per slot s: p_s = x^e,
+// q_s = x^(e-1), r_s = x^(e-2); prefix/suffix products of the p_s give every
+// product over all slots but one or two.  The coordinates of all slots are
+// read from LDS before any arithmetic, so the reads overlap.
+template <int NS, int MODE>
+__device__ inline void term_supp(const uint32_t wd[4], double c, double w2, double wgt, const double *xl,
+                                 const double *ul, double *al, double &sacc)
+{
+    int var[NS], ex[NS];
 #pragma unroll
-    for (int k = 0; k < NP; ++k) var[k] = (int)((wd[k >> 2] >> (8 * (k & 3))) & 0xffu);
-    double f[NP];
-#pragma unroll
-    for (int k = 0; k < NP; ++k) f[k] = xl[var[k] * kWave];
-    // run starts and lengths (uniform)
-    bool st[NP];
-    int e[NP];
-#pragma unroll
-    for (int a = 0; a < NP; ++a) {
-        st[a] = a < d && (a == 0 || var[a] != var[a - 1]);
-        int cnt = 1;
-#pragma unroll
-        for (int b = a + 1; b < NP; ++b) cnt += (b < d && var[b] == var[a]) ? 1 : 0;
-        e[a] = cnt;
+    for (int k = 0; k < NS; ++k) {
+        const uint32_t ent = (wd[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+        var[k] = (int)(ent & 0xffu);
+        ex[k] = (int)(ent >> 8);
     }
-    double pre[NP + 1], suf[NP + 1];
+    double x[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) x[k] = xl[var[k] * kWave];
+    double p[NS], q[NS], r[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        double qq = 1.0, rr = 1.0;
+        for (int i = 1; i < ex[k]; ++i) {
+            rr = qq;
+            qq = qq * x[k];
+        }
+        q[k] = qq;
+        r[k] = rr;
+        p[k] = ex[k] ? qq * x[k] : 1.0;
+    }
+    double pre[NS + 1], suf[NS + 1];
     pre[0] = 1.0;
+    suf[NS] = 1.0;
 #pragma unroll
-    for (int k = 0; k < NP; ++k) pre[k + 1] = pre[k] * f[k];
-    suf[NP] = 1.0;
+    for (int k = 0; k < NS; ++k) pre[k + 1] = pre[k] * p[k];
 #pragma unroll
-    for (int k = NP - 1; k >= 0; --k) suf[k] = f[k] * suf[k + 1];
+    for (int k = NS - 1; k >= 0; --k) suf[k] = p[k] * suf[k + 1];
     if constexpr (MODE == DM_GRAD || MODE == DM_DX) {
 #pragma unroll
-        for (int a = 0; a < NP; ++a) {
-            if (st[a]) {
-                const double v = (c * (double)e[a]) * (pre[a] * suf[a + 1]);
-                double *p = al + var[a] * DV_ACC_LD;
-                if constexpr (MODE == DM_GRAD) *p += v;
-                else *p = __builtin_fma(wgt, v, *p);
+        for (int k = 0; k < NS; ++k) {
+            if (ex[k]) {
+                const double v = (c * (double)ex[k]) * ((q[k] * pre[k]) * suf[k + 1]);
+                if constexpr (MODE == DM_GRAD) lds_add(al + var[k] * DV_ACC_LD, v);
+                else lds_add(al + var[k] * DV_ACC_LD, wgt * v);
             }
         }
     } else if constexpr (MODE == DM_DIRD) {
-        double s = 0.0;
+        double u[NS];
 #pragma unroll
-        for (int a = 0; a < NP; ++a)
-            if (st[a]) s = __builtin_fma(ul[var[a] * kWave], (double)e[a] * (pre[a] * suf[a + 1]), s);
-        sacc = __builtin_fma(c, s, sacc);
-        sacc = __builtin_fma(w2, pre[NP], sacc);
+        for (int k = 0; k < NS; ++k) u[k] = ul[var[k] * kWave];
+        double sd = 0.0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+            if (ex[k]) sd = __builtin_fma(u[k], (double)ex[k] * ((q[k] * pre[k]) * suf[k + 1]), sd);
+        sacc = __builtin_fma(c, sd, sacc);
+        sacc = __builtin_fma(w2, pre[NS], sacc);
     } else {   // DM_HVP
-        double u[NP], hv[NP];
+        double u[NS], hv[NS];
 #pragma unroll
-        for (int a = 0; a < NP; ++a) {
-            u[a] = st[a] ? ul[var[a] * kWave] : 0.0;
-            hv[a] = 0.0;
+        for (int k = 0; k < NS; ++k) {
+            u[k] = ul[var[k] * kWave];
+            hv[k] = 0.0;
         }
 #pragma unroll
-        for (int a = 0; a < NP; ++a) {
-            if (!st[a]) continue;
-            // the same variable twice: positions a and a + 1
-            if (a + 1 < NP && e[a] >= 2) {
-                const double h = (double)(e[a] * (e[a] - 1)) * (pre[a] * suf[a + 2]);
+        for (int a = 0; a < NS; ++a) {
+            if (!ex[a]) continue;
+            if (ex[a] >= 2) {   // d2 / dx_j^2: e (e - 1) x^(e-2) times the other slots
+                const double h = (double)(ex[a] * (ex[a] - 1)) * ((r[a] * pre[a]) * suf[a + 1]);
                 hv[a] = __builtin_fma(u[a], h, hv[a]);
             }
-            double mid = 1.0;   // product of positions strictly between a and b
+            double mid = 1.0;   // product of the slots strictly between a and b
 #pragma unroll
-            for (int b = a + 1; b < NP; ++b) {
-                if (st[b]) {
-                    const double h = (double)(e[a] * e[b]) * ((pre[a] * mid) * suf[b + 1]);
+            for (int b = a + 1; b < NS; ++b) {
+                if (ex[b]) {
+                    const double h = (double)(ex[a] * ex[b]) * (((q[a] * q[b]) * (pre[a] * mid)) * suf[b + 1]);
                     hv[a] = __builtin_fma(u[b], h, hv[a]);
                     hv[b] = __builtin_fma(u[a], h, hv[b]);
                 }
-                mid = mid * f[b];
+                mid = mid * p[b];
             }
         }
 #pragma unroll
-        for (int a = 0; a < NP; ++a) {
-            if (st[a]) {
-                double v = c * hv[a];
-                v = __builtin_fma(w2 * (double)e[a], pre[a] * suf[a + 1], v);
-                double *p = al + var[a] * DV_ACC_LD;
-                *p = __builtin_fma(wgt, v, *p);
+        for (int k = 0; k < NS; ++k) {
+            if (ex[k]) {
+                double v = c * hv[k];
+                v = __builtin_fma(w2 * (double)ex[k], (q[k] * pre[k]) * suf[k + 1], v);
+                lds_add(al + var[k] * DV_ACC_LD, wgt * v);
             }
         }
     }
 }
 
-// Terms of degree above EV_MAX_DEG: the same quantities from the dense row.
+// Terms with more than eight variables: the same quantities from the dense row.
 template <int MODE>
 __device__ inline void term_dense(const DerivArgs &A, int64_t t, double c, double w2, double wgt, const double *xl,
                                   const double *ul, double *al, double &sacc)
@@ -156,9 +171,8 @@ __device__ inline void term_dense(const DerivArgs &A, int64_t t, double c, doubl
             const int ej = row[j];
             if (!ej) continue;
             const double v = (c * (double)ej) * reduced(j, -1);
-            double *p = al + j * DV_ACC_LD;
-            if constexpr (MODE == DM_GRAD) *p += v;
-            else *p = __builtin_fma(wgt, v, *p);
+            if constexpr (MODE == DM_GRAD) lds_add(al + j * DV_ACC_LD, v);
+            else lds_add(al + j * DV_ACC_LD, wgt * v);
         }
     } else if constexpr (MODE == DM_DIRD) {
         double s = 0.0;
@@ -181,10 +195,18 @@ __device__ inline void term_dense(const DerivArgs &A, int64_t t, double c, doubl
             }
             double v = c * hv;
             v = __builtin_fma(w2 * (double)ej, reduced(j, -1), v);
-            double *p = al + j * DV_ACC_LD;
-            *p = __builtin_fma(wgt, v, *p);
+            lds_add(al + j * DV_ACC_LD, wgt * v);
         }
     }
+}
+
+// value of v in lane k (k uniform)
+__device__ inline double readlane_f64(double v, int k)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, k);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), k);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 // the polynomial holding term t: largest q with rp[q] <= t (rp nondecreasing)
@@ -239,12 +261,10 @@ __global__ void __launch_bounds__(512) k_deriv_terms(DerivArgs A)
     const double *xl = s_x + lane;
     const double *ul = s_u + lane;
     double *al = s_acc + lane;
-    int vz;   // a zero the compiler treats as per-lane: term records are fetched by vector loads
-    asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
     const int64_t S = A.S;
     const int64_t units = TR::weighted ? S : A.P * S;
     const int64_t ustride = (int64_t)gridDim.y * W;
-    const uint4 *enc = reinterpret_cast<const uint4 *>(A.enc);
+    const uint4 *enc = reinterpret_cast<const uint4 *>(A.enc);   // support encoding, 16 bytes per term
     for (int64_t u = (int64_t)blockIdx.y * W + w; u < units; u += ustride) {
         int64_t q, sg, ta, tb;
         if constexpr (TR::weighted) {
@@ -264,50 +284,57 @@ __global__ void __launch_bounds__(512) k_deriv_terms(DerivArgs A)
         double wgt = 1.0;
         if constexpr (TR::weighted) wgt = pt < N ? A.gY[q * N + pt] : 0.0;
         double sacc = 0.0;
-        uint4 cw = make_uint4(0, 0, 0, 0);
-        double cc = 0.0, cw2 = 0.0;
-        if (ta < tb) {
-            cw = enc[ta + vz];
-            cc = A.coefs[ta + vz];
-            if (A.coefs2) cw2 = A.coefs2[ta + vz];
+        // Term records travel in groups of 64: lane l loads the record of term
+        // g0 + l (one coalesced load per field), each term is then read out of
+        // its lane into scalar registers, and the next group's loads are in
+        // flight while the current group is evaluated.
+        uint4 gw = make_uint4(0, 0, 0, 0);
+        double gc = 0.0, gc2 = 0.0;
+        if (ta + lane < tb) {
+            gw = enc[ta + lane];
+            gc = A.coefs[ta + lane];
+            if (A.coefs2) gc2 = A.coefs2[ta + lane];
         }
-        for (int64_t t = ta; t < tb; ++t) {
-            // next term's record in flight while this one is evaluated
-            uint4 nw = cw;
-            double nc = cc, nw2 = cw2;
-            if (t + 1 < tb) {
-                nw = enc[t + 1 + vz];
-                nc = A.coefs[t + 1 + vz];
-                if (A.coefs2) nw2 = A.coefs2[t + 1 + vz];
+        for (int64_t g0 = ta; g0 < tb; g0 += kWave) {
+            uint4 hw = make_uint4(0, 0, 0, 0);
+            double hc = 0.0, hc2 = 0.0;
+            const int64_t tn = g0 + kWave + lane;
+            if (tn < tb) {
+                hw = enc[tn];
+                hc = A.coefs[tn];
+                if (A.coefs2) hc2 = A.coefs2[tn];
             }
-            if constexpr (TR::weighted) {
-                if (t >= qend) {
-                    do {
-                        ++q;
-                        qend = A.rp[q + 1];
-                    } while (t >= qend);
-                    wgt = pt < N ? A.gY[q * N + pt] : 0.0;
+            const int cnt = (int)(tb - g0 < kWave ? tb - g0 : kWave);
+            for (int k = 0; k < cnt; ++k) {
+                const int64_t t = g0 + k;
+                if constexpr (TR::weighted) {
+                    if (t >= qend) {
+                        do {
+                            ++q;
+                            qend = A.rp[q + 1];
+                        } while (t >= qend);
+                        wgt = pt < N ? A.gY[q * N + pt] : 0.0;
+                    }
+                }
+                const uint32_t wd[4] = {(uint32_t)__builtin_amdgcn_readlane((int)gw.x, k),
+                                        (uint32_t)__builtin_amdgcn_readlane((int)gw.y, k),
+                                        (uint32_t)__builtin_amdgcn_readlane((int)gw.z, k),
+                                        (uint32_t)__builtin_amdgcn_readlane((int)gw.w, k)};
+                const double c = readlane_f64(gc, k);
+                const double w2 = A.coefs2 ? readlane_f64(gc2, k) : 0.0;
+                if ((wd[0] & 0xffffu) == 0xffffu) {   // more than eight variables: the dense row
+                    term_dense<MODE>(A, t, c, w2, wgt, xl, ul, al, sacc);
+                } else if (wd[0] == 0) {   // a constant term: m = 1, no derivatives
+                    if constexpr (MODE == DM_DIRD) sacc += w2;
+                } else if ((wd[2] | wd[3]) == 0) {   // at most four variables
+                    term_supp<4, MODE>(wd, c, w2, wgt, xl, ul, al, sacc);
+                } else {
+                    term_supp<8, MODE>(wd, c, w2, wgt, xl, ul, al, sacc);
                 }
             }
-            const uint32_t d = __builtin_amdgcn_readfirstlane(cw.w);
-            const uint32_t wd[3] = {(uint32_t)__builtin_amdgcn_readfirstlane(cw.x),
-                                    (uint32_t)__builtin_amdgcn_readfirstlane(cw.y),
-                                    (uint32_t)__builtin_amdgcn_readfirstlane(cw.z)};
-            const double c = cc, w2 = cw2;
-            if (d == 0) {
-                if constexpr (MODE == DM_DIRD) sacc += w2;   // a constant term: m = 1, no derivatives
-            } else if (d <= 4) {
-                term_fact<4, MODE>(A, wd, (int)d, c, w2, wgt, xl, ul, al, sacc);
-            } else if (d <= 8) {
-                term_fact<8, MODE>(A, wd, (int)d, c, w2, wgt, xl, ul, al, sacc);
-            } else if (d <= (uint32_t)EV_MAX_DEG) {
-                term_fact<EV_MAX_DEG, MODE>(A, wd, (int)d, c, w2, wgt, xl, ul, al, sacc);
-            } else {
-                term_dense<MODE>(A, t, c, w2, wgt, xl, ul, al, sacc);
-            }
-            cw = nw;
-            cc = nc;
-            cw2 = nw2;
+            gw = hw;
+            gc = hc;
+            gc2 = hc2;
         }
         // result of the unit
         if constexpr (TR::acc) {

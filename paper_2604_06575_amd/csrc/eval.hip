@@ -321,57 +321,57 @@ __device__ inline double chunk4(double v, uint32_t word, const double *xl)
     return (((v * x0) * x1) * x2) * x3;
 }
 
-constexpr int EV_GROUP = 2;   // terms per load group
+// value of v in lane k (k uniform)
+__device__ inline double lane_f64(double v, int k)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, k);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), k);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
 
-// Sum of c_t * m_t(x) over terms [ta, tb), in term order.  Term records are
-// fetched with vector loads from an offset the compiler cannot see to be
-// uniform, so they are tracked by the in-order vector-memory counter and the
-// next group's loads stay in flight while the current group is evaluated.
+// Sum of c_t * m_t(x) over terms [ta, tb), in term order.  Term records
+// travel in groups of 64: lane l loads the record of term g0 + l (one
+// coalesced load per field), each term is read out of its lane into scalar
+// registers, and the next group's loads are in flight while the current
+// group is evaluated.  Only the factor words a term's degree needs are read.
 __device__ inline double term_range(const EvalArgs &A, const uint32_t *enc, int64_t ta, int64_t tb,
-                                    const double *xl, int vz)
+                                    const double *xl)
 {
     double acc = 0.0;
-    if (ta >= tb) return acc;
     const uint4 *ev = reinterpret_cast<const uint4 *>(enc);
-    uint4 w[EV_GROUP];
-    double c[EV_GROUP];
-#pragma unroll
-    for (int k = 0; k < EV_GROUP; ++k) {
-        const int64_t t = (ta + k < tb ? ta + k : tb - 1) + vz;
-        w[k] = ev[t];
-        c[k] = A.coefs[t];
+    const int lane = lane_id();
+    uint4 gw = make_uint4(0, 0, 0, 0);
+    double gc = 0.0;
+    if (ta + lane < tb) {
+        gw = ev[ta + lane];
+        gc = A.coefs[ta + lane];
     }
-    for (int64_t t0 = ta; t0 < tb; t0 += EV_GROUP) {
-        uint4 nw[EV_GROUP];
-        double nc[EV_GROUP];
-        const int64_t tn = t0 + EV_GROUP;
-#pragma unroll
-        for (int k = 0; k < EV_GROUP; ++k) {
-            const int64_t t = (tn + k < tb ? tn + k : tb - 1) + vz;
-            nw[k] = ev[t];
-            nc[k] = A.coefs[t];
+    for (int64_t g0 = ta; g0 < tb; g0 += kWave) {
+        uint4 hw = make_uint4(0, 0, 0, 0);
+        double hc = 0.0;
+        const int64_t tn = g0 + kWave + lane;
+        if (tn < tb) {
+            hw = ev[tn];
+            hc = A.coefs[tn];
         }
-#pragma unroll
-        for (int k = 0; k < EV_GROUP; ++k) {
-            if (t0 + k < tb) {
-                const uint32_t d = __builtin_amdgcn_readfirstlane(w[k].w);
-                double v;
-                if (d <= (uint32_t)EV_MAX_DEG) {
-                    v = 1.0;
-                    if (d > 0) v = chunk4(v, __builtin_amdgcn_readfirstlane(w[k].x), xl);
-                    if (d > 4) v = chunk4(v, __builtin_amdgcn_readfirstlane(w[k].y), xl);
-                    if (d > 8) v = chunk4(v, __builtin_amdgcn_readfirstlane(w[k].z), xl);
-                } else {
-                    v = monomial_dense(A.exps + (t0 + k) * A.n, A.n, xl);
-                }
-                acc += c[k] * v;
+        const int cnt = (int)(tb - g0 < kWave ? tb - g0 : kWave);
+        for (int k = 0; k < cnt; ++k) {
+            const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)gw.w, k);
+            const double c = lane_f64(gc, k);
+            double v;
+            if (d <= (uint32_t)EV_MAX_DEG) {
+                v = 1.0;
+                if (d > 0) v = chunk4(v, (uint32_t)__builtin_amdgcn_readlane((int)gw.x, k), xl);
+                if (d > 4) v = chunk4(v, (uint32_t)__builtin_amdgcn_readlane((int)gw.y, k), xl);
+                if (d > 8) v = chunk4(v, (uint32_t)__builtin_amdgcn_readlane((int)gw.z, k), xl);
+            } else {
+                v = monomial_dense(A.exps + (g0 + k) * A.n, A.n, xl);
             }
+            acc += c * v;
         }
-#pragma unroll
-        for (int k = 0; k < EV_GROUP; ++k) {
-            w[k] = nw[k];
-            c[k] = nc[k];
-        }
+        gw = hw;
+        gc = hc;
     }
     return acc;
 }
@@ -421,13 +421,56 @@ __global__ void __launch_bounds__(EV_THREADS) k_eval_terms(EvalArgs A, const uin
         const int64_t b1 = r1 < A.term_limit ? r1 : A.term_limit;
         const int64_t len = b1 > b0 ? b1 - b0 : 0;
         const int64_t sa = b0 + len * sg / S, sb = b0 + len * (sg + 1) / S;
-        const double acc = term_range(A, enc, sa, sb, xl, vz);
+        const double acc = term_range(A, enc, sa, sb, xl);
         if (pt < A.N) {
             if (S == 1) store_out(A, q, pt, acc);
             else partial[(sg * A.Q + q) * A.N + pt] = acc;
         }
         r0 = n0;
         r1 = n1;
+    }
+}
+
+// Weighted sum over polynomials of formed Jacobian entries (the reverse mode
+// of eval without per-polynomial gradients):
+//   out[pt][j] = sum_p gY[p][pt] * J_{p, j}(x_pt),  J_{p, j} = polynomial p * n + j.
+// Unit (j, s) takes the polynomials p of segment s of S, in order, and sums
+// gY * (that entry's terms summed in term order); with S > 1 the segments'
+// partials [S][N][n] are added in order by k_sum_slices.
+__global__ void __launch_bounds__(EV_THREADS) k_eval_wsum(EvalArgs A, const uint32_t *enc, const double *gY,
+                                                          int64_t P, int64_t S, double *out, double *partial)
+{
+    extern __shared__ double s_x[];
+    const int lane = lane_id();
+    const int w = wave_id();
+    const int n = A.n;
+    const int64_t pt0 = (int64_t)blockIdx.x * kWave;
+    const int64_t pt = pt0 + lane;
+    for (int idx = threadIdx.x; idx < (n + 1) * kWave; idx += EV_THREADS) {
+        const int i = idx / kWave, l = idx % kWave;
+        const int64_t p = pt0 + l;
+        s_x[idx] = i == n ? 1.0 : (p < A.N ? A.X[p * n + i] : 0.0);
+    }
+    __syncthreads();
+    const double *xl = s_x + lane;
+    const int64_t units = (int64_t)n * S;
+    for (int64_t u = (int64_t)blockIdx.y * EV_WAVES + w; u < units; u += (int64_t)gridDim.y * EV_WAVES) {
+        const int64_t j = u / S, sg = u % S;
+        const int64_t p0 = P * sg / S, p1 = P * (sg + 1) / S;
+        double acc = 0.0;
+        for (int64_t p = p0; p < p1; ++p) {
+            const int64_t q = p * n + j;
+            const int64_t b0 = A.rp[q];
+            const int64_t b1 = A.rp[q + 1] < A.term_limit ? A.rp[q + 1] : A.term_limit;
+            if (b1 <= b0) continue;
+            const double v = term_range(A, enc, b0, b1, xl);
+            const double g = pt < A.N ? gY[p * A.N + pt] : 0.0;
+            acc = __builtin_fma(g, v, acc);
+        }
+        if (pt < A.N) {
+            if (S == 1) out[pt * n + j] = acc;
+            else partial[(sg * A.N + pt) * n + j] = acc;
+        }
     }
 }
 
@@ -444,18 +487,6 @@ __global__ void k_eval_reduce(EvalArgs A, const double *partial, int64_t S)
 }
 
 // --------------------------------------------------------------- backward
-
-// dX[pt, j] = sum_p gY[p, pt] * G[p, pt, j], p ascending.
-__global__ void k_backward_dx(const double *G, const double *gY, int64_t P, int64_t N, int n, double *dX)
-{
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= N * n) return;
-    const int64_t pt = idx / n;
-    const int j = (int)(idx % n);
-    double s = 0.0;
-    for (int64_t p = 0; p < P; ++p) s += gY[p * N + pt] * G[(p * N + pt) * n + j];
-    dX[idx] = s;
-}
 
 // Partial dC over one chunk of points: lanes are terms.
 // grid: x = term blocks of 256, y = point chunks.  Dynamic LDS: cp * n doubles.

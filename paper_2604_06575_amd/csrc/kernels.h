@@ -13,6 +13,7 @@ struct Tunables {
     int64_t eval_blocks_per_cu;
     int64_t mul_sort_min_raw;
     int64_t simplify_wide_min;
+    int64_t deriv_fused_max_n;
 };
 Tunables tunables();
 
@@ -217,11 +218,12 @@ __global__ void k_affine_normal(int n, const uint4 *enc, const double *coefs, in
                                 int32_t *status);
 __global__ void k_eval_terms(EvalArgs A, const uint32_t *enc, double *partial, int64_t S);
 __global__ void k_eval_reduce(EvalArgs A, const double *partial, int64_t S);
+__global__ void k_eval_wsum(EvalArgs A, const uint32_t *enc, const double *gY, int64_t P, int64_t S, double *out,
+                            double *partial);
 constexpr int64_t EV_TARGET_WAVES = 16384;   // waves wanted before polynomials are cut into segments
 constexpr int64_t EV_MIN_SEGMENT = 256;      // fewest terms per segment
 constexpr int64_t EV_MAX_SEGMENTS = 256;
 
-__global__ void k_backward_dx(const double *G, const double *gY, int64_t P, int64_t N, int n, double *dX);
 
 // fused derivative streaming (deriv.hip)
 enum DerivMode { DM_GRAD = 0, DM_DX = 1, DM_HVP = 2, DM_DIRD = 3 };
@@ -229,10 +231,10 @@ struct DerivArgs {
     const int64_t *rp;        // [P+1] source CSR
     int64_t P;
     int64_t T;                // terms (rp[P])
-    const uint8_t *exps;      // [T * n] (terms above EV_MAX_DEG read their dense row)
+    const uint8_t *exps;      // [T * n] (terms with more than eight variables read their dense row)
     const double *coefs;      // c
     const double *coefs2;     // w (DM_HVP, DM_DIRD), may be null
-    const uint32_t *enc;      // factor lists (k_encode_factors)
+    const uint64_t *enc;      // support encoding (k_encode_support), two words per term
     int n;
     const double *X;          // [N * n]
     int64_t N;

@@ -32,11 +32,17 @@ def say(*a):
 
 @pytest.fixture(scope="module")
 def ph():
+    """The library with the source-term derivative path switched on for
+    gradients and dX at every n it fits (the formed-Jacobian path is held
+    to the oracle by test_gpu_parity with the default setting)."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_2604_06575_amd as ph
     ph.lib()
-    return ph
+    old = ph.tune_get("deriv_fused_max_n")
+    ph.tune_set("deriv_fused_max_n", 255)
+    yield ph
+    ph.tune_set("deriv_fused_max_n", old)
 
 
 def mixed_polys(rng, n, integer=False):
@@ -120,13 +126,20 @@ def test_eval_backward_dx_weighted(ph, npts):
     X = W.points(2120 + npts, npts, n)
     P = len(polys)
     gY = rng.standard_normal((P, npts))
-    say(f"eval backward: {P} polys, {E.shape[0]} terms, {npts} points")
     b = ph.batch_from_numpy(rp, E, C, n=n, max_exp=int(E.max()))
-    dX, dC = ph.eval_backward(b, torch.from_numpy(X).cuda(), torch.from_numpy(gY).cuda(), check=True)
     dXo, dCo = oracle.eval_backward(rp, E, C, X, gY)
     aX, aC = oracle.eval_backward(rp, E, np.abs(C), np.abs(X), np.abs(gY))
-    assert (np.abs(dX.cpu().numpy() - dXo) <= 1e-12 * aX + 1e-300).all()
-    assert (np.abs(dC.cpu().numpy() - dCo) <= 1e-12 * aC + 1e-300).all()
+    old = ph.tune_get("deriv_fused_max_n")
+    try:
+        # dX streamed from the source terms, then from the formed Jacobian
+        for fused in (255, 0):
+            ph.tune_set("deriv_fused_max_n", fused)
+            say(f"eval backward: {P} polys, {E.shape[0]} terms, {npts} points, deriv_fused_max_n {fused}")
+            dX, dC = ph.eval_backward(b, torch.from_numpy(X).cuda(), torch.from_numpy(gY).cuda(), check=True)
+            assert (np.abs(dX.cpu().numpy() - dXo) <= 1e-12 * aX + 1e-300).all()
+            assert (np.abs(dC.cpu().numpy() - dCo) <= 1e-12 * aC + 1e-300).all()
+    finally:
+        ph.tune_set("deriv_fused_max_n", old)
 
 
 @pytest.mark.parametrize("which", ["u_and_w", "u_only", "w_only"])
