@@ -497,6 +497,7 @@ void ensure_lds_attrs()
     (void)hipFuncSetAttribute((const void *)k_eval_terms, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
     (void)hipFuncSetAttribute((const void *)k_backward_dc, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
     (void)hipFuncSetAttribute((const void *)k_backward2_dc, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    (void)hipFuncSetAttribute((const void *)k_hess_transpose, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
     (void)hipFuncSetAttribute((const void *)k_deriv_terms<DM_GRAD>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)DV_LDS_MAX);
     (void)hipFuncSetAttribute((const void *)k_deriv_terms<DM_DX>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1404,7 +1405,7 @@ poly_status poly_grad(const poly_csr *f, const double *X, int64_t N, double *G, 
 // j <= k, formed from it (mode 1), encoded and evaluated in one pass.
 struct HessPlan {
     FormPlan jform, hform;
-    size_t jrp, jexps, jcoefs, hrp, hexps, hcoefs, henc, part;
+    size_t jrp, jexps, jcoefs, hrp, hexps, hcoefs, henc, part, stage;
     int64_t jcap, hcap, S;
 };
 
@@ -1427,6 +1428,7 @@ HessPlan plan_hess(const poly_csr *f, int64_t N, Layout &L)
     h.henc = L.take(16 * h.hcap);
     h.S = eval_segments(P * n * n, N, T);
     h.part = L.take(eval_partial_bytes(P * n * n, N, h.S));
+    h.stage = L.take(8 * (size_t)P * n * n * N);   // entries (j <= k), point-contiguous
     return h;
 }
 
@@ -1478,9 +1480,12 @@ poly_status run_hess(const poly_csr *f, const double *X, int64_t N, double *H, v
     A.N = N;
     A.Q = P * n * n;
     A.mode = OUT_HESS;
-    A.Y = H;
+    A.Y = at<double>(ws, h.stage);
     A.term_limit = h.hcap;
     launch_eval_blocks(A, henc, at<double>(ws, h.part), h.S, s);
+    hipLaunchKernelGGL(k_hess_transpose, dim3((unsigned)ceil_div(N, 32), (unsigned)n,
+                                               (unsigned)std::min<int64_t>(P, 65535)), dim3(256),
+                       (size_t)n * 33 * sizeof(double), s, (const double *)A.Y, P, N, n, H);
     LAUNCH_CHECK();
     return POLY_OK;
 }

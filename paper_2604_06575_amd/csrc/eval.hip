@@ -58,6 +58,25 @@ __device__ inline int group_mult(const FormArgs &A, const uint8_t *row, int64_t 
 
 }  // namespace
 
+// Rows of up to ROW_STAGE_MAX_N bytes for a block of 256 terms are staged in
+// LDS by coalesced word loads, so that per-term scans of a row read LDS
+// instead of issuing one divergent byte load per lane and variable.
+constexpr int ROW_STAGE_MAX_N = 128;
+
+__device__ inline void stage_rows(const uint8_t *exps, int64_t r0, int cnt, int n, uint32_t *s32)
+{
+    const uint8_t *src = exps + r0 * n;
+    const int nb = cnt * n;
+    uint8_t *s8 = reinterpret_cast<uint8_t *>(s32);
+    if ((reinterpret_cast<uintptr_t>(src) & 3) == 0) {
+        const uint32_t *w = reinterpret_cast<const uint32_t *>(src);
+        for (int i = threadIdx.x; i < (nb >> 2); i += blockDim.x) s32[i] = w[i];
+        for (int i = (nb & ~3) + threadIdx.x; i < nb; i += blockDim.x) s8[i] = src[i];
+    } else {
+        for (int i = threadIdx.x; i < nb; i += blockDim.x) s8[i] = src[i];
+    }
+}
+
 __global__ void k_item_count(const int64_t *rp, int64_t P, int64_t chunk, int64_t *items)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -78,12 +97,21 @@ __global__ void __launch_bounds__(JAC_THREADS) k_form_count(FormArgs A)
     const int64_t T = A.rp[p + 1] - base;
     const int64_t t0 = chunk * A.chunk;
     const int64_t t1 = t0 + A.chunk < T ? t0 + A.chunk : T;
+    __shared__ uint32_t s_rows[JAC_THREADS * ROW_STAGE_MAX_N / 4];
     const int w = threadIdx.x >> 6;
+    const bool staged = A.n <= ROW_STAGE_MAX_N;
     for (int i = threadIdx.x; i < (JAC_THREADS / kWave) * DF_MAX_GROUPS; i += JAC_THREADS) (&s_wc[0][0])[i] = 0;
     __syncthreads();
     for (int64_t c0 = t0; c0 < t1; c0 += JAC_THREADS) {
         const int64_t t = c0 + threadIdx.x;
-        const uint8_t *row = A.exps + (base + t) * A.n;
+        const int cnt = (int)(t1 - c0 < JAC_THREADS ? t1 - c0 : JAC_THREADS);
+        if (staged) {
+            __syncthreads();
+            stage_rows(A.exps, base + c0, cnt, A.n, s_rows);
+            __syncthreads();
+        }
+        const uint8_t *row = staged ? reinterpret_cast<const uint8_t *>(s_rows) + threadIdx.x * A.n
+                                    : A.exps + (base + t) * A.n;
         for (int64_t g = 0; g < A.ngroups; ++g) {
             const int m = t < t1 ? group_mult(A, row, p, g) : 0;
             const unsigned long long bal = __ballot(m > 0);
@@ -118,6 +146,7 @@ __global__ void __launch_bounds__(JAC_THREADS) k_form_write(FormArgs A, const in
 {
     __shared__ int s_wc[JAC_THREADS / kWave][DF_MAX_GROUPS];
     __shared__ int64_t s_run[DF_MAX_GROUPS];
+    __shared__ uint32_t s_rows[JAC_THREADS * ROW_STAGE_MAX_N / 4];
     const int64_t item = blockIdx.x;
     const int64_t p = item_poly(A.item_start, A.P, item);
     const int64_t nch = A.item_start[p + 1] - A.item_start[p];
@@ -132,13 +161,18 @@ __global__ void __launch_bounds__(JAC_THREADS) k_form_write(FormArgs A, const in
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t cb = A.item_start[p] * A.ngroups;
     const int n = A.n;
+    const bool staged = n <= ROW_STAGE_MAX_N;
     const bool words = (n & 3) == 0 && ((reinterpret_cast<uintptr_t>(A.exps) | reinterpret_cast<uintptr_t>(A.out_exps)) & 3) == 0;
     for (int64_t g = threadIdx.x; g < A.ngroups; g += JAC_THREADS) s_run[g] = off[cb + g * nch + chunk];
     __syncthreads();
     for (int64_t c0 = t0; c0 < t1; c0 += JAC_THREADS) {
         const int64_t t = c0 + threadIdx.x;
         const bool valid = t < t1;
-        const uint8_t *row = A.exps + (base + t) * n;
+        const int cnt = (int)(t1 - c0 < JAC_THREADS ? t1 - c0 : JAC_THREADS);
+        if (staged) stage_rows(A.exps, base + c0, cnt, n, s_rows);
+        const uint8_t *rows = staged ? reinterpret_cast<const uint8_t *>(s_rows) : A.exps + (base + c0) * n;
+        if (staged) __syncthreads();
+        const uint8_t *row = rows + threadIdx.x * n;
         for (int64_t g = 0; g < A.ngroups; ++g) {
             const int m = valid ? group_mult(A, row, p, g) : 0;
             const unsigned long long bal = __ballot(m > 0);
@@ -150,25 +184,32 @@ __global__ void __launch_bounds__(JAC_THREADS) k_form_write(FormArgs A, const in
             const int j = (int)g;
             const int m = valid ? group_mult(A, row, p, g) : 0;
             const unsigned long long bal = __ballot(m > 0);
+            if (bal == 0) continue;
+            int64_t o = s_run[g] + __popcll(bal & lt);
+            for (int q = 0; q < w; ++q) o += s_wc[q][g];
             if (m > 0) {
-                int64_t o = s_run[g] + __popcll(bal & lt);
-                for (int q = 0; q < w; ++q) o += s_wc[q][g];
-                if (o < A.capacity) {
-                    uint8_t *orow = A.out_exps + o * n;
-                    if (words) {   // 4-byte rows: copy words, decrement byte j in place (it is >= 1)
-                        const uint32_t *r32 = reinterpret_cast<const uint32_t *>(row);
-                        uint32_t *o32 = reinterpret_cast<uint32_t *>(orow);
-                        for (int v = 0; v < (n >> 2); ++v) {
-                            uint32_t x = r32[v];
-                            if (v == (j >> 2)) x -= 1u << (8 * (j & 3));
-                            o32[v] = x;
-                        }
-                    } else {
-                        for (int v = 0; v < n; ++v) orow[v] = (uint8_t)(row[v] - (v == j ? 1 : 0));
+                if (o < A.capacity) A.out_coefs[o] = A.keep_coefs ? c : c * (double)m;
+                else set_status(A.status, A.overflow_code);
+            }
+            // the survivors' rows, one at a time, spread over the wave's lanes
+            // (exponent j decremented: it is >= 1 in a survivor)
+            for (unsigned long long rem = bal; rem; rem &= rem - 1) {
+                const int b = __builtin_ctzll(rem);
+                const int64_t ob = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)o, b) |
+                                   ((int64_t)__builtin_amdgcn_readlane((int)(uint32_t)(o >> 32), b) << 32);
+                if (ob >= A.capacity) continue;
+                const uint8_t *src = rows + (w * kWave + b) * n;
+                uint8_t *dst = A.out_exps + ob * n;
+                if (words) {
+                    const uint32_t *s32 = reinterpret_cast<const uint32_t *>(src);
+                    uint32_t *d32 = reinterpret_cast<uint32_t *>(dst);
+                    for (int v = lane; v < (n >> 2); v += kWave) {
+                        uint32_t x = s32[v];
+                        if (v == (j >> 2)) x -= 1u << (8 * (j & 3));
+                        d32[v] = x;
                     }
-                    A.out_coefs[o] = A.keep_coefs ? c : c * (double)m;
                 } else {
-                    set_status(A.status, A.overflow_code);
+                    for (int v = lane; v < n; v += kWave) dst[v] = (uint8_t)(src[v] - (v == j ? 1 : 0));
                 }
             }
         }
@@ -190,11 +231,30 @@ __global__ void __launch_bounds__(JAC_THREADS) k_form_write(FormArgs A, const in
 // zero.  A term with more than eight nonzero exponents is marked 0xFFFF in the
 // first slot and evaluated from its dense row.  `used` (optional, device)
 // bounds the rows actually formed in a workspace of T rows.
-__global__ void k_encode_support(const uint8_t *exps, int64_t T, int n, uint64_t *enc, const int64_t *used)
+// Rows of the block's terms: staged in LDS (n <= ROW_STAGE_MAX_N, blocks of
+// at most 256 threads) or read in place.  Returns null for threads past lim.
+__device__ inline const uint8_t *encode_row(const uint8_t *exps, int64_t lim, int n, uint32_t *s_rows)
 {
+    const int64_t r0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t t = r0 + threadIdx.x;
+    const int cnt = (int)(lim - r0 < (int64_t)blockDim.x ? lim - r0 : (int64_t)blockDim.x);
+    if (n <= ROW_STAGE_MAX_N) {
+        stage_rows(exps, r0, cnt, n, s_rows);
+        __syncthreads();
+        return t < lim ? reinterpret_cast<const uint8_t *>(s_rows) + threadIdx.x * n : nullptr;
+    }
+    return t < lim ? exps + t * n : nullptr;
+}
+
+__global__ void __launch_bounds__(256) k_encode_support(const uint8_t *exps, int64_t T, int n, uint64_t *enc,
+                                                        const int64_t *used)
+{
+    __shared__ uint32_t s_rows[256 * ROW_STAGE_MAX_N / 4];
+    const int64_t lim = used && *used < T ? *used : T;
+    if ((int64_t)blockIdx.x * blockDim.x >= lim) return;   // the whole block
+    const uint8_t *row = encode_row(exps, lim, n, s_rows);
+    if (!row) return;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T || (used && t >= *used)) return;
-    const uint8_t *row = exps + t * n;
     uint64_t w[2] = {0, 0};
     int s = 0;
     for (int i = 0; i < n; ++i) {
@@ -216,11 +276,15 @@ __global__ void k_encode_support(const uint8_t *exps, int64_t T, int n, uint64_t
 // repetition, in variable order (x1^2 x3 -> 0, 0, 2), bytes 0..11, the rest
 // of the list padded with n (an LDS row of ones); byte 12 holds d.  A term of
 // higher degree has byte 12 = 0xFF and is evaluated from its dense row.
-__global__ void k_encode_factors(const uint8_t *exps, int64_t T, int n, uint32_t *enc, const int64_t *used)
+__global__ void __launch_bounds__(256) k_encode_factors(const uint8_t *exps, int64_t T, int n, uint32_t *enc,
+                                                        const int64_t *used)
 {
+    __shared__ uint32_t s_rows[256 * ROW_STAGE_MAX_N / 4];
+    const int64_t lim = used && *used < T ? *used : T;
+    if ((int64_t)blockIdx.x * blockDim.x >= lim) return;   // the whole block
+    const uint8_t *row = encode_row(exps, lim, n, s_rows);
+    if (!row) return;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T || (used && t >= *used)) return;
-    const uint8_t *row = exps + t * n;
     uint32_t w[4] = {0, 0, 0, 0};
     int d = 0;
     for (int i = 0; i < n && d <= EV_MAX_DEG; ++i) {
@@ -284,13 +348,10 @@ __device__ inline void store_out(const EvalArgs &A, int64_t q, int64_t pt, doubl
     } else if (A.mode == OUT_GRAD) {
         const int64_t p = q / A.n, j = q % A.n;
         A.Y[(p * A.N + pt) * A.n + j] = y;
-    } else {   // q = (p * n + j) * n + k; entries k < j are written by their mirror
-        const int64_t k = q % A.n, pj = q / A.n;
-        const int64_t j = pj % A.n, p = pj / A.n;
+    } else {   // q = (p * n + j) * n + k, k >= j: staged point-contiguous for k_hess_transpose
+        const int64_t k = q % A.n, j = (q / A.n) % A.n;
         if (k < j) return;
-        const int64_t b = (p * A.N + pt) * A.n;
-        A.Y[(b + j) * A.n + k] = y;
-        if (j != k) A.Y[(b + k) * A.n + j] = y;
+        A.Y[q * A.N + pt] = y;
     }
 }
 
@@ -471,6 +532,35 @@ __global__ void __launch_bounds__(EV_THREADS) k_eval_wsum(EvalArgs A, const uint
             if (S == 1) out[pt * n + j] = acc;
             else partial[(sg * A.N + pt) * n + j] = acc;
         }
+    }
+}
+
+// H[p][pt][j][k] = stage[p][min(j,k)][max(j,k)][pt]: each Hessian entry was
+// evaluated once (j <= k) into a point-contiguous staging row; both triangles
+// are written from it, so H is bitwise symmetric.  Block (point tile of 32,
+// row j, polynomials p = z, z + gridDim.z, ...): the rows of the tile are read
+// as 256-byte runs into LDS and leave as contiguous n-element rows of H.
+// Dynamic LDS: n * 33 doubles.
+__global__ void __launch_bounds__(256) k_hess_transpose(const double *stage, int64_t P, int64_t N, int n, double *H)
+{
+    extern __shared__ double s_t[];
+    constexpr int TP = 32;
+    const int64_t pt0 = (int64_t)blockIdx.x * TP;
+    const int j = blockIdx.y;
+    for (int64_t p = blockIdx.z; p < P; p += gridDim.z) {
+        for (int idx = threadIdx.x; idx < n * TP; idx += blockDim.x) {
+            const int k = idx / TP, l = idx % TP;
+            const int64_t pt = pt0 + l;
+            const int a = j < k ? j : k, b = j < k ? k : j;
+            s_t[k * (TP + 1) + l] = pt < N ? stage[((p * n + a) * n + b) * N + pt] : 0.0;
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < n * TP; idx += blockDim.x) {
+            const int l = idx / n, k = idx % n;
+            const int64_t pt = pt0 + l;
+            if (pt < N) H[((p * N + pt) * n + j) * n + k] = s_t[k * (TP + 1) + l];
+        }
+        __syncthreads();
     }
 }
 

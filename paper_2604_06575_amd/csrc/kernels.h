@@ -157,7 +157,8 @@ __global__ void k_form_write(FormArgs A, const int64_t *off);
 constexpr int EV_WAVES = 8;
 constexpr int EV_THREADS = EV_WAVES * kWave;  // 8 waves share 64 points
 
-// OUT_HESS: polynomial q = (p * n + j) * n + k is the Hessian entry (j, k) of f_p
+// OUT_HESS: polynomial q = (p * n + j) * n + k is the Hessian entry (j, k) of f_p, written (k >= j) to a
+// point-contiguous staging row Y[q * N + pt] that k_hess_transpose turns into both triangles
 enum OutMode { OUT_EVAL = 0, OUT_GRAD = 1, OUT_HESS = 2 };
 
 struct EvalArgs {
@@ -218,6 +219,7 @@ __global__ void k_affine_normal(int n, const uint4 *enc, const double *coefs, in
                                 int32_t *status);
 __global__ void k_eval_terms(EvalArgs A, const uint32_t *enc, double *partial, int64_t S);
 __global__ void k_eval_reduce(EvalArgs A, const double *partial, int64_t S);
+__global__ void k_hess_transpose(const double *stage, int64_t P, int64_t N, int n, double *H);
 __global__ void k_eval_wsum(EvalArgs A, const uint32_t *enc, const double *gY, int64_t P, int64_t S, double *out,
                             double *partial);
 constexpr int64_t EV_TARGET_WAVES = 16384;   // waves wanted before polynomials are cut into segments
