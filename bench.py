@@ -43,10 +43,11 @@ FP64_PEAK_TFLOPS = 78.6
 BYTES_PER_RAW_TERM = 24
 
 
-def sort_plan(n, max_exp_a, max_exp_b, raw):
+def sort_plan(n, max_exp_a, max_exp_b, raw, bits=8):
     """The radix-sort path's pass structure for one pair (the library's own
     rule): mixed-radix keys in [0, r^n) with r = max_exp_a + max_exp_b + 1,
-    as few passes of at most 8 bits as that range needs, and -- when the
+    as few passes of at most `bits` bits (the sort_digit_bits tunable) as
+    that range needs, and -- when the
     digits left after the first pass and the raw index fit one 64-bit word --
     packed 8-byte elements from the first pass on.  Returns (passes, digit
     bits, packed, average algorithmic bytes per raw term per scatter launch):
@@ -55,7 +56,7 @@ def sort_plan(n, max_exp_a, max_exp_b, raw):
     nothing per raw term) and writes 8 B packed or 12 B unpacked."""
     r = max_exp_a + max_exp_b + 1
     key_bits = (r ** n - 1).bit_length()
-    passes = -(-key_bits // 8)
+    passes = -(-key_bits // bits)
     db = max(-(-key_bits // passes) if passes else 4, 4)
     raw_bits = (raw - 1).bit_length() if raw > 1 else 0
     packed = passes >= 2 and key_bits - db + raw_bits <= 64
@@ -133,7 +134,7 @@ def bench_mul(args):
     # on its launch stream around every bucket-kernel launch of K more steps
     k_ms, k_n = kernel_ms(ph.TIMING_MUL, step, args.steps)
     sort_path = raw >= ph.tune_get("mul_sort_min_raw")
-    plan = sort_plan(wl.n, wl.max_exp, wl.max_exp, raw) if sort_path else None
+    plan = sort_plan(wl.n, wl.max_exp, wl.max_exp, raw, ph.tune_get("sort_digit_bits")) if sort_path else None
     return dict(raw=raw, unique=uniq, t=t_ev, t_wall=t_wall, ws_bytes=ws_bytes, wl=wl, k_ms=k_ms, k_n=k_n,
                 sort_path=sort_path, plan=plan)
 

@@ -114,6 +114,9 @@ poly_status poly_read_status(const void *ws, void *stream);
  *        "simplify_wide_min" largest-entry size from which simplify and mtimes
  *                            merge through the device-wide sort
  *        "eval_blocks_per_cu" point-tile workgroups per CU (sparse eval)
+ *        "sort_digit_bits"   widest digit (4..11 bits) of the global radix
+ *                            sorts (times of one large pair, device-wide
+ *                            simplify, mtimes): fewer, wider passes
  *        "deriv_fused_max_n" largest n for which poly_grad and the dX of
  *                            poly_eval_backward stream derivatives straight
  *                            from the source terms (0: always through the

@@ -90,6 +90,34 @@ def main():
     threshold = threshold if threshold is not None else 1 << 62
     ph.tune_set("mul_sort_min_raw", threshold)
     log["mul_sort_min_raw"] = {"best": threshold, "sweep": rows}
+    # global radix sorts: widest digit (fewer, wider passes against larger
+    # per-tile histograms), on the headline one-pair product
+    big = W.plain_large()
+    a2 = ph.batch_from_numpy([0, big.a_exps.shape[0]], big.a_exps, big.a_coefs, n=big.n, max_exp=big.max_exp)
+    b2 = ph.batch_from_numpy([0, big.b_exps.shape[0]], big.b_exps, big.b_coefs, n=big.n, max_exp=big.max_exp)
+    ph.tune_set("mul_sort_min_raw", 0)
+    # one workspace for every width (the widest needs the most), values
+    # interleaved over two rounds and the faster round kept, so allocation
+    # and clock drift do not pick the winner
+    ph.tune_set("sort_digit_bits", 11)
+    ws2_bytes, raw2 = ph.mul_workspace(a2, b2)
+    ws2 = torch.empty(ws2_bytes, dtype=torch.uint8, device="cuda")
+    out2 = ph._empty_out(big.n, 1, raw2, 2 * big.max_exp, "cuda")
+    widths = (6, 7, 8, 9, 10, 11)
+    best_of = {b: float("inf") for b in widths}
+    for _ in range(2):
+        for bits in widths:
+            ph.tune_set("sort_digit_bits", bits)
+            t = _time(lambda: ph.mul(a2, b2, ws=ws2, out=out2, finish=False), reps=20, warmup=3)
+            best_of[bits] = min(best_of[bits], t)
+    rows = [{"value": b, "ms": best_of[b]} for b in widths]
+    for r in rows:
+        print(f"sort_digit_bits={r['value']}: {r['ms']:.3f} ms", flush=True)
+    best_bits = min(widths, key=lambda b: best_of[b])
+    del ws2, out2
+    ph.tune_set("sort_digit_bits", best_bits)
+    ph.tune_set("mul_sort_min_raw", threshold)
+    log["sort_digit_bits"] = {"best": best_bits, "sweep": rows}
     # batched simplify: the largest-entry size from which the device-wide sort
     # beats one workgroup per entry (16 entries of that size)
     rows, threshold = [], None
@@ -120,6 +148,12 @@ def main():
     qb = ph.batch_from_numpy([0, 30000], q.exps, q.coefs, n=40, max_exp=4)
     X = torch.from_numpy(q.X).cuda()
     sweep("eval_blocks_per_cu", [2, 4, 8, 16, 32], lambda: ph.eval(qb, X), log)
+    # gradients: derivatives streamed from the source terms (n up to the
+    # value) or through the formed Jacobian, on a 20-variable matrix
+    gm = W.batch_matrix(entries=256, npts=4096)
+    gb = ph.simplify(ph.batch_from_numpy(gm.row_ptr, gm.exps, gm.coefs, n=gm.n, max_exp=gm.max_exp))
+    GX = torch.from_numpy(gm.X).cuda()
+    sweep("deriv_fused_max_n", [0, 255], lambda: ph.grad(gb, GX), log)
     res = {"arch": "gfx950", "tool": "paper_2604_06575_amd.autotune", "date": time.strftime("%Y-%m-%d"),
            "tunables": {k: v["best"] for k, v in log.items()}, "sweeps": log}
     os.makedirs(os.path.dirname(args.out), exist_ok=True)

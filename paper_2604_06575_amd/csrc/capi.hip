@@ -21,6 +21,7 @@ std::atomic<int64_t> g_eval_blocks_per_cu{16};
 std::atomic<int64_t> g_mul_sort_min_raw{int64_t(1) << 20};
 std::atomic<int64_t> g_simplify_wide_min{SEG_CAP + 1};
 std::atomic<int64_t> g_deriv_fused_max_n{0};
+std::atomic<int64_t> g_sort_digit_bits{8};
 
 struct TuneEntry {
     const char *name;
@@ -34,13 +35,19 @@ const TuneEntry kTune[] = {
     {"mul_sort_min_raw", &g_mul_sort_min_raw, 0, int64_t(1) << 62},
     {"simplify_wide_min", &g_simplify_wide_min, 1, int64_t(1) << 62},
     {"deriv_fused_max_n", &g_deriv_fused_max_n, 0, 255},
+    {"sort_digit_bits", &g_sort_digit_bits, GS_MIN_BITS, GS_MAX_BITS},
 };
 }  // namespace
+
+// widest radix digit of the global sorts, and its number of bins
+int sort_bits() { return (int)g_sort_digit_bits.load(); }
+int64_t sort_bins() { return int64_t(1) << sort_bits(); }
 
 Tunables tunables()
 {
     return Tunables{g_mul_bucket_terms.load(), g_seg_blocks_per_cu.load(), g_eval_blocks_per_cu.load(),
-                    g_mul_sort_min_raw.load(), g_simplify_wide_min.load(), g_deriv_fused_max_n.load()};
+                    g_mul_sort_min_raw.load(), g_simplify_wide_min.load(), g_deriv_fused_max_n.load(),
+                    g_sort_digit_bits.load()};
 }
 
 }  // namespace polyhip
@@ -187,9 +194,9 @@ void plan_wide(WidePlan &w, Layout &L, int64_t P, int64_t R, int n, uint32_t rad
     w.keys1 = L.take(8 * R);
     w.vals0 = L.take(4 * R);
     w.vals1 = L.take(4 * R);
-    w.hist = L.take(8 * GS_BINS * w.nbs);
-    w.hoff = L.take(8 * (GS_BINS * w.nbs + 1));
-    w.tmp = L.take(8 * (ceil_div(std::max<int64_t>(GS_BINS * w.nbs, w.nbm), LB_TILE) + 2));
+    w.hist = L.take(8 * sort_bins() * w.nbs);
+    w.hoff = L.take(8 * (sort_bins() * w.nbs + 1));
+    w.tmp = L.take(8 * (ceil_div(std::max<int64_t>(sort_bins() * w.nbs, w.nbm), LB_TILE) + 2));
     w.st_key = L.take(8 * R);
     w.st_ckey = L.take(8 * R);
     w.st_coef = L.take(8 * R);
@@ -328,9 +335,9 @@ poly_status plan_mul(const poly_csr *a, const poly_csr *b, MulPlan &m)
         m.gs_keys1 = L.take(8 * raw);
         m.gs_vals0 = L.take(4 * raw);
         m.gs_vals1 = L.take(4 * raw);
-        m.gs_hist = L.take(8 * GS_BINS * m.gs_blocks);
-        m.gs_hoff = L.take(8 * (GS_BINS * m.gs_blocks + 1));
-        m.gs_tmp = L.take(8 * scan_tmp_count(std::max<int64_t>(GS_BINS * m.gs_blocks, ceil_div(raw, MG_TILE))));
+        m.gs_hist = L.take(8 * sort_bins() * m.gs_blocks);
+        m.gs_hoff = L.take(8 * (sort_bins() * m.gs_blocks + 1));
+        m.gs_tmp = L.take(8 * scan_tmp_count(std::max<int64_t>(sort_bins() * m.gs_blocks, ceil_div(raw, MG_TILE))));
         m.gs_pa = L.take(16 * Ta);
         m.gs_pb = L.take(16 * Tb);
         m.gs_mblocks = ceil_div(raw, MG_TILE);
@@ -981,9 +988,9 @@ poly_status run_wide(const WidePlan &w, void *ws, int64_t P, int64_t R, int n, i
     int64_t *hist = at<int64_t>(ws, w.hist), *hoff = at<int64_t>(ws, w.hoff), *tmp = at<int64_t>(ws, w.tmp);
     const int64_t nb = w.nbs;
     // scan state: cleared once, then by each pass's scatter for the next scan
-    const int64_t scan_state = ceil_div(std::max<int64_t>(GS_BINS * nb, w.nbm), LB_TILE) + 2;
+    const int64_t scan_state = ceil_div(std::max<int64_t>(sort_bins() * nb, w.nbm), LB_TILE) + 2;
     clear_u64((unsigned long long *)tmp, scan_state, s);
-    const int passes = (w.key_bits + GS_BITS - 1) / GS_BITS;
+    const int passes = (w.key_bits + sort_bits() - 1) / sort_bits();
     const int db = std::max(passes ? (w.key_bits + passes - 1) / passes : GS_MIN_BITS, GS_MIN_BITS);
     const int64_t hgrid = std::min<int64_t>(ceil_div(nb, GS_HIST_THREADS / kWave), (int64_t)device_cus() * 8);
     const GsGen gen{};   // the stream is read, not generated
@@ -1003,7 +1010,10 @@ poly_status run_wide(const WidePlan &w, void *ws, int64_t P, int64_t R, int n, i
         case 5: pass(std::integral_constant<int, 5>(), p); break;
         case 6: pass(std::integral_constant<int, 6>(), p); break;
         case 7: pass(std::integral_constant<int, 7>(), p); break;
-        default: pass(std::integral_constant<int, 8>(), p); break;
+        case 8: pass(std::integral_constant<int, 8>(), p); break;
+        case 9: pass(std::integral_constant<int, 9>(), p); break;
+        case 10: pass(std::integral_constant<int, 10>(), p); break;
+        default: pass(std::integral_constant<int, 11>(), p); break;
         }
         std::swap(kcur, knext);
         std::swap(vcur, vnext);
@@ -1144,16 +1154,16 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
         int64_t *tmp = at<int64_t>(ws, m.gs_tmp);
         // scan state: cleared here for the first pass, then by each pass's
         // scatter (after its scan has finished) for the next scan
-        const int64_t scan_state = scan_tmp_count(std::max<int64_t>(GS_BINS * m.gs_blocks, ceil_div(R, MG_TILE)));
+        const int64_t scan_state = scan_tmp_count(std::max<int64_t>(sort_bins() * m.gs_blocks, ceil_div(R, MG_TILE)));
         clear_u64((unsigned long long *)tmp, scan_state, s);
 
         // key range r^n (at most 2^(n * bits), so it fits 64 bits); as few
-        // passes of at most GS_BITS bits as it needs, digits as even as possible
+        // passes of at most sort_bits() bits as it needs, digits as even as possible
         unsigned __int128 span = 1;
         for (int i = 0; i < n; ++i) span *= radix;
         const uint64_t kmax = (uint64_t)(span - 1);
         const int key_bits = kmax ? 64 - __builtin_clzll((unsigned long long)kmax) : 0;
-        const int passes = (key_bits + GS_BITS - 1) / GS_BITS;
+        const int passes = (key_bits + sort_bits() - 1) / sort_bits();
         const int db = std::max(passes ? (key_bits + passes - 1) / passes : GS_MIN_BITS, GS_MIN_BITS);
         // after the first pass, the digits still to sort and the raw index
         // share one 64-bit word when they fit: 8 bytes per element per pass
@@ -1201,7 +1211,10 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
             case 5: pass(std::integral_constant<int, 5>(), p); break;
             case 6: pass(std::integral_constant<int, 6>(), p); break;
             case 7: pass(std::integral_constant<int, 7>(), p); break;
-            default: pass(std::integral_constant<int, 8>(), p); break;
+            case 8: pass(std::integral_constant<int, 8>(), p); break;
+            case 9: pass(std::integral_constant<int, 9>(), p); break;
+            case 10: pass(std::integral_constant<int, 10>(), p); break;
+            default: pass(std::integral_constant<int, 11>(), p); break;
             }
             std::swap(kcur, knext);
             std::swap(vcur, vnext);

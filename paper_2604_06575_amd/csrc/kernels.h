@@ -14,8 +14,11 @@ struct Tunables {
     int64_t mul_sort_min_raw;
     int64_t simplify_wide_min;
     int64_t deriv_fused_max_n;
+    int64_t sort_digit_bits;
 };
 Tunables tunables();
+int sort_bits();
+int64_t sort_bins();
 
 // ------------------------------------------------------------ simplify / sort
 constexpr int SEG_THREADS = 512;

@@ -9,8 +9,7 @@ constexpr int GS_THREADS = 1024;                 // operand sort, raw product ge
 constexpr int GS_SC_THREADS = 512;               // radix-pass (scatter) workgroup
 constexpr int GS_ITEMS = 8;
 constexpr int GS_TILE = GS_SC_THREADS * GS_ITEMS;   // elements per scatter workgroup and pass
-constexpr int GS_BITS = 8;                       // widest digit
-constexpr int GS_BINS = 1 << GS_BITS;
+constexpr int GS_MAX_BITS = 11;                  // widest digit instantiated
 constexpr int GS_MIN_BITS = 4;                   // narrowest digit instantiated
 constexpr int GS_HIST_THREADS = 256;
 constexpr int MG_THREADS = 512;                  // merge workgroup

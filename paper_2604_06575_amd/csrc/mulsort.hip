@@ -11,8 +11,8 @@
 // The raw product of p (ta terms) and q (tb terms) is generated in (i, j)
 // order -- both operands in storage order, the order of the definition -- as
 // (key k_i + k_j, raw index i * tb + j).  A least-significant-digit radix
-// sort with digits of at most GS_BITS bits (as few passes as the key range
-// needs, digits as even as possible), stable in every pass, orders the pairs
+// sort with digits of at most "sort_digit_bits" bits (a tunable; as few
+// passes as the key range needs, digits as even as possible), stable in every pass, orders the pairs
 // by key while keeping (i, j) order among equal keys.  Each run of equal keys
 // is then summed left to right by one lane, with every product c_i * c_j
 // recomputed from the raw index, so the sums are the sequential ones of the
@@ -205,10 +205,23 @@ __global__ void __launch_bounds__(GS_SC_THREADS) k_gs_scatter(const uint64_t *ke
     }
     __syncthreads();
     {
+        // digit starts: each thread scans PER consecutive digits
+        constexpr int PER = (NB + GS_SC_THREADS - 1) / GS_SC_THREADS;
+        uint32_t loc[PER], sum = 0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int d = threadIdx.x * PER + i;
+            loc[i] = d < NB ? s_tot[d] : 0u;
+            sum += loc[i];
+        }
         uint32_t tot;
-        const uint32_t x = threadIdx.x < NB ? s_tot[threadIdx.x] : 0u;
-        const uint32_t ex = block_exclusive_scan<GS_SC_THREADS>(x, s_scan, tot);
-        if (threadIdx.x < NB) s_start[threadIdx.x] = ex;
+        uint32_t ex = block_exclusive_scan<GS_SC_THREADS>(sum, s_scan, tot);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int d = threadIdx.x * PER + i;
+            if (d < NB) s_start[d] = ex;
+            ex += loc[i];
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -467,91 +480,28 @@ __global__ void __launch_bounds__(MG_THREADS) k_gs_merge(const uint64_t *keys, c
     }
 }
 
-template __global__ void k_gs_hist<4, false>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
-template __global__ void k_gs_hist<4, true>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
-template __global__ void k_gs_hist<5, false>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
-template __global__ void k_gs_hist<5, true>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
-template __global__ void k_gs_hist<6, false>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
-template __global__ void k_gs_hist<6, true>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
-template __global__ void k_gs_hist<7, false>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
-template __global__ void k_gs_hist<7, true>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
-template __global__ void k_gs_hist<8, false>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
-template __global__ void k_gs_hist<8, true>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);
-template __global__ void k_gs_scatter<4, GS_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
+#define GS_SCATTER_INST(DB, MODE)                                                                              \
+    template __global__ void k_gs_scatter<DB, MODE>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,     \
+                                                    const int64_t *, uint64_t *, uint32_t *, int,                   \
                                                     unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<4, GS_KV_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<4, GS_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<4, GS_GEN_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<4, GS_GEN_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<5, GS_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<5, GS_KV_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<5, GS_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<5, GS_GEN_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<5, GS_GEN_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<6, GS_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<6, GS_KV_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<6, GS_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<6, GS_GEN_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<6, GS_GEN_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<7, GS_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<7, GS_KV_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<7, GS_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<7, GS_GEN_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<7, GS_GEN_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<8, GS_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<8, GS_KV_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<8, GS_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<8, GS_GEN_KV>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
-template __global__ void k_gs_scatter<8, GS_GEN_TO_PACKED>(const uint64_t *, const uint32_t *, int64_t, int, int64_t,
-                                                    const int64_t *, uint64_t *, uint32_t *, int,
-                                                    unsigned long long *, int64_t, GsGen);
+#define GS_DIGIT_INST(DB)                                                                                      \
+    template __global__ void k_gs_hist<DB, false>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);   \
+    template __global__ void k_gs_hist<DB, true>(const uint64_t *, int64_t, int, int64_t, int64_t *, GsGen);    \
+    GS_SCATTER_INST(DB, GS_KV)                                                                                  \
+    GS_SCATTER_INST(DB, GS_KV_TO_PACKED)                                                                        \
+    GS_SCATTER_INST(DB, GS_PACKED)                                                                              \
+    GS_SCATTER_INST(DB, GS_GEN_KV)                                                                              \
+    GS_SCATTER_INST(DB, GS_GEN_TO_PACKED)
+GS_DIGIT_INST(4)
+GS_DIGIT_INST(5)
+GS_DIGIT_INST(6)
+GS_DIGIT_INST(7)
+GS_DIGIT_INST(8)
+GS_DIGIT_INST(9)
+GS_DIGIT_INST(10)
+GS_DIGIT_INST(11)
+#undef GS_DIGIT_INST
+#undef GS_SCATTER_INST
 template __global__ void k_gs_merge<false>(const uint64_t *, const uint32_t *, int64_t, int64_t, int64_t,
                                            const uint64_t *, const uint64_t *, int, const double *,
                                            const double *, const GsKC *, const GsKC *, double, RadixDecode,

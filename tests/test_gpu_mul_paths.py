@@ -129,3 +129,34 @@ def test_long_partner(ph, path):
     wl = W.plain_large(seed=W.SEED_BASE + 44, terms=9000, n=8, d=8)
     say(f"[{path}] 40 x 9000 n=8")
     run_pair(ph, wl.a_exps[:40], wl.a_coefs[:40], wl.b_exps, wl.b_coefs, 8, 8)
+
+
+@pytest.mark.parametrize("bits", [4, 9, 10, 11])
+def test_sort_digit_widths(ph, bits):
+    """The global radix sorts with other widest digits (the sort_digit_bits
+    tunable): fewer, wider passes -- up to 2,048 bins per tile -- must give
+    the same bits: one pair with many tiles, one with 64-bit keys, and the
+    device-wide simplify of a batch."""
+    old_bits, old_min = ph.tune_get("sort_digit_bits"), ph.tune_get("simplify_wide_min")
+    try:
+        ph.tune_set("sort_digit_bits", bits)
+        ph.tune_set("mul_sort_min_raw", 0)
+        wl = W.plain_large(seed=W.SEED_BASE + 40, terms=700, n=6, d=6)
+        say(f"[digits {bits}] 700x700 n=6")
+        run_pair(ph, wl.a_exps, wl.a_coefs, wl.b_exps, wl.b_coefs, 6, 6)
+        rng = W.rng_for(78)
+        A = W.random_poly(rng, 16, 7, 300)
+        B = W.random_poly(rng, 16, 7, 300)
+        A[0][:, 0] = rng.integers(0, 8, A[0].shape[0])
+        B[0][:, 0] = rng.integers(0, 8, B[0].shape[0])
+        say(f"[digits {bits}] 64-bit keys")
+        run_pair(ph, A[0], A[1], B[0], B[1], 16, 7)
+        ph.tune_set("simplify_wide_min", 1)
+        bm = W.batch_matrix(seed=W.SEED_BASE + 79, entries=60, tmin=10, tmax=5000, npts=0)
+        say(f"[digits {bits}] device-wide simplify, {int(bm.row_ptr[-1])} terms")
+        sb = ph.batch_from_numpy(bm.row_ptr, bm.exps, bm.coefs, n=bm.n, max_exp=bm.max_exp)
+        orp, oe, oc = oracle.simplify_batch(bm.row_ptr, bm.exps, bm.coefs)
+        bitwise(ph.batch_to_numpy(ph.simplify(sb)), orp, oe, oc)
+    finally:
+        ph.tune_set("sort_digit_bits", old_bits)
+        ph.tune_set("simplify_wide_min", old_min)
