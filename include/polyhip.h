@@ -198,23 +198,41 @@ poly_status poly_jacobian(const poly_csr *in, poly_csr *out,
  *              polynomial with coefficient c * e_j * (e_k - [j==k]), the
  *              integer multiplier formed first).
  * Summation order inside the library is not the oracle's storage order, so
- * results agree with a sequential FP64 sum to rounding, not bitwise. */
-poly_status poly_eval_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes);
-poly_status poly_eval(const poly_csr *f, const double *X, int64_t N, double *Y,
+ * results agree with a sequential FP64 sum to rounding, not bitwise.
+ *
+ * prec selects the arithmetic (nslices is read only for the split path):
+ *   POLY_FP64        term streaming in FP64 on the vector units (any batch).
+ *   POLY_SPLIT_BF16  for a batch that is one shared monomial set stored as
+ *       CSR -- every polynomial lists the same K exponent rows in the same
+ *       order -- the coefficients are the P x K matrix of the dense split
+ *       contraction of poly_eval_dense (split BF16 digits, FP32 MFMA sums,
+ *       FP64 recombination; error bound as stated there), used in place.
+ *       Gradients are n such contractions over the derived monomial sets
+ *       e - u_j with coefficients e_j c, Hessians n (n + 1) / 2 over
+ *       e - u_j - u_k with coefficients e_j (e_k - [j == k]) c (the integer
+ *       multiplier formed first; entry (k, j) copied from (j, k)).  Unequal
+ *       polynomial lengths: POLY_ERR_UNSUPPORTED from the call (host check);
+ *       unequal rows: POLY_ERR_UNSUPPORTED in the device status (the
+ *       outputs are then undefined).  The workspace query takes the same
+ *       prec and nslices. */
+poly_status poly_eval_workspace(const poly_csr *f, int64_t N, poly_prec prec, int32_t nslices, size_t *ws_bytes);
+poly_status poly_eval(const poly_csr *f, const double *X, int64_t N, double *Y, poly_prec prec, int32_t nslices,
                       void *ws, size_t ws_bytes, void *stream);
-poly_status poly_grad_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes);
-poly_status poly_grad(const poly_csr *f, const double *X, int64_t N, double *G,
+poly_status poly_grad_workspace(const poly_csr *f, int64_t N, poly_prec prec, int32_t nslices, size_t *ws_bytes);
+poly_status poly_grad(const poly_csr *f, const double *X, int64_t N, double *G, poly_prec prec, int32_t nslices,
                       void *ws, size_t ws_bytes, void *stream);
-poly_status poly_hess_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes);
-poly_status poly_hess(const poly_csr *f, const double *X, int64_t N, double *H,
+poly_status poly_hess_workspace(const poly_csr *f, int64_t N, poly_prec prec, int32_t nslices, size_t *ws_bytes);
+poly_status poly_hess(const poly_csr *f, const double *X, int64_t N, double *H, poly_prec prec, int32_t nslices,
                       void *ws, size_t ws_bytes, void *stream);
 
 /* Reverse mode of Y = poly_eval(f, X) for a cotangent gY[P*N]:
  *   dC[t]        = sum_pt gY[p(t)*N + pt] * x_pt^{e_t}          (may be NULL)
- *   dX[pt*n + j] = sum_p  gY[p*N + pt] * d f_p / d x_{j+1}(x_pt) (may be NULL) */
-poly_status poly_eval_backward_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes);
+ *   dX[pt*n + j] = sum_p  gY[p*N + pt] * d f_p / d x_{j+1}(x_pt) (may be NULL)
+ * prec: POLY_FP64 (POLY_SPLIT_BF16 returns POLY_ERR_UNSUPPORTED). */
+poly_status poly_eval_backward_workspace(const poly_csr *f, int64_t N, poly_prec prec, int32_t nslices,
+                                         size_t *ws_bytes);
 poly_status poly_eval_backward(const poly_csr *f, const double *X, int64_t N,
-                               const double *gY, double *dX, double *dC,
+                               const double *gY, double *dX, double *dC, poly_prec prec, int32_t nslices,
                                void *ws, size_t ws_bytes, void *stream);
 
 /* Reverse mode of poly_eval_backward (second order; what a double backward
@@ -309,6 +327,35 @@ poly_status poly_eval_dense(int32_t n, int64_t K, const uint8_t *basis, int32_t 
                             int64_t P, const double *C, int64_t N, const double *X,
                             double *Y, poly_prec prec, int32_t nslices,
                             void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ plans
+ * A plan records, once, the pipeline of a polynomial matrix
+ *   simplified = simplify(in, zero_tol)        (Table "coresemantics")
+ *   jac        = jacobian(simplified)          (Section 3.3; entry p*n + j)
+ *   G[(p*N + pt)*n + j] = value of jac entry p*n + j at x_pt
+ * into one HIP graph; poly_plan_launch replays it on a stream with no host
+ * work and no read-back.  Sizes the eager calls learn by reading back
+ * (simplified and Jacobian term counts) stay on the device: the Jacobian is
+ * formed over worst-case work items, and its encoding and evaluation stop
+ * at the counts the device wrote.  Everything the plan touches is fixed at
+ * creation: in (its row_ptr_host too: the simplify launch shape depends on
+ * it), X, simplified, jac, G and ws must stay allocated until
+ * poly_plan_destroy; their contents may change between launches (new
+ * coefficients, exponents within max_exp, new points).  Requirements:
+ * simplified->npolys == in->npolys, capacity >= total input terms;
+ * jac->npolys == in->npolys * n, jac->capacity >= total input terms *
+ * min(n, 8) (terms with more than eight variables can need more: the device
+ * then reports POLY_ERR_CAPACITY); stream must not be NULL (the legacy
+ * stream cannot be captured); kernel timing (poly_timing_enable) must be
+ * off while a plan is created.  Device-detected errors land in the status
+ * word of ws (poly_read_status).  Calls that overlap on one plan race. */
+typedef struct poly_plan poly_plan;
+poly_status poly_plan_workspace(const poly_csr *in, int64_t N, size_t *ws_bytes);
+poly_status poly_plan_create(const poly_csr *in, double zero_tol, const double *X, int64_t N,
+                             poly_csr *simplified, poly_csr *jac, double *G,
+                             void *ws, size_t ws_bytes, void *stream, poly_plan **plan);
+poly_status poly_plan_launch(const poly_plan *plan, void *stream);
+poly_status poly_plan_destroy(poly_plan *plan);
 
 /* ------------------------------------------------ allocation-free simplify
  * For callers that cannot allocate device memory: code under HIP graph

@@ -15,7 +15,7 @@ import numpy as np
 import torch
 
 __all__ = [
-    "Batch", "PolyError", "PolyEval", "batch_from_numpy", "batch_to_numpy", "mul", "simplify", "jacobian",
+    "Batch", "PolyError", "PolyEval", "PolyEvalBackward", "Plan", "batch_from_numpy", "batch_to_numpy", "mul", "simplify", "jacobian",
     "eval", "grad", "hess", "eval_backward", "eval_dense", "mtimes", "mpower", "msum", "mprod", "concat", "subs",
     "affine_normal",
     "library_path", "lib",
@@ -45,6 +45,7 @@ EXPORTS = [
     "poly_mtimes_workspace", "poly_mtimes",
     "poly_concat",
     "poly_simplify_noalloc",
+    "poly_plan_workspace", "poly_plan_create", "poly_plan_launch", "poly_plan_destroy",
 ]
 
 
@@ -100,14 +101,14 @@ def lib():
         "poly_mul": ([pcsr, pcsr, pcsr, d, P, ctypes.c_size_t, P], i32),
         "poly_jacobian_workspace": ([pcsr, psz], i32),
         "poly_jacobian": ([pcsr, pcsr, P, ctypes.c_size_t, P], i32),
-        "poly_eval_workspace": ([pcsr, i64, psz], i32),
-        "poly_eval": ([pcsr, P, i64, P, P, ctypes.c_size_t, P], i32),
-        "poly_grad_workspace": ([pcsr, i64, psz], i32),
-        "poly_grad": ([pcsr, P, i64, P, P, ctypes.c_size_t, P], i32),
-        "poly_hess_workspace": ([pcsr, i64, psz], i32),
-        "poly_hess": ([pcsr, P, i64, P, P, ctypes.c_size_t, P], i32),
-        "poly_eval_backward_workspace": ([pcsr, i64, psz], i32),
-        "poly_eval_backward": ([pcsr, P, i64, P, P, P, P, ctypes.c_size_t, P], i32),
+        "poly_eval_workspace": ([pcsr, i64, i32, i32, psz], i32),
+        "poly_eval": ([pcsr, P, i64, P, i32, i32, P, ctypes.c_size_t, P], i32),
+        "poly_grad_workspace": ([pcsr, i64, i32, i32, psz], i32),
+        "poly_grad": ([pcsr, P, i64, P, i32, i32, P, ctypes.c_size_t, P], i32),
+        "poly_hess_workspace": ([pcsr, i64, i32, i32, psz], i32),
+        "poly_hess": ([pcsr, P, i64, P, i32, i32, P, ctypes.c_size_t, P], i32),
+        "poly_eval_backward_workspace": ([pcsr, i64, i32, i32, psz], i32),
+        "poly_eval_backward": ([pcsr, P, i64, P, P, P, i32, i32, P, ctypes.c_size_t, P], i32),
         "poly_eval_backward2_workspace": ([pcsr, i64, psz], i32),
         "poly_eval_backward2": ([pcsr, P, i64, P, P, P, P, P, P, P, ctypes.c_size_t, P], i32),
         "poly_eval_dense_workspace": ([i32, i64, i64, i64, i32, i32, psz], i32),
@@ -117,6 +118,10 @@ def lib():
         "poly_affine_normal": ([pcsr, P, i64, d, P, P, P, ctypes.c_size_t, P], i32),
         "poly_concat": ([ctypes.POINTER(pcsr), i32, pcsr, P], i32),
         "poly_simplify_noalloc": ([pcsr, pcsr, d, P, P], i32),
+        "poly_plan_workspace": ([pcsr, i64, psz], i32),
+        "poly_plan_create": ([pcsr, d, P, i64, pcsr, pcsr, P, P, ctypes.c_size_t, P, ctypes.POINTER(P)], i32),
+        "poly_plan_launch": ([P, P], i32),
+        "poly_plan_destroy": ([P], i32),
         "poly_eval_dense": ([i32, i64, P, i32, i64, P, i64, P, P, i32, i32, P, ctypes.c_size_t, P], i32),
     }
     for name, (args, res) in sig.items():
@@ -336,6 +341,56 @@ def simplify_noalloc(b: Batch, out: Batch, status: torch.Tensor, tol: float = 0.
     return out
 
 
+class Plan:
+    """The captured pipeline simplify -> jacobian -> gradient values of a
+    polynomial matrix (poly_plan_create).  ``launch()`` replays the graph on
+    the current stream; outputs: ``simplified`` and ``jac`` (row pointers on
+    the device; ``finish()`` reads them back) and ``G`` [P, N, n]."""
+
+    def __init__(self, b: Batch, X: torch.Tensor, tol: float = 0.0, stream=None):
+        L = lib()
+        self._b, self._X = b, X.contiguous()
+        _check_points(self._X, b.n, b.coefs.device)
+        dev = b.coefs.device
+        N, n, P, T = self._X.shape[0], b.n, b.npolys, b.nterms
+        cin = b.csr()
+        self._cin = cin
+        ws_bytes = ctypes.c_size_t()
+        _check(L.poly_plan_workspace(ctypes.byref(cin), N, ctypes.byref(ws_bytes)), "poly_plan_workspace")
+        self.ws = _workspace(ws_bytes.value, dev)
+        self.simplified = _empty_out(n, P, T, b.max_exp, dev)
+        self.jac = _empty_out(n, P * n, T * min(n, 8), b.max_exp, dev)
+        self.G = torch.empty((P, N, n), dtype=torch.float64, device=dev)
+        self._csimp, self._cjac = self.simplified.csr(), self.jac.csr()
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(L.poly_plan_create(ctypes.byref(cin), float(tol), _ptr(self._X), N, ctypes.byref(self._csimp),
+                                  ctypes.byref(self._cjac), _ptr(self.G), ctypes.c_void_p(self.ws.data_ptr()),
+                                  self.ws.numel(), _stream(self._stream), ctypes.byref(h)), "poly_plan_create")
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().poly_plan_launch(self._h, _stream(stream)), "poly_plan_launch")
+
+    def finish(self):
+        """Device status and the output row pointers on the host (one sync)."""
+        _check(lib().poly_read_status(ctypes.c_void_p(self.ws.data_ptr()), _stream()), "poly_plan")
+        self.simplified.row_ptr_host = self.simplified.row_ptr.cpu().numpy()
+        self.jac.row_ptr_host = self.jac.row_ptr.cpu().numpy()
+        return self
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(lib().poly_plan_destroy(self._h), "poly_plan_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def mul_workspace(a: Batch, b: Batch) -> tuple[int, int]:
     L = lib()
     ca, cb = a.csr(), b.csr()
@@ -536,36 +591,39 @@ def _check_points(X: torch.Tensor, n: int, device=None):
     _check_device("points", X, device)
 
 
-def _eval_like(fname: str, b: Batch, X: torch.Tensor, shape, check: bool):
+def _eval_like(fname: str, b: Batch, X: torch.Tensor, shape, check: bool, prec: int = POLY_FP64,
+               nslices: int = 5):
     L = lib()
     X = X.contiguous()
     cin = b.csr()
     _check_points(X, b.n, b.coefs.device)
     N = X.shape[0]
     ws_bytes = ctypes.c_size_t()
-    _check(getattr(L, fname + "_workspace")(ctypes.byref(cin), N, ctypes.byref(ws_bytes)), fname + "_workspace")
+    _check(getattr(L, fname + "_workspace")(ctypes.byref(cin), N, int(prec), int(nslices), ctypes.byref(ws_bytes)),
+           fname + "_workspace")
     ws = _workspace(ws_bytes.value, b.coefs.device)
     Y = torch.empty(shape, dtype=torch.float64, device=b.coefs.device)
-    _check(getattr(L, fname)(ctypes.byref(cin), _ptr(X), N, _ptr(Y), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
-                             _stream()), fname)
+    _check(getattr(L, fname)(ctypes.byref(cin), _ptr(X), N, _ptr(Y), int(prec), int(nslices),
+                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()), fname)
     if check:
         _check(L.poly_read_status(ctypes.c_void_p(ws.data_ptr()), _stream()), fname)
     return Y
 
 
-def eval(b: Batch, X: torch.Tensor, check: bool = False) -> torch.Tensor:
-    """Y[p, pt] = f_p(x_pt)."""
-    return _eval_like("poly_eval", b, X, (b.npolys, X.shape[0]), check)
+def eval(b: Batch, X: torch.Tensor, check: bool = False, prec: int = POLY_FP64, nslices: int = 5) -> torch.Tensor:
+    """Y[p, pt] = f_p(x_pt).  prec=POLY_SPLIT_BF16 needs a shared monomial set
+    (every polynomial the same exponent rows in the same order)."""
+    return _eval_like("poly_eval", b, X, (b.npolys, X.shape[0]), check, prec, nslices)
 
 
-def grad(b: Batch, X: torch.Tensor, check: bool = False) -> torch.Tensor:
+def grad(b: Batch, X: torch.Tensor, check: bool = False, prec: int = POLY_FP64, nslices: int = 5) -> torch.Tensor:
     """G[p, pt, j] = d f_p / d x_j at x_pt."""
-    return _eval_like("poly_grad", b, X, (b.npolys, X.shape[0], b.n), check)
+    return _eval_like("poly_grad", b, X, (b.npolys, X.shape[0], b.n), check, prec, nslices)
 
 
-def hess(b: Batch, X: torch.Tensor, check: bool = False) -> torch.Tensor:
+def hess(b: Batch, X: torch.Tensor, check: bool = False, prec: int = POLY_FP64, nslices: int = 5) -> torch.Tensor:
     """H[p, pt, j, k] = d^2 f_p / dx_j dx_k at x_pt."""
-    return _eval_like("poly_hess", b, X, (b.npolys, X.shape[0], b.n, b.n), check)
+    return _eval_like("poly_hess", b, X, (b.npolys, X.shape[0], b.n, b.n), check, prec, nslices)
 
 
 def eval_backward(b: Batch, X: torch.Tensor, gY: torch.Tensor, want_dX: bool = True, want_dC: bool = True,
@@ -581,12 +639,12 @@ def eval_backward(b: Batch, X: torch.Tensor, gY: torch.Tensor, want_dX: bool = T
         raise ValueError(f"gY must be float64 [{b.npolys}, {N}], got {gY.dtype} {tuple(gY.shape)}")
     _check_device("gY", gY, b.coefs.device)
     ws_bytes = ctypes.c_size_t()
-    _check(L.poly_eval_backward_workspace(ctypes.byref(cin), N, ctypes.byref(ws_bytes)),
+    _check(L.poly_eval_backward_workspace(ctypes.byref(cin), N, POLY_FP64, 5, ctypes.byref(ws_bytes)),
            "poly_eval_backward_workspace")
     ws = _workspace(ws_bytes.value, b.coefs.device)
     dX = torch.empty((N, b.n), dtype=torch.float64, device=b.coefs.device) if want_dX else None
     dC = torch.empty(b.nterms, dtype=torch.float64, device=b.coefs.device) if want_dC else None
-    _check(L.poly_eval_backward(ctypes.byref(cin), _ptr(X), N, _ptr(gY), _ptr(dX), _ptr(dC),
+    _check(L.poly_eval_backward(ctypes.byref(cin), _ptr(X), N, _ptr(gY), _ptr(dX), _ptr(dC), POLY_FP64, 5,
                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "poly_eval_backward")
     if check:
         _check(L.poly_read_status(ctypes.c_void_p(ws.data_ptr()), _stream()), "poly_eval_backward")

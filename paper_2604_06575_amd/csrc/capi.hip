@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <atomic>
 #include <mutex>
+#include <new>
 #include <type_traits>
 #include <vector>
 
@@ -57,7 +58,7 @@ poly_status dense_workspace(int32_t n, int64_t K, int64_t P, int64_t N, poly_pre
                             size_t *ws_bytes);
 poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp, int64_t P, const double *C,
                       int64_t N, const double *X, double *Y, poly_prec prec, int32_t nslices, void *ws,
-                      size_t ws_bytes, hipStream_t stream);
+                      size_t ws_bytes, hipStream_t stream, int64_t ys);
 }  // namespace polyhip
 
 namespace {
@@ -1335,11 +1336,107 @@ static poly_status check_eval(const poly_csr *f, const double *X, int64_t N, con
     return POLY_OK;
 }
 
-poly_status poly_eval_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)
+// ------------------------------------------------ split precision (CSR)
+//
+// prec = POLY_SPLIT_BF16 on the sparse entry points: the batch must be a
+// shared monomial set stored as CSR -- every polynomial holds the same K
+// exponent rows in the same order (equal row lengths, checked on the host;
+// equal rows, checked on the device: POLY_ERR_UNSUPPORTED otherwise).  Its
+// coefficients are then the row-major P x K matrix of the dense
+// contraction, used in place; derivatives are contractions over derived
+// bases (e - u_j, coefficients m c with the integer multiplier m).
+
+namespace {
+
+struct SplitCsrPlan {
+    int64_t K = 0;
+    size_t dense = 0, dbasis = 0, dC = 0, total = 0;
+};
+
+poly_status plan_split_csr(const poly_csr *f, int64_t N, int32_t nslices, bool derived, SplitCsrPlan &sp)
+{
+    const int64_t P = f->npolys;
+    sp.K = P > 0 ? f->row_ptr_host[1] : 0;
+    for (int64_t p = 1; p <= P; ++p)
+        if (f->row_ptr_host[p] - f->row_ptr_host[p - 1] != sp.K) return POLY_ERR_UNSUPPORTED;
+    size_t dws = 0;
+    poly_status st = dense_workspace(f->nvars, sp.K, P, N, POLY_SPLIT_BF16, nslices, &dws);
+    if (st != POLY_OK) return st;
+    Layout L;
+    L.off = std::max(dws, (size_t)kWsHeadBytes);
+    sp.dense = 0;   // the dense path's workspace starts at ws (its status word is the call's)
+    if (derived) {
+        sp.dbasis = L.take((size_t)sp.K * f->nvars);
+        sp.dC = L.take(8 * (size_t)P * sp.K);
+    }
+    sp.total = L.total();
+    return POLY_OK;
+}
+
+// mode 0: values; 1: gradient G[p][pt][j]; 2: Hessian H[p][pt][j][k]
+poly_status run_split_csr(int mode, const poly_csr *f, const double *X, int64_t N, double *out, int32_t nslices,
+                          void *ws, size_t ws_bytes, hipStream_t s)
+{
+    SplitCsrPlan sp;
+    poly_status st = plan_split_csr(f, N, nslices, mode != 0, sp);
+    if (st != POLY_OK) return st;
+    if (!ws || ws_bytes < sp.total) return POLY_ERR_WORKSPACE;
+    const int n = f->nvars;
+    const int64_t P = f->npolys, K = sp.K;
+    int32_t *status = at<int32_t>(ws, 0);
+    clear_u64(at<unsigned long long>(ws, 0), 1, s);
+    if (P == 0 || N == 0) {
+        LAUNCH_CHECK();
+        return POLY_OK;
+    }
+    if (mode == 0) {
+        st = dense_run(n, K, f->exps, f->max_exp, P, f->coefs, N, X, out, POLY_SPLIT_BF16, nslices, ws, ws_bytes, s,
+                       1);
+    } else {
+        uint8_t *db = at<uint8_t>(ws, sp.dbasis);
+        double *dC = at<double>(ws, sp.dC);
+        const unsigned g = (unsigned)std::min<int64_t>(grid1(P * K, 256), 65535);
+        for (int j = 0; j < n && st == POLY_OK; ++j) {
+            for (int k = (mode == 1 ? -1 : j); k < (mode == 1 ? 0 : n) && st == POLY_OK; ++k) {
+                hipLaunchKernelGGL(k_derive_basis, dim3(g), dim3(256), 0, s, f->exps, K, n, j, k, db, f->coefs, P, dC);
+                double *dst = mode == 1 ? out + j : out + (int64_t)j * n + k;
+                st = dense_run(n, K, db, f->max_exp, P, dC, N, X, dst, POLY_SPLIT_BF16, nslices, ws, ws_bytes, s,
+                               mode == 1 ? n : (int64_t)n * n);
+            }
+        }
+        if (st == POLY_OK && mode == 2)
+            hipLaunchKernelGGL(k_hess_mirror, dim3((unsigned)std::min<int64_t>(grid1(P * N * n * n, 256), 65535)),
+                               dim3(256), 0, s, out, P * N, n);
+    }
+    if (st != POLY_OK) return st;
+    // every polynomial must list polynomial 0's rows (checked after the
+    // contractions, which clear the status word first)
+    if (P > 1 && K > 0)
+        hipLaunchKernelGGL(k_check_shared, dim3((unsigned)std::min<int64_t>(grid1((P - 1) * K * n, 256), 65535)),
+                           dim3(256), 0, s, f->exps, P, K, n, status);
+    LAUNCH_CHECK();
+    return POLY_OK;
+}
+
+poly_status split_csr_workspace(int mode, const poly_csr *f, int64_t N, int32_t nslices, size_t *ws_bytes)
+{
+    SplitCsrPlan sp;
+    poly_status st = plan_split_csr(f, N, nslices, mode != 0, sp);
+    if (st != POLY_OK) return st;
+    *ws_bytes = sp.total;
+    return POLY_OK;
+}
+
+}  // namespace
+
+poly_status poly_eval_workspace(const poly_csr *f, int64_t N, poly_prec prec, int32_t nslices, size_t *ws_bytes)
 {
     poly_status st = check_eval(f, nullptr, 0, nullptr);
     if (st != POLY_OK) return st;
     if (!ws_bytes || N < 0) return POLY_ERR_ARG;
+    if (prec == POLY_SPLIT_BF16) return split_csr_workspace(0, f, N, nslices, ws_bytes);
+    if (prec != POLY_FP64) return POLY_ERR_ARG;
+    (void)nslices;
     Layout L;
     L.take(16 * total_terms(f));
     L.take(eval_partial_bytes(f->npolys, N, eval_segments(f->npolys, N, total_terms(f))));
@@ -1347,11 +1444,17 @@ poly_status poly_eval_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)
     return POLY_OK;
 }
 
-poly_status poly_eval(const poly_csr *f, const double *X, int64_t N, double *Y, void *ws, size_t ws_bytes,
-                      void *stream)
+poly_status poly_eval(const poly_csr *f, const double *X, int64_t N, double *Y, poly_prec prec, int32_t nslices,
+                      void *ws, size_t ws_bytes, void *stream)
 {
     poly_status st = check_eval(f, X, N, Y);
     if (st != POLY_OK) return st;
+    if (prec == POLY_SPLIT_BF16) {
+        ensure_lds_attrs();
+        return run_split_csr(0, f, X, N, Y, nslices, ws, ws_bytes, (hipStream_t)stream);
+    }
+    if (prec != POLY_FP64) return POLY_ERR_ARG;
+    (void)nslices;
     const int64_t T = total_terms(f);
     Layout L;
     const size_t o_enc = L.take(16 * T);
@@ -1385,22 +1488,31 @@ poly_status poly_eval(const poly_csr *f, const double *X, int64_t N, double *Y, 
     return POLY_OK;
 }
 
-poly_status poly_grad_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)
+poly_status poly_grad_workspace(const poly_csr *f, int64_t N, poly_prec prec, int32_t nslices, size_t *ws_bytes)
 {
     poly_status st = check_eval(f, nullptr, 0, nullptr);
     if (st != POLY_OK) return st;
     if (!ws_bytes || N < 0) return POLY_ERR_ARG;
+    if (prec == POLY_SPLIT_BF16) return split_csr_workspace(1, f, N, nslices, ws_bytes);
+    if (prec != POLY_FP64) return POLY_ERR_ARG;
+    (void)nslices;
     Layout L;
     plan_grad(f, N, L);
     *ws_bytes = L.total();
     return POLY_OK;
 }
 
-poly_status poly_grad(const poly_csr *f, const double *X, int64_t N, double *G, void *ws, size_t ws_bytes,
-                      void *stream)
+poly_status poly_grad(const poly_csr *f, const double *X, int64_t N, double *G, poly_prec prec, int32_t nslices,
+                      void *ws, size_t ws_bytes, void *stream)
 {
     poly_status st = check_eval(f, X, N, G);
     if (st != POLY_OK) return st;
+    if (prec == POLY_SPLIT_BF16) {
+        ensure_lds_attrs();
+        return run_split_csr(1, f, X, N, G, nslices, ws, ws_bytes, (hipStream_t)stream);
+    }
+    if (prec != POLY_FP64) return POLY_ERR_ARG;
+    (void)nslices;
     Layout L;
     const GradPlan g = plan_grad(f, N, L);
     if (!ws || ws_bytes < L.total()) return POLY_ERR_WORKSPACE;
@@ -1445,11 +1557,14 @@ HessPlan plan_hess(const poly_csr *f, int64_t N, Layout &L)
     return h;
 }
 
-poly_status poly_hess_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)
+poly_status poly_hess_workspace(const poly_csr *f, int64_t N, poly_prec prec, int32_t nslices, size_t *ws_bytes)
 {
     poly_status st = check_eval(f, nullptr, 0, nullptr);
     if (st != POLY_OK) return st;
     if (!ws_bytes || N < 0) return POLY_ERR_ARG;
+    if (prec == POLY_SPLIT_BF16) return split_csr_workspace(2, f, N, nslices, ws_bytes);
+    if (prec != POLY_FP64) return POLY_ERR_ARG;
+    (void)nslices;
     Layout L;
     plan_hess(f, N, L);
     *ws_bytes = L.total();
@@ -1503,11 +1618,17 @@ poly_status run_hess(const poly_csr *f, const double *X, int64_t N, double *H, v
     return POLY_OK;
 }
 
-poly_status poly_hess(const poly_csr *f, const double *X, int64_t N, double *H, void *ws, size_t ws_bytes,
-                      void *stream)
+poly_status poly_hess(const poly_csr *f, const double *X, int64_t N, double *H, poly_prec prec, int32_t nslices,
+                      void *ws, size_t ws_bytes, void *stream)
 {
     poly_status st = check_eval(f, X, N, H);
     if (st != POLY_OK) return st;
+    if (prec == POLY_SPLIT_BF16) {
+        ensure_lds_attrs();
+        return run_split_csr(2, f, X, N, H, nslices, ws, ws_bytes, (hipStream_t)stream);
+    }
+    if (prec != POLY_FP64) return POLY_ERR_ARG;
+    (void)nslices;
     Layout L;
     const HessPlan h = plan_hess(f, N, L);
     if (!ws || ws_bytes < L.total()) return POLY_ERR_WORKSPACE;
@@ -1848,11 +1969,14 @@ void launch_dc(const poly_csr *f, const double *X, int64_t N, const double *gY, 
 
 }  // namespace
 
-poly_status poly_eval_backward_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)
+poly_status poly_eval_backward_workspace(const poly_csr *f, int64_t N, poly_prec prec, int32_t nslices, size_t *ws_bytes)
 {
     poly_status st = check_eval(f, nullptr, 0, nullptr);
     if (st != POLY_OK) return st;
     if (!ws_bytes || N < 0) return POLY_ERR_ARG;
+    if (prec == POLY_SPLIT_BF16) return POLY_ERR_UNSUPPORTED;
+    if (prec != POLY_FP64) return POLY_ERR_ARG;
+    (void)nslices;
     Layout L;
     plan_backward(f, N, L);
     *ws_bytes = L.total();
@@ -1860,10 +1984,13 @@ poly_status poly_eval_backward_workspace(const poly_csr *f, int64_t N, size_t *w
 }
 
 poly_status poly_eval_backward(const poly_csr *f, const double *X, int64_t N, const double *gY, double *dX,
-                               double *dC, void *ws, size_t ws_bytes, void *stream)
+                               double *dC, poly_prec prec, int32_t nslices, void *ws, size_t ws_bytes, void *stream)
 {
     poly_status st = check_eval(f, X, N, gY);
     if (st != POLY_OK) return st;
+    if (prec == POLY_SPLIT_BF16) return POLY_ERR_UNSUPPORTED;
+    if (prec != POLY_FP64) return POLY_ERR_ARG;
+    (void)nslices;
     const int n = f->nvars;
     const int64_t P = f->npolys, T = total_terms(f);
     Layout L;
@@ -1976,6 +2103,170 @@ poly_status poly_eval_backward2(const poly_csr *f, const double *X, int64_t N, c
     return POLY_OK;
 }
 
+// --------------------------------------------------------------- plans
+//
+// A plan is the pipeline simplify -> jacobian -> gradient values of a
+// polynomial matrix, recorded once into a HIP graph.  Every size that the
+// eager entry points read back (the simplified term counts, the Jacobian's
+// term counts) stays on the device: the Jacobian is formed over worst-case
+// work items and capacities, its factor lists are encoded up to the count
+// the device wrote, and evaluation units skip what lies past it.
+
+}  // extern "C"
+
+struct poly_plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+struct PipePlan {
+    SimplifyPlan sp;
+    FormPlan form;
+    size_t enc = 0, part = 0, total = 0;
+    int64_t jcap = 0, S = 1;
+};
+
+PipePlan plan_pipeline(const poly_csr *in, int64_t N)
+{
+    PipePlan pp;
+    const int n = in->nvars;
+    const int64_t P = in->npolys, T = total_terms(in);
+    pp.sp = plan_simplify(P, T, in->row_ptr_host, n, (uint32_t)in->max_exp + 1);
+    Layout L;
+    L.off = pp.sp.total;
+    pp.jcap = grad_terms_bound(T, n);
+    pp.form = plan_form_bound(P, T, n, L);
+    pp.enc = L.take(16 * std::max<int64_t>(pp.jcap, 1));
+    pp.S = eval_segments(P * n, N, pp.jcap);
+    pp.part = L.take(eval_partial_bytes(P * n, N, pp.S));
+    pp.total = L.total();
+    return pp;
+}
+
+poly_status check_pipeline(const poly_csr *in, const double *X, int64_t N, const poly_csr *simp,
+                           const poly_csr *jac, const double *G)
+{
+    poly_status st = check_csr(in, true);
+    if (st != POLY_OK) return st;
+    if (N < 0) return POLY_ERR_ARG;
+    if ((int64_t)in->nvars * bit_width_u32((uint32_t)in->max_exp) > 64) return POLY_ERR_KEY_OVERFLOW;
+    if (!simp && !jac && !G) return POLY_OK;   // workspace query
+    if ((st = check_csr(simp, false)) != POLY_OK) return st;
+    if ((st = check_csr(jac, false)) != POLY_OK) return st;
+    const int n = in->nvars;
+    const int64_t P = in->npolys, T = total_terms(in);
+    if (simp->nvars != n || simp->npolys != P || simp->capacity < T || simp->max_exp < in->max_exp) return POLY_ERR_ARG;
+    if (jac->nvars != n || jac->npolys != P * n || jac->capacity < grad_terms_bound(T, n)) return POLY_ERR_ARG;
+    if (P > 0 && N > 0 && (!X || !G)) return POLY_ERR_ARG;
+    return POLY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+poly_status poly_plan_workspace(const poly_csr *in, int64_t N, size_t *ws_bytes)
+{
+    poly_status st = check_pipeline(in, nullptr, N, nullptr, nullptr, nullptr);
+    if (st != POLY_OK) return st;
+    if (!ws_bytes) return POLY_ERR_ARG;
+    *ws_bytes = plan_pipeline(in, N).total;
+    return POLY_OK;
+}
+
+poly_status poly_plan_create(const poly_csr *in, double zero_tol, const double *X, int64_t N, poly_csr *simplified,
+                             poly_csr *jac, double *G, void *ws, size_t ws_bytes, void *stream, poly_plan **plan)
+{
+    if (!plan) return POLY_ERR_ARG;
+    *plan = nullptr;
+    poly_status st = check_pipeline(in, X, N, simplified, jac, G);
+    if (st != POLY_OK) return st;
+    if (!(zero_tol >= 0.0)) return POLY_ERR_ARG;
+    if (!stream) return POLY_ERR_ARG;   // the legacy null stream cannot be captured
+    const PipePlan pp = plan_pipeline(in, N);
+    if (!ws || ws_bytes < pp.total) return POLY_ERR_WORKSPACE;
+    const int n = in->nvars;
+    const int64_t P = in->npolys;
+    hipStream_t s = (hipStream_t)stream;
+    ensure_lds_attrs();
+    (void)device_cus();
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return POLY_ERR_HIP;
+    int32_t *status = at<int32_t>(ws, 0);
+    clear_u64(at<unsigned long long>(ws, 0), 1, s);
+    if (P == 0) {
+        clear_u64((unsigned long long *)simplified->row_ptr, 1, s);
+        clear_u64((unsigned long long *)jac->row_ptr, 1, s);
+    } else {
+        st = run_simplify(in, simplified, zero_tol, ws, pp.sp, s);
+        if (st == POLY_OK) {
+            FormArgs F = form_args(simplified->row_ptr, simplified->exps, simplified->coefs, n, 0, 0, status,
+                                   (int32_t)POLY_ERR_CAPACITY);
+            F.out_rp = jac->row_ptr;
+            F.out_exps = jac->exps;
+            F.out_coefs = jac->coefs;
+            F.capacity = jac->capacity;
+            run_form(pp.form, F, ws, s);
+            if (N > 0) {
+                uint32_t *enc = at<uint32_t>(ws, pp.enc);
+                hipLaunchKernelGGL(k_encode_factors, dim3(grid1(pp.jcap, 256)), dim3(256), 0, s, jac->exps, pp.jcap, n,
+                                   enc, (const int64_t *)(jac->row_ptr + P * n));
+                EvalArgs A;
+                memset(&A, 0, sizeof(A));
+                A.rp = jac->row_ptr;
+                A.exps = jac->exps;
+                A.coefs = jac->coefs;
+                A.n = n;
+                A.X = X;
+                A.N = N;
+                A.Q = P * n;
+                A.mode = OUT_GRAD;
+                A.Y = G;
+                A.term_limit = pp.jcap;
+                launch_eval_blocks(A, enc, at<double>(ws, pp.part), pp.S, s);
+            }
+        }
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &graph);
+    if (st != POLY_OK || ec != hipSuccess || hipGetLastError() != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st != POLY_OK ? st : POLY_ERR_HIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return POLY_ERR_HIP;
+    }
+    poly_plan *p = new (std::nothrow) poly_plan;
+    if (!p) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return POLY_ERR_HIP;
+    }
+    p->graph = graph;
+    p->exec = exec;
+    *plan = p;
+    return POLY_OK;
+}
+
+poly_status poly_plan_launch(const poly_plan *plan, void *stream)
+{
+    if (!plan || !plan->exec) return POLY_ERR_ARG;
+    return hipGraphLaunch(plan->exec, (hipStream_t)stream) == hipSuccess ? POLY_OK : POLY_ERR_HIP;
+}
+
+poly_status poly_plan_destroy(poly_plan *plan)
+{
+    if (!plan) return POLY_OK;
+    poly_status st = POLY_OK;
+    if (plan->exec && hipGraphExecDestroy(plan->exec) != hipSuccess) st = POLY_ERR_HIP;
+    if (plan->graph && hipGraphDestroy(plan->graph) != hipSuccess) st = POLY_ERR_HIP;
+    delete plan;
+    return st;
+}
+
 // ----------------------------------------------------------- dense (shared set)
 
 poly_status poly_eval_dense_workspace(int32_t n, int64_t K, int64_t P, int64_t N, poly_prec prec, int32_t nslices,
@@ -1988,7 +2279,7 @@ poly_status poly_eval_dense(int32_t n, int64_t K, const uint8_t *basis, int32_t 
                             const double *C, int64_t N, const double *X, double *Y, poly_prec prec,
                             int32_t nslices, void *ws, size_t ws_bytes, void *stream)
 {
-    return dense_run(n, K, basis, max_exp, P, C, N, X, Y, prec, nslices, ws, ws_bytes, (hipStream_t)stream);
+    return dense_run(n, K, basis, max_exp, P, C, N, X, Y, prec, nslices, ws, ws_bytes, (hipStream_t)stream, 1);
 }
 
 }  // extern "C"

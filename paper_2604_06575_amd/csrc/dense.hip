@@ -101,7 +101,7 @@ constexpr int D64_BM = 64, D64_BN = 128, D64_KS = 16, D64_THREADS = 256;
 // factor lists staged in LDS one step ahead.
 __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, const uint8_t *basis,
                                                            const uint4 *enc, int64_t P, const double *C,
-                                                           int64_t N, const double *X, double *Y)
+                                                           int64_t N, const double *X, double *Y, int64_t ys)
 {
     extern __shared__ double s_x[];                    // [n + 1][D64_BN], last row ones
     __shared__ double s_c[D64_BM][D64_KS + 1];
@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, con
                 // row (l / 16) + 4 v, column l % 16 of the 16 x 16 tile
                 const int64_t r = r0 + wr * 32 + rt * 16 + (lane >> 4) + 4 * v;
                 const int64_t c = n0 + wc * 64 + ct * 16 + (lane & 15);
-                if (r < P && c < N) Y[r * N + c] = acc[rt][ct][v];
+                if (r < P && c < N) Y[(r * N + c) * ys] = acc[rt][ct][v];
             }
 }
 
@@ -312,7 +312,7 @@ template <int S>
 __global__ void __launch_bounds__(SP_THREADS) k_dense_split(int n, int64_t K, int64_t Kp, const uint8_t *basis,
                                                             const uint4 *enc, int64_t P,
                                                             const unsigned short *Cs, int64_t N, const double *X,
-                                                            const int32_t *sig_v, double *Y)
+                                                            const int32_t *sig_v, double *Y, int64_t ys)
 {
     static_assert(SP_VK == 4, "V digits are stored as 2 words per plane");
     extern __shared__ double s_dyn[];
@@ -511,7 +511,7 @@ __global__ void __launch_bounds__(SP_THREADS) k_dense_split(int n, int64_t K, in
         for (int v = 0; v < 16; ++v) {
             const int64_t r = r0 + w * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
             const int64_t c = n0 + ct * 32 + (lane & 31);
-            if (r < P && c < N) Y[r * N + c] = ct == 0 ? out[v] : my_out[64 * v];
+            if (r < P && c < N) Y[(r * N + c) * ys] = ct == 0 ? out[v] : my_out[64 * v];
         }
 }
 
@@ -546,7 +546,8 @@ DensePlan plan_dense(int32_t n, int64_t K, int64_t P, int64_t N, poly_prec prec,
 
 template <int S>
 void launch_split(int n, int64_t K, int64_t Kp, const uint8_t *basis, const uint4 *enc, int64_t P,
-                  const unsigned short *Cs, int64_t N, const double *X, const int32_t *sig_v, double *Y, hipStream_t s)
+                  const unsigned short *Cs, int64_t N, const double *X, const int32_t *sig_v, double *Y, int64_t ys,
+                  hipStream_t s)
 {
     const size_t lds = split_lds_bytes(n, S);
     static bool attr = false;
@@ -558,7 +559,7 @@ void launch_split(int n, int64_t K, int64_t Kp, const uint8_t *basis, const uint
     const dim3 grid((unsigned)ceil_div(N, SP_BN), (unsigned)ceil_div(P, SP_BM));
     TimedLaunch tl(POLY_TIMING_DENSE, s);
     hipLaunchKernelGGL((k_dense_split<S>), grid, dim3(SP_THREADS), lds, s, n, K, Kp, basis, enc, P, Cs, N, X, sig_v,
-                       Y);
+                       Y, ys);
     tl.done(s);
 }
 
@@ -575,7 +576,7 @@ poly_status dense_workspace(int32_t n, int64_t K, int64_t P, int64_t N, poly_pre
 
 poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp, int64_t P, const double *C,
                       int64_t N, const double *X, double *Y, poly_prec prec, int32_t S, void *ws, size_t ws_bytes,
-                      hipStream_t s)
+                      hipStream_t s, int64_t ys)
 {
     size_t need = 0;
     poly_status st = dense_workspace(n, K, P, N, prec, S, &need);
@@ -604,7 +605,7 @@ poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_ex
         const dim3 grid((unsigned)ceil_div(N, D64_BN), (unsigned)ceil_div(P, D64_BM));
         TimedLaunch tl(POLY_TIMING_DENSE, s);
         hipLaunchKernelGGL(k_dense_f64, grid, dim3(D64_THREADS), (size_t)(n + 1) * D64_BN * 8, s, n, K, basis,
-                           (const uint4 *)enc, P, C, N, X, Y);
+                           (const uint4 *)enc, P, C, N, X, Y, ys);
         tl.done(s);
     } else {
         unsigned short *Cs = (unsigned short *)((char *)ws + d.cs);
@@ -618,13 +619,66 @@ poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_ex
                                (size_t)(n + 1) * 64 * 8, s, n, K, basis, (const uint4 *)enc, N, X, sig_v);
         }
         switch (S) {
-        case 3: launch_split<3>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, s); break;
-        case 4: launch_split<4>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, s); break;
-        case 5: launch_split<5>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, s); break;
-        default: launch_split<6>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, s); break;
+        case 3: launch_split<3>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, ys, s); break;
+        case 4: launch_split<4>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, ys, s); break;
+        case 5: launch_split<5>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, ys, s); break;
+        default: launch_split<6>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, ys, s); break;
         }
     }
     return hipGetLastError() == hipSuccess ? POLY_OK : POLY_ERR_HIP;
+}
+
+// ------------------------------------------- CSR batches over a shared basis
+
+// Status POLY_ERR_UNSUPPORTED unless every polynomial of the batch (P rows
+// of K terms each) lists the same exponent rows as polynomial 0.
+__global__ void k_check_shared(const uint8_t *exps, int64_t P, int64_t K, int n, int32_t *status)
+{
+    const int64_t bytes = K * n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (P - 1) * bytes;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (exps[bytes + i] != exps[i % bytes]) {
+            set_status(status, POLY_ERR_UNSUPPORTED);
+            break;
+        }
+}
+
+// Derived basis and coefficients of a derivative of a shared-basis batch:
+// with j >= 0 (and k >= 0 for a second derivative) the basis row e becomes
+// e - u_j (- u_k) and the coefficients are scaled by the integer
+// multiplier m = e_j (or e_j (e_k - [j == k]), formed first), so that the
+// derivative is the contraction of C' = m C with the derived monomials.  A
+// row whose multiplier is zero keeps e with coefficient 0.
+__global__ void k_derive_basis(const uint8_t *basis, int64_t K, int n, int j, int k, uint8_t *dbasis, const double *C,
+                               int64_t P, double *dC)
+{
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < P * K;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t kk = idx % K;
+        const uint8_t *row = basis + kk * n;
+        const int ej = row[j];
+        const int m = k < 0 ? ej : ej * ((int)row[k] - (k == j ? 1 : 0));
+        dC[idx] = m > 0 ? C[idx] * (double)m : 0.0;
+        if (idx < K) {
+            for (int i = 0; i < n; ++i) {
+                const int e = row[i];
+                dbasis[kk * n + i] = (uint8_t)(m > 0 ? e - (i == j) - (k >= 0 && i == k) : e);
+            }
+        }
+    }
+}
+
+// H[p][pt][k][j] = H[p][pt][j][k] for j < k (the upper triangle was written)
+__global__ void k_hess_mirror(double *H, int64_t PN, int n)
+{
+    const int64_t total = PN * n * n;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = idx / ((int64_t)n * n);
+        const int r = (int)(idx % ((int64_t)n * n));
+        const int a = r / n, b = r % n;
+        if (a > b) H[idx] = H[q * n * n + (int64_t)b * n + a];
+    }
 }
 
 }  // namespace polyhip

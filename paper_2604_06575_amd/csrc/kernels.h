@@ -223,6 +223,11 @@ __global__ void k_affine_normal(int n, const uint4 *enc, const double *coefs, in
 __global__ void k_eval_terms(EvalArgs A, const uint32_t *enc, double *partial, int64_t S);
 __global__ void k_eval_reduce(EvalArgs A, const double *partial, int64_t S);
 __global__ void k_hess_transpose(const double *stage, int64_t P, int64_t N, int n, double *H);
+// CSR batches over a shared basis (dense.hip)
+__global__ void k_check_shared(const uint8_t *exps, int64_t P, int64_t K, int n, int32_t *status);
+__global__ void k_derive_basis(const uint8_t *basis, int64_t K, int n, int j, int k, uint8_t *dbasis, const double *C,
+                               int64_t P, double *dC);
+__global__ void k_hess_mirror(double *H, int64_t PN, int n);
 __global__ void k_eval_wsum(EvalArgs A, const uint32_t *enc, const double *gY, int64_t P, int64_t S, double *out,
                             double *partial);
 constexpr int64_t EV_TARGET_WAVES = 16384;   // waves wanted before polynomials are cut into segments
