@@ -241,7 +241,37 @@ def bench_eval(args):
             "kernel_mfma_frac": mfma_flops / (k_ms / 1e3) / 1e12 / peak,
             "error_sample": "8 points x all polynomials vs a NumPy FP64 reference (C V)",
         }
+        if prec == ph.POLY_FP64:
+            Y64 = Y.clone()
+        else:
+            # the split result over every output against the FP64 GPU path,
+            # condition-scaled by sum_k |c_k v_k| (an FP64 contraction of |C|
+            # with the monomials at |x|) and componentwise
+            A = ph.eval_dense(basis, C.abs(), X.abs(), prec=ph.POLY_FP64)
+            d = (Y - Y64).abs()
+            rel = d / Y64.abs().clamp_min(1e-300)
+            res[name]["all_outputs_vs_fp64_gpu"] = {
+                "outputs": int(Y.numel()),
+                "max_cond_scaled_err": float((d / A).max().item()),
+                "max_rel_err": float(rel.max().item()),
+                "median_rel_err": float(rel.flatten()[::97].median().item()),
+                "frac_rel_err_above_1e-10": float((rel > 1e-10).double().mean().item()),
+                "note": "median over every 97th output; max and fraction over all outputs",
+            }
+            del A, d, rel, Y64
         del ws
+    # reverse mode (FP64 MFMA): dC = gY V^T and dX through W = C^T gY
+    gY = torch.randn((P, N), dtype=torch.float64, device="cuda")
+    fn_b = lambda: ph.eval_dense_backward(basis, C, X, gY)  # noqa: E731
+    t_b, _ = time_events(fn_b, 1, 1)
+    k_ms_b, _ = kernel_ms(ph.TIMING_DENSE, lambda: ph.eval_dense_backward(basis, C, X, gY, want_dX=False), 1)
+    t_dx, _ = time_events(lambda: ph.eval_dense_backward(basis, C, X, gY, want_dC=False), 1, 1)
+    flops = 2.0 * P * K * N
+    res["backward_fp64"] = {"ms": t_b * 1e3, "dC_kernel_ms": k_ms_b, "dX_ms": t_dx * 1e3,
+                            "dC_mfma_frac": flops / (k_ms_b / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+                            "dX_mfma_frac": flops / t_dx / 1e12 / FP64_PEAK_TFLOPS,
+                            "flops_note": "dC = gY V^T and W = C^T gY are 2 P K N flops each"}
+    del gY
     res["workload"] = {"polys": P, "monomials": K, "points": N, "n": wl.n, "degree": 4}
     return res
 

@@ -328,6 +328,23 @@ poly_status poly_eval_dense(int32_t n, int64_t K, const uint8_t *basis, int32_t 
                             double *Y, poly_prec prec, int32_t nslices,
                             void *ws, size_t ws_bytes, void *stream);
 
+/* Reverse mode of poly_eval_dense for a cotangent gY [P x N]:
+ *   dC[p*K + k]  = sum_pt gY[p*N + pt] * v_k(x_pt)            (may be NULL)
+ *   dX[pt*n + j] = sum_k W[k][pt] * d v_k / d x_{j+1} (x_pt),
+ *                  W = C^T gY                                   (may be NULL)
+ * Both products run on FP64 MFMA: dC with V^T formed per step of points;
+ * dX per tile of 128 points with the W tile of each 64 monomials formed and
+ * contracted at once with the monomials' derivatives (W is never stored).
+ * prec: POLY_FP64 (POLY_SPLIT_BF16 returns POLY_ERR_UNSUPPORTED).  Limits:
+ * dX needs n <= 43 (points and four accumulator blocks in LDS), else
+ * POLY_ERR_UNSUPPORTED; basis, C and X as in poly_eval_dense. */
+poly_status poly_eval_dense_backward_workspace(int32_t n, int64_t K, int64_t P, int64_t N, poly_prec prec,
+                                               int32_t nslices, size_t *ws_bytes);
+poly_status poly_eval_dense_backward(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp, int64_t P,
+                                     const double *C, int64_t N, const double *X, const double *gY,
+                                     double *dC, double *dX, poly_prec prec, int32_t nslices,
+                                     void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------ plans
  * A plan records, once, the pipeline of a polynomial matrix
  *   simplified = simplify(in, zero_tol)        (Table "coresemantics")

@@ -15,7 +15,7 @@ import numpy as np
 import torch
 
 __all__ = [
-    "Batch", "PolyError", "PolyEval", "PolyEvalBackward", "Plan", "batch_from_numpy", "batch_to_numpy", "mul", "simplify", "jacobian",
+    "Batch", "PolyError", "PolyEval", "PolyEvalBackward", "PolyEvalDense", "Plan", "eval_dense_backward", "batch_from_numpy", "batch_to_numpy", "mul", "simplify", "jacobian",
     "eval", "grad", "hess", "eval_backward", "eval_dense", "mtimes", "mpower", "msum", "mprod", "concat", "subs",
     "affine_normal",
     "library_path", "lib",
@@ -46,6 +46,7 @@ EXPORTS = [
     "poly_concat",
     "poly_simplify_noalloc",
     "poly_plan_workspace", "poly_plan_create", "poly_plan_launch", "poly_plan_destroy",
+    "poly_eval_dense_backward_workspace", "poly_eval_dense_backward",
 ]
 
 
@@ -122,6 +123,9 @@ def lib():
         "poly_plan_create": ([pcsr, d, P, i64, pcsr, pcsr, P, P, ctypes.c_size_t, P, ctypes.POINTER(P)], i32),
         "poly_plan_launch": ([P, P], i32),
         "poly_plan_destroy": ([P], i32),
+        "poly_eval_dense_backward_workspace": ([i32, i64, i64, i64, i32, i32, psz], i32),
+        "poly_eval_dense_backward": ([i32, i64, P, i32, i64, P, i64, P, P, P, P, i32, i32, P, ctypes.c_size_t, P],
+                                     i32),
         "poly_eval_dense": ([i32, i64, P, i32, i64, P, i64, P, P, i32, i32, P, ctypes.c_size_t, P], i32),
     }
     for name, (args, res) in sig.items():
@@ -757,7 +761,54 @@ def eval_dense(basis: torch.Tensor, C: torch.Tensor, X: torch.Tensor, prec: int 
     return Y
 
 
+def eval_dense_backward(basis: torch.Tensor, C: torch.Tensor, X: torch.Tensor, gY: torch.Tensor,
+                        want_dC: bool = True, want_dX: bool = True, max_exp: int | None = None):
+    """Reverse mode of eval_dense (FP64 MFMA): (dC [P, K], dX [N, n])."""
+    L = lib()
+    basis, C, X, gY = basis.contiguous(), C.contiguous(), X.contiguous(), gY.contiguous()
+    K, n = basis.shape
+    P, N = C.shape[0], X.shape[0]
+    if basis.dtype != torch.uint8 or C.dtype != torch.float64 or C.dim() != 2 or C.shape[1] != K:
+        raise ValueError(f"basis must be uint8 [K, n] and C float64 [P, {K}]")
+    _check_device("C", C)
+    _check_device("basis", basis, C.device)
+    _check_points(X, n, C.device)
+    if gY.dtype != torch.float64 or tuple(gY.shape) != (P, N):
+        raise ValueError(f"gY must be float64 [{P}, {N}]")
+    _check_device("gY", gY, C.device)
+    ws_bytes = ctypes.c_size_t()
+    _check(L.poly_eval_dense_backward_workspace(n, K, P, N, POLY_FP64, 5, ctypes.byref(ws_bytes)),
+           "poly_eval_dense_backward_workspace")
+    ws = _workspace(ws_bytes.value, C.device)
+    dC = torch.empty((P, K), dtype=torch.float64, device=C.device) if want_dC else None
+    dX = torch.empty((N, n), dtype=torch.float64, device=C.device) if want_dX else None
+    me = int(max_exp) if max_exp is not None else 255
+    _check(L.poly_eval_dense_backward(n, K, _ptr(basis), me, P, _ptr(C), N, _ptr(X), _ptr(gY), _ptr(dC), _ptr(dX),
+                                      POLY_FP64, 5, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()),
+           "poly_eval_dense_backward")
+    return dC, dX
+
+
 # -------------------------------------------------------------------- autograd
+
+
+class PolyEvalDense(torch.autograd.Function):
+    """Y = C V for P polynomials over one shared monomial set, differentiable
+    in (C, X): the forward is eval_dense (FP64 or split BF16), the backward
+    the FP64 MFMA reverse mode (eval_dense_backward)."""
+
+    @staticmethod
+    def forward(ctx, C, X, basis, prec: int = POLY_FP64, nslices: int = 5):
+        ctx.save_for_backward(C, X, basis)
+        return eval_dense(basis, C.detach(), X.detach(), prec=prec, nslices=nslices)
+
+    @staticmethod
+    @torch.autograd.function.once_differentiable
+    def backward(ctx, gY):
+        C, X, basis = ctx.saved_tensors
+        dC, dX = eval_dense_backward(basis, C.detach(), X.detach(), gY.detach(),
+                                     want_dC=ctx.needs_input_grad[0], want_dX=ctx.needs_input_grad[1])
+        return dC, dX, None, None, None
 
 class PolyEval(torch.autograd.Function):
     """Y = eval(f, X) as a differentiable function of (coefs, X).

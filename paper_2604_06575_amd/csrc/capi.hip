@@ -59,6 +59,10 @@ poly_status dense_workspace(int32_t n, int64_t K, int64_t P, int64_t N, poly_pre
 poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp, int64_t P, const double *C,
                       int64_t N, const double *X, double *Y, poly_prec prec, int32_t nslices, void *ws,
                       size_t ws_bytes, hipStream_t stream, int64_t ys);
+poly_status dense_bwd_workspace(int32_t n, int64_t K, int64_t P, int64_t N, size_t *ws_bytes);
+poly_status dense_bwd_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp, int64_t P, const double *C,
+                          int64_t N, const double *X, const double *gY, double *dC, double *dX, void *ws,
+                          size_t ws_bytes, hipStream_t s);
 }  // namespace polyhip
 
 namespace {
@@ -2280,6 +2284,26 @@ poly_status poly_eval_dense(int32_t n, int64_t K, const uint8_t *basis, int32_t 
                             int32_t nslices, void *ws, size_t ws_bytes, void *stream)
 {
     return dense_run(n, K, basis, max_exp, P, C, N, X, Y, prec, nslices, ws, ws_bytes, (hipStream_t)stream, 1);
+}
+
+poly_status poly_eval_dense_backward_workspace(int32_t n, int64_t K, int64_t P, int64_t N, poly_prec prec,
+                                               int32_t nslices, size_t *ws_bytes)
+{
+    (void)nslices;
+    if (prec == POLY_SPLIT_BF16) return POLY_ERR_UNSUPPORTED;
+    if (prec != POLY_FP64) return POLY_ERR_ARG;
+    return dense_bwd_workspace(n, K, P, N, ws_bytes);
+}
+
+poly_status poly_eval_dense_backward(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp, int64_t P,
+                                     const double *C, int64_t N, const double *X, const double *gY, double *dC,
+                                     double *dX, poly_prec prec, int32_t nslices, void *ws, size_t ws_bytes,
+                                     void *stream)
+{
+    (void)nslices;
+    if (prec == POLY_SPLIT_BF16) return POLY_ERR_UNSUPPORTED;
+    if (prec != POLY_FP64) return POLY_ERR_ARG;
+    return dense_bwd_run(n, K, basis, max_exp, P, C, N, X, gY, dC, dX, ws, ws_bytes, (hipStream_t)stream);
 }
 
 }  // extern "C"

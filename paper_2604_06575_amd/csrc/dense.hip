@@ -207,6 +207,240 @@ __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, con
             }
 }
 
+// ------------------------------------------------------- FP64 reverse mode
+//
+// Reverse mode of Y = C V for a cotangent gY [P x N]:
+//   dC = gY V^T            [P x K]: MFMA over points, V^T built per step
+//   dX[pt][j] = sum_k W[k][pt] d v_k / d x_j (x_pt),   W = C^T gY [K x N]
+// dX never stores W: a workgroup owns a tile of points, forms W for one
+// tile of monomials at a time on MFMA (contraction over the polynomials),
+// and contracts it at once with the monomials' first derivatives.
+
+constexpr int DB_BM = 64, DB_BN = 128, DB_KS = 16, DB_THREADS = 256;
+
+// dC tile: rows p (64), columns k (128), contraction over points in steps
+// of 16.  Each thread owns one monomial column (its factor list held in
+// registers) and forms 8 of its values per step from the step's points,
+// staged in LDS (dynamic: (n + 1) * 16 doubles, last row ones).
+__global__ void __launch_bounds__(DB_THREADS) k_dense_bwd_dc(int n, int64_t K, const uint8_t *basis, const uint4 *enc,
+                                                            int64_t P, const double *gY, int64_t N, const double *X,
+                                                            double *dC)
+{
+    extern __shared__ double s_xp[];                 // [n + 1][DB_KS]
+    __shared__ double s_a[DB_BM][DB_KS + 1];
+    __shared__ double s_b[DB_KS][DB_BN + 2];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int64_t r0 = (int64_t)blockIdx.y * DB_BM;
+    const int64_t k0 = (int64_t)blockIdx.x * DB_BN;
+    const int vcol = tid & (DB_BN - 1), vpb = (tid >> 7) * 8;
+    const int64_t kcol = k0 + vcol;
+    const uint4 my_enc = kcol < K ? enc[kcol] : make_uint4(0, 0, 0, 0);
+    const int arow = tid >> 2, acol = (tid & 3) * 4;
+    d4v acc[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
+    for (int64_t p0 = 0; p0 < N; p0 += DB_KS) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t r = r0 + arow, pt = p0 + acol + q;
+            s_a[arow][acol + q] = (r < P && pt < N) ? gY[r * N + pt] : 0.0;
+        }
+        for (int idx = tid; idx < (n + 1) * DB_KS; idx += DB_THREADS) {
+            const int i = idx / DB_KS, l = idx % DB_KS;
+            const int64_t pt = p0 + l;
+            s_xp[idx] = i == n ? 1.0 : (pt < N ? X[pt * n + i] : 0.0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            s_b[vpb + q][vcol] =
+                kcol < K ? factor_value(my_enc, basis + kcol * n, n, s_xp + vpb + q, DB_KS) : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int k4 = 0; k4 < DB_KS; k4 += 4) {
+            double a[2], b[4];
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) a[rt] = s_a[wr * 32 + rt * 16 + (lane & 15)][k4 + (lane >> 4)];
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) b[ct] = s_b[k4 + (lane >> 4)][wc * 64 + ct * 16 + (lane & 15)];
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct)
+                    acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b[ct], acc[rt][ct], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t r = r0 + wr * 32 + rt * 16 + (lane >> 4) + 4 * v;
+                const int64_t c = k0 + wc * 64 + ct * 16 + (lane & 15);
+                if (r < P && c < K) dC[r * K + c] = acc[rt][ct][v];
+            }
+}
+
+// d v / d x_j for every variable j of a monomial given by its support
+// encoding (up to eight (variable, exponent) slots; 0xFFFF: the dense row),
+// each added, times w, to acc[j * 64] (an LDS accumulator column).
+__device__ inline void add_monomial_grad(const uint64_t w0, const uint64_t w1, const uint8_t *row, int n,
+                                         const double *x, int xs, double w, double *acc)
+{
+    if ((w0 & 0xffffull) == 0xffffull) {
+        for (int j = 0; j < n; ++j) {
+            const int ej = row[j];
+            if (!ej) continue;
+            double p = (double)ej;
+            for (int i = 0; i < n; ++i) {
+                const int ei = row[i] - (i == j);
+                if (ei > 0) p = p * powi_d(x[i * xs], (uint32_t)ei);
+            }
+            __hip_atomic_fetch_add(acc + j * kWave, w * p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        }
+        return;
+    }
+    int var[8], ex[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const uint32_t ent = (uint32_t)(((s < 4 ? w0 : w1) >> (16 * (s & 3))) & 0xffffu);
+        var[s] = (int)(ent & 0xffu);
+        ex[s] = (int)(ent >> 8);
+    }
+    double pw[8], pm[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const double xv = x[var[s] * xs];
+        double q = 1.0;
+        for (int i = 1; i < ex[s]; ++i) q = q * xv;
+        pm[s] = q;
+        pw[s] = ex[s] ? q * xv : 1.0;
+    }
+    double pre[9], suf[9];
+    pre[0] = 1.0;
+    suf[8] = 1.0;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) pre[s + 1] = pre[s] * pw[s];
+#pragma unroll
+    for (int s = 7; s >= 0; --s) suf[s] = pw[s] * suf[s + 1];
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+        if (ex[s])
+            __hip_atomic_fetch_add(acc + var[s] * kWave, w * ((double)ex[s] * ((pm[s] * pre[s]) * suf[s + 1])),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// dX for one tile of 128 points.  Per monomial tile (64): W tile on MFMA
+// (A = C^T rows k, B = gY rows p, contraction over P in steps of 16), then
+// each lane's W entries times the derivatives of their monomials at their
+// points, added into its wave's accumulator block [n][64 points] (LDS adds:
+// one wave's adds apply in program and lane order, so the sums do not
+// depend on scheduling).  The two waves covering the same points are added
+// in a fixed order at the end.  Dynamic LDS: points [(n + 1)][128] and four
+// accumulator blocks [n][64].
+__global__ void __launch_bounds__(DB_THREADS) k_dense_bwd_dx(int n, int64_t K, const uint8_t *basis,
+                                                            const uint64_t *senc, int64_t P, const double *C,
+                                                            const double *gY, int64_t N, const double *X, double *dX)
+{
+    extern __shared__ double s_dyn[];
+    double *s_x = s_dyn;                                    // [n + 1][DB_BN]
+    double *s_acc = s_dyn + (size_t)(n + 1) * DB_BN;        // [4][n][64]
+    __shared__ double s_a[DB_BM][DB_KS + 1];                // C^T tile: [k][p]
+    __shared__ double s_b[DB_KS][DB_BN + 2];                // gY tile: [p][pt]
+    __shared__ uint64_t s_enc[DB_BM][2];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int64_t n0 = (int64_t)blockIdx.x * DB_BN;
+    for (int idx = tid; idx < (n + 1) * DB_BN; idx += DB_THREADS) {
+        const int i = idx / DB_BN, c = idx % DB_BN;
+        const int64_t pt = n0 + c;
+        s_x[idx] = i == n ? 1.0 : (pt < N ? X[pt * n + i] : 0.0);
+    }
+    for (int idx = tid; idx < 4 * n * kWave; idx += DB_THREADS) s_acc[idx] = 0.0;
+    double *my_acc = s_acc + (size_t)w * n * kWave;
+    for (int64_t k0 = 0; k0 < K; k0 += DB_BM) {
+        __syncthreads();
+        if (tid < DB_BM) {
+            const int64_t k = k0 + tid;
+            s_enc[tid][0] = k < K ? senc[2 * k] : 0ull;
+            s_enc[tid][1] = k < K ? senc[2 * k + 1] : 0ull;
+        }
+        d4v acc[2][4];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
+        for (int64_t p0 = 0; p0 < P; p0 += DB_KS) {
+            __syncthreads();
+            // C^T tile: 16 polynomials x 64 monomials, read along k
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int idx = tid + q * DB_THREADS;
+                const int pp = idx / DB_BM, kr = idx % DB_BM;
+                const int64_t p = p0 + pp, k = k0 + kr;
+                s_a[kr][pp] = (p < P && k < K) ? C[p * K + k] : 0.0;
+            }
+            // gY tile: 16 polynomials x 128 points, read along the points
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int idx = tid + q * DB_THREADS;
+                const int pp = idx / DB_BN, c = idx % DB_BN;
+                const int64_t p = p0 + pp, pt = n0 + c;
+                s_b[pp][c] = (p < P && pt < N) ? gY[p * N + pt] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k4 = 0; k4 < DB_KS; k4 += 4) {
+                double a[2], b[4];
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt) a[rt] = s_a[wr * 32 + rt * 16 + (lane & 15)][k4 + (lane >> 4)];
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) b[ct] = s_b[k4 + (lane >> 4)][wc * 64 + ct * 16 + (lane & 15)];
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                    for (int ct = 0; ct < 4; ++ct)
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b[ct], acc[rt][ct], 0, 0, 0);
+            }
+        }
+        // W tile entries times the monomials' derivatives at their points
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int kr = wr * 32 + rt * 16 + (lane >> 4) + 4 * v;
+                const int64_t k = k0 + kr;
+                if (k >= K) continue;
+                const uint64_t e0 = s_enc[kr][0], e1 = s_enc[kr][1];
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    const int pl = ct * 16 + (lane & 15);   // point within the wave's 64
+                    add_monomial_grad(e0, e1, basis + k * n, n, s_x + wc * 64 + pl, DB_BN, acc[rt][ct][v],
+                                      my_acc + pl);
+                }
+            }
+    }
+    __syncthreads();
+    // waves (0, wc) and (1, wc) cover the same 64 points: add in that order
+    for (int idx = tid; idx < DB_BN * n; idx += DB_THREADS) {
+        const int pl = idx / n, j = idx % n;
+        const int c = pl >> 6, l = pl & 63;
+        const int64_t pt = n0 + pl;
+        if (pt < N)
+            dX[pt * n + j] = s_acc[((size_t)(0 * 2 + c) * n + j) * kWave + l] +
+                             s_acc[((size_t)(1 * 2 + c) * n + j) * kWave + l];
+    }
+}
+
 // ------------------------------------------------------------ split kernels
 
 // BF16 digit planes of C with their scale folded in, stored in the operand
@@ -624,6 +858,68 @@ poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_ex
         case 5: launch_split<5>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, ys, s); break;
         default: launch_split<6>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, ys, s); break;
         }
+    }
+    return hipGetLastError() == hipSuccess ? POLY_OK : POLY_ERR_HIP;
+}
+
+// ------------------------------------------------- reverse mode: host side
+
+// dynamic LDS of the dX kernel: points [(n + 1)][128], four accumulator blocks [n][64]
+inline size_t dense_bwd_dx_lds(int n) { return ((size_t)(n + 1) * DB_BN + 4 * (size_t)n * kWave) * 8; }
+constexpr size_t DB_DX_LDS_MAX = 130 * 1024;   // beside ~27 KB of static LDS
+
+poly_status dense_bwd_workspace(int32_t n, int64_t K, int64_t P, int64_t N, size_t *ws_bytes)
+{
+    if (!ws_bytes || n < 1 || n > 255 || K < 0 || P < 0 || N < 0) return POLY_ERR_ARG;
+    *ws_bytes = align_up(align_up(kWsHeadBytes, 256) + 16 * (size_t)K, 256) + align_up(16 * (size_t)K, 256);
+    return POLY_OK;
+}
+
+poly_status dense_bwd_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp, int64_t P, const double *C,
+                          int64_t N, const double *X, const double *gY, double *dC, double *dX, void *ws,
+                          size_t ws_bytes, hipStream_t s)
+{
+    size_t need = 0;
+    poly_status st = dense_bwd_workspace(n, K, P, N, &need);
+    if (st != POLY_OK) return st;
+    if (max_exp < 0 || max_exp > 255) return POLY_ERR_ARG;
+    if ((K > 0 && !basis) || (P > 0 && K > 0 && !C) || (N > 0 && !X) || (P > 0 && N > 0 && !gY)) return POLY_ERR_ARG;
+    if (!ws || ws_bytes < need) return POLY_ERR_WORKSPACE;
+    if (dX && dense_bwd_dx_lds(n) > DB_DX_LDS_MAX) return POLY_ERR_UNSUPPORTED;
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_dense_bwd_dx, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)DB_DX_LDS_MAX);
+        (void)hipFuncSetAttribute((const void *)k_dense_bwd_dc, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  64 * 1024);
+        attr = true;
+    }
+    const size_t o_fenc = align_up(kWsHeadBytes, 256);
+    const size_t o_senc = align_up(o_fenc + 16 * (size_t)K, 256);
+    uint4 *fenc = (uint4 *)((char *)ws + o_fenc);
+    uint64_t *senc = (uint64_t *)((char *)ws + o_senc);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (unsigned long long *)ws, 0ull, (int64_t)1);
+    if (K > 0) {
+        hipLaunchKernelGGL(k_encode_factors, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, s, basis, K, n,
+                           (uint32_t *)fenc, (const int64_t *)nullptr);
+        hipLaunchKernelGGL(k_encode_support, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, s, basis, K, n, senc,
+                           (const int64_t *)nullptr);
+    }
+    if (dC && P > 0 && K > 0) {
+        if (N == 0) {
+            hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)std::min<int64_t>(ceil_div(P * K, 256), 65535)), dim3(256), 0, s,
+                               (unsigned long long *)dC, 0ull, P * K);
+        } else {
+            const dim3 grid((unsigned)ceil_div(K, DB_BN), (unsigned)ceil_div(P, DB_BM));
+            TimedLaunch tl(POLY_TIMING_DENSE, s);
+            hipLaunchKernelGGL(k_dense_bwd_dc, grid, dim3(DB_THREADS), (size_t)(n + 1) * DB_KS * 8, s, n, K, basis,
+                               (const uint4 *)fenc, P, gY, N, X, dC);
+            tl.done(s);
+        }
+    }
+    if (dX && N > 0) {
+        hipLaunchKernelGGL(k_dense_bwd_dx, dim3((unsigned)ceil_div(N, DB_BN)), dim3(DB_THREADS), dense_bwd_dx_lds(n), s,
+                           n, K, basis, (const uint64_t *)senc, P, C, gY, N, X, dX);
     }
     return hipGetLastError() == hipSuccess ? POLY_OK : POLY_ERR_HIP;
 }

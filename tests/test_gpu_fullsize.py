@@ -127,6 +127,35 @@ def test_dense_shared_full_sampled(ph):
         del Y
 
 
+def test_dense_backward_full_sampled(ph):
+    """Reverse mode of the 4,096 x 46,376 x 65,536 contraction with a
+    cotangent that is zero except at 8 points: dC (all 190M entries) and dX
+    at those points against the oracle's reverse mode over the 8 points, per
+    element within 1e-12 times the sums over absolute values; dX rows of the
+    other points are exactly zero."""
+    wl = W.dense_shared()
+    P, K, N = wl.C.shape[0], wl.basis.shape[0], wl.X.shape[0]
+    pts = np.array([0, 1, 777, 20000, 40000, 65000, 65534, 65535])
+    g8 = W.rng_for(4020).standard_normal((P, pts.size))
+    gY = torch.zeros((P, N), dtype=torch.float64, device="cuda")
+    gY[:, torch.from_numpy(pts).cuda()] = torch.from_numpy(g8).cuda()
+    say("dense backward full size")
+    dC, dX = ph.eval_dense_backward(torch.from_numpy(wl.basis).cuda(), torch.from_numpy(wl.C).cuda(),
+                                    torch.from_numpy(wl.X).cuda(), gY)
+    dC, dX = dC.cpu().numpy().ravel(), dX.cpu().numpy()
+    del gY
+    say("dense backward oracle over 8 points")
+    rp = np.arange(P + 1, dtype=np.int64) * K
+    E = np.tile(wl.basis, (P, 1))
+    dXo, dCo = oracle.eval_backward(rp, E, wl.C.ravel(), wl.X[pts], g8)
+    aX, aC = oracle.eval_backward(rp, E, np.abs(wl.C.ravel()), np.abs(wl.X[pts]), np.abs(g8))
+    assert (np.abs(dC - dCo) <= 1e-12 * aC + 1e-300).all()
+    assert (np.abs(dX[pts] - dXo) <= 1e-12 * aX + 1e-300).all()
+    rest = np.ones(N, bool)
+    rest[pts] = False
+    assert not dX[rest].any()
+
+
 def test_quartic_full_sampled(ph):
     """Random quartic in 100 variables with 100,000 terms at 8,192 points:
     value, gradient (reverse-mode kernel with unit cotangent and poly_grad)
