@@ -129,10 +129,13 @@ def test_dense_shared_full_sampled(ph):
 
 def test_dense_backward_full_sampled(ph):
     """Reverse mode of the 4,096 x 46,376 x 65,536 contraction with a
-    cotangent that is zero except at 8 points: dC (all 190M entries) and dX
-    at those points against the oracle's reverse mode over the 8 points, per
-    element within 1e-12 times the sums over absolute values; dX rows of the
-    other points are exactly zero."""
+    cotangent that is zero except at 8 points.  References from the oracle:
+    dC[p][k] = sum over the 8 points of gY[p][pt] v_k(x_pt), with v_k the
+    oracle's values of the one-term polynomials x^{e_k}; dX at each of those
+    points is the oracle's gradient of the single polynomial
+    sum_p gY[p][pt] f_p (coefficients gY[:, pt] C, a NumPy product).  Every
+    element within 1e-12 times the same sums over absolute values; dX rows
+    of the other points exactly zero."""
     wl = W.dense_shared()
     P, K, N = wl.C.shape[0], wl.basis.shape[0], wl.X.shape[0]
     pts = np.array([0, 1, 777, 20000, 40000, 65000, 65534, 65535])
@@ -142,15 +145,20 @@ def test_dense_backward_full_sampled(ph):
     say("dense backward full size")
     dC, dX = ph.eval_dense_backward(torch.from_numpy(wl.basis).cuda(), torch.from_numpy(wl.C).cuda(),
                                     torch.from_numpy(wl.X).cuda(), gY)
-    dC, dX = dC.cpu().numpy().ravel(), dX.cpu().numpy()
+    dC, dX = dC.cpu().numpy(), dX.cpu().numpy()
     del gY
-    say("dense backward oracle over 8 points")
-    rp = np.arange(P + 1, dtype=np.int64) * K
-    E = np.tile(wl.basis, (P, 1))
-    dXo, dCo = oracle.eval_backward(rp, E, wl.C.ravel(), wl.X[pts], g8)
-    aX, aC = oracle.eval_backward(rp, E, np.abs(wl.C.ravel()), np.abs(wl.X[pts]), np.abs(g8))
-    assert (np.abs(dC - dCo) <= 1e-12 * aC + 1e-300).all()
-    assert (np.abs(dX[pts] - dXo) <= 1e-12 * aX + 1e-300).all()
+    say("references over 8 points")
+    X8 = wl.X[pts]
+    one = np.arange(K + 1, dtype=np.int64)
+    V = oracle.eval_batch(one, wl.basis, np.ones(K), X8)              # [K, 8] monomial values
+    Va = oracle.eval_batch(one, wl.basis, np.ones(K), np.abs(X8))
+    assert (np.abs(dC - g8 @ V.T) <= 1e-12 * (np.abs(g8) @ Va.T) + 1e-300).all()
+    for i, pt in enumerate(pts):
+        cw = g8[:, i] @ wl.C                                            # coefficients of sum_p gY f_p
+        ca = np.abs(g8[:, i]) @ np.abs(wl.C)
+        G = oracle.grad_batch([0, K], wl.basis, cw, X8[i:i + 1])[0, 0]
+        Ga = oracle.grad_batch([0, K], wl.basis, ca, np.abs(X8[i:i + 1]))[0, 0]
+        assert (np.abs(dX[pt] - G) <= 1e-12 * Ga + 1e-12 * np.abs(G) + 1e-300).all()
     rest = np.ones(N, bool)
     rest[pts] = False
     assert not dX[rest].any()
