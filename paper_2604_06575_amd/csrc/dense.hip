@@ -379,25 +379,41 @@ __global__ void __launch_bounds__(DB_THREADS) k_dense_bwd_dx(int n, int64_t K, c
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) acc[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
-        for (int64_t p0 = 0; p0 < P; p0 += DB_KS) {
-            __syncthreads();
-            // C^T tile: 16 polynomials x 64 monomials, read along k
+        // operand tiles of a step: C^T (16 polynomials x 64 monomials, read
+        // along k) and gY (16 polynomials x 128 points, read along the points);
+        // the next step's are loaded into registers while this step's MFMAs run
+        double ra[4], rb[8];
+        auto load_tiles = [&](int64_t p0) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int idx = tid + q * DB_THREADS;
                 const int pp = idx / DB_BM, kr = idx % DB_BM;
                 const int64_t p = p0 + pp, k = k0 + kr;
-                s_a[kr][pp] = (p < P && k < K) ? C[p * K + k] : 0.0;
+                ra[q] = (p < P && k < K) ? C[p * K + k] : 0.0;
             }
-            // gY tile: 16 polynomials x 128 points, read along the points
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int idx = tid + q * DB_THREADS;
                 const int pp = idx / DB_BN, c = idx % DB_BN;
                 const int64_t p = p0 + pp, pt = n0 + c;
-                s_b[pp][c] = (p < P && pt < N) ? gY[p * N + pt] : 0.0;
+                rb[q] = (p < P && pt < N) ? gY[p * N + pt] : 0.0;
+            }
+        };
+        load_tiles(0);
+        for (int64_t p0 = 0; p0 < P; p0 += DB_KS) {
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int idx = tid + q * DB_THREADS;
+                s_a[idx % DB_BM][idx / DB_BM] = ra[q];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int idx = tid + q * DB_THREADS;
+                s_b[idx / DB_BN][idx % DB_BN] = rb[q];
             }
             __syncthreads();
+            if (p0 + DB_KS < P) load_tiles(p0 + DB_KS);
 #pragma unroll
             for (int k4 = 0; k4 < DB_KS; k4 += 4) {
                 double a[2], b[4];
