@@ -7,7 +7,8 @@ share no code: this package wraps ``poly_oracle.c`` (the plain definitions of
 simplify, times, eval, diff and the reverse mode of eval) through ctypes, and
 adds a brute-force simplify built on a Python dict as a second, independent
 data structure for self-checks, the affine-normal direction of Section 5
-written out in NumPy from the symbolic derivatives (the reference route), and
+written out in NumPy from the symbolic derivatives (the reference route and
+the stochastic route: Hutchinson probes with conjugate-gradient solves), and
 the polynomial-matrix operations of Section 3.3 (mtimes, sum and prod along a
 dimension) and the substitution of Section 3.4, composed from simplify and
 times.
@@ -440,6 +441,106 @@ def affine_normal(exps, coefs, X, reg: float = 0.0):
         g, H, T = derivatives_at(exps, coefs, X[p], n)
         D[p], gn[p] = affine_normal_from_derivatives(g, H, T, reg)
     return D, gn
+
+
+def conjugate_gradients(A, b, tol: float, maxit: int):
+    """Krylov solve of A y = b for a symmetric A by conjugate gradients
+    (Hestenes-Stiefel), the linear solver of the stochastic route of
+    Section 5.  From y = 0, r = p = b, each step takes one product A p:
+    alpha = r'r / p'Ap, y += alpha p, r -= alpha A p, p = r + (r'r)_new /
+    (r'r) p.  A step is taken while fewer than maxit products have been
+    made and |r| > tol |b|; a product with p'Ap = 0 ends the iteration
+    (breakdown).  Returns y and the number of products."""
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    y = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rr = float(r @ r)
+    bn = float(np.sqrt(b @ b))
+    k = 0
+    while k < maxit and np.sqrt(rr) > tol * bn:
+        q = A @ p
+        k += 1
+        pq = float(p @ q)
+        if pq == 0.0:
+            break
+        alpha = rr / pq
+        y = y + alpha * p
+        r = r - alpha * q
+        rr_new = float(r @ r)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    return y, k
+
+
+def third_contraction(exps, coefs, x, u, v, n: int | None = None):
+    """c[l] = D^3 f(x)[u, v, e_l] = sum_jk d^3 f / dx_j dx_k dx_l (x) u_j v_k,
+    taken as the Hessian of the polynomial psi = sum_j u_j d f / dx_j
+    (symbolic diff, coefficients scaled by u_j) applied to v."""
+    x = np.asarray(x, dtype=np.float64)
+    n = n if n is not None else x.shape[0]
+    pe, pc = [], []
+    for j in range(n):
+        if u[j] == 0.0:
+            continue
+        e1, c1 = diff(exps, coefs, j, n)
+        pe.append(e1)
+        pc.append(u[j] * c1)
+    if not pe or sum(e.shape[0] for e in pe) == 0:
+        return np.zeros(n)
+    pe, pc = np.concatenate(pe), np.concatenate(pc)
+    Hp = hess_batch(np.array([0, pe.shape[0]], np.int64), pe, pc, x[None, :])[0, 0]
+    return Hp @ np.asarray(v, dtype=np.float64)
+
+
+def affine_normal_stochastic(exps, coefs, X, Z, reg: float, tol: float, maxit: int):
+    """Affine-normal directions by the stochastic log-det route of Section 5
+    (MF-logDet-Stochastic): the traces a_i = tr(A^-1 d_{t_i} H_T) of the
+    exact route are replaced by Hutchinson estimates over q probes and every
+    solve with A = H_T + reg I by conjugate gradients.
+
+    Probes are given in R^n, Z [q, n] (shared by all points) or [N, q, n];
+    the tangent probe of Z_s at a point is z_s = Q_T' Z_s.  With
+    y_s = A^-1 z_s (a Krylov solve) and A symmetric,
+      a_i ~ (1/q) sum_s z_s' A^-1 d_{t_i} H_T z_s
+          = (1/q) sum_s D^3 f[Q_T y_s, Q_T z_s, t_i],
+    so a = Q_T' w with w = (1/q) sum_s D^3 f[Q_T y_s, Q_T z_s, .]; then
+    tau = A^-1 (h - |g| / (n + 1) a) (another Krylov solve) and
+    nu = Q [tau; -1].  Returns D [N, n], |grad f| [N] and the Hessian-vector
+    products per point (one for h, one per conjugate-gradient step); the
+    third-derivative contractions per point are q."""
+    X = np.asarray(X, dtype=np.float64)
+    N, n = X.shape
+    Z = np.asarray(Z, dtype=np.float64)
+    q = Z.shape[-2]
+    D = np.empty((N, n))
+    gn = np.empty(N)
+    hv = np.zeros(N, dtype=np.int64)
+    rp = np.array([0, np.asarray(exps).shape[0]], np.int64)
+    for pt in range(N):
+        x = X[pt]
+        g = grad_batch(rp, exps, coefs, x[None, :])[0, 0]
+        H = hess_batch(rp, exps, coefs, x[None, :])[0, 0]
+        gn[pt] = np.linalg.norm(g)
+        Q = tangent_frame(g)
+        QT, e = Q[:, :n - 1], Q[:, n - 1]
+        A = QT.T @ H @ QT + reg * np.eye(n - 1)
+        h = QT.T @ (H @ e)
+        hv[pt] = 1
+        Zp = Z[pt] if Z.ndim == 3 else Z
+        w = np.zeros(n)
+        for s in range(q):
+            z = QT.T @ Zp[s]
+            y, k = conjugate_gradients(A, z, tol, maxit)
+            hv[pt] += k
+            w += third_contraction(exps, coefs, x, QT @ y, QT @ z, n)
+        w /= q
+        a = QT.T @ w
+        tau, k = conjugate_gradients(A, h - gn[pt] / (n + 1) * a, tol, maxit)
+        hv[pt] += k
+        D[pt] = Q @ np.concatenate([tau, [-1.0]])
+    return D, gn, hv
 
 
 # ------------------------------------------------------- polynomial matrices
