@@ -18,7 +18,9 @@ accumulation, FP64 recombination), each with its error against an FP64
 reference on sampled outputs; the sparse derivative paths, the
 affine-normal direction of a sparse quartic at a batch of points, the
 square of a 3 x 3 polynomial matrix, the paper's heavy-simplify family
-simplify(p_d^3), and its affine-normal scaling family up to n = 240.
+simplify(p_d^3), its affine-normal scaling family up to n = 240, and the
+stochastic affine-normal route on its crossover family (speed preset,
+against the exact route) and accuracy preset (angle over probe seeds).
 
 Prints one JSON line.  --gpus N with N > 1 exits: the benchmark runs on one GPU.
 """
@@ -85,6 +87,8 @@ def parse():
     ap.add_argument("--no-mtimes", action="store_true", help="skip the polynomial-matrix product workload")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's simplify(p_d^3) family")
     ap.add_argument("--no-affine-scaling", action="store_true", help="skip the affine-normal scaling family")
+    ap.add_argument("--no-affine-stochastic", action="store_true",
+                    help="skip the stochastic affine-normal route (crossover family and accuracy preset)")
     ap.add_argument("--affine-n", type=int, default=64)
     ap.add_argument("--affine-points", type=int, default=4096)
     ap.add_argument("--graph", action="store_true", help="also time the times+simplify step as a captured HIP graph")
@@ -378,6 +382,68 @@ def bench_affine_scaling(args):
     return res
 
 
+def _angles_deg(A, B):
+    import torch
+    c = (A * B).sum(1) / (A.norm(dim=1) * B.norm(dim=1))
+    return torch.rad2deg(torch.arccos(c.clamp(-1.0, 1.0)))
+
+
+def bench_affine_stochastic(args):
+    """The stochastic log-det route (Section 5, MF-logDet-Stochastic).
+    Crossover family of the paper's Section 6.6: support-2 sparse quartics
+    with m = 3n monomials at n = 80, 120, 180 and 240, 256 points per call
+    in [-0.25, 0.25]^n (where the tangent blocks are positive definite),
+    the speed preset (one Rademacher probe, reg 5e-4, tol 2e-2, 6 steps)
+    against the exact route (reg 1e-8) on the same points: time per call,
+    speedup t_exact / t_stochastic, and the angle between the two
+    directions.  Accuracy preset of the paper's accuracy tables (64
+    Rademacher probes, tol 1e-4, 80 steps, reg 1e-8) on a sparse quartic in 6
+    variables with 17 monomials at 4,096 points, over 10 probe seeds: angle
+    to the exact direction (mean and standard deviation over points and
+    seeds)."""
+    import torch
+    import paper_2604_06575_amd as ph
+    import workloads as W
+
+    cross = {}
+    for n in (80, 120, 180, 240):
+        wl = W.sparse_quartic(seed=W.SEED_BASE + 400 + n, n=n, npts=256, support=2)
+        N = wl.X.shape[0]
+        b = ph.batch_from_numpy([0, wl.exps.shape[0]], wl.exps, wl.coefs, n=n, max_exp=4)
+        X = torch.from_numpy(wl.X * 0.25).cuda()   # the locally convex regime: tangent blocks positive definite
+        Z = torch.from_numpy(W.rng_for(W.SEED_BASE + 401 + n).choice([-1.0, 1.0], size=(1, n))).cuda()
+        wse = torch.empty(ph.affine_normal_workspace(b, N), dtype=torch.uint8, device="cuda")
+        exact = lambda: ph.affine_normal(b, X, reg=1e-8, ws=wse)  # noqa: E731
+        stoch = lambda: ph.affine_normal_stochastic(b, X, Z, reg=5e-4, tol=2e-2, maxit=6)  # noqa: E731
+        De, _ = ph.affine_normal(b, X, reg=1e-8, ws=wse, check=True)
+        Ds, _, hv = ph.affine_normal_stochastic(b, X, Z, reg=5e-4, tol=2e-2, maxit=6, check=True)
+        te, _ = time_events(exact, 3, 1)
+        ts, _ = time_events(stoch, 5, 2)
+        ks, _ = kernel_ms(ph.TIMING_AFFINE, stoch, 5)
+        ang = _angles_deg(Ds, De)
+        cross[f"n{n}"] = {"terms": int(wl.exps.shape[0]), "points": N, "exact_ms": te * 1e3,
+                          "stochastic_ms": ts * 1e3, "stochastic_kernel_ms": ks, "speedup": te / ts,
+                          "angle_deg_mean": float(ang.mean()), "angle_deg_max": float(ang.max()),
+                          "hv_evals_mean": float(hv.double().mean())}
+        del wse
+    wl = W.sparse_quartic(seed=W.SEED_BASE + 450, n=6, npts=4096, m=11)
+    b = ph.batch_from_numpy([0, wl.exps.shape[0]], wl.exps, wl.coefs, n=6, max_exp=4)
+    X = torch.from_numpy(wl.X * 0.5).cuda()
+    De, _ = ph.affine_normal(b, X, reg=1e-8, check=True)
+    angs, times = [], []
+    for seed in range(10):
+        Z = torch.from_numpy(W.rng_for(W.SEED_BASE + 460 + seed).choice([-1.0, 1.0], size=(64, 6))).cuda()
+        Ds, _, _ = ph.affine_normal_stochastic(b, X, Z, reg=1e-8, tol=1e-4, maxit=80, check=True)
+        angs.append(_angles_deg(Ds, De))
+        t, _ = time_events(lambda: ph.affine_normal_stochastic(b, X, Z, reg=1e-8, tol=1e-4, maxit=80), 3, 1)
+        times.append(t)
+    a = torch.cat(angs)
+    acc = {"n": 6, "terms": int(wl.exps.shape[0]), "points": int(X.shape[0]), "probes": 64, "seeds": 10,
+           "ms_per_call": 1e3 * sum(times) / len(times), "points_per_s": X.shape[0] * len(times) / sum(times),
+           "angle_deg_mean": float(a.mean()), "angle_deg_std": float(a.std())}
+    return {"crossover_speed_preset": cross, "accuracy_preset": acc}
+
+
 def bench_mtimes(args):
     """A^2 for a 3 x 3 polynomial matrix whose entries are random degree-4
     polynomials in n=8 with 300 distinct monomials (N(0,1) coefficients):
@@ -599,6 +665,8 @@ def main():
         line["paper_family"] = bench_paper_family(args)
     if not args.no_affine and not args.no_affine_scaling:
         line["affine_scaling"] = bench_affine_scaling(args)
+    if not args.no_affine and not args.no_affine_stochastic:
+        line["affine_stochastic"] = bench_affine_stochastic(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(line), flush=True)

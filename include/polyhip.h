@@ -135,7 +135,8 @@ poly_status poly_tune_get(const char *name, int64_t *value);
  *                     on the radix-sort path each scatter pass
  *   POLY_TIMING_DENSE the contraction kernel of poly_eval_dense
  *   POLY_TIMING_TERMS the term-streaming kernel of poly_eval / grad / hess
- *   POLY_TIMING_AFFINE the per-point kernel of poly_affine_normal
+ *   POLY_TIMING_AFFINE the per-point kernel of poly_affine_normal or
+ *                     poly_affine_normal_stochastic
  * poly_timing_enable(1) clears every slot and starts recording; (0) stops.
  * poly_timing_read waits for the recorded events of `slot` (at most the last
  * 1024 launches are kept) and returns their summed duration in milliseconds
@@ -298,6 +299,35 @@ poly_status poly_concat(const poly_csr *const *ins, int32_t nin, poly_csr *out, 
 poly_status poly_affine_normal_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes);
 poly_status poly_affine_normal(const poly_csr *f, const double *X, int64_t N, double reg,
                                double *D, double *gnorm, void *ws, size_t ws_bytes, void *stream);
+
+/* Affine-normal direction by the stochastic log-determinant route of
+ * Section 5 (MF-logDet-Stochastic): the same direction as
+ * poly_affine_normal with each trace a_i replaced by a Hutchinson average
+ * over q probes and each solve with A by conjugate gradients.
+ *   Z          probes in R^n, [q*n] row-major shared by all points, or
+ *              [N*q*n] (point-major) when per_point = 1.  The tangent probe
+ *              of Z_s is z_s = Q_T' Z_s; Rademacher Z gives an unbiased
+ *              estimate of a, and sqrt(n) times an orthonormal basis of R^n
+ *              (q = n) gives a exactly.
+ *   a_i      ~ (1/q) sum_s D^3 f[Q_T y_s, Q_T z_s, Q_T e_i], y_s = A^-1 z_s
+ *   tau        the solve of A tau = h - |g| / (n + 1) a
+ *   D[pt*n+i]  (Q [tau; -1])_i, gnorm[pt] = |g|.
+ * Every solve is conjugate gradients from 0 with one A-product per step,
+ * taken while fewer than maxit products have been made and |r| > tol |b|
+ * (a step with p'Ap = 0 ends the solve).  hv_evals[pt] (may be NULL)
+ * receives the Hessian-vector products made at the point: one for H e plus
+ * one per step of the q + 1 solves; the third-derivative contractions per
+ * point are q.  Matrix-free: Hessian-vector products and third derivatives
+ * are taken per monomial, the n x n Hessian is never formed.
+ * One polynomial, 2 <= n <= 255, q >= 1, tol >= 0, maxit >= 0, reg >= 0
+ * (else POLY_ERR_ARG); terms of total degree above 12 give the device
+ * status POLY_ERR_UNSUPPORTED.  g = 0 gives non-finite output for that
+ * point.  X [N*n], D [N*n], gnorm [N] (required). */
+poly_status poly_affine_normal_stochastic_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes);
+poly_status poly_affine_normal_stochastic(const poly_csr *f, const double *X, int64_t N, const double *Z,
+                                          int32_t q, int32_t per_point, double reg, double tol, int32_t maxit,
+                                          double *D, double *gnorm, int32_t *hv_evals, void *ws, size_t ws_bytes,
+                                          void *stream);
 
 /* ----------------------------------------------------- shared monomial set
  * Y[p*N + pt] = sum_k C[p*K + k] * prod_i X[pt*n + i]^basis[k*n + i]:

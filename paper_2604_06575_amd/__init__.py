@@ -42,6 +42,7 @@ EXPORTS = [
     "poly_eval_backward2_workspace", "poly_eval_backward2",
     "poly_eval_dense_workspace", "poly_eval_dense",
     "poly_affine_normal_workspace", "poly_affine_normal",
+    "poly_affine_normal_stochastic_workspace", "poly_affine_normal_stochastic",
     "poly_mtimes_workspace", "poly_mtimes",
     "poly_concat",
     "poly_simplify_noalloc",
@@ -117,6 +118,9 @@ def lib():
         "poly_mtimes_workspace": ([pcsr, pcsr, i64, i64, i64, psz, ctypes.POINTER(i64)], i32),
         "poly_mtimes": ([pcsr, pcsr, i64, i64, i64, pcsr, d, P, ctypes.c_size_t, P], i32),
         "poly_affine_normal": ([pcsr, P, i64, d, P, P, P, ctypes.c_size_t, P], i32),
+        "poly_affine_normal_stochastic_workspace": ([pcsr, i64, psz], i32),
+        "poly_affine_normal_stochastic": ([pcsr, P, i64, P, i32, i32, d, d, i32, P, P, P, P, ctypes.c_size_t, P],
+                                          i32),
         "poly_concat": ([ctypes.POINTER(pcsr), i32, pcsr, P], i32),
         "poly_simplify_noalloc": ([pcsr, pcsr, d, P, P], i32),
         "poly_plan_workspace": ([pcsr, i64, psz], i32),
@@ -694,9 +698,13 @@ def eval_backward2(b: Batch, X: torch.Tensor, gY: torch.Tensor, u: torch.Tensor 
     return ggY, ggX, ggC
 
 
-def affine_normal(b: Batch, X: torch.Tensor, reg: float = 1e-6, check: bool = False, ws: torch.Tensor | None = None):
+def affine_normal(b: Batch, X: torch.Tensor, reg: float = 1e-6, check: bool = False, ws: torch.Tensor | None = None,
+                  info: bool = False):
     """Affine-normal directions of one polynomial at the rows of X:
-    (D [N, n], |grad f| [N])."""
+    (D [N, n], |grad f| [N]), plus with info=True a dict of the route's work
+    per point in the units of Section 5's example output: the Hessian as n
+    Hessian-vector products (hv_evals) and the n - 1 tangent third-derivative
+    directions (third_evals)."""
     L = lib()
     X = X.contiguous()
     cin = b.csr()
@@ -713,7 +721,44 @@ def affine_normal(b: Batch, X: torch.Tensor, reg: float = 1e-6, check: bool = Fa
                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "poly_affine_normal")
     if check:
         _check(L.poly_read_status(ctypes.c_void_p(ws.data_ptr()), _stream()), "poly_affine_normal")
+    if info:
+        return D, gn, {"method": "mf-exact", "hv_evals": b.n, "third_evals": b.n - 1}
     return D, gn
+
+
+def affine_normal_stochastic(b: Batch, X: torch.Tensor, Z: torch.Tensor, reg: float = 1e-6, tol: float = 1e-4,
+                             maxit: int = 40, check: bool = False, ws: torch.Tensor | None = None):
+    """Affine-normal directions by the stochastic log-det route: probes Z
+    [q, n] (shared by the points) or [N, q, n] (per point), conjugate-gradient
+    solves with relative tolerance tol and at most maxit steps.  Returns
+    (D [N, n], |grad f| [N], Hessian-vector products per point [N] int32)."""
+    L = lib()
+    X = X.contiguous()
+    Z = Z.contiguous()
+    cin = b.csr()
+    _check_points(X, b.n, b.coefs.device)
+    N = X.shape[0]
+    if Z.dtype != torch.float64 or Z.device != b.coefs.device or Z.dim() not in (2, 3) or Z.shape[-1] != b.n:
+        raise ValueError("Z must be float64 [q, n] or [N, q, n] on the batch's device")
+    per_point = 1 if Z.dim() == 3 else 0
+    if per_point and Z.shape[0] != N:
+        raise ValueError("per-point probes need Z.shape[0] == N")
+    q = int(Z.shape[-2])
+    ws_bytes = ctypes.c_size_t()
+    _check(L.poly_affine_normal_stochastic_workspace(ctypes.byref(cin), N, ctypes.byref(ws_bytes)),
+           "poly_affine_normal_stochastic_workspace")
+    if ws is None or ws.numel() < ws_bytes.value:
+        ws = _workspace(ws_bytes.value, b.coefs.device)
+    D = torch.empty((N, b.n), dtype=torch.float64, device=b.coefs.device)
+    gn = torch.empty(N, dtype=torch.float64, device=b.coefs.device)
+    hv = torch.empty(N, dtype=torch.int32, device=b.coefs.device)
+    _check(L.poly_affine_normal_stochastic(ctypes.byref(cin), _ptr(X), N, _ptr(Z), q, per_point, float(reg),
+                                           float(tol), int(maxit), _ptr(D), _ptr(gn), _ptr(hv),
+                                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()),
+           "poly_affine_normal_stochastic")
+    if check:
+        _check(L.poly_read_status(ctypes.c_void_p(ws.data_ptr()), _stream()), "poly_affine_normal_stochastic")
+    return D, gn, hv
 
 
 def affine_normal_workspace(b: Batch, N: int) -> int:

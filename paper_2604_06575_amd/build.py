@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB_PATH = os.path.join(HERE, "libpolyhip.so")
-SOURCES = ["simplify.hip", "mul.hip", "mulsort.hip", "eval.hip", "dense.hip", "affine.hip", "matrix.hip", "wide.hip", "capi.hip", "noalloc.hip", "deriv.hip"]
+SOURCES = ["simplify.hip", "mul.hip", "mulsort.hip", "eval.hip", "dense.hip", "affine.hip", "matrix.hip", "wide.hip", "capi.hip", "noalloc.hip", "deriv.hip", "stochastic.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -522,6 +522,8 @@ void ensure_lds_attrs()
                               (int)MB_LDS_LIMIT);
     (void)hipFuncSetAttribute((const void *)k_affine_normal, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)affine_lds_bytes(AN_MAX_N_LDS));
+    (void)hipFuncSetAttribute((const void *)k_affine_stochastic, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)AS_LDS_BUDGET);
     lds_attr_done = true;
 }
 
@@ -1887,6 +1889,77 @@ poly_status poly_affine_normal(const poly_csr *f, const double *X, int64_t N, do
     hipLaunchKernelGGL(k_affine_normal, dim3((unsigned)N), dim3(AN_THREADS), affine_lds_bytes(n), s, n,
                        (const uint4 *)enc, f->coefs, T, X, (const double *)G, H, reg, D, gnorm,
                        status);
+    tl.done(s);
+    LAUNCH_CHECK();
+    return POLY_OK;
+}
+
+// Probes solved at once by the stochastic route: the smallest power of two
+// holding all q probes, at most AS_MAX_SLOTS, halved until the point's
+// vectors fit the LDS budget (n <= 255 always fits one slot).
+static int affine_stochastic_slots(int n, int q)
+{
+    int b = 1;
+    while (b < q && b < AS_MAX_SLOTS) b <<= 1;
+    while (b > 1 && affine_stochastic_lds_bytes(n, b) > AS_LDS_BUDGET) b >>= 1;
+    return b;
+}
+
+poly_status poly_affine_normal_stochastic_workspace(const poly_csr *f, int64_t N, size_t *ws_bytes)
+{
+    poly_status st = check_affine(f, nullptr, 0, nullptr, 0.0);
+    if (st != POLY_OK) return st;
+    if (!ws_bytes || N < 0) return POLY_ERR_ARG;
+    *ws_bytes = kWsHeadBytes + 16 * (size_t)std::max<int64_t>(total_terms(f), 1);
+    return POLY_OK;
+}
+
+poly_status poly_affine_normal_stochastic(const poly_csr *f, const double *X, int64_t N, const double *Z, int32_t q,
+                                          int32_t per_point, double reg, double tol, int32_t maxit, double *D,
+                                          double *gnorm, int32_t *hv_evals, void *ws, size_t ws_bytes, void *stream)
+{
+    poly_status st = check_affine(f, X, N, D, reg);
+    if (st != POLY_OK) return st;
+    if (q < 1 || (N > 0 && !Z) || (per_point != 0 && per_point != 1) || !(tol >= 0.0) || maxit < 0 ||
+        N > INT32_MAX || (N > 0 && !gnorm))
+        return POLY_ERR_ARG;
+    size_t need = 0;
+    (void)poly_affine_normal_stochastic_workspace(f, N, &need);
+    if (!ws || ws_bytes < need) return POLY_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    ensure_lds_attrs();
+    int32_t *status = at<int32_t>(ws, 0);
+    clear_u64(at<unsigned long long>(ws, 0), 1, s);
+    if (N == 0) {
+        LAUNCH_CHECK();
+        return POLY_OK;
+    }
+    const int n = f->nvars;
+    const int64_t T = total_terms(f);
+    uint32_t *enc = at<uint32_t>(ws, kWsHeadBytes);
+    if (T > 0)
+        hipLaunchKernelGGL(k_encode_factors, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, enc,
+                           (const int64_t *)nullptr);
+    AffStochArgs A;
+    A.n = n;
+    A.enc = (const uint4 *)enc;
+    A.coefs = f->coefs;
+    A.T = T;
+    A.X = X;
+    A.Z = Z;
+    A.per_point = per_point;
+    A.q = q;
+    A.slots = affine_stochastic_slots(n, q);
+    A.reg = reg;
+    A.tol = tol;
+    A.maxit = maxit;
+    A.D = D;
+    A.gnorm = gnorm;
+    A.hv = hv_evals;
+    A.status = status;
+    TimedLaunch tl(POLY_TIMING_AFFINE, s);
+    hipLaunchKernelGGL(k_affine_stochastic, dim3((unsigned)N), dim3(AS_THREADS),
+                       affine_stochastic_lds_bytes(n, A.slots), s, A);
     tl.done(s);
     LAUNCH_CHECK();
     return POLY_OK;

@@ -220,6 +220,33 @@ __host__ __device__ constexpr size_t affine_lds_bytes(int n)
 __global__ void k_affine_normal(int n, const uint4 *enc, const double *coefs, int64_t T, const double *X,
                                 const double *G, double *H, double reg, double *D, double *gnorm,
                                 int32_t *status);
+// affine-normal direction, stochastic route (stochastic.hip): one workgroup
+// per point, probes solved AS slots at a time
+constexpr int AS_THREADS = 256;
+constexpr int AS_MAX_SLOTS = 64;
+constexpr size_t AS_LDS_BUDGET = 64 * 1024;
+__host__ __device__ constexpr size_t affine_stochastic_lds_bytes(int n, int slots)
+{
+    return (size_t)(4 + 5 * slots) * n * sizeof(double);
+}
+struct AffStochArgs {
+    int n;
+    const uint4 *enc;       // factor lists [T]
+    const double *coefs;    // [T]
+    int64_t T;
+    const double *X;        // [N][n]
+    const double *Z;        // probes [q][n], or [N][q][n] when per_point
+    int per_point;
+    int q;
+    int slots;              // probes solved at once, a power of two <= AS_MAX_SLOTS
+    double reg, tol;
+    int maxit;
+    double *D;              // [N][n]
+    double *gnorm;          // [N]
+    int32_t *hv;            // [N] or null
+    int32_t *status;
+};
+__global__ void k_affine_stochastic(AffStochArgs A);
 __global__ void k_eval_terms(EvalArgs A, const uint32_t *enc, double *partial, int64_t S);
 __global__ void k_eval_reduce(EvalArgs A, const double *partial, int64_t S);
 __global__ void k_hess_transpose(const double *stage, int64_t P, int64_t N, int n, double *H);

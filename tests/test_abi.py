@@ -22,7 +22,7 @@ def test_library_exports_every_declared_symbol():
         pytest.skip("library not built")
     L = ctypes.CDLL(ph.library_path())
     syms = header_symbols()
-    assert len(syms) == 36
+    assert len(syms) == 38
     for s in syms:
         assert hasattr(L, s), s
     assert sorted(ph.EXPORTS) == syms
@@ -76,6 +76,20 @@ def test_strerror_and_host_argument_checks():
     c.nvars = 255   # past the LDS-resident size the matrix works in the Hessian's workspace slot
     assert L.poly_affine_normal_workspace(ctypes.byref(c), 10, ctypes.byref(size)) == 0
     assert size.value >= 10 * 255 * 255 * 8
+    # stochastic route: matrix-free, the workspace holds only the factor lists
+    assert L.poly_affine_normal_stochastic_workspace(ctypes.byref(c), 10, ctypes.byref(size)) == 0
+    assert 0 < size.value < 4096
+    c.nvars = 1
+    assert L.poly_affine_normal_stochastic_workspace(ctypes.byref(c), 10, ctypes.byref(size)) == 1
+    c.nvars = 4
+    X = np.zeros(40)
+    Z = np.zeros(8)
+    D = np.zeros(40)
+    g = np.zeros(10)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    for q, per_point, tol, maxit in ((0, 0, 1e-4, 10), (2, 2, 1e-4, 10), (2, 0, -1.0, 10), (2, 0, 1e-4, -1)):
+        assert L.poly_affine_normal_stochastic(ctypes.byref(c), p(X), 10, p(Z), q, per_point, 1e-6, tol, maxit,
+                                               p(D), p(g), None, None, 0, None) == 1
 
 
 def test_noalloc_rejects_work_beyond_its_scratch():

@@ -57,6 +57,9 @@ def test_paper_example(ph):
     D = _check(ph, E, C, X, g["regularization"])
     for got, want in zip(D[0], g["d"]):
         assert abs(got - want) <= 0.5e-6 * abs(want) + 1e-22
+    b = ph.batch_from_numpy(np.array([0, E.shape[0]], np.int64), E, C, n=4, max_exp=4)
+    _, _, info = ph.affine_normal(b, torch.from_numpy(X).cuda(), reg=g["regularization"], info=True)
+    assert (info["hv_evals"], info["third_evals"]) == (g["hv_evals"], g["third_evals"])
 
 
 @pytest.mark.parametrize("n,terms,npts", [(3, 12, 5), (6, 40, 33), (9, 90, 70)])

@@ -227,18 +227,27 @@ def quartic(seed: int = SEED_BASE + 5, n: int = 100, terms: int = 100_000, npts:
     return ScalarWorkload(n, e, c, X)
 
 
-def sparse_quartic(seed: int = SEED_BASE + 6, n: int = 64, npts: int = 4096, m: int | None = None) -> ScalarWorkload:
-    """The affine-normal timing family: ``m`` (default 4n) distinct quartic
-    monomials of support size 3 (exponents a permutation of (2, 1, 1) on
-    three distinct variables), N(0,1) coefficients, plus sum_i x_i^2 so the
-    tangent Hessian blocks stay nonsingular; points uniform in [-1,1]^n."""
+def sparse_quartic(seed: int = SEED_BASE + 6, n: int = 64, npts: int = 4096, m: int | None = None,
+                   support: int = 3) -> ScalarWorkload:
+    """The affine-normal timing families: ``m`` distinct quartic monomials of
+    support size 3 (default m = 4n; exponents a permutation of (2, 1, 1) on
+    three distinct variables) or of support size 2 (default m = 3n;
+    exponents (a, 4 - a) on two distinct variables, a uniform in {1, 2, 3}),
+    N(0,1) coefficients, plus sum_i x_i^2 so the tangent Hessian blocks stay
+    nonsingular; points uniform in [-1,1]^n."""
+    if support not in (2, 3):
+        raise ValueError("support must be 2 or 3")
     rng = rng_for(seed)
-    m = 4 * n if m is None else m
+    m = (4 * n if support == 3 else 3 * n) if m is None else m
     rows, seen = [], set()
     while len(rows) < m:
-        v = rng.choice(n, size=3, replace=False)
+        v = rng.choice(n, size=support, replace=False)
         e = np.zeros(n, dtype=np.uint8)
-        e[v] = (2, 1, 1)
+        if support == 3:
+            e[v] = (2, 1, 1)
+        else:
+            a = int(rng.integers(1, 4))
+            e[v] = (a, 4 - a)
         key = e.tobytes()
         if key not in seen:
             seen.add(key)
