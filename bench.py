@@ -82,6 +82,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-terms", type=int, default=5000, help="q terms in the CPU baseline sample")
     ap.add_argument("--no-batch", action="store_true", help="skip the polynomial-matrix workload")
+    ap.add_argument("--no-latency", action="store_true", help="skip the small-call latency workload")
     ap.add_argument("--no-deriv", action="store_true", help="skip the quartic derivative workload")
     ap.add_argument("--no-affine", action="store_true", help="skip the affine-normal workload")
     ap.add_argument("--no-mtimes", action="store_true", help="skip the polynomial-matrix product workload")
@@ -302,8 +303,54 @@ def bench_batch(args):
             "simplify_ms": t_simp * 1e3, "simplify_terms_per_s": T_in / t_simp,
             "jacobian_ms": t_jac * 1e3, "jacobian_terms_per_s": T_j / t_jac,
             "jacobian_eval_ms": t_eval * 1e3, "jacobian_eval_term_points_per_s": term_points / t_eval,
-            "grad_fused_ms": t_grad * 1e3,
+            "grad_fused_ms": t_grad * 1e3, **bench_plan(b, X),
             "note": "simplify/jacobian times include the host readback of the output row pointer"}
+
+
+def bench_plan(b, X):
+    """simplify -> jacobian -> gradient values of the batch: eager calls (with
+    their host read-backs of output sizes) against the same pipeline captured
+    once as a plan (one HIP graph, sizes kept on the device) and replayed."""
+    import torch
+    import paper_2604_06575_amd as ph
+
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        plan = ph.Plan(b, X)
+        try:
+            t_plan, _ = time_events(plan.launch, 3, 1)
+            t_eager, _ = time_events(lambda: ph.grad(ph.simplify(b), X), 3, 1)
+        finally:
+            side.synchronize()
+            plan.close()
+    return {"pipeline_eager_ms": t_eager * 1e3, "pipeline_graph_ms": t_plan * 1e3}
+
+
+def bench_latency(args):
+    """Latency of single small calls (n=4, two polynomials of 200 terms,
+    degree <= 6, integer coefficients; 1,024 points): times + simplify of the
+    pair, simplify of one operand, evaluation of the product at the points;
+    microseconds per call over back-to-back calls with the workspace and
+    output allocated once, and the output size read back (mul, simplify)."""
+    import torch
+    import paper_2604_06575_amd as ph
+    import workloads as W
+
+    wl = W.plain_small()
+    rp = [0, wl.a_exps.shape[0]]
+    a = ph.batch_from_numpy(rp, wl.a_exps, wl.a_coefs, n=wl.n, max_exp=wl.max_exp)
+    b = ph.batch_from_numpy(rp, wl.b_exps, wl.b_coefs, n=wl.n, max_exp=wl.max_exp)
+    X = torch.from_numpy(wl.X).cuda()
+    ws_bytes, raw = ph.mul_workspace(a, b)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    out = ph._empty_out(wl.n, 1, raw, 2 * wl.max_exp, "cuda")
+    p = ph.mul(a, b)
+    t_mul, _ = time_events(lambda: ph.mul(a, b, ws=ws, out=out), 50, 5)
+    t_simp, _ = time_events(lambda: ph.simplify(a), 50, 5)
+    t_eval, _ = time_events(lambda: ph.eval(p, X), 50, 5)
+    return {"n": wl.n, "terms": [int(rp[1]), int(rp[1])], "raw_terms": int(raw), "product_terms": p.nterms,
+            "points": int(X.shape[0]), "mul_us": t_mul * 1e6, "simplify_us": t_simp * 1e6,
+            "eval_us": t_eval * 1e6}
 
 
 def bench_deriv(args):
@@ -653,6 +700,8 @@ def main():
         line["graph"] = bench_graph(args, m)
     if not args.no_eval:
         line["eval"] = bench_eval(args)
+    if not args.no_latency:
+        line["latency_small"] = bench_latency(args)
     if not args.no_batch:
         line["batch_matrix"] = bench_batch(args)
     if not args.no_deriv:

@@ -258,7 +258,7 @@ __global__ void k_hess_mirror(double *H, int64_t PN, int n);
 __global__ void k_eval_wsum(EvalArgs A, const uint32_t *enc, const double *gY, int64_t P, int64_t S, double *out,
                             double *partial);
 constexpr int64_t EV_TARGET_WAVES = 16384;   // waves wanted before polynomials are cut into segments
-constexpr int64_t EV_MIN_SEGMENT = 256;      // fewest terms per segment
+constexpr int64_t EV_MIN_SEGMENT = 32;       // fewest terms per segment
 constexpr int64_t EV_MAX_SEGMENTS = 256;
 
 
