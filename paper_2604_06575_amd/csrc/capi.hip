@@ -2,6 +2,8 @@
 // Declarations and their contracts are in include/polyhip.h.
 #include <string.h>
 
+#include <climits>
+
 #include <algorithm>
 #include <atomic>
 #include <mutex>
@@ -152,6 +154,8 @@ inline void set_u64(unsigned long long *p, unsigned long long v, hipStream_t s)
 // simplify_wide_min tunable): keys p * radix^n + (mixed-radix monomial key)
 // of key_bits bits radix-sorted with their value indices, runs merged by
 // tiles.  span = radix^n, or 0 for a single polynomial (key = monomial key).
+constexpr int kMaxWords = 40;   // 255 variables in words of at least 8 (radix <= 256), plus the top word
+
 struct WidePlan {
     bool on = false;
     int key_bits = 0;
@@ -160,6 +164,14 @@ struct WidePlan {
     int64_t nbs = 0, nbm = 0;   // radix-pass tiles, merge tiles
     size_t keys0 = 0, keys1 = 0, vals0 = 0, vals1 = 0, hist = 0, hoff = 0, tmp = 0;
     size_t st_key = 0, st_ckey = 0, st_coef = 0, cnt = 0, soff = 0, ooff = 0;
+    // key words (rows = true): word w covers variables [wlo[w], whi[w]),
+    // least significant first; the last word starts at variable 0 and holds
+    // the polynomial index above its variables when P > 1 (span = radix^whi
+    // of that word then); runs are found by comparing rows past it.
+    bool rows = false;
+    int nwords = 0;
+    int wlo[kMaxWords] = {}, whi[kMaxWords] = {}, wbits[kMaxWords] = {};
+    size_t head = 0;
 };
 
 inline int64_t max_segment(const int64_t *rph, int64_t P)
@@ -210,26 +222,139 @@ void plan_wide(WidePlan &w, Layout &L, int64_t P, int64_t R, int n, uint32_t rad
     w.ooff = L.take(8 * (w.nbm + 1));
 }
 
+inline int bit_width_u128(unsigned __int128 v)
+{
+    int b = 0;
+    while (v) {
+        ++b;
+        v >>= 1;
+    }
+    return b;
+}
+
+// The cheapest cut of the composite key (p, x1..xn) into words below 2^64:
+// the top word takes the polynomial index and the gt most significant
+// variables, the rest go into as few words as fit, from x_n upward; the cut
+// with the fewest radix passes of db-bit digits wins (ties: fewer words).
+// Returns false when no cut fits kMaxWords words.
+bool plan_words(WidePlan &w, int64_t P, int n, uint32_t radix, int db)
+{
+    const unsigned __int128 lim = (unsigned __int128)1 << 64;
+    int best = INT_MAX, best_words = INT_MAX;
+    for (int gt = n; gt >= 0; --gt) {
+        unsigned __int128 top = P > 1 ? (unsigned __int128)P : 1;
+        bool ok = true;
+        for (int i = 0; i < gt && ok; ++i) {
+            top *= radix;
+            ok = top <= lim;
+        }
+        if (!ok) continue;
+        int lo[kMaxWords], hi[kMaxWords], bits[kMaxWords];
+        int nw = 0, passes = 0, v = n;
+        while (v > gt && nw < kMaxWords - 1) {
+            unsigned __int128 r = 1;
+            int g = 0;
+            while (v - g > gt && r * radix <= lim) {
+                r *= radix;
+                ++g;
+            }
+            lo[nw] = v - g;
+            hi[nw] = v;
+            bits[nw] = bit_width_u128(r - 1);
+            passes += (bits[nw] + db - 1) / db;
+            ++nw;
+            v -= g;
+        }
+        if (v > gt) continue;
+        lo[nw] = 0;
+        hi[nw] = gt;
+        bits[nw] = bit_width_u128(top - 1);
+        passes += (bits[nw] + db - 1) / db;
+        ++nw;
+        if (passes < best || (passes == best && nw < best_words)) {
+            best = passes;
+            best_words = nw;
+            w.nwords = nw;
+            for (int k = 0; k < nw; ++k) {
+                w.wlo[k] = lo[k];
+                w.whi[k] = hi[k];
+                w.wbits[k] = bits[k];
+            }
+            unsigned __int128 sp = 1;
+            for (int i = 0; i < gt; ++i) sp *= radix;
+            w.span = P > 1 ? (uint64_t)sp : 0;
+        }
+    }
+    return best != INT_MAX;
+}
+
+// The device-wide simplify over key words (for composite keys past 64 bits,
+// or exponents past 64 bits of bit fields).
+bool plan_wide_words(WidePlan &w, Layout &L, int64_t P, int64_t R, int n, uint32_t radix)
+{
+    w.on = true;
+    w.rows = true;
+    w.radix = radix;
+    if (!plan_words(w, P, n, radix, sort_bits())) return false;
+    w.key_bits = 0;
+    for (int k = 0; k < w.nwords; ++k) w.key_bits = std::max(w.key_bits, w.wbits[k]);
+    w.nbs = ceil_div(R, GS_TILE);
+    w.nbm = ceil_div(R, MG_TILE);
+    w.keys0 = L.take(8 * R);
+    w.keys1 = L.take(8 * R);
+    w.vals0 = L.take(4 * R);
+    w.vals1 = L.take(4 * R);
+    w.hist = L.take(8 * sort_bins() * w.nbs);
+    w.hoff = L.take(8 * (sort_bins() * w.nbs + 1));
+    w.tmp = L.take(8 * (ceil_div(std::max<int64_t>(sort_bins() * w.nbs, w.nbm), LB_TILE) + 2));
+    w.st_key = L.take(4 * R);   // representative term index per kept run
+    w.st_ckey = L.take(8 * R);
+    w.st_coef = L.take(8 * R);
+    w.cnt = L.take(8 * w.nbm);
+    w.soff = L.take(8 * w.nbm);
+    w.ooff = L.take(8 * (w.nbm + 1));
+    w.head = L.take((size_t)R);
+    return true;
+}
+
 struct SimplifyPlan {
     size_t keys, st_key, st_coef, seg_count, order, queue;
     WidePlan wide;
     size_t total;
+    bool ok = true;   // false: too many terms for the device-wide path that the exponents need
 };
 
 poly_status run_simplify(const poly_csr *in, poly_csr *out, double zero_tol, void *ws, const struct SimplifyPlan &pl,
                          hipStream_t s);
 poly_status run_wide(const WidePlan &w, void *ws, int64_t P, int64_t R, int n, int bits, const double *coefs,
                      double zero_tol, poly_csr *out, hipStream_t s);
+poly_status run_wide_words(const WidePlan &w, void *ws, const poly_csr *in, double zero_tol, poly_csr *out,
+                           hipStream_t s);
 
 // T terms in P polynomials (row offsets rph on the host), n variables with
-// exponents below radix
+// exponents below radix.  Paths: one workgroup per polynomial on bit-field
+// keys; the device-wide sort on one composite key word; the device-wide sort
+// over several key words.  Exponents wider than 64 bits of bit fields take
+// the device-wide path whatever the sizes.
 SimplifyPlan plan_simplify(int64_t P, int64_t T, const int64_t *rph, int n, uint32_t radix)
 {
     Layout L;
     SimplifyPlan s;
-    if (wide_wanted(P, T, max_segment(rph, P), n, radix)) {
+    const int bits = bit_width_u32(radix - 1);
+    const bool fields = (int64_t)n * bits <= 64;
+    const bool big = T > 0 && max_segment(rph, P) >= tunables().simplify_wide_min;
+    if (T > 0 && T < (int64_t(1) << 32) && (big || !fields)) {
         s.keys = s.st_key = s.st_coef = s.seg_count = s.order = s.queue = 0;
-        plan_wide(s.wide, L, P, T, n, radix);
+        if (fields && wide_range(P, n, radix) != 0)
+            plan_wide(s.wide, L, P, T, n, radix);
+        else
+            s.ok = plan_wide_words(s.wide, L, P, T, n, radix);
+        s.total = L.total();
+        return s;
+    }
+    if (!fields && T > 0) {   // no path: too many terms for 32-bit element indices
+        s.ok = false;
+        s.keys = s.st_key = s.st_coef = s.seg_count = s.order = s.queue = 0;
         s.total = L.total();
         return s;
     }
@@ -911,8 +1036,10 @@ poly_status poly_simplify_workspace(const poly_csr *in, size_t *ws_bytes)
     poly_status st = check_csr(in, true);
     if (st != POLY_OK) return st;
     if (!ws_bytes) return POLY_ERR_ARG;
-    *ws_bytes =
-        plan_simplify(in->npolys, total_terms(in), in->row_ptr_host, in->nvars, (uint32_t)in->max_exp + 1).total;
+    const SimplifyPlan pl = plan_simplify(in->npolys, total_terms(in), in->row_ptr_host, in->nvars,
+                                          (uint32_t)in->max_exp + 1);
+    if (!pl.ok) return POLY_ERR_UNSUPPORTED;
+    *ws_bytes = pl.total;
     return POLY_OK;
 }
 
@@ -925,10 +1052,9 @@ poly_status poly_simplify(const poly_csr *in, poly_csr *out, double zero_tol, vo
     if (out->nvars != in->nvars || out->npolys != in->npolys) return POLY_ERR_ARG;
     if (!(zero_tol >= 0.0)) return POLY_ERR_ARG;
     const int n = in->nvars;
-    const int bits = bit_width_u32((uint32_t)in->max_exp);
-    if ((int64_t)n * bits > 64) return POLY_ERR_KEY_OVERFLOW;
     const int64_t P = in->npolys, T = total_terms(in);
     const SimplifyPlan pl = plan_simplify(P, T, in->row_ptr_host, n, (uint32_t)in->max_exp + 1);
+    if (!pl.ok) return POLY_ERR_UNSUPPORTED;
     if (!ws || ws_bytes < pl.total) return POLY_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     clear_u64(at<unsigned long long>(ws, 0), 1, s);
@@ -949,6 +1075,7 @@ poly_status run_simplify(const poly_csr *in, poly_csr *out, double zero_tol, voi
     const int bits = bit_width_u32((uint32_t)in->max_exp);
     const int64_t P = in->npolys, T = total_terms(in);
     int32_t *status = at<int32_t>(ws, 0);
+    if (pl.wide.rows) return run_wide_words(pl.wide, ws, in, zero_tol, out, s);
     if (pl.wide.on) {
         hipLaunchKernelGGL(k_ws_keys, dim3(grid1(T, 256)), dim3(256), 0, s, in->exps, T, n, pl.wide.radix,
                            in->max_exp, in->row_ptr, P, pl.wide.span, at<uint64_t>(ws, pl.wide.keys0),
@@ -1044,9 +1171,163 @@ poly_status run_wide(const WidePlan &w, void *ws, int64_t P, int64_t R, int n, i
     return POLY_OK;
 }
 
+// One stable LSD radix pass set over the `bits` low bits of kcur (digits of
+// at most sort_bits() bits), vals carried; kcur / vcur end up holding the
+// sorted stream.
+void radix_passes(uint64_t *&kcur, uint64_t *&knext, uint32_t *&vcur, uint32_t *&vnext, int64_t R, int64_t nb,
+                  int bits, int64_t *hist, int64_t *hoff, int64_t *tmp, int64_t scan_state, int32_t *status,
+                  hipStream_t s)
+{
+    const int passes = (bits + sort_bits() - 1) / sort_bits();
+    if (passes == 0) return;
+    const int db = std::max((bits + passes - 1) / passes, GS_MIN_BITS);
+    const int64_t hgrid = std::min<int64_t>(ceil_div(nb, GS_HIST_THREADS / kWave), (int64_t)device_cus() * 8);
+    const GsGen gen{};
+    auto pass = [&](auto dbc, int p) {
+        constexpr int DB = decltype(dbc)::value;
+        const int shift = p * DB;
+        hipLaunchKernelGGL((k_gs_hist<DB, false>), dim3((unsigned)hgrid), dim3(GS_HIST_THREADS), 0, s,
+                           (const uint64_t *)kcur, R, shift, nb, hist, gen);
+        launch_scan(hist, ((int64_t)1 << DB) * nb, hoff, tmp, status, s, true);
+        hipLaunchKernelGGL((k_gs_scatter<DB, GS_KV>), dim3((unsigned)nb), dim3(GS_SC_THREADS), 0, s,
+                           (const uint64_t *)kcur, (const uint32_t *)vcur, R, shift, nb, (const int64_t *)hoff,
+                           knext, vnext, 0, (unsigned long long *)tmp, scan_state, gen);
+    };
+    for (int p = 0; p < passes; ++p) {
+        switch (db) {
+        case 4: pass(std::integral_constant<int, 4>(), p); break;
+        case 5: pass(std::integral_constant<int, 5>(), p); break;
+        case 6: pass(std::integral_constant<int, 6>(), p); break;
+        case 7: pass(std::integral_constant<int, 7>(), p); break;
+        case 8: pass(std::integral_constant<int, 8>(), p); break;
+        case 9: pass(std::integral_constant<int, 9>(), p); break;
+        case 10: pass(std::integral_constant<int, 10>(), p); break;
+        default: pass(std::integral_constant<int, 11>(), p); break;
+        }
+        std::swap(kcur, knext);
+        std::swap(vcur, vnext);
+    }
+}
+
+// The device-wide simplify over key words: the permutation is sorted word
+// by word, least significant first, each word's keys rebuilt in the current
+// order before its passes; runs are then found by the top word and the
+// exponent rows, summed in order, and unpacked by copying a representative
+// row.
+poly_status run_wide_words(const WidePlan &w, void *ws, const poly_csr *in, double zero_tol, poly_csr *out,
+                           hipStream_t s)
+{
+    const int n = in->nvars;
+    const int64_t P = in->npolys, R = total_terms(in);
+    int32_t *status = at<int32_t>(ws, 0);
+    uint64_t *kcur = at<uint64_t>(ws, w.keys0), *knext = at<uint64_t>(ws, w.keys1);
+    uint32_t *vcur = at<uint32_t>(ws, w.vals0), *vnext = at<uint32_t>(ws, w.vals1);
+    int64_t *hist = at<int64_t>(ws, w.hist), *hoff = at<int64_t>(ws, w.hoff), *tmp = at<int64_t>(ws, w.tmp);
+    const int64_t nb = w.nbs;
+    const int64_t scan_state = ceil_div(std::max<int64_t>(sort_bins() * nb, w.nbm), LB_TILE) + 2;
+    clear_u64((unsigned long long *)tmp, scan_state, s);
+    hipLaunchKernelGGL(k_ww_iota, dim3(grid1(R, 256)), dim3(256), 0, s, vcur, R);
+    for (int k = 0; k < w.nwords; ++k) {
+        const bool top = k == w.nwords - 1;
+        hipLaunchKernelGGL(k_ww_word, dim3(grid1(R, 256)), dim3(256), 0, s, in->exps, R, n, w.radix, in->max_exp,
+                           w.wlo[k], w.whi[k], (int)(top && P > 1), in->row_ptr, P, (const uint32_t *)vcur, kcur,
+                           status);
+        radix_passes(kcur, knext, vcur, vnext, R, nb, w.wbits[k], hist, hoff, tmp, scan_state, status, s);
+    }
+    uint8_t *head = at<uint8_t>(ws, w.head);
+    hipLaunchKernelGGL(k_ww_heads, dim3(grid1(R, 256)), dim3(256), 0, s, (const uint64_t *)kcur,
+                       (const uint32_t *)vcur, R, in->exps, n, w.whi[w.nwords - 1], head);
+    int64_t *cnt = at<int64_t>(ws, w.cnt), *soff = at<int64_t>(ws, w.soff), *ooff = at<int64_t>(ws, w.ooff);
+    uint32_t *st_idx = at<uint32_t>(ws, w.st_key);
+    uint64_t *st_ckey = at<uint64_t>(ws, w.st_ckey);
+    double *st_coef = at<double>(ws, w.st_coef);
+    const int64_t mgrid = std::min<int64_t>(w.nbm, (int64_t)device_cus() * MG_BLOCKS_PER_CU);
+    hipLaunchKernelGGL(k_ww_merge, dim3((unsigned)mgrid), dim3(MG_THREADS), 0, s, (const uint64_t *)kcur,
+                       (const uint32_t *)vcur, (const uint8_t *)head, R, in->coefs, zero_tol, st_idx, st_ckey,
+                       st_coef, cnt, soff);
+    launch_scan(cnt, w.nbm, ooff, tmp, status, s, true);
+    hipLaunchKernelGGL(k_ww_compact, dim3((unsigned)w.nbm), dim3(256), 0, s, (const int64_t *)soff,
+                       (const int64_t *)cnt, (const int64_t *)ooff, (const uint32_t *)st_idx,
+                       (const double *)st_coef, in->exps, n, out->exps, out->coefs, out->capacity, status);
+    hipLaunchKernelGGL(k_ws_rowptr, dim3(grid1(P + 1, 256)), dim3(256), 0, s, P, w.span, (const uint64_t *)kcur,
+                       R, (const int64_t *)soff, (const int64_t *)cnt, (const int64_t *)ooff, w.nbm,
+                       (const uint64_t *)st_ckey, out->row_ptr);
+    LAUNCH_CHECK();
+    return POLY_OK;
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------------- mul
+
+namespace {
+
+// times of pairs whose exponent sums do not fit 64 bits of bit fields: the
+// raw products are written out as exponent rows in the order of the
+// definition and simplified by the device-wide path over key words.
+struct RowsMulPlan {
+    SimplifyPlan sp;
+    std::vector<int64_t> rph;
+    size_t re = 0, rc = 0, rrp = 0, sizes = 0, tmp = 0, total = 0;
+    int64_t raw = 0;
+};
+
+bool mul_needs_rows(const poly_csr *a, const poly_csr *b)
+{
+    return (int64_t)a->nvars * bit_width_u32((uint32_t)(a->max_exp + b->max_exp)) > 64;
+}
+
+poly_status plan_mul_rows(const poly_csr *a, const poly_csr *b, RowsMulPlan &m)
+{
+    const int64_t P = a->npolys;
+    const int n = a->nvars;
+    m.rph.assign(P + 1, 0);
+    for (int64_t p = 0; p < P; ++p)
+        m.rph[p + 1] = m.rph[p] + (a->row_ptr_host[p + 1] - a->row_ptr_host[p]) *
+                                      (b->row_ptr_host[p + 1] - b->row_ptr_host[p]);
+    m.raw = m.rph[P];
+    if (m.raw >= (int64_t(1) << 32)) return POLY_ERR_UNSUPPORTED;
+    m.sp = plan_simplify(P, m.raw, m.rph.data(), n, (uint32_t)(a->max_exp + b->max_exp) + 1);
+    if (!m.sp.ok) return POLY_ERR_UNSUPPORTED;
+    Layout L;
+    L.off = m.sp.total;
+    m.re = L.take((size_t)m.raw * n);
+    m.rc = L.take(8 * (size_t)m.raw);
+    m.rrp = L.take(8 * (size_t)(P + 1));
+    m.sizes = L.take(8 * (size_t)std::max<int64_t>(P, 1));
+    m.tmp = L.take(8 * (size_t)scan_tmp_count(P));
+    m.total = L.total();
+    return POLY_OK;
+}
+
+poly_status run_mul_rows(const poly_csr *a, const poly_csr *b, poly_csr *out, double zero_tol, void *ws,
+                         RowsMulPlan &m, hipStream_t s)
+{
+    const int64_t P = a->npolys;
+    const int n = a->nvars;
+    int32_t *status = at<int32_t>(ws, 0);
+    int64_t *sizes = at<int64_t>(ws, m.sizes), *rrp = at<int64_t>(ws, m.rrp);
+    uint8_t *re = at<uint8_t>(ws, m.re);
+    double *rc = at<double>(ws, m.rc);
+    hipLaunchKernelGGL(k_mul_raw_sizes, dim3(grid1(P, 256)), dim3(256), 0, s, a->row_ptr, b->row_ptr, P, sizes);
+    launch_scan(sizes, P, rrp, at<int64_t>(ws, m.tmp), status, s);
+    if (m.raw > 0)
+        hipLaunchKernelGGL(k_mul_expand_rows, dim3(grid1(m.raw, 256)), dim3(256), 0, s, a->row_ptr, a->exps,
+                           a->coefs, a->max_exp, b->row_ptr, b->exps, b->coefs, b->max_exp, P, n,
+                           (const int64_t *)rrp, m.raw, re, rc, status);
+    poly_csr R;
+    R.nvars = n;
+    R.max_exp = a->max_exp + b->max_exp;
+    R.npolys = P;
+    R.capacity = m.raw;
+    R.row_ptr_host = m.rph.data();
+    R.row_ptr = rrp;
+    R.exps = re;
+    R.coefs = rc;
+    return run_simplify(&R, out, zero_tol, ws, m.sp, s);
+}
+
+}  // namespace
 
 poly_status poly_mul_workspace(const poly_csr *a, const poly_csr *b, size_t *ws_bytes, int64_t *raw_terms)
 {
@@ -1054,6 +1335,14 @@ poly_status poly_mul_workspace(const poly_csr *a, const poly_csr *b, size_t *ws_
     if (st != POLY_OK) return st;
     if ((st = check_csr(b, true)) != POLY_OK) return st;
     if (a->nvars != b->nvars || a->npolys != b->npolys) return POLY_ERR_ARG;
+    if (mul_needs_rows(a, b)) {
+        if (a->max_exp + b->max_exp > 255) return POLY_ERR_UNSUPPORTED;
+        RowsMulPlan r;
+        if ((st = plan_mul_rows(a, b, r)) != POLY_OK) return st;
+        if (ws_bytes) *ws_bytes = r.total;
+        if (raw_terms) *raw_terms = r.raw;
+        return POLY_OK;
+    }
     MulPlan m;
     if ((st = plan_mul(a, b, m)) != POLY_OK) return st;
     if (ws_bytes) *ws_bytes = m.total;
@@ -1074,7 +1363,19 @@ poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out, double
     if (a->max_exp + b->max_exp > 255) return POLY_ERR_UNSUPPORTED;
     const int n = a->nvars;
     const int bits = bit_width_u32((uint32_t)(a->max_exp + b->max_exp));
-    if ((int64_t)n * bits > 64) return POLY_ERR_KEY_OVERFLOW;
+    if (mul_needs_rows(a, b)) {
+        RowsMulPlan r;
+        if ((st = plan_mul_rows(a, b, r)) != POLY_OK) return st;
+        if (!ws || ws_bytes < r.total) return POLY_ERR_WORKSPACE;
+        hipStream_t s = (hipStream_t)stream;
+        clear_u64(at<unsigned long long>(ws, 0), 1, s);
+        if (a->npolys == 0) {
+            clear_u64((unsigned long long *)out->row_ptr, 1, s);
+            LAUNCH_CHECK();
+            return POLY_OK;
+        }
+        return run_mul_rows(a, b, out, zero_tol, ws, r, s);
+    }
     MulPlan m;
     if ((st = plan_mul(a, b, m)) != POLY_OK) return st;
     if (!ws || ws_bytes < m.total) return POLY_ERR_WORKSPACE;
@@ -1702,7 +2003,6 @@ poly_status check_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_
     if (I < 0 || K < 0 || J < 0 || A->nvars != B->nvars || A->npolys != I * K || B->npolys != K * J)
         return POLY_ERR_ARG;
     if (A->max_exp + B->max_exp > 255) return POLY_ERR_ARG;
-    if ((int64_t)A->nvars * bit_width_u32((uint32_t)(A->max_exp + B->max_exp)) > 64) return POLY_ERR_KEY_OVERFLOW;
     return POLY_OK;
 }
 
@@ -1724,13 +2024,15 @@ poly_status plan_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t
     m.bits = bit_width_u32((uint32_t)(A->max_exp + B->max_exp));
     const uint32_t radix = (uint32_t)(A->max_exp + B->max_exp) + 1;
     Layout L;
-    if (wide_wanted(Q, m.raw, max_segment(rph.data(), Q), A->nvars, radix)) {
+    const bool fields = (int64_t)A->nvars * m.bits <= 64;
+    if (fields && wide_wanted(Q, m.raw, max_segment(rph.data(), Q), A->nvars, radix)) {
         plan_wide(m.wide, L, Q, m.raw, A->nvars, radix);
         m.ka = L.take(8 * total_terms(A));
         m.kb = L.take(8 * total_terms(B));
         m.re = 0;
     } else {
         m.sp = plan_simplify(Q, m.raw, rph.data(), A->nvars, radix);
+        if (!m.sp.ok) return POLY_ERR_UNSUPPORTED;
         L.off = m.sp.total;
         m.re = L.take((size_t)m.raw * A->nvars);
         m.ka = m.kb = 0;

@@ -204,6 +204,22 @@ __global__ void k_ws_keys(const uint8_t *exps, int64_t T, int n, uint32_t radix,
 __global__ void k_ws_merge(const uint64_t *keys, const uint32_t *vals, int64_t R, const double *coefs, double tol,
                            uint64_t span, uint32_t radix, int n, int bits, uint64_t *st_key, uint64_t *st_ckey,
                            double *st_coef, int64_t *seg_count, int64_t *stage_off);
+__global__ void k_ww_word(const uint8_t *exps, int64_t T, int n, uint32_t radix, int max_exp, int lo, int hi,
+                          int with_poly, const int64_t *row_ptr, int64_t P, const uint32_t *vals, uint64_t *keys,
+                          int32_t *status);
+__global__ void k_ww_iota(uint32_t *vals, int64_t T);
+__global__ void k_ww_heads(const uint64_t *keys, const uint32_t *vals, int64_t R, const uint8_t *exps, int n, int lo,
+                           uint8_t *head);
+__global__ void k_ww_merge(const uint64_t *keys, const uint32_t *vals, const uint8_t *head, int64_t R,
+                           const double *coefs, double tol, uint32_t *st_idx, uint64_t *st_ckey, double *st_coef,
+                           int64_t *seg_count, int64_t *stage_off);
+__global__ void k_ww_compact(const int64_t *stage_off, const int64_t *seg_count, const int64_t *out_off,
+                             const uint32_t *st_idx, const double *st_coef, const uint8_t *exps, int n,
+                             uint8_t *out_exps, double *out_coefs, int64_t capacity, int32_t *status);
+__global__ void k_mul_raw_sizes(const int64_t *a_rp, const int64_t *b_rp, int64_t P, int64_t *sizes);
+__global__ void k_mul_expand_rows(const int64_t *a_rp, const uint8_t *a_e, const double *a_c, int a_max,
+                                  const int64_t *b_rp, const uint8_t *b_e, const double *b_c, int b_max, int64_t P,
+                                  int n, const int64_t *r_rp, int64_t R, uint8_t *r_e, double *r_c, int32_t *status);
 __global__ void k_ws_rowptr(int64_t P, uint64_t span, const uint64_t *keys, int64_t R, const int64_t *stage_off,
                             const int64_t *seg_count, const int64_t *out_off, int64_t nb, const uint64_t *st_ckey,
                             int64_t *row_ptr);

@@ -12,6 +12,21 @@
 // bit-identical to the per-polynomial path) and stages the kept terms with
 // their exponents as bit fields for the unpack kernel; the row pointers come
 // from binary searches of the sorted keys.
+//
+// When p * r^n does not fit 64 bits (many variables, many polynomials), the
+// key is cut into words at variable boundaries: word 0 holds the least
+// significant variables, ..., the top word the polynomial index and the
+// most significant variables, each a mixed-radix number below 2^64.  The LSD
+// sort then runs word by word, least significant first: before a word's
+// passes its key is rebuilt for every element in the current order from the
+// element's exponent row (k_ww_word), so only the permutation travels
+// between words.  Runs are found by comparing each element's top word and
+// the exponents of the lower words with its predecessor's (k_ww_heads), the
+// merge stages a representative term index per kept run (k_ww_merge), and
+// the unpack copies that term's exponent row (k_ww_compact); the row
+// pointers come from the top words as above.  The same path serves
+// n * bit_width(max_exp) > 64, where exponents no longer fit one word of
+// bit fields.
 #include "kernels.h"
 
 namespace polyhip {
@@ -220,6 +235,219 @@ __global__ void k_ws_rowptr(int64_t P, uint64_t span, const uint64_t *__restrict
         else c = mid;
     }
     row_ptr[p] = out_off[b] + a;
+}
+
+// keys[i] = the key word of variables [lo, hi) of term t = vals[i]: the
+// mixed-radix number of those exponents, x_lo most significant, with the
+// polynomial index above them (p * radix^(hi - lo)) when with_poly.
+// Exponents above max_exp set POLY_ERR_EXPONENT (every variable is in
+// exactly one word).
+__global__ void k_ww_word(const uint8_t *__restrict__ exps, int64_t T, int n, uint32_t radix, int max_exp, int lo,
+                          int hi, int with_poly, const int64_t *__restrict__ row_ptr, int64_t P,
+                          const uint32_t *__restrict__ vals, uint64_t *__restrict__ keys, int32_t *status)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= T) return;
+    const int64_t t = vals[i];
+    const uint8_t *row = exps + t * n;
+    uint64_t k = 0;
+    if (with_poly) {
+        int64_t a = 0, b = P;   // the last p with row_ptr[p] <= t
+        while (b - a > 1) {
+            const int64_t mid = (a + b) >> 1;
+            if (row_ptr[mid] <= t) a = mid;
+            else b = mid;
+        }
+        k = (uint64_t)a;
+    }
+    int bad = 0;
+    for (int v = lo; v < hi; ++v) {
+        const uint32_t e = row[v];
+        bad |= (int)(e > (uint32_t)max_exp);
+        k = k * radix + e;
+    }
+    keys[i] = k;
+    if (bad) set_status(status, POLY_ERR_EXPONENT);
+}
+
+// The identity permutation (before the first word's passes).
+__global__ void k_ww_iota(uint32_t *vals, int64_t T)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < T) vals[i] = (uint32_t)i;
+}
+
+// head[i] = 1 if sorted element i starts a run: its top word or its
+// exponents of variables [lo, n) (those outside the top word) differ from
+// element i - 1's.
+__global__ void k_ww_heads(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals, int64_t R,
+                           const uint8_t *__restrict__ exps, int n, int lo, uint8_t *__restrict__ head)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= R) return;
+    bool h = i == 0 || keys[i] != keys[i - 1];
+    if (!h) {
+        const uint8_t *a = exps + (int64_t)vals[i] * n, *b = exps + (int64_t)vals[i - 1] * n;
+        for (int v = lo; v < n; ++v) {
+            if (a[v] != b[v]) {
+                h = true;
+                break;
+            }
+        }
+    }
+    head[i] = (uint8_t)h;
+}
+
+// As k_ws_merge, with the runs given by head flags: each run is summed left
+// to right in one lane; a kept run stages its first element's term index
+// (st_idx), top word (st_ckey) and sum.
+__global__ void __launch_bounds__(MG_THREADS) k_ww_merge(const uint64_t *__restrict__ keys,
+                                                        const uint32_t *__restrict__ vals,
+                                                        const uint8_t *__restrict__ head, int64_t R,
+                                                        const double *__restrict__ coefs, double tol,
+                                                        uint32_t *__restrict__ st_idx, uint64_t *__restrict__ st_ckey,
+                                                        double *__restrict__ st_coef, int64_t *seg_count,
+                                                        int64_t *stage_off)
+{
+    __shared__ double s_c[MG_TILE + GS_HALO];
+    __shared__ uint8_t s_h[MG_TILE + GS_HALO];
+    __shared__ uint32_t s_head[MG_TILE + 1];
+    __shared__ uint64_t s_scan[MG_THREADS / kWave];
+    constexpr int MI = MG_TILE / MG_THREADS;
+    static_assert(MI <= 4 && MG_TILE < 65536, "flags are packed 16 bits per round");
+    const int64_t nb = (R + MG_TILE - 1) / MG_TILE;
+    for (int64_t blk = blockIdx.x; blk < nb; blk += gridDim.x) {
+        const int64_t t0 = blk * MG_TILE;
+        const int m = (int)(R - t0 < MG_TILE ? R - t0 : MG_TILE);
+        const int hl = (int)(R - t0 - m < GS_HALO ? R - t0 - m : GS_HALO);
+        __syncthreads();   // the previous tile's LDS reads are done
+        for (int l = threadIdx.x; l < m + hl; l += MG_THREADS) {
+            s_c[l] = coefs[vals[t0 + l]];
+            s_h[l] = head[t0 + l];
+        }
+        __syncthreads();
+        uint64_t hflags = 0;
+#pragma unroll
+        for (int q = 0; q < MI; ++q) {
+            const int l = q * MG_THREADS + threadIdx.x;
+            if (l < m && s_h[l]) hflags |= 1ull << (16 * q);
+        }
+        uint64_t htot;
+        const uint64_t hpre = block_exclusive_scan<MG_THREADS>(hflags, s_scan, htot);
+        int nh = 0;
+#pragma unroll
+        for (int q = 0; q < MI; ++q) {
+            if ((hflags >> (16 * q)) & 1u)
+                s_head[nh + (int)((hpre >> (16 * q)) & 0xffffu)] = (uint32_t)(q * MG_THREADS + threadIdx.x);
+            nh += (int)((htot >> (16 * q)) & 0xffffu);
+        }
+        if (threadIdx.x == 0) s_head[nh] = (uint32_t)m;
+        __syncthreads();
+        int hl_k[MI];
+        double hs[MI];
+        uint64_t kflags = 0;
+#pragma unroll
+        for (int q = 0; q < MI; ++q) {
+            const int k = q * MG_THREADS + threadIdx.x;
+            hl_k[q] = 0;
+            hs[q] = 0.0;
+            if (k < nh) {
+                const int l = (int)s_head[k], e = (int)s_head[k + 1];
+                double s = s_c[l];
+                for (int f = l + 1; f < e; ++f) s = s + s_c[f];
+                if (k == nh - 1) {
+                    int f = m;
+                    for (; f < m + hl && !s_h[f]; ++f) s = s + s_c[f];
+                    if (f == m + hl)
+                        for (int64_t g = t0 + m + hl; g < R && !head[g]; ++g) s = s + coefs[vals[g]];
+                }
+                if (!(fabs(s) <= tol)) {
+                    hl_k[q] = l;
+                    hs[q] = s;
+                    kflags |= 1ull << (16 * q);
+                }
+            }
+        }
+        uint64_t ktot;
+        const uint64_t kpre = block_exclusive_scan<MG_THREADS>(kflags, s_scan, ktot);
+        int64_t tot = 0;
+#pragma unroll
+        for (int q = 0; q < MI; ++q) {
+            if ((kflags >> (16 * q)) & 1u) {
+                const int64_t d = t0 + tot + (int64_t)((kpre >> (16 * q)) & 0xffffu);
+                st_idx[d] = vals[t0 + hl_k[q]];
+                st_ckey[d] = keys[t0 + hl_k[q]];
+                st_coef[d] = hs[q];
+            }
+            tot += (int64_t)((ktot >> (16 * q)) & 0xffffu);
+        }
+        if (threadIdx.x == 0) {
+            seg_count[blk] = tot;
+            stage_off[blk] = t0;
+        }
+    }
+}
+
+// Raw product sizes of the pairs a_p * b_p.
+__global__ void k_mul_raw_sizes(const int64_t *a_rp, const int64_t *b_rp, int64_t P, int64_t *sizes)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < P) sizes[p] = (a_rp[p + 1] - a_rp[p]) * (b_rp[p + 1] - b_rp[p]);
+}
+
+// The raw products of the pairs as exponent rows and coefficients, in the
+// order of the definition (pair by pair, term i of a_p then term j of b_p,
+// i-major): element k of pair p is (i, j) = divmod(k - r_rp[p], |b_p|), row
+// a_i + b_j, coefficient fl(c_i * c_j).  One thread per raw term.
+__global__ void k_mul_expand_rows(const int64_t *__restrict__ a_rp, const uint8_t *__restrict__ a_e,
+                                  const double *__restrict__ a_c, int a_max, const int64_t *__restrict__ b_rp,
+                                  const uint8_t *__restrict__ b_e, const double *__restrict__ b_c, int b_max,
+                                  int64_t P, int n, const int64_t *__restrict__ r_rp, int64_t R,
+                                  uint8_t *__restrict__ r_e, double *__restrict__ r_c, int32_t *status)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= R) return;
+    int64_t lo = 0, hi = P;   // the last p with r_rp[p] <= k
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (r_rp[mid] <= k) lo = mid;
+        else hi = mid;
+    }
+    const int64_t nb = b_rp[lo + 1] - b_rp[lo];
+    const int64_t l = k - r_rp[lo], i = l / nb, j = l - i * nb;
+    const int64_t ia = a_rp[lo] + i, jb = b_rp[lo] + j;
+    const uint8_t *ra = a_e + ia * n, *rb = b_e + jb * n;
+    uint8_t *o = r_e + k * n;
+    int bad = 0;
+    for (int v = 0; v < n; ++v) {
+        const uint32_t x = ra[v], y = rb[v];
+        bad |= (int)(x > (uint32_t)a_max) | (int)(y > (uint32_t)b_max);
+        o[v] = (uint8_t)(x + y);
+    }
+    r_c[k] = a_c[ia] * b_c[jb];
+    if (bad) set_status(status, POLY_ERR_EXPONENT);
+}
+
+// Unpack of the staged runs of merge tile blockIdx.x: coefficients, and each
+// run's exponent row copied from its representative input term.
+__global__ void __launch_bounds__(256) k_ww_compact(const int64_t *stage_off, const int64_t *seg_count,
+                                                    const int64_t *out_off, const uint32_t *st_idx,
+                                                    const double *st_coef, const uint8_t *exps, int n,
+                                                    uint8_t *out_exps, double *out_coefs, int64_t capacity,
+                                                    int32_t *status)
+{
+    const int64_t b = blockIdx.x;
+    const int64_t cnt = seg_count[b], src = stage_off[b], dst = out_off[b];
+    if (threadIdx.x == 0 && dst + cnt > capacity) set_status(status, POLY_ERR_CAPACITY);
+    const int64_t end = dst + cnt < capacity ? dst + cnt : capacity;
+    if (end <= dst) return;
+    for (int64_t i = dst + threadIdx.x; i < end; i += blockDim.x) out_coefs[i] = st_coef[src + (i - dst)];
+    const int64_t nbytes = (end - dst) * n;
+    uint8_t *o = out_exps + dst * n;
+    for (int64_t bi = threadIdx.x; bi < nbytes; bi += blockDim.x) {
+        const int64_t r = bi / n, f = bi - r * n;
+        o[bi] = exps[(int64_t)st_idx[src + r] * n + f];
+    }
 }
 
 }  // namespace polyhip
