@@ -57,7 +57,7 @@ extern "C" {
 typedef enum poly_status {
     POLY_OK = 0,
     POLY_ERR_ARG = 1,          /* bad pointer, size or shape (host-detected)          */
-    POLY_ERR_KEY_OVERFLOW = 2, /* n * field width exceeds the 64-bit key              */
+    POLY_ERR_KEY_OVERFLOW = 2, /* no longer returned (keys of any width are handled)  */
     POLY_ERR_WORKSPACE = 3,    /* workspace smaller than the query returned           */
     POLY_ERR_CAPACITY = 4,     /* output capacity too small (device-detected)         */
     POLY_ERR_EXPONENT = 5,     /* an exponent exceeds the declared max_exp (device)   */
@@ -151,15 +151,19 @@ poly_status poly_timing_read(int32_t slot, double *total_ms, int64_t *launches);
  * out_p = simplify(in_p, zero_tol) for every p (Table "coresemantics").
  * Inputs may hold repeated monomials in any order.  Batches whose largest
  * entry has fewer than "simplify_wide_min" terms are processed by one
- * persistent launch that takes entries largest first; otherwise, when
- * npolys * (max_exp + 1)^n <= 2^64, by one device-wide radix sort of the keys
+ * persistent launch that takes entries largest first (exponent rows packed
+ * into 64-bit keys of b = bit width of max_exp bits per variable, x1 in the
+ * top field); otherwise by one device-wide stable radix sort of the keys
  * entry * (max_exp + 1)^n + (mixed-radix monomial key) and a tiled merge of
- * equal-key runs.  Both sum each run left to right in input order, so they
- * give bit-identical results.
+ * equal-key runs.  Where that key passes 64 bits it is cut into words below
+ * 2^64 at variable boundaries and sorted word by word, least significant
+ * first; where n*b > 64 the device-wide path is taken whatever the sizes.
+ * All paths sum each run left to right in input order, so they give
+ * bit-identical results.  The device-wide path needs fewer than 2^32 terms
+ * in all (else POLY_ERR_UNSUPPORTED when n*b > 64; the per-entry path is
+ * taken otherwise).
  * out->npolys must equal in->npolys, out->nvars in->nvars; out->capacity >=
- * total input terms always suffices.  zero_tol >= 0 (NaN sums are kept).
- * Exponent rows are packed into 64-bit keys with b = bit width of max_exp
- * bits per variable, x1 in the top field; n*b > 64 -> POLY_ERR_KEY_OVERFLOW. */
+ * total input terms always suffices.  zero_tol >= 0 (NaN sums are kept). */
 poly_status poly_simplify_workspace(const poly_csr *in, size_t *ws_bytes);
 poly_status poly_simplify(const poly_csr *in, poly_csr *out, double zero_tol,
                           void *ws, size_t ws_bytes, void *stream);
@@ -170,11 +174,13 @@ poly_status poly_simplify(const poly_csr *in, poly_csr *out, double zero_tol,
  * multiply-add), then merged as in poly_simplify (Section 3.3, entrywise
  * times; Section 6.3, expansion followed by simplify).  a and b must have
  * equal nvars and npolys.  Field width b = bit width of
- * (a->max_exp + b->max_exp); n*b > 64 -> POLY_ERR_KEY_OVERFLOW.  Per pair,
- * |a_p| * |b_p| must be below 2^32.  *raw_terms (host) receives
- * sum_p |a_p| * |b_p|; out->capacity >= that always suffices (the exact need
- * is the final row_ptr[P]).  The raw product terms are never written to
- * memory: they are generated per key range inside the merge kernel. */
+ * (a->max_exp + b->max_exp) <= 8.  Per pair, |a_p| * |b_p| must be below
+ * 2^32.  *raw_terms (host) receives sum_p |a_p| * |b_p|; out->capacity >=
+ * that always suffices (the exact need is the final row_ptr[P]).  With
+ * n*b <= 64 the raw product terms are never written to memory: they are
+ * generated per key range inside the merge kernel.  With n*b > 64 they are
+ * written as exponent rows in the order of the definition (sum_p |a_p| *
+ * |b_p| below 2^32) and simplified over key words as in poly_simplify. */
 poly_status poly_mul_workspace(const poly_csr *a, const poly_csr *b,
                                size_t *ws_bytes, int64_t *raw_terms);
 poly_status poly_mul(const poly_csr *a, const poly_csr *b, poly_csr *out,
@@ -264,8 +270,10 @@ poly_status poly_eval_backward2(const poly_csr *f, const double *X, int64_t N, c
  * multiplied and rounded once).  out->max_exp >= A->max_exp + B->max_exp
  * (at most 255); out->capacity >= the raw term count returned by the query
  * (device-checked, POLY_ERR_CAPACITY).  Matrix powers are repeated products.
- * When an output entry has at least "simplify_wide_min" raw terms, the raw
- * products go straight to the device-wide simplify as packed keys. */
+ * When an output entry has at least "simplify_wide_min" raw terms and the
+ * keys fit 64 bits, the raw products go straight to the device-wide
+ * simplify as packed keys; otherwise they are written as exponent rows and
+ * simplified as in poly_simplify (any width). */
 poly_status poly_mtimes_workspace(const poly_csr *A, const poly_csr *B, int64_t I, int64_t K, int64_t J,
                                   size_t *ws_bytes, int64_t *raw_terms);
 poly_status poly_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t K, int64_t J,

@@ -949,7 +949,7 @@ const char *poly_strerror(int32_t status)
     switch (status) {
     case POLY_OK: return "ok";
     case POLY_ERR_ARG: return "invalid argument, size or shape";
-    case POLY_ERR_KEY_OVERFLOW: return "packed exponent key would exceed 64 bits (n * field width > 64)";
+    case POLY_ERR_KEY_OVERFLOW: return "packed exponent key would exceed 64 bits (no longer returned)";
     case POLY_ERR_WORKSPACE: return "workspace too small";
     case POLY_ERR_CAPACITY: return "output capacity too small";
     case POLY_ERR_EXPONENT: return "an exponent exceeds the declared max_exp";
@@ -1228,10 +1228,15 @@ poly_status run_wide_words(const WidePlan &w, void *ws, const poly_csr *in, doub
     clear_u64((unsigned long long *)tmp, scan_state, s);
     hipLaunchKernelGGL(k_ww_iota, dim3(grid1(R, 256)), dim3(256), 0, s, vcur, R);
     for (int k = 0; k < w.nwords; ++k) {
+        // the word's keys in input order (coalesced reads of the rows), then,
+        // past the first word, gathered into the current order
         const bool top = k == w.nwords - 1;
+        uint64_t *dst = k == 0 ? kcur : knext;
         hipLaunchKernelGGL(k_ww_word, dim3(grid1(R, 256)), dim3(256), 0, s, in->exps, R, n, w.radix, in->max_exp,
-                           w.wlo[k], w.whi[k], (int)(top && P > 1), in->row_ptr, P, (const uint32_t *)vcur, kcur,
-                           status);
+                           w.wlo[k], w.whi[k], (int)(top && P > 1), in->row_ptr, P, dst, status);
+        if (k > 0)
+            hipLaunchKernelGGL(k_ww_gather, dim3(grid1(R, 256)), dim3(256), 0, s, (const uint64_t *)knext,
+                               (const uint32_t *)vcur, R, kcur);
         radix_passes(kcur, knext, vcur, vnext, R, nb, w.wbits[k], hist, hoff, tmp, scan_state, status, s);
     }
     uint8_t *head = at<uint8_t>(ws, w.head);
@@ -1246,7 +1251,7 @@ poly_status run_wide_words(const WidePlan &w, void *ws, const poly_csr *in, doub
                        (const uint32_t *)vcur, (const uint8_t *)head, R, in->coefs, zero_tol, st_idx, st_ckey,
                        st_coef, cnt, soff);
     launch_scan(cnt, w.nbm, ooff, tmp, status, s, true);
-    hipLaunchKernelGGL(k_ww_compact, dim3((unsigned)w.nbm), dim3(256), 0, s, (const int64_t *)soff,
+    hipLaunchKernelGGL(k_ww_compact, dim3((unsigned)w.nbm, MG_TILE / 256), dim3(256), 0, s, (const int64_t *)soff,
                        (const int64_t *)cnt, (const int64_t *)ooff, (const uint32_t *)st_idx,
                        (const double *)st_coef, in->exps, n, out->exps, out->coefs, out->capacity, status);
     hipLaunchKernelGGL(k_ws_rowptr, dim3(grid1(P + 1, 256)), dim3(256), 0, s, P, w.span, (const uint64_t *)kcur,
@@ -2530,7 +2535,6 @@ poly_status check_pipeline(const poly_csr *in, const double *X, int64_t N, const
     poly_status st = check_csr(in, true);
     if (st != POLY_OK) return st;
     if (N < 0) return POLY_ERR_ARG;
-    if ((int64_t)in->nvars * bit_width_u32((uint32_t)in->max_exp) > 64) return POLY_ERR_KEY_OVERFLOW;
     if (!simp && !jac && !G) return POLY_OK;   // workspace query
     if ((st = check_csr(simp, false)) != POLY_OK) return st;
     if ((st = check_csr(jac, false)) != POLY_OK) return st;
@@ -2551,7 +2555,9 @@ poly_status poly_plan_workspace(const poly_csr *in, int64_t N, size_t *ws_bytes)
     poly_status st = check_pipeline(in, nullptr, N, nullptr, nullptr, nullptr);
     if (st != POLY_OK) return st;
     if (!ws_bytes) return POLY_ERR_ARG;
-    *ws_bytes = plan_pipeline(in, N).total;
+    const PipePlan pp = plan_pipeline(in, N);
+    if (!pp.sp.ok) return POLY_ERR_UNSUPPORTED;
+    *ws_bytes = pp.total;
     return POLY_OK;
 }
 
@@ -2565,6 +2571,7 @@ poly_status poly_plan_create(const poly_csr *in, double zero_tol, const double *
     if (!(zero_tol >= 0.0)) return POLY_ERR_ARG;
     if (!stream) return POLY_ERR_ARG;   // the legacy null stream cannot be captured
     const PipePlan pp = plan_pipeline(in, N);
+    if (!pp.sp.ok) return POLY_ERR_UNSUPPORTED;
     if (!ws || ws_bytes < pp.total) return POLY_ERR_WORKSPACE;
     const int n = in->nvars;
     const int64_t P = in->npolys;

@@ -205,8 +205,8 @@ __global__ void k_ws_merge(const uint64_t *keys, const uint32_t *vals, int64_t R
                            uint64_t span, uint32_t radix, int n, int bits, uint64_t *st_key, uint64_t *st_ckey,
                            double *st_coef, int64_t *seg_count, int64_t *stage_off);
 __global__ void k_ww_word(const uint8_t *exps, int64_t T, int n, uint32_t radix, int max_exp, int lo, int hi,
-                          int with_poly, const int64_t *row_ptr, int64_t P, const uint32_t *vals, uint64_t *keys,
-                          int32_t *status);
+                          int with_poly, const int64_t *row_ptr, int64_t P, uint64_t *keys, int32_t *status);
+__global__ void k_ww_gather(const uint64_t *src, const uint32_t *vals, int64_t R, uint64_t *dst);
 __global__ void k_ww_iota(uint32_t *vals, int64_t T);
 __global__ void k_ww_heads(const uint64_t *keys, const uint32_t *vals, int64_t R, const uint8_t *exps, int n, int lo,
                            uint8_t *head);

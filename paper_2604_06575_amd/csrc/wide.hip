@@ -18,9 +18,9 @@
 // significant variables, ..., the top word the polynomial index and the
 // most significant variables, each a mixed-radix number below 2^64.  The LSD
 // sort then runs word by word, least significant first: before a word's
-// passes its key is rebuilt for every element in the current order from the
-// element's exponent row (k_ww_word), so only the permutation travels
-// between words.  Runs are found by comparing each element's top word and
+// passes its keys are built in input order from the exponent rows
+// (k_ww_word, coalesced) and gathered into the current order (k_ww_gather),
+// so only the permutation travels between words.  Runs are found by comparing each element's top word and
 // the exponents of the lower words with its predecessor's (k_ww_heads), the
 // merge stages a representative term index per kept run (k_ww_merge), and
 // the unpack copies that term's exponent row (k_ww_compact); the row
@@ -237,22 +237,21 @@ __global__ void k_ws_rowptr(int64_t P, uint64_t span, const uint64_t *__restrict
     row_ptr[p] = out_off[b] + a;
 }
 
-// keys[i] = the key word of variables [lo, hi) of term t = vals[i]: the
-// mixed-radix number of those exponents, x_lo most significant, with the
-// polynomial index above them (p * radix^(hi - lo)) when with_poly.
+// keys[t] = the key word of variables [lo, hi) of term t, in input order:
+// the mixed-radix number of those exponents, x_lo most significant, with
+// the polynomial index above them (p * radix^(hi - lo)) when with_poly.
 // Exponents above max_exp set POLY_ERR_EXPONENT (every variable is in
 // exactly one word).
 __global__ void k_ww_word(const uint8_t *__restrict__ exps, int64_t T, int n, uint32_t radix, int max_exp, int lo,
                           int hi, int with_poly, const int64_t *__restrict__ row_ptr, int64_t P,
-                          const uint32_t *__restrict__ vals, uint64_t *__restrict__ keys, int32_t *status)
+                          uint64_t *__restrict__ keys, int32_t *status)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= T) return;
-    const int64_t t = vals[i];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
     const uint8_t *row = exps + t * n;
     uint64_t k = 0;
     if (with_poly) {
-        int64_t a = 0, b = P;   // the last p with row_ptr[p] <= t
+        int64_t a = 0, b = P;   // the last p with row_ptr[p] <= t (neighbouring threads share the path)
         while (b - a > 1) {
             const int64_t mid = (a + b) >> 1;
             if (row_ptr[mid] <= t) a = mid;
@@ -261,13 +260,37 @@ __global__ void k_ww_word(const uint8_t *__restrict__ exps, int64_t T, int n, ui
         k = (uint64_t)a;
     }
     int bad = 0;
-    for (int v = lo; v < hi; ++v) {
-        const uint32_t e = row[v];
-        bad |= (int)(e > (uint32_t)max_exp);
-        k = k * radix + e;
+    if ((n & 3) == 0) {   // 4-byte aligned rows: one load per four exponents
+        const uint32_t *row4 = reinterpret_cast<const uint32_t *>(row);
+        uint32_t word = 0;
+        int wi = -1;
+        for (int v = lo; v < hi; ++v) {
+            if ((v >> 2) != wi) {
+                wi = v >> 2;
+                word = row4[wi];
+            }
+            const uint32_t e = (word >> (8 * (v & 3))) & 0xffu;
+            bad |= (int)(e > (uint32_t)max_exp);
+            k = k * radix + e;
+        }
+    } else {
+        for (int v = lo; v < hi; ++v) {
+            const uint32_t e = row[v];
+            bad |= (int)(e > (uint32_t)max_exp);
+            k = k * radix + e;
+        }
     }
-    keys[i] = k;
+    keys[t] = k;
     if (bad) set_status(status, POLY_ERR_EXPONENT);
+}
+
+// dst[i] = src[vals[i]]: a word's keys, built in input order, put in the
+// current sorted order.
+__global__ void k_ww_gather(const uint64_t *__restrict__ src, const uint32_t *__restrict__ vals, int64_t R,
+                            uint64_t *__restrict__ dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < R) dst[i] = src[vals[i]];
 }
 
 // The identity permutation (before the first word's passes).
@@ -429,24 +452,43 @@ __global__ void k_mul_expand_rows(const int64_t *__restrict__ a_rp, const uint8_
 }
 
 // Unpack of the staged runs of merge tile blockIdx.x: coefficients, and each
-// run's exponent row copied from its representative input term.
-__global__ void __launch_bounds__(256) k_ww_compact(const int64_t *stage_off, const int64_t *seg_count,
-                                                    const int64_t *out_off, const uint32_t *st_idx,
-                                                    const double *st_coef, const uint8_t *exps, int n,
-                                                    uint8_t *out_exps, double *out_coefs, int64_t capacity,
-                                                    int32_t *status)
+// run's exponent row copied from its representative input term.  One
+// thread per row, blockIdx.y picking a slice of the tile, so that many
+// scattered row reads are in flight; 4-byte words when rows are 4-byte
+// aligned.
+__global__ void __launch_bounds__(256) k_ww_compact(const int64_t *__restrict__ stage_off,
+                                                    const int64_t *__restrict__ seg_count,
+                                                    const int64_t *__restrict__ out_off,
+                                                    const uint32_t *__restrict__ st_idx,
+                                                    const double *__restrict__ st_coef,
+                                                    const uint8_t *__restrict__ exps, int n,
+                                                    uint8_t *__restrict__ out_exps, double *__restrict__ out_coefs,
+                                                    int64_t capacity, int32_t *status)
 {
     const int64_t b = blockIdx.x;
     const int64_t cnt = seg_count[b], src = stage_off[b], dst = out_off[b];
-    if (threadIdx.x == 0 && dst + cnt > capacity) set_status(status, POLY_ERR_CAPACITY);
+    if (threadIdx.x == 0 && blockIdx.y == 0 && dst + cnt > capacity) set_status(status, POLY_ERR_CAPACITY);
     const int64_t end = dst + cnt < capacity ? dst + cnt : capacity;
-    if (end <= dst) return;
-    for (int64_t i = dst + threadIdx.x; i < end; i += blockDim.x) out_coefs[i] = st_coef[src + (i - dst)];
-    const int64_t nbytes = (end - dst) * n;
-    uint8_t *o = out_exps + dst * n;
-    for (int64_t bi = threadIdx.x; bi < nbytes; bi += blockDim.x) {
-        const int64_t r = bi / n, f = bi - r * n;
-        o[bi] = exps[(int64_t)st_idx[src + r] * n + f];
+    for (int64_t i = dst + (int64_t)blockIdx.y * blockDim.x + threadIdx.x; i < end;
+         i += (int64_t)gridDim.y * blockDim.x) {
+        out_coefs[i] = st_coef[src + (i - dst)];
+        const uint8_t *from = exps + (int64_t)st_idx[src + (i - dst)] * n;
+        uint8_t *to = out_exps + i * n;
+        if ((n & 3) == 0) {   // chunks of up to 8 words: all loads issued before the stores
+            const uint32_t *f4 = reinterpret_cast<const uint32_t *>(from);
+            uint32_t *t4 = reinterpret_cast<uint32_t *>(to);
+            const int nw = n / 4;
+            for (int v0 = 0; v0 < nw; v0 += 8) {
+                uint32_t r[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) r[u] = v0 + u < nw ? f4[v0 + u] : 0u;
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (v0 + u < nw) t4[v0 + u] = r[u];
+            }
+        } else {
+            for (int v = 0; v < n; ++v) to[v] = from[v];
+        }
     }
 }
 

@@ -6,7 +6,8 @@ bit for bit (simplified terms, Jacobian terms, gradient values), with eager
 work and synchronisations between replays, and the input coefficients
 changed between replays (the plan reads its inputs at replay time).  The
 simplified matrix is also held to the oracle.  Both simplify paths (one
-workgroup per entry, device-wide sort) are captured."""
+workgroup per entry, device-wide sort over one key word or several) are
+captured."""
 import sys
 
 import numpy as np
@@ -39,14 +40,16 @@ def bits(a):
     return np.ascontiguousarray(a).view(np.uint64)
 
 
-@pytest.mark.parametrize("wide", [False, True])
-def test_plan_replays_match_eager(ph, wide):
-    ph.tune_set("simplify_wide_min", 1 if wide else 1 << 62)
-    wl = W.batch_matrix(seed=W.SEED_BASE + 60, entries=64, tmin=5, tmax=2000, npts=4096)
+@pytest.mark.parametrize("path", ["per-entry", "device-wide", "key words"])
+def test_plan_replays_match_eager(ph, path):
+    ph.tune_set("simplify_wide_min", 1 << 62 if path == "per-entry" else 1)
+    # 40 variables of degree <= 6: 120 bits of exponent fields, sorted over key words
+    n = 40 if path == "key words" else 20
+    wl = W.batch_matrix(seed=W.SEED_BASE + 60, entries=64, n=n, tmin=5, tmax=2000, npts=1024 if n == 40 else 4096)
     b = ph.batch_from_numpy(wl.row_ptr, wl.exps, wl.coefs, n=wl.n, max_exp=wl.max_exp)
     X = torch.from_numpy(wl.X).cuda()
     side = torch.cuda.Stream()
-    say(f"plan ({'device-wide' if wide else 'per-entry'} simplify): 64 entries, {b.nterms} terms, 4096 points")
+    say(f"plan ({path} simplify): 64 entries, n={n}, {b.nterms} terms, {X.shape[0]} points")
     with torch.cuda.stream(side):
         plan = ph.Plan(b, X)
     rng = W.rng_for(61)
