@@ -348,7 +348,9 @@ poly_status poly_affine_normal_stochastic(const poly_csr *f, const double *X, in
  *       K-block); slice products of diagonals s + t = 2 and 3 are summed
  *       exactly in FP32 by BF16 MFMA within each K-block, diagonals >= 4
  *       share one FP32 accumulator, and each K-block is recombined in FP64.
- *       nslices in [3, 6]; pairs with s + t > nslices + 1 are skipped.
+ *       nslices in [3, 5] (a sixth digit would sit below the FP32
+ *       rounding floor of the shared accumulator, so it is refused with
+ *       POLY_ERR_ARG); pairs with s + t > nslices + 1 are skipped.
  * Error of the split result is about max(2^-(8*nslices - 10), 2^-34)
  * relative to sum over K-blocks b of (sum_{k in b} |C[p,k]|) * max_{k in b}
  * |v_k(x)| (digits are relative to the block's largest monomial value; this

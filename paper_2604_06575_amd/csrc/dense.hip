@@ -532,7 +532,8 @@ constexpr int SP_BM = 256, SP_BN = 64;   // workgroup tile: 8 waves x (32 rows x
 // their own scale) and one shared group for diagonals >= 4 (at most 2^-16 of
 // the leading term), whose FP32 rounding sets an error floor near 2^-34 of
 // sum |C v| per K-block whatever the digit count; a fourth exact group would
-// lower it but does not fit the register budget of this tile shape.
+// lower it but does not fit the register budget of this tile shape, so no
+// more than five digits are offered (a sixth would sit below that floor).
 constexpr int SP_GROUPS = 3;
 constexpr int SP_LDK = SP_KS + 8;    // padded k stride (bf16 elements) of the LDS digit planes
 constexpr int SP_VK = SP_KS * SP_BN / SP_THREADS;   // V values per thread per K step
@@ -819,7 +820,7 @@ poly_status dense_workspace(int32_t n, int64_t K, int64_t P, int64_t N, poly_pre
 {
     if (!ws_bytes || n < 1 || n > 255 || K < 0 || P < 0 || N < 0) return POLY_ERR_ARG;
     if (prec != POLY_FP64 && prec != POLY_SPLIT_BF16) return POLY_ERR_ARG;
-    if (prec == POLY_SPLIT_BF16 && (S < 3 || S > 6)) return POLY_ERR_ARG;
+    if (prec == POLY_SPLIT_BF16 && (S < 3 || S > 5)) return POLY_ERR_ARG;
     *ws_bytes = plan_dense(n, K, P, N, prec, S).total;
     return POLY_OK;
 }
@@ -871,8 +872,7 @@ poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_ex
         switch (S) {
         case 3: launch_split<3>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, ys, s); break;
         case 4: launch_split<4>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, ys, s); break;
-        case 5: launch_split<5>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, ys, s); break;
-        default: launch_split<6>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, ys, s); break;
+        default: launch_split<5>(n, K, Kp, basis, enc, P, Cs, N, X, sig_v, Y, ys, s); break;
         }
     }
     return hipGetLastError() == hipSuccess ? POLY_OK : POLY_ERR_HIP;

@@ -344,7 +344,7 @@ def test_dense_fp64(ph, P, K, N):
     assert (np.abs(Y - Yo) <= 1e-12 * A).all()
 
 
-@pytest.mark.parametrize("S", [4, 5, 6])
+@pytest.mark.parametrize("S", [3, 4, 5])
 def test_dense_split(ph, S):
     wl = W.dense_shared(seed=950, P=70, N=90, n=8, d=4, K=400)
     say(f"dense split S={S}")
@@ -360,6 +360,15 @@ def test_dense_split(ph, S):
     assert err.max() <= bound
     if S >= 5:
         assert err.max() <= 1e-10
+
+
+def test_dense_split_refuses_six_slices(ph):
+    """A sixth digit would sit below the FP32 floor of the shared
+    accumulator group of diagonals >= 4: refused on the host."""
+    import ctypes
+    size = ctypes.c_size_t()
+    assert ph.lib().poly_eval_dense_workspace(8, 400, 70, 90, ph.POLY_SPLIT_BF16, 6, ctypes.byref(size)) == 1
+    assert ph.lib().poly_eval_dense_workspace(8, 400, 70, 90, ph.POLY_SPLIT_BF16, 5, ctypes.byref(size)) == 0
 
 
 def _dense_case(ph, wl, prec, S=5):
