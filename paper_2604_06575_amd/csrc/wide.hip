@@ -452,10 +452,11 @@ __global__ void k_mul_expand_rows(const int64_t *__restrict__ a_rp, const uint8_
 }
 
 // Unpack of the staged runs of merge tile blockIdx.x: coefficients, and each
-// run's exponent row copied from its representative input term.  One
-// thread per row, blockIdx.y picking a slice of the tile, so that many
-// scattered row reads are in flight; 4-byte words when rows are 4-byte
-// aligned.
+// run's exponent row copied from its representative input term.  Block
+// (b, y) takes rows y * 256 .. y * 256 + 255 of the tile, 64 per wave; a
+// wave copies its rows' bytes as one contiguous output run, lane by lane
+// (4-byte words when rows are 4-byte aligned), so the stores are coalesced
+// and the loads of one row come from one instruction.
 __global__ void __launch_bounds__(256) k_ww_compact(const int64_t *__restrict__ stage_off,
                                                     const int64_t *__restrict__ seg_count,
                                                     const int64_t *__restrict__ out_off,
@@ -469,25 +470,36 @@ __global__ void __launch_bounds__(256) k_ww_compact(const int64_t *__restrict__ 
     const int64_t cnt = seg_count[b], src = stage_off[b], dst = out_off[b];
     if (threadIdx.x == 0 && blockIdx.y == 0 && dst + cnt > capacity) set_status(status, POLY_ERR_CAPACITY);
     const int64_t end = dst + cnt < capacity ? dst + cnt : capacity;
-    for (int64_t i = dst + (int64_t)blockIdx.y * blockDim.x + threadIdx.x; i < end;
-         i += (int64_t)gridDim.y * blockDim.x) {
-        out_coefs[i] = st_coef[src + (i - dst)];
-        const uint8_t *from = exps + (int64_t)st_idx[src + (i - dst)] * n;
-        uint8_t *to = out_exps + i * n;
-        if ((n & 3) == 0) {   // chunks of up to 8 words: all loads issued before the stores
-            const uint32_t *f4 = reinterpret_cast<const uint32_t *>(from);
-            uint32_t *t4 = reinterpret_cast<uint32_t *>(to);
-            const int nw = n / 4;
-            for (int v0 = 0; v0 < nw; v0 += 8) {
-                uint32_t r[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) r[u] = v0 + u < nw ? f4[v0 + u] : 0u;
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (v0 + u < nw) t4[v0 + u] = r[u];
-            }
-        } else {
-            for (int v = 0; v < n; ++v) to[v] = from[v];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int64_t r0 = dst + (int64_t)blockIdx.y * blockDim.x + (int64_t)wave * kWave;
+    if (r0 >= end) return;
+    const int rows = (int)(end - r0 < kWave ? end - r0 : kWave);
+    uint32_t my_idx = 0;
+    if (lane < rows) {
+        out_coefs[r0 + lane] = st_coef[src + (r0 - dst) + lane];
+        my_idx = st_idx[src + (r0 - dst) + lane];
+    }
+    if ((n & 3) == 0) {
+        const uint32_t nw = (uint32_t)n / 4;
+        const uint32_t *ex4 = reinterpret_cast<const uint32_t *>(exps);
+        uint32_t *out4 = reinterpret_cast<uint32_t *>(out_exps) + r0 * nw;
+        const uint32_t total = (uint32_t)rows * nw;
+        // uniform trip count: every lane takes part in each shuffle
+        for (uint32_t d0 = 0; d0 < total; d0 += kWave) {
+            const uint32_t d = d0 + lane;
+            const uint32_t r = d / nw, w = d - r * nw;
+            const uint32_t t = (uint32_t)__shfl((int)my_idx, (int)(r < kWave ? r : kWave - 1), kWave);
+            if (d < total) out4[d] = ex4[(int64_t)t * nw + w];
+        }
+    } else {
+        const uint32_t un = (uint32_t)n;
+        uint8_t *out = out_exps + r0 * n;
+        const uint32_t total = (uint32_t)rows * un;
+        for (uint32_t d0 = 0; d0 < total; d0 += kWave) {
+            const uint32_t d = d0 + lane;
+            const uint32_t r = d / un, c = d - r * un;
+            const uint32_t t = (uint32_t)__shfl((int)my_idx, (int)(r < kWave ? r : kWave - 1), kWave);
+            if (d < total) out[d] = exps[(int64_t)t * n + c];
         }
     }
 }
