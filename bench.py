@@ -299,10 +299,19 @@ def bench_batch(args):
     t_grad, _ = time_events(lambda: ph.grad(s, X), 2, 1)
     T_in, T_s, T_j = int(wl.row_ptr[-1]), s.nterms, J.nterms
     term_points = T_j * X.shape[0]
+    # algorithmic work: simplify reads every input term and writes every kept
+    # one ((n + 8) B each); evaluating a term of degree d at a point is d
+    # multiplications and one FMA
+    simp_bytes = (T_in + T_s) * (wl.n + 8)
+    jd = J.exps[:T_j].sum(1, dtype=torch.int64)
+    eval_flops = float((jd + 2).sum().item()) * X.shape[0]
     return {"entries": 4096, "raw_terms": T_in, "simplified_terms": T_s, "jacobian_terms": T_j, "points": X.shape[0],
             "simplify_ms": t_simp * 1e3, "simplify_terms_per_s": T_in / t_simp,
+            "simplify_gbps": simp_bytes / t_simp / 1e9, "simplify_hbm_frac": simp_bytes / t_simp / 8e12,
             "jacobian_ms": t_jac * 1e3, "jacobian_terms_per_s": T_j / t_jac,
             "jacobian_eval_ms": t_eval * 1e3, "jacobian_eval_term_points_per_s": term_points / t_eval,
+            "jacobian_eval_fp64_tflops": eval_flops / t_eval / 1e12,
+            "jacobian_eval_fp64_frac": eval_flops / t_eval / 78.6e12,
             "grad_fused_ms": t_grad * 1e3, **bench_plan(b, X),
             "note": "simplify/jacobian times include the host readback of the output row pointer"}
 
@@ -368,8 +377,22 @@ def bench_deriv(args):
     t_bwd, _ = time_events(lambda: ph.eval_backward(b, X, gY), 2, 1)
     t_hess, _ = time_events(lambda: ph.hess(b, X), 1, 1)
     N = X.shape[0]
+    # algorithmic FP64 flops per point: a term of degree d costs d
+    # multiplications and one FMA; its first derivatives are supp terms of
+    # degree d - 1, its Hessian entries (j <= k) c2 terms of degree d - 2
+    E = wl.exps.astype(np.int64)
+    d = E.sum(1)
+    supp = (E > 0).sum(1)
+    c2 = supp * (supp - 1) // 2 + (E >= 2).sum(1)
+    f_eval = float((d + 2).sum()) * N
+    f_grad = float((supp * (d + 1)).sum()) * N
+    f_hess = float((c2 * d).sum()) * N
     return {"terms": wl.exps.shape[0], "n": wl.n, "points": N,
             "eval_ms": t_eval * 1e3, "backward_dx_dc_ms": t_bwd * 1e3, "hessian_ms": t_hess * 1e3,
+            "eval_fp64_tflops": f_eval / t_eval / 1e12, "hessian_fp64_tflops": f_hess / t_hess / 1e12,
+            "hessian_write_gbps": 8.0 * N * wl.n * wl.n / t_hess / 1e9,
+            "flops_note": f"per call: eval {f_eval:.3g}, gradient {f_grad:.3g} (inside the reverse mode), "
+                          f"Hessian {f_hess:.3g} FP64 flops; FP64 vector peak 78.6 TFLOP/s",
             "dtype": {"f": "f64", "grad": "f64", "hessian": "f64 (100x100 per point, both triangles)"}}
 
 
