@@ -218,10 +218,11 @@ def test_mul_errors(ph):
     a = dev_batch(ph, [(np.array([[200, 0]], np.uint8), np.array([1.0]))], 2, max_exp=200)
     with pytest.raises(ph.PolyError):
         ph.mul(a, a)            # 400 > 255 cannot be stored
-    wide = dev_batch(ph, [(np.ones((1, 40), np.uint8), np.array([1.0]))], 40, max_exp=3)
-    with pytest.raises(ph.PolyError) as ei:
-        ph.mul(wide, wide)      # 40 * 3 bits > 64
-    assert ei.value.code == 2
+    # 40 variables of 3-bit fields (120 bits) are no error: the product is
+    # simplified over key words (times has no width limit in Section 3.3)
+    wide = dev_batch(ph, [(np.ones((1, 40), np.uint8), np.array([1.5]))], 40, max_exp=3)
+    rp, E, C = ph.batch_to_numpy(ph.mul(wide, wide))
+    assert rp.tolist() == [0, 1] and (E == 2).all() and C.tolist() == [2.25]
     lie = dev_batch(ph, [(np.array([[5, 0]], np.uint8), np.array([1.0]))], 2, max_exp=2)
     with pytest.raises(ph.PolyError) as ei:
         ph.mul(lie, lie)        # exponent above the declared bound: device-detected
