@@ -129,6 +129,24 @@ def test_basis_probes_reduce_to_exact_route(ph):
     assert (err <= RTOL).all()
 
 
+def test_degenerate_solves(ph):
+    """Two variables (a one-dimensional tangent space), no Krylov steps at all
+    (maxit = 0: every solve returns 0 and the direction is -e), and a single
+    point with a single probe."""
+    E = np.array([[4, 0], [2, 2], [0, 2], [1, 0], [0, 0]], np.uint8)
+    C = np.array([1.0, 0.5, 2.0, 0.3, 1.0])
+    X = np.array([[0.3, -0.2], [0.1, 0.4], [-0.25, 0.15]])
+    Z = np.array([[1.0, -1.0], [1.0, 1.0]])
+    # a tolerance, not 0: in one dimension the oracle's residual can vanish
+    # exactly after the first step while the kernel's (in R^2) keeps a
+    # rounding-level remainder, and a zero tolerance would count the extra steps
+    D, hv = compare(ph, E, C, X, Z, 1e-8, 1e-12, 3, "n = 2")
+    assert (hv == 4).all()   # H e, then one step for each of the three solves
+    D, hv = compare(ph, E, C, X, Z, 1e-8, 1e-6, 0, "no Krylov steps")
+    assert (hv == 1).all()
+    compare(ph, E, C, X[:1], Z[:1], 1e-8, 1e-12, 5, "one point, one probe")
+
+
 def test_errors_and_empty(ph):
     wl = W.sparse_quartic(seed=5350, n=5, npts=4)
     b = ph.batch_from_numpy(np.array([0, wl.exps.shape[0]], np.int64), wl.exps, wl.coefs, n=5, max_exp=2)

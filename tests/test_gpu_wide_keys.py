@@ -77,6 +77,21 @@ def test_simplify_composite_past_64_bits(ph):
     _same(ph, ph.simplify(b), want)
 
 
+def test_simplify_words_empty_entries_and_total_cancellation(ph):
+    """Empty entries between full ones, and an entry whose terms all cancel,
+    on the word path (30 variables of 3-bit fields)."""
+    n = 30
+    rng = W.rng_for(7250)
+    E1, C1 = W.random_poly(rng, n, 5, 300, integer=False)
+    E2, C2 = W.random_poly(rng, n, 5, 200, integer=False)
+    empty = (np.zeros((0, n), np.uint8), np.zeros(0))
+    polys = [empty, (E1, C1), empty, empty, (np.vstack([E2, E2]), np.concatenate([C2, -C2])), (E2, C2), empty]
+    rp, E, C = W.csr_from_list(polys, n)
+    b = ph.batch_from_numpy(rp, E, C, n=n, max_exp=7)
+    say("simplify words: empty entries, a fully cancelled entry")
+    _same(ph, ph.simplify(b), oracle.simplify_batch(rp, E, C, n=n))
+
+
 def test_simplify_words_drop_zeros_and_tolerance(ph):
     """Exact cancellation and a tolerance on the word path."""
     n = 40
