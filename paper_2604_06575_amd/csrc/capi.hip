@@ -1174,7 +1174,7 @@ poly_status run_wide(const WidePlan &w, void *ws, int64_t P, int64_t R, int n, i
 // One stable LSD radix pass set over the `bits` low bits of kcur (digits of
 // at most sort_bits() bits), vals carried; kcur / vcur end up holding the
 // sorted stream.
-void radix_passes(uint64_t *&kcur, uint64_t *&knext, uint32_t *&vcur, uint32_t *&vnext, int64_t R, int64_t nb,
+static void radix_passes(uint64_t *&kcur, uint64_t *&knext, uint32_t *&vcur, uint32_t *&vnext, int64_t R, int64_t nb,
                   int bits, int64_t *hist, int64_t *hoff, int64_t *tmp, int64_t scan_state, int32_t *status,
                   hipStream_t s)
 {
@@ -1277,12 +1277,12 @@ struct RowsMulPlan {
     int64_t raw = 0;
 };
 
-bool mul_needs_rows(const poly_csr *a, const poly_csr *b)
+static bool mul_needs_rows(const poly_csr *a, const poly_csr *b)
 {
     return (int64_t)a->nvars * bit_width_u32((uint32_t)(a->max_exp + b->max_exp)) > 64;
 }
 
-poly_status plan_mul_rows(const poly_csr *a, const poly_csr *b, RowsMulPlan &m)
+static poly_status plan_mul_rows(const poly_csr *a, const poly_csr *b, RowsMulPlan &m)
 {
     const int64_t P = a->npolys;
     const int n = a->nvars;
@@ -1305,7 +1305,7 @@ poly_status plan_mul_rows(const poly_csr *a, const poly_csr *b, RowsMulPlan &m)
     return POLY_OK;
 }
 
-poly_status run_mul_rows(const poly_csr *a, const poly_csr *b, poly_csr *out, double zero_tol, void *ws,
+static poly_status run_mul_rows(const poly_csr *a, const poly_csr *b, poly_csr *out, double zero_tol, void *ws,
                          RowsMulPlan &m, hipStream_t s)
 {
     const int64_t P = a->npolys;
@@ -1665,7 +1665,7 @@ struct SplitCsrPlan {
     size_t dense = 0, dbasis = 0, dC = 0, total = 0;
 };
 
-poly_status plan_split_csr(const poly_csr *f, int64_t N, int32_t nslices, bool derived, SplitCsrPlan &sp)
+static poly_status plan_split_csr(const poly_csr *f, int64_t N, int32_t nslices, bool derived, SplitCsrPlan &sp)
 {
     const int64_t P = f->npolys;
     sp.K = P > 0 ? f->row_ptr_host[1] : 0;
@@ -1686,7 +1686,7 @@ poly_status plan_split_csr(const poly_csr *f, int64_t N, int32_t nslices, bool d
 }
 
 // mode 0: values; 1: gradient G[p][pt][j]; 2: Hessian H[p][pt][j][k]
-poly_status run_split_csr(int mode, const poly_csr *f, const double *X, int64_t N, double *out, int32_t nslices,
+static poly_status run_split_csr(int mode, const poly_csr *f, const double *X, int64_t N, double *out, int32_t nslices,
                           void *ws, size_t ws_bytes, hipStream_t s)
 {
     SplitCsrPlan sp;
@@ -1730,7 +1730,7 @@ poly_status run_split_csr(int mode, const poly_csr *f, const double *X, int64_t 
     return POLY_OK;
 }
 
-poly_status split_csr_workspace(int mode, const poly_csr *f, int64_t N, int32_t nslices, size_t *ws_bytes)
+static poly_status split_csr_workspace(int mode, const poly_csr *f, int64_t N, int32_t nslices, size_t *ws_bytes)
 {
     SplitCsrPlan sp;
     poly_status st = plan_split_csr(f, N, nslices, mode != 0, sp);
@@ -1846,7 +1846,7 @@ struct HessPlan {
     int64_t jcap, hcap, S;
 };
 
-HessPlan plan_hess(const poly_csr *f, int64_t N, Layout &L)
+static HessPlan plan_hess(const poly_csr *f, int64_t N, Layout &L)
 {
     HessPlan h;
     const int n = f->nvars;
@@ -1883,7 +1883,7 @@ poly_status poly_hess_workspace(const poly_csr *f, int64_t N, poly_prec prec, in
     return POLY_OK;
 }
 
-poly_status run_hess(const poly_csr *f, const double *X, int64_t N, double *H, void *ws, const HessPlan &h,
+static poly_status run_hess(const poly_csr *f, const double *X, int64_t N, double *H, void *ws, const HessPlan &h,
                      hipStream_t s)
 {
     const int n = f->nvars;
@@ -1963,7 +1963,7 @@ struct AffinePlan {
     size_t G, H, enc;
 };
 
-AffinePlan plan_affine(const poly_csr *f, int64_t N, Layout &L)
+static AffinePlan plan_affine(const poly_csr *f, int64_t N, Layout &L)
 {
     AffinePlan a;
     const int n = f->nvars;
@@ -1975,7 +1975,7 @@ AffinePlan plan_affine(const poly_csr *f, int64_t N, Layout &L)
     return a;
 }
 
-poly_status check_affine(const poly_csr *f, const double *X, int64_t N, const double *D, double reg)
+static poly_status check_affine(const poly_csr *f, const double *X, int64_t N, const double *D, double reg)
 {
     poly_status st = check_eval(f, X, N, D);
     if (st != POLY_OK) return st;
@@ -2000,7 +2000,7 @@ struct MtimesPlan {
     int bits;
 };
 
-poly_status check_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t K, int64_t J)
+static poly_status check_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t K, int64_t J)
 {
     poly_status st;
     if ((st = check_csr(A, true)) != POLY_OK) return st;
@@ -2011,7 +2011,7 @@ poly_status check_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_
     return POLY_OK;
 }
 
-poly_status plan_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t K, int64_t J,
+static poly_status plan_mtimes(const poly_csr *A, const poly_csr *B, int64_t I, int64_t K, int64_t J,
                         std::vector<int64_t> &rph, MtimesPlan &m)
 {
     const int64_t Q = I * J;
@@ -2288,7 +2288,7 @@ struct BackwardPlan {
     int64_t nchunks = 0;
 };
 
-BackwardPlan plan_backward(const poly_csr *f, int64_t N, Layout &L)
+static BackwardPlan plan_backward(const poly_csr *f, int64_t N, Layout &L)
 {
     BackwardPlan b;
     const int n = f->nvars;
@@ -2315,7 +2315,7 @@ struct Backward2Plan {
     int64_t nchunks = 0;
 };
 
-Backward2Plan plan_backward2(const poly_csr *f, int64_t N, Layout &L)
+static Backward2Plan plan_backward2(const poly_csr *f, int64_t N, Layout &L)
 {
     Backward2Plan b;
     const int n = f->nvars;
@@ -2332,7 +2332,7 @@ Backward2Plan plan_backward2(const poly_csr *f, int64_t N, Layout &L)
 }
 
 // dC[t] = sum_pt gY[p(t)][pt] m_t(x_pt) over point chunks, then in chunk order
-void launch_dc(const poly_csr *f, const double *X, int64_t N, const double *gY, double *dC, uint64_t *senc,
+static void launch_dc(const poly_csr *f, const double *X, int64_t N, const double *gY, double *dC, uint64_t *senc,
                double *part, int cp, int64_t nchunks, hipStream_t s)
 {
     const int n = f->nvars;
