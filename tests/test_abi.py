@@ -28,6 +28,20 @@ def test_library_exports_every_declared_symbol():
     assert sorted(ph.EXPORTS) == syms
 
 
+def test_only_declared_entry_points_have_c_linkage():
+    """Every unmangled symbol the library defines is an entry point the
+    header declares: internal helpers keep internal linkage."""
+    import shutil
+    import subprocess
+    import paper_2604_06575_amd as ph
+    if not os.path.exists(ph.library_path()) or not shutil.which("nm"):
+        pytest.skip("library not built or nm missing")
+    out = subprocess.run(["nm", "-D", "--defined-only", ph.library_path()], capture_output=True, text=True).stdout
+    names = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    plain = {n for n in names if not n.startswith("_Z") and not n.startswith("__hip_cuid")}
+    assert plain == set(header_symbols())
+
+
 def test_strerror_and_host_argument_checks():
     import paper_2604_06575_amd as ph
     if not os.path.exists(ph.library_path()):
