@@ -172,6 +172,15 @@ struct WidePlan {
     int nwords = 0;
     int wlo[kMaxWords] = {}, whi[kMaxWords] = {}, wbits[kMaxWords] = {};
     size_t head = 0;
+    // two words: the low word's keys kept in input order (low), gathered
+    // into sorted order for the run heads, staged per run (st_low) and
+    // decoded with the top word at unpack: no exponent row is gathered
+    bool two = false;
+    size_t low = 0, st_low = 0;
+    // decoding: chunks of `chunk` digits (div = radix^chunk < 2^32)
+    int chunk = 1;
+    uint64_t div = 0, div_magic = 0;   // div_magic = floor((2^64 - 1) / div)
+    uint32_t digit_magic = 0;          // floor((2^32 - 1) / radix)
 };
 
 inline int64_t max_segment(const int64_t *rph, int64_t P)
@@ -314,6 +323,19 @@ bool plan_wide_words(WidePlan &w, Layout &L, int64_t P, int64_t R, int n, uint32
     w.soff = L.take(8 * w.nbm);
     w.ooff = L.take(8 * (w.nbm + 1));
     w.head = L.take((size_t)R);
+    w.two = w.nwords == 2 && radix > 1;
+    if (w.two) {
+        w.low = L.take(8 * (size_t)R);
+        w.st_low = L.take(8 * (size_t)R);
+        w.chunk = 1;
+        w.div = radix;
+        while (w.div * radix <= 0xffffffffull) {
+            w.div *= radix;
+            ++w.chunk;
+        }
+        w.div_magic = ~0ull / w.div;
+        w.digit_magic = 0xffffffffu / radix;
+    }
     return true;
 }
 
@@ -1227,33 +1249,61 @@ poly_status run_wide_words(const WidePlan &w, void *ws, const poly_csr *in, doub
     const int64_t scan_state = ceil_div(std::max<int64_t>(sort_bins() * nb, w.nbm), LB_TILE) + 2;
     clear_u64((unsigned long long *)tmp, scan_state, s);
     hipLaunchKernelGGL(k_ww_iota, dim3(grid1(R, 256)), dim3(256), 0, s, vcur, R);
+    uint64_t *st_ckey = at<uint64_t>(ws, w.st_ckey);
+    uint64_t *low_in = w.two ? at<uint64_t>(ws, w.low) : nullptr;
+    // words 0 and 1 come from one pass over the rows (word 1 parked in the
+    // staging buffer of the merge, free until then)
+    if (w.nwords >= 2)
+        hipLaunchKernelGGL(k_ww_word2, dim3(grid1(R, 256)), dim3(256), 0, s, in->exps, R, n, w.radix, in->max_exp,
+                           w.wlo[0], w.whi[0], w.wlo[1], w.whi[1], (int)(w.nwords == 2 && P > 1), in->row_ptr, P,
+                           kcur, low_in, st_ckey, status);
     for (int k = 0; k < w.nwords; ++k) {
         // the word's keys in input order (coalesced reads of the rows), then,
         // past the first word, gathered into the current order
         const bool top = k == w.nwords - 1;
-        uint64_t *dst = k == 0 ? kcur : knext;
-        hipLaunchKernelGGL(k_ww_word, dim3(grid1(R, 256)), dim3(256), 0, s, in->exps, R, n, w.radix, in->max_exp,
-                           w.wlo[k], w.whi[k], (int)(top && P > 1), in->row_ptr, P, dst, status);
+        if (k == 0 && w.nwords == 1)
+            hipLaunchKernelGGL(k_ww_word, dim3(grid1(R, 256)), dim3(256), 0, s, in->exps, R, n, w.radix,
+                               in->max_exp, w.wlo[0], w.whi[0], (int)(P > 1), in->row_ptr, P, kcur, status);
+        if (k >= 2)
+            hipLaunchKernelGGL(k_ww_word, dim3(grid1(R, 256)), dim3(256), 0, s, in->exps, R, n, w.radix,
+                               in->max_exp, w.wlo[k], w.whi[k], (int)(top && P > 1), in->row_ptr, P, knext, status);
         if (k > 0)
-            hipLaunchKernelGGL(k_ww_gather, dim3(grid1(R, 256)), dim3(256), 0, s, (const uint64_t *)knext,
-                               (const uint32_t *)vcur, R, kcur);
+            hipLaunchKernelGGL(k_ww_gather, dim3(grid1(R, 256)), dim3(256), 0, s,
+                               (const uint64_t *)(k == 1 ? st_ckey : knext), (const uint32_t *)vcur, R, kcur);
         radix_passes(kcur, knext, vcur, vnext, R, nb, w.wbits[k], hist, hoff, tmp, scan_state, status, s);
     }
     uint8_t *head = at<uint8_t>(ws, w.head);
-    hipLaunchKernelGGL(k_ww_heads, dim3(grid1(R, 256)), dim3(256), 0, s, (const uint64_t *)kcur,
-                       (const uint32_t *)vcur, R, in->exps, n, w.whi[w.nwords - 1], head);
+    uint64_t *low = nullptr, *st_low = nullptr;
+    if (w.two) {   // the low word in sorted order (knext is free after the passes)
+        low = knext;
+        st_low = at<uint64_t>(ws, w.st_low);
+        hipLaunchKernelGGL(k_ww_gather, dim3(grid1(R, 256)), dim3(256), 0, s, (const uint64_t *)low_in,
+                           (const uint32_t *)vcur, R, low);
+        hipLaunchKernelGGL(k_ww_heads2, dim3(grid1(R, 256)), dim3(256), 0, s, (const uint64_t *)kcur,
+                           (const uint64_t *)low, R, head);
+    } else {
+        hipLaunchKernelGGL(k_ww_heads, dim3(grid1(R, 256)), dim3(256), 0, s, (const uint64_t *)kcur,
+                           (const uint32_t *)vcur, R, in->exps, n, w.whi[w.nwords - 1], head);
+    }
     int64_t *cnt = at<int64_t>(ws, w.cnt), *soff = at<int64_t>(ws, w.soff), *ooff = at<int64_t>(ws, w.ooff);
     uint32_t *st_idx = at<uint32_t>(ws, w.st_key);
-    uint64_t *st_ckey = at<uint64_t>(ws, w.st_ckey);
     double *st_coef = at<double>(ws, w.st_coef);
     const int64_t mgrid = std::min<int64_t>(w.nbm, (int64_t)device_cus() * MG_BLOCKS_PER_CU);
     hipLaunchKernelGGL(k_ww_merge, dim3((unsigned)mgrid), dim3(MG_THREADS), 0, s, (const uint64_t *)kcur,
                        (const uint32_t *)vcur, (const uint8_t *)head, R, in->coefs, zero_tol, st_idx, st_ckey,
-                       st_coef, cnt, soff);
+                       st_coef, cnt, soff, (const uint64_t *)low, st_low);
     launch_scan(cnt, w.nbm, ooff, tmp, status, s, true);
-    hipLaunchKernelGGL(k_ww_compact, dim3((unsigned)w.nbm, MG_TILE / 256), dim3(256), 0, s, (const int64_t *)soff,
-                       (const int64_t *)cnt, (const int64_t *)ooff, (const uint32_t *)st_idx,
-                       (const double *)st_coef, in->exps, n, out->exps, out->coefs, out->capacity, status);
+    if (w.two)
+        hipLaunchKernelGGL(k_ww_compact2, dim3((unsigned)w.nbm, MG_TILE / 256), dim3(256), (size_t)256 * n, s,
+                           (const int64_t *)soff, (const int64_t *)cnt, (const int64_t *)ooff,
+                           (const uint64_t *)st_ckey, (const uint64_t *)st_low, (const double *)st_coef, n,
+                           w.whi[1], (uint64_t)w.radix, w.chunk, w.div, w.div_magic, w.digit_magic, out->exps,
+                           out->coefs, out->capacity, status);
+    else
+        hipLaunchKernelGGL(k_ww_compact, dim3((unsigned)w.nbm, MG_TILE / 256), dim3(256), 0, s,
+                           (const int64_t *)soff, (const int64_t *)cnt, (const int64_t *)ooff,
+                           (const uint32_t *)st_idx, (const double *)st_coef, in->exps, n, out->exps, out->coefs,
+                           out->capacity, status);
     hipLaunchKernelGGL(k_ws_rowptr, dim3(grid1(P + 1, 256)), dim3(256), 0, s, P, w.span, (const uint64_t *)kcur,
                        R, (const int64_t *)soff, (const int64_t *)cnt, (const int64_t *)ooff, w.nbm,
                        (const uint64_t *)st_ckey, out->row_ptr);

@@ -212,7 +212,15 @@ __global__ void k_ww_heads(const uint64_t *keys, const uint32_t *vals, int64_t R
                            uint8_t *head);
 __global__ void k_ww_merge(const uint64_t *keys, const uint32_t *vals, const uint8_t *head, int64_t R,
                            const double *coefs, double tol, uint32_t *st_idx, uint64_t *st_ckey, double *st_coef,
-                           int64_t *seg_count, int64_t *stage_off);
+                           int64_t *seg_count, int64_t *stage_off, const uint64_t *low, uint64_t *st_low);
+__global__ void k_ww_word2(const uint8_t *exps, int64_t T, int n, uint32_t radix, int max_exp, int lo0, int hi0,
+                           int lo1, int hi1, int with_poly, const int64_t *row_ptr, int64_t P, uint64_t *keys0,
+                           uint64_t *copy0, uint64_t *keys1, int32_t *status);
+__global__ void k_ww_heads2(const uint64_t *top, const uint64_t *low, int64_t R, uint8_t *head);
+__global__ void k_ww_compact2(const int64_t *stage_off, const int64_t *seg_count, const int64_t *out_off,
+                              const uint64_t *st_top, const uint64_t *st_low, const double *st_coef, int n, int split,
+                              uint64_t radix, int chunk, uint64_t div, uint64_t div_magic, uint32_t digit_magic,
+                              uint8_t *out_exps, double *out_coefs, int64_t capacity, int32_t *status);
 __global__ void k_ww_compact(const int64_t *stage_off, const int64_t *seg_count, const int64_t *out_off,
                              const uint32_t *st_idx, const double *st_coef, const uint8_t *exps, int n,
                              uint8_t *out_exps, double *out_coefs, int64_t capacity, int32_t *status);

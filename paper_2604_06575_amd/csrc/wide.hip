@@ -31,12 +31,43 @@
 
 namespace polyhip {
 
+namespace {
+
+// The polynomial holding term t (the last p < P with row_ptr[p] <= t) for
+// the consecutive terms t of one block: thread 0 binary-searches the block's
+// first term t0, then each thread walks forward from there (a block of terms
+// usually lies in one or two polynomials), instead of every thread walking
+// a dependent chain of loads from the top.  Every thread of the block calls
+// it; the result is meaningful for t < T only.
+__device__ inline int64_t block_poly_of(const int64_t *__restrict__ row_ptr, int64_t P, int64_t t0, int64_t t,
+                                        int64_t T)
+{
+    __shared__ int64_t s_a;
+    if (threadIdx.x == 0) {
+        int64_t a = 0, b = P;
+        while (b - a > 1) {
+            const int64_t mid = (a + b) >> 1;
+            if (row_ptr[mid] <= t0) a = mid;
+            else b = mid;
+        }
+        s_a = a;
+    }
+    __syncthreads();
+    int64_t a = s_a;
+    if (t < T)
+        while (a + 1 < P && row_ptr[a + 1] <= t) ++a;
+    return a;
+}
+
+}  // namespace
+
 // span = r^n, or 0 for a single polynomial
 __global__ void k_ws_keys(const uint8_t *__restrict__ exps, int64_t T, int n, uint32_t radix, int max_exp,
                           const int64_t *__restrict__ row_ptr, int64_t P, uint64_t span, uint64_t *__restrict__ keys,
                           uint32_t *__restrict__ vals, int32_t *status)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x, t = t0 + threadIdx.x;
+    const int64_t lo = block_poly_of(row_ptr, P, t0, t, T);   // the polynomial holding term t
     if (t >= T) return;
     const uint8_t *row = exps + t * n;
     uint64_t k = 0;
@@ -45,13 +76,6 @@ __global__ void k_ws_keys(const uint8_t *__restrict__ exps, int64_t T, int n, ui
         const uint32_t e = row[i];
         bad |= (int)(e > (uint32_t)max_exp);
         k = k * radix + e;
-    }
-    // the polynomial holding term t: the last p < P with row_ptr[p] <= t
-    int64_t lo = 0, hi = P;
-    while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (row_ptr[mid] <= t) lo = mid;
-        else hi = mid;
     }
     keys[t] = (uint64_t)lo * span + k;
     vals[t] = (uint32_t)t;
@@ -246,19 +270,11 @@ __global__ void k_ww_word(const uint8_t *__restrict__ exps, int64_t T, int n, ui
                           int hi, int with_poly, const int64_t *__restrict__ row_ptr, int64_t P,
                           uint64_t *__restrict__ keys, int32_t *status)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x, t = t0 + threadIdx.x;
+    uint64_t k = 0;
+    if (with_poly) k = (uint64_t)block_poly_of(row_ptr, P, t0, t, T);
     if (t >= T) return;
     const uint8_t *row = exps + t * n;
-    uint64_t k = 0;
-    if (with_poly) {
-        int64_t a = 0, b = P;   // the last p with row_ptr[p] <= t (neighbouring threads share the path)
-        while (b - a > 1) {
-            const int64_t mid = (a + b) >> 1;
-            if (row_ptr[mid] <= t) a = mid;
-            else b = mid;
-        }
-        k = (uint64_t)a;
-    }
     int bad = 0;
     if ((n & 3) == 0) {   // 4-byte aligned rows: one load per four exponents
         const uint32_t *row4 = reinterpret_cast<const uint32_t *>(row);
@@ -282,6 +298,61 @@ __global__ void k_ww_word(const uint8_t *__restrict__ exps, int64_t T, int n, ui
     }
     keys[t] = k;
     if (bad) set_status(status, POLY_ERR_EXPONENT);
+}
+
+// The two least significant words in one pass over the rows: keys0[t] for
+// variables [lo0, hi0) and keys1[t] for [lo1, hi1) (with the polynomial
+// index when with_poly); copy0, when given, receives keys0 again.
+__global__ void k_ww_word2(const uint8_t *__restrict__ exps, int64_t T, int n, uint32_t radix, int max_exp,
+                           int lo0, int hi0, int lo1, int hi1, int with_poly, const int64_t *__restrict__ row_ptr,
+                           int64_t P, uint64_t *__restrict__ keys0, uint64_t *__restrict__ copy0,
+                           uint64_t *__restrict__ keys1, int32_t *status)
+{
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x, t = t0 + threadIdx.x;
+    uint64_t k0 = 0, k1 = 0;
+    if (with_poly) k1 = (uint64_t)block_poly_of(row_ptr, P, t0, t, T);
+    if (t >= T) return;
+    const uint8_t *row = exps + t * n;
+    int bad = 0;
+    // variables lo1 < hi1 <= lo0 < hi0: word 1 first, then word 0
+    auto digits = [&](int lo, int hi, uint64_t &k) {
+        if ((n & 3) == 0) {
+            const uint32_t *row4 = reinterpret_cast<const uint32_t *>(row);
+            uint32_t word = 0;
+            int wi = -1;
+            for (int v = lo; v < hi; ++v) {
+                if ((v >> 2) != wi) {
+                    wi = v >> 2;
+                    word = row4[wi];
+                }
+                const uint32_t e = (word >> (8 * (v & 3))) & 0xffu;
+                bad |= (int)(e > (uint32_t)max_exp);
+                k = k * radix + e;
+            }
+        } else {
+            for (int v = lo; v < hi; ++v) {
+                const uint32_t e = row[v];
+                bad |= (int)(e > (uint32_t)max_exp);
+                k = k * radix + e;
+            }
+        }
+    };
+    digits(lo1, hi1, k1);
+    digits(lo0, hi0, k0);
+    keys0[t] = k0;
+    if (copy0) copy0[t] = k0;
+    keys1[t] = k1;
+    if (bad) set_status(status, POLY_ERR_EXPONENT);
+}
+
+// head[i] for a two-word key: element i starts a run unless both its top
+// and its low word equal element i - 1's.
+__global__ void k_ww_heads2(const uint64_t *__restrict__ top, const uint64_t *__restrict__ low, int64_t R,
+                            uint8_t *__restrict__ head)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= R) return;
+    head[i] = (uint8_t)(i == 0 || top[i] != top[i - 1] || low[i] != low[i - 1]);
 }
 
 // dst[i] = src[vals[i]]: a word's keys, built in input order, put in the
@@ -323,14 +394,16 @@ __global__ void k_ww_heads(const uint64_t *__restrict__ keys, const uint32_t *__
 
 // As k_ws_merge, with the runs given by head flags: each run is summed left
 // to right in one lane; a kept run stages its first element's term index
-// (st_idx), top word (st_ckey) and sum.
+// (st_idx; for two-word keys the low word st_low instead), top word
+// (st_ckey) and sum.
 __global__ void __launch_bounds__(MG_THREADS) k_ww_merge(const uint64_t *__restrict__ keys,
                                                         const uint32_t *__restrict__ vals,
                                                         const uint8_t *__restrict__ head, int64_t R,
                                                         const double *__restrict__ coefs, double tol,
                                                         uint32_t *__restrict__ st_idx, uint64_t *__restrict__ st_ckey,
                                                         double *__restrict__ st_coef, int64_t *seg_count,
-                                                        int64_t *stage_off)
+                                                        int64_t *stage_off, const uint64_t *__restrict__ low,
+                                                        uint64_t *__restrict__ st_low)
 {
     __shared__ double s_c[MG_TILE + GS_HALO];
     __shared__ uint8_t s_h[MG_TILE + GS_HALO];
@@ -398,9 +471,10 @@ __global__ void __launch_bounds__(MG_THREADS) k_ww_merge(const uint64_t *__restr
         for (int q = 0; q < MI; ++q) {
             if ((kflags >> (16 * q)) & 1u) {
                 const int64_t d = t0 + tot + (int64_t)((kpre >> (16 * q)) & 0xffffu);
-                st_idx[d] = vals[t0 + hl_k[q]];
                 st_ckey[d] = keys[t0 + hl_k[q]];
                 st_coef[d] = hs[q];
+                if (low) st_low[d] = low[t0 + hl_k[q]];
+                else st_idx[d] = vals[t0 + hl_k[q]];
             }
             tot += (int64_t)((ktot >> (16 * q)) & 0xffffu);
         }
@@ -501,6 +575,86 @@ __global__ void __launch_bounds__(256) k_ww_compact(const int64_t *__restrict__ 
             const uint32_t t = (uint32_t)__shfl((int)my_idx, (int)(r < kWave ? r : kWave - 1), kWave);
             if (d < total) out[d] = exps[(int64_t)t * n + c];
         }
+    }
+}
+
+// Unpack of the staged runs of merge tile blockIdx.x for a two-word key:
+// the exponents are the mixed-radix digits of the top word (variables
+// [0, split), the polynomial index above them) and of the low word
+// (variables [split, n)), peeled least significant first by multiply-high
+// divisions (each quotient from floor((2^w - 1) / divisor) is exact or one
+// short, then corrected).  Each thread writes its row into the wave's LDS buffer; the
+// wave then stores its 64 rows as one contiguous run (4-byte words when
+// rows are 4-byte aligned).  Block (b, y) takes rows y * 256 .. + 255 of
+// the tile.  Dynamic LDS: 256 * n bytes.
+__global__ void __launch_bounds__(256) k_ww_compact2(const int64_t *__restrict__ stage_off,
+                                                     const int64_t *__restrict__ seg_count,
+                                                     const int64_t *__restrict__ out_off,
+                                                     const uint64_t *__restrict__ st_top,
+                                                     const uint64_t *__restrict__ st_low,
+                                                     const double *__restrict__ st_coef, int n, int split,
+                                                     uint64_t radix, int chunk, uint64_t div, uint64_t div_magic,
+                                                     uint32_t digit_magic, uint8_t *__restrict__ out_exps,
+                                                     double *__restrict__ out_coefs, int64_t capacity,
+                                                     int32_t *status)
+{
+    extern __shared__ uint8_t s_rows[];
+    const int64_t b = blockIdx.x;
+    const int64_t cnt = seg_count[b], src = stage_off[b], dst = out_off[b];
+    if (threadIdx.x == 0 && blockIdx.y == 0 && dst + cnt > capacity) set_status(status, POLY_ERR_CAPACITY);
+    const int64_t end = dst + cnt < capacity ? dst + cnt : capacity;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int64_t r0 = dst + (int64_t)blockIdx.y * blockDim.x + (int64_t)wave * kWave;
+    if (r0 >= end) return;
+    const int rows = (int)(end - r0 < kWave ? end - r0 : kWave);
+    uint8_t *buf = s_rows + (size_t)wave * kWave * n;
+    // digits least significant first: a chunk of `chunk` digits (radix^chunk
+    // below 2^32) is split off with one 64-bit multiply-high division by
+    // div = radix^chunk, then its digits with 32-bit ones.  The last chunk is
+    // split off too: the top word holds the polynomial index above its digits.
+    const uint32_t r32 = (uint32_t)radix;
+    auto digits = [&](uint64_t x, int v_hi, int v_lo, uint8_t *row) {
+        int v = v_hi - 1;
+        while (v >= v_lo) {
+            uint64_t q = __umul64hi(x, div_magic);
+            uint64_t rem = x - q * div;
+            if (rem >= div) {
+                ++q;
+                rem -= div;
+            }
+            uint32_t part = (uint32_t)rem;
+            x = q;
+            const int e = v - v_lo + 1 < chunk ? v - v_lo + 1 : chunk;
+            for (int j = 0; j < e; ++j, --v) {
+                uint32_t dq = __umulhi(part, digit_magic);
+                uint32_t dr = part - dq * r32;
+                if (dr >= r32) {
+                    ++dq;
+                    dr -= r32;
+                }
+                row[v] = (uint8_t)dr;
+                part = dq;
+            }
+        }
+    };
+    if (lane < rows) {
+        const int64_t k = src + (r0 - dst) + lane;
+        out_coefs[r0 + lane] = st_coef[k];
+        uint8_t *row = buf + lane * n;
+        digits(st_low[k], n, split, row);
+        digits(st_top[k], split, 0, row);   // the polynomial index above them is left over
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint32_t total = (uint32_t)rows * (uint32_t)n;
+    if ((n & 3) == 0) {
+        const uint32_t *b4 = reinterpret_cast<const uint32_t *>(buf);
+        uint32_t *o4 = reinterpret_cast<uint32_t *>(out_exps + r0 * n);
+        for (uint32_t d = lane; d < total / 4; d += kWave) o4[d] = b4[d];
+    } else {
+        uint8_t *o = out_exps + r0 * n;
+        for (uint32_t d = lane; d < total; d += kWave) o[d] = buf[d];
     }
 }
 
