@@ -145,6 +145,7 @@ __global__ void k_form_rowptr(FormArgs A, const int64_t *off)
 __global__ void __launch_bounds__(JAC_THREADS) k_form_write(FormArgs A, const int64_t *off)
 {
     __shared__ int s_wc[JAC_THREADS / kWave][DF_MAX_GROUPS];
+    __shared__ uint8_t s_map[JAC_THREADS / kWave][kWave];   // survivor rank -> lane, per wave
     __shared__ int64_t s_run[DF_MAX_GROUPS];
     __shared__ uint32_t s_rows[JAC_THREADS * ROW_STAGE_MAX_N / 4];
     const int64_t item = blockIdx.x;
@@ -185,33 +186,43 @@ __global__ void __launch_bounds__(JAC_THREADS) k_form_write(FormArgs A, const in
             const int m = valid ? group_mult(A, row, p, g) : 0;
             const unsigned long long bal = __ballot(m > 0);
             if (bal == 0) continue;
-            int64_t o = s_run[g] + __popcll(bal & lt);
-            for (int q = 0; q < w; ++q) o += s_wc[q][g];
+            // the wave's survivors take consecutive output slots from o0
+            int64_t o0 = s_run[g];
+            for (int q = 0; q < w; ++q) o0 += s_wc[q][g];
+            const int rank = __popcll(bal & lt);
+            const int nsurv = __popcll(bal);
             if (m > 0) {
+                const int64_t o = o0 + rank;
                 if (o < A.capacity) A.out_coefs[o] = A.keep_coefs ? c : c * (double)m;
                 else set_status(A.status, A.overflow_code);
+                s_map[w][rank] = (uint8_t)lane;
             }
-            // the survivors' rows, one at a time, spread over the wave's lanes
-            // (exponent j decremented: it is >= 1 in a survivor)
-            for (unsigned long long rem = bal; rem; rem &= rem - 1) {
-                const int b = __builtin_ctzll(rem);
-                const int64_t ob = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)o, b) |
-                                   ((int64_t)__builtin_amdgcn_readlane((int)(uint32_t)(o >> 32), b) << 32);
-                if (ob >= A.capacity) continue;
-                const uint8_t *src = rows + (w * kWave + b) * n;
-                uint8_t *dst = A.out_exps + ob * n;
-                if (words) {
-                    const uint32_t *s32 = reinterpret_cast<const uint32_t *>(src);
-                    uint32_t *d32 = reinterpret_cast<uint32_t *>(dst);
-                    for (int v = lane; v < (n >> 2); v += kWave) {
-                        uint32_t x = s32[v];
-                        if (v == (j >> 2)) x -= 1u << (8 * (j & 3));
-                        d32[v] = x;
-                    }
-                } else {
-                    for (int v = lane; v < n; v += kWave) dst[v] = (uint8_t)(src[v] - (v == j ? 1 : 0));
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // their rows (exponent j decremented: it is >= 1 in a survivor) as
+            // one contiguous output run, lane by lane, rows past the capacity
+            // dropped
+            const int64_t keep = o0 >= A.capacity ? 0 : (A.capacity - o0 < nsurv ? A.capacity - o0 : nsurv);
+            if (words) {
+                const uint32_t nw = (uint32_t)n >> 2;
+                uint32_t *d32 = reinterpret_cast<uint32_t *>(A.out_exps + o0 * n);
+                for (uint32_t d = lane; d < (uint32_t)keep * nw; d += kWave) {
+                    const uint32_t r = d / nw, v = d - r * nw;
+                    const uint32_t *s32 = reinterpret_cast<const uint32_t *>(rows + (w * kWave + s_map[w][r]) * n);
+                    uint32_t x = s32[v];
+                    if (v == (uint32_t)(j >> 2)) x -= 1u << (8 * (j & 3));
+                    d32[d] = x;
+                }
+            } else {
+                uint8_t *d8 = A.out_exps + o0 * n;
+                for (uint32_t d = lane; d < (uint32_t)keep * (uint32_t)n; d += kWave) {
+                    const uint32_t r = d / (uint32_t)n, v = d - r * (uint32_t)n;
+                    const uint8_t *src = rows + (w * kWave + s_map[w][r]) * n;
+                    d8[d] = (uint8_t)(src[v] - (v == (uint32_t)j ? 1 : 0));
                 }
             }
+            __builtin_amdgcn_wave_barrier();   // s_map is rewritten by the next group
         }
         __syncthreads();
         for (int64_t g = threadIdx.x; g < A.ngroups; g += JAC_THREADS) {
