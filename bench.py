@@ -305,6 +305,10 @@ def bench_batch(args):
     simp_bytes = (T_in + T_s) * (wl.n + 8)
     jd = J.exps[:T_j].sum(1, dtype=torch.int64)
     eval_flops = float((jd + 2).sum().item()) * X.shape[0]
+    # the kernel reads a term's factors from the LDS point tile in chunks of
+    # four (padding chunks point at a row of ones): 4 ceil(d / 4) 8-byte reads
+    # per term and point
+    lds_bytes = float((4 * ((jd + 3) // 4)).sum().item()) * 8.0 * X.shape[0]
     return {"entries": 4096, "raw_terms": T_in, "simplified_terms": T_s, "jacobian_terms": T_j, "points": X.shape[0],
             "simplify_ms": t_simp * 1e3, "simplify_terms_per_s": T_in / t_simp,
             "simplify_gbps": simp_bytes / t_simp / 1e9, "simplify_hbm_frac": simp_bytes / t_simp / 8e12,
@@ -312,6 +316,7 @@ def bench_batch(args):
             "jacobian_eval_ms": t_eval * 1e3, "jacobian_eval_term_points_per_s": term_points / t_eval,
             "jacobian_eval_fp64_tflops": eval_flops / t_eval / 1e12,
             "jacobian_eval_fp64_frac": eval_flops / t_eval / 78.6e12,
+            "jacobian_eval_lds_tbps": lds_bytes / t_eval / 1e12,
             "grad_fused_ms": t_grad * 1e3, **bench_plan(b, X),
             "note": "simplify/jacobian times include the host readback of the output row pointer"}
 
