@@ -5,7 +5,8 @@ bit (row pointers, exponent rows, coefficients) and report the same device
 status.  Two calls in a row share the library's fixed scratch: a batch that
 takes the device-wide path (an entry above the wide threshold), then a smaller
 batch of small entries that takes the per-entry path, so the second call
-starts from the scratch the first one left behind.  A third call declares an
+starts from the scratch the first one left behind; a third batch in 40
+variables takes the sort over key words.  A third call declares an
 exponent bound below a stored exponent and must report POLY_ERR_EXPONENT."""
 import sys
 
@@ -66,7 +67,9 @@ def test_noalloc_matches_simplify_on_two_calls(ph):
     small = W.batch_matrix(seed=W.SEED_BASE + 72, entries=300, tmin=1, tmax=600, npts=0)
     assert small.row_ptr[-1] < big.row_ptr[-1]
     assert int(np.diff(small.row_ptr).max()) < wide_min, "second call must take the per-entry path"
-    for name, wl, tol in (("wide", big, 0.0), ("per-entry", small, 0.5)):
+    # then 40 variables of 3-bit fields (120 bits): the sort over key words
+    words = W.batch_matrix(seed=W.SEED_BASE + 74, entries=30, n=40, tmin=5, tmax=3000, npts=0)
+    for name, wl, tol in (("wide", big, 0.0), ("per-entry", small, 0.5), ("key words", words, 0.0)):
         say(f"noalloc {name}: {wl.row_ptr.shape[0] - 1} entries, {int(wl.row_ptr[-1])} terms, tol {tol}")
         ref, out, st = _both(ph, _batch(ph, wl), tol)
         assert st == 0
