@@ -327,7 +327,8 @@ poly_status poly_affine_normal(const poly_csr *f, const double *X, int64_t N, do
  * one per step of the q + 1 solves; the third-derivative contractions per
  * point are q.  Matrix-free: Hessian-vector products and third derivatives
  * are taken per monomial, the n x n Hessian is never formed.
- * One polynomial, 2 <= n <= 255, q >= 1, tol >= 0, maxit >= 0, reg >= 0
+ * One polynomial, 2 <= n <= 255, q >= 1, tol >= 0, maxit >= 0 with
+ * (q + 1) * maxit + 1 <= 2^31 - 1 (the count fits int32), reg >= 0
  * (else POLY_ERR_ARG); terms of total degree above 12 give the device
  * status POLY_ERR_UNSUPPORTED.  g = 0 gives non-finite output for that
  * point.  X [N*n], D [N*n], gnorm [N] (required). */

@@ -2280,6 +2280,7 @@ poly_status poly_affine_normal_stochastic(const poly_csr *f, const double *X, in
     if (q < 1 || (N > 0 && !Z) || (per_point != 0 && per_point != 1) || !(tol >= 0.0) || maxit < 0 ||
         N > INT32_MAX || (N > 0 && !gnorm))
         return POLY_ERR_ARG;
+    if (((int64_t)q + 1) * maxit + 1 > INT32_MAX) return POLY_ERR_ARG;   // hv_evals must fit int32
     size_t need = 0;
     (void)poly_affine_normal_stochastic_workspace(f, N, &need);
     if (!ws || ws_bytes < need) return POLY_ERR_WORKSPACE;

@@ -101,7 +101,8 @@ def test_strerror_and_host_argument_checks():
     D = np.zeros(40)
     g = np.zeros(10)
     p = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
-    for q, per_point, tol, maxit in ((0, 0, 1e-4, 10), (2, 2, 1e-4, 10), (2, 0, -1.0, 10), (2, 0, 1e-4, -1)):
+    for q, per_point, tol, maxit in ((0, 0, 1e-4, 10), (2, 2, 1e-4, 10), (2, 0, -1.0, 10), (2, 0, 1e-4, -1),
+                                     (1 << 20, 0, 1e-4, 1 << 12)):
         assert L.poly_affine_normal_stochastic(ctypes.byref(c), p(X), 10, p(Z), q, per_point, 1e-6, tol, maxit,
                                                p(D), p(g), None, None, 0, None) == 1
 
