@@ -276,7 +276,29 @@ def bench_eval(args):
                             "dC_mfma_frac": flops / (k_ms_b / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
                             "dX_mfma_frac": flops / t_dx / 1e12 / FP64_PEAK_TFLOPS,
                             "flops_note": "dC = gY V^T and W = C^T gY are 2 P K N flops each"}
-    del gY
+    # split dC (BF16 digits of gY and V^T per 128-point block), against the
+    # FP64 kernel over every output, condition-scaled by sum_pt |gY v_k|
+    S = args.nslices
+    fn_s = lambda: ph.eval_dense_backward(basis, C, X, gY, want_dX=False,  # noqa: E731
+                                          prec=ph.POLY_SPLIT_BF16, nslices=S)
+    t_s, _ = time_events(fn_s, 1, 1)
+    k_ms_s, _ = kernel_ms(ph.TIMING_DENSE, fn_s, 1)
+    pairs = S * (S + 1) // 2
+    dCs = fn_s()[0]
+    d = (dCs - ph.eval_dense_backward(basis, C, X, gY, want_dX=False)[0]).abs()
+    del dCs
+    A = ph.eval_dense_backward(basis, C, X.abs(), gY.abs(), want_dX=False)[0]
+    cond = d / A
+    del A
+    res["backward_split_dC"] = {
+        "nslices": S, "ms": t_s * 1e3, "kernel_ms": k_ms_s,
+        "kernel_mfma_frac": flops * pairs / (k_ms_s / 1e3) / 1e12 / BF16_PEAK_TFLOPS,
+        "fp64_equiv_speedup_vs_fp64_kernel": k_ms_b / k_ms_s,
+        "max_cond_scaled_err_vs_fp64_gpu": float(cond.max().item()),
+        "frac_cond_scaled_err_above_1e-10": float((cond > 1e-10).double().mean().item()),
+        "note": "every output; sum_pt |gY v_k| from the FP64 kernel on |gY|, |x| (|C| does not enter dC)",
+    }
+    del d, cond, gY
     res["workload"] = {"polys": P, "monomials": K, "points": N, "n": wl.n, "degree": 4}
     return res
 

@@ -635,8 +635,11 @@ def hess(b: Batch, X: torch.Tensor, check: bool = False, prec: int = POLY_FP64, 
 
 
 def eval_backward(b: Batch, X: torch.Tensor, gY: torch.Tensor, want_dX: bool = True, want_dC: bool = True,
-                  check: bool = False):
-    """Reverse mode of eval: (dX [N, n], dC [T])."""
+                  check: bool = False, prec: int = POLY_FP64, nslices: int = 5):
+    """Reverse mode of eval: (dX [N, n], dC [T]).  prec=POLY_SPLIT_BF16 takes a
+    batch that is one shared monomial set (equal exponent rows in every
+    polynomial) through the dense reverse mode: dC on ``nslices`` BF16 digits,
+    dX in FP64 (check=True reads back the shared-rows check)."""
     L = lib()
     X = X.contiguous()
     gY = gY.contiguous()
@@ -647,12 +650,12 @@ def eval_backward(b: Batch, X: torch.Tensor, gY: torch.Tensor, want_dX: bool = T
         raise ValueError(f"gY must be float64 [{b.npolys}, {N}], got {gY.dtype} {tuple(gY.shape)}")
     _check_device("gY", gY, b.coefs.device)
     ws_bytes = ctypes.c_size_t()
-    _check(L.poly_eval_backward_workspace(ctypes.byref(cin), N, POLY_FP64, 5, ctypes.byref(ws_bytes)),
+    _check(L.poly_eval_backward_workspace(ctypes.byref(cin), N, prec, nslices, ctypes.byref(ws_bytes)),
            "poly_eval_backward_workspace")
     ws = _workspace(ws_bytes.value, b.coefs.device)
     dX = torch.empty((N, b.n), dtype=torch.float64, device=b.coefs.device) if want_dX else None
     dC = torch.empty(b.nterms, dtype=torch.float64, device=b.coefs.device) if want_dC else None
-    _check(L.poly_eval_backward(ctypes.byref(cin), _ptr(X), N, _ptr(gY), _ptr(dX), _ptr(dC), POLY_FP64, 5,
+    _check(L.poly_eval_backward(ctypes.byref(cin), _ptr(X), N, _ptr(gY), _ptr(dX), _ptr(dC), prec, nslices,
                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "poly_eval_backward")
     if check:
         _check(L.poly_read_status(ctypes.c_void_p(ws.data_ptr()), _stream()), "poly_eval_backward")
@@ -807,8 +810,11 @@ def eval_dense(basis: torch.Tensor, C: torch.Tensor, X: torch.Tensor, prec: int 
 
 
 def eval_dense_backward(basis: torch.Tensor, C: torch.Tensor, X: torch.Tensor, gY: torch.Tensor,
-                        want_dC: bool = True, want_dX: bool = True, max_exp: int | None = None):
-    """Reverse mode of eval_dense (FP64 MFMA): (dC [P, K], dX [N, n])."""
+                        want_dC: bool = True, want_dX: bool = True, max_exp: int | None = None,
+                        prec: int = POLY_FP64, nslices: int = 5):
+    """Reverse mode of eval_dense: (dC [P, K], dX [N, n]).  dX runs on FP64
+    MFMA; dC on FP64 MFMA or, with prec=POLY_SPLIT_BF16, on ``nslices`` BF16
+    digits per operand (the forward split scheme, contraction over points)."""
     L = lib()
     basis, C, X, gY = basis.contiguous(), C.contiguous(), X.contiguous(), gY.contiguous()
     K, n = basis.shape
@@ -822,14 +828,14 @@ def eval_dense_backward(basis: torch.Tensor, C: torch.Tensor, X: torch.Tensor, g
         raise ValueError(f"gY must be float64 [{P}, {N}]")
     _check_device("gY", gY, C.device)
     ws_bytes = ctypes.c_size_t()
-    _check(L.poly_eval_dense_backward_workspace(n, K, P, N, POLY_FP64, 5, ctypes.byref(ws_bytes)),
+    _check(L.poly_eval_dense_backward_workspace(n, K, P, N, prec, nslices, ctypes.byref(ws_bytes)),
            "poly_eval_dense_backward_workspace")
     ws = _workspace(ws_bytes.value, C.device)
     dC = torch.empty((P, K), dtype=torch.float64, device=C.device) if want_dC else None
     dX = torch.empty((N, n), dtype=torch.float64, device=C.device) if want_dX else None
     me = int(max_exp) if max_exp is not None else 255
     _check(L.poly_eval_dense_backward(n, K, _ptr(basis), me, P, _ptr(C), N, _ptr(X), _ptr(gY), _ptr(dC), _ptr(dX),
-                                      POLY_FP64, 5, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()),
+                                      prec, nslices, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()),
            "poly_eval_dense_backward")
     return dC, dX
 
@@ -840,11 +846,13 @@ def eval_dense_backward(basis: torch.Tensor, C: torch.Tensor, X: torch.Tensor, g
 class PolyEvalDense(torch.autograd.Function):
     """Y = C V for P polynomials over one shared monomial set, differentiable
     in (C, X): the forward is eval_dense (FP64 or split BF16), the backward
-    the FP64 MFMA reverse mode (eval_dense_backward)."""
+    eval_dense_backward at the same precision (dC split with the forward's
+    digit count, dX FP64)."""
 
     @staticmethod
     def forward(ctx, C, X, basis, prec: int = POLY_FP64, nslices: int = 5):
         ctx.save_for_backward(C, X, basis)
+        ctx.prec, ctx.nslices = prec, nslices
         return eval_dense(basis, C.detach(), X.detach(), prec=prec, nslices=nslices)
 
     @staticmethod
@@ -852,7 +860,8 @@ class PolyEvalDense(torch.autograd.Function):
     def backward(ctx, gY):
         C, X, basis = ctx.saved_tensors
         dC, dX = eval_dense_backward(basis, C.detach(), X.detach(), gY.detach(),
-                                     want_dC=ctx.needs_input_grad[0], want_dX=ctx.needs_input_grad[1])
+                                     want_dC=ctx.needs_input_grad[0], want_dX=ctx.needs_input_grad[1],
+                                     prec=ctx.prec, nslices=ctx.nslices)
         return dC, dX, None, None, None
 
 class PolyEval(torch.autograd.Function):

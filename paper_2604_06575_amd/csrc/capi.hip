@@ -61,10 +61,11 @@ poly_status dense_workspace(int32_t n, int64_t K, int64_t P, int64_t N, poly_pre
 poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp, int64_t P, const double *C,
                       int64_t N, const double *X, double *Y, poly_prec prec, int32_t nslices, void *ws,
                       size_t ws_bytes, hipStream_t stream, int64_t ys);
-poly_status dense_bwd_workspace(int32_t n, int64_t K, int64_t P, int64_t N, size_t *ws_bytes);
+poly_status dense_bwd_workspace(int32_t n, int64_t K, int64_t P, int64_t N, poly_prec prec, int32_t nslices,
+                                size_t *ws_bytes);
 poly_status dense_bwd_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp, int64_t P, const double *C,
-                          int64_t N, const double *X, const double *gY, double *dC, double *dX, void *ws,
-                          size_t ws_bytes, hipStream_t s);
+                          int64_t N, const double *X, const double *gY, double *dC, double *dX, poly_prec prec,
+                          int32_t nslices, void *ws, size_t ws_bytes, hipStream_t s);
 }  // namespace polyhip
 
 namespace {
@@ -2404,12 +2405,32 @@ static void launch_dc(const poly_csr *f, const double *X, int64_t N, const doubl
 
 }  // namespace
 
+namespace {
+
+// prec = POLY_SPLIT_BF16 on the reverse mode: a shared monomial set stored
+// as CSR (as for the forward) runs the dense reverse mode, dC on the split
+// scheme and dX in FP64; K = the common row length, or -1 if they differ
+static int64_t shared_row_length(const poly_csr *f)
+{
+    const int64_t P = f->npolys;
+    const int64_t K = P > 0 ? f->row_ptr_host[1] : 0;
+    for (int64_t p = 1; p <= P; ++p)
+        if (f->row_ptr_host[p] - f->row_ptr_host[p - 1] != K) return -1;
+    return K;
+}
+
+}  // namespace
+
 poly_status poly_eval_backward_workspace(const poly_csr *f, int64_t N, poly_prec prec, int32_t nslices, size_t *ws_bytes)
 {
     poly_status st = check_eval(f, nullptr, 0, nullptr);
     if (st != POLY_OK) return st;
     if (!ws_bytes || N < 0) return POLY_ERR_ARG;
-    if (prec == POLY_SPLIT_BF16) return POLY_ERR_UNSUPPORTED;
+    if (prec == POLY_SPLIT_BF16) {
+        const int64_t K = shared_row_length(f);
+        if (K < 0) return POLY_ERR_UNSUPPORTED;
+        return dense_bwd_workspace(f->nvars, K, f->npolys, N, prec, nslices, ws_bytes);
+    }
     if (prec != POLY_FP64) return POLY_ERR_ARG;
     (void)nslices;
     Layout L;
@@ -2423,7 +2444,22 @@ poly_status poly_eval_backward(const poly_csr *f, const double *X, int64_t N, co
 {
     poly_status st = check_eval(f, X, N, gY);
     if (st != POLY_OK) return st;
-    if (prec == POLY_SPLIT_BF16) return POLY_ERR_UNSUPPORTED;
+    if (prec == POLY_SPLIT_BF16) {
+        const int64_t K = shared_row_length(f);
+        if (K < 0) return POLY_ERR_UNSUPPORTED;
+        hipStream_t s = (hipStream_t)stream;
+        st = dense_bwd_run(f->nvars, K, f->exps, f->max_exp, f->npolys, f->coefs, N, X, gY, dC, dX, prec, nslices,
+                           ws, ws_bytes, s);
+        if (st != POLY_OK) return st;
+        // every polynomial must list polynomial 0's rows (the dense run
+        // cleared the status word first)
+        if (f->npolys > 1 && K > 0)
+            hipLaunchKernelGGL(k_check_shared,
+                               dim3((unsigned)std::min<int64_t>(grid1((f->npolys - 1) * K * f->nvars, 256), 65535)),
+                               dim3(256), 0, s, f->exps, f->npolys, K, f->nvars, at<int32_t>(ws, 0));
+        LAUNCH_CHECK();
+        return POLY_OK;
+    }
     if (prec != POLY_FP64) return POLY_ERR_ARG;
     (void)nslices;
     const int n = f->nvars;
@@ -2722,10 +2758,7 @@ poly_status poly_eval_dense(int32_t n, int64_t K, const uint8_t *basis, int32_t 
 poly_status poly_eval_dense_backward_workspace(int32_t n, int64_t K, int64_t P, int64_t N, poly_prec prec,
                                                int32_t nslices, size_t *ws_bytes)
 {
-    (void)nslices;
-    if (prec == POLY_SPLIT_BF16) return POLY_ERR_UNSUPPORTED;
-    if (prec != POLY_FP64) return POLY_ERR_ARG;
-    return dense_bwd_workspace(n, K, P, N, ws_bytes);
+    return dense_bwd_workspace(n, K, P, N, prec, nslices, ws_bytes);
 }
 
 poly_status poly_eval_dense_backward(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp, int64_t P,
@@ -2733,10 +2766,8 @@ poly_status poly_eval_dense_backward(int32_t n, int64_t K, const uint8_t *basis,
                                      double *dX, poly_prec prec, int32_t nslices, void *ws, size_t ws_bytes,
                                      void *stream)
 {
-    (void)nslices;
-    if (prec == POLY_SPLIT_BF16) return POLY_ERR_UNSUPPORTED;
-    if (prec != POLY_FP64) return POLY_ERR_ARG;
-    return dense_bwd_run(n, K, basis, max_exp, P, C, N, X, gY, dC, dX, ws, ws_bytes, (hipStream_t)stream);
+    return dense_bwd_run(n, K, basis, max_exp, P, C, N, X, gY, dC, dX, prec, nslices, ws, ws_bytes,
+                         (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -526,6 +526,31 @@ __global__ void __launch_bounds__(256) k_split_vscale(int n, int64_t K, const ui
         sig_v[kb * N + pt0 + c] = scale_exp(fmax(fmax(s_m[0][c], s_m[1][c]), fmax(s_m[2][c], s_m[3][c])));
 }
 
+// The S digits of y (|y| < 1), each times its scale (an exact BF16
+// number), into BF16 slot q of a thread's packed digit words dig[d][q / 2].
+// y is taken to 48 bits as yh + yl and the digits are extracted in FP32.
+template <int S>
+__device__ inline void put_digits(double y, const float *scale, int q, uint32_t (*dig)[2])
+{
+    const float yh = (float)y;
+    const float yl = (float)(y - (double)yh);
+    float t = yh;
+    float m[S];
+#pragma unroll
+    for (int d = 0; d < S; ++d) {
+        if (d == 3) t = t + yl * 16777216.0f;   // yl in the frame of digit 4
+        t = t * 256.0f;
+        m[d] = rintf(t);
+        t = t - m[d];
+    }
+#pragma unroll
+    for (int d = 0; d < S; ++d) {
+        const float f = m[d] * scale[d];
+        if (q & 1) dig[d][q >> 1] = (dig[d][q >> 1] & 0xffffu) | (__float_as_uint(f) & 0xffff0000u);
+        else dig[d][q >> 1] = __float_as_uint(f) >> 16;
+    }
+}
+
 constexpr int SP_KS = 32, SP_THREADS = 512;
 constexpr int SP_BM = 256, SP_BN = 64;   // workgroup tile: 8 waves x (32 rows x 64 points)
 // FP32 accumulator groups per tile: diagonals 2 and 3 (exact integer sums on
@@ -659,24 +684,7 @@ __global__ void __launch_bounds__(SP_THREADS) k_dense_split(int n, int64_t K, in
                 const uint64_t keep = (live && k < K) ? ~0ull : 0ull;
                 y = ldexp(__builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) & keep), -sig);
             }
-            // y = yh + yl to 48 bits; digits extracted in FP32
-            const float yh = (float)y;
-            const float yl = (float)(y - (double)yh);
-            float t = yh;
-            float m[S];
-#pragma unroll
-            for (int d = 0; d < S; ++d) {
-                if (d == 3) t = t + yl * 16777216.0f;   // yl in the frame of digit 4
-                t = t * 256.0f;
-                m[d] = rintf(t);
-                t = t - m[d];
-            }
-#pragma unroll
-            for (int d = 0; d < S; ++d) {
-                const float f = m[d] * scale[d];
-                if (q & 1) dig[d][q >> 1] = (dig[d][q >> 1] & 0xffffu) | (__float_as_uint(f) & 0xffff0000u);
-                else dig[d][q >> 1] = __float_as_uint(f) >> 16;
-            }
+            put_digits<S>(y, scale, q, dig);
         }
 #pragma unroll
         for (int d = 0; d < S; ++d)
@@ -763,6 +771,253 @@ __global__ void __launch_bounds__(SP_THREADS) k_dense_split(int n, int64_t K, in
             const int64_t r = r0 + w * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
             const int64_t c = n0 + ct * 32 + (lane & 31);
             if (r < P && c < N) Y[(r * N + c) * ys] = ct == 0 ? out[v] : my_out[64 * v];
+        }
+}
+
+// ------------------------------------------------- split reverse mode: dC
+//
+// dC = gY V^T on the same splitting with the operands' roles moved: the
+// contraction runs over points in blocks of DN_KB.  gY [P x N] is cut into
+// digit planes by k_split_c (one scale per row and point block); V^T gets one
+// scale per monomial and point block, written by k_split_wscale, and its
+// digits are formed per step in LDS.  The error bound is the forward's with
+// sum_pt |gY v| in place of sum_k |C v|.
+
+// Scales of V^T: sig_w[pb * K + k] = exponent above max |v_k(x_pt)| over the
+// points pt of block pb.  One block per (point block, 256 monomials), one
+// monomial per thread; the block's points sit point-major in LDS ([DN_KB][n +
+// 1], last entry of each point one), so a wave reads one point's
+// coordinates, each lane the variables its monomial names.
+__global__ void __launch_bounds__(256) k_split_wscale(int n, int64_t K, const uint8_t *basis, const uint4 *enc,
+                                                      int64_t N, const double *X, int32_t *sig_w)
+{
+    extern __shared__ double s_pt[];   // [DN_KB][n + 1]
+    const int64_t ktiles = ceil_div(K, 256);
+    const int64_t pb = blockIdx.x / ktiles;
+    const int64_t k = (blockIdx.x % ktiles) * 256 + threadIdx.x;
+    const int64_t p0 = pb * DN_KB;
+    const int np1 = n + 1;
+    for (int idx = threadIdx.x; idx < DN_KB * np1; idx += 256) {
+        const int l = idx / np1, i = idx % np1;
+        s_pt[idx] = i == n ? 1.0 : (p0 + l < N ? X[(p0 + l) * n + i] : 0.0);
+    }
+    __syncthreads();
+    if (k >= K) return;
+    const uint4 e = enc[k];
+    const int npts = (int)(N - p0 < DN_KB ? N - p0 : DN_KB);
+    double amax = 0.0;
+    for (int l = 0; l < npts; ++l) amax = fmax(amax, fabs(factor_value(e, basis + k * n, n, s_pt + l * np1, 1)));
+    sig_w[pb * K + k] = scale_exp(amax);
+}
+
+// coordinates per thread per step: XR = 2 for n <= 32, 4 for n <= 64
+constexpr int SW_XR_MAX = 4;
+
+__host__ __device__ constexpr size_t split_dc_lds_bytes(int n, int S)
+{
+    return (size_t)SP_THREADS * 16 * 8 + (size_t)2 * SP_KS * (n + 1) * 8 + (size_t)2 * S * SP_BN * SP_LDK * 2;
+}
+
+// grid: x = monomial tiles of SP_BN, y = row tiles of SP_BM.  The tile shape,
+// accumulator groups, K-block folds and double buffering are those of
+// k_dense_split with points as the contraction: wave w owns rows r0 + 32 w
+// .. + 31 and the workgroup's SP_BN monomials; its gY digits come from the
+// MFMA-ordered planes (Np = N padded to SP_KS) into registers.  Each thread
+// owns one monomial (its factor list stays in registers) and forms its
+// digits at 4 of a step's SP_KS points; the step's coordinates, SP_KS * n
+// consecutive doubles of X, are loaded into registers a step ahead and
+// stored point-major into LDS.  Dynamic LDS: FP64 sums [8 waves][16][64
+// lanes], points [2][SP_KS][n + 1] doubles, digits [2][S][BN][SP_LDK] bf16.
+template <int S, int XR>
+__global__ void __launch_bounds__(SP_THREADS) k_dense_bwd_dc_split(int n, int64_t K, const uint8_t *basis,
+                                                                   const uint4 *enc, int64_t P,
+                                                                   const unsigned short *Gs, int64_t N, int64_t Np,
+                                                                   const double *X, const int32_t *sig_w, double *dC)
+{
+    static_assert(SP_VK == 4, "V digits are stored as 2 words per plane");
+    extern __shared__ double s_dyn[];
+    const int np1 = n + 1;
+    double *s_out = s_dyn;                                                   // [8][16][64]
+    double *s_xp = s_out + SP_THREADS * 16;                                  // [2][SP_KS][n + 1]
+    unsigned short *s_vd = (unsigned short *)(s_xp + 2 * SP_KS * np1);      // [2][S][BN][SP_LDK]
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.y * SP_BM;
+    const int64_t k0 = (int64_t)blockIdx.x * SP_BN;
+    const int64_t RB = ceil_div(P, 32);
+    const int64_t KC = Np >> 4;
+    for (int idx = tid; idx < 2 * SP_KS; idx += SP_THREADS) s_xp[idx * np1 + n] = 1.0;
+    double out[16];
+    double *my_out = s_out + w * 16 * 64 + lane;
+    f16v acc[SP_GROUPS][2];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        out[v] = 0.0;
+        my_out[64 * v] = 0.0;
+    }
+#pragma unroll
+    for (int g = 0; g < SP_GROUPS; ++g)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[g][ct][v] = 0.0f;
+
+    // gY digits of this wave (as the C digits of k_dense_split; the host
+    // keeps a workgroup's rows of one plane below 2^31 bytes)
+    const int64_t rb0 = r0 >> 5;
+    const int nrb = (int)(RB - rb0 < SP_BM / 32 ? RB - rb0 : SP_BM / 32);
+    const int aoff = ((w * (int)KC) * 64 + lane) * 16;
+    u32x4 A[2][S];
+    auto load_a = [&](int64_t kk) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(Gs + ((s * RB + rb0) * KC << 9)), (short)0, nrb * (int)KC * 1024, 0x00020000);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                A[j][s] = __builtin_amdgcn_raw_buffer_load_b128(rs, aoff + (int)((kk >> 4) + j) * 1024, 0, 0);
+        }
+    };
+    // this thread's monomial and its slots of a step's points
+    const int vc = tid % SP_BN;
+    const int vkq = (tid / SP_BN) * SP_VK;
+    const int64_t kcol = k0 + vc;
+    const uint4 my_enc = kcol < K ? enc[kcol] : make_uint4(0, 0, 0, 0);
+    const bool high = my_enc.w > 4u;
+    const uint8_t *my_row = basis + (kcol < K ? kcol : 0) * n;
+    // coordinates of step kk: element e = l * n + i of the step's block of
+    // X (point kk + l, variable i), elements tid + r * SP_THREADS; past N zero
+    double xr[XR];
+    int xo[XR];
+#pragma unroll
+    for (int r = 0; r < XR; ++r) {
+        const int e = tid + r * SP_THREADS;
+        xo[r] = e < SP_KS * n ? (e / n) * np1 + e % n : -1;
+    }
+    auto load_x = [&](int64_t kk) {
+        const int64_t left = kk < N ? (N - kk) * n * 8 : 0;
+        const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(X + (kk < N ? kk * n : 0)), (short)0, (int)(left < SP_KS * n * 8 ? left : SP_KS * n * 8),
+            0x00020000);
+#pragma unroll
+        for (int r = 0; r < XR; ++r)
+            xr[r] = __builtin_bit_cast(double,
+                                       __builtin_amdgcn_raw_buffer_load_b64(rx, (tid + r * SP_THREADS) * 8, 0, 0));
+    };
+    auto store_x = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < XR; ++r)
+            if (xo[r] >= 0) s_xp[buf * SP_KS * np1 + xo[r]] = xr[r];
+    };
+    auto load_sig = [&](int64_t kk) -> int {   // monomials past K, steps past Np read zero; never used
+        const int nrec = kk < Np ? (int)((K - k0 < SP_BN ? K - k0 : SP_BN) * 4) : 0;
+        const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(sig_w + (kk < Np ? (kk / DN_KB) * K + k0 : 0)), (short)0, nrec, 0x00020000);
+        return (int)__builtin_amdgcn_raw_buffer_load_b32(rg, vc * 4, 0, 0);
+    };
+    // digits of v_kcol at points kk + vkq .. + 3 (points of buffer vb) into
+    // digit buffer vb.  general = false: one factor word (degree <= 4).
+    auto gen_v = [&](int64_t kk, int sig, int vb, bool general) {
+        const bool live = kcol < K && sig > -1100;
+        const double *xb = s_xp + vb * SP_KS * np1;
+        float scale[S];
+#pragma unroll
+        for (int t = 0; t < S; ++t) scale[t] = live ? ldexpf(1.0f, sig - 8 * (t + 1)) : 0.0f;
+        uint32_t dig[S][SP_VK / 2];
+#pragma unroll
+        for (int q = 0; q < SP_VK; ++q) {
+            const int64_t pt = kk + vkq + q;
+            const double *xq = xb + (vkq + q) * np1;
+            double y;
+            if (general) {
+                y = 0.0;
+                if (live && pt < N) y = ldexp(factor_value(my_enc, my_row, n, xq, 1), -sig);
+            } else {
+                const double v = factor_chunk(1.0, my_enc.x, xq, 1);
+                const uint64_t keep = (live && pt < N) ? ~0ull : 0ull;
+                y = ldexp(__builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) & keep), -sig);
+            }
+            put_digits<S>(y, scale, q, dig);
+        }
+#pragma unroll
+        for (int d = 0; d < S; ++d)
+            *(uint2 *)(s_vd + ((vb * S + d) * SP_BN + vc) * SP_LDK + vkq) = make_uint2(dig[d][0], dig[d][1]);
+    };
+    auto mfma_step = [&](int vb) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+                s8v b[2];
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct)
+                    b[ct] = *(const s8v *)(s_vd + ((vb * S + t) * SP_BN + ct * 32 + (lane & 31)) * SP_LDK + 16 * j +
+                                           8 * (lane >> 5));
+#pragma unroll
+                for (int s = 0; s < S - t; ++s) {
+                    const int g = (s + t) < SP_GROUPS - 1 ? (s + t) : SP_GROUPS - 1;
+#pragma unroll
+                    for (int ct = 0; ct < 2; ++ct)
+                        acc[g][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(bf8v, A[j][s]), __builtin_bit_cast(bf8v, b[ct]), acc[g][ct], 0, 0, 0);
+                }
+            }
+        }
+    };
+    auto fold = [&]() {
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                double t = 0.0;
+#pragma unroll
+                for (int g = SP_GROUPS - 1; g >= 0; --g) {
+                    t += (double)acc[g][ct][v];
+                    acc[g][ct][v] = 0.0f;
+                }
+                if (ct == 0) out[v] += t;
+                else my_out[64 * v] += t;
+            }
+    };
+
+    // prologue: points of steps 0 and 1 staged, digits of step 0 formed
+    load_a(0);
+    load_x(0);
+    int sg = load_sig(0);
+    __syncthreads();
+    store_x(0);
+    load_x(SP_KS);
+    __syncthreads();
+    gen_v(0, sg, 0, false);
+    if (high) gen_v(0, sg, 0, true);
+    store_x(1);
+    load_x(2 * SP_KS);
+    sg = load_sig(SP_KS);   // during step i: the scale of step i + 1
+    __syncthreads();
+    const int64_t nsteps = Np / SP_KS;
+    for (int64_t i = 0; i < nsteps; ++i) {
+        const int64_t k1 = (i + 1) * SP_KS;
+        const int vb = (int)(i & 1);
+        mfma_step(vb);
+        load_a(k1);
+        gen_v(k1, sg, vb ^ 1, false);
+        if (high) gen_v(k1, sg, vb ^ 1, true);
+        if ((k1 % DN_KB) == 0 || i + 1 == nsteps) fold();
+        // points of step i + 2 into the buffer step i's points leave (those
+        // of step i + 3 in flight), and the scale of step i + 2
+        store_x(vb);
+        load_x(k1 + 2 * SP_KS);
+        sg = load_sig(k1 + SP_KS);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int64_t r = r0 + w * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            const int64_t c = k0 + ct * 32 + (lane & 31);
+            if (r < P && c < K) dC[r * K + c] = ct == 0 ? out[v] : my_out[64 * v];
         }
 }
 
@@ -884,24 +1139,94 @@ poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_ex
 inline size_t dense_bwd_dx_lds(int n) { return ((size_t)(n + 1) * DB_BN + 4 * (size_t)n * kWave) * 8; }
 constexpr size_t DB_DX_LDS_MAX = 130 * 1024;   // beside ~27 KB of static LDS
 
-poly_status dense_bwd_workspace(int32_t n, int64_t K, int64_t P, int64_t N, size_t *ws_bytes)
+namespace {
+
+struct DenseBwdPlan {
+    size_t fenc, senc, gs, sigw, total;
+    int64_t Np;
+};
+
+// workspace: status word, factor lists and support encodings of the basis;
+// split: gY digit planes [S][ceil(P / 32) * 32][Np] and the scales of V^T
+// [ceil(N / DN_KB)][K]
+DenseBwdPlan plan_dense_bwd(int64_t K, int64_t P, int64_t N, poly_prec prec, int32_t S)
+{
+    size_t off = kWsHeadBytes;
+    auto take = [&](size_t b) {
+        const size_t o = align_up(off, 256);
+        off = o + b;
+        return o;
+    };
+    DenseBwdPlan d;
+    d.fenc = take(16 * (size_t)K);
+    d.senc = take(16 * (size_t)K);
+    d.gs = d.sigw = 0;
+    d.Np = (int64_t)align_up((size_t)N, SP_KS);
+    if (prec == POLY_SPLIT_BF16) {
+        d.gs = take((size_t)S * ceil_div(P, 32) * 32 * d.Np * 2);
+        d.sigw = take((size_t)ceil_div(N, DN_KB) * K * 4);
+    }
+    d.total = align_up(off, 256);
+    return d;
+}
+
+template <int S, int XR>
+void launch_bwd_dc_split_xr(int n, int64_t K, const uint8_t *basis, const uint4 *enc, int64_t P,
+                         const unsigned short *Gs, int64_t N, int64_t Np, const double *X, const int32_t *sig_w,
+                         double *dC, hipStream_t s)
+{
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_dense_bwd_dc_split<S, XR>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
+    }
+    const dim3 grid((unsigned)ceil_div(K, SP_BN), (unsigned)ceil_div(P, SP_BM));
+    TimedLaunch tl(POLY_TIMING_DENSE, s);
+    hipLaunchKernelGGL((k_dense_bwd_dc_split<S, XR>), grid, dim3(SP_THREADS), split_dc_lds_bytes(n, S), s, n, K, basis,
+                       enc, P, Gs, N, Np, X, sig_w, dC);
+    tl.done(s);
+}
+
+template <int S>
+void launch_bwd_dc_split(int n, int64_t K, const uint8_t *basis, const uint4 *enc, int64_t P,
+                         const unsigned short *Gs, int64_t N, int64_t Np, const double *X, const int32_t *sig_w,
+                         double *dC, hipStream_t s)
+{
+    if (n * SP_KS <= 2 * SP_THREADS) launch_bwd_dc_split_xr<S, 2>(n, K, basis, enc, P, Gs, N, Np, X, sig_w, dC, s);
+    else launch_bwd_dc_split_xr<S, 4>(n, K, basis, enc, P, Gs, N, Np, X, sig_w, dC, s);
+}
+
+}  // namespace
+
+poly_status dense_bwd_workspace(int32_t n, int64_t K, int64_t P, int64_t N, poly_prec prec, int32_t S,
+                                size_t *ws_bytes)
 {
     if (!ws_bytes || n < 1 || n > 255 || K < 0 || P < 0 || N < 0) return POLY_ERR_ARG;
-    *ws_bytes = align_up(align_up(kWsHeadBytes, 256) + 16 * (size_t)K, 256) + align_up(16 * (size_t)K, 256);
+    if (prec != POLY_FP64 && prec != POLY_SPLIT_BF16) return POLY_ERR_ARG;
+    if (prec == POLY_SPLIT_BF16 && (S < 3 || S > 5)) return POLY_ERR_ARG;
+    *ws_bytes = plan_dense_bwd(K, P, N, prec, S).total;
     return POLY_OK;
 }
 
 poly_status dense_bwd_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp, int64_t P, const double *C,
-                          int64_t N, const double *X, const double *gY, double *dC, double *dX, void *ws,
-                          size_t ws_bytes, hipStream_t s)
+                          int64_t N, const double *X, const double *gY, double *dC, double *dX, poly_prec prec,
+                          int32_t S, void *ws, size_t ws_bytes, hipStream_t s)
 {
     size_t need = 0;
-    poly_status st = dense_bwd_workspace(n, K, P, N, &need);
+    poly_status st = dense_bwd_workspace(n, K, P, N, prec, S, &need);
     if (st != POLY_OK) return st;
     if (max_exp < 0 || max_exp > 255) return POLY_ERR_ARG;
     if ((K > 0 && !basis) || (P > 0 && K > 0 && !C) || (N > 0 && !X) || (P > 0 && N > 0 && !gY)) return POLY_ERR_ARG;
     if (!ws || ws_bytes < need) return POLY_ERR_WORKSPACE;
     if (dX && dense_bwd_dx_lds(n) > DB_DX_LDS_MAX) return POLY_ERR_UNSUPPORTED;
+    const DenseBwdPlan d = plan_dense_bwd(K, P, N, prec, S);
+    // split dC: a step's coordinates are at most SW_XR_MAX per thread (n <= 64),
+    // and a workgroup's rows of one gY plane stay below 2^31 bytes
+    if (prec == POLY_SPLIT_BF16 && dC &&
+        ((int64_t)n * SP_KS > (int64_t)SW_XR_MAX * SP_THREADS || split_dc_lds_bytes(n, S) > 160 * 1024 ||
+         d.Np * 512 + 256 > INT32_MAX))
+        return POLY_ERR_UNSUPPORTED;
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute((const void *)k_dense_bwd_dx, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -910,10 +1235,8 @@ poly_status dense_bwd_run(int32_t n, int64_t K, const uint8_t *basis, int32_t ma
                                   64 * 1024);
         attr = true;
     }
-    const size_t o_fenc = align_up(kWsHeadBytes, 256);
-    const size_t o_senc = align_up(o_fenc + 16 * (size_t)K, 256);
-    uint4 *fenc = (uint4 *)((char *)ws + o_fenc);
-    uint64_t *senc = (uint64_t *)((char *)ws + o_senc);
+    uint4 *fenc = (uint4 *)((char *)ws + d.fenc);
+    uint64_t *senc = (uint64_t *)((char *)ws + d.senc);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (unsigned long long *)ws, 0ull, (int64_t)1);
     if (K > 0) {
         hipLaunchKernelGGL(k_encode_factors, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, s, basis, K, n,
@@ -925,6 +1248,25 @@ poly_status dense_bwd_run(int32_t n, int64_t K, const uint8_t *basis, int32_t ma
         if (N == 0) {
             hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)std::min<int64_t>(ceil_div(P * K, 256), 65535)), dim3(256), 0, s,
                                (unsigned long long *)dC, 0ull, P * K);
+        } else if (prec == POLY_SPLIT_BF16) {
+            unsigned short *Gs = (unsigned short *)((char *)ws + d.gs);
+            int32_t *sig_w = (int32_t *)((char *)ws + d.sigw);
+            const int64_t npb = ceil_div(N, DN_KB);
+            static bool wattr = false;
+            if (!wattr) {
+                (void)hipFuncSetAttribute((const void *)k_split_wscale, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          160 * 1024);
+                wattr = true;
+            }
+            hipLaunchKernelGGL(k_split_c, dim3((unsigned)(ceil_div(P, 32) * 32 * ceil_div(d.Np, DN_KB))), dim3(DN_KB),
+                               0, s, gY, P, N, d.Np, S, Gs);
+            hipLaunchKernelGGL(k_split_wscale, dim3((unsigned)(npb * ceil_div(K, 256))), dim3(256),
+                               (size_t)DN_KB * (n + 1) * 8, s, n, K, basis, (const uint4 *)fenc, N, X, sig_w);
+            switch (S) {
+            case 3: launch_bwd_dc_split<3>(n, K, basis, fenc, P, Gs, N, d.Np, X, sig_w, dC, s); break;
+            case 4: launch_bwd_dc_split<4>(n, K, basis, fenc, P, Gs, N, d.Np, X, sig_w, dC, s); break;
+            default: launch_bwd_dc_split<5>(n, K, basis, fenc, P, Gs, N, d.Np, X, sig_w, dC, s); break;
+            }
         } else {
             const dim3 grid((unsigned)ceil_div(K, DB_BN), (unsigned)ceil_div(P, DB_BM));
             TimedLaunch tl(POLY_TIMING_DENSE, s);

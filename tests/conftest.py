@@ -47,3 +47,25 @@ def oracle_over_points(fn, row_ptr, exps, coefs, X, nthreads=None):
     with ThreadPoolExecutor(max_workers=len(chunks)) as ex:
         parts = list(ex.map(lambda c: fn(row_ptr, exps, coefs, X[c[0]:c[-1] + 1]), chunks))
     return np.concatenate(parts, axis=1)
+
+
+def monomial_values(basis, X):
+    """V [K, N]: the oracle's values of the one-term polynomials x^{e_k}."""
+    import numpy as np
+    import oracle
+    K = basis.shape[0]
+    return oracle.eval_batch(np.arange(K + 1, dtype=np.int64), basis, np.ones(K), X)
+
+
+def block_scaled_reference(V, gY, pb=128):
+    """sum over 128-point blocks b of max_b |gY_p| sum_b |v_k| + sum_b |gY_p|
+    max_b |v_k|: the quantity the split dC's truncation error is proportional
+    to (the digits of both operands are relative to their block's largest
+    magnitude)."""
+    import numpy as np
+    aV, aG = np.abs(V), np.abs(gY)
+    ref = np.zeros((gY.shape[0], V.shape[0]))
+    for p0 in range(0, gY.shape[1], pb):
+        g, v = aG[:, p0:p0 + pb], aV[:, p0:p0 + pb]
+        ref += g.max(1)[:, None] * v.sum(1)[None, :] + g.sum(1)[:, None] * v.max(1)[None, :]
+    return ref

@@ -76,6 +76,13 @@ def test_strerror_and_host_argument_checks():
     # dense workspace sizes
     assert L.poly_eval_dense_workspace(30, 1000, 10, 10, 1, 9, ctypes.byref(size)) == 1   # nslices out of range
     assert L.poly_eval_dense_workspace(30, 1000, 10, 10, 1, 5, ctypes.byref(size)) == 0
+    # dense reverse mode: split dC takes 3..5 digits and its digit planes of gY
+    assert L.poly_eval_dense_backward_workspace(30, 1000, 10, 100, 1, 6, ctypes.byref(size)) == 1
+    assert L.poly_eval_dense_backward_workspace(30, 1000, 10, 100, 2, 5, ctypes.byref(size)) == 1   # no such prec
+    assert L.poly_eval_dense_backward_workspace(30, 1000, 10, 100, 0, 9, ctypes.byref(size)) == 0   # FP64: unused
+    fp64 = size.value
+    assert L.poly_eval_dense_backward_workspace(30, 1000, 10, 100, 1, 4, ctypes.byref(size)) == 0
+    assert size.value >= fp64 + 2 * 4 * 32 * 128
     # affine normal: one polynomial, 2 <= n <= 255
     c.nvars = 2
     c.npolys = 2

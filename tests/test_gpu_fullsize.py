@@ -164,6 +164,37 @@ def test_dense_backward_full_sampled(ph):
     assert not dX[rest].any()
 
 
+def test_dense_backward_split_full_sampled(ph):
+    """Split dC of the 4,096 x 46,376 x 65,536 contraction (5 digits) with a
+    dense N(0,1) cotangent: 16 rows x 64 monomials against the oracle's
+    monomial values over all 65,536 points (dC[p][k] = gY[p] . v_k, a NumPy
+    dot product), each within 1e-10 of sum_pt |gY v_k|; the FP64 kernel's
+    entries there within 1e-12; dX is not requested."""
+    wl = W.dense_shared()
+    P, K, N = wl.C.shape[0], wl.basis.shape[0], wl.X.shape[0]
+    gY = W.rng_for(4030).standard_normal((P, N))
+    say("split dC full size")
+    args = [torch.from_numpy(a).cuda() for a in (wl.basis, wl.C, wl.X, gY)]
+    dC = ph.eval_dense_backward(*args, want_dX=False, prec=ph.POLY_SPLIT_BF16, nslices=5)[0]
+    rows = np.sort(W.rng_for(4031).choice(P, 16, replace=False))
+    cols = np.sort(W.rng_for(4032).choice(K, 64, replace=False))
+    dCs = dC[torch.from_numpy(rows).cuda()][:, torch.from_numpy(cols).cuda()].cpu().numpy()
+    del dC
+    dC64 = ph.eval_dense_backward(*args, want_dX=False)[0]
+    dC64s = dC64[torch.from_numpy(rows).cuda()][:, torch.from_numpy(cols).cuda()].cpu().numpy()
+    del dC64, args
+    say("references over all points for 64 monomials")
+    one = np.arange(cols.size + 1, dtype=np.int64)
+    V = oracle.eval_batch(one, wl.basis[cols], np.ones(cols.size), wl.X)            # [64, N]
+    Va = oracle.eval_batch(one, wl.basis[cols], np.ones(cols.size), np.abs(wl.X))
+    ref = gY[rows] @ V.T
+    A = np.abs(gY[rows]) @ Va.T
+    err = np.abs(dCs - ref) / A
+    say(f"  max condition-scaled error {err.max():.3e}")
+    assert err.max() <= 1e-10
+    assert (np.abs(dC64s - ref) <= 1e-12 * A).all()
+
+
 def test_quartic_full_sampled(ph):
     """Random quartic in 100 variables with 100,000 terms at 8,192 points:
     value, gradient (reverse-mode kernel with unit cotangent and poly_grad)

@@ -1,5 +1,6 @@
 """prec = POLY_SPLIT_BF16 on the sparse entry points (poly_eval, poly_grad,
-poly_hess) for a CSR batch that is one shared monomial set.
+poly_hess, poly_eval_backward) for a CSR batch that is one shared monomial
+set.
 
 Values, gradients and Hessians from the split contraction are held to the
 oracle's symbolic derivatives: per element within the split scheme's bound,
@@ -130,7 +131,34 @@ def test_split_csr_requires_a_shared_set(ph):
     with pytest.raises(ph.PolyError) as ex:
         ph.grad(b2, X, prec=ph.POLY_SPLIT_BF16, nslices=S)
     assert ex.value.code == 6
-    import ctypes   # the reverse mode has no split path
-    size = ctypes.c_size_t()
-    c = b.csr()
-    assert ph.lib().poly_eval_backward_workspace(ctypes.byref(c), 20, ph.POLY_SPLIT_BF16, S, ctypes.byref(size)) == 6
+    say("split reverse mode on unequal rows and lengths")
+    gY = torch.ones((6, 20), dtype=torch.float64, device="cuda")
+    with pytest.raises(ph.PolyError) as ex:
+        ph.eval_backward(b, X, gY, check=True, prec=ph.POLY_SPLIT_BF16, nslices=S)
+    assert ex.value.code == 6
+    with pytest.raises(ph.PolyError) as ex:
+        ph.eval_backward(b2, X, gY[:3], prec=ph.POLY_SPLIT_BF16, nslices=S)
+    assert ex.value.code == 6
+
+
+def test_eval_backward_split_csr(ph):
+    """Reverse mode with prec = POLY_SPLIT_BF16: dC per term (the P x K
+    matrix in CSR order) on the split scheme against the oracle, within the
+    bound relative to the block-scaled reference over 128-point blocks and
+    within 1e-10 of sum_pt |gY v|; dX (FP64) within 1e-12 of the same sums
+    over absolute values."""
+    from conftest import block_scaled_reference, monomial_values
+    n = 6
+    B, C, rp, E, Cf = shared_batch(P=45, n=n, d=4, K=190, seed=3140)
+    X = W.points(3141, 300, n)
+    gY = W.rng_for(3142).standard_normal((45, 300))
+    b = ph.batch_from_numpy(rp, E, Cf, n=n, max_exp=4)
+    say("eval_backward split, shared set of 190 monomials, 45 polynomials, 300 points")
+    dX, dC = ph.eval_backward(b, torch.from_numpy(X).cuda(), torch.from_numpy(gY).cuda(), check=True,
+                              prec=ph.POLY_SPLIT_BF16, nslices=S)
+    dXo, dCo = oracle.eval_backward(rp, E, Cf, X, gY)
+    aX, aC = oracle.eval_backward(rp, E, np.abs(Cf), np.abs(X), np.abs(gY))
+    err = np.abs(dC.cpu().numpy() - dCo).reshape(45, -1)
+    assert (err <= BOUND * block_scaled_reference(monomial_values(B, X), gY) + 1e-300).all()
+    assert (err <= 1e-10 * aC.reshape(45, -1) + 1e-300).all()
+    assert (np.abs(dX.cpu().numpy() - dXo) <= 1e-12 * aX + 1e-300).all()
