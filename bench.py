@@ -276,8 +276,9 @@ def bench_eval(args):
                             "dC_mfma_frac": flops / (k_ms_b / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
                             "dX_mfma_frac": flops / t_dx / 1e12 / FP64_PEAK_TFLOPS,
                             "flops_note": "dC = gY V^T and W = C^T gY are 2 P K N flops each"}
-    # split dC (BF16 digits of gY and V^T per 128-point block), against the
-    # FP64 kernel over every output, condition-scaled by sum_pt |gY v_k|
+    # split reverse mode (BF16 digits per 128-point block for dC, per
+    # 128-polynomial block for W = C^T gY), against the FP64 kernels over
+    # every output, condition-scaled by the same sums over absolute values
     S = args.nslices
     fn_s = lambda: ph.eval_dense_backward(basis, C, X, gY, want_dX=False,  # noqa: E731
                                           prec=ph.POLY_SPLIT_BF16, nslices=S)
@@ -298,7 +299,23 @@ def bench_eval(args):
         "frac_cond_scaled_err_above_1e-10": float((cond > 1e-10).double().mean().item()),
         "note": "every output; sum_pt |gY v_k| from the FP64 kernel on |gY|, |x| (|C| does not enter dC)",
     }
-    del d, cond, gY
+    del d, cond
+    fn_x = lambda: ph.eval_dense_backward(basis, C, X, gY, want_dC=False,  # noqa: E731
+                                          prec=ph.POLY_SPLIT_BF16, nslices=S)
+    t_sx, _ = time_events(fn_x, 1, 1)
+    dx = (fn_x()[1] - ph.eval_dense_backward(basis, C, X, gY, want_dC=False)[1]).abs()
+    ax = ph.eval_dense_backward(basis, C.abs(), X.abs(), gY.abs(), want_dC=False)[1]
+    condx = dx / ax
+    res["backward_split_dX"] = {
+        "nslices": S, "ms": t_sx * 1e3, "speedup_vs_fp64": t_dx / t_sx,
+        "mfma_frac": flops * pairs / t_sx / 1e12 / BF16_PEAK_TFLOPS,
+        "max_cond_scaled_err_vs_fp64_gpu": float(condx.max().item()),
+        "frac_cond_scaled_err_above_1e-10": float((condx > 1e-10).double().mean().item()),
+        "note": "W = C^T gY on BF16 MFMA per chunk of 4,096 points, then W contracted with the monomial "
+                "derivatives in FP64; mfma_frac over the whole call (digit planes, W round trip and the "
+                "derivative pass included)",
+    }
+    del dx, ax, condx, gY
     res["workload"] = {"polys": P, "monomials": K, "points": N, "n": wl.n, "degree": 4}
     return res
 

@@ -238,8 +238,8 @@ poly_status poly_hess(const poly_csr *f, const double *X, int64_t N, double *H, 
  * prec: POLY_FP64, or POLY_SPLIT_BF16 for a batch that is one shared
  * monomial set (every polynomial the same K exponent rows in the same order,
  * as for poly_eval): then the call is poly_eval_dense_backward on that set
- * with C the P x K coefficient matrix (dC split on nslices digits, dX in
- * FP64, its limits included); unequal row lengths give
+ * with C the P x K coefficient matrix (dC and dX split on nslices digits,
+ * its limits included); unequal row lengths give
  * POLY_ERR_UNSUPPORTED, unequal rows POLY_ERR_UNSUPPORTED in the status word
  * (poly_read_status). */
 poly_status poly_eval_backward_workspace(const poly_csr *f, int64_t N, poly_prec prec, int32_t nslices,
@@ -379,20 +379,23 @@ poly_status poly_eval_dense(int32_t n, int64_t K, const uint8_t *basis, int32_t 
  *   dC[p*K + k]  = sum_pt gY[p*N + pt] * v_k(x_pt)            (may be NULL)
  *   dX[pt*n + j] = sum_k W[k][pt] * d v_k / d x_{j+1} (x_pt),
  *                  W = C^T gY                                   (may be NULL)
- * dX runs on FP64 MFMA per tile of 128 points, the W tile of each 64
- * monomials formed and contracted at once with the monomials' derivatives
- * (W is never stored).  dC runs on MFMA with V^T formed per step of points:
- * prec POLY_FP64 in FP64; POLY_SPLIT_BF16 on nslices (3..5) BF16 digits of
- * gY and of V^T, each scaled per 128-point block, with FP32 sums that are
- * exact per block and FP64 accumulation across blocks (the forward's split
- * scheme with points as the contraction; error relative to
- * sum_pt |gY v_k| as the forward's to sum_k |C v|); dX stays FP64 at either
- * prec.  Limits: dX needs n <= 43 (points and four accumulator blocks in
- * LDS), split dC n <= 64 and N below about 4.19 million points (32-bit
- * offsets into one workgroup's digit rows), else POLY_ERR_UNSUPPORTED;
- * nslices outside 3..5 with POLY_SPLIT_BF16 is POLY_ERR_ARG; basis, C and
- * X as in poly_eval_dense.  Workspace grows with prec POLY_SPLIT_BF16 by the
- * digit planes, 2 * nslices * ceil(P / 32) * 32 * ceil(N / 32) * 32 bytes. */
+ * prec POLY_FP64: both on FP64 MFMA.  dC with V^T formed per step of
+ * points; dX per tile of 128 points, the W tile of each 64 monomials formed
+ * and contracted at once with the monomials' derivatives (W never stored).
+ * prec POLY_SPLIT_BF16: the forward's split scheme on nslices (3..5) BF16
+ * digits per operand, FP32 sums exact per 128-long block of the
+ * contraction, FP64 accumulation across blocks.  dC: digits of gY and V^T
+ * scaled per 128-point block (error relative to sum_pt |gY v_k| as the
+ * forward's to sum_k |C v|).  dX: W = C^T gY from digits of C^T and gY^T
+ * scaled per 128-polynomial block, stored in FP64 per chunk of 4,096 points,
+ * then contracted with the monomials' derivatives in FP64 (error relative to
+ * sum_k sum_p |C gY| |d v_k / d x_j|).  Limits: dX needs n <= 43, split dC
+ * n <= 64, and the split digit rows of one workgroup stay below 2^31 bytes
+ * (N, P below about 4.19 million), else POLY_ERR_UNSUPPORTED; nslices
+ * outside 3..5 with POLY_SPLIT_BF16 is POLY_ERR_ARG; basis, C and X as in
+ * poly_eval_dense.  The split workspace holds the digit planes of gY, C^T
+ * and gY^T (2 * nslices bytes per padded element of each), the V^T scales,
+ * one W chunk (8 * K * min(N, 4096) bytes) and 16 partial dX chunks. */
 poly_status poly_eval_dense_backward_workspace(int32_t n, int64_t K, int64_t P, int64_t N, poly_prec prec,
                                                int32_t nslices, size_t *ws_bytes);
 poly_status poly_eval_dense_backward(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp, int64_t P,

@@ -638,8 +638,8 @@ def eval_backward(b: Batch, X: torch.Tensor, gY: torch.Tensor, want_dX: bool = T
                   check: bool = False, prec: int = POLY_FP64, nslices: int = 5):
     """Reverse mode of eval: (dX [N, n], dC [T]).  prec=POLY_SPLIT_BF16 takes a
     batch that is one shared monomial set (equal exponent rows in every
-    polynomial) through the dense reverse mode: dC on ``nslices`` BF16 digits,
-    dX in FP64 (check=True reads back the shared-rows check)."""
+    polynomial) through the dense reverse mode on ``nslices`` BF16 digits
+    (check=True reads back the shared-rows check)."""
     L = lib()
     X = X.contiguous()
     gY = gY.contiguous()
@@ -812,9 +812,10 @@ def eval_dense(basis: torch.Tensor, C: torch.Tensor, X: torch.Tensor, prec: int 
 def eval_dense_backward(basis: torch.Tensor, C: torch.Tensor, X: torch.Tensor, gY: torch.Tensor,
                         want_dC: bool = True, want_dX: bool = True, max_exp: int | None = None,
                         prec: int = POLY_FP64, nslices: int = 5):
-    """Reverse mode of eval_dense: (dC [P, K], dX [N, n]).  dX runs on FP64
-    MFMA; dC on FP64 MFMA or, with prec=POLY_SPLIT_BF16, on ``nslices`` BF16
-    digits per operand (the forward split scheme, contraction over points)."""
+    """Reverse mode of eval_dense: (dC [P, K], dX [N, n]) on FP64 MFMA or, with
+    prec=POLY_SPLIT_BF16, on ``nslices`` BF16 digits per operand (the forward
+    split scheme: dC contracts over points, W = C^T gY for dX over the
+    polynomials)."""
     L = lib()
     basis, C, X, gY = basis.contiguous(), C.contiguous(), X.contiguous(), gY.contiguous()
     K, n = basis.shape
@@ -846,8 +847,7 @@ def eval_dense_backward(basis: torch.Tensor, C: torch.Tensor, X: torch.Tensor, g
 class PolyEvalDense(torch.autograd.Function):
     """Y = C V for P polynomials over one shared monomial set, differentiable
     in (C, X): the forward is eval_dense (FP64 or split BF16), the backward
-    eval_dense_backward at the same precision (dC split with the forward's
-    digit count, dX FP64)."""
+    eval_dense_backward at the same precision and digit count."""
 
     @staticmethod
     def forward(ctx, C, X, basis, prec: int = POLY_FP64, nslices: int = 5):

@@ -2408,8 +2408,8 @@ static void launch_dc(const poly_csr *f, const double *X, int64_t N, const doubl
 namespace {
 
 // prec = POLY_SPLIT_BF16 on the reverse mode: a shared monomial set stored
-// as CSR (as for the forward) runs the dense reverse mode, dC on the split
-// scheme and dX in FP64; K = the common row length, or -1 if they differ
+// as CSR (as for the forward) runs the dense reverse mode on the split
+// scheme; K = the common row length, or -1 if they differ
 static int64_t shared_row_length(const poly_csr *f)
 {
     const int64_t P = f->npolys;

@@ -1021,6 +1021,263 @@ __global__ void __launch_bounds__(SP_THREADS) k_dense_bwd_dc_split(int n, int64_
         }
 }
 
+// ------------------------------------------------- split reverse mode: dX
+//
+// dX[pt][j] = sum_k W[k][pt] d v_k / d x_j (x_pt), W = C^T gY.  The split
+// form computes W for a chunk of points as a plain product of two given
+// matrices on the splitting above, contraction over the polynomials in
+// blocks of DN_KB: C^T and gY^T are cut into digit planes (rows monomials,
+// resp. points; one scale per row and polynomial block) by k_split_ct; W
+// [K x chunk] is stored in FP64; a second pass contracts it with the
+// monomials' derivatives, K split over blocks whose partial sums are added
+// in a fixed order.
+
+// Digit planes (split_c_index order) of the transpose of a row-major matrix:
+// row r, column kk of the operand is M[kk * ld + r], r < R, kk < Kc; rows up
+// to ceil(R / 32) * 32 and columns up to Kp (multiple of SP_KS) are padded
+// with zero digits.  One block per (32 rows, DN_KB columns): the tile is
+// read along r (coalesced) into LDS, each thread then owns one column.
+__global__ void __launch_bounds__(DN_KB) k_split_ct(const double *M, int64_t ld, int64_t R, int64_t Kc, int64_t Kp,
+                                                    int S, unsigned short *Ms)
+{
+    __shared__ double s_t[DN_KB][33];
+    __shared__ double s_m[4][32];
+    const int64_t nkb = ceil_div(Kp, DN_KB);
+    const int64_t RB = ceil_div(R, 32);
+    const int64_t rb = blockIdx.x / nkb, kb = blockIdx.x % nkb;
+    const int64_t r0 = rb * 32, k0 = kb * DN_KB;
+    const int t = threadIdx.x;
+    for (int idx = t; idx < DN_KB * 32; idx += DN_KB) {
+        const int kk = idx >> 5, r = idx & 31;
+        s_t[kk][r] = (r0 + r < R && k0 + kk < Kc) ? M[(k0 + kk) * ld + r0 + r] : 0.0;
+    }
+    __syncthreads();
+    {
+        const int r = t & 31, g = t >> 5;
+        double a = 0.0;
+        for (int q = 0; q < 32; ++q) a = fmax(a, fabs(s_t[g * 32 + q][r]));
+        s_m[g][r] = a;
+    }
+    __syncthreads();
+    const int64_t k = k0 + t;
+    if (k >= Kp) return;
+    for (int r = 0; r < 32; ++r) {
+        const double amax = fmax(fmax(s_m[0][r], s_m[1][r]), fmax(s_m[2][r], s_m[3][r]));
+        const int sig = scale_exp(amax);
+        double y = amax > 0.0 ? ldexp(s_t[t][r], -sig) : 0.0;
+        for (int d = 1; d <= S; ++d) {
+            y = y * 256.0;
+            const double m = rint(y);
+            y = y - m;
+            Ms[split_c_index(d - 1, r0 + r, k, RB, Kp)] = bf16_bits_exact(ldexpf((float)m, sig - 8 * d));
+        }
+    }
+}
+
+constexpr int SG_REC = 64 * 16;   // bytes of one operand record (64 lanes x 8 BF16)
+
+__host__ __device__ constexpr size_t split_gemm_lds_bytes(int S)
+{
+    return (size_t)SP_THREADS * 16 * 8 + (size_t)2 * 4 * S * SG_REC;
+}
+
+// out[r * ldo + c] = sum_kk A[r][kk] B[c][kk] for r < R, c < Cn, with A and
+// B given as digit planes (split_c_index order, RBa resp. RBb row blocks,
+// Kp columns); columns are those of B's row blocks cb0 .. of this launch.
+// grid: x = column tiles of SP_BN, y = row tiles of SP_BM.  The tile shape,
+// accumulator groups and K-block folds are k_dense_split's; wave w's A
+// digits come straight into registers, and the workgroup's B records (2
+// column blocks x S planes x 2 chunks of 16 per step) are staged in LDS,
+// loaded into registers a step ahead.  Dynamic LDS: FP64 sums [8][16][64],
+// B records [2][2 * S * 2][64 lanes][16 B].
+template <int S>
+__global__ void __launch_bounds__(SP_THREADS) k_split_gemm(int64_t R, int64_t RBa, const unsigned short *As,
+                                                           int64_t Cn, int64_t RBb, int64_t cb0,
+                                                           const unsigned short *Bs, int64_t Kp, double *out,
+                                                           int64_t ldo)
+{
+    constexpr int NREC = 2 * S * 2;                              // records per step
+    constexpr int BR = (NREC * 64 + SP_THREADS - 1) / SP_THREADS;  // record loads per thread
+    extern __shared__ double s_dyn[];
+    double *s_out = s_dyn;                                    // [8][16][64]
+    u32x4 *s_b = (u32x4 *)(s_out + SP_THREADS * 16);          // [2][NREC][64]
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.y * SP_BM;
+    const int64_t cblk0 = cb0 + (int64_t)blockIdx.x * 2;      // first of the tile's two column blocks
+    const int64_t KC = Kp >> 4;
+    double out_r[16];
+    double *my_out = s_out + w * 16 * 64 + lane;
+    f16v acc[SP_GROUPS][2];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        out_r[v] = 0.0;
+        my_out[64 * v] = 0.0;
+    }
+#pragma unroll
+    for (int g = 0; g < SP_GROUPS; ++g)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[g][ct][v] = 0.0f;
+    const int64_t rb0 = r0 >> 5;
+    const int nrb = (int)(RBa - rb0 < SP_BM / 32 ? RBa - rb0 : SP_BM / 32);
+    const int aoff = ((w * (int)KC) * 64 + lane) * 16;
+    u32x4 A[2][S];
+    auto load_a = [&](int64_t kk) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(As + ((s * RBa + rb0) * KC << 9)), (short)0, nrb * (int)KC * 1024, 0x00020000);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                A[j][s] = __builtin_amdgcn_raw_buffer_load_b128(rs, aoff + (int)((kk >> 4) + j) * 1024, 0, 0);
+        }
+    };
+    // record q = (ct * S + t) * 2 + j of step kk: plane t, column block
+    // cblk0 + ct, chunk kk / 16 + j; blocks past RBb and steps past Kp read zero
+    u32x4 breg[BR];
+    auto load_b = [&](int64_t kk) {
+#pragma unroll
+        for (int m = 0; m < BR; ++m) {
+            const int q = (tid >> 6) + m * (SP_THREADS / 64);
+            breg[m] = (u32x4){0u, 0u, 0u, 0u};
+            if (q < NREC) {
+                const int j = q & 1, t = (q >> 1) % S, ct = (q >> 1) / S;
+                const int64_t cblk = cblk0 + ct;
+                const int nrec = (cblk < RBb && kk < Kp) ? (int)(KC * 1024) : 0;
+                const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+                    (void *)(Bs + ((t * RBb + (cblk < RBb ? cblk : 0)) * KC << 9)), (short)0, nrec, 0x00020000);
+                breg[m] = __builtin_amdgcn_raw_buffer_load_b128(rb, (int)((kk >> 4) + j) * 1024 + lane * 16, 0, 0);
+            }
+        }
+    };
+    auto store_b = [&](int buf) {
+#pragma unroll
+        for (int m = 0; m < BR; ++m) {
+            const int q = (tid >> 6) + m * (SP_THREADS / 64);
+            if (q < NREC) s_b[(buf * NREC + q) * 64 + lane] = breg[m];
+        }
+    };
+    auto mfma_step = [&](int vb) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+                u32x4 b[2];
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct) b[ct] = s_b[(vb * NREC + (ct * S + t) * 2 + j) * 64 + lane];
+#pragma unroll
+                for (int s = 0; s < S - t; ++s) {
+                    const int g = (s + t) < SP_GROUPS - 1 ? (s + t) : SP_GROUPS - 1;
+#pragma unroll
+                    for (int ct = 0; ct < 2; ++ct)
+                        acc[g][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(bf8v, A[j][s]), __builtin_bit_cast(bf8v, b[ct]), acc[g][ct], 0, 0, 0);
+                }
+            }
+        }
+    };
+    auto fold = [&]() {
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                double t = 0.0;
+#pragma unroll
+                for (int g = SP_GROUPS - 1; g >= 0; --g) {
+                    t += (double)acc[g][ct][v];
+                    acc[g][ct][v] = 0.0f;
+                }
+                if (ct == 0) out_r[v] += t;
+                else my_out[64 * v] += t;
+            }
+    };
+    load_a(0);
+    load_b(0);
+    __syncthreads();
+    store_b(0);
+    load_b(SP_KS);
+    __syncthreads();
+    const int64_t nsteps = Kp / SP_KS;
+    for (int64_t i = 0; i < nsteps; ++i) {
+        const int64_t k1 = (i + 1) * SP_KS;
+        const int vb = (int)(i & 1);
+        mfma_step(vb);
+        load_a(k1);
+        store_b(vb ^ 1);          // B of step i + 1 (its buffer held step i - 1's)
+        load_b(k1 + SP_KS);
+        if ((k1 % DN_KB) == 0 || i + 1 == nsteps) fold();
+        __syncthreads();
+    }
+    const int64_t c0 = (cblk0 - cb0) * 32;
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int64_t r = r0 + w * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            const int64_t c = c0 + ct * 32 + (lane & 31);
+            if (r < R && c < Cn) out[r * ldo + c] = ct == 0 ? out_r[v] : my_out[64 * v];
+        }
+}
+
+constexpr int DW_WAVES = 4, DW_KSPLIT = 16;
+
+// Partial dX of a chunk of points from W [K x ldw] (FP64): block (point
+// tile of 64, K range q of DW_KSPLIT), wave w the w-th quarter of that range;
+// lane = point.  Each wave adds W[k][pt] d v_k / d x_j into its accumulator
+// block [n][64] in LDS in the order of k, then the four blocks are added in
+// wave order into part[q][pt][j].  Dynamic LDS: points [n + 1][64] (last row
+// ones), accumulators [DW_WAVES][n][64].
+__global__ void __launch_bounds__(DW_WAVES * 64) k_dx_from_w(int n, int64_t K, const uint8_t *basis,
+                                                             const uint64_t *senc, const double *W, int64_t ldw,
+                                                             int64_t Nc, const double *X, double *part)
+{
+    extern __shared__ double s_dyn[];
+    double *s_x = s_dyn;                              // [n + 1][64]
+    double *s_acc = s_dyn + (size_t)(n + 1) * 64;     // [DW_WAVES][n][64]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t p0 = (int64_t)blockIdx.x * 64;
+    const int q = blockIdx.y;
+    for (int idx = tid; idx < (n + 1) * 64; idx += DW_WAVES * 64) {
+        const int i = idx / 64, c = idx % 64;
+        s_x[idx] = i == n ? 1.0 : (p0 + c < Nc ? X[(p0 + c) * n + i] : 0.0);
+    }
+    for (int idx = tid; idx < DW_WAVES * n * 64; idx += DW_WAVES * 64) s_acc[idx] = 0.0;
+    __syncthreads();
+    const int64_t per = ceil_div(K, (int64_t)DW_KSPLIT * DW_WAVES);
+    const int64_t kb = ((int64_t)q * DW_WAVES + w) * per;
+    const int64_t ke = kb + per < K ? kb + per : K;
+    const int64_t pt = p0 + lane;
+    double *my_acc = s_acc + (size_t)w * n * 64 + lane;
+    if (pt < Nc)
+        for (int64_t k = kb; k < ke; ++k) {
+            const double wv = W[k * ldw + pt];
+            add_monomial_grad(senc[2 * k], senc[2 * k + 1], basis + k * n, n, s_x + lane, 64, wv, my_acc);
+        }
+    __syncthreads();
+    for (int idx = tid; idx < 64 * n; idx += DW_WAVES * 64) {
+        const int pl = idx / n, j = idx % n;
+        if (p0 + pl >= Nc) continue;
+        double a = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < DW_WAVES; ++ww) a += s_acc[((size_t)ww * n + j) * 64 + pl];
+        part[((size_t)q * Nc + p0 + pl) * n + j] = a;
+    }
+}
+
+// dX rows of a chunk: the DW_KSPLIT partial sums added in order
+__global__ void k_dx_reduce(const double *part, int64_t Nc, int n, double *dX)
+{
+    const int64_t m = Nc * n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        double a = 0.0;
+        for (int q = 0; q < DW_KSPLIT; ++q) a += part[q * m + i];
+        dX[i] = a;
+    }
+}
+
 // ---------------------------------------------------------------- host side
 
 namespace {
@@ -1141,15 +1398,19 @@ constexpr size_t DB_DX_LDS_MAX = 130 * 1024;   // beside ~27 KB of static LDS
 
 namespace {
 
+constexpr int64_t DX_CHUNK = 4096;   // points per W chunk of the split dX
+
 struct DenseBwdPlan {
-    size_t fenc, senc, gs, sigw, total;
-    int64_t Np;
+    size_t fenc, senc, gs, sigw, ct, gyt, w, part, total;
+    int64_t Np, Pp, Nc;
 };
 
 // workspace: status word, factor lists and support encodings of the basis;
-// split: gY digit planes [S][ceil(P / 32) * 32][Np] and the scales of V^T
-// [ceil(N / DN_KB)][K]
-DenseBwdPlan plan_dense_bwd(int64_t K, int64_t P, int64_t N, poly_prec prec, int32_t S)
+// split: for dC the gY digit planes [S][ceil(P / 32) * 32][Np] and the scales
+// of V^T [ceil(N / DN_KB)][K]; for dX the digit planes of C^T [S][ceil(K /
+// 32) * 32][Pp] and of gY^T [S][ceil(N / 32) * 32][Pp], one W chunk [K][Nc]
+// and the partial sums [DW_KSPLIT][Nc][n]
+DenseBwdPlan plan_dense_bwd(int32_t n, int64_t K, int64_t P, int64_t N, poly_prec prec, int32_t S)
 {
     size_t off = kWsHeadBytes;
     auto take = [&](size_t b) {
@@ -1160,11 +1421,17 @@ DenseBwdPlan plan_dense_bwd(int64_t K, int64_t P, int64_t N, poly_prec prec, int
     DenseBwdPlan d;
     d.fenc = take(16 * (size_t)K);
     d.senc = take(16 * (size_t)K);
-    d.gs = d.sigw = 0;
+    d.gs = d.sigw = d.ct = d.gyt = d.w = d.part = 0;
     d.Np = (int64_t)align_up((size_t)N, SP_KS);
+    d.Pp = (int64_t)align_up((size_t)P, SP_KS);
+    d.Nc = std::min<int64_t>((int64_t)align_up((size_t)N, 64), DX_CHUNK);
     if (prec == POLY_SPLIT_BF16) {
         d.gs = take((size_t)S * ceil_div(P, 32) * 32 * d.Np * 2);
         d.sigw = take((size_t)ceil_div(N, DN_KB) * K * 4);
+        d.ct = take((size_t)S * ceil_div(K, 32) * 32 * d.Pp * 2);
+        d.gyt = take((size_t)S * ceil_div(N, 32) * 32 * d.Pp * 2);
+        d.w = take((size_t)K * d.Nc * 8);
+        d.part = take((size_t)DW_KSPLIT * d.Nc * n * 8);
     }
     d.total = align_up(off, 256);
     return d;
@@ -1189,6 +1456,21 @@ void launch_bwd_dc_split_xr(int n, int64_t K, const uint8_t *basis, const uint4 
 }
 
 template <int S>
+void launch_split_gemm(int64_t K, const unsigned short *Cts, int64_t nc, int64_t RBn, int64_t cb0,
+                       const unsigned short *Gts, int64_t Pp, double *Wc, int64_t ldw, hipStream_t s)
+{
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_split_gemm<S>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        attr = true;
+    }
+    const dim3 grid((unsigned)ceil_div(nc, SP_BN), (unsigned)ceil_div(K, SP_BM));
+    hipLaunchKernelGGL((k_split_gemm<S>), grid, dim3(SP_THREADS), split_gemm_lds_bytes(S), s, K, ceil_div(K, 32),
+                       Cts, nc, RBn, cb0, Gts, Pp, Wc, ldw);
+}
+
+template <int S>
 void launch_bwd_dc_split(int n, int64_t K, const uint8_t *basis, const uint4 *enc, int64_t P,
                          const unsigned short *Gs, int64_t N, int64_t Np, const double *X, const int32_t *sig_w,
                          double *dC, hipStream_t s)
@@ -1205,7 +1487,7 @@ poly_status dense_bwd_workspace(int32_t n, int64_t K, int64_t P, int64_t N, poly
     if (!ws_bytes || n < 1 || n > 255 || K < 0 || P < 0 || N < 0) return POLY_ERR_ARG;
     if (prec != POLY_FP64 && prec != POLY_SPLIT_BF16) return POLY_ERR_ARG;
     if (prec == POLY_SPLIT_BF16 && (S < 3 || S > 5)) return POLY_ERR_ARG;
-    *ws_bytes = plan_dense_bwd(K, P, N, prec, S).total;
+    *ws_bytes = plan_dense_bwd(n, K, P, N, prec, S).total;
     return POLY_OK;
 }
 
@@ -1220,13 +1502,15 @@ poly_status dense_bwd_run(int32_t n, int64_t K, const uint8_t *basis, int32_t ma
     if ((K > 0 && !basis) || (P > 0 && K > 0 && !C) || (N > 0 && !X) || (P > 0 && N > 0 && !gY)) return POLY_ERR_ARG;
     if (!ws || ws_bytes < need) return POLY_ERR_WORKSPACE;
     if (dX && dense_bwd_dx_lds(n) > DB_DX_LDS_MAX) return POLY_ERR_UNSUPPORTED;
-    const DenseBwdPlan d = plan_dense_bwd(K, P, N, prec, S);
+    const DenseBwdPlan d = plan_dense_bwd(n, K, P, N, prec, S);
     // split dC: a step's coordinates are at most SW_XR_MAX per thread (n <= 64),
     // and a workgroup's rows of one gY plane stay below 2^31 bytes
     if (prec == POLY_SPLIT_BF16 && dC &&
         ((int64_t)n * SP_KS > (int64_t)SW_XR_MAX * SP_THREADS || split_dc_lds_bytes(n, S) > 160 * 1024 ||
          d.Np * 512 + 256 > INT32_MAX))
         return POLY_ERR_UNSUPPORTED;
+    // split dX: a workgroup's rows of one C^T plane below 2^31 bytes
+    if (prec == POLY_SPLIT_BF16 && dX && d.Pp * 512 + 256 > INT32_MAX) return POLY_ERR_UNSUPPORTED;
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute((const void *)k_dense_bwd_dx, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1275,7 +1559,37 @@ poly_status dense_bwd_run(int32_t n, int64_t K, const uint8_t *basis, int32_t ma
             tl.done(s);
         }
     }
-    if (dX && N > 0) {
+    if (dX && N > 0 && prec == POLY_SPLIT_BF16 && P > 0 && K > 0) {
+        unsigned short *Cts = (unsigned short *)((char *)ws + d.ct);
+        unsigned short *Gts = (unsigned short *)((char *)ws + d.gyt);
+        double *Wc = (double *)((char *)ws + d.w);
+        double *part = (double *)((char *)ws + d.part);
+        static bool xattr = false;
+        if (!xattr) {
+            (void)hipFuncSetAttribute((const void *)k_dx_from_w, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      160 * 1024);
+            xattr = true;
+        }
+        const int64_t nkb = ceil_div(d.Pp, DN_KB);
+        hipLaunchKernelGGL(k_split_ct, dim3((unsigned)(ceil_div(K, 32) * nkb)), dim3(DN_KB), 0, s, C, K, K, P, d.Pp,
+                           S, Cts);
+        hipLaunchKernelGGL(k_split_ct, dim3((unsigned)(ceil_div(N, 32) * nkb)), dim3(DN_KB), 0, s, gY, N, N, P, d.Pp,
+                           S, Gts);
+        const size_t xlds = ((size_t)(n + 1) * 64 + (size_t)DW_WAVES * n * 64) * 8;
+        for (int64_t c0 = 0; c0 < N; c0 += d.Nc) {
+            const int64_t nc = std::min<int64_t>(d.Nc, N - c0);
+            switch (S) {
+            case 3: launch_split_gemm<3>(K, Cts, nc, ceil_div(N, 32), c0 / 32, Gts, d.Pp, Wc, d.Nc, s); break;
+            case 4: launch_split_gemm<4>(K, Cts, nc, ceil_div(N, 32), c0 / 32, Gts, d.Pp, Wc, d.Nc, s); break;
+            default: launch_split_gemm<5>(K, Cts, nc, ceil_div(N, 32), c0 / 32, Gts, d.Pp, Wc, d.Nc, s); break;
+            }
+            hipLaunchKernelGGL(k_dx_from_w, dim3((unsigned)ceil_div(nc, 64), (unsigned)DW_KSPLIT),
+                               dim3(DW_WAVES * 64), xlds, s, n, K, basis, (const uint64_t *)senc,
+                               (const double *)Wc, d.Nc, nc, X + c0 * n, part);
+            hipLaunchKernelGGL(k_dx_reduce, dim3((unsigned)std::min<int64_t>(ceil_div(nc * n, 256), 65535)),
+                               dim3(256), 0, s, (const double *)part, nc, n, dX + c0 * n);
+        }
+    } else if (dX && N > 0) {
         hipLaunchKernelGGL(k_dense_bwd_dx, dim3((unsigned)ceil_div(N, DB_BN)), dim3(DB_THREADS), dense_bwd_dx_lds(n), s,
                            n, K, basis, (const uint64_t *)senc, P, C, gY, N, X, dX);
     }

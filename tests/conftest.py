@@ -69,3 +69,21 @@ def block_scaled_reference(V, gY, pb=128):
         g, v = aG[:, p0:p0 + pb], aV[:, p0:p0 + pb]
         ref += g.max(1)[:, None] * v.sum(1)[None, :] + g.sum(1)[:, None] * v.max(1)[None, :]
     return ref
+
+
+def split_dx_reference(basis, C, X, gY, pb=128):
+    """sum_k refW[k][pt] |d v_k / d x_j (x_pt)| with refW[k][pt] the
+    block-scaled reference of W = C^T gY over 128-polynomial blocks b,
+    max_b |C_k| sum_b |gY_pt| + sum_b |C_k| max_b |gY_pt|: the quantity the
+    split dX's truncation error is proportional to (the error of each W
+    entry, carried by the exact derivative factors)."""
+    import numpy as np
+    import oracle
+    K = basis.shape[0]
+    D = np.abs(oracle.grad_batch(np.arange(K + 1, dtype=np.int64), basis, np.ones(K), X))   # [K, N, n]
+    aC, aG = np.abs(C), np.abs(gY)
+    refW = np.zeros((K, X.shape[0]))
+    for p0 in range(0, C.shape[0], pb):
+        c, g = aC[p0:p0 + pb], aG[p0:p0 + pb]
+        refW += c.max(0)[:, None] * g.sum(0)[None, :] + c.sum(0)[:, None] * g.max(0)[None, :]
+    return np.einsum("kp,kpj->pj", refW, D)

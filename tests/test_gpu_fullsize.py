@@ -165,17 +165,22 @@ def test_dense_backward_full_sampled(ph):
 
 
 def test_dense_backward_split_full_sampled(ph):
-    """Split dC of the 4,096 x 46,376 x 65,536 contraction (5 digits) with a
-    dense N(0,1) cotangent: 16 rows x 64 monomials against the oracle's
-    monomial values over all 65,536 points (dC[p][k] = gY[p] . v_k, a NumPy
-    dot product), each within 1e-10 of sum_pt |gY v_k|; the FP64 kernel's
-    entries there within 1e-12; dX is not requested."""
+    """Split reverse mode of the 4,096 x 46,376 x 65,536 contraction (5
+    digits) with a dense N(0,1) cotangent.  dC: 16 rows x 64 monomials against
+    the oracle's monomial values over all 65,536 points (dC[p][k] = gY[p] .
+    v_k, a NumPy dot product), each within 1e-10 of sum_pt |gY v_k|; the FP64
+    kernel's entries there within 1e-12.  dX (16 chunks of W): 8 points
+    against the oracle's gradient of sum_p gY[p][pt] f_p (coefficients
+    gY[:, pt] C, a NumPy product), each within 1e-10 of the same sums over
+    absolute values."""
     wl = W.dense_shared()
     P, K, N = wl.C.shape[0], wl.basis.shape[0], wl.X.shape[0]
     gY = W.rng_for(4030).standard_normal((P, N))
     say("split dC full size")
     args = [torch.from_numpy(a).cuda() for a in (wl.basis, wl.C, wl.X, gY)]
-    dC = ph.eval_dense_backward(*args, want_dX=False, prec=ph.POLY_SPLIT_BF16, nslices=5)[0]
+    dC, dX = ph.eval_dense_backward(*args, prec=ph.POLY_SPLIT_BF16, nslices=5)
+    pts = np.array([0, 1, 4095, 4096, 30000, 65000, 65534, 65535])
+    dX = dX[torch.from_numpy(pts).cuda()].cpu().numpy()
     rows = np.sort(W.rng_for(4031).choice(P, 16, replace=False))
     cols = np.sort(W.rng_for(4032).choice(K, 64, replace=False))
     dCs = dC[torch.from_numpy(rows).cuda()][:, torch.from_numpy(cols).cuda()].cpu().numpy()
@@ -190,9 +195,18 @@ def test_dense_backward_split_full_sampled(ph):
     ref = gY[rows] @ V.T
     A = np.abs(gY[rows]) @ Va.T
     err = np.abs(dCs - ref) / A
-    say(f"  max condition-scaled error {err.max():.3e}")
+    say(f"  dC max condition-scaled error {err.max():.3e}")
     assert err.max() <= 1e-10
     assert (np.abs(dC64s - ref) <= 1e-12 * A).all()
+    say("dX references at 8 points")
+    for i, pt in enumerate(pts):
+        cw = gY[:, pt] @ wl.C
+        ca = np.abs(gY[:, pt]) @ np.abs(wl.C)
+        G = oracle.grad_batch([0, K], wl.basis, cw, wl.X[pt:pt + 1])[0, 0]
+        Ga = oracle.grad_batch([0, K], wl.basis, ca, np.abs(wl.X[pt:pt + 1]))[0, 0]
+        e = np.abs(dX[i] - G) / Ga
+        say(f"  dX point {pt}: max condition-scaled error {e.max():.3e}")
+        assert (e <= 1e-10).all()
 
 
 def test_quartic_full_sampled(ph):
