@@ -29,13 +29,34 @@ struct GsGen {
     const uint64_t *kb;
     uint32_t tb;
     double inv_tb;   // 1 / tb
-    __device__ uint64_t key(uint32_t r) const
+    // A lane's elements in a radix pass are raw indices in increasing order,
+    // at most one wavefront (64) apart: the first one's (i, j) is found by
+    // division, and from it on (i, j) steps forward without one whenever
+    // tb >= 64 (one row end at most per step).
+    struct Cursor {
+        uint32_t i, j, r;
+    };
+    __device__ uint64_t first(uint32_t r, Cursor &c) const
     {
         // r / tb in double precision (within one of the quotient for 32-bit r), then corrected
         uint32_t i = (uint32_t)((double)r * inv_tb);
         if (i * (uint64_t)tb > r) --i;
         else if ((uint64_t)(i + 1) * tb <= r) ++i;
-        return ka[i] + kb[r - i * tb];
+        c.i = i;
+        c.j = r - i * tb;
+        c.r = r;
+        return ka[c.i] + kb[c.j];
+    }
+    __device__ uint64_t next(uint32_t r, Cursor &c) const   // r >= c.r, r - c.r <= 64
+    {
+        if (tb < 64) return first(r, c);
+        c.j += r - c.r;
+        c.r = r;
+        if (c.j >= tb) {
+            c.j -= tb;
+            ++c.i;
+        }
+        return ka[c.i] + kb[c.j];
     }
 };
 

@@ -81,6 +81,7 @@ __global__ void __launch_bounds__(GS_HIST_THREADS) k_gs_hist(const uint64_t *key
         for (int d = lane; d < NB; d += kWave) cnt[d] = 0;
         const int64_t t0 = tile * GS_TILE;
         const int m = (int)(R - t0 < GS_TILE ? R - t0 : GS_TILE);
+        GsGen::Cursor cur;
         for (int c0 = 0; c0 < m; c0 += UN * kWave) {
             // loads unconditional (index clamped into the tile) so all UN are in
             // flight together; lanes past the tile get the padding digit
@@ -89,7 +90,8 @@ __global__ void __launch_bounds__(GS_HIST_THREADS) k_gs_hist(const uint64_t *key
             for (int u = 0; u < UN; ++u) {
                 const int l = c0 + u * kWave + lane;
                 const int64_t g = t0 + (l < m ? l : m - 1);
-                kv[u] = GEN ? gen.key((uint32_t)g) : keys[g];
+                if (GEN) kv[u] = (c0 == 0 && u == 0) ? gen.first((uint32_t)g, cur) : gen.next((uint32_t)g, cur);
+                else kv[u] = keys[g];
             }
             uint32_t dg[UN];
 #pragma unroll
@@ -144,7 +146,10 @@ __global__ void __launch_bounds__(GS_SC_THREADS) k_gs_scatter(const uint64_t *ke
     constexpr bool HAS_VALS = MODE != GS_PACKED;
     constexpr bool GEN = MODE == GS_GEN_KV || MODE == GS_GEN_TO_PACKED;
     __shared__ uint64_t s_key[GS_TILE];
-    __shared__ uint32_t s_val[HAS_VALS ? GS_TILE : 1];
+    // raw indices staged beside the keys; generated ones are t0 + (offset in
+    // the tile), so 16 bits each (LDS for three workgroups per CU, not two)
+    __shared__ uint32_t s_val[HAS_VALS && !GEN ? GS_TILE : 1];
+    __shared__ uint16_t s_gen[GEN ? GS_TILE : 1];
     __shared__ uint32_t s_cnt[W][NB];
     __shared__ uint32_t s_tot[NB];
     __shared__ uint32_t s_start[NB];
@@ -157,13 +162,14 @@ __global__ void __launch_bounds__(GS_SC_THREADS) k_gs_scatter(const uint64_t *ke
     uint64_t k[GS_ITEMS];
     uint32_t v[GS_ITEMS], dg[GS_ITEMS], rank[GS_ITEMS];
     // loads unconditional (index clamped into the tile) so all are in flight together
+    GsGen::Cursor cur;
 #pragma unroll
     for (int it = 0; it < GS_ITEMS; ++it) {
         const int e = (w * GS_ITEMS + it) * kWave + lane;
         const int ec = e < m ? e : m - 1;
         if (GEN) {
             v[it] = (uint32_t)(t0 + ec);
-            k[it] = gen.key(v[it]);
+            k[it] = it == 0 ? gen.first(v[it], cur) : gen.next(v[it], cur);
         } else {
             k[it] = keys_in[t0 + ec];
             v[it] = HAS_VALS ? vals_in[t0 + ec] : 0u;
@@ -229,18 +235,20 @@ __global__ void __launch_bounds__(GS_SC_THREADS) k_gs_scatter(const uint64_t *ke
         const uint32_t d = dg[it];
         const uint32_t lp = s_start[d] + s_cnt[w][d] + rank[it];
         s_key[lp] = k[it];
-        if (HAS_VALS) s_val[lp] = v[it];
+        if (GEN) s_gen[lp] = (uint16_t)(v[it] - (uint32_t)t0);
+        else if (HAS_VALS) s_val[lp] = v[it];
     }
     __syncthreads();
     for (int l = threadIdx.x; l < m; l += GS_SC_THREADS) {
         const uint64_t key = s_key[l];
         const uint32_t d = (uint32_t)(key >> shift) & (NB - 1);
         const int64_t gpos = hist_off[(int64_t)d * nblocks + blockIdx.x] + (l - (int64_t)s_start[d]);
+        const uint32_t val = GEN ? (uint32_t)t0 + s_gen[l] : (HAS_VALS ? s_val[l] : 0u);
         if (MODE == GS_KV || MODE == GS_GEN_KV) {
             keys_out[gpos] = key;
-            vals_out[gpos] = s_val[l];
+            vals_out[gpos] = val;
         } else if (MODE == GS_KV_TO_PACKED || MODE == GS_GEN_TO_PACKED) {
-            keys_out[gpos] = ((key >> DB) << raw_bits) | (uint64_t)s_val[l];
+            keys_out[gpos] = ((key >> DB) << raw_bits) | (uint64_t)val;
         } else {
             keys_out[gpos] = key;
         }
