@@ -154,6 +154,13 @@ def main():
     gb = ph.simplify(ph.batch_from_numpy(gm.row_ptr, gm.exps, gm.coefs, n=gm.n, max_exp=gm.max_exp))
     GX = torch.from_numpy(gm.X).cuda()
     sweep("deriv_fused_max_n", [0, 255], lambda: ph.grad(gb, GX), log)
+    # dense FP64 contraction: rows of C per workgroup, on a sixteenth of the
+    # 4,096 x 46,376 x 65,536 shape (the full degree-4 basis in 30 variables)
+    dw = W.dense_shared(P=1024, N=16384)
+    dbasis, dC, dX = (torch.from_numpy(x).cuda() for x in (dw.basis, dw.C, dw.X))
+    dY = torch.empty((dC.shape[0], dX.shape[0]), dtype=torch.float64, device="cuda")
+    sweep("dense_f64_rows", [64, 128], lambda: ph.eval_dense(dbasis, dC, dX, Y=dY), log)
+    del dbasis, dC, dX, dY
     res = {"arch": "gfx950", "tool": "paper_2604_06575_amd.autotune", "date": time.strftime("%Y-%m-%d"),
            "tunables": {k: v["best"] for k, v in log.items()}, "sweeps": log}
     os.makedirs(os.path.dirname(args.out), exist_ok=True)

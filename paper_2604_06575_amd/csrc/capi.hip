@@ -25,6 +25,7 @@ std::atomic<int64_t> g_mul_sort_min_raw{int64_t(1) << 20};
 std::atomic<int64_t> g_simplify_wide_min{SEG_CAP + 1};
 std::atomic<int64_t> g_deriv_fused_max_n{0};
 std::atomic<int64_t> g_sort_digit_bits{8};
+std::atomic<int64_t> g_dense_f64_rows{128};
 
 struct TuneEntry {
     const char *name;
@@ -39,6 +40,7 @@ const TuneEntry kTune[] = {
     {"simplify_wide_min", &g_simplify_wide_min, 1, int64_t(1) << 62},
     {"deriv_fused_max_n", &g_deriv_fused_max_n, 0, 255},
     {"sort_digit_bits", &g_sort_digit_bits, GS_MIN_BITS, GS_MAX_BITS},
+    {"dense_f64_rows", &g_dense_f64_rows, 64, 128},
 };
 }  // namespace
 
@@ -50,7 +52,7 @@ Tunables tunables()
 {
     return Tunables{g_mul_bucket_terms.load(), g_seg_blocks_per_cu.load(), g_eval_blocks_per_cu.load(),
                     g_mul_sort_min_raw.load(), g_simplify_wide_min.load(), g_deriv_fused_max_n.load(),
-                    g_sort_digit_bits.load()};
+                    g_sort_digit_bits.load(), g_dense_f64_rows.load()};
 }
 
 }  // namespace polyhip
@@ -989,6 +991,7 @@ poly_status poly_tune_set(const char *name, int64_t value)
     for (const TuneEntry &e : kTune) {
         if (strcmp(e.name, name) == 0) {
             if (value < e.lo || value > e.hi) return POLY_ERR_ARG;
+            if (e.value == &g_dense_f64_rows && value != 64 && value != 128) return POLY_ERR_ARG;
             e.value->store(value);
             return POLY_OK;
         }

@@ -90,53 +90,58 @@ __device__ inline unsigned short bf16_bits_exact(float f)
 
 // ------------------------------------------------------------ FP64 kernel
 
-constexpr int D64_BM = 64, D64_BN = 128, D64_KS = 16, D64_THREADS = 256;
+constexpr int D64_BN = 128, D64_KS = 16, D64_THREADS = 256;   // rows per workgroup: BM, 64 or 128
 
 // grid: x = N tiles (fastest, so concurrently running workgroups share a C
-// row panel), y = P tiles.  Dynamic LDS: (n + 1) * D64_BN doubles for the
+// row panel), y = P tiles of BM rows (64 or 128: each wave holds BM / 32
+// row tiles of 16 against four column tiles, so a V tile formed in LDS feeds
+// BM rows).  Dynamic LDS: (n + 1) * D64_BN doubles for the
 // points and a row of ones.  Each K step: the C tile and the factor lists of
 // the step after next are loaded into registers (buffer loads, so the only
 // per-thread addresses are 32-bit offsets and no load waits on another),
 // the MFMAs of this step run, and the V tile of the next step is formed from
 // factor lists staged in LDS one step ahead.
+template <int BM>
 __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, const uint8_t *basis,
                                                            const uint4 *enc, int64_t P, const double *C,
                                                            int64_t N, const double *X, double *Y, int64_t ys)
 {
+    constexpr int RT = BM / 32;                        // 16-row MFMA tiles per wave
+    constexpr int TPR = D64_THREADS / BM, CPT = D64_KS / TPR;   // C tile loads: threads per row, entries per thread
     extern __shared__ double s_x[];                    // [n + 1][D64_BN], last row ones
-    __shared__ double s_c[D64_BM][D64_KS + 1];
+    __shared__ double s_c[BM][D64_KS + 1];
     __shared__ double s_v[D64_KS][D64_BN + 2];
     __shared__ uint4 s_enc[2][D64_KS];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = tid >> 6;
-    const int wr = w >> 1, wc = w & 1;                 // wave: 32 rows x 64 points
-    const int64_t r0 = (int64_t)blockIdx.y * D64_BM;
+    const int wr = w >> 1, wc = w & 1;                 // wave: BM / 2 rows x 64 points
+    const int64_t r0 = (int64_t)blockIdx.y * BM;
     const int64_t n0 = (int64_t)blockIdx.x * D64_BN;
     for (int idx = tid; idx < (n + 1) * D64_BN; idx += D64_THREADS) {
         const int i = idx / D64_BN, c = idx % D64_BN;
         const int64_t pt = n0 + c;
         s_x[idx] = i == n ? 1.0 : (pt < N ? X[pt * n + i] : 0.0);
     }
-    d4v acc[2][4];
+    d4v acc[RT][4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < RT; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
     // load roles: C tile row/k of this thread, V tile point/k of this thread
-    const int crow = tid >> 2, ckk = (tid & 3) * 4;
+    const int crow = tid / TPR, ckk = (tid % TPR) * CPT;
     const int vcol = tid & (D64_BN - 1), vkb = (tid >> 7) * 8;
     // this block's rows of C as one buffer: rows past P read as zero; the
-    // host keeps D64_BM * K * 8 bytes below 2^31
-    const int rows_here = (int)(P - r0 < D64_BM ? P - r0 : D64_BM);
+    // host keeps BM * K * 8 bytes below 2^31
+    const int rows_here = (int)(P - r0 < BM ? P - r0 : BM);
     const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc((void *)(C + r0 * K), (short)0,
                                                                        rows_here * (int)K * 8, 0x00020000);
     const int cbase = (crow * (int)K + ckk) * 8;
-    double creg[4], vreg[8];
+    double creg[CPT], vreg[8];
     uint4 ereg = make_uint4(0, 0, 0, 0);
     auto load_c = [&](int64_t kk) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q)   // entries past K (next row's) are masked when stored
+        for (int q = 0; q < CPT; ++q)   // entries past K (next row's) are masked when stored
             creg[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rc, cbase + ((int)kk + q) * 8, 0, 0));
     };
     auto load_enc = [&](int64_t kk) {   // factor lists of k = kk + tid, tid < D64_KS (zero past K)
@@ -165,7 +170,7 @@ __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, con
     for (int64_t k0 = 0; k0 < K; k0 += D64_KS) {
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s_c[crow][ckk + q] = k0 + ckk + q < K ? creg[q] : 0.0;
+        for (int q = 0; q < CPT; ++q) s_c[crow][ckk + q] = k0 + ckk + q < K ? creg[q] : 0.0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) s_v[vkb + q][vcol] = vreg[q];
         if (tid < D64_KS) s_enc[par][tid] = ereg;
@@ -178,13 +183,13 @@ __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, con
         }
 #pragma unroll
         for (int k4 = 0; k4 < D64_KS; k4 += 4) {
-            double a[2], b[4];
+            double a[RT], b[4];
 #pragma unroll
-            for (int rt = 0; rt < 2; ++rt) a[rt] = s_c[wr * 32 + rt * 16 + (lane & 15)][k4 + (lane >> 4)];
+            for (int rt = 0; rt < RT; ++rt) a[rt] = s_c[wr * (BM / 2) + rt * 16 + (lane & 15)][k4 + (lane >> 4)];
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct) b[ct] = s_v[k4 + (lane >> 4)][wc * 64 + ct * 16 + (lane & 15)];
 #pragma unroll
-            for (int rt = 0; rt < 2; ++rt)
+            for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                 for (int ct = 0; ct < 4; ++ct)
                     acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b[ct], acc[rt][ct], 0, 0, 0);
@@ -194,14 +199,14 @@ __global__ void __launch_bounds__(D64_THREADS) k_dense_f64(int n, int64_t K, con
         par ^= 1;
     }
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 // v_mfma_f64_16x16x4f64 result: lane l, register v holds
                 // row (l / 16) + 4 v, column l % 16 of the 16 x 16 tile
-                const int64_t r = r0 + wr * 32 + rt * 16 + (lane >> 4) + 4 * v;
+                const int64_t r = r0 + wr * (BM / 2) + rt * 16 + (lane >> 4) + 4 * v;
                 const int64_t c = n0 + wc * 64 + ct * 16 + (lane & 15);
                 if (r < P && c < N) Y[(r * N + c) * ys] = acc[rt][ct][v];
             }
@@ -1349,9 +1354,10 @@ poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_ex
     if (!ws || ws_bytes < need) return POLY_ERR_WORKSPACE;
     if (prec == POLY_FP64 && (size_t)(n + 1) * D64_BN * 8 > 96 * 1024) return POLY_ERR_UNSUPPORTED;
     if (prec == POLY_SPLIT_BF16 && split_lds_bytes(n, S) > 160 * 1024) return POLY_ERR_UNSUPPORTED;
-    // both kernels address one block's rows of C (64 x K doubles, or 256 x Kp
-    // BF16 digits of one plane) with 32-bit byte offsets
-    if ((int64_t)align_up((size_t)K, 32) * 512 + 256 > INT32_MAX) return POLY_ERR_UNSUPPORTED;
+    // both kernels address one block's rows of C (up to 128 x K doubles, or
+    // 256 x Kp BF16 digits of one plane) with 32-bit byte offsets
+    const int bm = prec == POLY_FP64 && tunables().dense_f64_rows == 128 ? 128 : 64;
+    if ((int64_t)align_up((size_t)K, 32) * 8 * bm + 256 > INT32_MAX) return POLY_ERR_UNSUPPORTED;
     const DensePlan d = plan_dense(n, K, P, N, prec, S);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (unsigned long long *)ws, 0ull, (int64_t)1);
     if (P == 0 || N == 0) return hipGetLastError() == hipSuccess ? POLY_OK : POLY_ERR_HIP;
@@ -1362,13 +1368,22 @@ poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_ex
     if (prec == POLY_FP64) {
         static bool attr = false;
         if (!attr) {
-            (void)hipFuncSetAttribute((const void *)k_dense_f64, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+            // the points tile is at most 96 KB (checked above); with the static
+            // tiles of the 128-row form that is within the 160 KB of a CU
+            (void)hipFuncSetAttribute((const void *)k_dense_f64<64>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      96 * 1024);
+            (void)hipFuncSetAttribute((const void *)k_dense_f64<128>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      96 * 1024);
             attr = true;
         }
-        const dim3 grid((unsigned)ceil_div(N, D64_BN), (unsigned)ceil_div(P, D64_BM));
+        const dim3 grid((unsigned)ceil_div(N, D64_BN), (unsigned)ceil_div(P, bm));
         TimedLaunch tl(POLY_TIMING_DENSE, s);
-        hipLaunchKernelGGL(k_dense_f64, grid, dim3(D64_THREADS), (size_t)(n + 1) * D64_BN * 8, s, n, K, basis,
-                           (const uint4 *)enc, P, C, N, X, Y, ys);
+        if (bm == 128)
+            hipLaunchKernelGGL(k_dense_f64<128>, grid, dim3(D64_THREADS), (size_t)(n + 1) * D64_BN * 8, s, n, K,
+                               basis, (const uint4 *)enc, P, C, N, X, Y, ys);
+        else
+            hipLaunchKernelGGL(k_dense_f64<64>, grid, dim3(D64_THREADS), (size_t)(n + 1) * D64_BN * 8, s, n, K,
+                               basis, (const uint4 *)enc, P, C, N, X, Y, ys);
         tl.done(s);
     } else {
         unsigned short *Cs = (unsigned short *)((char *)ws + d.cs);

@@ -15,6 +15,7 @@ struct Tunables {
     int64_t simplify_wide_min;
     int64_t deriv_fused_max_n;
     int64_t sort_digit_bits;
+    int64_t dense_f64_rows;
 };
 Tunables tunables();
 int sort_bits();

@@ -190,6 +190,13 @@ def test_tunables_roundtrip():
         ph.tune_set("no_such_knob", 1)
     with pytest.raises(ph.PolyError):
         ph.tune_set("seg_blocks_per_cu", 0)
+    old = ph.tune_get("dense_f64_rows")
+    for bad in (96, 63, 256):
+        with pytest.raises(ph.PolyError):
+            ph.tune_set("dense_f64_rows", bad)
+    ph.tune_set("dense_f64_rows", 128)
+    assert ph.tune_get("dense_f64_rows") == 128
+    ph.tune_set("dense_f64_rows", old)
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

@@ -424,6 +424,22 @@ def test_dense_several_workgroup_tiles(ph, split):
     assert err.max() <= (1e-10 if split else 1e-12)
 
 
+@pytest.mark.parametrize("rows", [64, 128])
+def test_dense_fp64_row_tiles(ph, rows):
+    """The FP64 contraction with 64 or 128 rows of C per workgroup (the
+    dense_f64_rows tunable): P = 300 leaves a partial row tile either way,
+    K = 700 a ragged last step, N = 130 a ragged point tile; degrees to 14
+    in two variables take every factor-list form."""
+    old = ph.tune_get("dense_f64_rows")
+    try:
+        ph.tune_set("dense_f64_rows", rows)
+        for wl in (W.dense_shared(seed=962, P=300, N=130, n=9, d=4, K=700), W.dense_shared(seed=963, P=45, N=77, n=2, d=14)):
+            say(f"dense fp64 rows={rows} P={wl.C.shape[0]} K={wl.basis.shape[0]}")
+            assert _dense_case(ph, wl, ph.POLY_FP64).max() <= 1e-12
+    finally:
+        ph.tune_set("dense_f64_rows", old)
+
+
 def test_dense_empty_basis(ph):
     """K = 0: every output is the empty sum, 0."""
     basis = torch.zeros((0, 3), dtype=torch.uint8, device="cuda")
