@@ -117,8 +117,9 @@ poly_status poly_read_status(const void *ws, void *stream);
  *        "sort_digit_bits"   widest digit (4..11 bits) of the global radix
  *                            sorts (times of one large pair, device-wide
  *                            simplify, mtimes): fewer, wider passes
- *        "dense_f64_rows"    rows of C per workgroup of the FP64 dense
- *                            contraction (poly_eval_dense): 64 or 128
+ *        "dense_f64_rows"    rows per workgroup of the FP64 dense
+ *                            contraction (poly_eval_dense) and of the dC
+ *                            of its reverse mode: 64 or 128
  *        "deriv_fused_max_n" largest n for which poly_grad and the dX of
  *                            poly_eval_backward stream derivatives straight
  *                            from the source terms (0: always through the

@@ -227,32 +227,35 @@ constexpr int DB_BM = 64, DB_BN = 128, DB_KS = 16, DB_THREADS = 256;
 // of 16.  Each thread owns one monomial column (its factor list held in
 // registers) and forms 8 of its values per step from the step's points,
 // staged in LDS (dynamic: (n + 1) * 16 doubles, last row ones).
+template <int BM>
 __global__ void __launch_bounds__(DB_THREADS) k_dense_bwd_dc(int n, int64_t K, const uint8_t *basis, const uint4 *enc,
                                                             int64_t P, const double *gY, int64_t N, const double *X,
                                                             double *dC)
 {
+    constexpr int RT = BM / 32;                      // 16-row MFMA tiles per wave
+    constexpr int TPR = DB_THREADS / BM, CPT = DB_KS / TPR;   // gY tile loads: threads per row, points per thread
     extern __shared__ double s_xp[];                 // [n + 1][DB_KS]
-    __shared__ double s_a[DB_BM][DB_KS + 1];
+    __shared__ double s_a[BM][DB_KS + 1];
     __shared__ double s_b[DB_KS][DB_BN + 2];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = tid >> 6;
     const int wr = w >> 1, wc = w & 1;
-    const int64_t r0 = (int64_t)blockIdx.y * DB_BM;
+    const int64_t r0 = (int64_t)blockIdx.y * BM;
     const int64_t k0 = (int64_t)blockIdx.x * DB_BN;
     const int vcol = tid & (DB_BN - 1), vpb = (tid >> 7) * 8;
     const int64_t kcol = k0 + vcol;
     const uint4 my_enc = kcol < K ? enc[kcol] : make_uint4(0, 0, 0, 0);
-    const int arow = tid >> 2, acol = (tid & 3) * 4;
-    d4v acc[2][4];
+    const int arow = tid / TPR, acol = (tid % TPR) * CPT;
+    d4v acc[RT][4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < RT; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = (d4v){0.0, 0.0, 0.0, 0.0};
     for (int64_t p0 = 0; p0 < N; p0 += DB_KS) {
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < CPT; ++q) {
             const int64_t r = r0 + arow, pt = p0 + acol + q;
             s_a[arow][acol + q] = (r < P && pt < N) ? gY[r * N + pt] : 0.0;
         }
@@ -269,25 +272,25 @@ __global__ void __launch_bounds__(DB_THREADS) k_dense_bwd_dc(int n, int64_t K, c
         __syncthreads();
 #pragma unroll
         for (int k4 = 0; k4 < DB_KS; k4 += 4) {
-            double a[2], b[4];
+            double a[RT], b[4];
 #pragma unroll
-            for (int rt = 0; rt < 2; ++rt) a[rt] = s_a[wr * 32 + rt * 16 + (lane & 15)][k4 + (lane >> 4)];
+            for (int rt = 0; rt < RT; ++rt) a[rt] = s_a[wr * (BM / 2) + rt * 16 + (lane & 15)][k4 + (lane >> 4)];
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct) b[ct] = s_b[k4 + (lane >> 4)][wc * 64 + ct * 16 + (lane & 15)];
 #pragma unroll
-            for (int rt = 0; rt < 2; ++rt)
+            for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                 for (int ct = 0; ct < 4; ++ct)
                     acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b[ct], acc[rt][ct], 0, 0, 0);
         }
     }
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t r = r0 + wr * 32 + rt * 16 + (lane >> 4) + 4 * v;
+                const int64_t r = r0 + wr * (BM / 2) + rt * 16 + (lane >> 4) + 4 * v;
                 const int64_t c = k0 + wc * 64 + ct * 16 + (lane & 15);
                 if (r < P && c < K) dC[r * K + c] = acc[rt][ct][v];
             }
@@ -1530,7 +1533,9 @@ poly_status dense_bwd_run(int32_t n, int64_t K, const uint8_t *basis, int32_t ma
     if (!attr) {
         (void)hipFuncSetAttribute((const void *)k_dense_bwd_dx, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)DB_DX_LDS_MAX);
-        (void)hipFuncSetAttribute((const void *)k_dense_bwd_dc, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute((const void *)k_dense_bwd_dc<64>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  64 * 1024);
+        (void)hipFuncSetAttribute((const void *)k_dense_bwd_dc<128>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   64 * 1024);
         attr = true;
     }
@@ -1567,10 +1572,15 @@ poly_status dense_bwd_run(int32_t n, int64_t K, const uint8_t *basis, int32_t ma
             default: launch_bwd_dc_split<5>(n, K, basis, fenc, P, Gs, N, d.Np, X, sig_w, dC, s); break;
             }
         } else {
-            const dim3 grid((unsigned)ceil_div(K, DB_BN), (unsigned)ceil_div(P, DB_BM));
+            const int bm = tunables().dense_f64_rows == 128 ? 128 : 64;
+            const dim3 grid((unsigned)ceil_div(K, DB_BN), (unsigned)ceil_div(P, bm));
             TimedLaunch tl(POLY_TIMING_DENSE, s);
-            hipLaunchKernelGGL(k_dense_bwd_dc, grid, dim3(DB_THREADS), (size_t)(n + 1) * DB_KS * 8, s, n, K, basis,
-                               (const uint4 *)fenc, P, gY, N, X, dC);
+            if (bm == 128)
+                hipLaunchKernelGGL(k_dense_bwd_dc<128>, grid, dim3(DB_THREADS), (size_t)(n + 1) * DB_KS * 8, s, n, K,
+                                   basis, (const uint4 *)fenc, P, gY, N, X, dC);
+            else
+                hipLaunchKernelGGL(k_dense_bwd_dc<64>, grid, dim3(DB_THREADS), (size_t)(n + 1) * DB_KS * 8, s, n, K,
+                                   basis, (const uint4 *)fenc, P, gY, N, X, dC);
             tl.done(s);
         }
     }
