@@ -427,9 +427,10 @@ def test_dense_several_workgroup_tiles(ph, split):
 @pytest.mark.parametrize("rows", [64, 128])
 def test_dense_fp64_row_tiles(ph, rows):
     """The FP64 contraction and the reverse mode's dC with 64 or 128 rows per
-    workgroup (the dense_f64_rows tunable): P = 300 leaves a partial row tile
-    either way, K = 700 a ragged last step, N = 130 a ragged point tile;
-    degrees to 14 in two variables take every factor-list form."""
+    workgroup (the dense_f64_rows tunable), and dX beside them: P = 300
+    leaves a partial row tile either way, K = 700 a ragged last step, N = 130
+    a ragged point tile; degrees to 14 in two variables take every
+    factor-list form."""
     old = ph.tune_get("dense_f64_rows")
     try:
         ph.tune_set("dense_f64_rows", rows)
@@ -439,13 +440,14 @@ def test_dense_fp64_row_tiles(ph, rows):
             # the reverse mode's dC takes the same row tile
             P, Kr = wl.C.shape
             gY = W.rng_for(964).standard_normal((P, wl.X.shape[0]))
-            dC, _ = ph.eval_dense_backward(torch.from_numpy(wl.basis).cuda(), torch.from_numpy(wl.C).cuda(),
-                                           torch.from_numpy(wl.X).cuda(), torch.from_numpy(gY).cuda(), want_dX=False)
+            dC, dX = ph.eval_dense_backward(torch.from_numpy(wl.basis).cuda(), torch.from_numpy(wl.C).cuda(),
+                                            torch.from_numpy(wl.X).cuda(), torch.from_numpy(gY).cuda())
             rp = np.arange(P + 1, dtype=np.int64) * Kr
             E = np.tile(wl.basis, (P, 1))
-            _, dCo = oracle.eval_backward(rp, E, wl.C.ravel(), wl.X, gY)
-            _, aC = oracle.eval_backward(rp, E, np.abs(wl.C.ravel()), np.abs(wl.X), np.abs(gY))
+            dXo, dCo = oracle.eval_backward(rp, E, wl.C.ravel(), wl.X, gY)
+            aX, aC = oracle.eval_backward(rp, E, np.abs(wl.C.ravel()), np.abs(wl.X), np.abs(gY))
             assert (np.abs(dC.cpu().numpy().ravel() - dCo) <= 1e-12 * aC + 1e-300).all()
+            assert (np.abs(dX.cpu().numpy() - dXo) <= 1e-12 * aX + 1e-300).all()
     finally:
         ph.tune_set("dense_f64_rows", old)
 
