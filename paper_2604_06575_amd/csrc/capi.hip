@@ -2355,8 +2355,8 @@ static BackwardPlan plan_backward(const poly_csr *f, int64_t N, Layout &L)
     } else {
         b.g = plan_grad_formed(f, N, L, true);
     }
-    b.senc = L.take(16 * T);
-    b.cp = std::max(1, std::min(BWC_POINTS, 8192 / n));
+    b.senc = L.take(16 * T);   // factor lists of the dC kernel
+    b.cp = std::max(1, std::min(BWC_POINTS, 8192 / (n + 1)));
     b.nchunks = ceil_div(N, b.cp);
     b.part = L.take(8 * T * b.nchunks);
     return b;
@@ -2397,11 +2397,11 @@ static void launch_dc(const poly_csr *f, const double *X, int64_t N, const doubl
         clear_u64((unsigned long long *)dC, T, s);
         return;
     }
-    hipLaunchKernelGGL(k_encode_support, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, senc,
+    hipLaunchKernelGGL(k_encode_factors, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, (uint32_t *)senc,
                        (const int64_t *)nullptr);
-    const size_t lds = (size_t)cp * n * sizeof(double);
-    hipLaunchKernelGGL(k_backward_dc, dim3(grid1(T, BWC_THREADS), (unsigned)nchunks), dim3(BWC_THREADS), lds, s,
-                       f->row_ptr, P, f->exps, n, T, X, N, gY, part, nchunks, (const uint64_t *)senc, cp);
+    const size_t lds = (size_t)cp * (n + 1) * sizeof(double);
+    hipLaunchKernelGGL(k_backward_dc, dim3(grid1(T, BWC_TERMS * BWC_THREADS), (unsigned)nchunks), dim3(BWC_THREADS),
+                       lds, s, f->row_ptr, P, f->exps, n, T, X, N, gY, part, nchunks, (const uint4 *)senc, cp);
     hipLaunchKernelGGL(k_backward_dc_reduce, dim3(grid1(T, 256)), dim3(256), 0, s, (const double *)part, T, nchunks,
                        dC);
 }

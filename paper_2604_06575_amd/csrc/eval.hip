@@ -326,32 +326,6 @@ __device__ inline double powi(double x, uint32_t e)
     return p;
 }
 
-// Monomial value of encoded term t at the point whose coordinates are
-// x[i * xs] (i = variable).
-__device__ inline double term_value(const uint64_t *enc, const uint8_t *exps, int n, int64_t t, const double *x,
-                                    int xs)
-{
-    const uint64_t w0 = enc[2 * t];
-    const uint64_t w1 = enc[2 * t + 1];
-    double v = 1.0;
-    if ((w0 & 0xffffull) == 0xffffull) {
-        const uint8_t *row = exps + t * n;
-        for (int i = 0; i < n; ++i) {
-            const uint32_t e = row[i];
-            if (e) v = v * powi(x[i * xs], e);
-        }
-        return v;
-    }
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        const uint32_t ent = (uint32_t)(((s < 4 ? w0 : w1) >> (16 * (s & 3))) & 0xffffu);
-        const uint32_t e = ent >> 8;
-        if (e == 0) break;
-        v = v * powi(x[(ent & 0xffu) * xs], e);
-    }
-    return v;
-}
-
 __device__ inline void store_out(const EvalArgs &A, int64_t q, int64_t pt, double y)
 {
     if (A.mode == OUT_EVAL) {
@@ -589,33 +563,72 @@ __global__ void k_eval_reduce(EvalArgs A, const double *partial, int64_t S)
 
 // --------------------------------------------------------------- backward
 
-// Partial dC over one chunk of points: lanes are terms.
-// grid: x = term blocks of 256, y = point chunks.  Dynamic LDS: cp * n doubles.
+// Partial dC over one chunk of points: lanes are terms.  Each lane holds its
+// term's factor list (k_encode_factors: up to EV_MAX_DEG variable indices,
+// padded with n, the index of the one that ends every point's coordinates in
+// LDS), so a term of degree <= 4 costs four LDS reads and four
+// multiplications per point with no branch; longer lists take their other
+// words, degrees beyond EV_MAX_DEG the exponent row.  A thread takes
+// BWC_TERMS terms (BWC_THREADS apart) against one staging of the chunk.
+// grid: x = term blocks of BWC_TERMS * BWC_THREADS, y = point chunks.
+// Dynamic LDS: cp * (n + 1) doubles, point-major.
 __global__ void __launch_bounds__(BWC_THREADS) k_backward_dc(const int64_t *rp, int64_t P, const uint8_t *exps,
                                                              int n, int64_t T, const double *X, int64_t N,
                                                              const double *gY, double *partial, int64_t nchunks,
-                                                             const uint64_t *enc, int cp)
+                                                             const uint4 *fenc, int cp)
 {
     extern __shared__ double s_xc[];
     const int64_t c = blockIdx.y;
     const int64_t pt0 = c * cp;
     const int np = (int)((N - pt0) < cp ? (N - pt0) : cp);
-    for (int idx = threadIdx.x; idx < np * n; idx += BWC_THREADS) s_xc[idx] = X[pt0 * n + idx];
+    const int ld = n + 1;
+    for (int idx = threadIdx.x; idx < np * ld; idx += BWC_THREADS) {
+        const int q = idx / ld, i = idx % ld;
+        s_xc[idx] = i == n ? 1.0 : X[(pt0 + q) * n + i];
+    }
     __syncthreads();
-    const int64_t t = (int64_t)blockIdx.x * BWC_THREADS + threadIdx.x;
-    if (t >= T) return;
-    int64_t lo = 0, hi = P - 1;   // polynomial of term t
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (rp[mid] <= t) lo = mid;
-        else hi = mid - 1;
+    for (int r = 0; r < BWC_TERMS; ++r) {
+        const int64_t t = ((int64_t)blockIdx.x * BWC_TERMS + r) * BWC_THREADS + threadIdx.x;
+        if (t >= T) return;
+        int64_t lo = 0, hi = P - 1;   // polynomial of term t
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (rp[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const double *g = gY + lo * N + pt0;
+        const uint4 e = fenc[t];
+        double acc = 0.0;
+        if (e.w <= 4u) {
+            const int i0 = (int)(e.x & 0xffu), i1 = (int)((e.x >> 8) & 0xffu);
+            const int i2 = (int)((e.x >> 16) & 0xffu), i3 = (int)(e.x >> 24);
+            for (int q = 0; q < np; ++q) {
+                const double *xq = s_xc + q * ld;
+                acc += g[q] * (((xq[i0] * xq[i1]) * xq[i2]) * xq[i3]);
+            }
+        } else if (e.w <= (uint32_t)EV_MAX_DEG) {
+            const uint32_t wd[3] = {e.x, e.y, e.z};
+            const int nw = (int)((e.w + 3) / 4);
+            for (int q = 0; q < np; ++q) {
+                const double *xq = s_xc + q * ld;
+                double v = 1.0;
+                for (int k = 0; k < nw; ++k)
+                    v = (((v * xq[wd[k] & 0xffu]) * xq[(wd[k] >> 8) & 0xffu]) * xq[(wd[k] >> 16) & 0xffu]) *
+                        xq[wd[k] >> 24];
+                acc += g[q] * v;
+            }
+        } else {
+            const uint8_t *row = exps + t * n;
+            for (int q = 0; q < np; ++q) {
+                const double *xq = s_xc + q * ld;
+                double v = 1.0;
+                for (int i = 0; i < n; ++i)
+                    if (row[i]) v = v * powi(xq[i], row[i]);
+                acc += g[q] * v;
+            }
+        }
+        partial[c * T + t] = acc;
     }
-    const double *g = gY + lo * N + pt0;
-    double acc = 0.0;
-    for (int q = 0; q < np; ++q) {
-        acc += g[q] * term_value(enc, exps, n, t, s_xc + q * n, 1);
-    }
-    partial[c * T + t] = acc;
 }
 
 __global__ void k_backward_dc_reduce(const double *partial, int64_t T, int64_t nchunks, double *dC)

@@ -316,9 +316,10 @@ constexpr int DV_ACC_PITCH = 65;                 // doubles per accumulator row 
 constexpr size_t DV_LDS_MAX = 160 * 1024;        // LDS of one workgroup on gfx950
 constexpr int BWC_THREADS = 256;
 constexpr int BWC_POINTS = 512;   // points per chunk
+constexpr int BWC_TERMS = 4;      // terms per thread
 __global__ void k_backward_dc(const int64_t *rp, int64_t P, const uint8_t *exps, int n, int64_t T, const double *X,
                               int64_t N, const double *gY, double *partial, int64_t nchunks,
-                              const uint64_t *enc, int cp);
+                              const uint4 *fenc, int cp);
 __global__ void k_backward_dc_reduce(const double *partial, int64_t T, int64_t nchunks, double *dC);
 
 }  // namespace polyhip
