@@ -91,6 +91,11 @@ T *at(void *ws, size_t off)
     return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
 }
 
+// the word of the workspace head beside the status word (cleared with it at
+// the start of every call): the largest degree class of the terms the
+// evaluation kernels stream (k_encode_factors)
+uint32_t *ws_maxdeg(void *ws) { return at<uint32_t>(ws, 4); }
+
 int device_cus()
 {
     static std::mutex mu;
@@ -559,6 +564,7 @@ void launch_eval_blocks(const EvalArgs &A, const uint32_t *enc, double *partial,
     const unsigned gy = (unsigned)std::min<int64_t>(std::min<int64_t>(ceil_div(A.Q * S, EV_WAVES), want), 65535);
     const size_t lds = (size_t)(A.n + 1) * kWave * sizeof(double);
     TimedLaunch tl(POLY_TIMING_TERMS, s);
+    if (A.maxdeg) hipLaunchKernelGGL(k_eval_terms_short, dim3(gx, gy), dim3(EV_THREADS), lds, s, A, enc, partial, S);
     hipLaunchKernelGGL(k_eval_terms, dim3(gx, gy), dim3(EV_THREADS), lds, s, A, enc, partial, S);
     tl.done(s);
     if (S > 1) hipLaunchKernelGGL(k_eval_reduce, dim3(grid1(A.Q * A.N, 256)), dim3(256), 0, s, A, partial, S);
@@ -657,6 +663,8 @@ void ensure_lds_attrs()
     std::lock_guard<std::mutex> g(lds_mu);
     if (lds_attr_done) return;
     (void)hipFuncSetAttribute((const void *)k_eval_terms, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
+    (void)hipFuncSetAttribute((const void *)k_eval_terms_short, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024 - 8192);
     (void)hipFuncSetAttribute((const void *)k_backward_dc, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
     (void)hipFuncSetAttribute((const void *)k_backward2_dc, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
     (void)hipFuncSetAttribute((const void *)k_hess_transpose, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
@@ -884,9 +892,10 @@ EvalArgs form_jacobian(const poly_csr *f, const double *X, int64_t N, void *ws, 
     F.capacity = g.cap;
     run_form(g.form, F, ws, s);
     hipLaunchKernelGGL(k_encode_factors, dim3(grid1(g.cap, 256)), dim3(256), 0, s, jexps, g.cap, n, jenc,
-                       (const int64_t *)(jrp + P * n));
+                       (const int64_t *)(jrp + P * n), ws_maxdeg(ws));
     EvalArgs A;
     memset(&A, 0, sizeof(A));
+    A.maxdeg = ws_maxdeg(ws);
     A.rp = jrp;
     A.exps = jexps;
     A.coefs = jcoefs;
@@ -936,6 +945,9 @@ poly_status run_wsum(const poly_csr *f, const double *X, int64_t N, const double
     const size_t lds = (size_t)(n + 1) * kWave * sizeof(double);
     double *part = g.S > 1 ? at<double>(ws, g.part) : nullptr;
     TimedLaunch tl(POLY_TIMING_TERMS, s);
+    if (A.maxdeg)
+        hipLaunchKernelGGL(k_eval_wsum_short, dim3(gx, gy), dim3(EV_THREADS), lds, s, A,
+                           (const uint32_t *)at<uint32_t>(ws, g.jenc), gY, f->npolys, g.S, dX, part);
     hipLaunchKernelGGL(k_eval_wsum, dim3(gx, gy), dim3(EV_THREADS), lds, s, A, (const uint32_t *)at<uint32_t>(ws, g.jenc),
                        gY, f->npolys, g.S, dX, part);
     tl.done(s);
@@ -1836,9 +1848,10 @@ poly_status poly_eval(const poly_csr *f, const double *X, int64_t N, double *Y, 
     }
     uint32_t *enc = at<uint32_t>(ws, o_enc);
     if (T > 0) hipLaunchKernelGGL(k_encode_factors, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, f->nvars, enc,
-                                  (const int64_t *)nullptr);
+                                  (const int64_t *)nullptr, ws_maxdeg(ws));
     EvalArgs A;
     memset(&A, 0, sizeof(A));
+    A.maxdeg = ws_maxdeg(ws);
     A.rp = f->row_ptr;
     A.exps = f->exps;
     A.coefs = f->coefs;
@@ -1963,9 +1976,10 @@ static poly_status run_hess(const poly_csr *f, const double *X, int64_t N, doubl
     F.capacity = h.hcap;
     run_form(h.hform, F, ws, s);
     hipLaunchKernelGGL(k_encode_factors, dim3(grid1(h.hcap, 256)), dim3(256), 0, s, hexps, h.hcap, n, henc,
-                       (const int64_t *)(hrp + P * n * n));
+                       (const int64_t *)(hrp + P * n * n), ws_maxdeg(ws));
     EvalArgs A;
     memset(&A, 0, sizeof(A));
+    A.maxdeg = ws_maxdeg(ws);
     A.rp = hrp;
     A.exps = hexps;
     A.coefs = hcoefs;
@@ -2245,7 +2259,7 @@ poly_status poly_affine_normal(const poly_csr *f, const double *X, int64_t N, do
     if ((st = run_hess(f, X, N, H, ws, a.h, s)) != POLY_OK) return st;
     if (T > 0)
         hipLaunchKernelGGL(k_encode_factors, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, enc,
-                           (const int64_t *)nullptr);
+                           (const int64_t *)nullptr, (uint32_t *)nullptr);
     TimedLaunch tl(POLY_TIMING_AFFINE, s);
     hipLaunchKernelGGL(k_affine_normal, dim3((unsigned)N), dim3(AN_THREADS), affine_lds_bytes(n), s, n,
                        (const uint4 *)enc, f->coefs, T, X, (const double *)G, H, reg, D, gnorm,
@@ -2301,7 +2315,7 @@ poly_status poly_affine_normal_stochastic(const poly_csr *f, const double *X, in
     uint32_t *enc = at<uint32_t>(ws, kWsHeadBytes);
     if (T > 0)
         hipLaunchKernelGGL(k_encode_factors, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, enc,
-                           (const int64_t *)nullptr);
+                           (const int64_t *)nullptr, (uint32_t *)nullptr);
     AffStochArgs A;
     A.n = n;
     A.enc = (const uint4 *)enc;
@@ -2398,7 +2412,7 @@ static void launch_dc(const poly_csr *f, const double *X, int64_t N, const doubl
         return;
     }
     hipLaunchKernelGGL(k_encode_factors, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, n, (uint32_t *)senc,
-                       (const int64_t *)nullptr);
+                       (const int64_t *)nullptr, (uint32_t *)nullptr);
     const size_t lds = (size_t)cp * (n + 1) * sizeof(double);
     hipLaunchKernelGGL(k_backward_dc, dim3(grid1(T, BWC_TERMS * BWC_THREADS), (unsigned)nchunks), dim3(BWC_THREADS),
                        lds, s, f->row_ptr, P, f->exps, n, T, X, N, gY, part, nchunks, (const uint4 *)senc, cp);
@@ -2687,9 +2701,10 @@ poly_status poly_plan_create(const poly_csr *in, double zero_tol, const double *
             if (N > 0) {
                 uint32_t *enc = at<uint32_t>(ws, pp.enc);
                 hipLaunchKernelGGL(k_encode_factors, dim3(grid1(pp.jcap, 256)), dim3(256), 0, s, jac->exps, pp.jcap, n,
-                                   enc, (const int64_t *)(jac->row_ptr + P * n));
+                                   enc, (const int64_t *)(jac->row_ptr + P * n), ws_maxdeg(ws));
                 EvalArgs A;
                 memset(&A, 0, sizeof(A));
+                A.maxdeg = ws_maxdeg(ws);
                 A.rp = jac->row_ptr;
                 A.exps = jac->exps;
                 A.coefs = jac->coefs;

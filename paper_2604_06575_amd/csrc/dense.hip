@@ -1367,7 +1367,7 @@ poly_status dense_run(int32_t n, int64_t K, const uint8_t *basis, int32_t max_ex
     uint4 *enc = (uint4 *)((char *)ws + d.enc);
     if (K > 0)
         hipLaunchKernelGGL(k_encode_factors, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, s, basis, K, n,
-                           (uint32_t *)enc, (const int64_t *)nullptr);
+                           (uint32_t *)enc, (const int64_t *)nullptr, (uint32_t *)nullptr);
     if (prec == POLY_FP64) {
         static bool attr = false;
         if (!attr) {
@@ -1544,7 +1544,7 @@ poly_status dense_bwd_run(int32_t n, int64_t K, const uint8_t *basis, int32_t ma
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, (unsigned long long *)ws, 0ull, (int64_t)1);
     if (K > 0) {
         hipLaunchKernelGGL(k_encode_factors, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, s, basis, K, n,
-                           (uint32_t *)fenc, (const int64_t *)nullptr);
+                           (uint32_t *)fenc, (const int64_t *)nullptr, (uint32_t *)nullptr);
         hipLaunchKernelGGL(k_encode_support, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, s, basis, K, n, senc,
                            (const int64_t *)nullptr);
     }

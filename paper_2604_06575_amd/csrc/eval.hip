@@ -288,7 +288,7 @@ __global__ void __launch_bounds__(256) k_encode_support(const uint8_t *exps, int
 // of the list padded with n (an LDS row of ones); byte 12 holds d.  A term of
 // higher degree has byte 12 = 0xFF and is evaluated from its dense row.
 __global__ void __launch_bounds__(256) k_encode_factors(const uint8_t *exps, int64_t T, int n, uint32_t *enc,
-                                                        const int64_t *used)
+                                                        const int64_t *used, uint32_t *maxdeg)
 {
     __shared__ uint32_t s_rows[256 * ROW_STAGE_MAX_N / 4];
     const int64_t lim = used && *used < T ? *used : T;
@@ -313,6 +313,18 @@ __global__ void __launch_bounds__(256) k_encode_factors(const uint8_t *exps, int
     }
     uint4 *o = reinterpret_cast<uint4 *>(enc) + t;
     *o = make_uint4(w[0], w[1], w[2], w[3]);
+    if (maxdeg) {
+        // the wave's largest degree, as 2 (<= 2), 3, 4 or 255 (more), by one
+        // lane, and only if it raises the recorded value: the word soon holds
+        // the batch's class, after which waves read it and add nothing (one
+        // atomic per wave on one word would serialize on large batches)
+        const uint32_t cls = w[3] <= 2u ? 2u : (w[3] <= 4u ? w[3] : 255u);
+        const unsigned long long act = __ballot(1);
+        const uint32_t m = __ballot(cls == 255u) ? 255u : (__ballot(cls == 4u) ? 4u : (__ballot(cls == 3u) ? 3u : 2u));
+        if (lane_id() == __ffsll((long long)act) - 1 &&
+            m > __hip_atomic_load(maxdeg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(maxdeg, m);
+    }
 }
 
 // ------------------------------------------------------------- evaluation
@@ -422,6 +434,66 @@ __device__ inline double term_range(const EvalArgs &A, const uint32_t *enc, int6
     return acc;
 }
 
+// term_range for a batch whose terms all have degree <= C (C = 2, 3, 4: the
+// batch's recorded largest degree class): a term is the product of the first
+// C factors of its list, read with no branch on its degree.  The padding
+// factors are ones, so the value is the same to the bit as term_range's.
+template <int C>
+__device__ inline double term_range_short(const EvalArgs &A, const uint32_t *enc, int64_t ta, int64_t tb,
+                                                const double *xl)
+{
+    double acc = 0.0;
+    const uint4 *ev = reinterpret_cast<const uint4 *>(enc);
+    const int lane = lane_id();
+    uint32_t gx = 0;
+    double gc = 0.0;
+    if (ta + lane < tb) {
+        gx = ev[ta + lane].x;
+        gc = A.coefs[ta + lane];
+    }
+    for (int64_t g0 = ta; g0 < tb; g0 += kWave) {
+        uint32_t hx = 0;
+        double hc = 0.0;
+        const int64_t tn = g0 + kWave + lane;
+        if (tn < tb) {
+            hx = ev[tn].x;
+            hc = A.coefs[tn];
+        }
+        const int cnt = (int)(tb - g0 < kWave ? tb - g0 : kWave);
+        for (int k = 0; k < cnt; ++k) {
+            const uint32_t word = (uint32_t)__builtin_amdgcn_readlane((int)gx, k);
+            const double c = lane_f64(gc, k);
+            double v = 1.0 * xl[(word & 0xffu) * kWave];
+            if (C > 1) v = v * xl[((word >> 8) & 0xffu) * kWave];
+            if (C > 2) v = v * xl[((word >> 16) & 0xffu) * kWave];
+            if (C > 3) v = v * xl[(word >> 24) * kWave];
+            acc += c * v;
+        }
+        gx = hx;
+        gc = hc;
+    }
+    return acc;
+}
+
+// term_range_short with the factor reads the batch's degree class md (<= 4) needs
+__device__ inline double term_range_md(uint32_t md, const EvalArgs &A, const uint32_t *enc, int64_t ta, int64_t tb,
+                                       const double *xl)
+{
+    if (md <= 2) return term_range_short<2>(A, enc, ta, tb, xl);
+    if (md == 3) return term_range_short<3>(A, enc, ta, tb, xl);
+    return term_range_short<4>(A, enc, ta, tb, xl);
+}
+
+// Which of the two forms of an evaluation kernel runs: the short one when
+// the batch's degree class is recorded and at most 4, the general one
+// otherwise.  Both are launched; the other returns before staging anything.
+template <bool SHORT>
+__device__ inline bool eval_form_runs(const EvalArgs &A, uint32_t &md)
+{
+    md = A.maxdeg ? *A.maxdeg : 255u;
+    return SHORT == (md <= 4u);
+}
+
 }  // namespace
 
 // grid: x = blocks of 64 points (one point per lane), y = groups of work
@@ -433,10 +505,12 @@ __device__ inline double term_range(const EvalArgs &A, const uint32_t *enc, int6
 // pointers are fetched while the current unit is evaluated.  The block's
 // waves share the point tile in LDS: (n + 1) * 64 doubles, variable-major,
 // plus a row of ones that the factor lists use as padding.
-__global__ void __launch_bounds__(EV_THREADS) k_eval_terms(EvalArgs A, const uint32_t *enc, double *partial,
-                                                           int64_t S)
+template <bool SHORT>
+__device__ inline void eval_terms_body(const EvalArgs &A, const uint32_t *enc, double *partial, int64_t S)
 {
     extern __shared__ double s_x[];
+    uint32_t md;
+    if (!eval_form_runs<SHORT>(A, md)) return;
     const int lane = lane_id();
     const int w = wave_id();
     const int64_t pt0 = (int64_t)blockIdx.x * kWave;
@@ -467,7 +541,7 @@ __global__ void __launch_bounds__(EV_THREADS) k_eval_terms(EvalArgs A, const uin
         const int64_t b1 = r1 < A.term_limit ? r1 : A.term_limit;
         const int64_t len = b1 > b0 ? b1 - b0 : 0;
         const int64_t sa = b0 + len * sg / S, sb = b0 + len * (sg + 1) / S;
-        const double acc = term_range(A, enc, sa, sb, xl);
+        const double acc = SHORT ? term_range_md(md, A, enc, sa, sb, xl) : term_range(A, enc, sa, sb, xl);
         if (pt < A.N) {
             if (S == 1) store_out(A, q, pt, acc);
             else partial[(sg * A.Q + q) * A.N + pt] = acc;
@@ -477,16 +551,32 @@ __global__ void __launch_bounds__(EV_THREADS) k_eval_terms(EvalArgs A, const uin
     }
 }
 
+__global__ void __launch_bounds__(EV_THREADS) k_eval_terms(EvalArgs A, const uint32_t *enc, double *partial,
+                                                           int64_t S)
+{
+    eval_terms_body<false>(A, enc, partial, S);
+}
+
+// The same for batches of degree class <= 4 (term_range_short).
+__global__ void __launch_bounds__(EV_THREADS) k_eval_terms_short(EvalArgs A, const uint32_t *enc, double *partial,
+                                                                 int64_t S)
+{
+    eval_terms_body<true>(A, enc, partial, S);
+}
+
 // Weighted sum over polynomials of formed Jacobian entries (the reverse mode
 // of eval without per-polynomial gradients):
 //   out[pt][j] = sum_p gY[p][pt] * J_{p, j}(x_pt),  J_{p, j} = polynomial p * n + j.
 // Unit (j, s) takes the polynomials p of segment s of S, in order, and sums
 // gY * (that entry's terms summed in term order); with S > 1 the segments'
 // partials [S][N][n] are added in order by k_sum_slices.
-__global__ void __launch_bounds__(EV_THREADS) k_eval_wsum(EvalArgs A, const uint32_t *enc, const double *gY,
-                                                          int64_t P, int64_t S, double *out, double *partial)
+template <bool SHORT>
+__device__ inline void eval_wsum_body(const EvalArgs &A, const uint32_t *enc, const double *gY, int64_t P, int64_t S,
+                                      double *out, double *partial)
 {
     extern __shared__ double s_x[];
+    uint32_t md;
+    if (!eval_form_runs<SHORT>(A, md)) return;
     const int lane = lane_id();
     const int w = wave_id();
     const int n = A.n;
@@ -509,7 +599,7 @@ __global__ void __launch_bounds__(EV_THREADS) k_eval_wsum(EvalArgs A, const uint
             const int64_t b0 = A.rp[q];
             const int64_t b1 = A.rp[q + 1] < A.term_limit ? A.rp[q + 1] : A.term_limit;
             if (b1 <= b0) continue;
-            const double v = term_range(A, enc, b0, b1, xl);
+            const double v = SHORT ? term_range_md(md, A, enc, b0, b1, xl) : term_range(A, enc, b0, b1, xl);
             const double g = pt < A.N ? gY[p * A.N + pt] : 0.0;
             acc = __builtin_fma(g, v, acc);
         }
@@ -518,6 +608,19 @@ __global__ void __launch_bounds__(EV_THREADS) k_eval_wsum(EvalArgs A, const uint
             else partial[(sg * A.N + pt) * n + j] = acc;
         }
     }
+}
+
+__global__ void __launch_bounds__(EV_THREADS) k_eval_wsum(EvalArgs A, const uint32_t *enc, const double *gY,
+                                                          int64_t P, int64_t S, double *out, double *partial)
+{
+    eval_wsum_body<false>(A, enc, gY, P, S, out, partial);
+}
+
+// The same for batches of degree class <= 4 (term_range_short).
+__global__ void __launch_bounds__(EV_THREADS) k_eval_wsum_short(EvalArgs A, const uint32_t *enc, const double *gY,
+                                                                int64_t P, int64_t S, double *out, double *partial)
+{
+    eval_wsum_body<true>(A, enc, gY, P, S, out, partial);
 }
 
 // H[p][pt][j][k] = stage[p][min(j,k)][max(j,k)][pt]: each Hessian entry was

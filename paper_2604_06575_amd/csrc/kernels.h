@@ -176,11 +176,15 @@ struct EvalArgs {
     int mode;                     // OutMode
     double *Y;                    // output
     int64_t term_limit;           // terms at or beyond this index are never read
+    const uint32_t *maxdeg;       // bound on every term's degree (2, 3, 4; else 255), recorded by k_encode_factors, or null
 };
 
 __global__ void k_encode_support(const uint8_t *exps, int64_t T, int n, uint64_t *enc, const int64_t *used);
 constexpr int EV_MAX_DEG = 12;   // total degree handled by the factor-list encoding
-__global__ void k_encode_factors(const uint8_t *exps, int64_t T, int n, uint32_t *enc, const int64_t *used);
+// maxdeg (or null): a zeroed word that receives, by atomicMax, the largest
+// degree class of the encoded terms (2 for degree <= 2, then 3, 4, and 255)
+__global__ void k_encode_factors(const uint8_t *exps, int64_t T, int n, uint32_t *enc, const int64_t *used,
+                                 uint32_t *maxdeg);
 
 // products of polynomial matrices (matrix.hip)
 constexpr int MAT_THREADS = 256;
@@ -273,6 +277,9 @@ struct AffStochArgs {
 };
 __global__ void k_affine_stochastic(AffStochArgs A);
 __global__ void k_eval_terms(EvalArgs A, const uint32_t *enc, double *partial, int64_t S);
+// k_eval_terms for batches whose recorded degree class (A.maxdeg) is at most
+// 4; each of the two returns at once where the other applies
+__global__ void k_eval_terms_short(EvalArgs A, const uint32_t *enc, double *partial, int64_t S);
 __global__ void k_eval_reduce(EvalArgs A, const double *partial, int64_t S);
 __global__ void k_hess_transpose(const double *stage, int64_t P, int64_t N, int n, double *H);
 // CSR batches over a shared basis (dense.hip)
@@ -282,6 +289,8 @@ __global__ void k_derive_basis(const uint8_t *basis, int64_t K, int n, int j, in
 __global__ void k_hess_mirror(double *H, int64_t PN, int n);
 __global__ void k_eval_wsum(EvalArgs A, const uint32_t *enc, const double *gY, int64_t P, int64_t S, double *out,
                             double *partial);
+__global__ void k_eval_wsum_short(EvalArgs A, const uint32_t *enc, const double *gY, int64_t P, int64_t S,
+                                  double *out, double *partial);
 constexpr int64_t EV_TARGET_WAVES = 16384;   // waves wanted before polynomials are cut into segments
 constexpr int64_t EV_MIN_SEGMENT = 32;       // fewest terms per segment
 constexpr int64_t EV_MAX_SEGMENTS = 256;
