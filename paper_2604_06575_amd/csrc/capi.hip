@@ -564,7 +564,8 @@ void launch_eval_blocks(const EvalArgs &A, const uint32_t *enc, double *partial,
     const unsigned gy = (unsigned)std::min<int64_t>(std::min<int64_t>(ceil_div(A.Q * S, EV_WAVES), want), 65535);
     const size_t lds = (size_t)(A.n + 1) * kWave * sizeof(double);
     TimedLaunch tl(POLY_TIMING_TERMS, s);
-    if (A.maxdeg) hipLaunchKernelGGL(k_eval_terms_short, dim3(gx, gy), dim3(EV_THREADS), lds, s, A, enc, partial, S);
+    if (A.maxdeg)
+        hipLaunchKernelGGL(k_eval_terms_short, dim3(gx, gy), dim3(EV_THREADS), lds, s, A, enc, A.coefs, partial, S);
     hipLaunchKernelGGL(k_eval_terms, dim3(gx, gy), dim3(EV_THREADS), lds, s, A, enc, partial, S);
     tl.done(s);
     if (S > 1) hipLaunchKernelGGL(k_eval_reduce, dim3(grid1(A.Q * A.N, 256)), dim3(256), 0, s, A, partial, S);
@@ -947,7 +948,7 @@ poly_status run_wsum(const poly_csr *f, const double *X, int64_t N, const double
     TimedLaunch tl(POLY_TIMING_TERMS, s);
     if (A.maxdeg)
         hipLaunchKernelGGL(k_eval_wsum_short, dim3(gx, gy), dim3(EV_THREADS), lds, s, A,
-                           (const uint32_t *)at<uint32_t>(ws, g.jenc), gY, f->npolys, g.S, dX, part);
+                           (const uint32_t *)at<uint32_t>(ws, g.jenc), A.coefs, gY, f->npolys, g.S, dX, part);
     hipLaunchKernelGGL(k_eval_wsum, dim3(gx, gy), dim3(EV_THREADS), lds, s, A, (const uint32_t *)at<uint32_t>(ws, g.jenc),
                        gY, f->npolys, g.S, dX, part);
     tl.done(s);

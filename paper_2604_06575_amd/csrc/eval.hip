@@ -379,6 +379,14 @@ __device__ inline double chunk4(double v, uint32_t word, const double *xl)
     return (((v * x0) * x1) * x2) * x3;
 }
 
+// a 64-bit value that is the same on every lane, as a scalar
+__device__ inline int64_t uniform_i64(int64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // value of v in lane k (k uniform)
 __device__ inline double lane_f64(double v, int k)
 {
@@ -439,49 +447,46 @@ __device__ inline double term_range(const EvalArgs &A, const uint32_t *enc, int6
 // C factors of its list, read with no branch on its degree.  The padding
 // factors are ones, so the value is the same to the bit as term_range's.
 template <int C>
-__device__ inline double term_range_short(const EvalArgs &A, const uint32_t *enc, int64_t ta, int64_t tb,
-                                                const double *xl)
+__device__ inline double term_range_short(const double *__restrict__ coefs, const uint32_t *__restrict__ enc,
+                                          int64_t ta, int64_t tb, const double *xl)
 {
-    double acc = 0.0;
+    // the range is the same on every lane: as scalars, the term records and
+    // coefficients are read by scalar loads, eight terms at a time, and no
+    // vector instruction moves them
+    ta = uniform_i64(ta);
+    tb = uniform_i64(tb);
     const uint4 *ev = reinterpret_cast<const uint4 *>(enc);
-    const int lane = lane_id();
-    uint32_t gx = 0;
-    double gc = 0.0;
-    if (ta + lane < tb) {
-        gx = ev[ta + lane].x;
-        gc = A.coefs[ta + lane];
-    }
-    for (int64_t g0 = ta; g0 < tb; g0 += kWave) {
-        uint32_t hx = 0;
-        double hc = 0.0;
-        const int64_t tn = g0 + kWave + lane;
-        if (tn < tb) {
-            hx = ev[tn].x;
-            hc = A.coefs[tn];
+    double acc = 0.0;
+    auto term = [&](uint32_t word, double c) {
+        double v = 1.0 * xl[(word & 0xffu) * kWave];
+        if (C > 1) v = v * xl[((word >> 8) & 0xffu) * kWave];
+        if (C > 2) v = v * xl[((word >> 16) & 0xffu) * kWave];
+        if (C > 3) v = v * xl[(word >> 24) * kWave];
+        acc += c * v;
+    };
+    int64_t t = ta;
+    for (; t + 8 <= tb; t += 8) {
+        uint32_t wd[8];
+        double cf[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            wd[k] = ev[t + k].x;
+            cf[k] = coefs[t + k];
         }
-        const int cnt = (int)(tb - g0 < kWave ? tb - g0 : kWave);
-        for (int k = 0; k < cnt; ++k) {
-            const uint32_t word = (uint32_t)__builtin_amdgcn_readlane((int)gx, k);
-            const double c = lane_f64(gc, k);
-            double v = 1.0 * xl[(word & 0xffu) * kWave];
-            if (C > 1) v = v * xl[((word >> 8) & 0xffu) * kWave];
-            if (C > 2) v = v * xl[((word >> 16) & 0xffu) * kWave];
-            if (C > 3) v = v * xl[(word >> 24) * kWave];
-            acc += c * v;
-        }
-        gx = hx;
-        gc = hc;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) term(wd[k], cf[k]);
     }
+    for (; t < tb; ++t) term(ev[t].x, coefs[t]);
     return acc;
 }
 
 // term_range_short with the factor reads the batch's degree class md (<= 4) needs
-__device__ inline double term_range_md(uint32_t md, const EvalArgs &A, const uint32_t *enc, int64_t ta, int64_t tb,
-                                       const double *xl)
+__device__ inline double term_range_md(uint32_t md, const double *__restrict__ coefs, const uint32_t *__restrict__ enc,
+                                       int64_t ta, int64_t tb, const double *xl)
 {
-    if (md <= 2) return term_range_short<2>(A, enc, ta, tb, xl);
-    if (md == 3) return term_range_short<3>(A, enc, ta, tb, xl);
-    return term_range_short<4>(A, enc, ta, tb, xl);
+    if (md <= 2) return term_range_short<2>(coefs, enc, ta, tb, xl);
+    if (md == 3) return term_range_short<3>(coefs, enc, ta, tb, xl);
+    return term_range_short<4>(coefs, enc, ta, tb, xl);
 }
 
 // Which of the two forms of an evaluation kernel runs: the short one when
@@ -506,7 +511,8 @@ __device__ inline bool eval_form_runs(const EvalArgs &A, uint32_t &md)
 // waves share the point tile in LDS: (n + 1) * 64 doubles, variable-major,
 // plus a row of ones that the factor lists use as padding.
 template <bool SHORT>
-__device__ inline void eval_terms_body(const EvalArgs &A, const uint32_t *enc, double *partial, int64_t S)
+__device__ inline void eval_terms_body(const EvalArgs &A, const uint32_t *__restrict__ enc,
+                                       const double *__restrict__ coefs, double *partial, int64_t S)
 {
     extern __shared__ double s_x[];
     uint32_t md;
@@ -541,7 +547,7 @@ __device__ inline void eval_terms_body(const EvalArgs &A, const uint32_t *enc, d
         const int64_t b1 = r1 < A.term_limit ? r1 : A.term_limit;
         const int64_t len = b1 > b0 ? b1 - b0 : 0;
         const int64_t sa = b0 + len * sg / S, sb = b0 + len * (sg + 1) / S;
-        const double acc = SHORT ? term_range_md(md, A, enc, sa, sb, xl) : term_range(A, enc, sa, sb, xl);
+        const double acc = SHORT ? term_range_md(md, coefs, enc, sa, sb, xl) : term_range(A, enc, sa, sb, xl);
         if (pt < A.N) {
             if (S == 1) store_out(A, q, pt, acc);
             else partial[(sg * A.Q + q) * A.N + pt] = acc;
@@ -554,14 +560,15 @@ __device__ inline void eval_terms_body(const EvalArgs &A, const uint32_t *enc, d
 __global__ void __launch_bounds__(EV_THREADS) k_eval_terms(EvalArgs A, const uint32_t *enc, double *partial,
                                                            int64_t S)
 {
-    eval_terms_body<false>(A, enc, partial, S);
+    eval_terms_body<false>(A, enc, A.coefs, partial, S);
 }
 
 // The same for batches of degree class <= 4 (term_range_short).
-__global__ void __launch_bounds__(EV_THREADS) k_eval_terms_short(EvalArgs A, const uint32_t *enc, double *partial,
+__global__ void __launch_bounds__(EV_THREADS) k_eval_terms_short(EvalArgs A, const uint32_t *__restrict__ enc,
+                                                                 const double *__restrict__ coefs, double *partial,
                                                                  int64_t S)
 {
-    eval_terms_body<true>(A, enc, partial, S);
+    eval_terms_body<true>(A, enc, coefs, partial, S);
 }
 
 // Weighted sum over polynomials of formed Jacobian entries (the reverse mode
@@ -571,7 +578,8 @@ __global__ void __launch_bounds__(EV_THREADS) k_eval_terms_short(EvalArgs A, con
 // gY * (that entry's terms summed in term order); with S > 1 the segments'
 // partials [S][N][n] are added in order by k_sum_slices.
 template <bool SHORT>
-__device__ inline void eval_wsum_body(const EvalArgs &A, const uint32_t *enc, const double *gY, int64_t P, int64_t S,
+__device__ inline void eval_wsum_body(const EvalArgs &A, const uint32_t *__restrict__ enc,
+                                      const double *__restrict__ coefs, const double *gY, int64_t P, int64_t S,
                                       double *out, double *partial)
 {
     extern __shared__ double s_x[];
@@ -599,7 +607,7 @@ __device__ inline void eval_wsum_body(const EvalArgs &A, const uint32_t *enc, co
             const int64_t b0 = A.rp[q];
             const int64_t b1 = A.rp[q + 1] < A.term_limit ? A.rp[q + 1] : A.term_limit;
             if (b1 <= b0) continue;
-            const double v = SHORT ? term_range_md(md, A, enc, b0, b1, xl) : term_range(A, enc, b0, b1, xl);
+            const double v = SHORT ? term_range_md(md, coefs, enc, b0, b1, xl) : term_range(A, enc, b0, b1, xl);
             const double g = pt < A.N ? gY[p * A.N + pt] : 0.0;
             acc = __builtin_fma(g, v, acc);
         }
@@ -613,14 +621,15 @@ __device__ inline void eval_wsum_body(const EvalArgs &A, const uint32_t *enc, co
 __global__ void __launch_bounds__(EV_THREADS) k_eval_wsum(EvalArgs A, const uint32_t *enc, const double *gY,
                                                           int64_t P, int64_t S, double *out, double *partial)
 {
-    eval_wsum_body<false>(A, enc, gY, P, S, out, partial);
+    eval_wsum_body<false>(A, enc, A.coefs, gY, P, S, out, partial);
 }
 
 // The same for batches of degree class <= 4 (term_range_short).
-__global__ void __launch_bounds__(EV_THREADS) k_eval_wsum_short(EvalArgs A, const uint32_t *enc, const double *gY,
+__global__ void __launch_bounds__(EV_THREADS) k_eval_wsum_short(EvalArgs A, const uint32_t *__restrict__ enc,
+                                                                const double *__restrict__ coefs, const double *gY,
                                                                 int64_t P, int64_t S, double *out, double *partial)
 {
-    eval_wsum_body<true>(A, enc, gY, P, S, out, partial);
+    eval_wsum_body<true>(A, enc, coefs, gY, P, S, out, partial);
 }
 
 // H[p][pt][j][k] = stage[p][min(j,k)][max(j,k)][pt]: each Hessian entry was

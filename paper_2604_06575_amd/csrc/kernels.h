@@ -279,7 +279,8 @@ __global__ void k_affine_stochastic(AffStochArgs A);
 __global__ void k_eval_terms(EvalArgs A, const uint32_t *enc, double *partial, int64_t S);
 // k_eval_terms for batches whose recorded degree class (A.maxdeg) is at most
 // 4; each of the two returns at once where the other applies
-__global__ void k_eval_terms_short(EvalArgs A, const uint32_t *enc, double *partial, int64_t S);
+__global__ void k_eval_terms_short(EvalArgs A, const uint32_t *__restrict__ enc, const double *__restrict__ coefs,
+                                   double *partial, int64_t S);
 __global__ void k_eval_reduce(EvalArgs A, const double *partial, int64_t S);
 __global__ void k_hess_transpose(const double *stage, int64_t P, int64_t N, int n, double *H);
 // CSR batches over a shared basis (dense.hip)
@@ -289,8 +290,8 @@ __global__ void k_derive_basis(const uint8_t *basis, int64_t K, int n, int j, in
 __global__ void k_hess_mirror(double *H, int64_t PN, int n);
 __global__ void k_eval_wsum(EvalArgs A, const uint32_t *enc, const double *gY, int64_t P, int64_t S, double *out,
                             double *partial);
-__global__ void k_eval_wsum_short(EvalArgs A, const uint32_t *enc, const double *gY, int64_t P, int64_t S,
-                                  double *out, double *partial);
+__global__ void k_eval_wsum_short(EvalArgs A, const uint32_t *__restrict__ enc, const double *__restrict__ coefs,
+                                  const double *gY, int64_t P, int64_t S, double *out, double *partial);
 constexpr int64_t EV_TARGET_WAVES = 16384;   // waves wanted before polynomials are cut into segments
 constexpr int64_t EV_MIN_SEGMENT = 32;       // fewest terms per segment
 constexpr int64_t EV_MAX_SEGMENTS = 256;
