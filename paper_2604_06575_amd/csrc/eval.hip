@@ -13,7 +13,10 @@
 //    (variable indices with repetition, 16 bytes); the lane's point
 //    coordinates sit in LDS, and a monomial is the left-to-right product of
 //    its factors.  The waves of a workgroup share 64 points and split a
-//    polynomial's terms; their partial sums are added in a fixed order.
+//    polynomial's terms; their partial sums are added in a fixed order.  A
+//    batch whose terms all have degree <= 4 (the class the encoder records
+//    on the device) is streamed by the _short kernels, which read exactly
+//    that many factors per term, with no branch on the term's degree.
 #include "kernels.h"
 
 namespace polyhip {
