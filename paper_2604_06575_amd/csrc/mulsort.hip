@@ -60,9 +60,10 @@ __global__ void __launch_bounds__(GS_THREADS) k_gs_generate(const uint64_t *ka, 
 }
 
 // Per-tile digit counts, digit-major: hist[d * nblocks + b].  One wave
-// counts a whole tile into its own LDS histogram, with no barrier: lanes
-// holding the same digit are found with wavefront ballots and their lowest
-// lane adds the group size.  Waves take tiles wave_id, wave_id + total
+// counts a whole tile into its own LDS histogram, with no barrier: every
+// lane adds its element by an LDS atomic (lanes of one digit are serialized
+// by the hardware; grouping them with wavefront ballots first cost more
+// issue slots than it saved).  Waves take tiles wave_id, wave_id + total
 // waves, ... (few, long-lived workgroups rather than one per tile).
 template <int DB, bool GEN>
 __global__ void __launch_bounds__(GS_HIST_THREADS) k_gs_hist(const uint64_t *keys, int64_t R, int shift,
@@ -74,7 +75,6 @@ __global__ void __launch_bounds__(GS_HIST_THREADS) k_gs_hist(const uint64_t *key
     __shared__ uint32_t s_cnt[W][NB];
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
-    const unsigned long long lt = lane ? (~0ull >> (kWave - lane)) : 0ull;
     uint32_t *cnt = s_cnt[w];
     const int64_t nwaves = (int64_t)gridDim.x * W;
     for (int64_t tile = (int64_t)blockIdx.x * W + w; tile < nblocks; tile += nwaves) {
@@ -100,17 +100,8 @@ __global__ void __launch_bounds__(GS_HIST_THREADS) k_gs_hist(const uint64_t *key
                 dg[u] = l < m ? (uint32_t)(kv[u] >> shift) & (NB - 1) : (uint32_t)NB;
             }
 #pragma unroll
-            for (int u = 0; u < UN; ++u) {
-                const uint32_t d = dg[u];
-                unsigned long long peer = __ballot(d < (uint32_t)NB);   // padding lanes are in no group
-#pragma unroll
-                for (int bit = 0; bit < DB; ++bit) {
-                    const bool set = (d >> bit) & 1u;
-                    const unsigned long long bb = __ballot(set);
-                    peer &= set ? bb : ~bb;
-                }
-                if (d < (uint32_t)NB && (peer & lt) == 0) cnt[d] += (uint32_t)__popcll(peer);
-            }
+            for (int u = 0; u < UN; ++u)
+                if (dg[u] < (uint32_t)NB) atomicAdd(&cnt[dg[u]], 1u);   // padding lanes add nothing
         }
         for (int d = lane; d < NB; d += kWave) hist[(int64_t)d * nblocks + tile] = cnt[d];
     }
