@@ -1,8 +1,8 @@
 """Keys wider than 64 bits: simplify, times and mtimes of polynomials whose
 exponents do not fit one 64-bit word (n * bit_width(max_exp) > 64), and
-batches whose (polynomial, monomial) composite key does not (the config-3
-shape: many entries in 20 variables), through the device-wide sort over key
-words.  Every result is compared bit for bit with the oracle, which orders
+batches whose (polynomial, monomial) composite key does not (many entries in
+20 variables, as in the 4,096-entry polynomial matrix), through the
+device-wide sort over key words.  Every result is compared bit for bit with the oracle, which orders
 exponent rows lexicographically and has no key width at all; the composite
 case is also compared with the one-workgroup-per-polynomial path."""
 import sys
