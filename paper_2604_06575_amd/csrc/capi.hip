@@ -1848,11 +1848,14 @@ poly_status poly_eval(const poly_csr *f, const double *X, int64_t N, double *Y, 
         return POLY_OK;
     }
     uint32_t *enc = at<uint32_t>(ws, o_enc);
+    // small calls take the general kernel alone (one launch): the degree class
+    // pays only where the evaluation itself is long
+    uint32_t *md = T * N >= ((int64_t)1 << 22) ? ws_maxdeg(ws) : nullptr;
     if (T > 0) hipLaunchKernelGGL(k_encode_factors, dim3(grid1(T, 256)), dim3(256), 0, s, f->exps, T, f->nvars, enc,
-                                  (const int64_t *)nullptr, ws_maxdeg(ws));
+                                  (const int64_t *)nullptr, md);
     EvalArgs A;
     memset(&A, 0, sizeof(A));
-    A.maxdeg = ws_maxdeg(ws);
+    A.maxdeg = md;
     A.rp = f->row_ptr;
     A.exps = f->exps;
     A.coefs = f->coefs;
