@@ -369,8 +369,13 @@ poly_status poly_affine_normal_stochastic(const poly_csr *f, const double *X, in
  * diagonals s + t >= 4.
  * Limits (POLY_ERR_UNSUPPORTED beyond them): the points of one tile and a
  * row of ones fit in LDS (n <= 94 for FP64, n <= 89 for the split
- * path at nslices = 5), and K <= 4,194,272 (one workgroup's rows of C, or
- * of one BF16 slice of C, are addressed with 32-bit byte offsets). */
+ * path at nslices = 5), and one workgroup's rows of C, or of one BF16
+ * slice of C, are addressed with 32-bit byte offsets: K <= 2,097,120 for
+ * FP64 with 128 rows per workgroup (the "dense_f64_rows" tunable), else
+ * K <= 4,194,272.  The split digits carry their block's power-of-two scale
+ * as BF16 numbers, so the path assumes block magnitudes of C and V (and of
+ * gY in the reverse mode) between about 2^-80 and 2^120; beyond that range
+ * digits underflow or overflow. */
 poly_status poly_eval_dense_workspace(int32_t n, int64_t K, int64_t P, int64_t N,
                                       poly_prec prec, int32_t nslices, size_t *ws_bytes);
 poly_status poly_eval_dense(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp,
