@@ -373,9 +373,10 @@ poly_status poly_affine_normal_stochastic(const poly_csr *f, const double *X, in
  * slice of C, are addressed with 32-bit byte offsets: K <= 2,097,120 for
  * FP64 with 128 rows per workgroup (the "dense_f64_rows" tunable), else
  * K <= 4,194,272.  The split digits carry their block's power-of-two scale
- * as BF16 numbers, so the path assumes block magnitudes of C and V (and of
- * gY in the reverse mode) between about 2^-80 and 2^120; beyond that range
- * digits underflow or overflow. */
+ * as BF16 numbers and their products are summed in FP32, so the path
+ * assumes that the product of the two operands' block magnitudes (C and V;
+ * gY and V, or C and gY, in the reverse mode) lies between about 2^-78 and
+ * 2^126; beyond that range digit products underflow or overflow. */
 poly_status poly_eval_dense_workspace(int32_t n, int64_t K, int64_t P, int64_t N,
                                       poly_prec prec, int32_t nslices, size_t *ws_bytes);
 poly_status poly_eval_dense(int32_t n, int64_t K, const uint8_t *basis, int32_t max_exp,
