@@ -151,11 +151,6 @@ inline void clear_u64(unsigned long long *p, int64_t count, hipStream_t s)
     hipLaunchKernelGGL(k_fill_u64, dim3(grid1(count, 256)), dim3(256), 0, s, p, 0ull, count);
 }
 
-inline void set_u64(unsigned long long *p, unsigned long long v, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, p, v, (int64_t)1);
-}
-
 // ------------------------------------------------------------ simplify plan
 
 // Device-wide simplify (batches holding a polynomial larger than the
@@ -911,9 +906,7 @@ EvalArgs form_jacobian(const poly_csr *f, const double *X, int64_t N, void *ws, 
 poly_status run_grad(const poly_csr *f, const double *X, int64_t N, double *G, void *ws, const GradPlan &g,
                      hipStream_t s)
 {
-    const int64_t P = f->npolys;
     const int n = f->nvars;
-    int32_t *status = at<int32_t>(ws, 0);
     if (g.fused) {
         const int64_t T = total_terms(f);
         uint64_t *enc = at<uint64_t>(ws, g.enc);
